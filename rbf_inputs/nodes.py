@@ -1,0 +1,170 @@
+"""Jittered staggered node sets (stand-in for the DistMesh grids of Sec. 3).
+
+The paper puts pressure on the vertices of an unstructured triangulation (the
+P-grid) and velocity on the edge midpoints (the V-grid), N/M ~ 3.  DistMesh is
+not available, so the cavity uses a seeded jittered triangulation of the unit
+square with the same staggering (``cavity_nodes``).  The operator benchmark
+uses two jittered square lattices with N = M (``square_nodes``): V on cell
+centres, P on vertices.
+
+Random numbers come from SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) used
+as a counter-based generator: draw c of stream g is mix(seed + (c'+1)*GAMMA)
+with c' = (g << 40) | c, and a uniform double is (draw >> 11) * 2**-53.
+The C library implements the same published definition independently; every
+floating-point operation below is a single IEEE-754 rounding (no fused
+multiply-add), so both produce bit-identical coordinates.
+
+Layout: coordinates are SoA, ``x[2, n]`` (row 0 = x, row 1 = y), in a
+row-major lattice order (j outer, i inner) so that stencil neighbours are
+close in memory.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+MIX1 = np.uint64(0xBF58476D1CE4E5B9)
+MIX2 = np.uint64(0x94D049BB133111EB)
+
+TAG_INTERIOR = 0
+TAG_WALL = 1
+TAG_LID = 2
+
+STREAM_V = 0
+STREAM_P = 1
+SQRT_HALF = 0.7071067811865476  # 1/sqrt(2) rounded to nearest
+
+
+def splitmix64(seed, counters):
+    """SplitMix64 output for the given 64-bit counters (vectorised)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.asarray(counters, dtype=np.uint64) + np.uint64(1)) * GAMMA
+        z = (z ^ (z >> np.uint64(30))) * MIX1
+        z = (z ^ (z >> np.uint64(27))) * MIX2
+        return z ^ (z >> np.uint64(31))
+
+
+def uniform01(seed, stream, counters):
+    """Uniform doubles in [0, 1) for draws ``counters`` of ``stream``."""
+    c = (np.uint64(stream) << np.uint64(40)) | np.asarray(counters, dtype=np.uint64)
+    return (splitmix64(seed, c) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def _jitter(seed, stream, node_index, amp):
+    """Offsets (2u-1)*amp for x (draw 2i) and y (draw 2i+1) of each node."""
+    node_index = np.asarray(node_index, dtype=np.uint64)
+    ux = uniform01(seed, stream, np.uint64(2) * node_index)
+    uy = uniform01(seed, stream, np.uint64(2) * node_index + np.uint64(1))
+    return (2.0 * ux - 1.0) * amp, (2.0 * uy - 1.0) * amp
+
+
+@dataclass
+class NodeSet:
+    """A staggered pair of node sets with boundary information."""
+    xv: np.ndarray        # float64 [2, N]
+    v_tag: np.ndarray     # int8 [N]: 0 interior, 1 wall, 2 lid
+    xp: np.ndarray        # float64 [2, M]
+    p_tag: np.ndarray     # int8 [M]: 0 interior, 1 wall
+    p_normal: np.ndarray  # float64 [2, M], outward unit normal on wall P-nodes, 0 elsewhere
+    K: int
+    h: float
+
+    @property
+    def n_v(self):
+        return self.xv.shape[1]
+
+    @property
+    def n_p(self):
+        return self.xp.shape[1]
+
+
+def cavity_nodes(K, jitter=0.3, seed=0):
+    """Unit-square cavity on the paper's staggered layout (Sec. 3).
+
+    P-grid: the vertices (i h, j h), i, j = 0..K, h = 1/K, of a triangulation
+    of the square; interior vertices are jittered by U(-jitter h, jitter h)
+    per coordinate (draws 2v, 2v+1 of stream P for vertex v = j (K+1) + i),
+    boundary vertices (corners included) stay on the walls.  Each lattice cell
+    (i, j) is split into two triangles by a diagonal whose direction
+    alternates like a checkerboard: (i,j)-(i+1,j+1) when i+j is even,
+    (i+1,j)-(i,j+1) when odd.
+    V-grid: the midpoints (a + b) * 0.5 of all triangle edges.
+    Counts: M = (K+1)^2, N = 3K^2 + 2K (N/M ~ 3, as in the paper).
+
+    Ordering: P row-major over vertices (j outer).  V by owning vertex in the
+    same order: vertex (i, j) emits its rightward edge (if i < K), its upward
+    edge (if j < K) and the diagonal of cell (i, j) (if i, j < K).
+    Tags: wall edges/vertices are 1, V-nodes on the top wall are 2 (lid).
+    P normals are outward; at corners the diagonal (+-1, +-1)/sqrt(2).
+    """
+    if K < 2:
+        raise ValueError("K must be >= 2")
+    h = 1.0 / K
+    amp = jitter * h
+    n1 = K + 1
+    ii, jj = np.meshgrid(np.arange(n1), np.arange(n1), indexing="xy")
+    ii = ii.ravel()
+    jj = jj.ravel()
+    M = n1 * n1
+    interior = (ii > 0) & (ii < K) & (jj > 0) & (jj < K)
+    ox, oy = _jitter(seed, STREAM_P, np.arange(M), amp)
+    px = np.where(ii == K, 1.0, ii * h)
+    py = np.where(jj == K, 1.0, jj * h)
+    px = np.where(interior, px + ox, px)
+    py = np.where(interior, py + oy, py)
+    p_tag = np.where(interior, TAG_INTERIOR, TAG_WALL).astype(np.int8)
+    nx = np.where(ii == 0, -1.0, np.where(ii == K, 1.0, 0.0))
+    ny = np.where(jj == 0, -1.0, np.where(jj == K, 1.0, 0.0))
+    corner = (nx != 0.0) & (ny != 0.0)
+    nx = np.where(corner, nx * SQRT_HALF, nx)
+    ny = np.where(corner, ny * SQRT_HALF, ny)
+    # Edges, grouped by owning vertex in row-major order.
+    vid = jj * n1 + ii
+    right = ii < K
+    up = jj < K
+    cell = right & up
+    even = (ii + jj) % 2 == 0
+    ea = np.stack([vid, vid, np.where(even, vid, vid + 1)])
+    eb = np.stack([vid + 1, vid + n1, np.where(even, vid + n1 + 1, vid + n1)])
+    keep = np.stack([right, up, cell])
+    ea = ea.T[keep.T]
+    eb = eb.T[keep.T]
+    vx = (px[ea] + px[eb]) * 0.5
+    vy = (py[ea] + py[eb]) * 0.5
+    on_wall = (p_tag[ea] != TAG_INTERIOR) & (p_tag[eb] != TAG_INTERIOR) & (
+        (px[ea] == px[eb]) & ((px[ea] == 0.0) | (px[ea] == 1.0))
+        | (py[ea] == py[eb]) & ((py[ea] == 0.0) | (py[ea] == 1.0)))
+    lid = on_wall & (vy == 1.0)
+    v_tag = np.where(lid, TAG_LID, np.where(on_wall, TAG_WALL, TAG_INTERIOR)).astype(np.int8)
+    return NodeSet(np.stack([vx, vy]), v_tag, np.stack([px, py]), p_tag,
+                   np.stack([nx, ny]), K, h)
+
+
+def square_nodes(K, jitter=0.3, seed=0):
+    """Operator-bench square: K^2 V-nodes ((i+1/2)h, (j+1/2)h) and K^2
+    P-nodes (ih, jh), i, j = 0..K-1, h = 1/K, both jittered; no walls."""
+    if K < 1:
+        raise ValueError("K must be >= 1")
+    h = 1.0 / K
+    amp = jitter * h
+    ii, jj = np.meshgrid(np.arange(K), np.arange(K), indexing="xy")
+    ii = ii.ravel()
+    jj = jj.ravel()
+    n = K * K
+    ox, oy = _jitter(seed, STREAM_V, np.arange(n), amp)
+    vx = (ii + 0.5) * h + ox
+    vy = (jj + 0.5) * h + oy
+    ox, oy = _jitter(seed, STREAM_P, np.arange(n), amp)
+    px = ii * h + ox
+    py = jj * h + oy
+    return NodeSet(np.stack([vx, vy]), np.zeros(n, np.int8), np.stack([px, py]),
+                   np.zeros(n, np.int8), np.zeros((2, n)), K, h)
+
+
+def build_nodes(kind, K, jitter=0.3, seed=0):
+    """kind 0: cavity; kind 1: bench square."""
+    if kind == 0:
+        return cavity_nodes(K, jitter, seed)
+    if kind == 1:
+        return square_nodes(K, jitter, seed)
+    raise ValueError(f"unknown node-set kind {kind}")

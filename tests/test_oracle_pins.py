@@ -1,0 +1,435 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix
+(CPU only).  Each check is chosen so that a plausible mistake in the oracle
+(a dropped term, a wrong sign or exponent, a transposed operand, a wrong
+boundary row) fails at least one of them."""
+import json
+import os
+
+import mpmath
+import numpy as np
+import pytest
+
+import rbf_inputs as ri
+from oracle import knn as oknn, weights as ow, operators as oops, cavity as ocav, metrics as Mx
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+OPS = [ow.OP_ID, ow.OP_DX, ow.OP_DY, ow.OP_LAP]
+
+
+# ------------------------------------------------------------------ nodes --
+@pytest.mark.parametrize("K", [2, 5, 40])
+def test_cavity_node_layout(K):
+    nd = ri.cavity_nodes(K, 0.3, 1)
+    assert nd.n_v == 3 * K * K + 2 * K and nd.n_p == (K + 1) ** 2
+    for x in (nd.xv, nd.xp):
+        assert x.min() >= 0.0 and x.max() <= 1.0
+    on_wall = lambda x: (x[0] == 0) | (x[0] == 1) | (x[1] == 0) | (x[1] == 1)  # noqa: E731
+    assert np.array_equal(nd.v_tag != 0, on_wall(nd.xv))
+    assert np.array_equal(nd.p_tag != 0, on_wall(nd.xp))
+    assert (nd.v_tag == ri.TAG_LID).sum() == K and np.all(nd.xv[1][nd.v_tag == ri.TAG_LID] == 1.0)
+    # Every V node is the midpoint of two nearby P nodes (an edge midpoint).
+    from scipy.spatial import cKDTree
+    _, nb = cKDTree(nd.xp.T).query(nd.xv.T, k=min(8, nd.n_p))
+    for i in range(nd.n_v):
+        c = nb[i]
+        mids = (nd.xp[:, c][:, :, None] + nd.xp[:, c][:, None, :]) * 0.5
+        hit = (mids[0] == nd.xv[0, i]) & (mids[1] == nd.xv[1, i])
+        assert hit.any(), i
+    n = np.hypot(nd.p_normal[0], nd.p_normal[1])
+    assert np.allclose(n[nd.p_tag != 0], 1.0) and np.all(n[nd.p_tag == 0] == 0)
+
+
+def test_node_generator_is_seeded_and_splitmix():
+    # SplitMix64 reference values for seed 0 (Vigna's published generator):
+    # the first outputs of the sequence started at state 0.
+    out = ri.splitmix64(0, np.arange(3, dtype=np.uint64))
+    assert [int(v) for v in out] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    a, b = ri.cavity_nodes(8, 0.3, 5), ri.cavity_nodes(8, 0.3, 5)
+    assert np.array_equal(a.xv, b.xv)
+    assert not np.array_equal(a.xv, ri.cavity_nodes(8, 0.3, 6).xv)
+    sq = ri.square_nodes(30, 0.3, 0)
+    base = (np.arange(30) + 0.5) / 30
+    assert np.max(np.abs(sq.xv[0].reshape(30, 30) - base[None, :])) <= 0.3 / 30 + 1e-15
+
+
+# -------------------------------------------------------------------- kNN --
+def _knn_by_definition(xq, xs, k):
+    """Pure-Python sort of (d2, index) pairs, row by row (tiny inputs only)."""
+    out = []
+    for r in range(xq.shape[1]):
+        keys = []
+        for j in range(xs.shape[1]):
+            dx = float(xs[0, j]) - float(xq[0, r])
+            dy = float(xs[1, j]) - float(xq[1, r])
+            keys.append((dx * dx + dy * dy, j))
+        keys.sort()
+        out.append([j for _, j in keys[:k]])
+    return np.array(out, np.int32).T
+
+
+@pytest.mark.parametrize("jit", [0.0, 0.3])
+def test_knn_definition_and_ties(jit):
+    nd = ri.square_nodes(9, jit, 2)  # jitter 0: many exact ties
+    ref = _knn_by_definition(nd.xp[:, :40], nd.xv, 28)
+    assert np.array_equal(oknn.knn_bruteforce(nd.xp[:, :40], nd.xv, 28), ref)
+    assert np.array_equal(oknn.knn(nd.xp[:, :40], nd.xv, 28), ref)
+    nd = ri.cavity_nodes(20, jit, 0)
+    for xq, xs in ((nd.xv, nd.xv), (nd.xp, nd.xv), (nd.xv, nd.xp)):
+        assert np.array_equal(oknn.knn(xq, xs, 28), oknn.knn_bruteforce(xq, xs, 28))
+    idx = oknn.knn(nd.xv, nd.xv, 28)
+    assert np.array_equal(idx[0], np.arange(nd.n_v))
+
+
+# ---------------------------------------------------------------- weights --
+def _monomial_and_derivs(a, b, x, y):
+    """x^a y^b and its d/dx, d/dy, Laplacian (closed forms)."""
+    f = x ** a * y ** b
+    fx = a * x ** max(a - 1, 0) * y ** b if a else 0 * x
+    fy = b * x ** a * y ** max(b - 1, 0) if b else 0 * y
+    lap = (a * (a - 1) * x ** max(a - 2, 0) * y ** b if a > 1 else 0 * x) + \
+          (b * (b - 1) * x ** a * y ** max(b - 2, 0) if b > 1 else 0 * y)
+    return {ow.OP_ID: f, ow.OP_DX: fx, ow.OP_DY: fy, ow.OP_LAP: lap}
+
+
+@pytest.mark.parametrize("m,q", [(7, 3), (3, 1), (5, 2), (7, 4), (9, 3)])
+def test_polynomial_reproduction(m, q):
+    """Sec. 2.1, vanishing-moment conditions (eq. (7)): weights reproduce L of
+    every monomial of degree <= q exactly (to rounding), in physical units."""
+    nd = ri.cavity_nodes(10, 0.3, 3)
+    n = max(28, (q + 1) * (q + 2))
+    for xq, xs in ((nd.xv, nd.xv), (nd.xp, nd.xv), (nd.xv, nd.xp)):
+        idx = oknn.knn(xq, xs, n)
+        w = ow.stencil_weights(xq, xs, idx, m, q, OPS)
+        X, Y = xs[0][idx] - 0.3, xs[1][idx] + 0.2  # shifted origin: no special point
+        x0, y0 = xq[0] - 0.3, xq[1] + 0.2
+        for a, b in ow.monomial_exponents(q):
+            fj = X ** a * Y ** b
+            exact = _monomial_and_derivs(a, b, x0, y0)
+            for o, op in enumerate(OPS):
+                got = np.sum(w[o] * fj, axis=0)
+                scale = np.sum(np.abs(w[o] * fj), axis=0) + 1.0
+                assert np.max(np.abs(got - exact[op]) / scale) < 1e-11, (a, b, op)
+
+
+def test_rbf_space_exactness():
+    """Eq. (6)/(9): for f = sum_k lam_k |x - x_k|^m with P^T lam = 0 (f in the
+    PHS+poly space), sum_j w_j f(x_j) equals L f(x_0) exactly.  Pins the PHS
+    exponent and the sign of L phi independently of polynomial reproduction."""
+    nd = ri.cavity_nodes(8, 0.3, 4)
+    xq, xs = nd.xp, nd.xv
+    idx = oknn.knn(xq, xs, 28)
+    m = 7
+    w = ow.stencil_weights(xq, xs, idx, m, 3, OPS)
+    rng = np.random.default_rng(0)
+    for r in (0, 17, 40, nd.n_p - 1):
+        pts = xs[:, idx[:, r]]
+        Pm = np.stack([pts[0] ** a * pts[1] ** b for a, b in ow.monomial_exponents(3)], 1)
+        lam = rng.standard_normal(28)
+        Q, _ = np.linalg.qr(Pm, mode="complete")
+        lam = Q[:, 10:] @ (Q[:, 10:].T @ lam)  # orthogonal to all cubics
+        x0, y0 = xq[0, r], xq[1, r]
+        dxk, dyk = x0 - pts[0], y0 - pts[1]
+        rk = np.hypot(dxk, dyk)
+        Lf = {ow.OP_ID: np.sum(lam * rk ** m),
+              ow.OP_DX: np.sum(lam * m * rk ** (m - 2) * dxk),
+              ow.OP_DY: np.sum(lam * m * rk ** (m - 2) * dyk),
+              ow.OP_LAP: np.sum(lam * m * m * rk ** (m - 2))}
+        fj = np.array([np.sum(lam * np.hypot(pts[0, j] - pts[0], pts[1, j] - pts[1]) ** m)
+                       for j in range(28)])
+        for o, op in enumerate(OPS):
+            got = np.sum(w[o][:, r] * fj)
+            scale = np.sum(np.abs(w[o][:, r] * fj)) + abs(Lf[op])
+            assert abs(got - Lf[op]) / scale < 1e-9, (r, op)
+
+
+def _mp_weights(xq, xs, idx_row, m, q, op, dps=40):
+    """Independent 40-digit solve of eq. (9) for one row, built directly from
+    the coordinates (no local scaling).  ``op`` is one code or a list; the
+    factorisation is shared by all right-hand sides."""
+    mpmath.mp.dps = dps
+    ops = op if isinstance(op, (list, tuple)) else [op]
+    x0, y0 = mpmath.mpf(xq[0]), mpmath.mpf(xq[1])
+    px = [mpmath.mpf(xs[0, j]) for j in idx_row]
+    py = [mpmath.mpf(xs[1, j]) for j in idx_row]
+    n = len(idx_row)
+    ex = ow.monomial_exponents(q)
+    s = n + len(ex)
+    A = mpmath.zeros(s, s)
+    for i in range(n):
+        for j in range(n):
+            A[i, j] = mpmath.sqrt((px[i] - px[j]) ** 2 + (py[i] - py[j]) ** 2) ** m
+        for t, (a, b) in enumerate(ex):
+            A[i, n + t] = (px[i] - x0) ** a * (py[i] - y0) ** b
+            A[n + t, i] = A[i, n + t]
+    LU, perm = mpmath.mp.LU_decomp(A.copy())
+    out = []
+    for o in ops:
+        rhs = mpmath.zeros(s, 1)
+        for i in range(n):
+            dx, dy = x0 - px[i], y0 - py[i]
+            rr = mpmath.sqrt(dx * dx + dy * dy)
+            rhs[i] = {ow.OP_ID: rr ** m, ow.OP_DX: m * rr ** (m - 2) * dx,
+                      ow.OP_DY: m * rr ** (m - 2) * dy, ow.OP_LAP: m * m * rr ** (m - 2)}[o]
+        for t, (a, b) in enumerate(ex):
+            # L of (x - x0)^a (y - y0)^b at x0: nonzero only for the matching monomial.
+            rhs[n + t] = {ow.OP_ID: 1 if (a, b) == (0, 0) else 0,
+                          ow.OP_DX: 1 if (a, b) == (1, 0) else 0,
+                          ow.OP_DY: 1 if (a, b) == (0, 1) else 0,
+                          ow.OP_LAP: 2 if (a, b) in ((2, 0), (0, 2)) else 0}[o]
+        sol = mpmath.mp.U_solve(LU, mpmath.mp.L_solve(LU, rhs, perm))
+        out.append(np.array([float(sol[i]) for i in range(n)]))
+    return out if isinstance(op, (list, tuple)) else out[0]
+
+
+def test_weights_against_40_digit_solves():
+    """Brute force: a 40-digit solve of the exact system (entries from the
+    coordinates, no FP64 rounding) on sampled rows of all four stencil sets
+    (interior, wall and corner rows).  The FP64 result may differ only by the
+    rounding of the FP64 system, bounded by a small multiple of
+    eps * cond(A_aug)."""
+    nd = ri.cavity_nodes(8, 0.3, 0)
+    pairs = {"vv": (nd.xv, nd.xv), "pv": (nd.xp, nd.xv), "pp": (nd.xp, nd.xp), "vp": (nd.xv, nd.xp)}
+    eps = np.finfo(float).eps
+    for name, (xq, xs) in pairs.items():
+        idx = oknn.knn(xq, xs, 28)
+        w = ow.stencil_weights(xq, xs, idx, 7, 3, OPS)
+        rows = [0, xq.shape[1] // 2, xq.shape[1] - 1]
+        xt, yt, _ = ow.local_coordinates(xq[:, rows], xs, idx[:, rows])
+        A, _ = ow.augmented_system(xt, yt, 7, 3, OPS)
+        for i, r in enumerate(rows):
+            cond = np.linalg.cond(A[i])
+            assert cond < 1e8
+            refs = _mp_weights(xq[:, r], xs, idx[:, r], 7, 3, OPS)
+            for o, op in enumerate(OPS):
+                ref = refs[o]
+                err = np.max(np.abs(w[o][:, r] - ref)) / np.max(np.abs(ref))
+                assert err < 10 * eps * cond, (name, r, op, err, cond)
+
+
+def test_translation_and_scale_invariance():
+    """PHS+poly weights are invariant under translation and scale as s^-k for
+    a k-th derivative (a property of the method, used by the local scaling)."""
+    nd = ri.cavity_nodes(6, 0.3, 2)
+    xq, xs = nd.xp, nd.xv
+    idx = oknn.knn(xq, xs, 28)
+    w0 = ow.stencil_weights(xq, xs, idx, 7, 3, OPS)
+    for shift, s in (((3.7, -1.2), 1.0), ((0.0, 0.0), 3.0), ((-5.0, 2.5), 0.01)):
+        tq = xq * s + np.array(shift)[:, None]
+        ts = xs * s + np.array(shift)[:, None]
+        w1 = ow.stencil_weights(tq, ts, idx, 7, 3, OPS)
+        for o, order in enumerate((0, 1, 1, 2)):
+            a = w1[o] * s ** order
+            assert np.max(np.abs(a - w0[o])) / np.max(np.abs(w0[o])) < 1e-11
+
+
+def test_convergence_order_under_refinement():
+    """Order set by q (Sec. 4): degree-3 reproduction gives O(h^3) for first
+    and O(h^2) for second derivatives on quasi-uniform nodes."""
+    k = 2 * np.pi * 1.5
+    errs = {ow.OP_DX: [], ow.OP_LAP: []}
+    Ks = [16, 32, 64]
+    for K in Ks:
+        nd = ri.square_nodes(K, 0.3, 0)
+        x = nd.xv
+        idx = oknn.knn(x, x, 28)
+        w = ow.stencil_weights(x, x, idx, 7, 3, [ow.OP_DX, ow.OP_LAP])
+        f = ri.wave_field(x, k)
+        inner = np.minimum.reduce([x[0], x[1], 1 - x[0], 1 - x[1]]) > 0.2
+        dx = np.sum(w[0] * f[idx], 0)
+        lap = np.sum(w[1] * f[idx], 0)
+        errs[ow.OP_DX].append(np.max(np.abs(dx - k * np.cos(k * x[0]) * np.cos(k * x[1]))[inner]))
+        errs[ow.OP_LAP].append(np.max(np.abs(lap + 2 * k * k * f)[inner]))
+    sx = np.polyfit(np.log(Ks), np.log(errs[ow.OP_DX]), 1)[0]
+    sl = np.polyfit(np.log(Ks), np.log(errs[ow.OP_LAP]), 1)[0]
+    assert sx < -2.6, sx
+    assert sl < -1.7, sl
+
+
+def test_paper_error_band_at_sqrt2():
+    """Sec. 4 / Sec. 6: at k~ dr = sqrt(2) the modified wavenumber deviates from
+    the spectral limit by at most 1.5% (the paper's grids differ; this is a
+    sanity band, the paper's E(n,m,q) curves exist only in figures)."""
+    band = GOLD["mw_error_max_all"]["value"]
+    nd = ri.cavity_nodes(40, 0.3, 0)
+    for xq, xs in ((nd.xv, nd.xv), (nd.xp, nd.xp)):
+        idx = oknn.knn(xq, xs, 28)
+        w = ow.stencil_weights(xq, xs, idx, 7, 3, [ow.OP_DX, ow.OP_DY, ow.OP_LAP])
+        inner = np.minimum.reduce([xq[0], xq[1], 1 - xq[0], 1 - xq[1]]) > 0.1
+        _, f1, f2 = Mx.modified_wavenumber(xq[:, inner], xs, idx[:, inner], w[0][:, inner],
+                                           w[1][:, inner], w[2][:, inner])
+        assert np.max(np.abs(f1 - 1)) < band and np.max(np.abs(f2 - 1)) < band
+        for o, op in enumerate([ow.OP_DX, ow.OP_DY, ow.OP_LAP]):
+            assert Mx.relative_error_E(xq[:, inner], xs, idx[:, inner], w[o][:, inner], op) < band
+
+
+def test_stability_rule_and_argument_checks():
+    nd = ri.cavity_nodes(6, 0.3, 0)
+    idx = oknn.knn(nd.xv, nd.xv, 28)
+    with pytest.raises(ValueError):
+        ow.stencil_weights(nd.xv, nd.xv, idx, 7, 4)  # 28 < (4+1)(4+2) = 30
+    with pytest.raises(ValueError):
+        ow.stencil_weights(nd.xv, nd.xv, idx, 6, 3)  # even m
+    with pytest.raises(ValueError):
+        ow.stencil_weights(nd.xv, nd.xv, idx, 1, 3, [ow.OP_DX])  # L phi not continuous
+    assert GOLD["stencil_triple"] == {**GOLD["stencil_triple"], "n": 28, "m": 7, "q": 3}
+    assert 28 >= (3 + 1) * (3 + 2)
+
+
+# -------------------------------------------------------------- operators --
+def test_ell_csr_consistency():
+    nd = ri.cavity_nodes(6, 0.3, 0)
+    ss = oops.StencilSet(nd.xp, nd.xv, 28, 7, 3, [ow.OP_DX])
+    D = ss.csr(ow.OP_DX).toarray()
+    for r in range(nd.n_p):
+        assert np.array_equal(np.nonzero(D[r])[0], np.sort(ss.idx[:, r]))
+    x = ri.random_vector(nd.n_v, 1)
+    assert np.allclose(D @ x, oops.ell_apply(ss.idx, ss.w[0], x), rtol=0, atol=1e-12 * np.abs(D).sum())
+
+
+def test_poisson_matrix_structure():
+    """Neumann rows annihilate constants (polynomial reproduction), so the
+    unpinned matrix is singular and the pinned one is not."""
+    nd = ri.cavity_nodes(8, 0.3, 1)
+    ops = oops.CavityOperators(nd)
+    A, pin = oops.poisson_matrix(ops)
+    assert nd.p_tag[pin] == 0
+    d2 = (nd.xp[0] - 0.5) ** 2 + (nd.xp[1] - 0.5) ** 2
+    assert pin == np.argmin(np.where(nd.p_tag == 0, d2, np.inf))
+    Ad = A.toarray()
+    ones = np.ones(nd.n_p)
+    rows = np.arange(nd.n_p) != pin
+    assert np.max(np.abs((Ad @ ones)[rows])) < 1e-9 * np.abs(Ad).max()
+    assert np.linalg.svd(Ad, compute_uv=False).min() > 1e-8 * np.abs(Ad).max()
+
+
+# ----------------------------------------------------------------- solver --
+def _cavity(K, re, dt, seed=0):
+    nd = ri.cavity_nodes(K, 0.3, seed)
+    u_bc, v_bc = ri.cavity_bc(nd.v_tag)
+    return nd, ocav.CavityOracle(nd, u_bc, v_bc, re, dt)
+
+
+def test_advection_stage_closed_form():
+    """Eq. (15) on a polynomial field (exactly differentiated by q = 3)."""
+    nd, orc = _cavity(10, 100.0, 1e-3)
+    x, y = nd.xv
+    u, v = x * x + y, x * y - 0.5 * y * y
+    cu, cv = orc.advection(u, v)
+    assert np.max(np.abs(cu + (u * 2 * x + v * 1.0))) < 1e-9
+    assert np.max(np.abs(cv + (u * y + v * (x - y)))) < 1e-9
+
+
+def test_first_step_stages_and_projection():
+    """One step: the Kim-Moin wall values (eq. (21)) enter u**; the Poisson
+    rows hold at the solution; p = p~ - a Lap p~ (eq. (19)); and the
+    projection (eqs. (17)-(20)) removes most of the divergence of a smooth
+    divergent field away from the walls (it is an approximate projection:
+    D_Lap^PP differs from D^PV D^VP at the truncation level)."""
+    nd, orc = _cavity(24, 100.0, 1e-3)
+    o = orc.ops
+    wall = nd.v_tag != 0
+    s0 = orc.initial_state()
+    s0.pt = ri.random_vector(nd.n_p, 4) * 1e-2  # nonzero p~_j exercises eq. (21)
+    st = {}
+    s1 = orc.step(s0, st)
+    assert np.allclose(st["ru"][wall], orc.u_bc[wall] + orc.dt * (o.Dx_vp @ s0.pt)[wall])
+    assert np.allclose(st["rv"][wall], orc.v_bc[wall] + orc.dt * (o.Dy_vp @ s0.pt)[wall])
+    assert np.allclose(st["uss"][wall], st["ru"][wall], atol=1e-14)
+    res = orc.Lp @ s1.pt - st["prhs"]
+    assert np.max(np.abs(res)) < 1e-8 * np.max(np.abs(st["prhs"]))
+    assert np.allclose(s1.p, s1.pt - orc.a * (o.L_pp @ s1.pt))
+    x, y = nd.xv
+    s0 = orc.initial_state()
+    s0.u = np.where(wall, orc.u_bc, np.sin(np.pi * x) * np.sin(np.pi * y))
+    st = {}
+    s1 = orc.step(s0, st)
+    div = orc.divergence(s1.u, s1.v)
+    far = np.minimum.reduce([nd.xp[0], nd.xp[1], 1 - nd.xp[0], 1 - nd.xp[1]]) > 0.2
+    far[orc.pin] = False  # the pin row replaces that node's Poisson equation
+    assert np.max(np.abs(st["F"][far])) > 1.0
+    assert np.max(np.abs(div[far])) < 0.05 * np.max(np.abs(st["F"][far]))
+
+
+def test_time_convergence():
+    """Appendix D states O(dt^2).  With eq. (16) read as printed (Crank-Nicolson
+    applied to u*), the transient from a common state converges at first
+    order here (dt-halving ratios ~2.1-2.4); this pins convergence (ratio
+    >= 1.8 per halving, monotone), not the paper's order.  The paper's
+    second-order claim is unpinned."""
+    K, re, T = 10, 100.0, 0.08
+    nd = ri.cavity_nodes(K, 0.3, 0)
+    u_bc, v_bc = ri.cavity_bc(nd.v_tag)
+    ops = oops.CavityOperators(nd)
+    s0 = ocav.CavityOracle(nd, u_bc, v_bc, re, 2.5e-4, ops=ops).run(160)
+    res = {}
+    for dt in (4e-3, 2e-3, 1e-3, 2.5e-4):
+        orc = ocav.CavityOracle(nd, u_bc, v_bc, re, dt, ops=ops)
+        s = s0.copy()
+        s.step = 0
+        res[dt] = orc.run(int(round(T / dt)), s).u
+    ref = res[2.5e-4]
+    e = [np.max(np.abs(res[dt] - ref)) for dt in (4e-3, 2e-3, 1e-3)]
+    r1, r2 = e[0] / e[1], e[1] / e[2]
+    assert r1 > 1.8 and r2 > 1.8, (e, r1, r2)
+
+
+def test_stable_small_cavity_run():
+    """Sec. 5.1: runs without hyperviscosity; 200 steps at Re = 100 stay
+    bounded with the wall velocity at its boundary value to O(dt^2)."""
+    nd, orc = _cavity(16, 100.0, 2e-3)
+    s = orc.run(200)
+    assert np.all(np.isfinite(s.u)) and np.max(np.abs(s.u)) < 1.1
+    wall = nd.v_tag != 0
+    assert np.max(np.abs(s.u[wall] - orc.u_bc[wall])) < 5e-3
+
+
+def test_brute_force_dense_tiny_cavity():
+    """K = 5 cavity (N = 85, M = 36): operators from independent 40-digit row
+    solves, implicit systems solved densely with numpy.linalg.solve, 5 steps
+    of eqs. (14)-(21); the oracle (SciPy LU) agrees to 1e-11."""
+    nd, orc = _cavity(5, 100.0, 2e-3)
+    pairs = {"vv": (nd.xv, nd.xv, OPS[1:]), "pv": (nd.xp, nd.xv, OPS[1:3]),
+             "pp": (nd.xp, nd.xp, OPS[1:]), "vp": (nd.xv, nd.xp, OPS[1:3])}
+    D = {}
+    for name, (xq, xs, ops) in pairs.items():
+        idx = oknn.knn_bruteforce(xq, xs, 28)
+        mats = {op: np.zeros((xq.shape[1], xs.shape[1])) for op in ops}
+        for r in range(xq.shape[1]):
+            ws = _mp_weights(xq[:, r], xs, idx[:, r], 7, 3, list(ops), dps=30)
+            for op, wr in zip(ops, ws):
+                mats[op][r, idx[:, r]] = wr
+        for op in ops:
+            D[(name, op)] = mats[op]
+    X, Y, L = ow.OP_DX, ow.OP_DY, ow.OP_LAP
+    dt, a = orc.dt, orc.a
+    wall = nd.v_tag != 0
+    Nn, Mm = nd.n_v, nd.n_p
+    H = np.eye(Nn) - a * np.where(wall[:, None], 0.0, D[("vv", L)])
+    Pm = np.where((nd.p_tag == 0)[:, None], D[("pp", L)],
+                  nd.p_normal[0][:, None] * D[("pp", X)] + nd.p_normal[1][:, None] * D[("pp", Y)])
+    Pm[orc.pin] = 0.0
+    Pm[orc.pin, orc.pin] = 1.0
+    u = np.where(wall, orc.u_bc, 0.0)
+    v = np.zeros(Nn)
+    pt = np.zeros(Mm)
+    cu_p = cv_p = None
+    s = orc.initial_state()
+    for j in range(5):
+        cu = -(u * (D[("vv", X)] @ u) + v * (D[("vv", Y)] @ u))
+        cv = -(u * (D[("vv", X)] @ v) + v * (D[("vv", Y)] @ v))
+        if cu_p is None:
+            cu_p, cv_p = cu, cv
+        us = u + dt * (1.5 * cu - 0.5 * cu_p)
+        vs = v + dt * (1.5 * cv - 0.5 * cv_p)
+        ru = np.where(wall, orc.u_bc + dt * (D[("vp", X)] @ pt), us + a * (D[("vv", L)] @ us))
+        rv = np.where(wall, orc.v_bc + dt * (D[("vp", Y)] @ pt), vs + a * (D[("vv", L)] @ vs))
+        uss, vss = np.linalg.solve(H, ru), np.linalg.solve(H, rv)
+        F = D[("pv", X)] @ uss + D[("pv", Y)] @ vss
+        rhs = np.where(nd.p_tag == 0, F / dt, 0.0)
+        rhs[orc.pin] = 0.0
+        pt = np.linalg.solve(Pm, rhs)
+        u, v = uss - dt * (D[("vp", X)] @ pt), vss - dt * (D[("vp", Y)] @ pt)
+        cu_p, cv_p = cu, cv
+        s = orc.step(s)
+        assert np.max(np.abs(s.u - u)) < 1e-11 * max(1.0, np.max(np.abs(u)))
+        assert np.max(np.abs(s.pt - pt)) < 1e-11 * max(1.0, np.max(np.abs(pt)))
