@@ -1,0 +1,281 @@
+/*
+ * rbffd.h -- C ABI of the MI355X (gfx950) staggered-node PHS+poly RBF-FD
+ * Navier-Stokes library.
+ *
+ * Method: Chu & Schmidt, "RBF-FD discretization of the Navier-Stokes
+ * equations on scattered but staggered nodes".  The library generates local
+ * RBF-FD stencil weights (Sec. 2.1-2.2), stores them as fixed-width ELL
+ * sparse operators, and applies them every time step of the semi-implicit
+ * fractional-step scheme of Sec. 3 (AB2 advection, Crank-Nicolson viscous
+ * step, pressure projection with Kim-Moin intermediate boundary values).
+ *
+ * Conventions (all calls):
+ *  - Every call returns rbf_status: RBF_OK (0) or a negative error code and
+ *    never aborts; rbf_last_error() returns a message for the calling thread,
+ *    valid until that thread's next call.
+ *  - Pointers documented as "device" are HIP device allocations (for example
+ *    torch tensors on a ROCm device); "host" pointers are ordinary memory.
+ *    The caller owns every buffer it passes; the library never frees or
+ *    reallocates caller memory.  A solver handle owns only its internal
+ *    copies and workspace, released by rbf_solver_destroy().
+ *  - Node coordinates are structure-of-arrays: x[2][n] holds all x first,
+ *    then all y (FP64).
+ *  - ELL operators are slot-major: entry s of row r is at [s * rows + r];
+ *    idx is int32 (column index into the source node set), weights FP64
+ *    (or FP32 where stated).  Sizes are int64.
+ *  - rbf_stream is a hipStream_t passed as an opaque pointer (NULL = the
+ *    default stream).  All device work of a call is ordered on that stream;
+ *    calls do not synchronise the device except where stated (setup calls
+ *    that read back a few scalars, and the solver calls that read back
+ *    convergence flags).
+ *  - Operator codes (bit mask, outputs in increasing bit order):
+ *    RBF_OP_ID = 1 (interpolation, L = identity), RBF_OP_DX = 2 (d/dx),
+ *    RBF_OP_DY = 4 (d/dy), RBF_OP_LAP = 8 (Laplacian).
+ */
+#ifndef RBFFD_H
+#define RBFFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rbf_status;
+#define RBF_OK 0
+#define RBF_E_ARG (-1)      /* invalid argument (sizes, pointers, parameters) */
+#define RBF_E_SINGULAR (-2) /* a local saddle-point system is singular        */
+#define RBF_E_NOCONV (-3)   /* Krylov solve hit its iteration cap             */
+#define RBF_E_DEVICE (-4)   /* HIP runtime error                              */
+#define RBF_E_NOMEM (-5)    /* device allocation failed                       */
+#define RBF_E_NAN (-6)      /* non-finite value in a Krylov solve             */
+
+#define RBF_OP_ID 1u
+#define RBF_OP_DX 2u
+#define RBF_OP_DY 4u
+#define RBF_OP_LAP 8u
+
+#define RBF_ABI_VERSION 1
+
+typedef void *rbf_stream;
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *rbf_last_error(void);
+
+/* RBF_ABI_VERSION of the loaded library. */
+int32_t rbf_abi_version(void);
+
+/*
+ * rbf_build_nodes -- seeded staggered node sets (host only, no device work).
+ *
+ * Stand-in for the DistMesh grids of Sec. 3.  kind 0: lid-driven cavity on
+ * the unit square with the paper's staggering: P-nodes are the vertices
+ * (i/K, j/K), i, j = 0..K, of a triangulation whose interior vertices are
+ * jittered by U(-jitter/K, jitter/K) per coordinate, V-nodes are the
+ * midpoints of all triangle edges (cell diagonals alternate in a checkerboard);
+ * N = 3K^2 + 2K, M = (K+1)^2.  kind 1: operator-bench square, N = M = K^2,
+ * V on jittered cell centres ((i+1/2)/K, (j+1/2)/K), P on jittered vertices
+ * (i/K, j/K), i, j = 0..K-1, no walls.  Random numbers: SplitMix64 as a
+ * counter-based generator (draw c of stream g uses counter (g << 40) | c;
+ * stream 0 = V, 1 = P; draws 2n and 2n+1 jitter node n).
+ *
+ * Two-call pattern: pass NULL for every array to obtain *n_v and *n_p, then
+ * call again with host arrays of that size:
+ *   xv [2][n_v], v_tag [n_v] (0 interior, 1 wall, 2 lid = top wall),
+ *   xp [2][n_p], p_tag [n_p] (0 interior, 1 wall),
+ *   p_normal [2][n_p] (outward unit normal of wall P-nodes, 0 elsewhere).
+ * Errors: RBF_E_ARG for an unknown kind, K < 2 (cavity) or K < 1 (square),
+ * jitter outside [0, 0.45], or a partial set of NULL arrays.
+ */
+rbf_status rbf_build_nodes(int32_t kind, int32_t K, double jitter, uint64_t seed,
+                           int64_t *n_v, double *xv, int8_t *v_tag,
+                           int64_t *n_p, double *xp, int8_t *p_tag, double *p_normal);
+
+/*
+ * rbf_knn -- n-nearest-neighbour stencils (Sec. 2.2: row r of D^(alpha,beta)
+ * uses the k nearest beta-nodes of the alpha-node r; Sec. 4 uses k = 28).
+ *
+ * xq: device [2][nq] query (alpha) nodes; xs: device [2][ns] source (beta)
+ * nodes; idx: device int32 [k][nq], slot-major output.  The stencil is the
+ * first k source nodes in the order of the key (d^2, index), with
+ * d^2 = dx*dx + dy*dy in FP64 with separately rounded products (no fused
+ * multiply-add), so ties are broken by the lower index and the result is a
+ * unique function of the inputs.  When alpha = beta and nodes are distinct,
+ * slot 0 is the node itself.  Synchronises the stream once (bounding box).
+ * Errors: RBF_E_ARG if k < 1, k > 64, k > ns, nq < 0, ns < 1 or a NULL
+ * pointer with a non-zero size.
+ */
+rbf_status rbf_knn(const double *xq, int64_t nq, const double *xs, int64_t ns, int32_t k,
+                   int32_t *idx, rbf_stream st);
+
+/*
+ * rbf_assemble_weights -- local PHS+poly RBF-FD weights (Sec. 2.1, eqs. (3)-(9)).
+ *
+ * For each query node r, solves the augmented saddle-point system
+ *   [A P; P^T 0] [w; c] = [L phi; L P]
+ * with A_ij = ||x_i - x_j||^m (m odd), P the (q+1)(q+2)/2 monomials of degree
+ * <= q (graded order 1; x, y; x^2, xy, y^2; ...), and right-hand sides L
+ * applied to phi(||x - x_j||) and to the monomials at x = x_r, for every
+ * operator in op_mask at once; w (the first k unknowns) is kept, c is
+ * discarded.  Coordinates are shifted to x_r and divided by the power of two
+ * s = 2^e with 1/4 <= max_j |x_j - x_r|^2 / s^2 < 1 (exact); weights are
+ * returned in physical units (local weights times s^-order).  Each system is
+ * solved by LU with partial pivoting in FP64 followed by one step of
+ * iterative refinement with a double-FP64 residual.
+ *
+ * xq: device [2][nq]; xs: device [2][ns]; idx: device int32 [k][nq] (from
+ * rbf_knn); w: device FP64 [popcount(op_mask)][k][nq], operators in
+ * increasing bit order.  bad_row: host, set to the lowest row whose system
+ * was numerically singular or non-finite, -1 if none (synchronises the
+ * stream to read it back).
+ * Limits: 1 <= k, k + (q+1)(q+2)/2 <= 64, q in [-1, 5] (-1: no polynomials),
+ * m odd in [1, 11] (m >= 3 for derivative operators), and
+ * k >= (q+1)(q+2) (stability rule of Sec. 4) unless op_mask has bit 31 set.
+ * Errors: RBF_E_ARG for violated limits or an empty op_mask;
+ * RBF_E_SINGULAR if any row failed (weights of that row are then NaN).
+ */
+#define RBF_FORCE_SMALL_STENCIL 0x80000000u
+rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const double *xs, int64_t ns,
+                                const int32_t *idx, int32_t k, int32_t m, int32_t q,
+                                uint32_t op_mask, double *w, int64_t *bad_row, rbf_stream st);
+
+/*
+ * rbf_ell_apply -- y = D x for one ELL operator (eq. (10) applied to a vector).
+ *
+ * rows: number of rows; k: entries per row; idx: device int32 [k][rows];
+ * w: device [k][rows]; x: device vector indexed by idx; y: device [rows].
+ * dtype 0: w, x, y FP64, FP64 accumulation; dtype 1: w, x, y FP32, FP32
+ * accumulation.  No synchronisation.  Errors: RBF_E_ARG for bad sizes/dtype.
+ */
+rbf_status rbf_ell_apply(int64_t rows, int32_t k, const int32_t *idx, const void *w,
+                         const void *x, void *y, int32_t dtype, rbf_stream st);
+
+/*
+ * rbf_cast_f32 -- dst[i] = (float)src[i] (round to nearest) for i < n; used
+ * to build FP32-stored copies of ELL weights and vectors.  src: device FP64
+ * [n]; dst: device FP32 [n].  No synchronisation.  Errors: RBF_E_ARG.
+ */
+rbf_status rbf_cast_f32(const double *src, float *dst, int64_t n, rbf_stream st);
+
+/* ---------------------------------------------------------------------------
+ * Fractional-step solver (Sec. 3).
+ * ------------------------------------------------------------------------- */
+
+/* Node sets and boundary data, all device memory. */
+typedef struct {
+    int64_t n_v, n_p;
+    const double *xv;       /* [2][n_v]                                      */
+    const double *xp;       /* [2][n_p]                                      */
+    const int8_t *v_tag;    /* [n_v]: 0 interior, != 0 wall (Dirichlet)     */
+    const int8_t *p_tag;    /* [n_p]: 0 interior, != 0 wall (Neumann)        */
+    const double *p_normal; /* [2][n_p] outward unit normal at wall P-nodes  */
+} rbf_grid;
+
+/* The eight operators of Sec. 4 plus D_x, D_y on (P,P) for the pressure
+ * boundary rows; device memory, slot-major [k][rows].  The solver copies
+ * them at creation, so the caller may free them afterwards. */
+typedef struct {
+    int32_t k;
+    const int32_t *idx_vv; const double *vv_dx, *vv_dy, *vv_lap; /* rows n_v, cols n_v */
+    const int32_t *idx_pv; const double *pv_dx, *pv_dy;          /* rows n_p, cols n_v */
+    const int32_t *idx_pp; const double *pp_dx, *pp_dy, *pp_lap; /* rows n_p, cols n_p */
+    const int32_t *idx_vp; const double *vp_dx, *vp_dy;          /* rows n_v, cols n_p */
+} rbf_ops;
+
+typedef struct {
+    double re;        /* Reynolds number                                     */
+    double dt;        /* time step                                           */
+    double rtol_h;    /* relative residual tolerance, Helmholtz solves       */
+    double rtol_p;    /* relative residual tolerance, pressure Poisson solve */
+    int32_t maxit_h;  /* iteration caps                                      */
+    int32_t maxit_p;
+    int32_t precision;/* 0 = FP64 (only value accepted)                      */
+    int32_t reserved;
+} rbf_params;
+
+/* Solver state at step j, device memory owned by the caller. */
+typedef struct {
+    double *u, *v;             /* [n_v] velocity                             */
+    double *p_tilde, *p;       /* [n_p] pressure correction and pressure     */
+    double *cu_prev, *cv_prev; /* [n_v] advection terms C_{j-1} (AB2)        */
+    int64_t step;              /* j; the AB2 start uses C_{-1} = C_0 at j=0 */
+} rbf_state;
+
+typedef struct {
+    int32_t iterations;    /* BiCGSTAB iterations of this solve             */
+    int32_t converged;     /* 1 if the tolerance was met                    */
+    double rel_residual;   /* ||b - A x|| / ||b|| recomputed at the end     */
+} rbf_solve_stats;
+
+typedef struct {
+    int32_t steps_done;            /* steps committed by this call          */
+    int32_t status;                /* status of the last step attempted     */
+    int64_t helmholtz_iters;       /* summed over steps (both components)   */
+    int64_t poisson_iters;         /* summed over steps                     */
+    rbf_solve_stats last_helmholtz_u, last_helmholtz_v, last_poisson;
+} rbf_step_stats;
+
+typedef struct rbf_solver rbf_solver;
+
+/*
+ * rbf_solver_create -- build the implicit system matrices of Sec. 3.
+ *
+ * Helmholtz (eq. (16)): H = I - a D_Lap^(V,V), a = dt/(2 Re), on interior
+ * V rows, identity on wall rows (which carry the Kim-Moin values of
+ * eq. (21)).  Pressure Poisson (eq. (18)): D_Lap^(P,P) on interior P rows;
+ * homogeneous Neumann rows n_x D_x^(P,P) + n_y D_y^(P,P) on wall rows; one pin
+ * row (identity) at the interior P-node nearest (0.5, 0.5), lowest index on
+ * a tie.  Both are solved by BiCGSTAB: H with Jacobi preconditioning; the
+ * Poisson matrix is stored row-scaled (interior rows by -1/||row||_2, wall
+ * rows by +1/||row||_2) and iterated without further preconditioning, so its
+ * residual tolerance applies to the row-scaled system.
+ * u_bc, v_bc: device [n_v] boundary velocities (read on wall rows; copied).
+ * The solver keeps `st` for all of its work.
+ * Errors: RBF_E_ARG (NULL pointers, sizes, dt/re <= 0, precision != 0,
+ * a self index missing from a (V,V) or (P,P) stencil), RBF_E_NOMEM.
+ */
+rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, const rbf_ops *ops,
+                             const double *u_bc, const double *v_bc, const rbf_params *prm,
+                             rbf_stream st);
+
+/*
+ * rbf_step -- advance `state` by nsteps steps of Sec. 3, eqs. (14)-(21).
+ *
+ * Transactional: each step is computed in solver workspace and committed
+ * only if every solve converged and stayed finite; on error `state` holds the
+ * last committed step and stats (host, nullable) says where it stopped.
+ * Reads back a convergence flag every few Krylov iterations (synchronises).
+ * Errors: RBF_E_ARG, RBF_E_NOCONV, RBF_E_NAN, RBF_E_DEVICE.
+ */
+rbf_status rbf_step(rbf_solver *s, int32_t nsteps, rbf_state *state, rbf_step_stats *stats);
+
+/*
+ * rbf_solve_pressure -- solve the pressure-Poisson system of eq. (18) (with
+ * the boundary and pin rows above) for right-hand side rhs (device [n_p];
+ * entries on wall and pin rows are the values those rows are set to).
+ * p_tilde: device [n_p], initial guess in, solution out.  stats nullable.
+ * Errors: RBF_E_ARG, RBF_E_NOCONV, RBF_E_NAN.
+ */
+rbf_status rbf_solve_pressure(rbf_solver *s, const double *rhs, double *p_tilde,
+                              rbf_solve_stats *stats);
+
+/*
+ * rbf_solver_profile -- sample the duration of the pressure-Poisson SpMV
+ * kernel (v = A p^ inside BiCGSTAB) with HIP events on the solver's stream.
+ * Returns, in *avg_ms and *count (nullable host outputs), the average
+ * duration and number of samples collected so far; then, if
+ * sample_every >= 0, resets the counters and times every sample_every-th
+ * launch from now on (0 disables sampling; each sample synchronises once).
+ * Errors: RBF_E_ARG (NULL solver), RBF_E_DEVICE.
+ */
+rbf_status rbf_solver_profile(rbf_solver *s, int32_t sample_every, double *avg_ms,
+                              int64_t *count);
+
+/* Release a solver (NULL is ignored). */
+void rbf_solver_destroy(rbf_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBFFD_H */

@@ -1,0 +1,196 @@
+"""Python binding of the gfx950 RBF-FD library (argument marshalling only).
+
+Every function takes/returns torch tensors on a ROCm device and forwards
+device pointers and the current HIP stream to the C ABI; all arithmetic
+runs in the HIP kernels of librbffd.so.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import OP_ID, OP_DX, OP_DY, OP_LAP, check, lib
+
+__all__ = ["build_nodes", "knn", "assemble_weights", "ell_apply", "cast_f32", "Solver",
+           "OP_ID", "OP_DX", "OP_DY", "OP_LAP"]
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a ROCm device")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def build_nodes(kind, K, jitter=0.3, seed=0):
+    """Host node sets from rbf_build_nodes: dict of numpy arrays."""
+    nv = ctypes.c_int64()
+    npn = ctypes.c_int64()
+    check(lib.rbf_build_nodes(kind, K, jitter, seed, ctypes.byref(nv), None, None,
+                              ctypes.byref(npn), None, None, None))
+    N, M = nv.value, npn.value
+    xv = np.empty((2, N), np.float64)
+    vt = np.empty(N, np.int8)
+    xp = np.empty((2, M), np.float64)
+    pt = np.empty(M, np.int8)
+    pn = np.empty((2, M), np.float64)
+    c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    check(lib.rbf_build_nodes(kind, K, jitter, seed, ctypes.byref(nv), c(xv), c(vt),
+                              ctypes.byref(npn), c(xp), c(pt), c(pn)))
+    return {"xv": xv, "v_tag": vt, "xp": xp, "p_tag": pt, "p_normal": pn}
+
+
+def knn(xq, xs, k):
+    """int32 [k, nq] stencil indices (slot-major) of the k nearest xs-nodes."""
+    _dev(xq, torch.float64, name="xq")
+    _dev(xs, torch.float64, name="xs")
+    if xq.dim() != 2 or xq.shape[0] != 2 or xs.dim() != 2 or xs.shape[0] != 2:
+        raise ValueError("coordinates must have shape [2, n]")
+    nq, ns = xq.shape[1], xs.shape[1]
+    idx = torch.empty((k, nq), dtype=torch.int32, device=xq.device)
+    check(lib.rbf_knn(_ptr(xq), nq, _ptr(xs), ns, k, _ptr(idx), _stream()))
+    return idx
+
+
+def assemble_weights(xq, xs, idx, m=7, q=3, op_mask=OP_DX | OP_DY | OP_LAP, force=False):
+    """FP64 weights [nops, k, nq] for the operators in op_mask (bit order)."""
+    _dev(xq, torch.float64, name="xq")
+    _dev(xs, torch.float64, name="xs")
+    _dev(idx, torch.int32, name="idx")
+    k, nq = idx.shape
+    if xq.shape != (2, nq) or xs.dim() != 2 or xs.shape[0] != 2:
+        raise ValueError("shape mismatch between xq, xs and idx")
+    nops = bin(op_mask & 15).count("1")
+    w = torch.empty((max(nops, 1), k, nq), dtype=torch.float64, device=xq.device)
+    bad = ctypes.c_int64(-1)
+    mask = op_mask | (_lib.FORCE_SMALL_STENCIL if force else 0)
+    check(lib.rbf_assemble_weights(_ptr(xq), nq, _ptr(xs), xs.shape[1], _ptr(idx), k, m, q,
+                                   ctypes.c_uint32(mask), _ptr(w), ctypes.byref(bad), _stream()))
+    return w
+
+
+def ell_apply(idx, w, x, out=None):
+    """y = D x for ELL (idx [k, rows], w [k, rows]); FP64 or FP32 (w, x, y alike)."""
+    _dev(idx, torch.int32, name="idx")
+    k, rows = idx.shape
+    if w.dtype not in (torch.float64, torch.float32):
+        raise ValueError("w must be float64 or float32")
+    _dev(w, w.dtype, (k, rows), name="w")
+    _dev(x, w.dtype, name="x")
+    if out is None:
+        out = torch.empty(rows, dtype=w.dtype, device=w.device)
+    _dev(out, w.dtype, (rows,), name="out")
+    dtype = 0 if w.dtype == torch.float64 else 1
+    check(lib.rbf_ell_apply(rows, k, _ptr(idx), _ptr(w), _ptr(x), _ptr(out), dtype, _stream()))
+    return out
+
+
+def cast_f32(a):
+    """FP32 copy of an FP64 device tensor (round to nearest), on the GPU."""
+    _dev(a, torch.float64, name="a")
+    out = torch.empty(a.shape, dtype=torch.float32, device=a.device)
+    check(lib.rbf_cast_f32(_ptr(a), _ptr(out), a.numel(), _stream()))
+    return out
+
+
+class Solver:
+    """Fractional-step solver handle (rbf_solver_create / rbf_step / ...).
+
+    grid: dict with device tensors xv [2,N], xp [2,M], v_tag int8 [N],
+    p_tag int8 [M], p_normal [2,M].  ops: dict with k and the ELL arrays
+    idx_vv, vv_dx, vv_dy, vv_lap, idx_pv, pv_dx, pv_dy, idx_pp, pp_dx, pp_dy,
+    pp_lap, idx_vp, vp_dx, vp_dy (device, [k, rows]).
+    """
+
+    def __init__(self, grid, ops, u_bc, v_bc, re, dt, rtol_h=1e-13, rtol_p=1e-13,
+                 maxit_h=2000, maxit_p=20000):
+        N = grid["xv"].shape[1]
+        M = grid["xp"].shape[1]
+        self.N, self.M = N, M
+        self.device = grid["xv"].device
+        _dev(grid["xv"], torch.float64, (2, N), "xv")
+        _dev(grid["xp"], torch.float64, (2, M), "xp")
+        _dev(grid["v_tag"], torch.int8, (N,), "v_tag")
+        _dev(grid["p_tag"], torch.int8, (M,), "p_tag")
+        _dev(grid["p_normal"], torch.float64, (2, M), "p_normal")
+        k = int(ops["k"])
+        for name, rows in (("vv", N), ("pv", M), ("pp", M), ("vp", N)):
+            _dev(ops["idx_" + name], torch.int32, (k, rows), "idx_" + name)
+        for name, rows in (("vv_dx", N), ("vv_dy", N), ("vv_lap", N), ("pv_dx", M), ("pv_dy", M),
+                           ("pp_dx", M), ("pp_dy", M), ("pp_lap", M), ("vp_dx", N), ("vp_dy", N)):
+            _dev(ops[name], torch.float64, (k, rows), name)
+        _dev(u_bc, torch.float64, (N,), "u_bc")
+        _dev(v_bc, torch.float64, (N,), "v_bc")
+        g = _lib.Grid(N, M, grid["xv"].data_ptr(), grid["xp"].data_ptr(), grid["v_tag"].data_ptr(),
+                      grid["p_tag"].data_ptr(), grid["p_normal"].data_ptr())
+        o = _lib.Ops(k, *[ops[n].data_ptr() for n in (
+            "idx_vv", "vv_dx", "vv_dy", "vv_lap", "idx_pv", "pv_dx", "pv_dy",
+            "idx_pp", "pp_dx", "pp_dy", "pp_lap", "idx_vp", "vp_dx", "vp_dy")])
+        prm = _lib.Params(float(re), float(dt), float(rtol_h), float(rtol_p), int(maxit_h),
+                          int(maxit_p), 0, 0)
+        h = ctypes.c_void_p()
+        check(lib.rbf_solver_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(o),
+                                    _ptr(u_bc), _ptr(v_bc), ctypes.byref(prm), _stream()))
+        self._h = h
+
+    def new_state(self, u, v):
+        """Caller-owned state tensors with u, v given and p~ = p = C = 0."""
+        z = lambda n: torch.zeros(n, dtype=torch.float64, device=self.device)  # noqa: E731
+        return {"u": u.clone(), "v": v.clone(), "p_tilde": z(self.M), "p": z(self.M),
+                "cu_prev": z(self.N), "cv_prev": z(self.N), "step": 0}
+
+    def step(self, state, nsteps=1):
+        """Advance the state dict in place; returns the step statistics."""
+        for key, n in (("u", self.N), ("v", self.N), ("cu_prev", self.N), ("cv_prev", self.N),
+                       ("p_tilde", self.M), ("p", self.M)):
+            _dev(state[key], torch.float64, (n,), key)
+        st = _lib.State(*[state[k].data_ptr() for k in ("u", "v", "p_tilde", "p", "cu_prev",
+                                                          "cv_prev")], int(state["step"]))
+        stats = _lib.StepStats()
+        rc = lib.rbf_step(self._h, int(nsteps), ctypes.byref(st), ctypes.byref(stats))
+        state["step"] = st.step
+        check(rc)
+        return stats
+
+    def solve_pressure(self, rhs, p_tilde):
+        _dev(rhs, torch.float64, (self.M,), "rhs")
+        _dev(p_tilde, torch.float64, (self.M,), "p_tilde")
+        stats = _lib.SolveStats()
+        check(lib.rbf_solve_pressure(self._h, _ptr(rhs), _ptr(p_tilde), ctypes.byref(stats)))
+        return stats
+
+    def profile(self, sample_every=-1):
+        """(avg_ms, count) of the sampled Poisson SpMV launches so far; with
+        sample_every >= 0, reset and sample every sample_every-th launch."""
+        avg = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        check(lib.rbf_solver_profile(self._h, int(sample_every), ctypes.byref(avg),
+                                     ctypes.byref(cnt)))
+        return avg.value, cnt.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.rbf_solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,54 @@
+// Device helpers for slot-major ELL operators: entry s of row r is at
+// [s * rows + r], so consecutive rows (threads) read consecutive addresses
+// for every slot and the index/weight streams are fully coalesced.
+#pragma once
+
+#include "common.h"
+
+namespace rbf {
+
+// Sum over the stencil of row `r`: acc += w[s][r] * f(idx[s][r]) for
+// each slot.  KT > 0 fixes the stencil width at compile time (all loads of
+// the row are issued before the gathers); KT == 0 uses the runtime width k.
+// NW weight arrays share one index array (e.g. D_x and D_y of one stencil
+// set); the gather functor g(j, v) fills Gather::NV values taken at column j
+// (several vectors on one matrix).  FP64 weights and accumulation.
+template <int KT, int NW, class Gather>
+__device__ __forceinline__ void ell_row(const int *__restrict__ idx, const double *const (&w)[NW],
+                                        int64_t rows, int64_t r, int k, Gather g,
+                                        double (&acc)[NW][Gather::NV]) {
+    if constexpr (KT > 0) {
+        int jj[KT];
+        double ww[NW][KT];
+#pragma unroll
+        for (int s = 0; s < KT; ++s) jj[s] = ld_stream(idx + (int64_t)s * rows + r);
+#pragma unroll
+        for (int s = 0; s < KT; ++s)
+#pragma unroll
+            for (int o = 0; o < NW; ++o) ww[o][s] = ld_stream(w[o] + (int64_t)s * rows + r);
+#pragma unroll
+        for (int s = 0; s < KT; ++s) {
+            double v[Gather::NV];
+            g(jj[s], v);
+#pragma unroll
+            for (int o = 0; o < NW; ++o)
+#pragma unroll
+                for (int c = 0; c < Gather::NV; ++c) acc[o][c] = fma(ww[o][s], v[c], acc[o][c]);
+        }
+    } else {
+#pragma unroll 4
+        for (int s = 0; s < k; ++s) {
+            const int j = ld_stream(idx + (int64_t)s * rows + r);
+            double v[Gather::NV];
+            g(j, v);
+#pragma unroll
+            for (int o = 0; o < NW; ++o) {
+                const double ws = ld_stream(w[o] + (int64_t)s * rows + r);
+#pragma unroll
+                for (int c = 0; c < Gather::NV; ++c) acc[o][c] = fma(ws, v[c], acc[o][c]);
+            }
+        }
+    }
+}
+
+}  // namespace rbf

@@ -1,0 +1,291 @@
+// rbf_knn: exact k-nearest-neighbour stencils on the GPU.
+//
+// Sec. 2.2 builds row r of D^(alpha,beta) from the n nearest beta-nodes of
+// the alpha-node r.  The stencil is defined as the first k beta-nodes in the
+// order of the key (d^2, index), with d^2 = dx*dx + dy*dy evaluated with
+// separately rounded products (this file is compiled with
+// -ffp-contract=off), so the result is unique even on lattices with ties.
+//
+// Method: a uniform cell grid over the source bounding box (counting sort of
+// the sources by cell), then one thread per query searching square rings of
+// cells outward.  The thread keeps its best k candidates as a sorted list in
+// registers (fully unrolled insertion, static indices) and stops once the
+// k-th best squared distance is strictly below the squared distance to every
+// cell not yet visited.
+#include <climits>
+
+#include "common.h"
+
+namespace {
+
+struct Grid {
+    double x0, y0, c, inv_c;
+    int gx, gy;
+};
+
+__device__ __forceinline__ bool key_less(double d, int i, double bd, int bi) {
+    return d < bd || (d == bd && i < bi);
+}
+
+__device__ __forceinline__ int cell_coord(double v, double v0, double inv_c, int g) {
+    double t = floor((v - v0) * inv_c);
+    int c = (t < 0.0) ? 0 : (t >= (double)g ? g - 1 : (int)t);
+    return c;
+}
+
+__global__ void k_bbox_partial(const double *__restrict__ x, int64_t n, double *__restrict__ part) {
+    __shared__ double lds[4 * 16];
+    double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double px = x[i], py = x[n + i];
+        v[0] = fmin(v[0], px);
+        v[1] = fmax(v[1], px);
+        v[2] = fmin(v[2], py);
+        v[3] = fmax(v[3], py);
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        v[0] = fmin(v[0], __shfl_xor(v[0], off, 64));
+        v[1] = fmax(v[1], __shfl_xor(v[1], off, 64));
+        v[2] = fmin(v[2], __shfl_xor(v[2], off, 64));
+        v[3] = fmax(v[3], __shfl_xor(v[3], off, 64));
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0)
+        for (int q = 0; q < 4; ++q) lds[q * 16 + wid] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; ++w) {
+            v[0] = fmin(v[0], lds[w]);
+            v[1] = fmax(v[1], lds[16 + w]);
+            v[2] = fmin(v[2], lds[32 + w]);
+            v[3] = fmax(v[3], lds[48 + w]);
+        }
+        for (int q = 0; q < 4; ++q) part[blockIdx.x * 4 + q] = v[q];
+    }
+}
+
+__global__ void k_cell_count(const double *__restrict__ x, int64_t n, Grid g,
+                             int *__restrict__ cell, int *__restrict__ count) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cx = cell_coord(x[i], g.x0, g.inv_c, g.gx);
+    int cy = cell_coord(x[n + i], g.y0, g.inv_c, g.gy);
+    int c = cy * g.gx + cx;
+    cell[i] = c;
+    atomicAdd(&count[c], 1);
+}
+
+// Exclusive scan of count[0..n) into start[0..n], one block of 1024 threads.
+__global__ void k_scan(const int *__restrict__ count, int64_t n, int *__restrict__ start) {
+    __shared__ int lds[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t a = t * chunk, b = (a + chunk < n) ? a + chunk : n;
+    int s = 0;
+    for (int64_t i = a; i < b; ++i) s += count[i];
+    lds[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = (t >= off) ? lds[t - off] : 0;
+        __syncthreads();
+        lds[t] += v;
+        __syncthreads();
+    }
+    int run = lds[t] - s;
+    for (int64_t i = a; i < b; ++i) {
+        start[i] = run;
+        run += count[i];
+    }
+    if (t == 1023) start[n] = lds[1023];
+}
+
+__global__ void k_scatter(const double *__restrict__ x, int64_t n, const int *__restrict__ cell,
+                          const int *__restrict__ start, int *__restrict__ fill,
+                          double *__restrict__ sx, double *__restrict__ sy, int *__restrict__ sid) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = cell[i];
+    int pos = start[c] + atomicAdd(&fill[c], 1);
+    sx[pos] = x[i];
+    sy[pos] = x[n + i];
+    sid[pos] = (int)i;
+}
+
+template <int KMAX>
+__global__ void __launch_bounds__(128) k_query(const double *__restrict__ xq, int64_t nq, int k,
+                                               Grid g, const int *__restrict__ start,
+                                               const double *__restrict__ sx,
+                                               const double *__restrict__ sy,
+                                               const int *__restrict__ sid,
+                                               int *__restrict__ idx) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const double qx = xq[q], qy = xq[nq + q];
+    const int cx = cell_coord(qx, g.x0, g.inv_c, g.gx);
+    const int cy = cell_coord(qy, g.y0, g.inv_c, g.gy);
+    double bd[KMAX];
+    int bi[KMAX];
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s) {
+        bd[s] = INFINITY;
+        bi[s] = INT_MAX;
+    }
+    double thr_d = INFINITY;
+    int thr_i = INT_MAX;
+    const int rmax = max(max(cx, g.gx - 1 - cx), max(cy, g.gy - 1 - cy));
+    for (int r = 0; r <= rmax; ++r) {
+        const int ylo = cy - r, yhi = cy + r;
+        for (int iy = max(ylo, 0); iy <= min(yhi, g.gy - 1); ++iy) {
+            const bool full_row = (iy == ylo) || (iy == yhi);
+            const int step = full_row ? 1 : 2 * r;
+            for (int ix = cx - r; ix <= cx + r; ix += (step > 0 ? step : 1)) {
+                if (ix < 0 || ix >= g.gx) continue;
+                const int c = iy * g.gx + ix;
+                const int pe = start[c + 1];
+                for (int p = start[c]; p < pe; ++p) {
+                    const double dx = sx[p] - qx;
+                    const double dy = sy[p] - qy;
+                    const double d2 = dx * dx + dy * dy;
+                    const int id = sid[p];
+                    if (!key_less(d2, id, thr_d, thr_i)) continue;
+                    // Sorted insertion; the former last entry drops out.
+#pragma unroll
+                    for (int s = KMAX - 1; s > 0; --s) {
+                        const bool before_prev = key_less(d2, id, bd[s - 1], bi[s - 1]);
+                        const bool before_cur = key_less(d2, id, bd[s], bi[s]);
+                        if (before_prev) {
+                            bd[s] = bd[s - 1];
+                            bi[s] = bi[s - 1];
+                        } else if (before_cur) {
+                            bd[s] = d2;
+                            bi[s] = id;
+                        }
+                    }
+                    if (key_less(d2, id, bd[0], bi[0])) {
+                        bd[0] = d2;
+                        bi[0] = id;
+                    }
+#pragma unroll
+                    for (int s = 0; s < KMAX; ++s)
+                        if (s == k - 1) {
+                            thr_d = bd[s];
+                            thr_i = bi[s];
+                        }
+                }
+                if (step == 0) break;
+            }
+        }
+        if (thr_d == INFINITY) continue;  // fewer than k candidates so far
+        // Distance from the query to the nearest cell outside the block.
+        double bound = INFINITY;
+        if (cx - r > 0) bound = fmin(bound, qx - (g.x0 + (double)(cx - r) * g.c));
+        if (cx + r < g.gx - 1) bound = fmin(bound, (g.x0 + (double)(cx + r + 1) * g.c) - qx);
+        if (cy - r > 0) bound = fmin(bound, qy - (g.y0 + (double)(cy - r) * g.c));
+        if (cy + r < g.gy - 1) bound = fmin(bound, (g.y0 + (double)(cy + r + 1) * g.c) - qy);
+        if (bound == INFINITY) break;
+        bound -= 1e-9 * g.c;  // margin for the rounding of cell assignment
+        if (bound > 0.0 && thr_d < bound * bound) break;
+    }
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s)
+        if (s < k) idx[(int64_t)s * nq + q] = bi[s];
+}
+
+}  // namespace
+
+extern "C" rbf_status rbf_knn(const double *xq, int64_t nq, const double *xs, int64_t ns,
+                              int32_t k, int32_t *idx, rbf_stream st_) {
+    rbf::clear_error();
+    RBF_ARG(k >= 1 && k <= 64, "rbf_knn: k must be in [1, 64] (got %d)", k);
+    RBF_ARG(ns >= 1 && k <= ns, "rbf_knn: need 1 <= k <= ns (k=%d, ns=%lld)", k, (long long)ns);
+    RBF_ARG(nq >= 0 && nq < INT_MAX && ns < INT_MAX, "rbf_knn: sizes out of range");
+    RBF_ARG(xs && (nq == 0 || (xq && idx)), "rbf_knn: NULL pointer");
+    if (nq == 0) return RBF_OK;
+    hipStream_t st = rbf::as_stream(st_);
+
+    // Bounding box of the sources.
+    const int nbb = 256;
+    double *part = nullptr, *hbb = nullptr;
+    RBF_HIP(hipMalloc(&part, nbb * 4 * sizeof(double)));
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(1024), 0, st, xs, ns, part);
+    RBF_CHECK_LAUNCH();
+    double hpart[nbb * 4];
+    RBF_HIP(hipMemcpyAsync(hpart, part, sizeof(hpart), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+    RBF_HIP(hipFree(part));
+    (void)hbb;
+    double bb[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int b = 0; b < nbb; ++b) {
+        bb[0] = fmin(bb[0], hpart[4 * b]);
+        bb[1] = fmax(bb[1], hpart[4 * b + 1]);
+        bb[2] = fmin(bb[2], hpart[4 * b + 2]);
+        bb[3] = fmax(bb[3], hpart[4 * b + 3]);
+    }
+    RBF_ARG(std::isfinite(bb[0]) && std::isfinite(bb[1]) && std::isfinite(bb[2]) &&
+                std::isfinite(bb[3]),
+            "rbf_knn: non-finite source coordinates");
+    const double ex = bb[1] - bb[0], ey = bb[3] - bb[2];
+    double c = sqrt(fmax(ex * ey, 0.0) * 2.0 / (double)ns);
+    c = fmax(c, fmax(ex, ey) / 4096.0);
+    if (!(c > 0.0)) c = 1.0;
+    Grid g;
+    g.x0 = bb[0];
+    g.y0 = bb[2];
+    g.c = c;
+    g.inv_c = 1.0 / c;
+    g.gx = (int)(ex * g.inv_c) + 1;
+    g.gy = (int)(ey * g.inv_c) + 1;
+    const int64_t ncell = (int64_t)g.gx * g.gy;
+
+    int *cell = nullptr, *count = nullptr, *start = nullptr, *fill = nullptr, *sid = nullptr;
+    double *sx = nullptr, *sy = nullptr;
+    rbf_status rc = RBF_OK;
+    auto cleanup = [&]() {
+        hipFree(cell);
+        hipFree(count);
+        hipFree(start);
+        hipFree(fill);
+        hipFree(sid);
+        hipFree(sx);
+        hipFree(sy);
+    };
+    do {
+        if (hipMalloc(&cell, ns * sizeof(int)) != hipSuccess ||
+            hipMalloc(&count, ncell * sizeof(int)) != hipSuccess ||
+            hipMalloc(&start, (ncell + 1) * sizeof(int)) != hipSuccess ||
+            hipMalloc(&fill, ncell * sizeof(int)) != hipSuccess ||
+            hipMalloc(&sid, ns * sizeof(int)) != hipSuccess ||
+            hipMalloc(&sx, ns * sizeof(double)) != hipSuccess ||
+            hipMalloc(&sy, ns * sizeof(double)) != hipSuccess) {
+            rbf::set_error("rbf_knn: device allocation failed");
+            rc = RBF_E_NOMEM;
+            break;
+        }
+        if (hipMemsetAsync(count, 0, ncell * sizeof(int), st) != hipSuccess ||
+            hipMemsetAsync(fill, 0, ncell * sizeof(int), st) != hipSuccess) {
+            rbf::set_error("rbf_knn: memset failed");
+            rc = RBF_E_DEVICE;
+            break;
+        }
+        hipLaunchKernelGGL(k_cell_count, dim3(rbf::blocks_for(ns, 256)), dim3(256), 0, st, xs, ns,
+                           g, cell, count);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, count, ncell, start);
+        hipLaunchKernelGGL(k_scatter, dim3(rbf::blocks_for(ns, 256)), dim3(256), 0, st, xs, ns,
+                           cell, start, fill, sx, sy, sid);
+        if (k <= 32)
+            hipLaunchKernelGGL(k_query<32>, dim3(rbf::blocks_for(nq, 128)), dim3(128), 0, st, xq,
+                               nq, k, g, start, sx, sy, sid, idx);
+        else
+            hipLaunchKernelGGL(k_query<64>, dim3(rbf::blocks_for(nq, 128)), dim3(128), 0, st, xq,
+                               nq, k, g, start, sx, sy, sid, idx);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            rbf::set_error("rbf_knn: %s", hipGetErrorString(e));
+            rc = RBF_E_DEVICE;
+        }
+    } while (0);
+    cleanup();
+    return rc;
+}

@@ -1,0 +1,1091 @@
+// Fractional-step Navier-Stokes solver on staggered nodes (Sec. 3):
+//   stage 1  AB2 advection (eqs. (14)-(15))            k_advect
+//   stage 2  Crank-Nicolson viscous step (eq. (16))    k_helm_rhs, k_wall_rhs,
+//            with Kim-Moin wall values (eq. (21))      BiCGSTAB on H (2 RHS)
+//   stage 3  divergence (eq. (17)), pressure Poisson   k_divergence,
+//            (eq. (18)), pressure (eq. (19)) and       BiCGSTAB on the Poisson
+//            velocity correction (eq. (20))            matrix, k_pressure, k_correct
+//
+// The paper factors its implicit matrices once by LU.  Here both systems are
+// solved by Jacobi-preconditioned BiCGSTAB (van der Vorst 1992) built from
+// ELL SpMV kernels and fused vector kernels.  Every scalar of the iteration
+// (rho, alpha, omega, residual norm) is reduced on the device: producers
+// write one partial sum per block, and each block of the consumer kernel
+// re-reduces the partials in a fixed order (deterministic, no host round
+// trip).  Convergence is a device flag; the host reads it back only every
+// few iterations, and kernels launched after convergence exit immediately.
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "common.h"
+#include "ell.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxBlocks = 1024;
+constexpr int kMaxNR = 2;
+
+// ------------------------------------------------------------ gathers --
+template <int NR>
+struct GatherN {
+    static constexpr int NV = NR;
+    const double *x;
+    int64_t stride;
+    __device__ __forceinline__ void operator()(int j, double (&v)[NR]) const {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) v[c] = x[c * stride + j];
+    }
+};
+
+struct Gather2 {
+    static constexpr int NV = 2;
+    const double *a, *b;
+    __device__ __forceinline__ void operator()(int j, double (&v)[2]) const {
+        v[0] = a[j];
+        v[1] = b[j];
+    }
+};
+
+// -------------------------------------------------------- reductions --
+// Block-partial sums: part[(q * NR + c) * nb + block] for NQ quantities.
+template <int NQ>
+__device__ __forceinline__ void store_partials(double (&v)[NQ], double *part, int nb) {
+    __shared__ double lds[NQ * (kThreads / 64)];
+    rbf::block_sum<NQ>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) part[(int64_t)q * nb + blockIdx.x] = v[q];
+    }
+}
+
+// Each block re-reduces NQ rows of nb partials in a fixed order.
+template <int NQ>
+__device__ __forceinline__ void load_partials(const double *part, int nb, double (&out)[NQ]) {
+    __shared__ double lds[NQ * (kThreads / 64)];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(int64_t)q * nb + b];
+        out[q] = s;
+    }
+    rbf::block_sum<NQ>(out, lds);
+}
+
+// ------------------------------------------------------ Krylov state --
+// Per right-hand side c and iteration it: rec[(it * NR + c) * 4 + {0,1,2,3}]
+// = rho, alpha, omega, ||r||^2.  flag[c]: 0 running, 1 converged, -1 failed
+// (non-finite), 2 breakdown (the host restarts from the current iterate).
+struct KDev {
+    double *r, *rh, *p, *v, *ph, *sh, *t;  // [NR][n] each
+    double *partE, *partB, *partD;           // partial sums
+    double *rec, *bb, *rhrh;                 // rhrh: ||rh||^2 of the current cycle
+    int *flag, *iters;
+};
+
+// Breakdown threshold for |rho| = |(rh, r)| relative to ||rh|| ||r||.
+constexpr double kBreakdown = 1e-13;
+
+struct EllM {
+    const int *idx;
+    const double *w;
+    const double *dinv;
+    int64_t n;
+    int k;
+};
+
+__device__ __forceinline__ int64_t row_of(int64_t it) {
+    return ((int64_t)rbf::xcd_block(blockIdx.x, gridDim.x) + it * gridDim.x) * kThreads +
+           threadIdx.x;
+}
+
+// r = b - A x, rh = r, p = v = 0; partials (rh.r, r.r, b.b).
+template <int NR, int KT>
+__global__ void __launch_bounds__(kThreads) k_bicg_init(EllM A, const double *__restrict__ b,
+                                                         const double *__restrict__ x, KDev K) {
+    const int nb = gridDim.x;
+    double acc3[3 * NR];
+#pragma unroll
+    for (int i = 0; i < 3 * NR; ++i) acc3[i] = 0.0;
+    for (int64_t it = 0;; ++it) {
+        const int64_t r = row_of(it);
+        if (r - threadIdx.x >= A.n) break;
+        if (r < A.n) {
+            double acc[1][NR] = {};
+            const double *ws[1] = {A.w};
+            rbf::ell_row<KT, 1>(A.idx, ws, A.n, r, A.k, GatherN<NR>{x, A.n}, acc);
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                const int64_t o = c * A.n + r;
+                const double rr = b[o] - acc[0][c];
+                K.r[o] = rr;
+                K.rh[o] = rr;
+                K.p[o] = 0.0;
+                K.v[o] = 0.0;
+                acc3[0 * NR + c] += rr * rr;
+                acc3[1 * NR + c] += rr * rr;
+                acc3[2 * NR + c] += b[o] * b[o];
+            }
+        }
+    }
+    store_partials<3 * NR>(acc3, K.partE, nb);
+    if (blockIdx.x == 0 && threadIdx.x < NR) {
+        K.flag[threadIdx.x] = 0;
+        K.iters[threadIdx.x] = 0;
+    }
+}
+
+// Start of iteration `it`: reduce (rh.r, r.r[, b.b]) from the previous
+// update, test convergence, then p = r + beta (p - omega v), ph = D^-1 p.
+template <int NR>
+__global__ void __launch_bounds__(kThreads) k_bicg_p(EllM A, KDev K, int it, int it0, int nbprev,
+                                                     double tol2) {
+    double red[3 * NR];
+    load_partials<3 * NR>(K.partE, nbprev, red);
+    bool active[NR];
+    double beta[NR], om[NR];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        const double rho = red[c], rr = red[NR + c];
+        const bool first = (it == it0);
+        const double bb = first ? red[2 * NR + c] : K.bb[c];
+        const double rhrh = first ? rr : K.rhrh[c];
+        const int f = K.flag[c];
+        active[c] = (f == 0);
+        beta[c] = 0.0;
+        om[c] = 0.0;
+        if (!active[c]) continue;
+        const bool bad = !isfinite(rho) || !isfinite(rr);
+        const bool conv = !bad && (rr <= tol2 * fmax(bb, 1e-300) || rr == 0.0);
+        const bool brk = !bad && !conv && !(fabs(rho) > kBreakdown * sqrt(rr * rhrh));
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            double *rc = K.rec + ((int64_t)it * NR + c) * 4;
+            rc[0] = rho;
+            rc[3] = rr;
+            if (first) {
+                K.bb[c] = bb;
+                K.rhrh[c] = rhrh;
+            }
+            if (bad) K.flag[c] = -1;
+            else if (conv) {
+                K.flag[c] = 1;
+                K.iters[c] = it;
+            } else if (brk) {
+                K.flag[c] = 2;
+                K.iters[c] = it;
+            }
+        }
+        if (bad || conv || brk) {
+            active[c] = false;
+            continue;
+        }
+        if (!first) {
+            const double *pr = K.rec + ((int64_t)(it - 1) * NR + c) * 4;
+            beta[c] = (rho / pr[0]) * (pr[1] / pr[2]);
+            om[c] = pr[2];
+        }
+        any = true;
+    }
+    if (!any) return;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < A.n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const double di = A.dinv[i];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            if (!active[c]) continue;
+            const int64_t o = c * A.n + i;
+            const double pn = K.r[o] + beta[c] * (K.p[o] - om[c] * K.v[o]);
+            K.p[o] = pn;
+            K.ph[o] = di * pn;
+        }
+    }
+}
+
+__device__ __forceinline__ bool all_done(const int *flag, int nr) {
+    for (int c = 0; c < nr; ++c)
+        if (flag[c] == 0) return false;
+    return true;
+}
+
+// v = A ph; partials (rh.v).
+template <int NR, int KT>
+__global__ void __launch_bounds__(kThreads) k_bicg_v(EllM A, KDev K) {
+    if (all_done(K.flag, NR)) return;
+    const int nb = gridDim.x;
+    double part[NR] = {};
+    for (int64_t it = 0;; ++it) {
+        const int64_t r = row_of(it);
+        if (r - threadIdx.x >= A.n) break;
+        if (r < A.n) {
+            double acc[1][NR] = {};
+            const double *ws[1] = {A.w};
+            rbf::ell_row<KT, 1>(A.idx, ws, A.n, r, A.k, GatherN<NR>{K.ph, A.n}, acc);
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                const int64_t o = c * A.n + r;
+                K.v[o] = acc[0][c];
+                part[c] += K.rh[o] * acc[0][c];
+            }
+        }
+    }
+    store_partials<NR>(part, K.partB, nb);
+}
+
+// alpha = rho / (rh.v); s = r - alpha v (stored in t), sh = D^-1 s.
+template <int NR>
+__global__ void __launch_bounds__(kThreads) k_bicg_s(EllM A, KDev K, int it, int nbprev) {
+    if (all_done(K.flag, NR)) return;
+    double red[NR];
+    load_partials<NR>(K.partB, nbprev, red);
+    bool active[NR];
+    double alpha[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        active[c] = K.flag[c] == 0;
+        const double rho = K.rec[((int64_t)it * NR + c) * 4];
+        alpha[c] = rho / red[c];
+        if (active[c] && !isfinite(alpha[c])) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                K.flag[c] = 2;
+                K.iters[c] = it;
+            }
+            active[c] = false;
+        }
+        if (active[c] && blockIdx.x == 0 && threadIdx.x == 0)
+            K.rec[((int64_t)it * NR + c) * 4 + 1] = alpha[c];
+    }
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < A.n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const double di = A.dinv[i];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            if (!active[c]) continue;
+            const int64_t o = c * A.n + i;
+            const double s = K.r[o] - alpha[c] * K.v[o];
+            K.t[o] = s;  // s lives in t until t = A sh overwrites it
+            K.sh[o] = di * s;
+        }
+    }
+}
+
+// t = A sh; partials (t.s, t.t); s is read from t before it is overwritten
+// (same row only).
+template <int NR, int KT>
+__global__ void __launch_bounds__(kThreads) k_bicg_t(EllM A, KDev K, double *sbuf) {
+    if (all_done(K.flag, NR)) return;
+    const int nb = gridDim.x;
+    double part[2 * NR] = {};
+    for (int64_t it = 0;; ++it) {
+        const int64_t r = row_of(it);
+        if (r - threadIdx.x >= A.n) break;
+        if (r < A.n) {
+            double acc[1][NR] = {};
+            const double *ws[1] = {A.w};
+            rbf::ell_row<KT, 1>(A.idx, ws, A.n, r, A.k, GatherN<NR>{K.sh, A.n}, acc);
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                const int64_t o = c * A.n + r;
+                const double s = K.t[o];
+                sbuf[o] = s;
+                K.t[o] = acc[0][c];
+                part[c] += acc[0][c] * s;
+                part[NR + c] += acc[0][c] * acc[0][c];
+            }
+        }
+    }
+    store_partials<2 * NR>(part, K.partD, nb);
+}
+
+// omega = (t.s)/(t.t); x += alpha ph + omega sh; r = s - omega t;
+// partials (rh.r, r.r).
+template <int NR>
+__global__ void __launch_bounds__(kThreads) k_bicg_x(EllM A, KDev K, int it, int nbprev,
+                                                     double *__restrict__ x,
+                                                     const double *__restrict__ sbuf) {
+    if (all_done(K.flag, NR)) return;
+    double red[2 * NR];
+    load_partials<2 * NR>(K.partD, nbprev, red);
+    bool active[NR];
+    double alpha[NR], omega[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        active[c] = K.flag[c] == 0;
+        alpha[c] = K.rec[((int64_t)it * NR + c) * 4 + 1];
+        omega[c] = (red[NR + c] != 0.0) ? red[c] / red[NR + c] : 0.0;
+        if (active[c] && !(omega[c] != 0.0) && red[NR + c] != 0.0) {
+            // omega = 0 stalls the recurrence: take the alpha step, then restart.
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                K.flag[c] = 2;
+                K.iters[c] = it + 1;
+            }
+        }
+        if (active[c] && blockIdx.x == 0 && threadIdx.x == 0)
+            K.rec[((int64_t)it * NR + c) * 4 + 2] = omega[c];
+    }
+    double part[3 * NR] = {};
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < A.n;
+         i += (int64_t)gridDim.x * kThreads) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            if (!active[c]) continue;
+            const int64_t o = c * A.n + i;
+            const double s = sbuf[o];
+            x[o] = x[o] + alpha[c] * K.ph[o] + omega[c] * K.sh[o];
+            const double rn = s - omega[c] * K.t[o];
+            K.r[o] = rn;
+            part[c] += K.rh[o] * rn;
+            part[NR + c] += rn * rn;
+        }
+    }
+    store_partials<3 * NR>(part, K.partE, gridDim.x);
+}
+
+// True residual ||b - A x||^2 per right-hand side (for the statistics).
+template <int NR, int KT>
+__global__ void __launch_bounds__(kThreads) k_resid(EllM A, const double *__restrict__ b,
+                                                     const double *__restrict__ x, double *part) {
+    double acc2[NR] = {};
+    for (int64_t it = 0;; ++it) {
+        const int64_t r = row_of(it);
+        if (r - threadIdx.x >= A.n) break;
+        if (r < A.n) {
+            double acc[1][NR] = {};
+            const double *ws[1] = {A.w};
+            rbf::ell_row<KT, 1>(A.idx, ws, A.n, r, A.k, GatherN<NR>{x, A.n}, acc);
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                const double e = b[c * A.n + r] - acc[0][c];
+                acc2[c] += e * e;
+            }
+        }
+    }
+    store_partials<NR>(acc2, part, gridDim.x);
+}
+
+// ---------------------------------------------------------- step kernels --
+// Stage 1: C(q) = -(u o D_x q + v o D_y q), u* = u + dt (3/2 C_j - 1/2 C_{j-1}).
+template <int KT>
+__global__ void __launch_bounds__(kThreads) k_advect(int64_t n, int k, const int *__restrict__ idx,
+                                                      const double *__restrict__ wdx,
+                                                      const double *__restrict__ wdy,
+                                                      const double *__restrict__ u,
+                                                      const double *__restrict__ v,
+                                                      const double *__restrict__ cu_prev,
+                                                      const double *__restrict__ cv_prev,
+                                                      int first, double dt, double *__restrict__ us,
+                                                      double *__restrict__ vs,
+                                                      double *__restrict__ cu,
+                                                      double *__restrict__ cv) {
+    const int64_t r = (int64_t)rbf::xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+    if (r >= n) return;
+    double acc[2][2] = {};
+    const double *ws[2] = {wdx, wdy};
+    rbf::ell_row<KT, 2>(idx, ws, n, r, k, Gather2{u, v}, acc);
+    const double ui = u[r], vi = v[r];
+    const double cun = -(ui * acc[0][0] + vi * acc[1][0]);
+    const double cvn = -(ui * acc[0][1] + vi * acc[1][1]);
+    const double cup = first ? cun : cu_prev[r];
+    const double cvp = first ? cvn : cv_prev[r];
+    us[r] = ui + dt * (1.5 * cun - 0.5 * cup);
+    vs[r] = vi + dt * (1.5 * cvn - 0.5 * cvp);
+    cu[r] = cun;
+    cv[r] = cvn;
+}
+
+// Stage 2 right-hand side on interior rows: (I + a D_Lap) u*, and the same
+// for v; the initial guess of the solve is the right-hand side.
+template <int KT>
+__global__ void __launch_bounds__(kThreads) k_helm_rhs(int64_t n, int k, const int *__restrict__ idx,
+                                                        const double *__restrict__ wlap, double a,
+                                                        const double *__restrict__ us,
+                                                        const double *__restrict__ vs,
+                                                        double *__restrict__ rhs,
+                                                        double *__restrict__ x0) {
+    const int64_t r = (int64_t)rbf::xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+    if (r >= n) return;
+    double acc[1][2] = {};
+    const double *ws[1] = {wlap};
+    rbf::ell_row<KT, 1>(idx, ws, n, r, k, Gather2{us, vs}, acc);
+    const double ru = us[r] + a * acc[0][0];
+    const double rv = vs[r] + a * acc[0][1];
+    rhs[r] = ru;
+    rhs[n + r] = rv;
+    x0[r] = ru;
+    x0[n + r] = rv;
+}
+
+// Kim-Moin wall values (eq. (21)): u** = u_bc + dt D_x^VP p~_j, v** likewise.
+__global__ void __launch_bounds__(kThreads) k_wall_rhs(int64_t nwall, const int *__restrict__ rows,
+                                                        int64_t n, int k, const int *__restrict__ idx,
+                                                        const double *__restrict__ wdx,
+                                                        const double *__restrict__ wdy,
+                                                        const double *__restrict__ pt,
+                                                        const double *__restrict__ u_bc,
+                                                        const double *__restrict__ v_bc, double dt,
+                                                        double *__restrict__ rhs,
+                                                        double *__restrict__ x0) {
+    const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (i >= nwall) return;
+    const int64_t r = rows[i];
+    double gx = 0.0, gy = 0.0;
+    for (int s = 0; s < k; ++s) {
+        const int64_t o = (int64_t)s * n + r;
+        const double pj = pt[idx[o]];
+        gx = fma(wdx[o], pj, gx);
+        gy = fma(wdy[o], pj, gy);
+    }
+    const double ru = u_bc[r] + dt * gx, rv = v_bc[r] + dt * gy;
+    rhs[r] = ru;
+    rhs[n + r] = rv;
+    x0[r] = ru;
+    x0[n + r] = rv;
+}
+
+// Stage 3a: F = D_x^PV u** + D_y^PV v**; Poisson right-hand side F/dt on
+// interior rows (times the row scaling of the stored Poisson matrix), 0 on
+// wall and pin rows.
+template <int KT>
+__global__ void __launch_bounds__(kThreads) k_divergence(int64_t m, int k, const int *__restrict__ idx,
+                                                          const double *__restrict__ wdx,
+                                                          const double *__restrict__ wdy,
+                                                          const double *__restrict__ uss,
+                                                          const double *__restrict__ vss,
+                                                          const int8_t *__restrict__ ptag, int64_t pin,
+                                                          double inv_dt,
+                                                          const double *__restrict__ rowscale,
+                                                          double *__restrict__ rhs) {
+    const int64_t r = (int64_t)rbf::xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+    if (r >= m) return;
+    double acc[2][2] = {};
+    const double *ws[2] = {wdx, wdy};
+    rbf::ell_row<KT, 2>(idx, ws, m, r, k, Gather2{uss, vss}, acc);
+    const double F = acc[0][0] + acc[1][1];
+    rhs[r] = (ptag[r] == 0 && r != pin) ? rowscale[r] * (F * inv_dt) : 0.0;
+}
+
+// Stage 3c (pressure): p = p~ - a D_Lap^PP p~.
+template <int KT>
+__global__ void __launch_bounds__(kThreads) k_pressure(int64_t m, int k, const int *__restrict__ idx,
+                                                        const double *__restrict__ wlap, double a,
+                                                        const double *__restrict__ pt,
+                                                        double *__restrict__ p) {
+    const int64_t r = (int64_t)rbf::xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+    if (r >= m) return;
+    double acc[1][1] = {};
+    const double *ws[1] = {wlap};
+    rbf::ell_row<KT, 1>(idx, ws, m, r, k, GatherN<1>{pt, 0}, acc);
+    p[r] = pt[r] - a * acc[0][0];
+}
+
+// Stage 3c (velocity): u = u** - dt D_x^VP p~, v = v** - dt D_y^VP p~, all rows.
+template <int KT>
+__global__ void __launch_bounds__(kThreads) k_correct(int64_t n, int k, const int *__restrict__ idx,
+                                                       const double *__restrict__ wdx,
+                                                       const double *__restrict__ wdy, double dt,
+                                                       const double *__restrict__ pt,
+                                                       const double *__restrict__ uvss,
+                                                       double *__restrict__ u, double *__restrict__ v) {
+    const int64_t r = (int64_t)rbf::xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+    if (r >= n) return;
+    double acc[2][1] = {};
+    const double *ws[2] = {wdx, wdy};
+    rbf::ell_row<KT, 2>(idx, ws, n, r, k, GatherN<1>{pt, 0}, acc);
+    u[r] = uvss[r] - dt * acc[0][0];
+    v[r] = uvss[n + r] - dt * acc[1][0];
+}
+
+// ----------------------------------------------- system matrix assembly --
+// H = I - a D_Lap on interior V rows, identity on wall rows.
+__global__ void k_build_helmholtz(int64_t n, int k, const int *__restrict__ idx,
+                                  const double *__restrict__ lap, const int8_t *__restrict__ tag,
+                                  double a, double *__restrict__ hw, double *__restrict__ dinv,
+                                  int *__restrict__ err) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const bool wall = tag[r] != 0;
+    double diag = 0.0;
+    bool self = false;
+    for (int s = 0; s < k; ++s) {
+        const int64_t o = (int64_t)s * n + r;
+        const bool me = idx[o] == r;
+        double wv = wall ? 0.0 : -a * lap[o];
+        if (me) {
+            wv += 1.0;
+            diag = wv;
+            self = true;
+        }
+        hw[o] = wv;
+    }
+    if (!self) atomicOr(err, 1);
+    dinv[r] = (diag != 0.0) ? 1.0 / diag : 1.0;
+}
+
+// Poisson rows: D_Lap^PP (interior), n_x D_x^PP + n_y D_y^PP (wall),
+// identity (pin), stored row-scaled: interior rows by -1/||row||_2, wall
+// rows by +1/||row||_2 (so the scaled operator is -Lap with outward-normal
+// Neumann rows, whose spectrum lies in the right half-plane), pin row by 1.
+// RBF-FD self-weights do not have a fixed sign on scattered nodes, so Jacobi
+// scaling would make the spectrum indefinite; BiCGSTAB on the row-scaled
+// matrix runs unpreconditioned (dinv = 1).  rowscale[r] scales the RHS.
+__global__ void k_build_poisson(int64_t m, int k, const int *__restrict__ idx,
+                                const double *__restrict__ lap, const double *__restrict__ dx,
+                                const double *__restrict__ dy, const int8_t *__restrict__ tag,
+                                const double *__restrict__ nrm, int64_t pin,
+                                double *__restrict__ pw, double *__restrict__ dinv,
+                                double *__restrict__ rowscale, int *__restrict__ err) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const bool wall = tag[r] != 0;
+    const double nx = nrm[r], ny = nrm[m + r];
+    bool self = false;
+    double ss = 0.0;
+    for (int s = 0; s < k; ++s) {
+        const int64_t o = (int64_t)s * m + r;
+        const bool me = idx[o] == r;
+        double wv;
+        if (r == pin) wv = me ? 1.0 : 0.0;
+        else if (wall) wv = nx * dx[o] + ny * dy[o];
+        else wv = lap[o];
+        if (me) self = true;
+        ss += wv * wv;
+        pw[o] = wv;
+    }
+    if (!self || !(ss > 0.0)) atomicOr(err, 2);
+    const double sc = (r == pin) ? 1.0 : (wall ? 1.0 : -1.0) / sqrt(ss);
+    for (int s = 0; s < k; ++s) pw[(int64_t)s * m + r] *= sc;
+    rowscale[r] = sc;
+    dinv[r] = 1.0;
+}
+
+// rhs_scaled = rowscale o rhs (for rbf_solve_pressure).
+__global__ void k_scale(int64_t n, const double *__restrict__ sc, const double *__restrict__ a,
+                        double *__restrict__ b) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r < n) b[r] = sc[r] * a[r];
+}
+
+// Pin: the interior P-node nearest (0.5, 0.5), lowest index on ties.
+__global__ void k_pin_partial(int64_t m, const double *__restrict__ xp,
+                              const int8_t *__restrict__ tag, double *__restrict__ bd,
+                              long long *__restrict__ bi) {
+    __shared__ double sd[kThreads];
+    __shared__ long long si[kThreads];
+    double best = INFINITY;
+    long long bidx = -1;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < m;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        if (tag[r] != 0) continue;
+        const double dx = xp[r] - 0.5, dy = xp[m + r] - 0.5;
+        const double d2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+        if (d2 < best || (d2 == best && r < bidx)) {
+            best = d2;
+            bidx = r;
+        }
+    }
+    sd[threadIdx.x] = best;
+    si[threadIdx.x] = bidx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int t = 1; t < (int)blockDim.x; ++t) {
+            if (si[t] < 0) continue;
+            if (bidx < 0 || sd[t] < best || (sd[t] == best && si[t] < bidx)) {
+                best = sd[t];
+                bidx = si[t];
+            }
+        }
+        bd[blockIdx.x] = best;
+        bi[blockIdx.x] = bidx;
+    }
+}
+
+__global__ void k_wall_list(int64_t n, const int8_t *__restrict__ tag, int *__restrict__ list,
+                            int *__restrict__ count) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n || tag[r] == 0) return;
+    list[atomicAdd(count, 1)] = (int)r;
+}
+
+}  // namespace
+
+// ====================================================================== host
+struct rbf_solver {
+    hipStream_t st = nullptr;
+    int64_t N = 0, M = 0;
+    int k = 0;
+    double re = 0, dt = 0, a = 0, rtol_h = 0, rtol_p = 0;
+    int maxit_h = 0, maxit_p = 0;
+    int64_t pin = -1;
+    int64_t nwall = 0;
+    // operators
+    int *idx_vv = nullptr, *idx_pv = nullptr, *idx_pp = nullptr, *idx_vp = nullptr;
+    double *vv_dx = nullptr, *vv_dy = nullptr, *vv_lap = nullptr, *pv_dx = nullptr,
+           *pv_dy = nullptr, *pp_lap = nullptr, *vp_dx = nullptr, *vp_dy = nullptr;
+    double *h_w = nullptr, *h_dinv = nullptr, *p_w = nullptr, *p_dinv = nullptr,
+           *p_rowscale = nullptr, *p_rhs_tmp = nullptr;
+    int8_t *p_tag = nullptr;
+    int *wall_rows = nullptr;
+    double *u_bc = nullptr, *v_bc = nullptr;
+    // state (committed) and step workspace
+    double *u = nullptr, *v = nullptr, *pt = nullptr, *p = nullptr, *cu = nullptr, *cv = nullptr;
+    double *un = nullptr, *vn = nullptr, *ptn = nullptr, *pn = nullptr, *cun = nullptr,
+           *cvn = nullptr;
+    double *us = nullptr, *vs = nullptr, *hrhs = nullptr, *uvss = nullptr, *prhs = nullptr;
+    // Krylov workspaces: Helmholtz (2 RHS over N), Poisson (1 RHS over M)
+    KDev kh{}, kp{};
+    double *sbuf_h = nullptr, *sbuf_p = nullptr, *rpart = nullptr;
+    int last_iters_h = 0, last_iters_p = 0;
+    // optional sampling of the Poisson SpMV (k_bicg_v) duration with HIP events
+    int prof_every = 0;
+    int64_t prof_launches = 0, prof_count = 0;
+    double prof_ms = 0.0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // pinned host buffers
+    int *hflag = nullptr;
+    double *hred = nullptr;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+rbf_status dalloc(rbf_solver *S, void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+    if (e != hipSuccess) {
+        rbf::set_error("rbf_solver: hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return RBF_E_NOMEM;
+    }
+    S->allocs.push_back(*p);
+    return RBF_OK;
+}
+
+#define ALLOC(ptr, count)                                                          \
+    do {                                                                           \
+        rbf_status rc_ = dalloc(S, (void **)&(ptr), sizeof(*(ptr)) * (size_t)(count)); \
+        if (rc_ != RBF_OK) return rc_;                                             \
+    } while (0)
+
+int nblocks_rows(int64_t n) {
+    return (int)std::min<int64_t>(kMaxBlocks, (n + kThreads - 1) / kThreads);
+}
+
+rbf_status alloc_krylov(rbf_solver *S, KDev &K, int nr, int64_t n, int maxit) {
+    const int64_t len = (int64_t)nr * n;
+    ALLOC(K.r, len);
+    ALLOC(K.rh, len);
+    ALLOC(K.p, len);
+    ALLOC(K.v, len);
+    ALLOC(K.ph, len);
+    ALLOC(K.sh, len);
+    ALLOC(K.t, len);
+    ALLOC(K.partE, 3 * nr * kMaxBlocks);
+    ALLOC(K.partB, nr * kMaxBlocks);
+    ALLOC(K.partD, 2 * nr * kMaxBlocks);
+    ALLOC(K.rec, (int64_t)(maxit + 2) * nr * 4);
+    ALLOC(K.bb, nr);
+    ALLOC(K.rhrh, nr);
+    ALLOC(K.flag, nr);
+    ALLOC(K.iters, nr);
+    return RBF_OK;
+}
+
+// Jacobi-BiCGSTAB on A x = b for NR stacked right-hand sides.
+template <int NR>
+rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, double *sbuf,
+                    double tol, int maxit, int &last_iters, rbf_solve_stats *stats) {
+    hipStream_t st = S->st;
+    const int nb = nblocks_rows(A.n);
+    const double tol2 = tol * tol;
+    const bool k28 = A.k == 28;
+#define L28(kern, ...)                                                                    \
+    do {                                                                                  \
+        if (k28) hipLaunchKernelGGL((kern<NR, 28>), dim3(nb), dim3(kThreads), 0, st, __VA_ARGS__); \
+        else hipLaunchKernelGGL((kern<NR, 0>), dim3(nb), dim3(kThreads), 0, st, __VA_ARGS__);      \
+    } while (0)
+    L28(k_bicg_init, A, b, x, K);
+    int it = 0, it0 = 0, restarts = 0;
+    rbf_status rc = RBF_OK;
+    int batch = std::max(4, last_iters > 0 ? last_iters - 1 : 8);
+    bool done = false;
+    while (!done) {
+        const int stop = std::min(maxit, it + batch);
+        for (; it < stop; ++it) {
+            hipLaunchKernelGGL((k_bicg_p<NR>), dim3(nb), dim3(kThreads), 0, st, A, K, it, it0, nb, tol2);
+            const bool sample = NR == 1 && S->prof_every > 0 && (S->prof_launches++ % S->prof_every) == 0;
+            if (sample) RBF_HIP(hipEventRecord(S->ev0, st));
+            L28(k_bicg_v, A, K);
+            if (sample) {
+                RBF_HIP(hipEventRecord(S->ev1, st));
+                RBF_HIP(hipEventSynchronize(S->ev1));
+                float ms = 0.f;
+                RBF_HIP(hipEventElapsedTime(&ms, S->ev0, S->ev1));
+                S->prof_ms += ms;
+                ++S->prof_count;
+            }
+            hipLaunchKernelGGL((k_bicg_s<NR>), dim3(nb), dim3(kThreads), 0, st, A, K, it, nb);
+            L28(k_bicg_t, A, K, sbuf);
+            hipLaunchKernelGGL((k_bicg_x<NR>), dim3(nb), dim3(kThreads), 0, st, A, K, it, nb, x, sbuf);
+        }
+        if (it >= maxit)  // final convergence test of the last update
+            hipLaunchKernelGGL((k_bicg_p<NR>), dim3(nb), dim3(kThreads), 0, st, A, K, it, it0, nb, tol2);
+        RBF_CHECK_LAUNCH();
+        RBF_HIP(hipMemcpyAsync(S->hflag, K.flag, NR * sizeof(int), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipMemcpyAsync(S->hflag + kMaxNR, K.iters, NR * sizeof(int), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        done = true;
+        bool restart = false;
+        for (int c = 0; c < NR; ++c) {
+            if (S->hflag[c] == 0) done = false;
+            if (S->hflag[c] == 2) restart = true;
+        }
+        if (restart && it < maxit && restarts < 50) {
+            // Breakdown: restart from the current iterate with rh = r.  The
+            // iteration count continues; finished right-hand sides re-enter
+            // and are found converged at once.
+            ++restarts;
+            it0 = it;
+            L28(k_bicg_init, A, b, x, K);
+            done = false;
+            continue;
+        }
+        if (!done && it >= maxit) break;
+        batch = std::max(4, std::min(64, (it - it0) / 4));
+    }
+    // Final statistics: true residual.
+    L28(k_resid, A, b, x, S->rpart);
+    RBF_CHECK_LAUNCH();
+    RBF_HIP(hipMemcpyAsync(S->hred, S->rpart, (size_t)NR * nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipMemcpyAsync(S->hred + kMaxNR * kMaxBlocks, K.bb, NR * sizeof(double), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+#undef L28
+    int maxi = 0;
+    for (int c = 0; c < NR; ++c) {
+        double rr = 0.0;
+        for (int bidx = 0; bidx < nb; ++bidx) rr += S->hred[c * nb + bidx];
+        const double bb = S->hred[kMaxNR * kMaxBlocks + c];
+        const int f = S->hflag[c];
+        const int iters = (f == 1) ? S->hflag[kMaxNR + c] : it;
+        maxi = std::max(maxi, iters);
+        if (stats) {
+            stats[c].iterations = iters;
+            stats[c].converged = (f == 1);
+            stats[c].rel_residual = (bb > 0.0) ? std::sqrt(rr / bb) : std::sqrt(rr);
+        }
+        if (f == -1) {
+            rbf::set_error("BiCGSTAB: non-finite value (rhs %d, iteration %d)", c, it);
+            rc = RBF_E_NAN;
+        } else if ((f == 0 || f == 2) && rc == RBF_OK) {
+            rbf::set_error("BiCGSTAB: no convergence in %d iterations (rhs %d)", maxit, c);
+            rc = RBF_E_NOCONV;
+        }
+    }
+    last_iters = maxi;
+    return rc;
+}
+
+template <class F>
+void launch_kt(int k, F f) {
+    if (k == 28) f(std::integral_constant<int, 28>{});
+    else f(std::integral_constant<int, 0>{});
+}
+
+rbf_status copy_in(rbf_solver *S, void *dst, const void *src, size_t bytes) {
+    RBF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, S->st));
+    return RBF_OK;
+}
+
+rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const double *u_bc,
+                       const double *v_bc, const rbf_params *prm) {
+    const int64_t N = g->n_v, M = g->n_p;
+    const int k = o->k;
+    S->N = N;
+    S->M = M;
+    S->k = k;
+    S->re = prm->re;
+    S->dt = prm->dt;
+    S->a = prm->dt / (2.0 * prm->re);
+    S->rtol_h = prm->rtol_h;
+    S->rtol_p = prm->rtol_p;
+    S->maxit_h = prm->maxit_h;
+    S->maxit_p = prm->maxit_p;
+    const int64_t kN = (int64_t)k * N, kM = (int64_t)k * M;
+    ALLOC(S->idx_vv, kN);
+    ALLOC(S->idx_pv, kM);
+    ALLOC(S->idx_pp, kM);
+    ALLOC(S->idx_vp, kN);
+    ALLOC(S->vv_dx, kN);
+    ALLOC(S->vv_dy, kN);
+    ALLOC(S->vv_lap, kN);
+    ALLOC(S->pv_dx, kM);
+    ALLOC(S->pv_dy, kM);
+    ALLOC(S->pp_lap, kM);
+    ALLOC(S->vp_dx, kN);
+    ALLOC(S->vp_dy, kN);
+    ALLOC(S->h_w, kN);
+    ALLOC(S->h_dinv, N);
+    ALLOC(S->p_w, kM);
+    ALLOC(S->p_dinv, M);
+    ALLOC(S->p_rowscale, M);
+    ALLOC(S->p_rhs_tmp, M);
+    ALLOC(S->p_tag, M);
+    ALLOC(S->u_bc, N);
+    ALLOC(S->v_bc, N);
+    ALLOC(S->wall_rows, N);
+    for (double **q : {&S->u, &S->v, &S->cu, &S->cv, &S->un, &S->vn, &S->cun, &S->cvn, &S->us, &S->vs})
+        ALLOC(*q, N);
+    for (double **q : {&S->pt, &S->p, &S->ptn, &S->pn, &S->prhs}) ALLOC(*q, M);
+    ALLOC(S->hrhs, 2 * N);
+    ALLOC(S->uvss, 2 * N);
+    ALLOC(S->sbuf_h, 2 * N);
+    ALLOC(S->sbuf_p, M);
+    ALLOC(S->rpart, kMaxNR * kMaxBlocks);
+    rbf_status rc;
+    if ((rc = alloc_krylov(S, S->kh, 2, N, S->maxit_h)) != RBF_OK) return rc;
+    if ((rc = alloc_krylov(S, S->kp, 1, M, S->maxit_p)) != RBF_OK) return rc;
+    RBF_HIP(hipHostMalloc((void **)&S->hflag, 4 * kMaxNR * sizeof(int), hipHostMallocDefault));
+    RBF_HIP(hipHostMalloc((void **)&S->hred, (kMaxNR * kMaxBlocks + kMaxNR) * sizeof(double),
+                          hipHostMallocDefault));
+
+    const size_t ib = sizeof(int), db = sizeof(double);
+    struct {
+        void *d;
+        const void *s;
+        size_t b;
+    } cp[] = {{S->idx_vv, o->idx_vv, kN * ib}, {S->idx_pv, o->idx_pv, kM * ib},
+              {S->idx_pp, o->idx_pp, kM * ib}, {S->idx_vp, o->idx_vp, kN * ib},
+              {S->vv_dx, o->vv_dx, kN * db},   {S->vv_dy, o->vv_dy, kN * db},
+              {S->vv_lap, o->vv_lap, kN * db}, {S->pv_dx, o->pv_dx, kM * db},
+              {S->pv_dy, o->pv_dy, kM * db},   {S->pp_lap, o->pp_lap, kM * db},
+              {S->vp_dx, o->vp_dx, kN * db},   {S->vp_dy, o->vp_dy, kN * db},
+              {S->p_tag, g->p_tag, (size_t)M}, {S->u_bc, u_bc, N * db},
+              {S->v_bc, v_bc, N * db}};
+    for (auto &c : cp)
+        if ((rc = copy_in(S, c.d, c.s, c.b)) != RBF_OK) return rc;
+
+    hipStream_t st = S->st;
+    // Pin row.
+    const int npb = 64;
+    double *bd;
+    long long *bi;
+    ALLOC(bd, npb);
+    ALLOC(bi, npb);
+    hipLaunchKernelGGL(k_pin_partial, dim3(npb), dim3(kThreads), 0, st, M, g->xp, g->p_tag, bd, bi);
+    int *err, *cnt;
+    ALLOC(err, 1);
+    ALLOC(cnt, 1);
+    RBF_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
+    RBF_HIP(hipMemsetAsync(cnt, 0, sizeof(int), st));
+    std::vector<double> hbd(npb);
+    std::vector<long long> hbi(npb);
+    RBF_HIP(hipMemcpyAsync(hbd.data(), bd, npb * db, hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipMemcpyAsync(hbi.data(), bi, npb * sizeof(long long), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+    double best = INFINITY;
+    long long pin = -1;
+    for (int b = 0; b < npb; ++b) {
+        if (hbi[b] < 0) continue;
+        if (pin < 0 || hbd[b] < best || (hbd[b] == best && hbi[b] < pin)) {
+            best = hbd[b];
+            pin = hbi[b];
+        }
+    }
+    RBF_ARG(pin >= 0, "rbf_solver_create: no interior P-node for the pressure pin");
+    S->pin = pin;
+    hipLaunchKernelGGL(k_build_helmholtz, dim3(rbf::blocks_for(N, 256)), dim3(256), 0, st, N, k,
+                       S->idx_vv, S->vv_lap, g->v_tag, S->a, S->h_w, S->h_dinv, err);
+    hipLaunchKernelGGL(k_build_poisson, dim3(rbf::blocks_for(M, 256)), dim3(256), 0, st, M, k,
+                       S->idx_pp, S->pp_lap, o->pp_dx, o->pp_dy, g->p_tag, g->p_normal, S->pin,
+                       S->p_w, S->p_dinv, S->p_rowscale, err);
+    hipLaunchKernelGGL(k_wall_list, dim3(rbf::blocks_for(N, 256)), dim3(256), 0, st, N, g->v_tag,
+                       S->wall_rows, cnt);
+    RBF_CHECK_LAUNCH();
+    int herr[2] = {0, 0};
+    RBF_HIP(hipMemcpyAsync(&herr[0], err, ib, hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipMemcpyAsync(&herr[1], cnt, ib, hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+    RBF_ARG(herr[0] == 0, "rbf_solver_create: a %s stencil does not contain its own node (or a zero row)",
+            (herr[0] & 1) ? "(V,V)" : "(P,P)");
+    S->nwall = herr[1];
+    // The wall list order from atomics is irrelevant: rows are independent.
+    return RBF_OK;
+}
+
+rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
+    hipStream_t st = S->st;
+    const int64_t N = S->N, M = S->M;
+    const int k = S->k;
+    const dim3 gN(rbf::blocks_for(N, kThreads)), gM(rbf::blocks_for(M, kThreads)), blk(kThreads);
+    // Stage 1.
+    launch_kt(k, [&](auto KT) {
+        hipLaunchKernelGGL((k_advect<decltype(KT)::value>), gN, blk, 0, st, N, k, S->idx_vv, S->vv_dx,
+                           S->vv_dy, S->u, S->v, S->cu, S->cv, first ? 1 : 0, S->dt, S->us, S->vs,
+                           S->cun, S->cvn);
+        // Stage 2 right-hand side and initial guess.
+        hipLaunchKernelGGL((k_helm_rhs<decltype(KT)::value>), gN, blk, 0, st, N, k, S->idx_vv, S->vv_lap, S->a,
+                           S->us, S->vs, S->hrhs, S->uvss);
+    });
+    if (S->nwall > 0)
+        hipLaunchKernelGGL(k_wall_rhs, dim3(rbf::blocks_for(S->nwall, kThreads)), blk, 0, st,
+                           S->nwall, S->wall_rows, N, k, S->idx_vp, S->vp_dx, S->vp_dy, S->pt,
+                           S->u_bc, S->v_bc, S->dt, S->hrhs, S->uvss);
+    RBF_CHECK_LAUNCH();
+    rbf_solve_stats hs[2];
+    EllM H{S->idx_vv, S->h_w, S->h_dinv, N, k};
+    rbf_status rc = bicgstab<2>(S, S->kh, H, S->hrhs, S->uvss, S->sbuf_h, S->rtol_h, S->maxit_h,
+                                S->last_iters_h, hs);
+    if (stats) {
+        stats->last_helmholtz_u = hs[0];
+        stats->last_helmholtz_v = hs[1];
+        stats->helmholtz_iters += hs[0].iterations + hs[1].iterations;
+    }
+    if (rc != RBF_OK) return rc;
+    // Stage 3: divergence, Poisson (warm start from p~_j), pressure, correction.
+    launch_kt(k, [&](auto KT) {
+        hipLaunchKernelGGL((k_divergence<decltype(KT)::value>), gM, blk, 0, st, M, k, S->idx_pv, S->pv_dx,
+                           S->pv_dy, S->uvss, S->uvss + N, S->p_tag, S->pin, 1.0 / S->dt,
+                           S->p_rowscale, S->prhs);
+    });
+    RBF_HIP(hipMemcpyAsync(S->ptn, S->pt, M * sizeof(double), hipMemcpyDeviceToDevice, st));
+    rbf_solve_stats ps;
+    EllM P{S->idx_pp, S->p_w, S->p_dinv, M, k};
+    rc = bicgstab<1>(S, S->kp, P, S->prhs, S->ptn, S->sbuf_p, S->rtol_p, S->maxit_p,
+                     S->last_iters_p, &ps);
+    if (stats) {
+        stats->last_poisson = ps;
+        stats->poisson_iters += ps.iterations;
+    }
+    if (rc != RBF_OK) return rc;
+    launch_kt(k, [&](auto KT) {
+        hipLaunchKernelGGL((k_pressure<decltype(KT)::value>), gM, blk, 0, st, M, k, S->idx_pp, S->pp_lap, S->a,
+                           S->ptn, S->pn);
+        hipLaunchKernelGGL((k_correct<decltype(KT)::value>), gN, blk, 0, st, N, k, S->idx_vp, S->vp_dx,
+                           S->vp_dy, S->dt, S->ptn, S->uvss, S->un, S->vn);
+    });
+    RBF_CHECK_LAUNCH();
+    // Commit.
+    std::swap(S->u, S->un);
+    std::swap(S->v, S->vn);
+    std::swap(S->pt, S->ptn);
+    std::swap(S->p, S->pn);
+    std::swap(S->cu, S->cun);
+    std::swap(S->cv, S->cvn);
+    return RBF_OK;
+}
+
+}  // namespace
+
+extern "C" rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, const rbf_ops *ops,
+                                        const double *u_bc, const double *v_bc,
+                                        const rbf_params *prm, rbf_stream st) {
+    rbf::clear_error();
+    RBF_ARG(out && grid && ops && prm && u_bc && v_bc, "rbf_solver_create: NULL argument");
+    *out = nullptr;
+    RBF_ARG(grid->n_v > 0 && grid->n_p > 0 && grid->n_v < INT32_MAX && grid->n_p < INT32_MAX,
+            "rbf_solver_create: node counts out of range");
+    RBF_ARG(grid->xv && grid->xp && grid->v_tag && grid->p_tag && grid->p_normal,
+            "rbf_solver_create: NULL grid array");
+    RBF_ARG(ops->k >= 1 && ops->k <= 64 && ops->k <= grid->n_v && ops->k <= grid->n_p,
+            "rbf_solver_create: stencil size out of range");
+    RBF_ARG(ops->idx_vv && ops->vv_dx && ops->vv_dy && ops->vv_lap && ops->idx_pv && ops->pv_dx &&
+                ops->pv_dy && ops->idx_pp && ops->pp_dx && ops->pp_dy && ops->pp_lap &&
+                ops->idx_vp && ops->vp_dx && ops->vp_dy,
+            "rbf_solver_create: NULL operator array");
+    RBF_ARG(prm->re > 0 && prm->dt > 0 && std::isfinite(prm->re) && std::isfinite(prm->dt),
+            "rbf_solver_create: re and dt must be positive");
+    RBF_ARG(prm->rtol_h > 0 && prm->rtol_p > 0, "rbf_solver_create: tolerances must be positive");
+    RBF_ARG(prm->maxit_h >= 1 && prm->maxit_p >= 1 && prm->maxit_h <= 1000000 &&
+                prm->maxit_p <= 1000000,
+            "rbf_solver_create: iteration caps out of range");
+    RBF_ARG(prm->precision == 0, "rbf_solver_create: only precision 0 (FP64) is supported");
+    rbf_solver *S = new rbf_solver();
+    S->st = rbf::as_stream(st);
+    rbf_status rc = create_impl(S, grid, ops, u_bc, v_bc, prm);
+    if (rc != RBF_OK) {
+        rbf_solver_destroy(S);
+        return rc;
+    }
+    *out = S;
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_step(rbf_solver *S, int32_t nsteps, rbf_state *state,
+                               rbf_step_stats *stats) {
+    rbf::clear_error();
+    RBF_ARG(S && state, "rbf_step: NULL argument");
+    RBF_ARG(nsteps >= 0, "rbf_step: nsteps < 0");
+    RBF_ARG(state->u && state->v && state->p_tilde && state->p && state->cu_prev && state->cv_prev,
+            "rbf_step: NULL state array");
+    if (stats) *stats = rbf_step_stats{};
+    const size_t nb = S->N * sizeof(double), mb = S->M * sizeof(double);
+    hipStream_t st = S->st;
+    RBF_HIP(hipMemcpyAsync(S->u, state->u, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->v, state->v, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->cu, state->cu_prev, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->cv, state->cv_prev, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->pt, state->p_tilde, mb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->p, state->p, mb, hipMemcpyDeviceToDevice, st));
+    rbf_status rc = RBF_OK;
+    int done = 0;
+    for (; done < nsteps; ++done) {
+        rc = step_once(S, state->step + done == 0, stats);
+        if (stats) stats->status = rc;
+        if (rc != RBF_OK) break;
+    }
+    if (stats) stats->steps_done = done;
+    if (done > 0) {
+        RBF_HIP(hipMemcpyAsync(state->u, S->u, nb, hipMemcpyDeviceToDevice, st));
+        RBF_HIP(hipMemcpyAsync(state->v, S->v, nb, hipMemcpyDeviceToDevice, st));
+        RBF_HIP(hipMemcpyAsync(state->cu_prev, S->cu, nb, hipMemcpyDeviceToDevice, st));
+        RBF_HIP(hipMemcpyAsync(state->cv_prev, S->cv, nb, hipMemcpyDeviceToDevice, st));
+        RBF_HIP(hipMemcpyAsync(state->p_tilde, S->pt, mb, hipMemcpyDeviceToDevice, st));
+        RBF_HIP(hipMemcpyAsync(state->p, S->p, mb, hipMemcpyDeviceToDevice, st));
+        state->step += done;
+    }
+    RBF_HIP(hipStreamSynchronize(st));
+    return rc;
+}
+
+extern "C" rbf_status rbf_solve_pressure(rbf_solver *S, const double *rhs, double *p_tilde,
+                                         rbf_solve_stats *stats) {
+    rbf::clear_error();
+    RBF_ARG(S && rhs && p_tilde, "rbf_solve_pressure: NULL argument");
+    EllM P{S->idx_pp, S->p_w, S->p_dinv, S->M, S->k};
+    hipLaunchKernelGGL(k_scale, dim3(rbf::blocks_for(S->M, 256)), dim3(256), 0, S->st, S->M,
+                       S->p_rowscale, rhs, S->p_rhs_tmp);
+    RBF_CHECK_LAUNCH();
+    rbf_status rc = bicgstab<1>(S, S->kp, P, S->p_rhs_tmp, p_tilde, S->sbuf_p, S->rtol_p,
+                                S->maxit_p, S->last_iters_p, stats);
+    return rc;
+}
+
+extern "C" rbf_status rbf_solver_profile(rbf_solver *S, int32_t sample_every, double *avg_ms,
+                                         int64_t *count) {
+    rbf::clear_error();
+    RBF_ARG(S, "rbf_solver_profile: NULL solver");
+    if (avg_ms) *avg_ms = S->prof_count ? S->prof_ms / (double)S->prof_count : 0.0;
+    if (count) *count = S->prof_count;
+    if (sample_every >= 0) {
+        if (sample_every > 0 && !S->ev0) {
+            RBF_HIP(hipEventCreate(&S->ev0));
+            RBF_HIP(hipEventCreate(&S->ev1));
+        }
+        S->prof_every = sample_every;
+        S->prof_launches = 0;
+        S->prof_count = 0;
+        S->prof_ms = 0.0;
+    }
+    return RBF_OK;
+}
+
+extern "C" void rbf_solver_destroy(rbf_solver *S) {
+    if (!S) return;
+    if (S->st) hipStreamSynchronize(S->st);
+    if (S->ev0) hipEventDestroy(S->ev0);
+    if (S->ev1) hipEventDestroy(S->ev1);
+    for (void *p : S->allocs) hipFree(p);
+    if (S->hflag) hipHostFree(S->hflag);
+    if (S->hred) hipHostFree(S->hred);
+    delete S;
+}

@@ -1,0 +1,384 @@
+// rbf_assemble_weights: batched local PHS+poly RBF-FD weight solves.
+//
+// Sec. 2.1 (eqs. (3)-(9)): for evaluation node x_0 with stencil x_1..x_n,
+//   [A P; P^T 0] [w; c] = [L phi; L P],  A_ij = ||x_i - x_j||^m,
+// P_jt = the monomials of degree <= q at x_j, right-hand sides L applied to
+// phi(||x - x_j||) and to the monomials at x = x_0; w is kept.
+//
+// One wavefront (64 lanes) solves one system.  Lane i owns row i of the
+// augmented matrix (s = n + K_p <= 64 rows) in registers; LU with partial
+// pivoting runs across lanes: the pivot is found by a butterfly arg-max over
+// the wave, its row is broadcast through LDS, and every other unfinished row
+// eliminates with it (row swaps are virtual: each lane remembers the step at
+// which its row became pivot).  All right-hand sides (one per operator) are
+// eliminated together.  One step of iterative refinement with a residual
+// accumulated in double-FP64 arithmetic (exact products via fma) brings the
+// solution to within a few ulps of the exact solution of the FP64 system.
+//
+// Local coordinates: x~ = (x_j - x_0) * 2^-e with e = ceil(E/2),
+// max_j |x_j - x_0|^2 = f 2^E, 1/2 <= f < 1 (exact scaling); weights are
+// returned as w~ * 2^(-e * order).  Matrix and right-hand-side entries are
+// computed with separately rounded operations (file built with
+// -ffp-contract=off): squared distances dx*dx + dy*dy, r = sqrt(d^2),
+// r^m = (d^2)^((m-1)/2) * r as a left-to-right product chain.
+// A system is reported singular when a pivot is not larger than
+// 16 eps max|A_aug| (e.g. duplicated stencil nodes) or a weight is not finite.
+#include <climits>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kMaxOps = 4;
+
+struct OpSet {
+    int n;               // number of operators
+    int code[kMaxOps];   // RBF_OP_* codes
+    int order[kMaxOps];  // derivative order (scaling exponent multiplier)
+};
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double ipow(double b, int n) {
+    if (n == 0) return 1.0;
+    double t = b;
+    for (int i = 1; i < n; ++i) t = t * b;
+    return t;
+}
+
+// t^a from a table of powers p[0..5] with a runtime exponent a.
+__device__ __forceinline__ double pick_pow(const double (&p)[6], int a) {
+    double r = p[0];
+#pragma unroll
+    for (int i = 1; i < 6; ++i) r = (a == i) ? p[i] : r;
+    return r;
+}
+
+__device__ __forceinline__ void powers(double t, int q, double (&p)[6]) {
+    p[0] = 1.0;
+#pragma unroll
+    for (int i = 1; i < 6; ++i) p[i] = (i <= q) ? p[i - 1] * t : 0.0;
+}
+
+// Graded monomial index t -> exponents (a, b): degree d, b = t - d(d+1)/2.
+__device__ __forceinline__ void mono_exp(int t, int &a, int &b) {
+    int d = 0;
+    while ((d + 1) * (d + 2) / 2 <= t) ++d;
+    b = t - d * (d + 1) / 2;
+    a = d - b;
+}
+
+// L applied to phi(||x - x_j||) at x_0 = 0, for a stencil node at (x, y).
+__device__ __forceinline__ double rhs_phs(double x, double y, int m, int code) {
+    const double d2 = x * x + y * y;
+    const double r = sqrt(d2);
+    if (code == RBF_OP_ID) return ipow(d2, (m - 1) / 2) * r;
+    const double rm2 = ipow(d2, (m - 3) / 2) * r;
+    if (code == RBF_OP_DX) return (-(double)m * rm2) * x;
+    if (code == RBF_OP_DY) return (-(double)m * rm2) * y;
+    return (double)(m * m) * rm2;  // Laplacian of r^m in 2-D
+}
+
+// L applied to monomial x^a y^b at x_0 = 0.
+__device__ __forceinline__ double rhs_poly(int a, int b, int code) {
+    if (code == RBF_OP_ID) return (a == 0 && b == 0) ? 1.0 : 0.0;
+    if (code == RBF_OP_DX) return (a == 1 && b == 0) ? 1.0 : 0.0;
+    if (code == RBF_OP_DY) return (a == 0 && b == 1) ? 1.0 : 0.0;
+    return ((a == 2 && b == 0) || (a == 0 && b == 2)) ? 2.0 : 0.0;
+}
+
+template <int SMAX>
+__global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, int64_t nq,
+                                                const double *__restrict__ xs, int64_t ns,
+                                                const int *__restrict__ idx, int n, int m, int q,
+                                                OpSet ops, double *__restrict__ w,
+                                                unsigned long long *__restrict__ bad) {
+    __shared__ double sx[64], sy[64];
+    __shared__ double prow[SMAX + kMaxOps];
+    __shared__ double sol[kMaxOps][SMAX];
+    __shared__ int pl[SMAX];
+
+    const int64_t row = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int kp = (q < 0) ? 0 : (q + 1) * (q + 2) / 2;
+    const int s = n + kp;
+
+    // 1. Stencil in shifted coordinates; exact power-of-two scaling.
+    double dx = 0.0, dy = 0.0, d2 = 0.0;
+    if (lane < n) {
+        const int j = idx[(int64_t)lane * nq + row];
+        dx = xs[j] - xq[row];
+        dy = xs[ns + j] - xq[nq + row];
+        d2 = dx * dx + dy * dy;
+    }
+    double d2max = d2;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) d2max = fmax(d2max, __shfl_xor(d2max, off, 64));
+    int E = 0;
+    frexp(d2max, &E);
+    const int e = (E >= 0) ? (E + 1) / 2 : -((-E) / 2);
+    bool bad_row = !(d2max > 0.0) || !isfinite(d2max);
+    const double xt = ldexp(dx, -e), yt = ldexp(dy, -e);
+    sx[lane] = xt;
+    sy[lane] = yt;
+    __syncthreads();
+
+    // 2. This lane's row of [A P; P^T 0] and its right-hand sides.
+    double a[SMAX], b[kMaxOps];
+    if (lane < n) {
+        double px[6], py[6];
+        powers(xt, q, px);
+        powers(yt, q, py);
+#pragma unroll
+        for (int j = 0; j < SMAX; ++j) {
+            double v = 0.0;
+            if (j < n) {
+                const double ddx = xt - sx[j], ddy = yt - sy[j];
+                const double dd = ddx * ddx + ddy * ddy;
+                v = ipow(dd, (m - 1) / 2) * sqrt(dd);
+            } else if (j < s) {
+                int ea, eb;
+                mono_exp(j - n, ea, eb);
+                v = pick_pow(px, ea) * pick_pow(py, eb);
+            }
+            a[j] = v;
+        }
+#pragma unroll
+        for (int o = 0; o < kMaxOps; ++o)
+            b[o] = (o < ops.n) ? rhs_phs(xt, yt, m, ops.code[o]) : 0.0;
+    } else if (lane < s) {
+        int ea, eb;
+        mono_exp(lane - n, ea, eb);
+#pragma unroll
+        for (int j = 0; j < SMAX; ++j) {
+            double v = 0.0;
+            if (j < n) {
+                double px[6], py[6];
+                powers(sx[j], q, px);
+                powers(sy[j], q, py);
+                v = pick_pow(px, ea) * pick_pow(py, eb);
+            }
+            a[j] = v;
+        }
+#pragma unroll
+        for (int o = 0; o < kMaxOps; ++o) b[o] = (o < ops.n) ? rhs_poly(ea, eb, ops.code[o]) : 0.0;
+    } else {
+#pragma unroll
+        for (int j = 0; j < SMAX; ++j) a[j] = 0.0;
+#pragma unroll
+        for (int o = 0; o < kMaxOps; ++o) b[o] = 0.0;
+    }
+    double a0[SMAX], b0[kMaxOps];
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j) a0[j] = a[j];
+#pragma unroll
+    for (int o = 0; o < kMaxOps; ++o) b0[o] = b[o];
+
+    // Scale for the singularity test: largest entry of the whole matrix.
+    double amax = 0.0;
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j) amax = fmax(amax, fabs(a[j]));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    const double tiny = 16.0 * __DBL_EPSILON__ * amax;
+
+    // 3. LU with partial pivoting across lanes.
+    int mystep = (lane < s) ? INT_MAX : -1;  // INT_MAX: row not yet a pivot
+    double myinv = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < SMAX; ++kk) {
+        if (kk < s) {
+            double cand = (mystep == INT_MAX) ? fabs(a[kk]) : -1.0;
+            int cl = lane;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ov = __shfl_xor(cand, off, 64);
+                const int ol = __shfl_xor(cl, off, 64);
+                const bool take = ov > cand || (ov == cand && ol < cl);
+                cand = take ? ov : cand;
+                cl = take ? ol : cl;
+            }
+            const int piv = __builtin_amdgcn_readfirstlane(cl);
+            const double pv = readlane_d(a[kk], piv);
+            if (!(fabs(pv) > tiny) || !isfinite(pv)) bad_row = true;
+            const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
+            if (lane == piv) {
+                mystep = kk;
+                myinv = inv;
+#pragma unroll
+                for (int j = kk + 1; j < SMAX; ++j) prow[j] = a[j];
+#pragma unroll
+                for (int o = 0; o < kMaxOps; ++o) prow[SMAX + o] = b[o];
+                pl[kk] = lane;
+            }
+            __syncthreads();
+            if (mystep == INT_MAX) {
+                const double l = a[kk] * inv;
+                a[kk] = l;  // multiplier, kept for the refinement solve
+#pragma unroll
+                for (int j = kk + 1; j < SMAX; ++j) a[j] = fma(-l, prow[j], a[j]);
+#pragma unroll
+                for (int o = 0; o < kMaxOps; ++o) b[o] = fma(-l, prow[SMAX + o], b[o]);
+            }
+            __syncthreads();
+        }
+    }
+
+    // 4. Back substitution: unknown kk lives in the pivot lane of step kk.
+#pragma unroll
+    for (int kk = SMAX - 1; kk >= 0; --kk) {
+        if (kk < s) {
+            const int pk = pl[kk];
+#pragma unroll
+            for (int o = 0; o < kMaxOps; ++o) {
+                if (o < ops.n) {
+                    const double xk = readlane_d(b[o] * myinv, pk);
+                    if (mystep < kk) b[o] = fma(-a[kk], xk, b[o]);
+                    if (lane == 0) sol[o][kk] = xk;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // 5. One refinement step: r = b0 - A0 x in double-FP64, solve with LU.
+    double r[kMaxOps];
+#pragma unroll
+    for (int o = 0; o < kMaxOps; ++o) {
+        double hi = b0[o], lo = 0.0;
+        if (o < ops.n && lane < s) {
+#pragma unroll
+            for (int j = 0; j < SMAX; ++j) {
+                if (j < s) {
+                    const double xj = sol[o][j];
+                    const double p = a0[j] * xj;
+                    const double pe = fma(a0[j], xj, -p);
+                    const double t = hi - p;
+                    const double bv = t - hi;
+                    const double err = (hi - (t - bv)) + (-p - bv);
+                    hi = t;
+                    lo = lo + (err - pe);
+                }
+            }
+        }
+        r[o] = hi + lo;
+    }
+    // Forward substitution with the stored multipliers (virtual pivoting).
+#pragma unroll
+    for (int kk = 0; kk < SMAX; ++kk) {
+        if (kk < s) {
+            const int pk = pl[kk];
+#pragma unroll
+            for (int o = 0; o < kMaxOps; ++o) {
+                if (o < ops.n) {
+                    const double yk = readlane_d(r[o], pk);
+                    if (mystep > kk && mystep != INT_MAX) r[o] = fma(-a[kk], yk, r[o]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int kk = SMAX - 1; kk >= 0; --kk) {
+        if (kk < s) {
+            const int pk = pl[kk];
+#pragma unroll
+            for (int o = 0; o < kMaxOps; ++o) {
+                if (o < ops.n) {
+                    const double dk = readlane_d(r[o] * myinv, pk);
+                    if (mystep < kk) r[o] = fma(-a[kk], dk, r[o]);
+                    if (lane == 0) sol[o][kk] += dk;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // 6. Weights in physical units; NaN for failed rows.
+    if (lane < n) {
+#pragma unroll
+        for (int o = 0; o < kMaxOps; ++o) {
+            if (o < ops.n) {
+                double v = ldexp(sol[o][lane], -e * ops.order[o]);
+                if (!isfinite(v)) bad_row = true;
+                w[((int64_t)o * n + lane) * nq + row] = v;
+            }
+        }
+    }
+    // A row is bad if any lane saw a problem.
+    const bool any_bad = __any(bad_row);
+    if (any_bad) {
+        if (lane < n) {
+            for (int o = 0; o < ops.n; ++o) w[((int64_t)o * n + lane) * nq + row] = NAN;
+        }
+        if (lane == 0) atomicMin(bad, (unsigned long long)row);
+    }
+}
+
+}  // namespace
+
+extern "C" rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const double *xs,
+                                           int64_t ns, const int32_t *idx, int32_t k, int32_t m,
+                                           int32_t q, uint32_t op_mask, double *w,
+                                           int64_t *bad_row, rbf_stream st_) {
+    rbf::clear_error();
+    const bool force = (op_mask & RBF_FORCE_SMALL_STENCIL) != 0;
+    op_mask &= ~RBF_FORCE_SMALL_STENCIL;
+    RBF_ARG(bad_row, "rbf_assemble_weights: bad_row must not be NULL");
+    *bad_row = -1;
+    RBF_ARG(op_mask != 0 && (op_mask & ~15u) == 0, "rbf_assemble_weights: op_mask must be a non-empty subset of ID|DX|DY|LAP");
+    RBF_ARG(q >= -1 && q <= 5, "rbf_assemble_weights: q must be in [-1, 5]");
+    RBF_ARG(m >= 1 && m <= 11 && (m % 2) == 1, "rbf_assemble_weights: m must be odd in [1, 11]");
+    RBF_ARG((op_mask & ~RBF_OP_ID) == 0 || m >= 3,
+            "rbf_assemble_weights: derivative operators need m >= 3 (L phi continuous)");
+    const int kp = (q < 0) ? 0 : (q + 1) * (q + 2) / 2;
+    RBF_ARG(k >= 1 && k + kp <= 64, "rbf_assemble_weights: need 1 <= k and k + (q+1)(q+2)/2 <= 64");
+    RBF_ARG(kp < k, "rbf_assemble_weights: stencil must have more nodes than monomials");
+    RBF_ARG(force || q < 0 || k >= (q + 1) * (q + 2),
+            "rbf_assemble_weights: k < (q+1)(q+2) violates the stability rule (set RBF_FORCE_SMALL_STENCIL to override)");
+    RBF_ARG(ns >= k && nq >= 0 && nq < INT_MAX && ns < INT_MAX, "rbf_assemble_weights: sizes out of range");
+    RBF_ARG(xs && (nq == 0 || (xq && idx && w)), "rbf_assemble_weights: NULL pointer");
+    if (nq == 0) return RBF_OK;
+    OpSet ops{};
+    for (int c : {1, 2, 4, 8}) {
+        if (op_mask & c) {
+            ops.code[ops.n] = c;
+            ops.order[ops.n] = (c == 1) ? 0 : (c == 8 ? 2 : 1);
+            ++ops.n;
+        }
+    }
+    hipStream_t st = rbf::as_stream(st_);
+    unsigned long long *dbad = nullptr;
+    RBF_HIP(hipMalloc(&dbad, sizeof(unsigned long long)));
+    unsigned long long init = ~0ull;
+    rbf_status rc = RBF_OK;
+    hipError_t e = hipMemcpyAsync(dbad, &init, sizeof(init), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        if (k + kp <= 40)
+            hipLaunchKernelGGL(k_weights<40>, dim3((uint32_t)nq), dim3(64), 0, st, xq, nq, xs, ns,
+                               idx, k, m, q, ops, w, dbad);
+        else
+            hipLaunchKernelGGL(k_weights<64>, dim3((uint32_t)nq), dim3(64), 0, st, xq, nq, xs, ns,
+                               idx, k, m, q, ops, w, dbad);
+        e = hipGetLastError();
+    }
+    unsigned long long hb = ~0ull;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hb, dbad, sizeof(hb), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(dbad);
+    if (e != hipSuccess) {
+        rbf::set_error("rbf_assemble_weights: %s", hipGetErrorString(e));
+        return RBF_E_DEVICE;
+    }
+    if (hb != ~0ull) {
+        *bad_row = (int64_t)hb;
+        rbf::set_error("rbf_assemble_weights: singular or non-finite system at row %lld",
+                       (long long)hb);
+        rc = RBF_E_SINGULAR;
+    }
+    return rc;
+}

@@ -1,0 +1,263 @@
+"""GPU (HIP, through the C ABI) against the CPU oracle on identical seeded
+inputs.  Bars: stencil indices bit-exact; weights within 1e-12 relative per
+row; FP64 fields within 1e-10 relative; ELL products within the rounding
+bound of their summation."""
+import numpy as np
+import pytest
+
+import rbf_inputs as ri
+from oracle import knn as oknn, weights as ow, operators as oops, cavity as ocav
+from tests.helpers import (OP_ID, OP_DX, OP_DY, OP_LAP, rel_err, row_rel_err, to_dev,
+                           gpu_cavity_ops)
+
+pytestmark = pytest.mark.gpu
+
+OPS_ALL = [OP_ID, OP_DX, OP_DY, OP_LAP]
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P(gpu):
+    import paper_2206_06495_amd as P
+    return P
+
+
+def _pairs(nd):
+    return {"vv": (nd.xv, nd.xv), "pv": (nd.xp, nd.xv), "pp": (nd.xp, nd.xp), "vp": (nd.xv, nd.xp)}
+
+
+@pytest.mark.parametrize("K,jit,seed", [(40, 0.3, 0), (13, 0.0, 1), (7, 0.25, 2)])
+def test_knn_cavity_bit_exact(P, gpu, K, jit, seed):
+    _say("knn cavity", K, jit, seed)
+    nd = ri.cavity_nodes(K, jit, seed)
+    for name, (xq, xs) in _pairs(nd).items():
+        idx = P.knn(to_dev(xq, gpu), to_dev(xs, gpu), 28).cpu().numpy()
+        ref = oknn.knn_bruteforce(xq, xs, 28)
+        assert np.array_equal(idx, ref), name
+        if name in ("vv", "pp"):
+            assert np.array_equal(idx[0], np.arange(xq.shape[1]))
+
+
+@pytest.mark.parametrize("jit", [0.0, 0.3])
+@pytest.mark.parametrize("k", [1, 5, 28, 33, 64])
+def test_knn_square_ties_and_widths(P, gpu, jit, k):
+    _say("knn square", jit, k)
+    nd = ri.square_nodes(23, jit, 3)
+    for xq, xs in ((nd.xv, nd.xv), (nd.xp, nd.xv)):
+        idx = P.knn(to_dev(xq, gpu), to_dev(xs, gpu), k).cpu().numpy()
+        assert np.array_equal(idx, oknn.knn_bruteforce(xq, xs, k))
+
+
+def test_knn_degenerate_inputs(P, gpu):
+    import torch
+    _say("knn degenerate")
+    xs = np.array([[0.0, 1.0, 2.0], [0.0, 0.0, 0.0]])  # collinear sources
+    xq = np.array([[0.4, 5.0, -3.0], [0.0, 7.0, 0.0]])  # queries outside the box too
+    idx = P.knn(to_dev(xq, gpu), to_dev(xs, gpu), 3).cpu().numpy()
+    assert np.array_equal(idx, oknn.knn_bruteforce(xq, xs, 3))
+    empty = P.knn(torch.zeros((2, 0), dtype=torch.float64, device=gpu), to_dev(xs, gpu), 2)
+    assert empty.shape == (2, 0)
+    with pytest.raises(P.RbfError):
+        P.knn(to_dev(xq, gpu), to_dev(xs, gpu), 4)  # k > ns
+
+
+@pytest.mark.parametrize("K,seed", [(40, 0), (9, 1)])
+def test_weights_cavity_parity(P, gpu, K, seed):
+    _say("weights cavity", K, seed)
+    nd = ri.cavity_nodes(K, 0.3, seed)
+    worst = 0.0
+    for name, (xq, xs) in _pairs(nd).items():
+        dq, ds = to_dev(xq, gpu), to_dev(xs, gpu)
+        idx = P.knn(dq, ds, 28)
+        w = P.assemble_weights(dq, ds, idx, 7, 3, 15).cpu().numpy()
+        ref = ow.stencil_weights(xq, xs, idx.cpu().numpy(), 7, 3, OPS_ALL)
+        for o in range(4):
+            e = row_rel_err(w[o], ref[o])
+            worst = max(worst, e)
+            assert e <= 1e-12, (name, o, e)
+    _say("worst weight error", worst)
+
+
+@pytest.mark.parametrize("n,m,q,mask", [(28, 7, -1, 15), (12, 3, 1, 15), (20, 5, 2, 7),
+                                        (36, 9, 4, 15), (45, 7, 3, 8), (28, 1, 2, 1),
+                                        (40, 9, 3, 6), (43, 7, 5, 15)])
+def test_weights_parameter_variants(P, gpu, n, m, q, mask):
+    _say("weights variant", n, m, q, mask)
+    nd = ri.cavity_nodes(11, 0.3, 4)
+    xq, xs = nd.xv, nd.xp
+    dq, ds = to_dev(xq, gpu), to_dev(xs, gpu)
+    idx = P.knn(dq, ds, n)
+    force = q >= 0 and n < (q + 1) * (q + 2)
+    w = P.assemble_weights(dq, ds, idx, m, q, mask, force=force).cpu().numpy()
+    ops = [c for c in OPS_ALL if mask & c]
+    ref = ow.stencil_weights(xq, xs, idx.cpu().numpy(), m, q, ops, force=True)
+    for o in range(len(ops)):
+        assert row_rel_err(w[o], ref[o]) <= 1e-12, (ops[o], row_rel_err(w[o], ref[o]))
+
+
+def test_weights_argument_checks(P, gpu):
+    nd = ri.cavity_nodes(6, 0.3, 0)
+    dq = to_dev(nd.xv, gpu)
+    idx = P.knn(dq, dq, 28)
+    for m, q, mask in ((6, 3, 15), (7, 6, 15), (1, 3, 2), (7, 3, 0), (7, 4, 15)):
+        with pytest.raises(P.RbfError) as ei:
+            P.assemble_weights(dq, dq, idx, m, q, mask)
+        assert ei.value.status == -1
+
+
+def test_weights_singular_row_reported(P, gpu):
+    import torch
+    _say("weights singular")
+    nd = ri.cavity_nodes(8, 0.3, 0)
+    xs = nd.xv.copy()
+    xs[:, 5] = xs[:, 4]  # duplicated node -> singular local systems
+    d = to_dev(xs, gpu)
+    idx = P.knn(d, d, 28)
+    import ctypes
+    from paper_2206_06495_amd import _lib
+    w = torch.empty((1, 28, xs.shape[1]), dtype=torch.float64, device=gpu)
+    bad = ctypes.c_int64(-7)
+    rc = _lib.lib.rbf_assemble_weights(ctypes.c_void_p(d.data_ptr()), xs.shape[1],
+                                       ctypes.c_void_p(d.data_ptr()), xs.shape[1],
+                                       ctypes.c_void_p(idx.data_ptr()), 28, 7, 3, 2,
+                                       ctypes.c_void_p(w.data_ptr()), ctypes.byref(bad), None)
+    torch.cuda.synchronize()
+    assert rc == _lib.RBF_E_SINGULAR
+    idxh = idx.cpu().numpy()
+    rows_with_both = np.nonzero(np.isin(idxh, [4]).any(0) & np.isin(idxh, [5]).any(0))[0]
+    assert bad.value == rows_with_both.min()
+    assert np.isnan(w.cpu().numpy()[0][:, bad.value]).all()
+
+
+def test_weights_bench_square_sampled(P, gpu):
+    """Operator-bench size (10^6 + 10^6 nodes): full GPU assembly, oracle on
+    sampled rows."""
+    _say("weights bench square 1000")
+    nd = ri.square_nodes(1000, 0.3, 0)
+    rng = np.random.default_rng(5)
+    for xq, xs, mask in ((nd.xv, nd.xv, OP_DX | OP_DY | OP_LAP), (nd.xp, nd.xv, OP_ID)):
+        dq, ds = to_dev(xq, gpu), to_dev(xs, gpu)
+        idx = P.knn(dq, ds, 28)
+        w = P.assemble_weights(dq, ds, idx, 7, 3, mask)
+        rows = np.sort(np.concatenate([rng.choice(xq.shape[1], 1500, replace=False),
+                                       [0, xq.shape[1] - 1]]))
+        idx_h = idx.cpu().numpy()
+        ref_idx = oknn.knn_bruteforce(xq[:, rows], xs, 28)
+        assert np.array_equal(idx_h[:, rows], ref_idx)
+        ops = [c for c in OPS_ALL if mask & c]
+        ref = ow.stencil_weights(xq[:, rows], xs, ref_idx, 7, 3, ops)
+        wh = w.cpu().numpy()
+        for o in range(len(ops)):
+            assert row_rel_err(wh[o][:, rows], ref[o]) <= 1e-12
+        assert np.isfinite(wh).all()
+
+
+def _sum_bound(idx, w, x, u):
+    return 2.0 * idx.shape[0] * u * np.sum(np.abs(w * x[idx]), axis=0) + 1e-300
+
+
+def test_ell_apply_parity(P, gpu):
+    import torch
+    _say("ell apply")
+    nd = ri.cavity_nodes(40, 0.3, 0)
+    for n in (28, 17):
+        dv = to_dev(nd.xv, gpu)
+        idx = P.knn(dv, dv, n)
+        w = P.assemble_weights(dv, dv, idx, 7, 3, OP_DX | OP_LAP, force=True)
+        x = ri.random_vector(nd.n_v, 11)
+        idx_h, w_h = idx.cpu().numpy(), w.cpu().numpy()
+        for o in range(2):
+            y = P.ell_apply(idx, w[o].contiguous(), to_dev(x, gpu)).cpu().numpy()
+            ref = oops.ell_apply(idx_h, w_h[o], x)
+            assert np.all(np.abs(y - ref) <= _sum_bound(idx_h, w_h[o], x, 2.0 ** -53))
+            # FP32-stored: inputs rounded to FP32 on the GPU, FP32 accumulation.
+            w32 = P.cast_f32(w[o].contiguous())
+            x32 = P.cast_f32(to_dev(x, gpu))
+            y32 = P.ell_apply(idx, w32, x32).cpu().numpy().astype(np.float64)
+            w32h = w32.cpu().numpy().astype(np.float64)
+            x32h = x32.cpu().numpy().astype(np.float64)
+            assert np.array_equal(w32h, w_h[o].astype(np.float32).astype(np.float64))
+            ref32 = oops.ell_apply(idx_h, w32h, x32h)
+            assert np.all(np.abs(y32 - ref32) <= _sum_bound(idx_h, w32h, x32h, 2.0 ** -24))
+    # Ragged tail and one-row operators.
+    idx = torch.zeros((28, 1), dtype=torch.int32, device=gpu)
+    w = torch.ones((28, 1), dtype=torch.float64, device=gpu)
+    y = P.ell_apply(idx, w, torch.full((1,), 0.5, dtype=torch.float64, device=gpu))
+    assert float(y.cpu()[0]) == 14.0
+
+
+def _gpu_solver(P, nd, gpu, re, dt, **kw):
+    grid, ops = gpu_cavity_ops(nd, gpu)
+    u_bc, v_bc = ri.cavity_bc(nd.v_tag)
+    S = P.Solver(grid, ops, to_dev(u_bc, gpu), to_dev(v_bc, gpu), re, dt, **kw)
+    return S, ops, u_bc, v_bc
+
+
+def test_cavity_parity_small_workload(P, gpu):
+    """K=40 cavity (N=4880, M=1681), Re=100, dt=2e-3, 200 steps: GPU BiCGSTAB
+    against the oracle's LU, u, v, p within 1e-10 every 20 steps."""
+    _say("cavity parity K=40")
+    nd = ri.cavity_nodes(40, 0.3, 0)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 2e-3)
+    orc = ocav.CavityOracle(nd, u_bc, v_bc, 100.0, 2e-3)
+    s0 = orc.initial_state()
+    st = S.new_state(to_dev(s0.u, gpu), to_dev(s0.v, gpu))
+    so = s0
+    worst = 0.0
+    for chunk in range(10):
+        stats = S.step(st, 20)
+        so = orc.run(20, so)
+        for key, ref in (("u", so.u), ("v", so.v), ("p", so.p), ("p_tilde", so.pt)):
+            e = rel_err(st[key].cpu().numpy(), ref)
+            worst = max(worst, e)
+            assert e <= 1e-10, (chunk, key, e)
+        assert stats.steps_done == 20
+        assert stats.last_poisson.converged and stats.last_poisson.rel_residual < 1e-11
+    assert st["step"] == 200
+    _say("cavity worst rel err", worst, "poisson iters/step", stats.poisson_iters / 20)
+    S.close()
+
+
+def test_solve_pressure_parity(P, gpu):
+    _say("solve_pressure")
+    nd = ri.cavity_nodes(24, 0.3, 1)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 1e-3)
+    orc = ocav.CavityOracle(nd, u_bc, v_bc, 100.0, 1e-3)
+    rhs = ri.random_vector(nd.n_p, 3)
+    rhs[nd.p_tag != 0] = 0.0
+    rhs[orc.pin] = 0.0
+    x = to_dev(np.zeros(nd.n_p), gpu)
+    stats = S.solve_pressure(to_dev(rhs, gpu), x)
+    ref = orc.Lp_lu.solve(rhs)
+    assert stats.converged and stats.rel_residual <= 1e-10
+    assert rel_err(x.cpu().numpy(), ref) <= 1e-10
+    S.close()
+
+
+def test_step_error_paths_are_transactional(P, gpu):
+    import torch
+    _say("error paths")
+    nd = ri.cavity_nodes(12, 0.3, 0)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 2e-3, maxit_p=1)
+    st = S.new_state(to_dev(np.where(nd.v_tag != 0, u_bc, 0.0), gpu), to_dev(v_bc, gpu))
+    before = {k: (v.clone() if isinstance(v, torch.Tensor) else v) for k, v in st.items()}
+    with pytest.raises(P.RbfError) as ei:
+        S.step(st, 3)
+    assert ei.value.status == -3  # RBF_E_NOCONV
+    for k, v in before.items():
+        if isinstance(v, torch.Tensor):
+            assert torch.equal(v, st[k]), k
+    assert st["step"] == 0
+    S.close()
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 2e-3)
+    u0 = np.where(nd.v_tag != 0, u_bc, 0.0)
+    u0[np.nonzero(nd.v_tag == 0)[0][3]] = np.nan
+    st = S.new_state(to_dev(u0, gpu), to_dev(v_bc, gpu))
+    with pytest.raises(P.RbfError) as ei:
+        S.step(st, 1)
+    assert ei.value.status == -6  # RBF_E_NAN
+    assert st["step"] == 0
+    S.close()
