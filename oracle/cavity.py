@@ -18,9 +18,10 @@ paper does at the end of Sec. 3 (dense LU for small grids, SuperLU above).
 Readings where the paper is silent or ambiguous:
   * AB2 start: C_{-1} := C_0.
   * The CN right-hand side acts on u* (eq. (16) as printed).
-  * Pressure boundary rows: homogeneous Neumann plus one pin row (see
-    ``operators.poisson_matrix``); the Poisson right-hand side is F/dt on
-    interior P-rows and 0 on wall and pin rows.
+  * Pressure boundary rows: homogeneous Neumann, with the Neumann system
+    bordered by a uniform source and a zero-mean condition on p~ (see
+    ``operators.poisson_matrix``); the right-hand side is F/dt on interior
+    P-rows and 0 on wall rows.
   * Eq. (20) is applied on every V row, wall rows included, and the Kim-Moin
     values enter u** (and hence the divergence F) on wall rows: the scheme as
     printed.  Wall velocities then equal the boundary values to O(dt^2) and are
@@ -74,7 +75,7 @@ class CavityOracle:
         if dense is None:
             dense = max(nodes.n_v, nodes.n_p) <= 6000
         self.H = helmholtz_matrix(self.ops, self.a)
-        self.Lp, self.pin = poisson_matrix(self.ops)
+        self.A0, self.chi, self.Lp = poisson_matrix(self.ops)
         self.H_lu = _Factored(self.H, dense)
         self.Lp_lu = _Factored(self.Lp, dense)
 
@@ -92,9 +93,12 @@ class CavityOracle:
         return cu, cv
 
     def pressure_rhs(self, F):
-        rhs = np.where(self.pint, F / self.dt, 0.0)
-        rhs[self.pin] = 0.0
-        return rhs
+        return np.where(self.pint, F / self.dt, 0.0)
+
+    def solve_pressure(self, rhs):
+        """p~ (zero mean) and the uniform source lam of the bordered system."""
+        sol = self.Lp_lu.solve(np.concatenate([rhs, [0.0]]))
+        return sol[:-1], sol[-1]
 
     def step(self, s, stages=None):
         """Advance one step; returns the new state.  ``stages`` (a dict), if
@@ -116,13 +120,13 @@ class CavityOracle:
         # Stage 3: divergence, pressure Poisson, pressure and correction.
         F = o.Dx_pv @ uss + o.Dy_pv @ vss
         prhs = self.pressure_rhs(F)
-        pt = self.Lp_lu.solve(prhs)
+        pt, lam = self.solve_pressure(prhs)
         p = pt - a * (o.L_pp @ pt)
         un = uss - dt * (o.Dx_vp @ pt)
         vn = vss - dt * (o.Dy_vp @ pt)
         if stages is not None:
             stages.update(cu=cu, cv=cv, us=us, vs=vs, ru=ru, rv=rv, uss=uss, vss=vss,
-                          F=F, prhs=prhs)
+                          F=F, prhs=prhs, lam=lam)
         return CavityState(un, vn, pt, p, cu, cv, s.step + 1)
 
     def run(self, nsteps, state=None, every=None, callback=None):

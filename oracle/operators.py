@@ -74,16 +74,6 @@ class CavityOperators:
         self.Dy_vp = self.vp.csr(Y)
 
 
-def pin_index(xp, p_tag):
-    """The pressure pin: the interior P-node nearest (0.5, 0.5), lowest index
-    on a tie (distance squared without fused multiply-add)."""
-    dx = xp[0] - 0.5
-    dy = xp[1] - 0.5
-    d2 = dx * dx + dy * dy
-    d2 = np.where(p_tag == 0, d2, np.inf)
-    return int(np.argmin(d2))  # argmin returns the first minimum
-
-
 def helmholtz_matrix(ops, a):
     """Crank-Nicolson matrix of eq. (16): I - a D_Lap^(V,V) on interior V rows,
     identity on wall rows (which carry the Dirichlet/Kim-Moin values)."""
@@ -94,22 +84,29 @@ def helmholtz_matrix(ops, a):
 
 
 def poisson_matrix(ops):
-    """Pressure-Poisson matrix of eq. (18) with boundary rows.
+    """Pressure-Poisson operator of eq. (18) with boundary rows, bordered.
 
-    The paper states no pressure boundary condition.  Reading: the
-    pressure correction of the Kim-Moin scheme satisfies a homogeneous Neumann
-    condition, so wall P-rows are n_x D_x^(P,P) + n_y D_y^(P,P); with Neumann
-    rows the matrix has the constants as a null vector, which one pin row
-    (identity at ``pin_index``) removes.  Interior rows are D_Lap^(P,P).
+    The paper states no pressure boundary condition.  Reading: the pressure
+    correction of the Kim-Moin scheme satisfies a homogeneous Neumann
+    condition, so wall P-rows are n_x D_x^(P,P) + n_y D_y^(P,P); interior rows
+    are D_Lap^(P,P).  With Neumann rows the constants span the null space and
+    the right-hand side F/dt is in general not compatible with the discrete
+    operator, so the system is bordered: one Lagrange multiplier lam enters
+    every interior row as a uniform source and one row fixes mean(p~) = 0,
+
+        [ A0   chi ] [p~ ]   [ F/dt on interior rows, 0 on wall rows ]
+        [ 1/M  0   ] [lam] = [ 0                                     ]
+
+    (chi = indicator of interior rows).  Returns (A0, chi) in CSR/ndarray
+    form and the bordered (M+1) x (M+1) matrix.
     """
     nd = ops.nodes
     M = nd.n_p
     interior = (nd.p_tag == 0).astype(np.float64)
     wall = 1.0 - interior
-    Lmat = sp.diags(interior) @ ops.L_pp
-    Nmat = sp.diags(wall * nd.p_normal[0]) @ ops.Dx_pp + sp.diags(wall * nd.p_normal[1]) @ ops.Dy_pp
-    Amat = (Lmat + Nmat).tolil()
-    pin = pin_index(nd.xp, nd.p_tag)
-    Amat[pin, :] = 0.0
-    Amat[pin, pin] = 1.0
-    return Amat.tocsr(), pin
+    A0 = (sp.diags(interior) @ ops.L_pp + sp.diags(wall * nd.p_normal[0]) @ ops.Dx_pp
+          + sp.diags(wall * nd.p_normal[1]) @ ops.Dy_pp).tocsr()
+    border_col = sp.csr_matrix(interior[:, None])
+    border_row = sp.csr_matrix(np.full((1, M), 1.0 / M))
+    B = sp.bmat([[A0, border_col], [border_row, None]], format="csr")
+    return A0, interior, B

@@ -287,19 +287,27 @@ def test_ell_csr_consistency():
 
 
 def test_poisson_matrix_structure():
-    """Neumann rows annihilate constants (polynomial reproduction), so the
-    unpinned matrix is singular and the pinned one is not."""
+    """Neumann rows and Laplacian rows annihilate constants (polynomial
+    reproduction), so A0 is singular; the bordered system is not, and its
+    solution has zero mean with the incompatibility carried by lam."""
     nd = ri.cavity_nodes(8, 0.3, 1)
     ops = oops.CavityOperators(nd)
-    A, pin = oops.poisson_matrix(ops)
-    assert nd.p_tag[pin] == 0
-    d2 = (nd.xp[0] - 0.5) ** 2 + (nd.xp[1] - 0.5) ** 2
-    assert pin == np.argmin(np.where(nd.p_tag == 0, d2, np.inf))
-    Ad = A.toarray()
-    ones = np.ones(nd.n_p)
-    rows = np.arange(nd.n_p) != pin
-    assert np.max(np.abs((Ad @ ones)[rows])) < 1e-9 * np.abs(Ad).max()
-    assert np.linalg.svd(Ad, compute_uv=False).min() > 1e-8 * np.abs(Ad).max()
+    A0, chi, B = oops.poisson_matrix(ops)
+    Ad = A0.toarray()
+    assert np.max(np.abs(Ad @ np.ones(nd.n_p))) < 1e-9 * np.abs(Ad).max()
+    assert np.linalg.svd(Ad, compute_uv=False).min() < 1e-10 * np.abs(Ad).max()
+    Bd = B.toarray()
+    assert np.linalg.svd(Bd, compute_uv=False).min() > 1e-8
+    rhs = np.where(chi > 0, ri.random_vector(nd.n_p, 2), 0.0)
+    sol = np.linalg.solve(Bd, np.concatenate([rhs, [0.0]]))
+    pt, lam = sol[:-1], sol[-1]
+    assert abs(pt.mean()) < 1e-12 * np.abs(pt).max()
+    assert np.allclose(Ad @ pt + lam * chi, rhs, atol=1e-9 * np.abs(rhs).max())
+    # A compatible right-hand side (in the range of A0) needs no source.
+    q = np.cos(np.pi * nd.xp[0]) * np.cos(np.pi * nd.xp[1])
+    sol = np.linalg.solve(Bd, np.concatenate([Ad @ q, [0.0]]))
+    assert abs(sol[-1]) < 1e-8 * np.abs(Ad @ q).max()
+    assert np.allclose(sol[:-1], q - q.mean(), atol=1e-8)
 
 
 # ----------------------------------------------------------------- solver --
@@ -335,8 +343,9 @@ def test_first_step_stages_and_projection():
     assert np.allclose(st["ru"][wall], orc.u_bc[wall] + orc.dt * (o.Dx_vp @ s0.pt)[wall])
     assert np.allclose(st["rv"][wall], orc.v_bc[wall] + orc.dt * (o.Dy_vp @ s0.pt)[wall])
     assert np.allclose(st["uss"][wall], st["ru"][wall], atol=1e-14)
-    res = orc.Lp @ s1.pt - st["prhs"]
+    res = orc.A0 @ s1.pt + st["lam"] * orc.chi - st["prhs"]
     assert np.max(np.abs(res)) < 1e-8 * np.max(np.abs(st["prhs"]))
+    assert abs(s1.pt.mean()) < 1e-12 * np.max(np.abs(s1.pt))
     assert np.allclose(s1.p, s1.pt - orc.a * (o.L_pp @ s1.pt))
     x, y = nd.xv
     s0 = orc.initial_state()
@@ -345,7 +354,6 @@ def test_first_step_stages_and_projection():
     s1 = orc.step(s0, st)
     div = orc.divergence(s1.u, s1.v)
     far = np.minimum.reduce([nd.xp[0], nd.xp[1], 1 - nd.xp[0], 1 - nd.xp[1]]) > 0.2
-    far[orc.pin] = False  # the pin row replaces that node's Poisson equation
     assert np.max(np.abs(st["F"][far])) > 1.0
     assert np.max(np.abs(div[far])) < 0.05 * np.max(np.abs(st["F"][far]))
 
@@ -407,8 +415,10 @@ def test_brute_force_dense_tiny_cavity():
     H = np.eye(Nn) - a * np.where(wall[:, None], 0.0, D[("vv", L)])
     Pm = np.where((nd.p_tag == 0)[:, None], D[("pp", L)],
                   nd.p_normal[0][:, None] * D[("pp", X)] + nd.p_normal[1][:, None] * D[("pp", Y)])
-    Pm[orc.pin] = 0.0
-    Pm[orc.pin, orc.pin] = 1.0
+    Bm = np.zeros((Mm + 1, Mm + 1))
+    Bm[:Mm, :Mm] = Pm
+    Bm[:Mm, Mm] = (nd.p_tag == 0)
+    Bm[Mm, :Mm] = 1.0 / Mm
     u = np.where(wall, orc.u_bc, 0.0)
     v = np.zeros(Nn)
     pt = np.zeros(Mm)
@@ -426,8 +436,7 @@ def test_brute_force_dense_tiny_cavity():
         uss, vss = np.linalg.solve(H, ru), np.linalg.solve(H, rv)
         F = D[("pv", X)] @ uss + D[("pv", Y)] @ vss
         rhs = np.where(nd.p_tag == 0, F / dt, 0.0)
-        rhs[orc.pin] = 0.0
-        pt = np.linalg.solve(Pm, rhs)
+        pt = np.linalg.solve(Bm, np.concatenate([rhs, [0.0]]))[:-1]
         u, v = uss - dt * (D[("vp", X)] @ pt), vss - dt * (D[("vp", Y)] @ pt)
         cu_p, cv_p = cu, cv
         s = orc.step(s)
