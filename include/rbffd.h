@@ -205,6 +205,8 @@ typedef struct {
     int32_t iterations;    /* BiCGSTAB iterations of this solve             */
     int32_t converged;     /* 1 if the tolerance was met                    */
     double rel_residual;   /* ||b - A x|| / ||b|| recomputed at the end     */
+    int32_t restarts;      /* restarts after a BiCGSTAB breakdown           */
+    int32_t final_flag;    /* 0 running, 1 converged, -1 non-finite, 2 breakdown */
 } rbf_solve_stats;
 
 typedef struct {
@@ -222,17 +224,22 @@ typedef struct rbf_solver rbf_solver;
  *
  * Helmholtz (eq. (16)): H = I - a D_Lap^(V,V), a = dt/(2 Re), on interior
  * V rows, identity on wall rows (which carry the Kim-Moin values of
- * eq. (21)).  Pressure Poisson (eq. (18)): D_Lap^(P,P) on interior P rows;
- * homogeneous Neumann rows n_x D_x^(P,P) + n_y D_y^(P,P) on wall rows; one pin
- * row (identity) at the interior P-node nearest (0.5, 0.5), lowest index on
- * a tie.  Both are solved by BiCGSTAB: H with Jacobi preconditioning; the
- * Poisson matrix is stored row-scaled (interior rows by -1/||row||_2, wall
- * rows by +1/||row||_2) and iterated without further preconditioning, so its
- * residual tolerance applies to the row-scaled system.
+ * eq. (21)); solved by Jacobi-preconditioned BiCGSTAB.
+ * Pressure Poisson (eq. (18)): D_Lap^(P,P) on interior P rows and
+ * homogeneous Neumann rows n_x D_x^(P,P) + n_y D_y^(P,P) on wall rows.  The
+ * paper states no pressure boundary condition; with Neumann rows the
+ * constants are a null vector and F/dt is in general not compatible, so the
+ * system is bordered: a uniform source lam on interior rows absorbs the
+ * incompatibility and p~ has zero mean.  It is solved as
+ * (A0 + u1 v^T) x = b with the rank-one border, then p~ = x - mean(x); the
+ * operator is stored row-scaled (interior rows by -1/||row||_2, wall rows by
+ * +1/||row||_2) and iterated by unpreconditioned BiCGSTAB, so the Poisson
+ * tolerance applies to the row-scaled system.
  * u_bc, v_bc: device [n_v] boundary velocities (read on wall rows; copied).
  * The solver keeps `st` for all of its work.
  * Errors: RBF_E_ARG (NULL pointers, sizes, dt/re <= 0, precision != 0,
- * a self index missing from a (V,V) or (P,P) stencil), RBF_E_NOMEM.
+ * a self index missing from a (V,V) or (P,P) stencil, no interior P node),
+ * RBF_E_NOMEM.
  */
 rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, const rbf_ops *ops,
                              const double *u_bc, const double *v_bc, const rbf_params *prm,
@@ -250,11 +257,11 @@ rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, const rbf_o
 rbf_status rbf_step(rbf_solver *s, int32_t nsteps, rbf_state *state, rbf_step_stats *stats);
 
 /*
- * rbf_solve_pressure -- solve the pressure-Poisson system of eq. (18) (with
- * the boundary and pin rows above) for right-hand side rhs (device [n_p];
- * entries on wall and pin rows are the values those rows are set to).
- * p_tilde: device [n_p], initial guess in, solution out.  stats nullable.
- * Errors: RBF_E_ARG, RBF_E_NOCONV, RBF_E_NAN.
+ * rbf_solve_pressure -- solve the bordered pressure-Poisson system of
+ * eq. (18) described at rbf_solver_create: D_Lap^PP p~ + lam = rhs on
+ * interior rows, n . grad p~ = rhs on wall rows, mean(p~) = 0.  rhs: device
+ * [n_p]; p_tilde: device [n_p], initial guess in, zero-mean solution out.
+ * stats nullable.  Synchronises.  Errors: RBF_E_ARG, RBF_E_NOCONV, RBF_E_NAN.
  */
 rbf_status rbf_solve_pressure(rbf_solver *s, const double *rhs, double *p_tilde,
                               rbf_solve_stats *stats);

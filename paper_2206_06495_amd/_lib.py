@@ -62,7 +62,8 @@ class State(ctypes.Structure):
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("rel_residual", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("restarts", ctypes.c_int32),
+                ("final_flag", ctypes.c_int32)]
 
 
 class StepStats(ctypes.Structure):

@@ -13,27 +13,35 @@ namespace rbf {
 // NW weight arrays share one index array (e.g. D_x and D_y of one stencil
 // set); the gather functor g(j, v) fills Gather::NV values taken at column j
 // (several vectors on one matrix).  FP64 weights and accumulation.
-template <int KT, int NW, class Gather>
+//
+// CH (a divisor of KT) bounds register use when the gather returns several
+// values: slots are processed CH at a time instead of all KT at once.
+template <int KT, int NW, class Gather, int CH = KT>
 __device__ __forceinline__ void ell_row(const int *__restrict__ idx, const double *const (&w)[NW],
                                         int64_t rows, int64_t r, int k, Gather g,
                                         double (&acc)[NW][Gather::NV]) {
     if constexpr (KT > 0) {
-        int jj[KT];
-        double ww[NW][KT];
+        static_assert(KT % CH == 0, "chunk must divide the stencil width");
+#pragma unroll 1
+        for (int s0 = 0; s0 < KT; s0 += CH) {
+            int jj[CH];
+            double ww[NW][CH];
 #pragma unroll
-        for (int s = 0; s < KT; ++s) jj[s] = ld_stream(idx + (int64_t)s * rows + r);
+            for (int s = 0; s < CH; ++s) jj[s] = ld_stream(idx + (int64_t)(s0 + s) * rows + r);
 #pragma unroll
-        for (int s = 0; s < KT; ++s)
+            for (int s = 0; s < CH; ++s)
 #pragma unroll
-            for (int o = 0; o < NW; ++o) ww[o][s] = ld_stream(w[o] + (int64_t)s * rows + r);
+                for (int o = 0; o < NW; ++o)
+                    ww[o][s] = ld_stream(w[o] + (int64_t)(s0 + s) * rows + r);
 #pragma unroll
-        for (int s = 0; s < KT; ++s) {
-            double v[Gather::NV];
-            g(jj[s], v);
+            for (int s = 0; s < CH; ++s) {
+                double v[Gather::NV];
+                g(jj[s], v);
 #pragma unroll
-            for (int o = 0; o < NW; ++o)
+                for (int o = 0; o < NW; ++o)
 #pragma unroll
-                for (int c = 0; c < Gather::NV; ++c) acc[o][c] = fma(ww[o][s], v[c], acc[o][c]);
+                    for (int c = 0; c < Gather::NV; ++c) acc[o][c] = fma(ww[o][s], v[c], acc[o][c]);
+            }
         }
     } else {
 #pragma unroll 4

@@ -7,13 +7,8 @@
 //            velocity correction (eq. (20))            matrix, k_pressure, k_correct
 //
 // The paper factors its implicit matrices once by LU.  Here both systems are
-// solved by Jacobi-preconditioned BiCGSTAB (van der Vorst 1992) built from
-// ELL SpMV kernels and fused vector kernels.  Every scalar of the iteration
-// (rho, alpha, omega, residual norm) is reduced on the device: producers
-// write one partial sum per block, and each block of the consumer kernel
-// re-reduces the partials in a fixed order (deterministic, no host round
-// trip).  Convergence is a device flag; the host reads it back only every
-// few iterations, and kernels launched after convergence exit immediately.
+// solved by BiCGSTAB (van der Vorst 1992) with two fused ELL SpMV kernels per
+// iteration (see the Krylov section below).
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
@@ -76,133 +71,83 @@ __device__ __forceinline__ void load_partials(const double *part, int nb, double
 }
 
 // ------------------------------------------------------ Krylov state --
-// Per right-hand side c and iteration it: rec[(it * NR + c) * 4 + {0,1,2,3}]
-// = rho, alpha, omega, ||r||^2.  flag[c]: 0 running, 1 converged, -1 failed
-// (non-finite), 2 breakdown (the host restarts from the current iterate).
+// BiCGSTAB (van der Vorst 1992), right-preconditioned with D^-1 (Jacobi for
+// H, identity for the row-scaled Poisson matrix), restructured into two
+// SpMV kernels per iteration:
+//   k_kry_a(i): at every row, finish the update of iteration i-1
+//                 s = r - alpha v,  r' = s - omega t,  x += alpha D^-1 p + omega D^-1 s,
+//               start iteration i
+//                 p' = r' + beta (p - omega v),  v' = A D^-1 p'
+//               where the gathered D^-1 p'_j of the SpMV is recomputed at each
+//               neighbour from r, v, t, p (no separate vector pass).
+//   k_kry_b(i): alpha = rho / (rh, v'),  t = A D^-1 (r' - alpha v').
+// The scalars use (rh, s) = 0, so rho_{i+1} = (rh, r') = -omega (rh, t).
+// r, p, v are double-buffered (the kernel that rewrites them also gathers
+// the old values at neighbouring rows).  Every scalar is reduced on the
+// device from block partial sums written by the producer and re-reduced, in
+// a fixed order, by each block of the consumer: deterministic, no host
+// round trip.  Convergence (||r'|| <= tol ||b||, tested in k_kry_b) and
+// breakdown are device flags that the host reads every few iterations;
+// kernels launched after they are set exit at once.
+//
+// rec[(i * NR + c) * 4 + {0,1,2,3}] = rho_i, alpha_i, omega_i, ||r_i||^2.
+// flag[c]: 0 running, 1 converged, -1 non-finite, 2 breakdown (the host
+// restarts from the current iterate with rh = r).
+// The iteration vectors are interleaved per node, q[j] = {r_0..r_{NR-1},
+// v_0.., t_0.., p_0..} (4 NR doubles), so the on-the-fly gathers of the two
+// SpMV kernels read one contiguous 16-byte-aligned record per neighbour.
 struct KDev {
-    double *r, *rh, *p, *v, *ph, *sh, *t;  // [NR][n] each
-    double *partE, *partB, *partD;           // partial sums
-    double *rec, *bb, *rhrh;                 // rhrh: ||rh||^2 of the current cycle
+    double *q[2];                // [n][4 NR], ping-pong by iteration parity
+    double *rh;                  // [NR][n]
+    double *partA[2];            // 5 quantities x NR x blocks (k_kry_a / init)
+    double *partB;               // 4 quantities x NR x blocks (k_kry_b)
+    double *partX;               // NR x blocks (sum of x for the rank-one term)
+    double *rec, *bb, *rhrh;     // per-iteration scalars, ||b||^2, ||rh||^2
     int *flag, *iters;
 };
 
 // Breakdown threshold for |rho| = |(rh, r)| relative to ||rh|| ||r||.
 constexpr double kBreakdown = 1e-13;
 
+// A = ELL(idx, w) + u1 (vscale 1^T): the optional rank-one term carries the
+// zero-mean border of the pressure-Poisson system (u1 == nullptr: none).
 struct EllM {
     const int *idx;
     const double *w;
-    const double *dinv;
+    const double *dinv;  // nullptr: no preconditioner
     int64_t n;
     int k;
+    const double *u1;
+    double vscale;
 };
+
+// Block sums of NR stacked vectors (for the rank-one term).
+template <int NR>
+__global__ void __launch_bounds__(kThreads) k_sum(int64_t n, const double *__restrict__ x,
+                                                   double *part) {
+    double acc[NR] = {};
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] += x[c * n + i];
+    }
+    store_partials<NR>(acc, part, gridDim.x);
+}
+
+// y = x - mean(x) (one right-hand side), the mean from k_sum partials.
+__global__ void __launch_bounds__(kThreads) k_sub_mean(int64_t n, const double *part, int nbprev,
+                                                        const double *x, double *y) {
+    double sm[1];
+    load_partials<1>(part, nbprev, sm);
+    const double mean = sm[0] / (double)n;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        y[i] = x[i] - mean;
+}
 
 __device__ __forceinline__ int64_t row_of(int64_t it) {
     return ((int64_t)rbf::xcd_block(blockIdx.x, gridDim.x) + it * gridDim.x) * kThreads +
            threadIdx.x;
-}
-
-// r = b - A x, rh = r, p = v = 0; partials (rh.r, r.r, b.b).
-template <int NR, int KT>
-__global__ void __launch_bounds__(kThreads) k_bicg_init(EllM A, const double *__restrict__ b,
-                                                         const double *__restrict__ x, KDev K) {
-    const int nb = gridDim.x;
-    double acc3[3 * NR];
-#pragma unroll
-    for (int i = 0; i < 3 * NR; ++i) acc3[i] = 0.0;
-    for (int64_t it = 0;; ++it) {
-        const int64_t r = row_of(it);
-        if (r - threadIdx.x >= A.n) break;
-        if (r < A.n) {
-            double acc[1][NR] = {};
-            const double *ws[1] = {A.w};
-            rbf::ell_row<KT, 1>(A.idx, ws, A.n, r, A.k, GatherN<NR>{x, A.n}, acc);
-#pragma unroll
-            for (int c = 0; c < NR; ++c) {
-                const int64_t o = c * A.n + r;
-                const double rr = b[o] - acc[0][c];
-                K.r[o] = rr;
-                K.rh[o] = rr;
-                K.p[o] = 0.0;
-                K.v[o] = 0.0;
-                acc3[0 * NR + c] += rr * rr;
-                acc3[1 * NR + c] += rr * rr;
-                acc3[2 * NR + c] += b[o] * b[o];
-            }
-        }
-    }
-    store_partials<3 * NR>(acc3, K.partE, nb);
-    if (blockIdx.x == 0 && threadIdx.x < NR) {
-        K.flag[threadIdx.x] = 0;
-        K.iters[threadIdx.x] = 0;
-    }
-}
-
-// Start of iteration `it`: reduce (rh.r, r.r[, b.b]) from the previous
-// update, test convergence, then p = r + beta (p - omega v), ph = D^-1 p.
-template <int NR>
-__global__ void __launch_bounds__(kThreads) k_bicg_p(EllM A, KDev K, int it, int it0, int nbprev,
-                                                     double tol2) {
-    double red[3 * NR];
-    load_partials<3 * NR>(K.partE, nbprev, red);
-    bool active[NR];
-    double beta[NR], om[NR];
-    bool any = false;
-#pragma unroll
-    for (int c = 0; c < NR; ++c) {
-        const double rho = red[c], rr = red[NR + c];
-        const bool first = (it == it0);
-        const double bb = first ? red[2 * NR + c] : K.bb[c];
-        const double rhrh = first ? rr : K.rhrh[c];
-        const int f = K.flag[c];
-        active[c] = (f == 0);
-        beta[c] = 0.0;
-        om[c] = 0.0;
-        if (!active[c]) continue;
-        const bool bad = !isfinite(rho) || !isfinite(rr);
-        const bool conv = !bad && (rr <= tol2 * fmax(bb, 1e-300) || rr == 0.0);
-        const bool brk = !bad && !conv && !(fabs(rho) > kBreakdown * sqrt(rr * rhrh));
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            double *rc = K.rec + ((int64_t)it * NR + c) * 4;
-            rc[0] = rho;
-            rc[3] = rr;
-            if (first) {
-                K.bb[c] = bb;
-                K.rhrh[c] = rhrh;
-            }
-            if (bad) K.flag[c] = -1;
-            else if (conv) {
-                K.flag[c] = 1;
-                K.iters[c] = it;
-            } else if (brk) {
-                K.flag[c] = 2;
-                K.iters[c] = it;
-            }
-        }
-        if (bad || conv || brk) {
-            active[c] = false;
-            continue;
-        }
-        if (!first) {
-            const double *pr = K.rec + ((int64_t)(it - 1) * NR + c) * 4;
-            beta[c] = (rho / pr[0]) * (pr[1] / pr[2]);
-            om[c] = pr[2];
-        }
-        any = true;
-    }
-    if (!any) return;
-    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < A.n;
-         i += (int64_t)gridDim.x * kThreads) {
-        const double di = A.dinv[i];
-#pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            if (!active[c]) continue;
-            const int64_t o = c * A.n + i;
-            const double pn = K.r[o] + beta[c] * (K.p[o] - om[c] * K.v[o]);
-            K.p[o] = pn;
-            K.ph[o] = di * pn;
-        }
-    }
 }
 
 __device__ __forceinline__ bool all_done(const int *flag, int nr) {
@@ -211,143 +156,262 @@ __device__ __forceinline__ bool all_done(const int *flag, int nr) {
     return true;
 }
 
-// v = A ph; partials (rh.v).
+// partA layout: quantity q in {0: (rh,v'), 1: ||r'||^2, 2: sum r', 3: sum p', 4: sum v'}
+// (init: 0: ||r0||^2 (= rho_0), 1: ||r0||^2, 2: sum r0, 3: ||b||^2, 4: 0).
+// partB layout: {0: (t,s), 1: (t,t), 2: (rh,t), 3: sum t}.
+
+// r0 = b - A x (x from the caller), rh = r0, p = v = t = 0.
 template <int NR, int KT>
-__global__ void __launch_bounds__(kThreads) k_bicg_v(EllM A, KDev K) {
-    if (all_done(K.flag, NR)) return;
+__global__ void __launch_bounds__(kThreads) k_kry_init(EllM A, const double *__restrict__ b,
+                                                        const double *__restrict__ x, KDev K,
+                                                        int par) {
     const int nb = gridDim.x;
-    double part[NR] = {};
+    double sx[NR] = {};
+    if (A.u1) load_partials<NR>(K.partX, nb, sx);
+    double acc5[5 * NR] = {};
+    double *q = K.q[par];
     for (int64_t it = 0;; ++it) {
-        const int64_t r = row_of(it);
-        if (r - threadIdx.x >= A.n) break;
-        if (r < A.n) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= A.n) break;
+        if (row < A.n) {
             double acc[1][NR] = {};
             const double *ws[1] = {A.w};
-            rbf::ell_row<KT, 1>(A.idx, ws, A.n, r, A.k, GatherN<NR>{K.ph, A.n}, acc);
+            rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherN<NR>{x, A.n}, acc);
+            const double u1 = A.u1 ? A.u1[row] * A.vscale : 0.0;
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
-                const int64_t o = c * A.n + r;
-                K.v[o] = acc[0][c];
-                part[c] += K.rh[o] * acc[0][c];
+                const int64_t o = c * A.n + row;
+                const double rr = b[o] - (acc[0][c] + u1 * sx[c]);
+                double *qr = q + row * 4 * NR;
+                qr[c] = rr;
+                qr[NR + c] = 0.0;
+                qr[2 * NR + c] = 0.0;
+                qr[3 * NR + c] = 0.0;
+                K.rh[o] = rr;
+                acc5[0 * NR + c] += rr * rr;
+                acc5[1 * NR + c] += rr * rr;
+                acc5[2 * NR + c] += rr;
+                acc5[3 * NR + c] += b[o] * b[o];
             }
         }
     }
-    store_partials<NR>(part, K.partB, nb);
+    store_partials<5 * NR>(acc5, K.partA[par], nb);
+    if (blockIdx.x == 0 && threadIdx.x < NR) {
+        K.flag[threadIdx.x] = 0;
+        K.iters[threadIdx.x] = 0;
+    }
 }
 
-// alpha = rho / (rh.v); s = r - alpha v (stored in t), sh = D^-1 s.
-template <int NR>
-__global__ void __launch_bounds__(kThreads) k_bicg_s(EllM A, KDev K, int it, int nbprev) {
+// On-the-fly D^-1 p' at a gathered column j (see k_kry_a).
+template <int NR, bool JAC>
+struct GatherP {
+    static constexpr int NV = NR;
+    const double *q, *dinv;
+    double al[NR], om[NR], be[NR];
+    __device__ __forceinline__ void operator()(int j, double (&out)[NR]) const {
+        const double dj = JAC ? dinv[j] : 1.0;
+        const double2 *qj = reinterpret_cast<const double2 *>(q + (int64_t)j * 4 * NR);
+        double e[4 * NR];
+#pragma unroll
+        for (int h = 0; h < 2 * NR; ++h) {
+            const double2 d = qj[h];
+            e[2 * h] = d.x;
+            e[2 * h + 1] = d.y;
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            const double rj = e[c], vj = e[NR + c], tj = e[2 * NR + c], pj = e[3 * NR + c];
+            const double rn = (rj - al[c] * vj) - om[c] * tj;
+            out[c] = dj * (rn + be[c] * (pj - om[c] * vj));
+        }
+    }
+};
+
+// On-the-fly D^-1 s at a gathered column j (see k_kry_b).
+template <int NR, bool JAC>
+struct GatherS {
+    static constexpr int NV = NR;
+    const double *q, *dinv;
+    double al[NR];
+    __device__ __forceinline__ void operator()(int j, double (&out)[NR]) const {
+        const double dj = JAC ? dinv[j] : 1.0;
+        const double2 *qj = reinterpret_cast<const double2 *>(q + (int64_t)j * 4 * NR);
+        double e[2 * NR];
+#pragma unroll
+        for (int h = 0; h < NR; ++h) {
+            const double2 d = qj[h];
+            e[2 * h] = d.x;
+            e[2 * h + 1] = d.y;
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c) out[c] = dj * (e[c] - al[c] * e[NR + c]);
+    }
+};
+
+// Iteration i, first half.  par = i & 1: read buffers [par], write [par^1].
+template <int NR, int KT, bool JAC>
+__global__ void __launch_bounds__(kThreads) k_kry_a(EllM A, KDev K, double *__restrict__ x,
+                                                     int i, int i0, int par) {
     if (all_done(K.flag, NR)) return;
-    double red[NR];
-    load_partials<NR>(K.partB, nbprev, red);
+    const int nb = gridDim.x;
+    const bool first = (i == i0);
+    double ra[5 * NR], rb[4 * NR];
+    load_partials<5 * NR>(K.partA[par], nb, ra);
+    if (!first) load_partials<4 * NR>(K.partB, nb, rb);
+    GatherP<NR, JAC> g;
+    g.q = K.q[par];
+    g.dinv = A.dinv;
+    double sp[NR];
     bool active[NR];
-    double alpha[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
         active[c] = K.flag[c] == 0;
-        const double rho = K.rec[((int64_t)it * NR + c) * 4];
-        alpha[c] = rho / red[c];
-        if (active[c] && !isfinite(alpha[c])) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                K.flag[c] = 2;
-                K.iters[c] = it;
+        double rho, om = 0.0, al = 0.0, be = 0.0;
+        if (first) {
+            rho = ra[0 * NR + c];
+            sp[c] = ra[2 * NR + c];  // p' = r0
+        } else {
+            const double *pr = K.rec + ((int64_t)(i - 1) * NR + c) * 4;
+            al = pr[1];
+            om = (rb[1 * NR + c] != 0.0) ? rb[0 * NR + c] / rb[1 * NR + c] : 0.0;
+            rho = -om * rb[2 * NR + c];
+            be = (rho / pr[0]) * (al / om);
+            // sum of p' from exact sums of r, p, v (this half) and t (k_kry_b)
+            const double srn = ra[2 * NR + c] - al * ra[4 * NR + c] - om * rb[3 * NR + c];
+            sp[c] = srn + be * (ra[3 * NR + c] - om * ra[4 * NR + c]);
+        }
+        g.al[c] = al;
+        g.om[c] = om;
+        g.be[c] = be;
+        if (active[c] && blockIdx.x == 0 && threadIdx.x == 0) {
+            K.rec[((int64_t)i * NR + c) * 4 + 0] = rho;
+            if (first) {
+                K.bb[c] = ra[3 * NR + c];
+                K.rhrh[c] = ra[1 * NR + c];
+            } else {
+                K.rec[((int64_t)(i - 1) * NR + c) * 4 + 2] = om;
+                if (!(om != 0.0) || !isfinite(be)) {  // stall: restart after this update
+                    K.flag[c] = 2;
+                    K.iters[c] = i;
+                }
             }
-            active[c] = false;
-        }
-        if (active[c] && blockIdx.x == 0 && threadIdx.x == 0)
-            K.rec[((int64_t)it * NR + c) * 4 + 1] = alpha[c];
-    }
-    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < A.n;
-         i += (int64_t)gridDim.x * kThreads) {
-        const double di = A.dinv[i];
-#pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            if (!active[c]) continue;
-            const int64_t o = c * A.n + i;
-            const double s = K.r[o] - alpha[c] * K.v[o];
-            K.t[o] = s;  // s lives in t until t = A sh overwrites it
-            K.sh[o] = di * s;
         }
     }
-}
-
-// t = A sh; partials (t.s, t.t); s is read from t before it is overwritten
-// (same row only).
-template <int NR, int KT>
-__global__ void __launch_bounds__(kThreads) k_bicg_t(EllM A, KDev K, double *sbuf) {
-    if (all_done(K.flag, NR)) return;
-    const int nb = gridDim.x;
-    double part[2 * NR] = {};
+    double *qout = K.q[par ^ 1];
+    double acc5[5 * NR] = {};
     for (int64_t it = 0;; ++it) {
-        const int64_t r = row_of(it);
-        if (r - threadIdx.x >= A.n) break;
-        if (r < A.n) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= A.n) break;
+        if (row < A.n) {
             double acc[1][NR] = {};
             const double *ws[1] = {A.w};
-            rbf::ell_row<KT, 1>(A.idx, ws, A.n, r, A.k, GatherN<NR>{K.sh, A.n}, acc);
+            rbf::ell_row<KT, 1, decltype(g), (KT > 0 ? 7 : KT)>(A.idx, ws, A.n, row, A.k, g, acc);
+            const double u1 = A.u1 ? A.u1[row] * A.vscale : 0.0;
+            const double di = JAC ? A.dinv[row] : 1.0;
+            const double *qi = g.q + row * 4 * NR;
+            double *qo = qout + row * 4 * NR;
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
-                const int64_t o = c * A.n + r;
-                const double s = K.t[o];
-                sbuf[o] = s;
-                K.t[o] = acc[0][c];
-                part[c] += acc[0][c] * s;
-                part[NR + c] += acc[0][c] * acc[0][c];
+                if (!active[c]) continue;
+                const int64_t o = c * A.n + row;
+                const double vo = qi[NR + c], po = qi[3 * NR + c];
+                const double s = qi[c] - g.al[c] * vo;
+                const double rn = s - g.om[c] * qi[2 * NR + c];
+                if (!first) x[o] = x[o] + g.al[c] * (di * po) + g.om[c] * (di * s);
+                const double pn = rn + g.be[c] * (po - g.om[c] * vo);
+                const double vn = acc[0][c] + u1 * sp[c];
+                qo[c] = rn;
+                qo[NR + c] = vn;
+                qo[3 * NR + c] = pn;
+                acc5[0 * NR + c] += K.rh[o] * vn;
+                acc5[1 * NR + c] += rn * rn;
+                acc5[2 * NR + c] += rn;
+                acc5[3 * NR + c] += pn;
+                acc5[4 * NR + c] += vn;
             }
         }
     }
-    store_partials<2 * NR>(part, K.partD, nb);
+    store_partials<5 * NR>(acc5, K.partA[par ^ 1], nb);
 }
 
-// omega = (t.s)/(t.t); x += alpha ph + omega sh; r = s - omega t;
-// partials (rh.r, r.r).
-template <int NR>
-__global__ void __launch_bounds__(kThreads) k_bicg_x(EllM A, KDev K, int it, int nbprev,
-                                                     double *__restrict__ x,
-                                                     const double *__restrict__ sbuf) {
+// Iteration i, second half: convergence test on ||r'||, alpha, t = A D^-1 s.
+template <int NR, int KT, bool JAC>
+__global__ void __launch_bounds__(kThreads) k_kry_b(EllM A, KDev K, int i, int par,
+                                                     double tol2) {
     if (all_done(K.flag, NR)) return;
-    double red[2 * NR];
-    load_partials<2 * NR>(K.partD, nbprev, red);
+    const int nb = gridDim.x;
+    double ra[5 * NR];
+    load_partials<5 * NR>(K.partA[par ^ 1], nb, ra);
+    GatherS<NR, JAC> g;
+    g.q = K.q[par ^ 1];
+    g.dinv = A.dinv;
+    double ss[NR];
     bool active[NR];
-    double alpha[NR], omega[NR];
+    bool any = false;
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
         active[c] = K.flag[c] == 0;
-        alpha[c] = K.rec[((int64_t)it * NR + c) * 4 + 1];
-        omega[c] = (red[NR + c] != 0.0) ? red[c] / red[NR + c] : 0.0;
-        if (active[c] && !(omega[c] != 0.0) && red[NR + c] != 0.0) {
-            // omega = 0 stalls the recurrence: take the alpha step, then restart.
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double rho = K.rec[((int64_t)i * NR + c) * 4];
+        const double rv = ra[0 * NR + c], rr = ra[1 * NR + c];
+        const double al = rho / rv;
+        g.al[c] = al;
+        ss[c] = ra[2 * NR + c] - al * ra[4 * NR + c];
+        if (!active[c]) continue;
+        const double bb = K.bb[c], rhrh = K.rhrh[c];
+        const bool bad = !isfinite(rr) || !isfinite(rho);
+        const bool conv = !bad && (rr <= tol2 * fmax(bb, 1e-300) || rr == 0.0);
+        const bool brk = !bad && !conv &&
+                         (!(fabs(rho) > kBreakdown * sqrt(rr * rhrh)) || !isfinite(al));
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            double *rc = K.rec + ((int64_t)i * NR + c) * 4;
+            rc[1] = al;
+            rc[3] = rr;
+            if (bad) K.flag[c] = -1;
+            else if (conv) {
+                K.flag[c] = 1;
+                K.iters[c] = i;
+            } else if (brk) {
                 K.flag[c] = 2;
-                K.iters[c] = it + 1;
+                K.iters[c] = i;
             }
         }
-        if (active[c] && blockIdx.x == 0 && threadIdx.x == 0)
-            K.rec[((int64_t)it * NR + c) * 4 + 2] = omega[c];
+        if (bad || conv || brk) active[c] = false;
+        else any = true;
     }
-    double part[3 * NR] = {};
-    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < A.n;
-         i += (int64_t)gridDim.x * kThreads) {
+    if (!any) return;
+    double acc4[4 * NR] = {};
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= A.n) break;
+        if (row < A.n) {
+            double acc[1][NR] = {};
+            const double *ws[1] = {A.w};
+            rbf::ell_row<KT, 1, decltype(g), (KT > 0 ? 7 : KT)>(A.idx, ws, A.n, row, A.k, g, acc);
+            const double u1 = A.u1 ? A.u1[row] * A.vscale : 0.0;
+            double *qr = K.q[par ^ 1] + row * 4 * NR;
 #pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            if (!active[c]) continue;
-            const int64_t o = c * A.n + i;
-            const double s = sbuf[o];
-            x[o] = x[o] + alpha[c] * K.ph[o] + omega[c] * K.sh[o];
-            const double rn = s - omega[c] * K.t[o];
-            K.r[o] = rn;
-            part[c] += K.rh[o] * rn;
-            part[NR + c] += rn * rn;
+            for (int c = 0; c < NR; ++c) {
+                const int64_t o = c * A.n + row;
+                const double tv = acc[0][c] + u1 * ss[c];
+                const double s = qr[c] - g.al[c] * qr[NR + c];
+                qr[2 * NR + c] = tv;
+                acc4[0 * NR + c] += tv * s;
+                acc4[1 * NR + c] += tv * tv;
+                acc4[2 * NR + c] += K.rh[o] * tv;
+                acc4[3 * NR + c] += tv;
+            }
         }
     }
-    store_partials<3 * NR>(part, K.partE, gridDim.x);
+    store_partials<4 * NR>(acc4, K.partB, nb);
 }
 
 // True residual ||b - A x||^2 per right-hand side (for the statistics).
 template <int NR, int KT>
 __global__ void __launch_bounds__(kThreads) k_resid(EllM A, const double *__restrict__ b,
-                                                     const double *__restrict__ x, double *part) {
+                                                     const double *__restrict__ x, double *part,
+                                                     const double *partX) {
+    double sx[NR] = {};
+    if (A.u1) load_partials<NR>(partX, gridDim.x, sx);
     double acc2[NR] = {};
     for (int64_t it = 0;; ++it) {
         const int64_t r = row_of(it);
@@ -356,9 +420,10 @@ __global__ void __launch_bounds__(kThreads) k_resid(EllM A, const double *__rest
             double acc[1][NR] = {};
             const double *ws[1] = {A.w};
             rbf::ell_row<KT, 1>(A.idx, ws, A.n, r, A.k, GatherN<NR>{x, A.n}, acc);
+            const double u1 = A.u1 ? A.u1[r] * A.vscale : 0.0;
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
-                const double e = b[c * A.n + r] - acc[0][c];
+                const double e = b[c * A.n + r] - (acc[0][c] + u1 * sx[c]);
                 acc2[c] += e * e;
             }
         }
@@ -447,14 +512,14 @@ __global__ void __launch_bounds__(kThreads) k_wall_rhs(int64_t nwall, const int 
 
 // Stage 3a: F = D_x^PV u** + D_y^PV v**; Poisson right-hand side F/dt on
 // interior rows (times the row scaling of the stored Poisson matrix), 0 on
-// wall and pin rows.
+// wall rows.
 template <int KT>
 __global__ void __launch_bounds__(kThreads) k_divergence(int64_t m, int k, const int *__restrict__ idx,
                                                           const double *__restrict__ wdx,
                                                           const double *__restrict__ wdy,
                                                           const double *__restrict__ uss,
                                                           const double *__restrict__ vss,
-                                                          const int8_t *__restrict__ ptag, int64_t pin,
+                                                          const int8_t *__restrict__ ptag,
                                                           double inv_dt,
                                                           const double *__restrict__ rowscale,
                                                           double *__restrict__ rhs) {
@@ -464,7 +529,7 @@ __global__ void __launch_bounds__(kThreads) k_divergence(int64_t m, int k, const
     const double *ws[2] = {wdx, wdy};
     rbf::ell_row<KT, 2>(idx, ws, m, r, k, Gather2{uss, vss}, acc);
     const double F = acc[0][0] + acc[1][1];
-    rhs[r] = (ptag[r] == 0 && r != pin) ? rowscale[r] * (F * inv_dt) : 0.0;
+    rhs[r] = (ptag[r] == 0) ? rowscale[r] * (F * inv_dt) : 0.0;
 }
 
 // Stage 3c (pressure): p = p~ - a D_Lap^PP p~.
@@ -524,19 +589,20 @@ __global__ void k_build_helmholtz(int64_t n, int k, const int *__restrict__ idx,
     dinv[r] = (diag != 0.0) ? 1.0 / diag : 1.0;
 }
 
-// Poisson rows: D_Lap^PP (interior), n_x D_x^PP + n_y D_y^PP (wall),
-// identity (pin), stored row-scaled: interior rows by -1/||row||_2, wall
-// rows by +1/||row||_2 (so the scaled operator is -Lap with outward-normal
-// Neumann rows, whose spectrum lies in the right half-plane), pin row by 1.
-// RBF-FD self-weights do not have a fixed sign on scattered nodes, so Jacobi
-// scaling would make the spectrum indefinite; BiCGSTAB on the row-scaled
-// matrix runs unpreconditioned (dinv = 1).  rowscale[r] scales the RHS.
+// Poisson rows: D_Lap^PP (interior), n_x D_x^PP + n_y D_y^PP (wall), stored
+// row-scaled: interior rows by -1/||row||_2, wall rows by +1/||row||_2, so
+// the scaled operator is -Lap with outward-normal Neumann rows, whose
+// spectrum lies in the right half-plane.  RBF-FD self-weights do not have a
+// fixed sign on scattered nodes, so Jacobi scaling would make the spectrum
+// indefinite; BiCGSTAB on the row-scaled matrix runs unpreconditioned
+// (dinv = 1).  rowscale[r] scales the right-hand side; u1 = rowscale on
+// interior rows (0 on wall rows) is the uniform-source column of the border.
 __global__ void k_build_poisson(int64_t m, int k, const int *__restrict__ idx,
                                 const double *__restrict__ lap, const double *__restrict__ dx,
                                 const double *__restrict__ dy, const int8_t *__restrict__ tag,
-                                const double *__restrict__ nrm, int64_t pin,
-                                double *__restrict__ pw, double *__restrict__ dinv,
-                                double *__restrict__ rowscale, int *__restrict__ err) {
+                                const double *__restrict__ nrm, double *__restrict__ pw,
+                                double *__restrict__ dinv, double *__restrict__ rowscale,
+                                double *__restrict__ u1, int *__restrict__ err) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= m) return;
     const bool wall = tag[r] != 0;
@@ -545,19 +611,16 @@ __global__ void k_build_poisson(int64_t m, int k, const int *__restrict__ idx,
     double ss = 0.0;
     for (int s = 0; s < k; ++s) {
         const int64_t o = (int64_t)s * m + r;
-        const bool me = idx[o] == r;
-        double wv;
-        if (r == pin) wv = me ? 1.0 : 0.0;
-        else if (wall) wv = nx * dx[o] + ny * dy[o];
-        else wv = lap[o];
-        if (me) self = true;
+        if (idx[o] == r) self = true;
+        const double wv = wall ? nx * dx[o] + ny * dy[o] : lap[o];
         ss += wv * wv;
         pw[o] = wv;
     }
     if (!self || !(ss > 0.0)) atomicOr(err, 2);
-    const double sc = (r == pin) ? 1.0 : (wall ? 1.0 : -1.0) / sqrt(ss);
+    const double sc = (wall ? 1.0 : -1.0) / sqrt(ss);
     for (int s = 0; s < k; ++s) pw[(int64_t)s * m + r] *= sc;
     rowscale[r] = sc;
+    u1[r] = wall ? 0.0 : sc;
     dinv[r] = 1.0;
 }
 
@@ -566,40 +629,6 @@ __global__ void k_scale(int64_t n, const double *__restrict__ sc, const double *
                         double *__restrict__ b) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r < n) b[r] = sc[r] * a[r];
-}
-
-// Pin: the interior P-node nearest (0.5, 0.5), lowest index on ties.
-__global__ void k_pin_partial(int64_t m, const double *__restrict__ xp,
-                              const int8_t *__restrict__ tag, double *__restrict__ bd,
-                              long long *__restrict__ bi) {
-    __shared__ double sd[kThreads];
-    __shared__ long long si[kThreads];
-    double best = INFINITY;
-    long long bidx = -1;
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < m;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        if (tag[r] != 0) continue;
-        const double dx = xp[r] - 0.5, dy = xp[m + r] - 0.5;
-        const double d2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
-        if (d2 < best || (d2 == best && r < bidx)) {
-            best = d2;
-            bidx = r;
-        }
-    }
-    sd[threadIdx.x] = best;
-    si[threadIdx.x] = bidx;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int t = 1; t < (int)blockDim.x; ++t) {
-            if (si[t] < 0) continue;
-            if (bidx < 0 || sd[t] < best || (sd[t] == best && si[t] < bidx)) {
-                best = sd[t];
-                bidx = si[t];
-            }
-        }
-        bd[blockIdx.x] = best;
-        bi[blockIdx.x] = bidx;
-    }
 }
 
 __global__ void k_wall_list(int64_t n, const int8_t *__restrict__ tag, int *__restrict__ list,
@@ -618,14 +647,14 @@ struct rbf_solver {
     int k = 0;
     double re = 0, dt = 0, a = 0, rtol_h = 0, rtol_p = 0;
     int maxit_h = 0, maxit_p = 0;
-    int64_t pin = -1;
     int64_t nwall = 0;
     // operators
     int *idx_vv = nullptr, *idx_pv = nullptr, *idx_pp = nullptr, *idx_vp = nullptr;
     double *vv_dx = nullptr, *vv_dy = nullptr, *vv_lap = nullptr, *pv_dx = nullptr,
            *pv_dy = nullptr, *pp_lap = nullptr, *vp_dx = nullptr, *vp_dy = nullptr;
     double *h_w = nullptr, *h_dinv = nullptr, *p_w = nullptr, *p_dinv = nullptr,
-           *p_rowscale = nullptr, *p_rhs_tmp = nullptr;
+           *p_rowscale = nullptr, *p_rhs_tmp = nullptr, *p_u1 = nullptr, *p_warm = nullptr;
+    double p_vscale = 0.0;
     int8_t *p_tag = nullptr;
     int *wall_rows = nullptr;
     double *u_bc = nullptr, *v_bc = nullptr;
@@ -636,7 +665,7 @@ struct rbf_solver {
     double *us = nullptr, *vs = nullptr, *hrhs = nullptr, *uvss = nullptr, *prhs = nullptr;
     // Krylov workspaces: Helmholtz (2 RHS over N), Poisson (1 RHS over M)
     KDev kh{}, kp{};
-    double *sbuf_h = nullptr, *sbuf_p = nullptr, *rpart = nullptr;
+    double *rpart = nullptr;
     int last_iters_h = 0, last_iters_p = 0;
     // optional sampling of the Poisson SpMV (k_bicg_v) duration with HIP events
     int prof_every = 0;
@@ -673,16 +702,13 @@ int nblocks_rows(int64_t n) {
 
 rbf_status alloc_krylov(rbf_solver *S, KDev &K, int nr, int64_t n, int maxit) {
     const int64_t len = (int64_t)nr * n;
-    ALLOC(K.r, len);
+    for (int q = 0; q < 2; ++q) {
+        ALLOC(K.q[q], 4 * len);
+        ALLOC(K.partA[q], 5 * nr * kMaxBlocks);
+    }
     ALLOC(K.rh, len);
-    ALLOC(K.p, len);
-    ALLOC(K.v, len);
-    ALLOC(K.ph, len);
-    ALLOC(K.sh, len);
-    ALLOC(K.t, len);
-    ALLOC(K.partE, 3 * nr * kMaxBlocks);
-    ALLOC(K.partB, nr * kMaxBlocks);
-    ALLOC(K.partD, 2 * nr * kMaxBlocks);
+    ALLOC(K.partB, 4 * nr * kMaxBlocks);
+    ALLOC(K.partX, nr * kMaxBlocks);
     ALLOC(K.rec, (int64_t)(maxit + 2) * nr * 4);
     ALLOC(K.bb, nr);
     ALLOC(K.rhrh, nr);
@@ -691,31 +717,43 @@ rbf_status alloc_krylov(rbf_solver *S, KDev &K, int nr, int64_t n, int maxit) {
     return RBF_OK;
 }
 
-// Jacobi-BiCGSTAB on A x = b for NR stacked right-hand sides.
-template <int NR>
-rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, double *sbuf,
-                    double tol, int maxit, int &last_iters, rbf_solve_stats *stats) {
+// BiCGSTAB on A x = b for NR stacked right-hand sides (x: initial guess in,
+// solution out).  JAC: Jacobi preconditioning with A.dinv.
+template <int NR, bool JAC>
+rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, double tol,
+                    int maxit, int &last_iters, rbf_solve_stats *stats) {
     hipStream_t st = S->st;
     const int nb = nblocks_rows(A.n);
     const double tol2 = tol * tol;
     const bool k28 = A.k == 28;
-#define L28(kern, ...)                                                                    \
-    do {                                                                                  \
-        if (k28) hipLaunchKernelGGL((kern<NR, 28>), dim3(nb), dim3(kThreads), 0, st, __VA_ARGS__); \
-        else hipLaunchKernelGGL((kern<NR, 0>), dim3(nb), dim3(kThreads), 0, st, __VA_ARGS__);      \
+    const dim3 grid(nb), block(kThreads);
+#define KRY(kern, ...)                                                                         \
+    do {                                                                                       \
+        if (k28) hipLaunchKernelGGL((kern<NR, 28, JAC>), grid, block, 0, st, __VA_ARGS__);     \
+        else hipLaunchKernelGGL((kern<NR, 0, JAC>), grid, block, 0, st, __VA_ARGS__);          \
     } while (0)
-    L28(k_bicg_init, A, b, x, K);
-    int it = 0, it0 = 0, restarts = 0;
+#define KRY2(kern, ...)                                                                        \
+    do {                                                                                       \
+        if (k28) hipLaunchKernelGGL((kern<NR, 28>), grid, block, 0, st, __VA_ARGS__);          \
+        else hipLaunchKernelGGL((kern<NR, 0>), grid, block, 0, st, __VA_ARGS__);               \
+    } while (0)
+    auto init = [&](int i) {
+        if (A.u1) hipLaunchKernelGGL((k_sum<NR>), grid, block, 0, st, A.n, x, K.partX);
+        KRY2(k_kry_init, A, b, x, K, i & 1);
+    };
+    init(0);
+    int it = 0, i0 = 0, restarts = 0;
     rbf_status rc = RBF_OK;
     int batch = std::max(4, last_iters > 0 ? last_iters - 1 : 8);
     bool done = false;
     while (!done) {
-        const int stop = std::min(maxit, it + batch);
+        const int stop = std::min(maxit + 1, it + batch);
         for (; it < stop; ++it) {
-            hipLaunchKernelGGL((k_bicg_p<NR>), dim3(nb), dim3(kThreads), 0, st, A, K, it, it0, nb, tol2);
-            const bool sample = NR == 1 && S->prof_every > 0 && (S->prof_launches++ % S->prof_every) == 0;
+            const int par = it & 1;
+            const bool sample =
+                NR == 1 && S->prof_every > 0 && (S->prof_launches++ % S->prof_every) == 0;
             if (sample) RBF_HIP(hipEventRecord(S->ev0, st));
-            L28(k_bicg_v, A, K);
+            KRY(k_kry_a, A, K, x, it, i0, par);
             if (sample) {
                 RBF_HIP(hipEventRecord(S->ev1, st));
                 RBF_HIP(hipEventSynchronize(S->ev1));
@@ -724,42 +762,44 @@ rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, 
                 S->prof_ms += ms;
                 ++S->prof_count;
             }
-            hipLaunchKernelGGL((k_bicg_s<NR>), dim3(nb), dim3(kThreads), 0, st, A, K, it, nb);
-            L28(k_bicg_t, A, K, sbuf);
-            hipLaunchKernelGGL((k_bicg_x<NR>), dim3(nb), dim3(kThreads), 0, st, A, K, it, nb, x, sbuf);
+            KRY(k_kry_b, A, K, it, par, tol2);
         }
-        if (it >= maxit)  // final convergence test of the last update
-            hipLaunchKernelGGL((k_bicg_p<NR>), dim3(nb), dim3(kThreads), 0, st, A, K, it, it0, nb, tol2);
         RBF_CHECK_LAUNCH();
         RBF_HIP(hipMemcpyAsync(S->hflag, K.flag, NR * sizeof(int), hipMemcpyDeviceToHost, st));
         RBF_HIP(hipMemcpyAsync(S->hflag + kMaxNR, K.iters, NR * sizeof(int), hipMemcpyDeviceToHost, st));
         RBF_HIP(hipStreamSynchronize(st));
         done = true;
         bool restart = false;
+        int brk_at = it;
         for (int c = 0; c < NR; ++c) {
             if (S->hflag[c] == 0) done = false;
-            if (S->hflag[c] == 2) restart = true;
+            if (S->hflag[c] == 2) {
+                restart = true;
+                brk_at = std::min(brk_at, S->hflag[kMaxNR + c]);
+            }
         }
-        if (restart && it < maxit && restarts < 50) {
-            // Breakdown: restart from the current iterate with rh = r.  The
-            // iteration count continues; finished right-hand sides re-enter
-            // and are found converged at once.
+        if (restart && it <= maxit && restarts < 50) {
+            // Breakdown: restart from the current iterate with rh = r.  Kernels
+            // launched after the flag was set did nothing, so the iteration
+            // count resumes where the breakdown occurred.
             ++restarts;
-            it0 = it;
-            L28(k_bicg_init, A, b, x, K);
+            it = i0 = brk_at;
+            init(it);
             done = false;
             continue;
         }
-        if (!done && it >= maxit) break;
-        batch = std::max(4, std::min(64, (it - it0) / 4));
+        if (!done && it > maxit) break;
+        batch = std::max(4, std::min(64, (it - i0) / 4));
     }
     // Final statistics: true residual.
-    L28(k_resid, A, b, x, S->rpart);
+    if (A.u1) hipLaunchKernelGGL((k_sum<NR>), grid, block, 0, st, A.n, x, K.partX);
+    KRY2(k_resid, A, b, x, S->rpart, K.partX);
     RBF_CHECK_LAUNCH();
     RBF_HIP(hipMemcpyAsync(S->hred, S->rpart, (size_t)NR * nb * sizeof(double), hipMemcpyDeviceToHost, st));
     RBF_HIP(hipMemcpyAsync(S->hred + kMaxNR * kMaxBlocks, K.bb, NR * sizeof(double), hipMemcpyDeviceToHost, st));
     RBF_HIP(hipStreamSynchronize(st));
-#undef L28
+#undef KRY
+#undef KRY2
     int maxi = 0;
     for (int c = 0; c < NR; ++c) {
         double rr = 0.0;
@@ -772,12 +812,15 @@ rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, 
             stats[c].iterations = iters;
             stats[c].converged = (f == 1);
             stats[c].rel_residual = (bb > 0.0) ? std::sqrt(rr / bb) : std::sqrt(rr);
+            stats[c].restarts = restarts;
+            stats[c].final_flag = f;
         }
         if (f == -1) {
             rbf::set_error("BiCGSTAB: non-finite value (rhs %d, iteration %d)", c, it);
             rc = RBF_E_NAN;
         } else if ((f == 0 || f == 2) && rc == RBF_OK) {
-            rbf::set_error("BiCGSTAB: no convergence in %d iterations (rhs %d)", maxit, c);
+            rbf::set_error("BiCGSTAB: no convergence (rhs %d, %d of %d iterations, %d restarts, flag %d)",
+                           c, it, maxit, restarts, f);
             rc = RBF_E_NOCONV;
         }
     }
@@ -828,6 +871,8 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     ALLOC(S->p_w, kM);
     ALLOC(S->p_dinv, M);
     ALLOC(S->p_rowscale, M);
+    ALLOC(S->p_u1, M);
+    ALLOC(S->p_warm, M);
     ALLOC(S->p_rhs_tmp, M);
     ALLOC(S->p_tag, M);
     ALLOC(S->u_bc, N);
@@ -838,8 +883,6 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     for (double **q : {&S->pt, &S->p, &S->ptn, &S->pn, &S->prhs}) ALLOC(*q, M);
     ALLOC(S->hrhs, 2 * N);
     ALLOC(S->uvss, 2 * N);
-    ALLOC(S->sbuf_h, 2 * N);
-    ALLOC(S->sbuf_p, M);
     ALLOC(S->rpart, kMaxNR * kMaxBlocks);
     rbf_status rc;
     if ((rc = alloc_krylov(S, S->kh, 2, N, S->maxit_h)) != RBF_OK) return rc;
@@ -865,39 +908,16 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
         if ((rc = copy_in(S, c.d, c.s, c.b)) != RBF_OK) return rc;
 
     hipStream_t st = S->st;
-    // Pin row.
-    const int npb = 64;
-    double *bd;
-    long long *bi;
-    ALLOC(bd, npb);
-    ALLOC(bi, npb);
-    hipLaunchKernelGGL(k_pin_partial, dim3(npb), dim3(kThreads), 0, st, M, g->xp, g->p_tag, bd, bi);
     int *err, *cnt;
     ALLOC(err, 1);
     ALLOC(cnt, 1);
     RBF_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
     RBF_HIP(hipMemsetAsync(cnt, 0, sizeof(int), st));
-    std::vector<double> hbd(npb);
-    std::vector<long long> hbi(npb);
-    RBF_HIP(hipMemcpyAsync(hbd.data(), bd, npb * db, hipMemcpyDeviceToHost, st));
-    RBF_HIP(hipMemcpyAsync(hbi.data(), bi, npb * sizeof(long long), hipMemcpyDeviceToHost, st));
-    RBF_HIP(hipStreamSynchronize(st));
-    double best = INFINITY;
-    long long pin = -1;
-    for (int b = 0; b < npb; ++b) {
-        if (hbi[b] < 0) continue;
-        if (pin < 0 || hbd[b] < best || (hbd[b] == best && hbi[b] < pin)) {
-            best = hbd[b];
-            pin = hbi[b];
-        }
-    }
-    RBF_ARG(pin >= 0, "rbf_solver_create: no interior P-node for the pressure pin");
-    S->pin = pin;
     hipLaunchKernelGGL(k_build_helmholtz, dim3(rbf::blocks_for(N, 256)), dim3(256), 0, st, N, k,
                        S->idx_vv, S->vv_lap, g->v_tag, S->a, S->h_w, S->h_dinv, err);
     hipLaunchKernelGGL(k_build_poisson, dim3(rbf::blocks_for(M, 256)), dim3(256), 0, st, M, k,
-                       S->idx_pp, S->pp_lap, o->pp_dx, o->pp_dy, g->p_tag, g->p_normal, S->pin,
-                       S->p_w, S->p_dinv, S->p_rowscale, err);
+                       S->idx_pp, S->pp_lap, o->pp_dx, o->pp_dy, g->p_tag, g->p_normal,
+                       S->p_w, S->p_dinv, S->p_rowscale, S->p_u1, err);
     hipLaunchKernelGGL(k_wall_list, dim3(rbf::blocks_for(N, 256)), dim3(256), 0, st, N, g->v_tag,
                        S->wall_rows, cnt);
     RBF_CHECK_LAUNCH();
@@ -908,6 +928,20 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     RBF_ARG(herr[0] == 0, "rbf_solver_create: a %s stencil does not contain its own node (or a zero row)",
             (herr[0] & 1) ? "(V,V)" : "(P,P)");
     S->nwall = herr[1];
+    // Scale of the zero-mean border: v = gamma / M with gamma = 1 / mean |u1|
+    // over interior rows, so the border couples at the scale of the rows.
+    std::vector<double> hu(M);
+    RBF_HIP(hipMemcpyAsync(hu.data(), S->p_u1, M * db, hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+    double su = 0.0;
+    int64_t ni = 0;
+    for (int64_t r = 0; r < M; ++r)
+        if (hu[r] != 0.0) {
+            su += std::fabs(hu[r]);
+            ++ni;
+        }
+    RBF_ARG(ni > 0, "rbf_solver_create: no interior P-node");
+    S->p_vscale = ((double)ni / su) / (double)M;
     // The wall list order from atomics is irrelevant: rows are independent.
     return RBF_OK;
 }
@@ -932,9 +966,9 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
                            S->u_bc, S->v_bc, S->dt, S->hrhs, S->uvss);
     RBF_CHECK_LAUNCH();
     rbf_solve_stats hs[2];
-    EllM H{S->idx_vv, S->h_w, S->h_dinv, N, k};
-    rbf_status rc = bicgstab<2>(S, S->kh, H, S->hrhs, S->uvss, S->sbuf_h, S->rtol_h, S->maxit_h,
-                                S->last_iters_h, hs);
+    EllM H{S->idx_vv, S->h_w, S->h_dinv, N, k, nullptr, 0.0};
+    rbf_status rc = bicgstab<2, true>(S, S->kh, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h,
+                                      S->last_iters_h, hs);
     if (stats) {
         stats->last_helmholtz_u = hs[0];
         stats->last_helmholtz_v = hs[1];
@@ -944,14 +978,19 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
     // Stage 3: divergence, Poisson (warm start from p~_j), pressure, correction.
     launch_kt(k, [&](auto KT) {
         hipLaunchKernelGGL((k_divergence<decltype(KT)::value>), gM, blk, 0, st, M, k, S->idx_pv, S->pv_dx,
-                           S->pv_dy, S->uvss, S->uvss + N, S->p_tag, S->pin, 1.0 / S->dt,
+                           S->pv_dy, S->uvss, S->uvss + N, S->p_tag, 1.0 / S->dt,
                            S->p_rowscale, S->prhs);
     });
-    RBF_HIP(hipMemcpyAsync(S->ptn, S->pt, M * sizeof(double), hipMemcpyDeviceToDevice, st));
     rbf_solve_stats ps;
-    EllM P{S->idx_pp, S->p_w, S->p_dinv, M, k};
-    rc = bicgstab<1>(S, S->kp, P, S->prhs, S->ptn, S->sbuf_p, S->rtol_p, S->maxit_p,
-                     S->last_iters_p, &ps);
+    EllM P{S->idx_pp, S->p_w, nullptr, M, k, S->p_u1, S->p_vscale};
+    rc = bicgstab<1, false>(S, S->kp, P, S->prhs, S->p_warm, S->rtol_p, S->maxit_p,
+                            S->last_iters_p, &ps);
+    if (rc == RBF_OK) {  // p~ = solution minus its mean (zero-mean border)
+        const int nbm = nblocks_rows(M);
+        hipLaunchKernelGGL((k_sum<1>), dim3(nbm), dim3(kThreads), 0, st, M, S->p_warm, S->kp.partX);
+        hipLaunchKernelGGL(k_sub_mean, dim3(nbm), dim3(kThreads), 0, st, M, S->kp.partX, nbm,
+                           S->p_warm, S->ptn);
+    }
     if (stats) {
         stats->last_poisson = ps;
         stats->poisson_iters += ps.iterations;
@@ -1025,6 +1064,7 @@ extern "C" rbf_status rbf_step(rbf_solver *S, int32_t nsteps, rbf_state *state,
     RBF_HIP(hipMemcpyAsync(S->cu, state->cu_prev, nb, hipMemcpyDeviceToDevice, st));
     RBF_HIP(hipMemcpyAsync(S->cv, state->cv_prev, nb, hipMemcpyDeviceToDevice, st));
     RBF_HIP(hipMemcpyAsync(S->pt, state->p_tilde, mb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->p_warm, state->p_tilde, mb, hipMemcpyDeviceToDevice, st));
     RBF_HIP(hipMemcpyAsync(S->p, state->p, mb, hipMemcpyDeviceToDevice, st));
     rbf_status rc = RBF_OK;
     int done = 0;
@@ -1051,12 +1091,21 @@ extern "C" rbf_status rbf_solve_pressure(rbf_solver *S, const double *rhs, doubl
                                          rbf_solve_stats *stats) {
     rbf::clear_error();
     RBF_ARG(S && rhs && p_tilde, "rbf_solve_pressure: NULL argument");
-    EllM P{S->idx_pp, S->p_w, S->p_dinv, S->M, S->k};
+    EllM P{S->idx_pp, S->p_w, nullptr, S->M, S->k, S->p_u1, S->p_vscale};
     hipLaunchKernelGGL(k_scale, dim3(rbf::blocks_for(S->M, 256)), dim3(256), 0, S->st, S->M,
                        S->p_rowscale, rhs, S->p_rhs_tmp);
     RBF_CHECK_LAUNCH();
-    rbf_status rc = bicgstab<1>(S, S->kp, P, S->p_rhs_tmp, p_tilde, S->sbuf_p, S->rtol_p,
-                                S->maxit_p, S->last_iters_p, stats);
+    rbf_status rc = bicgstab<1, false>(S, S->kp, P, S->p_rhs_tmp, p_tilde, S->rtol_p,
+                                       S->maxit_p, S->last_iters_p, stats);
+    if (rc == RBF_OK) {
+        const int nbm = nblocks_rows(S->M);
+        hipLaunchKernelGGL((k_sum<1>), dim3(nbm), dim3(kThreads), 0, S->st, S->M, p_tilde,
+                           S->kp.partX);
+        hipLaunchKernelGGL(k_sub_mean, dim3(nbm), dim3(kThreads), 0, S->st, S->M, S->kp.partX,
+                           nbm, p_tilde, p_tilde);
+        RBF_CHECK_LAUNCH();
+        RBF_HIP(hipStreamSynchronize(S->st));
+    }
     return rc;
 }
 

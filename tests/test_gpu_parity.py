@@ -228,10 +228,9 @@ def test_solve_pressure_parity(P, gpu):
     orc = ocav.CavityOracle(nd, u_bc, v_bc, 100.0, 1e-3)
     rhs = ri.random_vector(nd.n_p, 3)
     rhs[nd.p_tag != 0] = 0.0
-    rhs[orc.pin] = 0.0
     x = to_dev(np.zeros(nd.n_p), gpu)
     stats = S.solve_pressure(to_dev(rhs, gpu), x)
-    ref = orc.Lp_lu.solve(rhs)
+    ref, _ = orc.solve_pressure(rhs)
     assert stats.converged and stats.rel_residual <= 1e-10
     assert rel_err(x.cpu().numpy(), ref) <= 1e-10
     S.close()
