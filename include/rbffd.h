@@ -55,7 +55,7 @@ typedef int32_t rbf_status;
 #define RBF_OP_DY 4u
 #define RBF_OP_LAP 8u
 
-#define RBF_ABI_VERSION 1
+#define RBF_ABI_VERSION 2
 
 typedef void *rbf_stream;
 
@@ -190,8 +190,23 @@ typedef struct {
     int32_t maxit_h;  /* iteration caps                                      */
     int32_t maxit_p;
     int32_t precision;/* 0 = FP64 (only value accepted)                      */
-    int32_t reserved;
+    int32_t precond;  /* pressure-solve preconditioner, RBF_PRECOND_*        */
 } rbf_params;
+
+/* rbf_params.precond:
+ * AUTO     the lattice preconditioner when the P-nodes form a jittered
+ *          (K+1)^2 lattice of the unit square (the cavity layout of
+ *          rbf_build_nodes), none otherwise;
+ * NONE     unpreconditioned BiCGSTAB on the row-scaled system;
+ * LATTICE  the lattice preconditioner, RBF_E_ARG if the P-nodes are not
+ *          such a lattice.
+ * The lattice preconditioner is the 5-point Laplacian of the unjittered
+ * lattice with one-sided Neumann rows, inverted exactly by a fast
+ * (DCT-II) Poisson solve, followed by bilinear interpolation to the node
+ * positions.  It changes only the iteration, not the system solved. */
+#define RBF_PRECOND_AUTO 0
+#define RBF_PRECOND_NONE 1
+#define RBF_PRECOND_LATTICE 2
 
 /* Solver state at step j, device memory owned by the caller. */
 typedef struct {
@@ -233,13 +248,14 @@ typedef struct rbf_solver rbf_solver;
  * incompatibility and p~ has zero mean.  It is solved as
  * (A0 + u1 v^T) x = b with the rank-one border, then p~ = x - mean(x); the
  * operator is stored row-scaled (interior rows by -1/||row||_2, wall rows by
- * +1/||row||_2) and iterated by unpreconditioned BiCGSTAB, so the Poisson
- * tolerance applies to the row-scaled system.
+ * +1/||row||_2) and iterated by BiCGSTAB, right-preconditioned as chosen by
+ * prm->precond; the Poisson tolerance applies to the row-scaled system.
  * u_bc, v_bc: device [n_v] boundary velocities (read on wall rows; copied).
  * The solver keeps `st` for all of its work.
  * Errors: RBF_E_ARG (NULL pointers, sizes, dt/re <= 0, precision != 0,
- * a self index missing from a (V,V) or (P,P) stencil, no interior P node),
- * RBF_E_NOMEM.
+ * unknown precond, RBF_PRECOND_LATTICE on a non-lattice P-grid, a self
+ * index missing from a (V,V) or (P,P) stencil, no interior P node),
+ * RBF_E_NOMEM, RBF_E_DEVICE (including a failed rocBLAS call).
  */
 rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, const rbf_ops *ops,
                              const double *u_bc, const double *v_bc, const rbf_params *prm,

@@ -52,7 +52,7 @@ class Params(ctypes.Structure):
     _fields_ = [("re", ctypes.c_double), ("dt", ctypes.c_double),
                 ("rtol_h", ctypes.c_double), ("rtol_p", ctypes.c_double),
                 ("maxit_h", ctypes.c_int32), ("maxit_p", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):

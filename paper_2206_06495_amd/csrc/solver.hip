@@ -15,6 +15,8 @@
 #include <utility>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "common.h"
 #include "ell.h"
 
@@ -431,6 +433,320 @@ __global__ void __launch_bounds__(kThreads) k_resid(EllM A, const double *__rest
     store_partials<NR>(acc2, part, gridDim.x);
 }
 
+// ------------------------------------------ lattice preconditioner --
+// Right preconditioner of the pressure system when the P-nodes are a
+// jittered (K+1) x (K+1) lattice (vertex (i, j) near (i h, j h), h = 1/K,
+// row-major, boundary vertices on the walls):
+//   P^-1 = J (L5 + chi c 1^T)^-1 D^-1
+// D: the row scale of the stored Poisson rows; L5: the 5-point Laplacian of
+// the unjittered lattice with one-sided Neumann rows (z_w - z_in) / |w - in|
+// to the inward lattice neighbour (the diagonal one at corners); chi c 1^T:
+// the same zero-mean border as the operator; J: bilinear interpolation from
+// the lattice points to the actual node positions.  L5 is inverted exactly:
+// the wall rows give z_w = z_in + |w - in| g_w, which leaves on the (K-1)^2
+// interior nodes the separable operator (T (x) I + I (x) T) / h^2, T the
+// 1-D second difference with Neumann ends, diagonalised by the DCT-II basis
+// Q (T = Q Lam Q^-1).  The two-dimensional transforms Q^-1 X Q^-T and
+// Q Z Q^T are dense (K-1) x (K-1) products (rocBLAS DGEMM on the matrix
+// cores); the border fixes the zero mode and the sum of z.
+//
+// Interior work array X (column-major, ld n = K-1): X(a, b) belongs to
+// lattice node (i, j) = (a + 1, b + 1).
+struct Lat {
+    int K, n;
+    double h, c;           // spacing; border scale
+    const double *rs;      // [M] row scale of the stored Poisson rows
+    const int *cell;       // [M] lower-left lattice node of the cell holding the node
+    const double *fx, *fy; // [M] bilinear coordinates in that cell
+    const double *lam;     // [n] eigenvalues of T (unit spacing)
+    double *X;             // [n * n]
+    double *mean;          // [1] zero-mode coefficient (mean of the reduced rhs)
+};
+
+// Preconditioned BiCGSTAB vectors and scalars (one right-hand side).
+// p is double-buffered by iteration parity (the kernel that rewrites it also
+// recomputes the new value at wall neighbours from the old one).
+struct PKry {
+    double *r, *rh, *p[2], *v, *s, *t, *ph, *sh;
+    double *partI;  // init: {rho_0, ||b||^2}
+    double *part1;  // k_pc_dir: ||r||^2
+    double *part3;  // k_pc_av (v): (rh, v)
+    double *part6;  // k_pc_av (t): (t, s), (t, t), (rh, t)
+    double *partS;  // k_pc_post: sum of the preconditioned vector
+    double *rec;    // per iteration {rho, alpha, omega, ||r||^2}
+    double *bb, *rhrh;
+    int *flag, *iters;
+};
+
+// Reduced right-hand side at interior lattice node `row` = (i, j), from the
+// values val(node) of the vector being preconditioned: D^-1 y with the wall
+// values moved to the right-hand side.
+template <class V>
+__device__ __forceinline__ void pc_reduce(const Lat &L, int64_t row, V val) {
+    const int K = L.K, K1 = K + 1;
+    const int i = (int)(row % K1), j = (int)(row / K1);
+    if (i < 1 || i > K - 1 || j < 1 || j > K - 1) return;
+    double g = val(row) / L.rs[row];
+    double wsum = 0.0;
+    if (i == 1) wsum += val(row - 1) / L.rs[row - 1];
+    if (i == K - 1) wsum += val(row + 1) / L.rs[row + 1];
+    if (j == 1) wsum += val(row - K1) / L.rs[row - K1];
+    if (j == K - 1) wsum += val(row + K1) / L.rs[row + K1];
+    g -= wsum / L.h;
+    L.X[(int64_t)(i - 1) + (int64_t)(j - 1) * L.n] = g;
+}
+
+// r0 = b - A x, rh = r0.
+template <int KT>
+__global__ void __launch_bounds__(kThreads) k_pc_init(EllM A, const double *__restrict__ b,
+                                                       const double *__restrict__ x, PKry K,
+                                                       const double *partX) {
+    const int nb = gridDim.x;
+    double sx[1] = {0.0};
+    if (A.u1) load_partials<1>(partX, nb, sx);
+    double acc[2] = {};
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= A.n) break;
+        if (row < A.n) {
+            double ax[1][1] = {};
+            const double *ws[1] = {A.w};
+            rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherN<1>{x, A.n}, ax);
+            const double u1 = A.u1 ? A.u1[row] * A.vscale : 0.0;
+            const double rr = b[row] - (ax[0][0] + u1 * sx[0]);
+            K.r[row] = rr;
+            K.rh[row] = rr;
+            acc[0] += rr * rr;
+            acc[1] += b[row] * b[row];
+        }
+    }
+    store_partials<2>(acc, K.partI, nb);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        K.flag[0] = 0;
+        K.iters[0] = 0;
+    }
+}
+
+// Iteration i, step 1: finish iteration i-1 (r = s - omega t,
+// x += alpha ph + omega sh), new direction p = r + beta (p - omega v), and
+// the reduced right-hand side of p for the preconditioner.  Breakdowns are
+// detected by k_pc_s from the recorded scalars, so that every block of this
+// kernel performs the same update.
+__global__ void __launch_bounds__(kThreads) k_pc_dir(PKry K, Lat L, double *__restrict__ x,
+                                                      int64_t m, int i, int i0) {
+    if (K.flag[0] != 0) return;
+    const int nb = gridDim.x;
+    const bool first = (i == i0);
+    const int par = i & 1;
+    double al = 0.0, om = 0.0, be = 0.0, rho;
+    if (first) {
+        double q[2];
+        load_partials<2>(K.partI, nb, q);
+        rho = q[0];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            K.bb[0] = q[1];
+            K.rhrh[0] = q[0];
+            K.rec[(int64_t)i * 4 + 0] = rho;
+        }
+    } else {
+        double q[3];
+        load_partials<3>(K.part6, nb, q);
+        const double *pr = K.rec + (int64_t)(i - 1) * 4;
+        al = pr[1];
+        om = (q[1] != 0.0) ? q[0] / q[1] : 0.0;
+        rho = -om * q[2];  // (rh, s) = 0 by the choice of alpha
+        be = (rho / pr[0]) * (al / om);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            K.rec[(int64_t)(i - 1) * 4 + 2] = om;
+            K.rec[(int64_t)i * 4 + 0] = rho;
+        }
+    }
+    const double *pold = K.p[par ^ 1];
+    double *pnew = K.p[par];
+    auto pval = [&](int64_t j) {
+        if (first) return K.r[j];
+        const double rn = K.s[j] - om * K.t[j];
+        return rn + be * (pold[j] - om * K.v[j]);
+    };
+    double acc[1] = {0.0};
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= m) break;
+        if (row < m) {
+            double rn, pn;
+            if (first) {
+                rn = K.r[row];
+                pn = rn;
+            } else {
+                rn = K.s[row] - om * K.t[row];
+                x[row] = x[row] + al * K.ph[row] + om * K.sh[row];
+                K.r[row] = rn;
+                pn = rn + be * (pold[row] - om * K.v[row]);
+            }
+            pnew[row] = pn;
+            acc[0] += rn * rn;
+            pc_reduce(L, row, pval);
+        }
+    }
+    store_partials<1>(acc, K.part1, nb);
+}
+
+// Iteration i, step 2: convergence test on ||r_i||, alpha = rho / (rh, v),
+// s = r - alpha v and its reduced right-hand side.
+__global__ void __launch_bounds__(kThreads) k_pc_s(PKry K, Lat L, int64_t m, int i,
+                                                    double tol2) {
+    if (K.flag[0] != 0) return;
+    const int nb = gridDim.x;
+    double q1[1], q3[1];
+    load_partials<1>(K.part1, nb, q1);
+    load_partials<1>(K.part3, nb, q3);
+    const double rr = q1[0], rv = q3[0];
+    const double rho = K.rec[(int64_t)i * 4];
+    const double al = rho / rv;
+    const double bb = K.bb[0], rhrh = K.rhrh[0];
+    const bool bad = !isfinite(rr) || !isfinite(rho);
+    const bool conv = !bad && (rr <= tol2 * fmax(bb, 1e-300) || rr == 0.0);
+    const bool brk = !bad && !conv && (!(fabs(rho) > kBreakdown * sqrt(rr * rhrh)) || !isfinite(al));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double *rc = K.rec + (int64_t)i * 4;
+        rc[1] = al;
+        rc[3] = rr;
+        if (bad) K.flag[0] = -1;
+        else if (conv || brk) {
+            K.flag[0] = conv ? 1 : 2;
+            K.iters[0] = i;
+        }
+    }
+    if (bad || conv || brk) return;
+    auto sval = [&](int64_t j) { return K.r[j] - al * K.v[j]; };
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= m) break;
+        if (row < m) {
+            K.s[row] = sval(row);
+            pc_reduce(L, row, sval);
+        }
+    }
+}
+
+// Zero mode: remember the mean of the reduced right-hand side, then divide
+// by the eigenvalues of the interior operator (the zero mode is set to 0).
+__global__ void __launch_bounds__(kThreads) k_pc_scale(Lat L) {
+    const int64_t nn = (int64_t)L.n * L.n;
+    const double h2 = L.h * L.h;
+    for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < nn;
+         e += (int64_t)gridDim.x * kThreads) {
+        const int k = (int)(e % L.n), l = (int)(e / L.n);
+        if (e == 0) {
+            *L.mean = L.X[0];
+            L.X[0] = 0.0;
+        } else {
+            L.X[e] *= h2 / (L.lam[k] + L.lam[l]);
+        }
+    }
+}
+
+// Lattice value of L5^-1 at node (i, j), before the constant shift.
+__device__ __forceinline__ double pc_lattice(const Lat &L, const double *y, int i, int j) {
+    const int K = L.K;
+    const int ci = min(max(i, 1), K - 1), cj = min(max(j, 1), K - 1);
+    double z = L.X[(int64_t)(ci - 1) + (int64_t)(cj - 1) * L.n];
+    const bool bi = (i == 0 || i == K), bj = (j == 0 || j == K);
+    if (bi || bj) {
+        const int64_t node = (int64_t)j * (K + 1) + i;
+        const double dist = (bi && bj) ? L.h * 1.4142135623730951 : L.h;
+        z += dist * (y[node] / L.rs[node]);
+    }
+    return z;
+}
+
+// out = J (zl + alpha) at every node; alpha makes the lattice sum equal to
+// the value the border prescribes (mean / c); block partials of sum(out).
+__global__ void __launch_bounds__(kThreads) k_pc_post(Lat L, PKry K, const double *__restrict__ y,
+                                                       double *__restrict__ out, int64_t m,
+                                                       double *partS) {
+    if (K.flag[0] != 0) return;
+    const int Kl = L.K;
+    // Boundary sum (each block, same order): the interior part of the
+    // lattice solution has zero sum (no zero mode).
+    double bs[1] = {0.0};
+    const int nbnd = 4 * Kl;
+    for (int b = threadIdx.x; b < nbnd; b += kThreads) {
+        int i, j;
+        if (b < Kl + 1) {
+            i = b;
+            j = 0;
+        } else if (b < 2 * (Kl + 1)) {
+            i = b - (Kl + 1);
+            j = Kl;
+        } else if (b < 2 * (Kl + 1) + (Kl - 1)) {
+            i = 0;
+            j = b - 2 * (Kl + 1) + 1;
+        } else {
+            i = Kl;
+            j = b - 2 * (Kl + 1) - (Kl - 1) + 1;
+        }
+        bs[0] += pc_lattice(L, y, i, j);
+    }
+    {
+        __shared__ double lds[kThreads / 64];
+        rbf::block_sum<1>(bs, lds);
+    }
+    const double alpha = (*L.mean / L.c - bs[0]) / (double)m;
+    double acc[1] = {0.0};
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= m) break;
+        if (row < m) {
+            const int c = L.cell[row];
+            const int i0 = c % (Kl + 1), j0 = c / (Kl + 1);
+            const double fx = L.fx[row], fy = L.fy[row];
+            const double z00 = pc_lattice(L, y, i0, j0), z10 = pc_lattice(L, y, i0 + 1, j0);
+            const double z01 = pc_lattice(L, y, i0, j0 + 1), z11 = pc_lattice(L, y, i0 + 1, j0 + 1);
+            const double z = ((1.0 - fy) * ((1.0 - fx) * z00 + fx * z10) +
+                              fy * ((1.0 - fx) * z01 + fx * z11)) + alpha;
+            out[row] = z;
+            acc[0] += z;
+        }
+    }
+    store_partials<1>(acc, partS, gridDim.x);
+}
+
+// out = A y (+ rank-one border); MODE 0: partials (rh, out) -> part3,
+// MODE 1: partials (out, s), (out, out), (rh, out) -> part6.
+template <int KT, int MODE>
+__global__ void __launch_bounds__(kThreads) k_pc_av(EllM A, PKry K, const double *__restrict__ y,
+                                                     double *__restrict__ out) {
+    if (K.flag[0] != 0) return;
+    const int nb = gridDim.x;
+    double sy[1] = {0.0};
+    if (A.u1) load_partials<1>(K.partS, nb, sy);
+    constexpr int NQ = MODE == 0 ? 1 : 3;
+    double acc[NQ] = {};
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= A.n) break;
+        if (row < A.n) {
+            double ay[1][1] = {};
+            const double *ws[1] = {A.w};
+            rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherN<1>{y, A.n}, ay);
+            const double u1 = A.u1 ? A.u1[row] * A.vscale : 0.0;
+            const double val = ay[0][0] + u1 * sy[0];
+            out[row] = val;
+            const double rh = K.rh[row];
+            if constexpr (MODE == 0) {
+                acc[0] += rh * val;
+            } else {
+                const double sv = K.s[row];
+                acc[0] += val * sv;
+                acc[1] += val * val;
+                acc[2] += rh * val;
+            }
+        }
+    }
+    store_partials<NQ>(acc, MODE == 0 ? K.part3 : K.part6, nb);
+}
+
 // ---------------------------------------------------------- step kernels --
 // Stage 1: C(q) = -(u o D_x q + v o D_y q), u* = u + dt (3/2 C_j - 1/2 C_{j-1}).
 template <int KT>
@@ -667,11 +983,17 @@ struct rbf_solver {
     KDev kh{}, kp{};
     double *rpart = nullptr;
     int last_iters_h = 0, last_iters_p = 0;
-    // optional sampling of the Poisson SpMV (k_bicg_v) duration with HIP events
+    // optional sampling of the Poisson SpMV duration with HIP events
     int prof_every = 0;
     int64_t prof_launches = 0, prof_count = 0;
     double prof_ms = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // lattice preconditioner of the pressure system
+    bool pc_on = false;
+    Lat lat{};
+    PKry pk{};
+    double *pc_Q = nullptr, *pc_Qi = nullptr, *pc_T = nullptr;
+    rocblas_handle blas = nullptr;
     // pinned host buffers
     int *hflag = nullptr;
     double *hred = nullptr;
@@ -828,6 +1150,272 @@ rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, 
     return rc;
 }
 
+#define RBF_BLAS(call)                                                                 \
+    do {                                                                               \
+        rocblas_status b_ = (call);                                                    \
+        if (b_ != rocblas_status_success) {                                            \
+            ::rbf::set_error("%s failed: %s", #call, rocblas_status_to_string(b_));     \
+            return RBF_E_DEVICE;                                                       \
+        }                                                                              \
+    } while (0)
+
+// One application of the lattice preconditioner's interior solve on L.X:
+// X <- Q (Lam^-1 o (Q^-1 X Q^-T)) Q^T (column-major n x n products).
+rbf_status pc_apply(rbf_solver *S) {
+    const int n = S->lat.n;
+    const double one = 1.0, zero = 0.0;
+    double *X = S->lat.X, *T = S->pc_T;
+    const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
+    RBF_BLAS(rocblas_dgemm(S->blas, N_, N_, n, n, n, &one, S->pc_Qi, n, X, n, &zero, T, n));
+    RBF_BLAS(rocblas_dgemm(S->blas, N_, T_, n, n, n, &one, T, n, S->pc_Qi, n, &zero, X, n));
+    const int64_t nn = (int64_t)n * n;
+    hipLaunchKernelGGL(k_pc_scale, dim3(std::min<int64_t>(kMaxBlocks, rbf::blocks_for(nn, kThreads))),
+                       dim3(kThreads), 0, S->st, S->lat);
+    RBF_BLAS(rocblas_dgemm(S->blas, N_, N_, n, n, n, &one, S->pc_Q, n, X, n, &zero, T, n));
+    RBF_BLAS(rocblas_dgemm(S->blas, N_, T_, n, n, n, &one, T, n, S->pc_Q, n, &zero, X, n));
+    return RBF_OK;
+}
+
+// Right-preconditioned BiCGSTAB on the pressure system (one right-hand side)
+// with the lattice preconditioner; same contract as bicgstab<1, false>.
+// Per iteration: k_pc_dir, P^-1 (4 DGEMM + k_pc_scale + k_pc_post),
+// k_pc_av (v), k_pc_s, P^-1, k_pc_av (t).
+rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double tol, int maxit,
+                     int &last_iters, rbf_solve_stats *stats) {
+    hipStream_t st = S->st;
+    PKry &K = S->pk;
+    const Lat &L = S->lat;
+    const int64_t m = A.n;
+    const int nb = nblocks_rows(m);
+    const dim3 grid(nb), block(kThreads);
+    const double tol2 = tol * tol;
+    const bool k28 = A.k == 28;
+    double *partX = S->kp.partX;
+    auto init = [&]() {
+        if (A.u1) hipLaunchKernelGGL((k_sum<1>), grid, block, 0, st, m, x, partX);
+        if (k28) hipLaunchKernelGGL((k_pc_init<28>), grid, block, 0, st, A, b, x, K, partX);
+        else hipLaunchKernelGGL((k_pc_init<0>), grid, block, 0, st, A, b, x, K, partX);
+    };
+    auto av = [&](int mode, const double *y, double *out) {
+        if (k28) {
+            if (mode == 0) hipLaunchKernelGGL((k_pc_av<28, 0>), grid, block, 0, st, A, K, y, out);
+            else hipLaunchKernelGGL((k_pc_av<28, 1>), grid, block, 0, st, A, K, y, out);
+        } else {
+            if (mode == 0) hipLaunchKernelGGL((k_pc_av<0, 0>), grid, block, 0, st, A, K, y, out);
+            else hipLaunchKernelGGL((k_pc_av<0, 1>), grid, block, 0, st, A, K, y, out);
+        }
+    };
+    init();
+    int it = 0, i0 = 0, restarts = 0;
+    rbf_status rc = RBF_OK;
+    int batch = std::max(2, last_iters > 0 ? last_iters - 1 : 8);
+    bool done = false;
+    while (!done) {
+        const int stop = std::min(maxit + 1, it + batch);
+        for (; it < stop; ++it) {
+            const int par = it & 1;
+            hipLaunchKernelGGL(k_pc_dir, grid, block, 0, st, K, L, x, m, it, i0);
+            if ((rc = pc_apply(S)) != RBF_OK) return rc;
+            hipLaunchKernelGGL(k_pc_post, grid, block, 0, st, L, K, K.p[par], K.ph, m, K.partS);
+            const bool sample = S->prof_every > 0 && (S->prof_launches++ % S->prof_every) == 0;
+            if (sample) RBF_HIP(hipEventRecord(S->ev0, st));
+            av(0, K.ph, K.v);
+            if (sample) {
+                RBF_HIP(hipEventRecord(S->ev1, st));
+                RBF_HIP(hipEventSynchronize(S->ev1));
+                float ms = 0.f;
+                RBF_HIP(hipEventElapsedTime(&ms, S->ev0, S->ev1));
+                S->prof_ms += ms;
+                ++S->prof_count;
+            }
+            hipLaunchKernelGGL(k_pc_s, grid, block, 0, st, K, L, m, it, tol2);
+            if ((rc = pc_apply(S)) != RBF_OK) return rc;
+            hipLaunchKernelGGL(k_pc_post, grid, block, 0, st, L, K, K.s, K.sh, m, K.partS);
+            av(1, K.sh, K.t);
+        }
+        RBF_CHECK_LAUNCH();
+        RBF_HIP(hipMemcpyAsync(S->hflag, K.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipMemcpyAsync(S->hflag + kMaxNR, K.iters, sizeof(int), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        const int f = S->hflag[0];
+        done = (f != 0);
+        if (f == 2 && it <= maxit && restarts < 50) {
+            // Breakdown: restart from the current iterate with rh = r.
+            ++restarts;
+            it = i0 = S->hflag[kMaxNR];
+            init();
+            done = false;
+            continue;
+        }
+        if (!done && it > maxit) break;
+        batch = std::max(2, std::min(16, (it - i0) / 4));
+    }
+    if (A.u1) hipLaunchKernelGGL((k_sum<1>), grid, block, 0, st, m, x, partX);
+    if (k28) hipLaunchKernelGGL((k_resid<1, 28>), grid, block, 0, st, A, b, x, S->rpart, partX);
+    else hipLaunchKernelGGL((k_resid<1, 0>), grid, block, 0, st, A, b, x, S->rpart, partX);
+    RBF_CHECK_LAUNCH();
+    RBF_HIP(hipMemcpyAsync(S->hred, S->rpart, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipMemcpyAsync(S->hred + kMaxNR * kMaxBlocks, K.bb, sizeof(double), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+    double rr = 0.0;
+    for (int bidx = 0; bidx < nb; ++bidx) rr += S->hred[bidx];
+    const double bb = S->hred[kMaxNR * kMaxBlocks];
+    const int f = S->hflag[0];
+    const int iters = (f == 1) ? S->hflag[kMaxNR] : it;
+    if (stats) {
+        stats->iterations = iters;
+        stats->converged = (f == 1);
+        stats->rel_residual = (bb > 0.0) ? std::sqrt(rr / bb) : std::sqrt(rr);
+        stats->restarts = restarts;
+        stats->final_flag = f;
+    }
+    if (f == -1) {
+        rbf::set_error("preconditioned BiCGSTAB: non-finite value (iteration %d)", it);
+        rc = RBF_E_NAN;
+    } else if (f == 0 || f == 2) {
+        rbf::set_error("preconditioned BiCGSTAB: no convergence (%d of %d iterations, %d restarts, flag %d)",
+                       it, maxit, restarts, f);
+        rc = RBF_E_NOCONV;
+    }
+    last_iters = iters;
+    return rc;
+}
+
+// Pressure solve on the row-scaled bordered system (x: guess in, solution out).
+rbf_status poisson_solve(rbf_solver *S, const double *b, double *x, rbf_solve_stats *stats) {
+    EllM P{S->idx_pp, S->p_w, nullptr, S->M, S->k, S->p_u1, S->p_vscale};
+    if (S->pc_on) return pbicgstab(S, P, b, x, S->rtol_p, S->maxit_p, S->last_iters_p, stats);
+    return bicgstab<1, false>(S, S->kp, P, b, x, S->rtol_p, S->maxit_p, S->last_iters_p, stats);
+}
+
+// DCT-II eigenbasis of the 1-D Neumann second difference on n points
+// (tridiag(1, -2, 1) with -1 at both ends): q_k(a) = cos(pi k (a + 1/2) / n),
+// lam_k = -4 sin^2(pi k / (2 n)).  Q(a, k) at Q[a + k n]; Q^-1(k, a) =
+// d_k Q(a, k) with d_0 = 1/n, d_k = 2/n, at Qi[k + a n].
+void dct2_basis(int n, std::vector<double> &Q, std::vector<double> &Qi, std::vector<double> &lam) {
+    Q.assign((size_t)n * n, 0.0);
+    Qi.assign((size_t)n * n, 0.0);
+    lam.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; k < n; ++k) {
+        const double sk = std::sin(pi * k / (2.0 * n));
+        lam[k] = -4.0 * sk * sk;
+        for (int a = 0; a < n; ++a) {
+            const int64_t mth = ((int64_t)k * (2 * a + 1)) % (4LL * n);  // angle pi mth / (2n)
+            const double c = std::cos(pi * (double)mth / (2.0 * n));
+            Q[(size_t)a + (size_t)k * n] = c;
+            Qi[(size_t)k + (size_t)a * n] = (k == 0 ? 1.0 / n : 2.0 / n) * c;
+        }
+    }
+}
+
+// True if the P-nodes are the jittered (K+1)^2 lattice the preconditioner
+// assumes: row-major vertices within half a spacing of (i h, j h), wall
+// nodes exactly on their walls and tagged, interior nodes untagged.
+bool is_lattice(const std::vector<double> &xp, const std::vector<int8_t> &tag, int64_t m, int &Kout) {
+    const int64_t K1 = (int64_t)std::llround(std::sqrt((double)m));
+    if (K1 * K1 != m || K1 < 5) return false;
+    const int K = (int)(K1 - 1);
+    const double h = 1.0 / K;
+    for (int64_t v = 0; v < m; ++v) {
+        const int i = (int)(v % K1), j = (int)(v / K1);
+        const double x = xp[v], y = xp[m + v];
+        const bool bnd = (i == 0 || i == K || j == 0 || j == K);
+        if (bnd != (tag[v] != 0)) return false;
+        if (!(std::fabs(x - i * h) < 0.5 * h && std::fabs(y - j * h) < 0.5 * h)) return false;
+        if ((i == 0 && x != 0.0) || (i == K && x != 1.0) || (j == 0 && y != 0.0) ||
+            (j == K && y != 1.0))
+            return false;
+    }
+    Kout = K;
+    return true;
+}
+
+// Set up the lattice preconditioner if the grid allows it (mode: RBF_PRECOND_*).
+rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
+    if (mode == RBF_PRECOND_NONE) return RBF_OK;
+    const int64_t M = S->M;
+    hipStream_t st = S->st;
+    std::vector<double> hx(2 * M);
+    std::vector<int8_t> ht(M);
+    RBF_HIP(hipMemcpyAsync(hx.data(), g->xp, 2 * M * sizeof(double), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipMemcpyAsync(ht.data(), g->p_tag, M, hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+    int K = 0;
+    if (!is_lattice(hx, ht, M, K)) {
+        RBF_ARG(mode != RBF_PRECOND_LATTICE,
+                "rbf_solver_create: RBF_PRECOND_LATTICE needs the P-nodes on a jittered "
+                "(K+1)^2 lattice of the unit square (row-major, walls tagged)");
+        return RBF_OK;
+    }
+    const int n = K - 1;
+    std::vector<double> Q, Qi, lam;
+    dct2_basis(n, Q, Qi, lam);
+    std::vector<int> cell(M);
+    std::vector<double> fx(M), fy(M);
+    for (int64_t v = 0; v < M; ++v) {
+        const double sx = hx[v] * K, sy = hx[M + v] * K;
+        const int i0 = std::min(std::max((int)std::floor(sx), 0), K - 1);
+        const int j0 = std::min(std::max((int)std::floor(sy), 0), K - 1);
+        cell[v] = j0 * (K + 1) + i0;
+        fx[v] = std::min(std::max(sx - i0, 0.0), 1.0);
+        fy[v] = std::min(std::max(sy - j0, 0.0), 1.0);
+    }
+    const size_t nn = (size_t)n * n;
+    int *dcell;
+    double *dfx, *dfy, *dlam, *dX, *dmean;
+    ALLOC(dcell, M);
+    ALLOC(dfx, M);
+    ALLOC(dfy, M);
+    ALLOC(dlam, n);
+    ALLOC(dX, nn);
+    ALLOC(dmean, 1);
+    ALLOC(S->pc_Q, nn);
+    ALLOC(S->pc_Qi, nn);
+    ALLOC(S->pc_T, nn);
+    PKry &P = S->pk;
+    for (double **q : {&P.r, &P.rh, &P.p[0], &P.p[1], &P.v, &P.s, &P.t, &P.ph, &P.sh}) ALLOC(*q, M);
+    ALLOC(P.partI, 2 * kMaxBlocks);
+    ALLOC(P.part1, kMaxBlocks);
+    ALLOC(P.part3, kMaxBlocks);
+    ALLOC(P.part6, 3 * kMaxBlocks);
+    ALLOC(P.partS, kMaxBlocks);
+    ALLOC(P.rec, (int64_t)(S->maxit_p + 2) * 4);
+    ALLOC(P.bb, 1);
+    ALLOC(P.rhrh, 1);
+    ALLOC(P.flag, 1);
+    ALLOC(P.iters, 1);
+    RBF_HIP(hipMemcpyAsync(dcell, cell.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(dfx, fx.data(), M * sizeof(double), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(dfy, fy.data(), M * sizeof(double), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(dlam, lam.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->pc_Q, Q.data(), nn * sizeof(double), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->pc_Qi, Qi.data(), nn * sizeof(double), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemsetAsync(dX, 0, nn * sizeof(double), st));
+    RBF_HIP(hipMemsetAsync(P.flag, 0, sizeof(int), st));
+    RBF_HIP(hipStreamSynchronize(st));
+    Lat &L = S->lat;
+    L.K = K;
+    L.n = n;
+    L.h = 1.0 / K;
+    L.c = S->p_vscale;
+    L.rs = S->p_rowscale;
+    L.cell = dcell;
+    L.fx = dfx;
+    L.fy = dfy;
+    L.lam = dlam;
+    L.X = dX;
+    L.mean = dmean;
+    RBF_BLAS(rocblas_create_handle(&S->blas));
+    RBF_BLAS(rocblas_set_stream(S->blas, st));
+    RBF_BLAS(rocblas_set_pointer_mode(S->blas, rocblas_pointer_mode_host));
+    rbf_status rc = pc_apply(S);  // first call loads the GEMM kernels
+    if (rc != RBF_OK) return rc;
+    RBF_HIP(hipStreamSynchronize(st));
+    S->pc_on = true;
+    return RBF_OK;
+}
+
 template <class F>
 void launch_kt(int k, F f) {
     if (k == 28) f(std::integral_constant<int, 28>{});
@@ -943,7 +1531,7 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     RBF_ARG(ni > 0, "rbf_solver_create: no interior P-node");
     S->p_vscale = ((double)ni / su) / (double)M;
     // The wall list order from atomics is irrelevant: rows are independent.
-    return RBF_OK;
+    return setup_lattice_pc(S, g, prm->precond);
 }
 
 rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
@@ -982,9 +1570,7 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
                            S->p_rowscale, S->prhs);
     });
     rbf_solve_stats ps;
-    EllM P{S->idx_pp, S->p_w, nullptr, M, k, S->p_u1, S->p_vscale};
-    rc = bicgstab<1, false>(S, S->kp, P, S->prhs, S->p_warm, S->rtol_p, S->maxit_p,
-                            S->last_iters_p, &ps);
+    rc = poisson_solve(S, S->prhs, S->p_warm, &ps);
     if (rc == RBF_OK) {  // p~ = solution minus its mean (zero-mean border)
         const int nbm = nblocks_rows(M);
         hipLaunchKernelGGL((k_sum<1>), dim3(nbm), dim3(kThreads), 0, st, M, S->p_warm, S->kp.partX);
@@ -1038,6 +1624,9 @@ extern "C" rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, 
                 prm->maxit_p <= 1000000,
             "rbf_solver_create: iteration caps out of range");
     RBF_ARG(prm->precision == 0, "rbf_solver_create: only precision 0 (FP64) is supported");
+    RBF_ARG(prm->precond == RBF_PRECOND_AUTO || prm->precond == RBF_PRECOND_NONE ||
+                prm->precond == RBF_PRECOND_LATTICE,
+            "rbf_solver_create: unknown precond %d", prm->precond);
     rbf_solver *S = new rbf_solver();
     S->st = rbf::as_stream(st);
     rbf_status rc = create_impl(S, grid, ops, u_bc, v_bc, prm);
@@ -1091,12 +1680,10 @@ extern "C" rbf_status rbf_solve_pressure(rbf_solver *S, const double *rhs, doubl
                                          rbf_solve_stats *stats) {
     rbf::clear_error();
     RBF_ARG(S && rhs && p_tilde, "rbf_solve_pressure: NULL argument");
-    EllM P{S->idx_pp, S->p_w, nullptr, S->M, S->k, S->p_u1, S->p_vscale};
     hipLaunchKernelGGL(k_scale, dim3(rbf::blocks_for(S->M, 256)), dim3(256), 0, S->st, S->M,
                        S->p_rowscale, rhs, S->p_rhs_tmp);
     RBF_CHECK_LAUNCH();
-    rbf_status rc = bicgstab<1, false>(S, S->kp, P, S->p_rhs_tmp, p_tilde, S->rtol_p,
-                                       S->maxit_p, S->last_iters_p, stats);
+    rbf_status rc = poisson_solve(S, S->p_rhs_tmp, p_tilde, stats);
     if (rc == RBF_OK) {
         const int nbm = nblocks_rows(S->M);
         hipLaunchKernelGGL((k_sum<1>), dim3(nbm), dim3(kThreads), 0, S->st, S->M, p_tilde,
@@ -1133,6 +1720,7 @@ extern "C" void rbf_solver_destroy(rbf_solver *S) {
     if (S->st) hipStreamSynchronize(S->st);
     if (S->ev0) hipEventDestroy(S->ev0);
     if (S->ev1) hipEventDestroy(S->ev1);
+    if (S->blas) rocblas_destroy_handle(S->blas);
     for (void *p : S->allocs) hipFree(p);
     if (S->hflag) hipHostFree(S->hflag);
     if (S->hred) hipHostFree(S->hred);

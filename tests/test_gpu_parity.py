@@ -221,10 +221,11 @@ def test_cavity_parity_small_workload(P, gpu):
     S.close()
 
 
-def test_solve_pressure_parity(P, gpu):
-    _say("solve_pressure")
+@pytest.mark.parametrize("precond", ["none", "lattice"])
+def test_solve_pressure_parity(P, gpu, precond):
+    _say("solve_pressure", precond)
     nd = ri.cavity_nodes(24, 0.3, 1)
-    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 1e-3)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 1e-3, precond=precond)
     orc = ocav.CavityOracle(nd, u_bc, v_bc, 100.0, 1e-3)
     rhs = ri.random_vector(nd.n_p, 3)
     rhs[nd.p_tag != 0] = 0.0
@@ -233,6 +234,71 @@ def test_solve_pressure_parity(P, gpu):
     ref, _ = orc.solve_pressure(rhs)
     assert stats.converged and stats.rel_residual <= 1e-10
     assert rel_err(x.cpu().numpy(), ref) <= 1e-10
+    S.close()
+
+
+def test_lattice_preconditioner_cuts_iterations(P, gpu):
+    """K=64 cavity pressure solve from a zero guess: both variants reach the
+    oracle's bordered solution; the lattice preconditioner needs at most a
+    fifth of the unpreconditioned iterations."""
+    _say("lattice preconditioner K=64")
+    nd = ri.cavity_nodes(64, 0.3, 2)
+    grid, ops = gpu_cavity_ops(nd, gpu)
+    u_bc, v_bc = ri.cavity_bc(nd.v_tag)
+    orc = ocav.CavityOracle(nd, u_bc, v_bc, 100.0, 1e-3)
+    rhs = ri.random_vector(nd.n_p, 5)
+    rhs[nd.p_tag != 0] = 0.0
+    ref, _ = orc.solve_pressure(rhs)
+    its = {}
+    for precond in ("none", "lattice"):
+        S = P.Solver(grid, ops, to_dev(u_bc, gpu), to_dev(v_bc, gpu), 100.0, 1e-3,
+                     rtol_p=1e-12, precond=precond)
+        x = to_dev(np.zeros(nd.n_p), gpu)
+        stats = S.solve_pressure(to_dev(rhs, gpu), x)
+        assert stats.converged and stats.rel_residual <= 1e-11, precond
+        assert rel_err(x.cpu().numpy(), ref) <= 1e-9, precond
+        its[precond] = stats.iterations
+        S.close()
+    _say("iterations", its)
+    assert its["lattice"] * 5 <= its["none"], its
+
+
+def test_lattice_preconditioner_needs_a_lattice(P, gpu):
+    """A P-node moved out of its lattice cell: 'lattice' is refused with
+    RBF_E_ARG, 'auto' falls back to the unpreconditioned iteration."""
+    _say("lattice detection")
+    nd = ri.cavity_nodes(12, 0.3, 0)
+    v = 5 * 13 + 6
+    assert nd.p_tag[v] == 0
+    nd.xp[0, v] = (6 + 0.7) * nd.h  # vertex (6, 5), now outside its lattice cell
+    grid, ops = gpu_cavity_ops(nd, gpu)
+    u_bc, v_bc = ri.cavity_bc(nd.v_tag)
+    with pytest.raises(P.RbfError) as ei:
+        P.Solver(grid, ops, to_dev(u_bc, gpu), to_dev(v_bc, gpu), 100.0, 1e-3, precond="lattice")
+    assert ei.value.status == -1
+    S = P.Solver(grid, ops, to_dev(u_bc, gpu), to_dev(v_bc, gpu), 100.0, 1e-3, precond="auto")
+    orc = ocav.CavityOracle(nd, u_bc, v_bc, 100.0, 1e-3)
+    rhs = ri.random_vector(nd.n_p, 7)
+    rhs[nd.p_tag != 0] = 0.0
+    x = to_dev(np.zeros(nd.n_p), gpu)
+    stats = S.solve_pressure(to_dev(rhs, gpu), x)
+    ref, _ = orc.solve_pressure(rhs)
+    assert stats.converged and rel_err(x.cpu().numpy(), ref) <= 1e-10
+    S.close()
+
+
+def test_cavity_parity_unpreconditioned(P, gpu):
+    """The unpreconditioned pressure iteration on the K=24 cavity, 40 steps."""
+    _say("cavity parity K=24, precond none")
+    nd = ri.cavity_nodes(24, 0.3, 1)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 2e-3, precond="none")
+    orc = ocav.CavityOracle(nd, u_bc, v_bc, 100.0, 2e-3)
+    s0 = orc.initial_state()
+    st = S.new_state(to_dev(s0.u, gpu), to_dev(s0.v, gpu))
+    S.step(st, 40)
+    so = orc.run(40, s0)
+    for key, ref in (("u", so.u), ("v", so.v), ("p", so.p), ("p_tilde", so.pt)):
+        assert rel_err(st[key].cpu().numpy(), ref) <= 1e-10, key
     S.close()
 
 
