@@ -255,7 +255,7 @@ typedef struct rbf_solver rbf_solver;
  * Errors: RBF_E_ARG (NULL pointers, sizes, dt/re <= 0, precision != 0,
  * unknown precond, RBF_PRECOND_LATTICE on a non-lattice P-grid, a self
  * index missing from a (V,V) or (P,P) stencil, no interior P node),
- * RBF_E_NOMEM, RBF_E_DEVICE (including a failed rocBLAS call).
+ * RBF_E_NOMEM, RBF_E_DEVICE.
  */
 rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, const rbf_ops *ops,
                              const double *u_bc, const double *v_bc, const rbf_params *prm,
@@ -281,6 +281,15 @@ rbf_status rbf_step(rbf_solver *s, int32_t nsteps, rbf_state *state, rbf_step_st
  */
 rbf_status rbf_solve_pressure(rbf_solver *s, const double *rhs, double *p_tilde,
                               rbf_solve_stats *stats);
+
+/*
+ * rbf_solver_apply_precond -- apply the pressure preconditioner once:
+ * z = P^-1 y with P^-1 = J (L5 + chi c 1^T)^-1 D^-1 as described at
+ * rbf_params.precond (D: the row scale of the stored Poisson rows).  For
+ * tests and diagnostics.  y, z: device [n_p], distinct.  Synchronises the
+ * solver's stream.  Errors: RBF_E_ARG (NULL, or no lattice preconditioner).
+ */
+rbf_status rbf_solver_apply_precond(rbf_solver *s, const double *y, double *z);
 
 /*
  * rbf_solver_profile -- sample the duration of the pressure-Poisson SpMV

@@ -25,7 +25,8 @@ FORCE_SMALL_STENCIL = 0x80000000
 EXPORTED = [
     "rbf_last_error", "rbf_abi_version", "rbf_build_nodes", "rbf_knn",
     "rbf_assemble_weights", "rbf_ell_apply", "rbf_cast_f32", "rbf_solver_create",
-    "rbf_step", "rbf_solve_pressure", "rbf_solver_profile", "rbf_solver_destroy",
+    "rbf_step", "rbf_solve_pressure", "rbf_solver_apply_precond", "rbf_solver_profile",
+    "rbf_solver_destroy",
 ]
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -109,6 +110,8 @@ def _load():
                              ctypes.POINTER(StepStats)]
     lib.rbf_solve_pressure.restype = S
     lib.rbf_solve_pressure.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveStats)]
+    lib.rbf_solver_apply_precond.restype = S
+    lib.rbf_solver_apply_precond.argtypes = [c_void_p, c_void_p, c_void_p]
     lib.rbf_solver_profile.restype = S
     lib.rbf_solver_profile.argtypes = [c_void_p, ctypes.c_int32, c_double_p, c_int64_p]
     lib.rbf_solver_destroy.restype = None

@@ -120,7 +120,7 @@ class Solver:
 
     PRECOND = {"auto": 0, "none": 1, "lattice": 2}
 
-    def __init__(self, grid, ops, u_bc, v_bc, re, dt, rtol_h=1e-13, rtol_p=1e-13,
+    def __init__(self, grid, ops, u_bc, v_bc, re, dt, rtol_h=1e-13, rtol_p=1e-12,
                  maxit_h=2000, maxit_p=20000, precond="auto"):
         N = grid["xv"].shape[1]
         M = grid["xp"].shape[1]
@@ -176,6 +176,13 @@ class Solver:
         stats = _lib.SolveStats()
         check(lib.rbf_solve_pressure(self._h, _ptr(rhs), _ptr(p_tilde), ctypes.byref(stats)))
         return stats
+
+    def apply_precond(self, y):
+        """z = P^-1 y, one application of the lattice pressure preconditioner."""
+        _dev(y, torch.float64, (self.M,), "y")
+        z = torch.empty_like(y)
+        check(lib.rbf_solver_apply_precond(self._h, _ptr(y), _ptr(z)))
+        return z
 
     def profile(self, sample_every=-1):
         """(avg_ms, count) of the sampled Poisson SpMV launches so far; with

@@ -15,9 +15,8 @@
 #include <utility>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "common.h"
+#include "dgemm_mfma.h"
 #include "ell.h"
 
 namespace {
@@ -447,20 +446,33 @@ __global__ void __launch_bounds__(kThreads) k_resid(EllM A, const double *__rest
 // interior nodes the separable operator (T (x) I + I (x) T) / h^2, T the
 // 1-D second difference with Neumann ends, diagonalised by the DCT-II basis
 // Q (T = Q Lam Q^-1).  The two-dimensional transforms Q^-1 X Q^-T and
-// Q Z Q^T are dense (K-1) x (K-1) products (rocBLAS DGEMM on the matrix
-// cores); the border fixes the zero mode and the sum of z.
+// Q Zh Q^T are dense (K-1) x (K-1) FP64 products on the matrix cores
+// (dgemm_mfma.h); the division by the eigenvalues is the epilogue of the
+// second product.  The border fixes the zero mode and the sum of z.
 //
-// Interior work array X (column-major, ld n = K-1): X(a, b) belongs to
-// lattice node (i, j) = (a + 1, b + 1).
+// Interior arrays, n = K - 1, X(a, b) / Z(a, b) belong to lattice node
+// (i, j) = (a + 1, b + 1):
+//   X  reduced right-hand side, row-major  (a n + b)
+//   T  Q^-1 X (column-major), then Q Zh (column-major)
+//   Zh coefficients / eigenvalues, row-major (k n + l)
+//   Z  interior solution, column-major      (a + b n)
+// The constant shift needs the lattice sum of the boundary values:
+// sum_w Z(in(w)) = sum_kl Zh(k, l) What(k, l) with What = Q^T w Q (w counts
+// the boundary nodes clamped to each interior node), reduced per tile in the
+// second product, plus sum_w |w - in(w)| g_w, reduced by the kernel that
+// builds X.
 struct Lat {
-    int K, n;
+    int K, n, ntiles;
     double h, c;           // spacing; border scale
     const double *rs;      // [M] row scale of the stored Poisson rows
     const int *cell;       // [M] lower-left lattice node of the cell holding the node
     const double *fx, *fy; // [M] bilinear coordinates in that cell
     const double *lam;     // [n] eigenvalues of T (unit spacing)
-    double *X;             // [n * n]
+    const double *Q, *Qi;  // [n * n] column-major
+    const double *What;    // [n * n] column-major
+    double *X, *T, *Zh;    // [n * n] work (Z overwrites X)
     double *mean;          // [1] zero-mode coefficient (mean of the reduced rhs)
+    double *partW;         // [ntiles] per-tile sums of Zh o What
 };
 
 // Preconditioned BiCGSTAB vectors and scalars (one right-hand side).
@@ -469,31 +481,39 @@ struct Lat {
 struct PKry {
     double *r, *rh, *p[2], *v, *s, *t, *ph, *sh;
     double *partI;  // init: {rho_0, ||b||^2}
-    double *part1;  // k_pc_dir: ||r||^2
+    double *part1;  // k_pc_dir: ||r||^2, boundary sum of the reduced rhs of p
+    double *partGs; // k_pc_s: boundary sum of the reduced rhs of s
     double *part3;  // k_pc_av (v): (rh, v)
     double *part6;  // k_pc_av (t): (t, s), (t, t), (rh, t)
     double *partS;  // k_pc_post: sum of the preconditioned vector
     double *rec;    // per iteration {rho, alpha, omega, ||r||^2}
     double *bb, *rhrh;
+    double *best;   // [2][2] {best ||r||^2, its iteration}, by iteration parity
     int *flag, *iters;
 };
 
+// Iterations without progress after which the preconditioned iteration restarts.
+constexpr int kStall = 30;
+
 // Reduced right-hand side at interior lattice node `row` = (i, j), from the
-// values val(node) of the vector being preconditioned: D^-1 y with the wall
-// values moved to the right-hand side.
+// values val(node) of the vector y being preconditioned: D^-1 y with the
+// wall values moved to the right-hand side.  At a boundary node, returns
+// its term |w - in(w)| (D^-1 y)_w of the boundary sum (0 elsewhere).
 template <class V>
-__device__ __forceinline__ void pc_reduce(const Lat &L, int64_t row, V val) {
+__device__ __forceinline__ double pc_reduce(const Lat &L, int64_t row, double vself, V val) {
     const int K = L.K, K1 = K + 1;
     const int i = (int)(row % K1), j = (int)(row / K1);
-    if (i < 1 || i > K - 1 || j < 1 || j > K - 1) return;
-    double g = val(row) / L.rs[row];
+    const bool bi = (i == 0 || i == K), bj = (j == 0 || j == K);
+    if (bi || bj) return ((bi && bj) ? L.h * 1.4142135623730951 : L.h) * (vself / L.rs[row]);
+    double g = vself / L.rs[row];
     double wsum = 0.0;
     if (i == 1) wsum += val(row - 1) / L.rs[row - 1];
     if (i == K - 1) wsum += val(row + 1) / L.rs[row + 1];
     if (j == 1) wsum += val(row - K1) / L.rs[row - K1];
     if (j == K - 1) wsum += val(row + K1) / L.rs[row + K1];
     g -= wsum / L.h;
-    L.X[(int64_t)(i - 1) + (int64_t)(j - 1) * L.n] = g;
+    L.X[(int64_t)(i - 1) * L.n + (j - 1)] = g;
+    return 0.0;
 }
 
 // r0 = b - A x, rh = r0.
@@ -568,7 +588,7 @@ __global__ void __launch_bounds__(kThreads) k_pc_dir(PKry K, Lat L, double *__re
         const double rn = K.s[j] - om * K.t[j];
         return rn + be * (pold[j] - om * K.v[j]);
     };
-    double acc[1] = {0.0};
+    double acc[2] = {0.0, 0.0};
     for (int64_t it = 0;; ++it) {
         const int64_t row = row_of(it);
         if (row - threadIdx.x >= m) break;
@@ -585,15 +605,15 @@ __global__ void __launch_bounds__(kThreads) k_pc_dir(PKry K, Lat L, double *__re
             }
             pnew[row] = pn;
             acc[0] += rn * rn;
-            pc_reduce(L, row, pval);
+            acc[1] += pc_reduce(L, row, pn, pval);
         }
     }
-    store_partials<1>(acc, K.part1, nb);
+    store_partials<2>(acc, K.part1, nb);
 }
 
 // Iteration i, step 2: convergence test on ||r_i||, alpha = rho / (rh, v),
 // s = r - alpha v and its reduced right-hand side.
-__global__ void __launch_bounds__(kThreads) k_pc_s(PKry K, Lat L, int64_t m, int i,
+__global__ void __launch_bounds__(kThreads) k_pc_s(PKry K, Lat L, int64_t m, int i, int i0,
                                                     double tol2) {
     if (K.flag[0] != 0) return;
     const int nb = gridDim.x;
@@ -606,11 +626,25 @@ __global__ void __launch_bounds__(kThreads) k_pc_s(PKry K, Lat L, int64_t m, int
     const double bb = K.bb[0], rhrh = K.rhrh[0];
     const bool bad = !isfinite(rr) || !isfinite(rho);
     const bool conv = !bad && (rr <= tol2 * fmax(bb, 1e-300) || rr == 0.0);
-    const bool brk = !bad && !conv && (!(fabs(rho) > kBreakdown * sqrt(rr * rhrh)) || !isfinite(al));
+    // Stagnation: no 0.1% decrease of the best ||r||^2 for kStall iterations
+    // is handled like a breakdown (restart from the true residual).  The best
+    // value is double-buffered by parity: read from the previous launch,
+    // written for the next one.
+    const double *bprev = K.best + ((i + 1) & 1) * 2;
+    const bool fresh = (i == i0);
+    const double best = fresh ? rr : bprev[0];
+    const int best_it = fresh ? i : (int)bprev[1];
+    const bool better = fresh || rr < 0.999 * best;
+    const bool stall = !better && (i - best_it >= kStall);
+    const bool brk = !bad && !conv &&
+                     (!(fabs(rho) > kBreakdown * sqrt(rr * rhrh)) || !isfinite(al) || stall);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         double *rc = K.rec + (int64_t)i * 4;
         rc[1] = al;
         rc[3] = rr;
+        double *bnext = K.best + (i & 1) * 2;
+        bnext[0] = better ? rr : best;
+        bnext[1] = better ? (double)i : (double)best_it;
         if (bad) K.flag[0] = -1;
         else if (conv || brk) {
             K.flag[0] = conv ? 1 : 2;
@@ -619,34 +653,67 @@ __global__ void __launch_bounds__(kThreads) k_pc_s(PKry K, Lat L, int64_t m, int
     }
     if (bad || conv || brk) return;
     auto sval = [&](int64_t j) { return K.r[j] - al * K.v[j]; };
+    double acc[1] = {0.0};
     for (int64_t it = 0;; ++it) {
         const int64_t row = row_of(it);
         if (row - threadIdx.x >= m) break;
         if (row < m) {
-            K.s[row] = sval(row);
-            pc_reduce(L, row, sval);
+            const double sv = sval(row);
+            K.s[row] = sv;
+            acc[0] += pc_reduce(L, row, sv, sval);
         }
     }
+    store_partials<1>(acc, K.partGs, nb);
 }
 
-// Zero mode: remember the mean of the reduced right-hand side, then divide
-// by the eigenvalues of the interior operator (the zero mode is set to 0).
-__global__ void __launch_bounds__(kThreads) k_pc_scale(Lat L) {
-    const int64_t nn = (int64_t)L.n * L.n;
+// Reduced right-hand side of an explicit vector y (rbf_solver_apply_precond).
+__global__ void __launch_bounds__(kThreads) k_pc_pre(Lat L, const double *__restrict__ y, int64_t m,
+                                                      double *partG) {
+    auto yval = [&](int64_t j) { return y[j]; };
+    double acc[1] = {0.0};
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= m) break;
+        if (row < m) acc[0] += pc_reduce(L, row, y[row], yval);
+    }
+    store_partials<1>(acc, partG, gridDim.x);
+}
+
+// The four transforms of the interior solve, one 16x16 tile per workgroup
+// of kGemmWaves waves.  STAGE 0: T = Q^-1 X; 1: Zh = (T Q^-T) / eig with
+// the zero mode recorded in *mean and set to 0, and the tile's sum of
+// Zh o What; 2: T = Q Zh; 3: Z = T Q^T (into X).
+constexpr int kGemmWaves = 4;
+template <int STAGE>
+__global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
+    const int n = L.n, nt = (n + 15) / 16;
+    const int ti = (int)(blockIdx.x % nt), tj = (int)(blockIdx.x / nt);
+    const double *A = STAGE == 0 ? L.Qi : STAGE == 1 ? L.T : STAGE == 2 ? L.Q : L.T;
+    const double *B = STAGE == 0 ? L.X : STAGE == 1 ? L.Qi : STAGE == 2 ? L.Zh : L.Q;
+    double wsum = 0.0;
     const double h2 = L.h * L.h;
-    for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < nn;
-         e += (int64_t)gridDim.x * kThreads) {
-        const int k = (int)(e % L.n), l = (int)(e / L.n);
-        if (e == 0) {
-            *L.mean = L.X[0];
-            L.X[0] = 0.0;
+    const bool owner = rbf::dgemm_tile_16x16<kGemmWaves>(n, A, B, ti, tj, [&](int i, int j, double v) {
+        if constexpr (STAGE == 1) {
+            double z = 0.0;
+            if (i == 0 && j == 0) *L.mean = v;
+            else z = v * h2 / (L.lam[i] + L.lam[j]);
+            L.Zh[(int64_t)i * n + j] = z;
+            wsum += z * L.What[i + (int64_t)j * n];
+        } else if constexpr (STAGE == 3) {
+            L.X[i + (int64_t)j * n] = v;
         } else {
-            L.X[e] *= h2 / (L.lam[k] + L.lam[l]);
+            L.T[i + (int64_t)j * n] = v;
+        }
+    });
+    if constexpr (STAGE == 1) {
+        if (owner) {
+            wsum = rbf::wave_sum(wsum);
+            if ((threadIdx.x & 63) == 0) L.partW[blockIdx.x] = wsum;
         }
     }
 }
 
-// Lattice value of L5^-1 at node (i, j), before the constant shift.
+// Lattice value of L5^-1 at node (i, j), before the constant shift (Z in X).
 __device__ __forceinline__ double pc_lattice(const Lat &L, const double *y, int i, int j) {
     const int K = L.K;
     const int ci = min(max(i, 1), K - 1), cj = min(max(j, 1), K - 1);
@@ -661,38 +728,20 @@ __device__ __forceinline__ double pc_lattice(const Lat &L, const double *y, int 
 }
 
 // out = J (zl + alpha) at every node; alpha makes the lattice sum equal to
-// the value the border prescribes (mean / c); block partials of sum(out).
+// the value the border prescribes (mean / c): the interior part of the
+// lattice solution has zero sum (no zero mode), the boundary part is
+// reduced from the partials of k_pc_gemm<1> (partW) and of the kernel that
+// built X (partG, nbG blocks).  Writes block partials of sum(out).
 __global__ void __launch_bounds__(kThreads) k_pc_post(Lat L, PKry K, const double *__restrict__ y,
                                                        double *__restrict__ out, int64_t m,
-                                                       double *partS) {
+                                                       double *partS, const double *partG,
+                                                       int nbG) {
     if (K.flag[0] != 0) return;
     const int Kl = L.K;
-    // Boundary sum (each block, same order): the interior part of the
-    // lattice solution has zero sum (no zero mode).
-    double bs[1] = {0.0};
-    const int nbnd = 4 * Kl;
-    for (int b = threadIdx.x; b < nbnd; b += kThreads) {
-        int i, j;
-        if (b < Kl + 1) {
-            i = b;
-            j = 0;
-        } else if (b < 2 * (Kl + 1)) {
-            i = b - (Kl + 1);
-            j = Kl;
-        } else if (b < 2 * (Kl + 1) + (Kl - 1)) {
-            i = 0;
-            j = b - 2 * (Kl + 1) + 1;
-        } else {
-            i = Kl;
-            j = b - 2 * (Kl + 1) - (Kl - 1) + 1;
-        }
-        bs[0] += pc_lattice(L, y, i, j);
-    }
-    {
-        __shared__ double lds[kThreads / 64];
-        rbf::block_sum<1>(bs, lds);
-    }
-    const double alpha = (*L.mean / L.c - bs[0]) / (double)m;
+    double bw[1], bg[1];
+    load_partials<1>(L.partW, L.ntiles, bw);
+    load_partials<1>(partG, nbG, bg);
+    const double alpha = (*L.mean / L.c - (bw[0] + bg[0])) / (double)m;
     double acc[1] = {0.0};
     for (int64_t it = 0;; ++it) {
         const int64_t row = row_of(it);
@@ -992,8 +1041,6 @@ struct rbf_solver {
     bool pc_on = false;
     Lat lat{};
     PKry pk{};
-    double *pc_Q = nullptr, *pc_Qi = nullptr, *pc_T = nullptr;
-    rocblas_handle blas = nullptr;
     // pinned host buffers
     int *hflag = nullptr;
     double *hred = nullptr;
@@ -1150,35 +1197,20 @@ rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, 
     return rc;
 }
 
-#define RBF_BLAS(call)                                                                 \
-    do {                                                                               \
-        rocblas_status b_ = (call);                                                    \
-        if (b_ != rocblas_status_success) {                                            \
-            ::rbf::set_error("%s failed: %s", #call, rocblas_status_to_string(b_));     \
-            return RBF_E_DEVICE;                                                       \
-        }                                                                              \
-    } while (0)
-
-// One application of the lattice preconditioner's interior solve on L.X:
-// X <- Q (Lam^-1 o (Q^-1 X Q^-T)) Q^T (column-major n x n products).
+// One application of the lattice preconditioner's interior solve:
+// Z = Q (Lam^-1 o (Q^-1 X Q^-T)) Q^T, four tiled MFMA products.
 rbf_status pc_apply(rbf_solver *S) {
-    const int n = S->lat.n;
-    const double one = 1.0, zero = 0.0;
-    double *X = S->lat.X, *T = S->pc_T;
-    const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
-    RBF_BLAS(rocblas_dgemm(S->blas, N_, N_, n, n, n, &one, S->pc_Qi, n, X, n, &zero, T, n));
-    RBF_BLAS(rocblas_dgemm(S->blas, N_, T_, n, n, n, &one, T, n, S->pc_Qi, n, &zero, X, n));
-    const int64_t nn = (int64_t)n * n;
-    hipLaunchKernelGGL(k_pc_scale, dim3(std::min<int64_t>(kMaxBlocks, rbf::blocks_for(nn, kThreads))),
-                       dim3(kThreads), 0, S->st, S->lat);
-    RBF_BLAS(rocblas_dgemm(S->blas, N_, N_, n, n, n, &one, S->pc_Q, n, X, n, &zero, T, n));
-    RBF_BLAS(rocblas_dgemm(S->blas, N_, T_, n, n, n, &one, T, n, S->pc_Q, n, &zero, X, n));
+    const dim3 g(S->lat.ntiles), b(64 * kGemmWaves);
+    hipLaunchKernelGGL(k_pc_gemm<0>, g, b, 0, S->st, S->lat);
+    hipLaunchKernelGGL(k_pc_gemm<1>, g, b, 0, S->st, S->lat);
+    hipLaunchKernelGGL(k_pc_gemm<2>, g, b, 0, S->st, S->lat);
+    hipLaunchKernelGGL(k_pc_gemm<3>, g, b, 0, S->st, S->lat);
     return RBF_OK;
 }
 
 // Right-preconditioned BiCGSTAB on the pressure system (one right-hand side)
 // with the lattice preconditioner; same contract as bicgstab<1, false>.
-// Per iteration: k_pc_dir, P^-1 (4 DGEMM + k_pc_scale + k_pc_post),
+// Per iteration: k_pc_dir, P^-1 (4 x k_pc_gemm + k_pc_post),
 // k_pc_av (v), k_pc_s, P^-1, k_pc_av (t).
 rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double tol, int maxit,
                      int &last_iters, rbf_solve_stats *stats) {
@@ -1216,7 +1248,8 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
             const int par = it & 1;
             hipLaunchKernelGGL(k_pc_dir, grid, block, 0, st, K, L, x, m, it, i0);
             if ((rc = pc_apply(S)) != RBF_OK) return rc;
-            hipLaunchKernelGGL(k_pc_post, grid, block, 0, st, L, K, K.p[par], K.ph, m, K.partS);
+            hipLaunchKernelGGL(k_pc_post, grid, block, 0, st, L, K, K.p[par], K.ph, m, K.partS,
+                               K.part1 + nb, nb);
             const bool sample = S->prof_every > 0 && (S->prof_launches++ % S->prof_every) == 0;
             if (sample) RBF_HIP(hipEventRecord(S->ev0, st));
             av(0, K.ph, K.v);
@@ -1228,9 +1261,10 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
                 S->prof_ms += ms;
                 ++S->prof_count;
             }
-            hipLaunchKernelGGL(k_pc_s, grid, block, 0, st, K, L, m, it, tol2);
+            hipLaunchKernelGGL(k_pc_s, grid, block, 0, st, K, L, m, it, i0, tol2);
             if ((rc = pc_apply(S)) != RBF_OK) return rc;
-            hipLaunchKernelGGL(k_pc_post, grid, block, 0, st, L, K, K.s, K.sh, m, K.partS);
+            hipLaunchKernelGGL(k_pc_post, grid, block, 0, st, L, K, K.s, K.sh, m, K.partS,
+                               K.partGs, nb);
             av(1, K.sh, K.t);
         }
         RBF_CHECK_LAUNCH();
@@ -1361,40 +1395,60 @@ rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
         fx[v] = std::min(std::max(sx - i0, 0.0), 1.0);
         fy[v] = std::min(std::max(sy - j0, 0.0), 1.0);
     }
+    // What = Q^T w Q for the boundary-count weights w(a, b) = [a = 0] +
+    // [a = n-1] + [b = 0] + [b = n-1] + [corner]: with s_l = sum_b Q(b, l),
+    // What(k, l) = (Q(0,k) + Q(n-1,k)) s_l + s_k (Q(0,l) + Q(n-1,l))
+    //            + (Q(0,k) + Q(n-1,k)) (Q(0,l) + Q(n-1,l)).
+    std::vector<double> csum(n, 0.0), edge(n), What((size_t)n * n);
+    for (int k = 0; k < n; ++k) {
+        for (int a = 0; a < n; ++a) csum[k] += Q[(size_t)a + (size_t)k * n];
+        edge[k] = Q[(size_t)k * n] + Q[(size_t)(n - 1) + (size_t)k * n];
+    }
+    for (int l = 0; l < n; ++l)
+        for (int k = 0; k < n; ++k)
+            What[(size_t)k + (size_t)l * n] = edge[k] * csum[l] + csum[k] * edge[l] + edge[k] * edge[l];
     const size_t nn = (size_t)n * n;
+    const int nt = (n + 15) / 16;
+    Lat &L = S->lat;
+    L.ntiles = nt * nt;
     int *dcell;
-    double *dfx, *dfy, *dlam, *dX, *dmean;
+    double *dfx, *dfy, *dlam, *dQ, *dQi, *dW;
     ALLOC(dcell, M);
     ALLOC(dfx, M);
     ALLOC(dfy, M);
     ALLOC(dlam, n);
-    ALLOC(dX, nn);
-    ALLOC(dmean, 1);
-    ALLOC(S->pc_Q, nn);
-    ALLOC(S->pc_Qi, nn);
-    ALLOC(S->pc_T, nn);
+    ALLOC(dQ, nn);
+    ALLOC(dQi, nn);
+    ALLOC(dW, nn);
+    ALLOC(L.X, nn);
+    ALLOC(L.T, nn);
+    ALLOC(L.Zh, nn);
+    ALLOC(L.mean, 1);
+    ALLOC(L.partW, L.ntiles);
     PKry &P = S->pk;
     for (double **q : {&P.r, &P.rh, &P.p[0], &P.p[1], &P.v, &P.s, &P.t, &P.ph, &P.sh}) ALLOC(*q, M);
     ALLOC(P.partI, 2 * kMaxBlocks);
-    ALLOC(P.part1, kMaxBlocks);
+    ALLOC(P.part1, 2 * kMaxBlocks);
+    ALLOC(P.partGs, kMaxBlocks);
     ALLOC(P.part3, kMaxBlocks);
     ALLOC(P.part6, 3 * kMaxBlocks);
     ALLOC(P.partS, kMaxBlocks);
     ALLOC(P.rec, (int64_t)(S->maxit_p + 2) * 4);
     ALLOC(P.bb, 1);
     ALLOC(P.rhrh, 1);
+    ALLOC(P.best, 4);
     ALLOC(P.flag, 1);
     ALLOC(P.iters, 1);
     RBF_HIP(hipMemcpyAsync(dcell, cell.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
     RBF_HIP(hipMemcpyAsync(dfx, fx.data(), M * sizeof(double), hipMemcpyHostToDevice, st));
     RBF_HIP(hipMemcpyAsync(dfy, fy.data(), M * sizeof(double), hipMemcpyHostToDevice, st));
     RBF_HIP(hipMemcpyAsync(dlam, lam.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
-    RBF_HIP(hipMemcpyAsync(S->pc_Q, Q.data(), nn * sizeof(double), hipMemcpyHostToDevice, st));
-    RBF_HIP(hipMemcpyAsync(S->pc_Qi, Qi.data(), nn * sizeof(double), hipMemcpyHostToDevice, st));
-    RBF_HIP(hipMemsetAsync(dX, 0, nn * sizeof(double), st));
+    RBF_HIP(hipMemcpyAsync(dQ, Q.data(), nn * sizeof(double), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(dQi, Qi.data(), nn * sizeof(double), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(dW, What.data(), nn * sizeof(double), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemsetAsync(L.X, 0, nn * sizeof(double), st));
     RBF_HIP(hipMemsetAsync(P.flag, 0, sizeof(int), st));
     RBF_HIP(hipStreamSynchronize(st));
-    Lat &L = S->lat;
     L.K = K;
     L.n = n;
     L.h = 1.0 / K;
@@ -1404,14 +1458,9 @@ rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
     L.fx = dfx;
     L.fy = dfy;
     L.lam = dlam;
-    L.X = dX;
-    L.mean = dmean;
-    RBF_BLAS(rocblas_create_handle(&S->blas));
-    RBF_BLAS(rocblas_set_stream(S->blas, st));
-    RBF_BLAS(rocblas_set_pointer_mode(S->blas, rocblas_pointer_mode_host));
-    rbf_status rc = pc_apply(S);  // first call loads the GEMM kernels
-    if (rc != RBF_OK) return rc;
-    RBF_HIP(hipStreamSynchronize(st));
+    L.Q = dQ;
+    L.Qi = dQi;
+    L.What = dW;
     S->pc_on = true;
     return RBF_OK;
 }
@@ -1696,6 +1745,24 @@ extern "C" rbf_status rbf_solve_pressure(rbf_solver *S, const double *rhs, doubl
     return rc;
 }
 
+extern "C" rbf_status rbf_solver_apply_precond(rbf_solver *S, const double *y, double *z) {
+    rbf::clear_error();
+    RBF_ARG(S && y && z, "rbf_solver_apply_precond: NULL argument");
+    RBF_ARG(S->pc_on, "rbf_solver_apply_precond: the solver has no lattice preconditioner");
+    hipStream_t st = S->st;
+    const int64_t m = S->M;
+    const int nb = nblocks_rows(m);
+    RBF_HIP(hipMemsetAsync(S->pk.flag, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_pc_pre, dim3(nb), dim3(kThreads), 0, st, S->lat, y, m, S->pk.partGs);
+    rbf_status rc = pc_apply(S);
+    if (rc != RBF_OK) return rc;
+    hipLaunchKernelGGL(k_pc_post, dim3(nb), dim3(kThreads), 0, st, S->lat, S->pk, y, z, m,
+                       S->pk.partS, S->pk.partGs, nb);
+    RBF_CHECK_LAUNCH();
+    RBF_HIP(hipStreamSynchronize(st));
+    return RBF_OK;
+}
+
 extern "C" rbf_status rbf_solver_profile(rbf_solver *S, int32_t sample_every, double *avg_ms,
                                          int64_t *count) {
     rbf::clear_error();
@@ -1720,7 +1787,6 @@ extern "C" void rbf_solver_destroy(rbf_solver *S) {
     if (S->st) hipStreamSynchronize(S->st);
     if (S->ev0) hipEventDestroy(S->ev0);
     if (S->ev1) hipEventDestroy(S->ev1);
-    if (S->blas) rocblas_destroy_handle(S->blas);
     for (void *p : S->allocs) hipFree(p);
     if (S->hflag) hipHostFree(S->hflag);
     if (S->hred) hipHostFree(S->hred);

@@ -263,6 +263,68 @@ def test_lattice_preconditioner_cuts_iterations(P, gpu):
     assert its["lattice"] * 5 <= its["none"], its
 
 
+def _lattice_precond_reference(nd, ops, y):
+    """Plain numpy statement of the lattice preconditioner (header of
+    rbf_params.precond): z = J (L5 + chi c 1^T)^-1 D^-1 y, with L5 solved by
+    sparse LU on the full lattice (no transforms, no wall elimination)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    K = nd.K
+    n1 = K + 1
+    M = n1 * n1
+    h = 1.0 / K
+    # D: signed inverse row norms of the stored Poisson rows.
+    wall = nd.p_tag != 0
+    lap = ops["pp_lap"].cpu().numpy()
+    dx = ops["pp_dx"].cpu().numpy()
+    dy = ops["pp_dy"].cpu().numpy()
+    rows = np.where(wall[None, :], nd.p_normal[0][None, :] * dx + nd.p_normal[1][None, :] * dy, lap)
+    rs = np.where(wall, 1.0, -1.0) / np.sqrt((rows * rows).sum(axis=0))
+    u1 = np.where(wall, 0.0, rs)
+    c = ((~wall).sum() / np.abs(u1).sum()) / M
+    # L5 with one-sided Neumann rows, bordered by chi c 1^T.
+    r_, c_, v_ = [], [], []
+    for j in range(n1):
+        for i in range(n1):
+            r = j * n1 + i
+            if 0 < i < K and 0 < j < K:
+                r_ += [r] * 5
+                c_ += [r, r - 1, r + 1, r - n1, r + n1]
+                v_ += [-4 / h**2] + [1 / h**2] * 4
+            else:
+                di = 1 if i == 0 else (-1 if i == K else 0)
+                dj = 1 if j == 0 else (-1 if j == K else 0)
+                d = h * np.hypot(di, dj)
+                r_ += [r, r]
+                c_ += [r, (j + dj) * n1 + i + di]
+                v_ += [1 / d, -1 / d]
+    L5 = sp.csr_matrix((v_, (r_, c_)), shape=(M, M)).toarray()
+    L5 += c * np.outer(~wall, np.ones(M))
+    zl = np.linalg.solve(L5, y / rs)
+    # J: bilinear interpolation from the lattice points to the nodes.
+    sx, sy = nd.xp[0] * K, nd.xp[1] * K
+    i0 = np.clip(np.floor(sx).astype(int), 0, K - 1)
+    j0 = np.clip(np.floor(sy).astype(int), 0, K - 1)
+    fx, fy = sx - i0, sy - j0
+    z = lambda i, j: zl[j * n1 + i]  # noqa: E731
+    return ((1 - fy) * ((1 - fx) * z(i0, j0) + fx * z(i0 + 1, j0))
+            + fy * ((1 - fx) * z(i0, j0 + 1) + fx * z(i0 + 1, j0 + 1)))
+
+
+@pytest.mark.parametrize("K", [12, 23, 40])
+def test_lattice_preconditioner_matches_its_definition(P, gpu, K):
+    """One application of P^-1 through the C ABI against the dense statement
+    (K=23: interior size 22, a ragged 16x16 tiling)."""
+    _say("apply_precond K=", K)
+    nd = ri.cavity_nodes(K, 0.3, 4)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 1e-3, precond="lattice")
+    y = ri.random_vector(nd.n_p, 11)
+    z = S.apply_precond(to_dev(y, gpu)).cpu().numpy()
+    ref = _lattice_precond_reference(nd, ops, y)
+    assert rel_err(z, ref) <= 1e-12
+    S.close()
+
+
 def test_lattice_preconditioner_needs_a_lattice(P, gpu):
     """A P-node moved out of its lattice cell: 'lattice' is refused with
     RBF_E_ARG, 'auto' falls back to the unpreconditioned iteration."""
