@@ -12,10 +12,13 @@ Workload (one JSON line on stdout):
     in FP64 and FP32-stored ELL, timed with HIP events; achieved GB/s from the
     algorithmic bytes; truncation error against closed-form derivatives of
     sin(kx)cos(ky), k = 2 pi {4, 16, 64}.
-  * roofline of the dominant kernel of the step (the pressure-Poisson SpMV
-    inside BiCGSTAB), its average duration sampled with HIP events on the
-    solver's stream during the timed steps.
-  * cpu_baseline: the CPU oracle (SciPy LU solves) on a bounded sample.
+  * roofline of the dominant kernel of the step: the FP64 MFMA transform
+    k_pc_gemm of the lattice preconditioner (2 n^3 flops per launch,
+    n = K - 1), its average duration sampled with HIP events on the solver's
+    stream during the timed steps; the pressure SpMV k_pc_av (HBM bytes per
+    launch) is reported beside it.
+  * cpu_baseline: the CPU oracle (SciPy sparse LU solves) on a bounded
+    sample: the same cavity at h = 1/200.
 """
 import argparse
 import json
@@ -30,13 +33,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+# Traffic beyond L2 per launch at K=400 from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE, scaled by the same counters on a plain 256 MiB copy
+# (profiles/k_pc_gemm_cavity_K400_pmc.md); mean of the four k_pc_gemm
+# stages, and the pressure SpMV k_pc_av<28,0>.  Set to None when the kernel
+# changes until it is measured again.
+GEMM_TRAFFIC_BYTES = 22.58e6
+SPMV_TRAFFIC_BYTES = 61.03e6
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--K", type=int, default=400, help="cavity cells per side (h = 1/K)")
     ap.add_argument("--re", type=float, default=1e4)
     ap.add_argument("--dt", type=float, default=2e-4)
@@ -46,9 +59,9 @@ def parse():
     ap.add_argument("--spmv-reps", type=int, default=1000)
     ap.add_argument("--no-spmv", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-K", type=int, default=100)
+    ap.add_argument("--cpu-K", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=20)
-    ap.add_argument("--prof-every", type=int, default=50)
+    ap.add_argument("--prof-every", type=int, default=25)
     ap.add_argument("--rtol-p", type=float, default=1e-10)
     ap.add_argument("--rtol-h", type=float, default=1e-12)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -123,6 +136,7 @@ def spmv_bench(P, args, dev):
     out = {"setup_s": setup_s, "systems": nsys,
            "weights_vv_ms": wt_ms,
            "weights_vv_tflops": xv.shape[1] * flops_per_sys / (wt_ms * 1e-3) / 1e12}
+    out["weights_vv_frac_fp64_peak"] = out["weights_vv_tflops"] / FP64_VALU_PEAK_TFLOPS
     res = {}
     for k_wave in (4, 16, 64):
         kk = 2 * math.pi * k_wave
@@ -183,13 +197,15 @@ def cpu_baseline(args):
     t0 = time.perf_counter()
     s = orc.run(args.cpu_steps, s)
     el = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": (nd.n_v + nd.n_p) * args.cpu_steps / el, "unit": "node-steps/s",
-            "cores": min(threads, os.cpu_count() or 1), "kind": "oracle",
-            "sample": f"cavity K={args.cpu_K} (N={nd.n_v}, M={nd.n_p}), {args.cpu_steps} steps "
-                      f"after an untimed SuperLU factorisation ({setup:.1f} s); same Re, dt, "
-                      f"stencils; per-step cost grows with K, so this overstates the oracle "
-                      f"rate at K={args.K}"}
+            "cores": 1, "kind": "oracle",
+            "sample": f"cavity h=1/{args.cpu_K} (N={nd.n_v}, M={nd.n_p}), {args.cpu_steps} steps "
+                      f"({el:.1f} s) after an untimed setup with SuperLU factorisations "
+                      f"({setup:.1f} s); same Re, dt and stencils as the GPU run. The timed "
+                      f"steps are SuperLU triangular solves and CSR products, single-threaded. "
+                      f"The oracle's cost per node grows with K, so this overstates its rate "
+                      f"at h=1/{args.K}",
+            "u_abs_max": float(np.abs(s.u).max())}
 
 
 def main():
@@ -222,13 +238,22 @@ def main():
     stats = S.step(st, args.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    avg_ms, cnt = S.profile(0)
+    prof = S.profile(0)
     value = (N + M) * args.steps / el
     umax = float(st["u"].abs().max())
     log(f"{el:.3f}s  {value:.3e} node-steps/s  poisson iters/step "
         f"{stats.poisson_iters / max(1, args.steps):.1f}  |u|max {umax:.3f}")
-    bytes_launch = M * (28 * (4 + 8) + 8 + 8 + 8)  # idx + w, p^ (once), rh read, v write
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
+    # Dominant kernel: k_pc_gemm, the n x n x n FP64 products of the
+    # preconditioner (n = K - 1); four launches per application, timed together.
+    n = args.K - 1
+    gemm_ms, gemm_cnt = prof["gemm"]
+    gemm_flops = 2.0 * n ** 3
+    gemm_tf = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else None
+    # Pressure SpMV k_pc_av<28, 0>: idx + w (28 each), p^ gathered (once),
+    # rh read, v written.
+    spmv_ms, spmv_cnt = prof["spmv"]
+    spmv_bytes = M * (28 * (4 + 8) + 8 + 8 + 8)
+    spmv_gbs = spmv_bytes / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else None
     out = {
         "metric": "node-steps/s + ELL SpMV HBM GB/s, mixed/batched vs FP64 at rel err 1e-8",
         "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -236,18 +261,27 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"lid-driven cavity Re={args.re:g} dt={args.dt:g} h=1/{args.K} "
                                f"(N={N} V + M={M} P nodes, jitter {args.jitter}h), "
-                               "28-point PHS r^7 + cubic, FP64 BiCGSTAB",
+                               "28-point PHS r^7 + cubic, FP64 BiCGSTAB with the lattice "
+                               "fast-Poisson preconditioner",
                    "poisson_rtol": args.rtol_p, "helmholtz_rtol": args.rtol_h,
                    "setup_s": setup_s,
                    "poisson_iters_per_step": stats.poisson_iters / max(1, args.steps),
                    "helmholtz_iters_per_step": stats.helmholtz_iters / max(1, args.steps),
                    "last_poisson_rel_residual": stats.last_poisson.rel_residual,
                    "u_abs_max": umax},
-        "roofline": {"kernel": "k_bicg_v<1,28> (pressure-Poisson SpMV in BiCGSTAB)",
-                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                     "avg_us": avg_ms * 1e3, "samples": cnt,
-                     "bytes_per_launch": bytes_launch},
+        "roofline": {"kernel": f"k_pc_gemm<0..3> (preconditioner transforms, FP64 MFMA, "
+                               f"{n}x{n}x{n} each)",
+                     "bound": "mfma", "achieved": gemm_tf, "peak": FP64_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s",
+                     "frac": (gemm_tf / FP64_MFMA_PEAK_TFLOPS) if gemm_tf else None,
+                     "traffic": GEMM_TRAFFIC_BYTES, "avg_us": gemm_ms * 1e3,
+                     "samples": gemm_cnt, "flops_per_launch": gemm_flops},
+        "spmv_roofline": {"kernel": "k_pc_av<28,0> (pressure SpMV v = A p^)", "bound": "hbm",
+                          "achieved": spmv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": (spmv_gbs / HBM_PEAK_GBS) if spmv_gbs else None,
+                          "traffic": SPMV_TRAFFIC_BYTES, "avg_us": spmv_ms * 1e3,
+                          "samples": spmv_cnt,
+                          "bytes_per_launch": spmv_bytes},
     }
     S.close()
     del st

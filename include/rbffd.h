@@ -292,14 +292,23 @@ rbf_status rbf_solve_pressure(rbf_solver *s, const double *rhs, double *p_tilde,
 rbf_status rbf_solver_apply_precond(rbf_solver *s, const double *y, double *z);
 
 /*
- * rbf_solver_profile -- sample the duration of the pressure-Poisson SpMV
- * kernel (v = A p^ inside BiCGSTAB) with HIP events on the solver's stream.
- * Returns, in *avg_ms and *count (nullable host outputs), the average
- * duration and number of samples collected so far; then, if
- * sample_every >= 0, resets the counters and times every sample_every-th
- * launch from now on (0 disables sampling; each sample synchronises once).
+ * rbf_solver_profile -- sample kernel durations of the pressure solve with
+ * HIP events on the solver's stream: slot RBF_PROF_GEMM, the transforms of
+ * the lattice preconditioner (k_pc_gemm, four n x n x n FP64 products per
+ * application, n = K - 1, timed together and counted as four launches);
+ * slot RBF_PROF_SPMV, the Poisson SpMV v = A p^ (k_pc_av, or k_kry_a
+ * without the lattice preconditioner).
+ * Returns in avg_ms[q] and count[q] (nullable host arrays of RBF_PROF_N) the
+ * average duration per launch and the number of launches timed so far; then, if
+ * sample_every >= 0, resets the counters and samples every
+ * sample_every-th iteration from now on (0 disables sampling).  Samples are
+ * event pairs around the launch, read at the solver's next stream
+ * synchronisation (no extra synchronisation).
  * Errors: RBF_E_ARG (NULL solver), RBF_E_DEVICE.
  */
+#define RBF_PROF_GEMM 0
+#define RBF_PROF_SPMV 1
+#define RBF_PROF_N 2
 rbf_status rbf_solver_profile(rbf_solver *s, int32_t sample_every, double *avg_ms,
                               int64_t *count);
 

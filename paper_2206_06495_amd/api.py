@@ -185,13 +185,13 @@ class Solver:
         return z
 
     def profile(self, sample_every=-1):
-        """(avg_ms, count) of the sampled Poisson SpMV launches so far; with
-        sample_every >= 0, reset and sample every sample_every-th launch."""
-        avg = ctypes.c_double()
-        cnt = ctypes.c_int64()
-        check(lib.rbf_solver_profile(self._h, int(sample_every), ctypes.byref(avg),
-                                     ctypes.byref(cnt)))
-        return avg.value, cnt.value
+        """Sampled kernel durations so far: {"gemm": (avg_ms, count),
+        "spmv": (avg_ms, count)}; with sample_every >= 0, reset and sample
+        every sample_every-th pressure iteration from now on."""
+        avg = (ctypes.c_double * 2)()
+        cnt = (ctypes.c_int64 * 2)()
+        check(lib.rbf_solver_profile(self._h, int(sample_every), avg, cnt))
+        return {"gemm": (avg[0], cnt[0]), "spmv": (avg[1], cnt[1])}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -692,7 +692,7 @@ __global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
     const double *B = STAGE == 0 ? L.X : STAGE == 1 ? L.Qi : STAGE == 2 ? L.Zh : L.Q;
     double wsum = 0.0;
     const double h2 = L.h * L.h;
-    const bool owner = rbf::dgemm_tile_16x16<kGemmWaves>(n, A, B, ti, tj, [&](int i, int j, double v) {
+    const bool owner = rbf::mfma_block<double, 1, 1, kGemmWaves, 8>(n, A, B, ti, tj, [&](int i, int j, double v) {
         if constexpr (STAGE == 1) {
             double z = 0.0;
             if (i == 0 && j == 0) *L.mean = v;
@@ -1033,10 +1033,14 @@ struct rbf_solver {
     double *rpart = nullptr;
     int last_iters_h = 0, last_iters_p = 0;
     // optional sampling of the Poisson SpMV duration with HIP events
+    // Sampled kernel durations (rbf_solver_profile): event pairs recorded
+    // around sampled launches, read after the solver's next stream sync.
+    static constexpr int kProfPairs = 64;
     int prof_every = 0;
-    int64_t prof_launches = 0, prof_count = 0;
-    double prof_ms = 0.0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int64_t prof_launches = 0, prof_count[RBF_PROF_N] = {};
+    double prof_ms[RBF_PROF_N] = {};
+    std::vector<hipEvent_t> prof_ev[RBF_PROF_N];
+    int prof_pending[RBF_PROF_N] = {};
     // lattice preconditioner of the pressure system
     bool pc_on = false;
     Lat lat{};
@@ -1048,6 +1052,34 @@ struct rbf_solver {
 };
 
 namespace {
+
+// Start / end of a sampled launch in profiling slot q (no-op when the
+// slot's event pairs are all pending).
+bool prof_begin(rbf_solver *S, int q) {
+    if (S->prof_pending[q] >= rbf_solver::kProfPairs || S->prof_ev[q].empty()) return false;
+    return hipEventRecord(S->prof_ev[q][2 * S->prof_pending[q]], S->st) == hipSuccess;
+}
+void prof_end(rbf_solver *S, int q) {
+    if (hipEventRecord(S->prof_ev[q][2 * S->prof_pending[q] + 1], S->st) == hipSuccess)
+        ++S->prof_pending[q];
+}
+// After a stream synchronisation: accumulate the recorded pairs (a GEMM
+// sample covers the four launches of one preconditioner application).
+constexpr int kProfGemmLaunches = 4;
+void prof_flush(rbf_solver *S) {
+    for (int q = 0; q < RBF_PROF_N; ++q) {
+        const int per = (q == RBF_PROF_GEMM) ? kProfGemmLaunches : 1;
+        for (int e = 0; e < S->prof_pending[q]; ++e) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, S->prof_ev[q][2 * e], S->prof_ev[q][2 * e + 1]) ==
+                hipSuccess) {
+                S->prof_ms[q] += ms;
+                S->prof_count[q] += per;
+            }
+        }
+        S->prof_pending[q] = 0;
+    }
+}
 
 rbf_status dalloc(rbf_solver *S, void **p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes ? bytes : 8);
@@ -1121,22 +1153,16 @@ rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, 
             const int par = it & 1;
             const bool sample =
                 NR == 1 && S->prof_every > 0 && (S->prof_launches++ % S->prof_every) == 0;
-            if (sample) RBF_HIP(hipEventRecord(S->ev0, st));
+            const bool timed = sample && prof_begin(S, RBF_PROF_SPMV);
             KRY(k_kry_a, A, K, x, it, i0, par);
-            if (sample) {
-                RBF_HIP(hipEventRecord(S->ev1, st));
-                RBF_HIP(hipEventSynchronize(S->ev1));
-                float ms = 0.f;
-                RBF_HIP(hipEventElapsedTime(&ms, S->ev0, S->ev1));
-                S->prof_ms += ms;
-                ++S->prof_count;
-            }
+            if (timed) prof_end(S, RBF_PROF_SPMV);
             KRY(k_kry_b, A, K, it, par, tol2);
         }
         RBF_CHECK_LAUNCH();
         RBF_HIP(hipMemcpyAsync(S->hflag, K.flag, NR * sizeof(int), hipMemcpyDeviceToHost, st));
         RBF_HIP(hipMemcpyAsync(S->hflag + kMaxNR, K.iters, NR * sizeof(int), hipMemcpyDeviceToHost, st));
         RBF_HIP(hipStreamSynchronize(st));
+        prof_flush(S);
         done = true;
         bool restart = false;
         int brk_at = it;
@@ -1199,12 +1225,15 @@ rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, 
 
 // One application of the lattice preconditioner's interior solve:
 // Z = Q (Lam^-1 o (Q^-1 X Q^-T)) Q^T, four tiled MFMA products.
-rbf_status pc_apply(rbf_solver *S) {
+rbf_status pc_apply(rbf_solver *S, bool sample = false) {
     const dim3 g(S->lat.ntiles), b(64 * kGemmWaves);
+    // A sample spans the four back-to-back launches (kProfGemmLaunches).
+    const bool timed = sample && prof_begin(S, RBF_PROF_GEMM);
     hipLaunchKernelGGL(k_pc_gemm<0>, g, b, 0, S->st, S->lat);
     hipLaunchKernelGGL(k_pc_gemm<1>, g, b, 0, S->st, S->lat);
     hipLaunchKernelGGL(k_pc_gemm<2>, g, b, 0, S->st, S->lat);
     hipLaunchKernelGGL(k_pc_gemm<3>, g, b, 0, S->st, S->lat);
+    if (timed) prof_end(S, RBF_PROF_GEMM);
     return RBF_OK;
 }
 
@@ -1246,21 +1275,14 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
         const int stop = std::min(maxit + 1, it + batch);
         for (; it < stop; ++it) {
             const int par = it & 1;
+            const bool sample = S->prof_every > 0 && (S->prof_launches++ % S->prof_every) == 0;
             hipLaunchKernelGGL(k_pc_dir, grid, block, 0, st, K, L, x, m, it, i0);
-            if ((rc = pc_apply(S)) != RBF_OK) return rc;
+            if ((rc = pc_apply(S, sample)) != RBF_OK) return rc;
             hipLaunchKernelGGL(k_pc_post, grid, block, 0, st, L, K, K.p[par], K.ph, m, K.partS,
                                K.part1 + nb, nb);
-            const bool sample = S->prof_every > 0 && (S->prof_launches++ % S->prof_every) == 0;
-            if (sample) RBF_HIP(hipEventRecord(S->ev0, st));
+            const bool timed = sample && prof_begin(S, RBF_PROF_SPMV);
             av(0, K.ph, K.v);
-            if (sample) {
-                RBF_HIP(hipEventRecord(S->ev1, st));
-                RBF_HIP(hipEventSynchronize(S->ev1));
-                float ms = 0.f;
-                RBF_HIP(hipEventElapsedTime(&ms, S->ev0, S->ev1));
-                S->prof_ms += ms;
-                ++S->prof_count;
-            }
+            if (timed) prof_end(S, RBF_PROF_SPMV);
             hipLaunchKernelGGL(k_pc_s, grid, block, 0, st, K, L, m, it, i0, tol2);
             if ((rc = pc_apply(S)) != RBF_OK) return rc;
             hipLaunchKernelGGL(k_pc_post, grid, block, 0, st, L, K, K.s, K.sh, m, K.partS,
@@ -1271,6 +1293,7 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
         RBF_HIP(hipMemcpyAsync(S->hflag, K.flag, sizeof(int), hipMemcpyDeviceToHost, st));
         RBF_HIP(hipMemcpyAsync(S->hflag + kMaxNR, K.iters, sizeof(int), hipMemcpyDeviceToHost, st));
         RBF_HIP(hipStreamSynchronize(st));
+        prof_flush(S);
         const int f = S->hflag[0];
         done = (f != 0);
         if (f == 2 && it <= maxit && restarts < 50) {
@@ -1767,17 +1790,23 @@ extern "C" rbf_status rbf_solver_profile(rbf_solver *S, int32_t sample_every, do
                                          int64_t *count) {
     rbf::clear_error();
     RBF_ARG(S, "rbf_solver_profile: NULL solver");
-    if (avg_ms) *avg_ms = S->prof_count ? S->prof_ms / (double)S->prof_count : 0.0;
-    if (count) *count = S->prof_count;
+    for (int q = 0; q < RBF_PROF_N; ++q) {
+        if (avg_ms) avg_ms[q] = S->prof_count[q] ? S->prof_ms[q] / (double)S->prof_count[q] : 0.0;
+        if (count) count[q] = S->prof_count[q];
+    }
     if (sample_every >= 0) {
-        if (sample_every > 0 && !S->ev0) {
-            RBF_HIP(hipEventCreate(&S->ev0));
-            RBF_HIP(hipEventCreate(&S->ev1));
+        if (sample_every > 0 && S->prof_ev[0].empty()) {
+            for (int q = 0; q < RBF_PROF_N; ++q) {
+                S->prof_ev[q].resize(2 * rbf_solver::kProfPairs, nullptr);
+                for (auto &e : S->prof_ev[q]) RBF_HIP(hipEventCreate(&e));
+            }
         }
         S->prof_every = sample_every;
         S->prof_launches = 0;
-        S->prof_count = 0;
-        S->prof_ms = 0.0;
+        for (int q = 0; q < RBF_PROF_N; ++q) {
+            S->prof_count[q] = 0;
+            S->prof_ms[q] = 0.0;
+        }
     }
     return RBF_OK;
 }
@@ -1785,8 +1814,9 @@ extern "C" rbf_status rbf_solver_profile(rbf_solver *S, int32_t sample_every, do
 extern "C" void rbf_solver_destroy(rbf_solver *S) {
     if (!S) return;
     if (S->st) hipStreamSynchronize(S->st);
-    if (S->ev0) hipEventDestroy(S->ev0);
-    if (S->ev1) hipEventDestroy(S->ev1);
+    for (auto &v : S->prof_ev)
+        for (hipEvent_t e : v)
+            if (e) hipEventDestroy(e);
     for (void *p : S->allocs) hipFree(p);
     if (S->hflag) hipHostFree(S->hflag);
     if (S->hred) hipHostFree(S->hred);
