@@ -41,7 +41,7 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 # (profiles/k_pc_gemm_cavity_K400_pmc.md); mean of the four k_pc_gemm
 # stages, and the pressure SpMV k_pc_av<28,0>.  Set to None when the kernel
 # changes until it is measured again.
-GEMM_TRAFFIC_BYTES = 22.58e6
+GEMM_TRAFFIC_BYTES = None
 SPMV_TRAFFIC_BYTES = 61.03e6
 
 

@@ -16,7 +16,9 @@
 // w / (TM TN) (split-K, so the dependent MFMA chain per wave is short).
 // The waves of one sub-tile read the same operand rows as their neighbours
 // in the block, which the CU's L1 serves.  Operands are loaded C k-steps
-// at a time, one chunk ahead of the MFMAs that use them; the S partial tiles are summed through
+// at a time, one chunk ahead of the MFMAs that use them (ONESHOT: the
+// caller guarantees that a wave's share is at most C steps, and all of it
+// is loaded before the first MFMA); the S partial tiles are summed through
 // LDS.  Ragged edges are zero-filled.  The epilogue functor receives
 // (i, j, value) for every in-range element, on the waves with k-share 0;
 // the return value tells the calling wave whether it holds a result.
@@ -46,7 +48,7 @@ struct mfma16<float> {
     static __device__ __forceinline__ int row(int r, int lk) { return 4 * lk + r; }
 };
 
-template <class T, int TM, int TN, int S, int C, class Epi>
+template <class T, int TM, int TN, int S, int C, bool ONESHOT, class Epi>
 __device__ __forceinline__ bool mfma_block(int n, const T *__restrict__ A, const T *__restrict__ B,
                                            int bm, int bn, Epi epi) {
     using M = mfma16<T>;
@@ -74,7 +76,15 @@ __device__ __forceinline__ bool mfma_block(int n, const T *__restrict__ A, const
     acc4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     T a[C], b[C];
     load(s0, a, b);
-    for (int sb = s0; sb < s1; sb += C) {
+    if constexpr (ONESHOT) {
+        // The whole k-share fits in one chunk (per <= C, checked by the
+        // caller): every operand load is in flight before the first MFMA.
+#pragma unroll
+        for (int g = 0; g < C; g += 2) {
+            if (s0 + g < s1) acc0 = M::step(a[g], b[g], acc0);
+            if (g + 1 < C && s0 + g + 1 < s1) acc1 = M::step(a[g + 1], b[g + 1], acc1);
+        }
+    } else for (int sb = s0; sb < s1; sb += C) {
         T an[C], bn_[C];
         if (sb + C < s1) load(sb + C, an, bn_);
 #pragma unroll

@@ -683,8 +683,11 @@ __global__ void __launch_bounds__(kThreads) k_pc_pre(Lat L, const double *__rest
 // of kGemmWaves waves.  STAGE 0: T = Q^-1 X; 1: Zh = (T Q^-T) / eig with
 // the zero mode recorded in *mean and set to 0, and the tile's sum of
 // Zh o What; 2: T = Q Zh; 3: Z = T Q^T (into X).
-constexpr int kGemmWaves = 4;
-template <int STAGE>
+// Split-K factor and chunk: with n <= 4 kGemmWaves kGemmChunk (K <= 449)
+// a wave's whole k-share is loaded before its MFMAs (ONESHOT).
+constexpr int kGemmWaves = 8;
+constexpr int kGemmChunk = 14;
+template <int STAGE, bool ONESHOT>
 __global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
     const int n = L.n, nt = (n + 15) / 16;
     const int ti = (int)(blockIdx.x % nt), tj = (int)(blockIdx.x / nt);
@@ -692,7 +695,7 @@ __global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
     const double *B = STAGE == 0 ? L.X : STAGE == 1 ? L.Qi : STAGE == 2 ? L.Zh : L.Q;
     double wsum = 0.0;
     const double h2 = L.h * L.h;
-    const bool owner = rbf::mfma_block<double, 1, 1, kGemmWaves, 8>(n, A, B, ti, tj, [&](int i, int j, double v) {
+    const bool owner = rbf::mfma_block<double, 1, 1, kGemmWaves, kGemmChunk, ONESHOT>(n, A, B, ti, tj, [&](int i, int j, double v) {
         if constexpr (STAGE == 1) {
             double z = 0.0;
             if (i == 0 && j == 0) *L.mean = v;
@@ -1229,10 +1232,18 @@ rbf_status pc_apply(rbf_solver *S, bool sample = false) {
     const dim3 g(S->lat.ntiles), b(64 * kGemmWaves);
     // A sample spans the four back-to-back launches (kProfGemmLaunches).
     const bool timed = sample && prof_begin(S, RBF_PROF_GEMM);
-    hipLaunchKernelGGL(k_pc_gemm<0>, g, b, 0, S->st, S->lat);
-    hipLaunchKernelGGL(k_pc_gemm<1>, g, b, 0, S->st, S->lat);
-    hipLaunchKernelGGL(k_pc_gemm<2>, g, b, 0, S->st, S->lat);
-    hipLaunchKernelGGL(k_pc_gemm<3>, g, b, 0, S->st, S->lat);
+    const int steps = (S->lat.n + 3) / 4;
+    if ((steps + kGemmWaves - 1) / kGemmWaves <= kGemmChunk) {
+        hipLaunchKernelGGL((k_pc_gemm<0, true>), g, b, 0, S->st, S->lat);
+        hipLaunchKernelGGL((k_pc_gemm<1, true>), g, b, 0, S->st, S->lat);
+        hipLaunchKernelGGL((k_pc_gemm<2, true>), g, b, 0, S->st, S->lat);
+        hipLaunchKernelGGL((k_pc_gemm<3, true>), g, b, 0, S->st, S->lat);
+    } else {
+        hipLaunchKernelGGL((k_pc_gemm<0, false>), g, b, 0, S->st, S->lat);
+        hipLaunchKernelGGL((k_pc_gemm<1, false>), g, b, 0, S->st, S->lat);
+        hipLaunchKernelGGL((k_pc_gemm<2, false>), g, b, 0, S->st, S->lat);
+        hipLaunchKernelGGL((k_pc_gemm<3, false>), g, b, 0, S->st, S->lat);
+    }
     if (timed) prof_end(S, RBF_PROF_GEMM);
     return RBF_OK;
 }
