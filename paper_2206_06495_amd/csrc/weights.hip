@@ -8,9 +8,11 @@
 // One wavefront (64 lanes) solves one system.  Lane i owns row i of the
 // augmented matrix (s = n + K_p <= 64 rows) in registers; LU with partial
 // pivoting runs across lanes: the pivot is found by a butterfly arg-max over
-// the wave, its row is broadcast through LDS, and every other unfinished row
-// eliminates with it (row swaps are virtual: each lane remembers the step at
-// which its row became pivot).  All right-hand sides (one per operator) are
+// the wave, its row is broadcast with v_readlane (scalar operands of the
+// updates), and every other unfinished row eliminates with it (row swaps are
+// virtual: each lane remembers the step at which its row became pivot).
+// The residual of the refinement step recomputes the lane's row of the
+// original matrix instead of keeping a copy in registers.  All right-hand sides (one per operator) are
 // eliminated together.  One step of iterative refinement with a residual
 // accumulated in double-FP64 arithmetic (exact products via fma) brings the
 // solution to within a few ulps of the exact solution of the FP64 system.
@@ -51,18 +53,16 @@ __device__ __forceinline__ double ipow(double b, int n) {
     return t;
 }
 
-// t^a from a table of powers p[0..5] with a runtime exponent a.
-__device__ __forceinline__ double pick_pow(const double (&p)[6], int a) {
-    double r = p[0];
+// t^a (0 <= a <= 5) as the product chain ((t t) t)..., without a table
+// (a table indexed by a runtime exponent would live in scratch memory).
+__device__ __forceinline__ double pow_chain(double t, int a) {
+    double r = 1.0, p = t;
 #pragma unroll
-    for (int i = 1; i < 6; ++i) r = (a == i) ? p[i] : r;
+    for (int i = 1; i <= 5; ++i) {
+        r = (i == a) ? p : r;
+        p = p * t;
+    }
     return r;
-}
-
-__device__ __forceinline__ void powers(double t, int q, double (&p)[6]) {
-    p[0] = 1.0;
-#pragma unroll
-    for (int i = 1; i < 6; ++i) p[i] = (i <= q) ? p[i - 1] * t : 0.0;
 }
 
 // Graded monomial index t -> exponents (a, b): degree d, b = t - d(d+1)/2.
@@ -92,6 +92,29 @@ __device__ __forceinline__ double rhs_poly(int a, int b, int code) {
     return ((a == 2 && b == 0) || (a == 0 && b == 2)) ? 2.0 : 0.0;
 }
 
+// Entry (lane, j) of [A P; P^T 0] (0 beyond s) in local coordinates; sx, sy
+// hold the scaled stencil offsets of all lanes, (xt, yt) this lane's own,
+// (ea, eb) its monomial exponents when n <= lane < s.
+__device__ __forceinline__ double system_entry(int lane, int j, int n, int s, int m, double xt,
+                                               double yt, int ea, int eb, const double *sx,
+                                               const double *sy) {
+    if (lane < n) {
+        if (j < n) {
+            const double ddx = xt - sx[j], ddy = yt - sy[j];
+            const double dd = ddx * ddx + ddy * ddy;
+            return ipow(dd, (m - 1) / 2) * sqrt(dd);
+        }
+        if (j < s) {
+            int ja, jb;
+            mono_exp(j - n, ja, jb);
+            return pow_chain(xt, ja) * pow_chain(yt, jb);
+        }
+        return 0.0;
+    }
+    if (lane < s && j < n) return pow_chain(sx[j], ea) * pow_chain(sy[j], eb);
+    return 0.0;
+}
+
 template <int SMAX>
 __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, int64_t nq,
                                                 const double *__restrict__ xs, int64_t ns,
@@ -99,7 +122,6 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
                                                 OpSet ops, double *__restrict__ w,
                                                 unsigned long long *__restrict__ bad) {
     __shared__ double sx[64], sy[64];
-    __shared__ double prow[SMAX + kMaxOps];
     __shared__ double sol[kMaxOps][SMAX];
     __shared__ int pl[SMAX];
 
@@ -129,53 +151,23 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
     __syncthreads();
 
     // 2. This lane's row of [A P; P^T 0] and its right-hand sides.
+    int ea = 0, eb = 0;
+    if (lane >= n && lane < s) mono_exp(lane - n, ea, eb);
     double a[SMAX], b[kMaxOps];
-    if (lane < n) {
-        double px[6], py[6];
-        powers(xt, q, px);
-        powers(yt, q, py);
 #pragma unroll
-        for (int j = 0; j < SMAX; ++j) {
-            double v = 0.0;
-            if (j < n) {
-                const double ddx = xt - sx[j], ddy = yt - sy[j];
-                const double dd = ddx * ddx + ddy * ddy;
-                v = ipow(dd, (m - 1) / 2) * sqrt(dd);
-            } else if (j < s) {
-                int ea, eb;
-                mono_exp(j - n, ea, eb);
-                v = pick_pow(px, ea) * pick_pow(py, eb);
-            }
-            a[j] = v;
-        }
+    for (int j = 0; j < SMAX; ++j) a[j] = system_entry(lane, j, n, s, m, xt, yt, ea, eb, sx, sy);
+    if (lane < n) {
 #pragma unroll
         for (int o = 0; o < kMaxOps; ++o)
             b[o] = (o < ops.n) ? rhs_phs(xt, yt, m, ops.code[o]) : 0.0;
     } else if (lane < s) {
-        int ea, eb;
-        mono_exp(lane - n, ea, eb);
-#pragma unroll
-        for (int j = 0; j < SMAX; ++j) {
-            double v = 0.0;
-            if (j < n) {
-                double px[6], py[6];
-                powers(sx[j], q, px);
-                powers(sy[j], q, py);
-                v = pick_pow(px, ea) * pick_pow(py, eb);
-            }
-            a[j] = v;
-        }
 #pragma unroll
         for (int o = 0; o < kMaxOps; ++o) b[o] = (o < ops.n) ? rhs_poly(ea, eb, ops.code[o]) : 0.0;
     } else {
 #pragma unroll
-        for (int j = 0; j < SMAX; ++j) a[j] = 0.0;
-#pragma unroll
         for (int o = 0; o < kMaxOps; ++o) b[o] = 0.0;
     }
-    double a0[SMAX], b0[kMaxOps];
-#pragma unroll
-    for (int j = 0; j < SMAX; ++j) a0[j] = a[j];
+    double b0[kMaxOps];
 #pragma unroll
     for (int o = 0; o < kMaxOps; ++o) b0[o] = b[o];
 
@@ -207,25 +199,20 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
             const double pv = readlane_d(a[kk], piv);
             if (!(fabs(pv) > tiny) || !isfinite(pv)) bad_row = true;
             const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
+            const bool elim = (mystep == INT_MAX) && lane != piv;
+            // Rows that do not eliminate use the multiplier 0: fma(-0, p, a)
+            // returns a unchanged for finite p, so no per-entry select.
+            const double l = elim ? a[kk] * inv : 0.0;
             if (lane == piv) {
                 mystep = kk;
                 myinv = inv;
-#pragma unroll
-                for (int j = kk + 1; j < SMAX; ++j) prow[j] = a[j];
-#pragma unroll
-                for (int o = 0; o < kMaxOps; ++o) prow[SMAX + o] = b[o];
                 pl[kk] = lane;
             }
-            __syncthreads();
-            if (mystep == INT_MAX) {
-                const double l = a[kk] * inv;
-                a[kk] = l;  // multiplier, kept for the refinement solve
+            if (elim) a[kk] = l;  // multiplier, kept for the refinement solve
 #pragma unroll
-                for (int j = kk + 1; j < SMAX; ++j) a[j] = fma(-l, prow[j], a[j]);
+            for (int j = kk + 1; j < SMAX; ++j) a[j] = fma(-l, readlane_d(a[j], piv), a[j]);
 #pragma unroll
-                for (int o = 0; o < kMaxOps; ++o) b[o] = fma(-l, prow[SMAX + o], b[o]);
-            }
-            __syncthreads();
+            for (int o = 0; o < kMaxOps; ++o) b[o] = fma(-l, readlane_d(b[o], piv), b[o]);
         }
     }
 
@@ -247,27 +234,37 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
     __syncthreads();
 
     // 5. One refinement step: r = b0 - A0 x in double-FP64, solve with LU.
-    double r[kMaxOps];
+    // Entries are recomputed (same operations as in step 2) one column at a
+    // time; each right-hand side accumulates over j in increasing order.
+    double r[kMaxOps], hi[kMaxOps], lo[kMaxOps];
 #pragma unroll
     for (int o = 0; o < kMaxOps; ++o) {
-        double hi = b0[o], lo = 0.0;
-        if (o < ops.n && lane < s) {
+        hi[o] = b0[o];
+        lo[o] = 0.0;
+    }
+    if (lane < s) {
 #pragma unroll
-            for (int j = 0; j < SMAX; ++j) {
-                if (j < s) {
-                    const double xj = sol[o][j];
-                    const double p = a0[j] * xj;
-                    const double pe = fma(a0[j], xj, -p);
-                    const double t = hi - p;
-                    const double bv = t - hi;
-                    const double err = (hi - (t - bv)) + (-p - bv);
-                    hi = t;
-                    lo = lo + (err - pe);
+        for (int j = 0; j < SMAX; ++j) {
+            if (j < s) {
+                const double aj = system_entry(lane, j, n, s, m, xt, yt, ea, eb, sx, sy);
+#pragma unroll
+                for (int o = 0; o < kMaxOps; ++o) {
+                    if (o < ops.n) {
+                        const double xj = sol[o][j];
+                        const double p = aj * xj;
+                        const double pe = fma(aj, xj, -p);
+                        const double t = hi[o] - p;
+                        const double bv = t - hi[o];
+                        const double err = (hi[o] - (t - bv)) + (-p - bv);
+                        hi[o] = t;
+                        lo[o] = lo[o] + (err - pe);
+                    }
                 }
             }
         }
-        r[o] = hi + lo;
     }
+#pragma unroll
+    for (int o = 0; o < kMaxOps; ++o) r[o] = hi[o] + lo[o];
     // Forward substitution with the stored multipliers (virtual pivoting).
 #pragma unroll
     for (int kk = 0; kk < SMAX; ++kk) {
