@@ -189,20 +189,31 @@ typedef struct {
     double rtol_p;    /* relative residual tolerance, pressure Poisson solve */
     int32_t maxit_h;  /* iteration caps                                      */
     int32_t maxit_p;
-    int32_t precision;/* 0 = FP64 (only value accepted)                      */
+    int32_t precision;/* RBF_PRECISION_*                                     */
     int32_t precond;  /* pressure-solve preconditioner, RBF_PRECOND_*        */
 } rbf_params;
+
+/* rbf_params.precision:
+ * FP64   every stage in FP64;
+ * MIXED  the lattice preconditioner's transforms and tridiagonal solves
+ *        stored in FP32 (FP32 matrix cores); operators, residuals, the
+ *        Krylov iteration, the weights and the projection stay FP64, so the
+ *        tolerance still refers to the FP64 residual (the fields differ from
+ *        FP64 runs at the tolerance level). */
+#define RBF_PRECISION_FP64 0
+#define RBF_PRECISION_MIXED 1
 
 /* rbf_params.precond:
  * AUTO     the lattice preconditioner when the P-nodes form a jittered
  *          (K+1)^2 lattice of the unit square (the cavity layout of
- *          rbf_build_nodes), none otherwise;
+ *          rbf_build_nodes) with K <= 513, none otherwise;
  * NONE     unpreconditioned BiCGSTAB on the row-scaled system;
  * LATTICE  the lattice preconditioner, RBF_E_ARG if the P-nodes are not
- *          such a lattice.
+ *          such a lattice or K > 513.
  * The lattice preconditioner is the 5-point Laplacian of the unjittered
- * lattice with one-sided Neumann rows, inverted exactly by a fast
- * (DCT-II) Poisson solve, followed by bilinear interpolation to the node
+ * lattice with one-sided Neumann rows, inverted exactly by a fast Poisson
+ * solve (DCT-II along x as dense products on the matrix cores, tridiagonal
+ * solves along y), followed by bilinear interpolation to the node
  * positions.  It changes only the iteration, not the system solved. */
 #define RBF_PRECOND_AUTO 0
 #define RBF_PRECOND_NONE 1
@@ -252,7 +263,7 @@ typedef struct rbf_solver rbf_solver;
  * prm->precond; the Poisson tolerance applies to the row-scaled system.
  * u_bc, v_bc: device [n_v] boundary velocities (read on wall rows; copied).
  * The solver keeps `st` for all of its work.
- * Errors: RBF_E_ARG (NULL pointers, sizes, dt/re <= 0, precision != 0,
+ * Errors: RBF_E_ARG (NULL pointers, sizes, dt/re <= 0, unknown precision,
  * unknown precond, RBF_PRECOND_LATTICE on a non-lattice P-grid, a self
  * index missing from a (V,V) or (P,P) stencil, no interior P node),
  * RBF_E_NOMEM, RBF_E_DEVICE.
@@ -292,18 +303,18 @@ rbf_status rbf_solve_pressure(rbf_solver *s, const double *rhs, double *p_tilde,
 rbf_status rbf_solver_apply_precond(rbf_solver *s, const double *y, double *z);
 
 /*
- * rbf_solver_profile -- sample kernel durations of the pressure solve with
- * HIP events on the solver's stream: slot RBF_PROF_GEMM, the transforms of
- * the lattice preconditioner (k_pc_gemm, four n x n x n FP64 products per
- * application, n = K - 1, timed together and counted as four launches);
- * slot RBF_PROF_SPMV, the Poisson SpMV v = A p^ (k_pc_av, or k_kry_a
- * without the lattice preconditioner).
- * Returns in avg_ms[q] and count[q] (nullable host arrays of RBF_PROF_N) the
- * average duration per launch and the number of launches timed so far; then, if
- * sample_every >= 0, resets the counters and samples every
- * sample_every-th iteration from now on (0 disables sampling).  Samples are
- * event pairs around the launch, read at the solver's next stream
+ * rbf_solver_profile -- sample kernel durations of the pressure solve on the
+ * solver's stream: slot RBF_PROF_GEMM, the first transform of the lattice
+ * preconditioner (k_pc_gemm<0>, an n x n x n FP64 product, n = K - 1); slot
+ * RBF_PROF_SPMV, the Poisson SpMV v = A p^ (k_pc_av, or k_kry_a without the
+ * lattice preconditioner).  A sampled launch goes through
+ * hipExtLaunchKernelGGL with an event pair that records the kernel's own
+ * start and end; the pairs are read at the solver's next stream
  * synchronisation (no extra synchronisation).
+ * Returns in avg_ms[q] and count[q] (nullable host arrays of RBF_PROF_N) the
+ * average duration per launch and the number of launches timed so far;
+ * then, if sample_every >= 0, resets the counters and samples every
+ * sample_every-th iteration from now on (0 disables sampling).
  * Errors: RBF_E_ARG (NULL solver), RBF_E_DEVICE.
  */
 #define RBF_PROF_GEMM 0

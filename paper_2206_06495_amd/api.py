@@ -119,9 +119,10 @@ class Solver:
     """
 
     PRECOND = {"auto": 0, "none": 1, "lattice": 2}
+    PRECISION = {"fp64": 0, "mixed": 1}
 
     def __init__(self, grid, ops, u_bc, v_bc, re, dt, rtol_h=1e-13, rtol_p=1e-12,
-                 maxit_h=2000, maxit_p=20000, precond="auto"):
+                 maxit_h=2000, maxit_p=20000, precond="auto", precision="fp64"):
         N = grid["xv"].shape[1]
         M = grid["xp"].shape[1]
         self.N, self.M = N, M
@@ -145,7 +146,7 @@ class Solver:
             "idx_vv", "vv_dx", "vv_dy", "vv_lap", "idx_pv", "pv_dx", "pv_dy",
             "idx_pp", "pp_dx", "pp_dy", "pp_lap", "idx_vp", "vp_dx", "vp_dy")])
         prm = _lib.Params(float(re), float(dt), float(rtol_h), float(rtol_p), int(maxit_h),
-                          int(maxit_p), 0, self.PRECOND[precond])
+                          int(maxit_p), self.PRECISION[precision], self.PRECOND[precond])
         h = ctypes.c_void_p()
         check(lib.rbf_solver_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(o),
                                     _ptr(u_bc), _ptr(v_bc), ctypes.byref(prm), _stream()))

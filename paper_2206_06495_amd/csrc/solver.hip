@@ -15,6 +15,8 @@
 #include <utility>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "dgemm_mfma.h"
 #include "ell.h"
@@ -444,36 +446,49 @@ __global__ void __launch_bounds__(kThreads) k_resid(EllM A, const double *__rest
 // the lattice points to the actual node positions.  L5 is inverted exactly:
 // the wall rows give z_w = z_in + |w - in| g_w, which leaves on the (K-1)^2
 // interior nodes the separable operator (T (x) I + I (x) T) / h^2, T the
-// 1-D second difference with Neumann ends, diagonalised by the DCT-II basis
-// Q (T = Q Lam Q^-1).  The two-dimensional transforms Q^-1 X Q^-T and
-// Q Zh Q^T are dense (K-1) x (K-1) FP64 products on the matrix cores
-// (dgemm_mfma.h); the division by the eigenvalues is the epilogue of the
-// second product.  The border fixes the zero mode and the sum of z.
+// 1-D second difference with Neumann ends.  The x-direction is
+// diagonalised by the DCT-II basis Q (T = Q Lam Q^-1): a dense product
+// Q^-1 X on the matrix cores (k_pc_gemm, FP64 MFMA); for each x-mode k the
+// y-direction system (T + lam_k I) w = h^2 t is tridiagonal and is solved by
+// parallel cyclic reduction (k_pc_tri, one workgroup per mode); the product
+// Q W returns to the lattice.  Mode k = 0 is
+// singular: its right-hand side loses its mean (recorded: it fixes the
+// constant through the border), the last unknown is fixed and the solution
+// shifted to zero mean.
 //
 // Interior arrays, n = K - 1, X(a, b) / Z(a, b) belong to lattice node
 // (i, j) = (a + 1, b + 1):
-//   X  reduced right-hand side, row-major  (a n + b)
-//   T  Q^-1 X (column-major), then Q Zh (column-major)
-//   Zh coefficients / eigenvalues, row-major (k n + l)
-//   Z  interior solution, column-major      (a + b n)
+//   X  reduced right-hand side, row-major  (a n + b); then Z, column-major
+//   T  Q^-1 X, column-major (k + b n)
+//   W  tridiagonal solutions, row-major (k n + b)
 // The constant shift needs the lattice sum of the boundary values:
-// sum_w Z(in(w)) = sum_kl Zh(k, l) What(k, l) with What = Q^T w Q (w counts
-// the boundary nodes clamped to each interior node), reduced per tile in the
-// second product, plus sum_w |w - in(w)| g_w, reduced by the kernel that
+// sum_w Z(in(w)) = sum_kb W(k, b) V(k, b) with V = Q^T w (w counts the
+// boundary nodes clamped to each interior node), reduced per block by
+// k_pc_tri per mode, plus sum_w |w - in(w)| g_w, reduced by the kernel that
 // builds X.
+// The transform arrays are FP64, or FP32 when f32 is set (mixed precision:
+// the preconditioner only shapes the iteration, the residuals stay FP64).
 struct Lat {
-    int K, n, ntiles;
+    int K, n, ntiles, f32;
     double h, c;           // spacing; border scale
     const double *rs;      // [M] row scale of the stored Poisson rows
     const int *cell;       // [M] lower-left lattice node of the cell holding the node
     const double *fx, *fy; // [M] bilinear coordinates in that cell
+    const void *Q, *Qi;    // [n * n] column-major
     const double *lam;     // [n] eigenvalues of T (unit spacing)
-    const double *Q, *Qi;  // [n * n] column-major
-    const double *What;    // [n * n] column-major
-    double *X, *T, *Zh;    // [n * n] work (Z overwrites X)
+    const double *V;       // [n * n] boundary weights in (k, b), at b n + k
+    void *X, *T, *W;       // [n * n] work (Z overwrites X)
     double *mean;          // [1] zero-mode coefficient (mean of the reduced rhs)
-    double *partW;         // [ntiles] per-tile sums of Zh o What
+    double *partW;         // [n] per-mode sums of W o V
 };
+
+__device__ __forceinline__ void lat_store(const Lat &L, void *a, int64_t e, double v) {
+    if (L.f32) static_cast<float *>(a)[e] = (float)v;
+    else static_cast<double *>(a)[e] = v;
+}
+__device__ __forceinline__ double lat_load(const Lat &L, const void *a, int64_t e) {
+    return L.f32 ? (double)static_cast<const float *>(a)[e] : static_cast<const double *>(a)[e];
+}
 
 // Preconditioned BiCGSTAB vectors and scalars (one right-hand side).
 // p is double-buffered by iteration parity (the kernel that rewrites it also
@@ -512,7 +527,7 @@ __device__ __forceinline__ double pc_reduce(const Lat &L, int64_t row, double vs
     if (j == 1) wsum += val(row - K1) / L.rs[row - K1];
     if (j == K - 1) wsum += val(row + K1) / L.rs[row + K1];
     g -= wsum / L.h;
-    L.X[(int64_t)(i - 1) * L.n + (j - 1)] = g;
+    lat_store(L, L.X, (int64_t)(i - 1) * L.n + (j - 1), g);
     return 0.0;
 }
 
@@ -679,48 +694,106 @@ __global__ void __launch_bounds__(kThreads) k_pc_pre(Lat L, const double *__rest
     store_partials<1>(acc, partG, gridDim.x);
 }
 
-// The four transforms of the interior solve, one 16x16 tile per workgroup
-// of kGemmWaves waves.  STAGE 0: T = Q^-1 X; 1: Zh = (T Q^-T) / eig with
-// the zero mode recorded in *mean and set to 0, and the tile's sum of
-// Zh o What; 2: T = Q Zh; 3: Z = T Q^T (into X).
+// The two transforms of the interior solve, one 16x16 tile per workgroup of
+// kGemmWaves waves.  STAGE 0: T = Q^-1 X; STAGE 1: Z = Q W (into X).
 // Split-K factor and chunk: with n <= 4 kGemmWaves kGemmChunk (K <= 449)
 // a wave's whole k-share is loaded before its MFMAs (ONESHOT).
 constexpr int kGemmWaves = 8;
 constexpr int kGemmChunk = 14;
-template <int STAGE, bool ONESHOT>
+template <int STAGE, bool ONESHOT, class TP>
 __global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
     const int n = L.n, nt = (n + 15) / 16;
     const int ti = (int)(blockIdx.x % nt), tj = (int)(blockIdx.x / nt);
-    const double *A = STAGE == 0 ? L.Qi : STAGE == 1 ? L.T : STAGE == 2 ? L.Q : L.T;
-    const double *B = STAGE == 0 ? L.X : STAGE == 1 ? L.Qi : STAGE == 2 ? L.Zh : L.Q;
-    double wsum = 0.0;
+    const TP *A = static_cast<const TP *>(STAGE == 0 ? L.Qi : L.Q);
+    const TP *B = static_cast<const TP *>(STAGE == 0 ? L.X : L.W);
+    TP *C = static_cast<TP *>(STAGE == 0 ? L.T : L.X);
+    rbf::mfma_block<TP, 1, 1, kGemmWaves, kGemmChunk, ONESHOT>(
+        n, A, B, ti, tj, [&](int i, int j, TP v) { C[i + (int64_t)j * n] = v; });
+}
+
+// For each x-mode k (one workgroup): (T + lam_k I) w = h^2 t along y by
+// parallel cyclic reduction in LDS (log2 n halving steps, every row
+// updated in parallel; the systems are diagonally dominant).  Mode 0 drops
+// its last row (w_{n-1} = 0) after removing the right-hand side's mean,
+// then is shifted to zero mean.  Writes W row-major and the block's sum of
+// W o V into partW[k].
+constexpr int kTriThreads = 512;  // n <= kTriThreads (K <= 513)
+template <class TP>
+__global__ void __launch_bounds__(kTriThreads) k_pc_tri(Lat L) {
+    __shared__ double sa[kTriThreads], sb[kTriThreads], sc[kTriThreads], sd[kTriThreads];
+    __shared__ double red[kTriThreads / 64];
+    const int n = L.n, k = blockIdx.x, i = threadIdx.x;
     const double h2 = L.h * L.h;
-    const bool owner = rbf::mfma_block<double, 1, 1, kGemmWaves, kGemmChunk, ONESHOT>(n, A, B, ti, tj, [&](int i, int j, double v) {
-        if constexpr (STAGE == 1) {
-            double z = 0.0;
-            if (i == 0 && j == 0) *L.mean = v;
-            else z = v * h2 / (L.lam[i] + L.lam[j]);
-            L.Zh[(int64_t)i * n + j] = z;
-            wsum += z * L.What[i + (int64_t)j * n];
-        } else if constexpr (STAGE == 3) {
-            L.X[i + (int64_t)j * n] = v;
-        } else {
-            L.T[i + (int64_t)j * n] = v;
-        }
-    });
-    if constexpr (STAGE == 1) {
-        if (owner) {
-            wsum = rbf::wave_sum(wsum);
-            if ((threadIdx.x & 63) == 0) L.partW[blockIdx.x] = wsum;
-        }
+    const TP *T = static_cast<const TP *>(L.T);
+    const double lamk = L.lam[k];
+    const double t = (i < n) ? (double)T[k + (int64_t)i * n] : 0.0;
+    const int size = (k == 0) ? n - 1 : n;
+    double shift = 0.0;
+    if (k == 0) {  // block-uniform branch
+        double v[1] = {t};
+        rbf::block_sum<1>(v, red);
+        shift = v[0] / n;
+        if (i == 0) *L.mean = shift;
     }
+    if (i < size) {
+        const bool end = (i == 0) || (i == n - 1);
+        sa[i] = (i == 0) ? 0.0 : 1.0;
+        sc[i] = (i == size - 1) ? 0.0 : 1.0;
+        sb[i] = (end ? -1.0 : -2.0) + lamk;
+        sd[i] = h2 * (t - shift);
+    }
+    __syncthreads();
+    for (int st = 1; st < size; st <<= 1) {
+        double a2 = 0.0, b2 = 1.0, c2 = 0.0, d2 = 0.0;
+        if (i < size) {
+            const double ai = sa[i], bi = sb[i], ci = sc[i], di = sd[i];
+            double al = 0.0, ga = 0.0;
+            a2 = 0.0;
+            c2 = 0.0;
+            b2 = bi;
+            d2 = di;
+            if (i - st >= 0) {
+                al = -ai / sb[i - st];
+                a2 = al * sa[i - st];
+                b2 += al * sc[i - st];
+                d2 += al * sd[i - st];
+            }
+            if (i + st < size) {
+                ga = -ci / sb[i + st];
+                c2 = ga * sc[i + st];
+                b2 += ga * sa[i + st];
+                d2 += ga * sd[i + st];
+            }
+        }
+        __syncthreads();
+        if (i < size) {
+            sa[i] = a2;
+            sb[i] = b2;
+            sc[i] = c2;
+            sd[i] = d2;
+        }
+        __syncthreads();
+    }
+    double z = (i < size) ? sd[i] / sb[i] : 0.0;
+    if (k == 0) {
+        double v[1] = {z};
+        rbf::block_sum<1>(v, red);
+        if (i < n) z -= v[0] / n;
+    }
+    double zv[1] = {0.0};
+    if (i < n) {
+        static_cast<TP *>(L.W)[(int64_t)k * n + i] = (TP)z;
+        zv[0] = z * L.V[(int64_t)i * n + k];
+    }
+    rbf::block_sum<1>(zv, red);
+    if (i == 0) L.partW[k] = zv[0];
 }
 
 // Lattice value of L5^-1 at node (i, j), before the constant shift (Z in X).
 __device__ __forceinline__ double pc_lattice(const Lat &L, const double *y, int i, int j) {
     const int K = L.K;
     const int ci = min(max(i, 1), K - 1), cj = min(max(j, 1), K - 1);
-    double z = L.X[(int64_t)(ci - 1) + (int64_t)(cj - 1) * L.n];
+    double z = lat_load(L, L.X, (int64_t)(ci - 1) + (int64_t)(cj - 1) * L.n);
     const bool bi = (i == 0 || i == K), bj = (j == 0 || j == K);
     if (bi || bj) {
         const int64_t node = (int64_t)j * (K + 1) + i;
@@ -733,7 +806,7 @@ __device__ __forceinline__ double pc_lattice(const Lat &L, const double *y, int 
 // out = J (zl + alpha) at every node; alpha makes the lattice sum equal to
 // the value the border prescribes (mean / c): the interior part of the
 // lattice solution has zero sum (no zero mode), the boundary part is
-// reduced from the partials of k_pc_gemm<1> (partW) and of the kernel that
+// reduced from the partials of k_pc_tri (partW) and of the kernel that
 // built X (partG, nbG blocks).  Writes block partials of sum(out).
 __global__ void __launch_bounds__(kThreads) k_pc_post(Lat L, PKry K, const double *__restrict__ y,
                                                        double *__restrict__ out, int64_t m,
@@ -742,7 +815,7 @@ __global__ void __launch_bounds__(kThreads) k_pc_post(Lat L, PKry K, const doubl
     if (K.flag[0] != 0) return;
     const int Kl = L.K;
     double bw[1], bg[1];
-    load_partials<1>(L.partW, L.ntiles, bw);
+    load_partials<1>(L.partW, L.n, bw);
     load_partials<1>(partG, nbG, bg);
     const double alpha = (*L.mean / L.c - (bw[0] + bg[0])) / (double)m;
     double acc[1] = {0.0};
@@ -1046,6 +1119,7 @@ struct rbf_solver {
     int prof_pending[RBF_PROF_N] = {};
     // lattice preconditioner of the pressure system
     bool pc_on = false;
+    bool mixed = false;  // RBF_PRECISION_MIXED
     Lat lat{};
     PKry pk{};
     // pinned host buffers
@@ -1056,22 +1130,20 @@ struct rbf_solver {
 
 namespace {
 
-// Start / end of a sampled launch in profiling slot q (no-op when the
-// slot's event pairs are all pending).
-bool prof_begin(rbf_solver *S, int q) {
+// Event pair for a sampled launch in profiling slot q (false when the
+// slot's pairs are all pending).  The launch is made with
+// hipExtLaunchKernelGGL, which stamps the kernel's own start and end.
+bool prof_pair(rbf_solver *S, int q, hipEvent_t &e0, hipEvent_t &e1) {
     if (S->prof_pending[q] >= rbf_solver::kProfPairs || S->prof_ev[q].empty()) return false;
-    return hipEventRecord(S->prof_ev[q][2 * S->prof_pending[q]], S->st) == hipSuccess;
+    e0 = S->prof_ev[q][2 * S->prof_pending[q]];
+    e1 = S->prof_ev[q][2 * S->prof_pending[q] + 1];
+    ++S->prof_pending[q];
+    return true;
 }
-void prof_end(rbf_solver *S, int q) {
-    if (hipEventRecord(S->prof_ev[q][2 * S->prof_pending[q] + 1], S->st) == hipSuccess)
-        ++S->prof_pending[q];
-}
-// After a stream synchronisation: accumulate the recorded pairs (a GEMM
-// sample covers the four launches of one preconditioner application).
-constexpr int kProfGemmLaunches = 4;
+// After a stream synchronisation: accumulate the recorded pairs.
 void prof_flush(rbf_solver *S) {
     for (int q = 0; q < RBF_PROF_N; ++q) {
-        const int per = (q == RBF_PROF_GEMM) ? kProfGemmLaunches : 1;
+        const int per = 1;
         for (int e = 0; e < S->prof_pending[q]; ++e) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, S->prof_ev[q][2 * e], S->prof_ev[q][2 * e + 1]) ==
@@ -1156,9 +1228,15 @@ rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, 
             const int par = it & 1;
             const bool sample =
                 NR == 1 && S->prof_every > 0 && (S->prof_launches++ % S->prof_every) == 0;
-            const bool timed = sample && prof_begin(S, RBF_PROF_SPMV);
-            KRY(k_kry_a, A, K, x, it, i0, par);
-            if (timed) prof_end(S, RBF_PROF_SPMV);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (sample && prof_pair(S, RBF_PROF_SPMV, e0, e1)) {
+                if (k28) hipExtLaunchKernelGGL((k_kry_a<NR, 28, JAC>), grid, block, 0, st, e0, e1, 0,
+                                               A, K, x, it, i0, par);
+                else hipExtLaunchKernelGGL((k_kry_a<NR, 0, JAC>), grid, block, 0, st, e0, e1, 0,
+                                           A, K, x, it, i0, par);
+            } else {
+                KRY(k_kry_a, A, K, x, it, i0, par);
+            }
             KRY(k_kry_b, A, K, it, par, tol2);
         }
         RBF_CHECK_LAUNCH();
@@ -1227,30 +1305,32 @@ rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, 
 }
 
 // One application of the lattice preconditioner's interior solve:
-// Z = Q (Lam^-1 o (Q^-1 X Q^-T)) Q^T, four tiled MFMA products.
+// T = Q^-1 X, Thomas along y per x-mode, Z = Q W.
 rbf_status pc_apply(rbf_solver *S, bool sample = false) {
     const dim3 g(S->lat.ntiles), b(64 * kGemmWaves);
-    // A sample spans the four back-to-back launches (kProfGemmLaunches).
-    const bool timed = sample && prof_begin(S, RBF_PROF_GEMM);
+    const dim3 gt(S->lat.n), bt(kTriThreads);
+    // A sample times the first product (its own start and end stamps).
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool timed = sample && prof_pair(S, RBF_PROF_GEMM, e0, e1);
     const int steps = (S->lat.n + 3) / 4;
-    if ((steps + kGemmWaves - 1) / kGemmWaves <= kGemmChunk) {
-        hipLaunchKernelGGL((k_pc_gemm<0, true>), g, b, 0, S->st, S->lat);
-        hipLaunchKernelGGL((k_pc_gemm<1, true>), g, b, 0, S->st, S->lat);
-        hipLaunchKernelGGL((k_pc_gemm<2, true>), g, b, 0, S->st, S->lat);
-        hipLaunchKernelGGL((k_pc_gemm<3, true>), g, b, 0, S->st, S->lat);
-    } else {
-        hipLaunchKernelGGL((k_pc_gemm<0, false>), g, b, 0, S->st, S->lat);
-        hipLaunchKernelGGL((k_pc_gemm<1, false>), g, b, 0, S->st, S->lat);
-        hipLaunchKernelGGL((k_pc_gemm<2, false>), g, b, 0, S->st, S->lat);
-        hipLaunchKernelGGL((k_pc_gemm<3, false>), g, b, 0, S->st, S->lat);
-    }
-    if (timed) prof_end(S, RBF_PROF_GEMM);
+    const bool one = (steps + kGemmWaves - 1) / kGemmWaves <= kGemmChunk;
+    auto run = [&](auto tp) {
+        using TP = decltype(tp);
+        if (one) hipExtLaunchKernelGGL((k_pc_gemm<0, true, TP>), g, b, 0, S->st, e0, e1, 0, S->lat);
+        else hipExtLaunchKernelGGL((k_pc_gemm<0, false, TP>), g, b, 0, S->st, e0, e1, 0, S->lat);
+        hipLaunchKernelGGL(k_pc_tri<TP>, gt, bt, 0, S->st, S->lat);
+        if (one) hipLaunchKernelGGL((k_pc_gemm<1, true, TP>), g, b, 0, S->st, S->lat);
+        else hipLaunchKernelGGL((k_pc_gemm<1, false, TP>), g, b, 0, S->st, S->lat);
+    };
+    if (S->lat.f32) run(float{});
+    else run(double{});
+    (void)timed;
     return RBF_OK;
 }
 
 // Right-preconditioned BiCGSTAB on the pressure system (one right-hand side)
 // with the lattice preconditioner; same contract as bicgstab<1, false>.
-// Per iteration: k_pc_dir, P^-1 (4 x k_pc_gemm + k_pc_post),
+// Per iteration: k_pc_dir, P^-1 (k_pc_gemm, k_pc_tri, k_pc_gemm, k_pc_post),
 // k_pc_av (v), k_pc_s, P^-1, k_pc_av (t).
 rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double tol, int maxit,
                      int &last_iters, rbf_solve_stats *stats) {
@@ -1268,12 +1348,12 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
         if (k28) hipLaunchKernelGGL((k_pc_init<28>), grid, block, 0, st, A, b, x, K, partX);
         else hipLaunchKernelGGL((k_pc_init<0>), grid, block, 0, st, A, b, x, K, partX);
     };
-    auto av = [&](int mode, const double *y, double *out) {
+    auto av = [&](int mode, const double *y, double *out, hipEvent_t e0, hipEvent_t e1) {
         if (k28) {
-            if (mode == 0) hipLaunchKernelGGL((k_pc_av<28, 0>), grid, block, 0, st, A, K, y, out);
+            if (mode == 0) hipExtLaunchKernelGGL((k_pc_av<28, 0>), grid, block, 0, st, e0, e1, 0, A, K, y, out);
             else hipLaunchKernelGGL((k_pc_av<28, 1>), grid, block, 0, st, A, K, y, out);
         } else {
-            if (mode == 0) hipLaunchKernelGGL((k_pc_av<0, 0>), grid, block, 0, st, A, K, y, out);
+            if (mode == 0) hipExtLaunchKernelGGL((k_pc_av<0, 0>), grid, block, 0, st, e0, e1, 0, A, K, y, out);
             else hipLaunchKernelGGL((k_pc_av<0, 1>), grid, block, 0, st, A, K, y, out);
         }
     };
@@ -1291,14 +1371,14 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
             if ((rc = pc_apply(S, sample)) != RBF_OK) return rc;
             hipLaunchKernelGGL(k_pc_post, grid, block, 0, st, L, K, K.p[par], K.ph, m, K.partS,
                                K.part1 + nb, nb);
-            const bool timed = sample && prof_begin(S, RBF_PROF_SPMV);
-            av(0, K.ph, K.v);
-            if (timed) prof_end(S, RBF_PROF_SPMV);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (sample) prof_pair(S, RBF_PROF_SPMV, e0, e1);
+            av(0, K.ph, K.v, e0, e1);
             hipLaunchKernelGGL(k_pc_s, grid, block, 0, st, K, L, m, it, i0, tol2);
             if ((rc = pc_apply(S)) != RBF_OK) return rc;
             hipLaunchKernelGGL(k_pc_post, grid, block, 0, st, L, K, K.s, K.sh, m, K.partS,
                                K.partGs, nb);
-            av(1, K.sh, K.t);
+            av(1, K.sh, K.t, nullptr, nullptr);
         }
         RBF_CHECK_LAUNCH();
         RBF_HIP(hipMemcpyAsync(S->hflag, K.flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1416,6 +1496,12 @@ rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
                 "(K+1)^2 lattice of the unit square (row-major, walls tagged)");
         return RBF_OK;
     }
+    if (K - 1 > kTriThreads) {  // the tridiagonal kernel holds one mode per workgroup
+        RBF_ARG(mode != RBF_PRECOND_LATTICE,
+                "rbf_solver_create: RBF_PRECOND_LATTICE supports K <= %d (got K = %d)",
+                kTriThreads + 1, K);
+        return RBF_OK;
+    }
     const int n = K - 1;
     std::vector<double> Q, Qi, lam;
     dct2_basis(n, Q, Qi, lam);
@@ -1429,36 +1515,36 @@ rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
         fx[v] = std::min(std::max(sx - i0, 0.0), 1.0);
         fy[v] = std::min(std::max(sy - j0, 0.0), 1.0);
     }
-    // What = Q^T w Q for the boundary-count weights w(a, b) = [a = 0] +
-    // [a = n-1] + [b = 0] + [b = n-1] + [corner]: with s_l = sum_b Q(b, l),
-    // What(k, l) = (Q(0,k) + Q(n-1,k)) s_l + s_k (Q(0,l) + Q(n-1,l))
-    //            + (Q(0,k) + Q(n-1,k)) (Q(0,l) + Q(n-1,l)).
-    std::vector<double> csum(n, 0.0), edge(n), What((size_t)n * n);
+    // V = Q^T w for the boundary-count weights w(a, b) = [a = 0] + [a = n-1]
+    // + [b = 0] + [b = n-1] + [corner]: with s_k = sum_a Q(a, k) and
+    // e_k = Q(0, k) + Q(n-1, k), V(k, b) = e_k + (s_k + e_k) ([b = 0] + [b = n-1]).
+    std::vector<double> V((size_t)n * n);
     for (int k = 0; k < n; ++k) {
-        for (int a = 0; a < n; ++a) csum[k] += Q[(size_t)a + (size_t)k * n];
-        edge[k] = Q[(size_t)k * n] + Q[(size_t)(n - 1) + (size_t)k * n];
+        double sk = 0.0;
+        for (int a = 0; a < n; ++a) sk += Q[(size_t)a + (size_t)k * n];
+        const double ek = Q[(size_t)k * n] + Q[(size_t)(n - 1) + (size_t)k * n];
+        for (int b = 0; b < n; ++b)
+            V[(size_t)b * n + k] = ek + ((b == 0 || b == n - 1) ? sk + ek : 0.0);
     }
-    for (int l = 0; l < n; ++l)
-        for (int k = 0; k < n; ++k)
-            What[(size_t)k + (size_t)l * n] = edge[k] * csum[l] + csum[k] * edge[l] + edge[k] * edge[l];
     const size_t nn = (size_t)n * n;
     const int nt = (n + 15) / 16;
     Lat &L = S->lat;
     L.ntiles = nt * nt;
+    L.f32 = S->mixed ? 1 : 0;
+    const size_t es = L.f32 ? sizeof(float) : sizeof(double);
     int *dcell;
-    double *dfx, *dfy, *dlam, *dQ, *dQi, *dW;
+    double *dfx, *dfy, *dlam, *dV;
+    void *dQ, *dQi;
     ALLOC(dcell, M);
     ALLOC(dfx, M);
     ALLOC(dfy, M);
     ALLOC(dlam, n);
-    ALLOC(dQ, nn);
-    ALLOC(dQi, nn);
-    ALLOC(dW, nn);
-    ALLOC(L.X, nn);
-    ALLOC(L.T, nn);
-    ALLOC(L.Zh, nn);
+    ALLOC(dV, nn);
+    rbf_status rc;
+    for (void **a : {&dQ, &dQi, &L.X, &L.T, &L.W})
+        if ((rc = dalloc(S, a, nn * es)) != RBF_OK) return rc;
     ALLOC(L.mean, 1);
-    ALLOC(L.partW, L.ntiles);
+    ALLOC(L.partW, n);
     PKry &P = S->pk;
     for (double **q : {&P.r, &P.rh, &P.p[0], &P.p[1], &P.v, &P.s, &P.t, &P.ph, &P.sh}) ALLOC(*q, M);
     ALLOC(P.partI, 2 * kMaxBlocks);
@@ -1477,10 +1563,18 @@ rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
     RBF_HIP(hipMemcpyAsync(dfx, fx.data(), M * sizeof(double), hipMemcpyHostToDevice, st));
     RBF_HIP(hipMemcpyAsync(dfy, fy.data(), M * sizeof(double), hipMemcpyHostToDevice, st));
     RBF_HIP(hipMemcpyAsync(dlam, lam.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
-    RBF_HIP(hipMemcpyAsync(dQ, Q.data(), nn * sizeof(double), hipMemcpyHostToDevice, st));
-    RBF_HIP(hipMemcpyAsync(dQi, Qi.data(), nn * sizeof(double), hipMemcpyHostToDevice, st));
-    RBF_HIP(hipMemcpyAsync(dW, What.data(), nn * sizeof(double), hipMemcpyHostToDevice, st));
-    RBF_HIP(hipMemsetAsync(L.X, 0, nn * sizeof(double), st));
+    RBF_HIP(hipMemcpyAsync(dV, V.data(), nn * sizeof(double), hipMemcpyHostToDevice, st));
+    std::vector<float> Qf, Qif;
+    const void *hQ = Q.data(), *hQi = Qi.data();
+    if (L.f32) {  // transform matrices rounded to FP32
+        Qf.assign(Q.begin(), Q.end());
+        Qif.assign(Qi.begin(), Qi.end());
+        hQ = Qf.data();
+        hQi = Qif.data();
+    }
+    RBF_HIP(hipMemcpyAsync(dQ, hQ, nn * es, hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(dQi, hQi, nn * es, hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemsetAsync(L.X, 0, nn * es, st));
     RBF_HIP(hipMemsetAsync(P.flag, 0, sizeof(int), st));
     RBF_HIP(hipStreamSynchronize(st));
     L.K = K;
@@ -1491,10 +1585,10 @@ rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
     L.cell = dcell;
     L.fx = dfx;
     L.fy = dfy;
-    L.lam = dlam;
     L.Q = dQ;
     L.Qi = dQi;
-    L.What = dW;
+    L.lam = dlam;
+    L.V = dV;
     S->pc_on = true;
     return RBF_OK;
 }
@@ -1524,6 +1618,7 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     S->rtol_p = prm->rtol_p;
     S->maxit_h = prm->maxit_h;
     S->maxit_p = prm->maxit_p;
+    S->mixed = (prm->precision == RBF_PRECISION_MIXED);
     const int64_t kN = (int64_t)k * N, kM = (int64_t)k * M;
     ALLOC(S->idx_vv, kN);
     ALLOC(S->idx_pv, kM);
@@ -1706,7 +1801,8 @@ extern "C" rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, 
     RBF_ARG(prm->maxit_h >= 1 && prm->maxit_p >= 1 && prm->maxit_h <= 1000000 &&
                 prm->maxit_p <= 1000000,
             "rbf_solver_create: iteration caps out of range");
-    RBF_ARG(prm->precision == 0, "rbf_solver_create: only precision 0 (FP64) is supported");
+    RBF_ARG(prm->precision == RBF_PRECISION_FP64 || prm->precision == RBF_PRECISION_MIXED,
+            "rbf_solver_create: unknown precision %d", prm->precision);
     RBF_ARG(prm->precond == RBF_PRECOND_AUTO || prm->precond == RBF_PRECOND_NONE ||
                 prm->precond == RBF_PRECOND_LATTICE,
             "rbf_solver_create: unknown precond %d", prm->precond);

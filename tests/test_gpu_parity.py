@@ -196,12 +196,14 @@ def _gpu_solver(P, nd, gpu, re, dt, **kw):
     return S, ops, u_bc, v_bc
 
 
-def test_cavity_parity_small_workload(P, gpu):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cavity_parity_small_workload(P, gpu, precision):
     """K=40 cavity (N=4880, M=1681), Re=100, dt=2e-3, 200 steps: GPU BiCGSTAB
-    against the oracle's LU, u, v, p within 1e-10 every 20 steps."""
-    _say("cavity parity K=40")
+    against the oracle's LU, u, v, p within 1e-10 every 20 steps (mixed: FP32
+    preconditioner transforms, FP64 residuals, same bar)."""
+    _say("cavity parity K=40", precision)
     nd = ri.cavity_nodes(40, 0.3, 0)
-    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 2e-3)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 2e-3, precision=precision)
     orc = ocav.CavityOracle(nd, u_bc, v_bc, 100.0, 2e-3)
     s0 = orc.initial_state()
     st = S.new_state(to_dev(s0.u, gpu), to_dev(s0.v, gpu))
@@ -311,17 +313,20 @@ def _lattice_precond_reference(nd, ops, y):
             + fy * ((1 - fx) * z(i0, j0 + 1) + fx * z(i0 + 1, j0 + 1)))
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-5)])
 @pytest.mark.parametrize("K", [12, 23, 40])
-def test_lattice_preconditioner_matches_its_definition(P, gpu, K):
+def test_lattice_preconditioner_matches_its_definition(P, gpu, K, precision, tol):
     """One application of P^-1 through the C ABI against the dense statement
-    (K=23: interior size 22, a ragged 16x16 tiling)."""
-    _say("apply_precond K=", K)
+    (K=23: interior size 22, a ragged 16x16 tiling).  Mixed precision runs
+    the transforms in FP32: the bound is a few hundred FP32 roundings."""
+    _say("apply_precond K=", K, precision)
     nd = ri.cavity_nodes(K, 0.3, 4)
-    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 1e-3, precond="lattice")
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 1e-3, precond="lattice",
+                                     precision=precision)
     y = ri.random_vector(nd.n_p, 11)
     z = S.apply_precond(to_dev(y, gpu)).cpu().numpy()
     ref = _lattice_precond_reference(nd, ops, y)
-    assert rel_err(z, ref) <= 1e-12
+    assert rel_err(z, ref) <= tol
     S.close()
 
 
