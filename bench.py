@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--cpu-K", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--prof-every", type=int, default=25)
-    ap.add_argument("--rtol-p", type=float, default=1e-10)
+    ap.add_argument("--rtol-p", type=float, default=1e-12)
     ap.add_argument("--rtol-h", type=float, default=1e-12)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy first (HBM counter calibration)")

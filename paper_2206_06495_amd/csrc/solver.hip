@@ -1065,6 +1065,16 @@ __global__ void k_build_poisson(int64_t m, int k, const int *__restrict__ idx,
     dinv[r] = 1.0;
 }
 
+// Warm start of the pressure solve by linear extrapolation in time:
+// x0 = 2 x_j - x_{j-1}; x_{j-1} <- x_j.
+__global__ void k_extrapolate(int64_t n, double *__restrict__ x, double *__restrict__ xprev) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const double t = x[r];
+    x[r] = 2.0 * t - xprev[r];
+    xprev[r] = t;
+}
+
 // rhs_scaled = rowscale o rhs (for rbf_solve_pressure).
 __global__ void k_scale(int64_t n, const double *__restrict__ sc, const double *__restrict__ a,
                         double *__restrict__ b) {
@@ -1094,7 +1104,9 @@ struct rbf_solver {
     double *vv_dx = nullptr, *vv_dy = nullptr, *vv_lap = nullptr, *pv_dx = nullptr,
            *pv_dy = nullptr, *pp_lap = nullptr, *vp_dx = nullptr, *vp_dy = nullptr;
     double *h_w = nullptr, *h_dinv = nullptr, *p_w = nullptr, *p_dinv = nullptr,
-           *p_rowscale = nullptr, *p_rhs_tmp = nullptr, *p_u1 = nullptr, *p_warm = nullptr;
+           *p_rowscale = nullptr, *p_rhs_tmp = nullptr, *p_u1 = nullptr, *p_warm = nullptr,
+           *p_prev = nullptr;
+    bool have_prev = false;  // p_prev holds the previous solution (within one rbf_step call)
     double p_vscale = 0.0;
     int8_t *p_tag = nullptr;
     int *wall_rows = nullptr;
@@ -1639,6 +1651,7 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     ALLOC(S->p_rowscale, M);
     ALLOC(S->p_u1, M);
     ALLOC(S->p_warm, M);
+    ALLOC(S->p_prev, M);
     ALLOC(S->p_rhs_tmp, M);
     ALLOC(S->p_tag, M);
     ALLOC(S->u_bc, N);
@@ -1747,6 +1760,15 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
                            S->pv_dy, S->uvss, S->uvss + N, S->p_tag, 1.0 / S->dt,
                            S->p_rowscale, S->prhs);
     });
+    // Initial guess: the previous solution, linearly extrapolated in time
+    // from the two previous steps of this call when available.
+    if (S->have_prev) {
+        hipLaunchKernelGGL(k_extrapolate, dim3(rbf::blocks_for(M, 256)), dim3(256), 0, st, M,
+                           S->p_warm, S->p_prev);
+    } else {
+        RBF_HIP(hipMemcpyAsync(S->p_prev, S->p_warm, M * sizeof(double), hipMemcpyDeviceToDevice, st));
+        S->have_prev = true;
+    }
     rbf_solve_stats ps;
     rc = poisson_solve(S, S->prhs, S->p_warm, &ps);
     if (rc == RBF_OK) {  // p~ = solution minus its mean (zero-mean border)
@@ -1833,6 +1855,7 @@ extern "C" rbf_status rbf_step(rbf_solver *S, int32_t nsteps, rbf_state *state,
     RBF_HIP(hipMemcpyAsync(S->cv, state->cv_prev, nb, hipMemcpyDeviceToDevice, st));
     RBF_HIP(hipMemcpyAsync(S->pt, state->p_tilde, mb, hipMemcpyDeviceToDevice, st));
     RBF_HIP(hipMemcpyAsync(S->p_warm, state->p_tilde, mb, hipMemcpyDeviceToDevice, st));
+    S->have_prev = false;
     RBF_HIP(hipMemcpyAsync(S->p, state->p, mb, hipMemcpyDeviceToDevice, st));
     rbf_status rc = RBF_OK;
     int done = 0;
