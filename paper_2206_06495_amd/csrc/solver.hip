@@ -1065,14 +1065,23 @@ __global__ void k_build_poisson(int64_t m, int k, const int *__restrict__ idx,
     dinv[r] = 1.0;
 }
 
-// Warm start of the pressure solve by linear extrapolation in time:
-// x0 = 2 x_j - x_{j-1}; x_{j-1} <- x_j.
-__global__ void k_extrapolate(int64_t n, double *__restrict__ x, double *__restrict__ xprev) {
+// Warm start of the pressure solve by extrapolation in time from the
+// previous solutions: ORDER 1: x0 = 2 x_j - x_{j-1}; ORDER 2:
+// x0 = 3 x_j - 3 x_{j-1} + x_{j-2}; the history shifts by one step.
+template <int ORDER>
+__global__ void k_extrapolate(int64_t n, double *__restrict__ x, double *__restrict__ x1,
+                              double *__restrict__ x2) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const double t = x[r];
-    x[r] = 2.0 * t - xprev[r];
-    xprev[r] = t;
+    const double t = x[r], t1 = x1[r];
+    if constexpr (ORDER == 2) {
+        x[r] = 3.0 * t - 3.0 * t1 + x2[r];
+        x2[r] = t1;
+    } else {
+        x[r] = 2.0 * t - t1;
+        x2[r] = t1;
+    }
+    x1[r] = t;
 }
 
 // rhs_scaled = rowscale o rhs (for rbf_solve_pressure).
@@ -1105,8 +1114,8 @@ struct rbf_solver {
            *pv_dy = nullptr, *pp_lap = nullptr, *vp_dx = nullptr, *vp_dy = nullptr;
     double *h_w = nullptr, *h_dinv = nullptr, *p_w = nullptr, *p_dinv = nullptr,
            *p_rowscale = nullptr, *p_rhs_tmp = nullptr, *p_u1 = nullptr, *p_warm = nullptr,
-           *p_prev = nullptr;
-    bool have_prev = false;  // p_prev holds the previous solution (within one rbf_step call)
+           *p_prev = nullptr, *p_prev2 = nullptr;
+    int have_prev = 0;  // previous solutions held in p_prev, p_prev2 (within one rbf_step call)
     double p_vscale = 0.0;
     int8_t *p_tag = nullptr;
     int *wall_rows = nullptr;
@@ -1652,6 +1661,7 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     ALLOC(S->p_u1, M);
     ALLOC(S->p_warm, M);
     ALLOC(S->p_prev, M);
+    ALLOC(S->p_prev2, M);
     ALLOC(S->p_rhs_tmp, M);
     ALLOC(S->p_tag, M);
     ALLOC(S->u_bc, N);
@@ -1762,12 +1772,16 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
     });
     // Initial guess: the previous solution, linearly extrapolated in time
     // from the two previous steps of this call when available.
-    if (S->have_prev) {
-        hipLaunchKernelGGL(k_extrapolate, dim3(rbf::blocks_for(M, 256)), dim3(256), 0, st, M,
-                           S->p_warm, S->p_prev);
+    if (S->have_prev >= 2) {
+        hipLaunchKernelGGL(k_extrapolate<2>, dim3(rbf::blocks_for(M, 256)), dim3(256), 0, st, M,
+                           S->p_warm, S->p_prev, S->p_prev2);
+    } else if (S->have_prev == 1) {
+        hipLaunchKernelGGL(k_extrapolate<1>, dim3(rbf::blocks_for(M, 256)), dim3(256), 0, st, M,
+                           S->p_warm, S->p_prev, S->p_prev2);
+        S->have_prev = 2;
     } else {
         RBF_HIP(hipMemcpyAsync(S->p_prev, S->p_warm, M * sizeof(double), hipMemcpyDeviceToDevice, st));
-        S->have_prev = true;
+        S->have_prev = 1;
     }
     rbf_solve_stats ps;
     rc = poisson_solve(S, S->prhs, S->p_warm, &ps);
@@ -1855,7 +1869,7 @@ extern "C" rbf_status rbf_step(rbf_solver *S, int32_t nsteps, rbf_state *state,
     RBF_HIP(hipMemcpyAsync(S->cv, state->cv_prev, nb, hipMemcpyDeviceToDevice, st));
     RBF_HIP(hipMemcpyAsync(S->pt, state->p_tilde, mb, hipMemcpyDeviceToDevice, st));
     RBF_HIP(hipMemcpyAsync(S->p_warm, state->p_tilde, mb, hipMemcpyDeviceToDevice, st));
-    S->have_prev = false;
+    S->have_prev = 0;
     RBF_HIP(hipMemcpyAsync(S->p, state->p, mb, hipMemcpyDeviceToDevice, st));
     rbf_status rc = RBF_OK;
     int done = 0;
