@@ -13,10 +13,12 @@ Workload (one JSON line on stdout):
     algorithmic bytes; truncation error against closed-form derivatives of
     sin(kx)cos(ky), k = 2 pi {4, 16, 64}.
   * roofline of the dominant kernel of the step: the FP64 MFMA transform
-    k_pc_gemm of the lattice preconditioner (2 n^3 flops per launch,
-    n = K - 1), its average duration sampled with HIP events on the solver's
-    stream during the timed steps; the pressure SpMV k_pc_av (HBM bytes per
-    launch) is reported beside it.
+    k_pc_gemm<0> of the lattice preconditioner (2 n^3 flops per launch,
+    n = K - 1), its average duration sampled with the launch's own start/end
+    stamps on the solver's stream during the timed steps; the pressure SpMV
+    k_pc_av (HBM bytes per launch) is reported beside it.
+  * mixed: the same steps with FP32 preconditioner arrays, and the relative
+    difference of the fields from the FP64 run.
   * cpu_baseline: the CPU oracle (SciPy sparse LU solves) on a bounded
     sample: the same cavity at h = 1/200.
 """
@@ -38,11 +40,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 
 # Traffic beyond L2 per launch at K=400 from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE, scaled by the same counters on a plain 256 MiB copy
-# (profiles/k_pc_gemm_cavity_K400_pmc.md); mean of the four k_pc_gemm
-# stages, and the pressure SpMV k_pc_av<28,0>.  Set to None when the kernel
-# changes until it is measured again.
-GEMM_TRAFFIC_BYTES = None
-SPMV_TRAFFIC_BYTES = 61.03e6
+# (profiles/k_pc_gemm_cavity_K400_pmc.md): k_pc_gemm<0> and the pressure
+# SpMV k_pc_av<28,0>.  Set to None when the kernel changes until it is
+# measured again.
+GEMM_TRAFFIC_BYTES = 21.95e6
+SPMV_TRAFFIC_BYTES = 61.00e6
 
 
 def parse():
