@@ -1084,6 +1084,18 @@ __global__ void k_extrapolate(int64_t n, double *__restrict__ x, double *__restr
     x1[r] = t;
 }
 
+// Initial guess of the viscous solve from the previous solutions h0
+// (latest), h1, h2 (ORDER 1, 2, 3: constant, linear, quadratic in time).
+template <int ORDER>
+__global__ void k_guess(int64_t n, double *__restrict__ x, const double *__restrict__ h0,
+                        const double *__restrict__ h1, const double *__restrict__ h2) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    if constexpr (ORDER == 1) x[r] = h0[r];
+    else if constexpr (ORDER == 2) x[r] = 2.0 * h0[r] - h1[r];
+    else x[r] = 3.0 * h0[r] - 3.0 * h1[r] + h2[r];
+}
+
 // rhs_scaled = rowscale o rhs (for rbf_solve_pressure).
 __global__ void k_scale(int64_t n, const double *__restrict__ sc, const double *__restrict__ a,
                         double *__restrict__ b) {
@@ -1116,6 +1128,8 @@ struct rbf_solver {
            *p_rowscale = nullptr, *p_rhs_tmp = nullptr, *p_u1 = nullptr, *p_warm = nullptr,
            *p_prev = nullptr, *p_prev2 = nullptr;
     int have_prev = 0;  // previous solutions held in p_prev, p_prev2 (within one rbf_step call)
+    double *hh[3] = {nullptr, nullptr, nullptr};  // previous viscous solutions [2][N], latest first
+    int have_h = 0;
     double p_vscale = 0.0;
     int8_t *p_tag = nullptr;
     int *wall_rows = nullptr;
@@ -1662,6 +1676,7 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     ALLOC(S->p_warm, M);
     ALLOC(S->p_prev, M);
     ALLOC(S->p_prev2, M);
+    for (double *&q : S->hh) ALLOC(q, 2 * N);
     ALLOC(S->p_rhs_tmp, M);
     ALLOC(S->p_tag, M);
     ALLOC(S->u_bc, N);
@@ -1749,6 +1764,17 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
         hipLaunchKernelGGL((k_helm_rhs<decltype(KT)::value>), gN, blk, 0, st, N, k, S->idx_vv, S->vv_lap, S->a,
                            S->us, S->vs, S->hrhs, S->uvss);
     });
+    // Initial guess on interior rows: the previous solutions of this call,
+    // extrapolated in time (wall rows get their values below).
+    {
+        const dim3 g2(rbf::blocks_for(2 * N, 256)), b2(256);
+        if (S->have_h >= 3)
+            hipLaunchKernelGGL(k_guess<3>, g2, b2, 0, st, 2 * N, S->uvss, S->hh[0], S->hh[1], S->hh[2]);
+        else if (S->have_h == 2)
+            hipLaunchKernelGGL(k_guess<2>, g2, b2, 0, st, 2 * N, S->uvss, S->hh[0], S->hh[1], S->hh[2]);
+        else if (S->have_h == 1)
+            hipLaunchKernelGGL(k_guess<1>, g2, b2, 0, st, 2 * N, S->uvss, S->hh[0], S->hh[1], S->hh[2]);
+    }
     if (S->nwall > 0)
         hipLaunchKernelGGL(k_wall_rhs, dim3(rbf::blocks_for(S->nwall, kThreads)), blk, 0, st,
                            S->nwall, S->wall_rows, N, k, S->idx_vp, S->vp_dx, S->vp_dy, S->pt,
@@ -1758,6 +1784,12 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
     EllM H{S->idx_vv, S->h_w, S->h_dinv, N, k, nullptr, 0.0};
     rbf_status rc = bicgstab<2, true>(S, S->kh, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h,
                                       S->last_iters_h, hs);
+    if (rc == RBF_OK) {  // history: the oldest buffer takes the new solution
+        RBF_HIP(hipMemcpyAsync(S->hh[2], S->uvss, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+        std::swap(S->hh[1], S->hh[2]);
+        std::swap(S->hh[0], S->hh[1]);
+        S->have_h = std::min(S->have_h + 1, 3);
+    }
     if (stats) {
         stats->last_helmholtz_u = hs[0];
         stats->last_helmholtz_v = hs[1];
@@ -1870,6 +1902,7 @@ extern "C" rbf_status rbf_step(rbf_solver *S, int32_t nsteps, rbf_state *state,
     RBF_HIP(hipMemcpyAsync(S->pt, state->p_tilde, mb, hipMemcpyDeviceToDevice, st));
     RBF_HIP(hipMemcpyAsync(S->p_warm, state->p_tilde, mb, hipMemcpyDeviceToDevice, st));
     S->have_prev = 0;
+    S->have_h = 0;
     RBF_HIP(hipMemcpyAsync(S->p, state->p, mb, hipMemcpyDeviceToDevice, st));
     rbf_status rc = RBF_OK;
     int done = 0;
