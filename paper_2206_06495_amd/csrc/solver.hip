@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(kThreads) k_resid(EllM A, const double *__rest
 // Interior arrays, n = K - 1, X(a, b) / Z(a, b) belong to lattice node
 // (i, j) = (a + 1, b + 1):
 //   X  reduced right-hand side, row-major  (a n + b); then Z, column-major
-//   T  Q^-1 X, column-major (k + b n)
+//   T  Q^-1 X, row-major (k n + b)
 //   W  tridiagonal solutions, row-major (k n + b)
 // The constant shift needs the lattice sum of the boundary values:
 // sum_w Z(in(w)) = sum_kb W(k, b) V(k, b) with V = Q^T w (w counts the
@@ -476,7 +476,7 @@ struct Lat {
     const double *fx, *fy; // [M] bilinear coordinates in that cell
     const void *Q, *Qi;    // [n * n] column-major
     const double *lam;     // [n] eigenvalues of T (unit spacing)
-    const double *V;       // [n * n] boundary weights in (k, b), at b n + k
+    const double *V;       // [n * n] boundary weights in (k, b), at k n + b
     void *X, *T, *W;       // [n * n] work (Z overwrites X)
     double *mean;          // [1] zero-mode coefficient (mean of the reduced rhs)
     double *partW;         // [n] per-mode sums of W o V
@@ -707,8 +707,12 @@ __global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
     const TP *A = static_cast<const TP *>(STAGE == 0 ? L.Qi : L.Q);
     const TP *B = static_cast<const TP *>(STAGE == 0 ? L.X : L.W);
     TP *C = static_cast<TP *>(STAGE == 0 ? L.T : L.X);
+    // T row-major (one mode per row, read whole by k_pc_tri), Z column-major.
     rbf::mfma_block<TP, 1, 1, kGemmWaves, kGemmChunk, ONESHOT>(
-        n, A, B, ti, tj, [&](int i, int j, TP v) { C[i + (int64_t)j * n] = v; });
+        n, A, B, ti, tj, [&](int i, int j, TP v) {
+            if constexpr (STAGE == 0) C[(int64_t)i * n + j] = v;
+            else C[i + (int64_t)j * n] = v;
+        });
 }
 
 // For each x-mode k (one workgroup): (T + lam_k I) w = h^2 t along y by
@@ -726,7 +730,7 @@ __global__ void __launch_bounds__(kTriThreads) k_pc_tri(Lat L) {
     const double h2 = L.h * L.h;
     const TP *T = static_cast<const TP *>(L.T);
     const double lamk = L.lam[k];
-    const double t = (i < n) ? (double)T[k + (int64_t)i * n] : 0.0;
+    const double t = (i < n) ? (double)T[(int64_t)k * n + i] : 0.0;
     const int size = (k == 0) ? n - 1 : n;
     double shift = 0.0;
     if (k == 0) {  // block-uniform branch
@@ -744,22 +748,26 @@ __global__ void __launch_bounds__(kTriThreads) k_pc_tri(Lat L) {
     }
     __syncthreads();
     for (int st = 1; st < size; st <<= 1) {
+        // sb holds 1 / b of every row during the step (one division per row).
         double a2 = 0.0, b2 = 1.0, c2 = 0.0, d2 = 0.0;
+        const double bi = (i < size) ? sb[i] : 1.0;
+        __syncthreads();
+        if (i < size) sb[i] = 1.0 / bi;
+        __syncthreads();
         if (i < size) {
-            const double ai = sa[i], bi = sb[i], ci = sc[i], di = sd[i];
-            double al = 0.0, ga = 0.0;
+            const double ai = sa[i], ci = sc[i], di = sd[i];
             a2 = 0.0;
             c2 = 0.0;
             b2 = bi;
             d2 = di;
             if (i - st >= 0) {
-                al = -ai / sb[i - st];
+                const double al = -ai * sb[i - st];
                 a2 = al * sa[i - st];
                 b2 += al * sc[i - st];
                 d2 += al * sd[i - st];
             }
             if (i + st < size) {
-                ga = -ci / sb[i + st];
+                const double ga = -ci * sb[i + st];
                 c2 = ga * sc[i + st];
                 b2 += ga * sa[i + st];
                 d2 += ga * sd[i + st];
@@ -783,7 +791,7 @@ __global__ void __launch_bounds__(kTriThreads) k_pc_tri(Lat L) {
     double zv[1] = {0.0};
     if (i < n) {
         static_cast<TP *>(L.W)[(int64_t)k * n + i] = (TP)z;
-        zv[0] = z * L.V[(int64_t)i * n + k];
+        zv[0] = z * L.V[(int64_t)k * n + i];
     }
     rbf::block_sum<1>(zv, red);
     if (i == 0) L.partW[k] = zv[0];
@@ -1559,7 +1567,7 @@ rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
         for (int a = 0; a < n; ++a) sk += Q[(size_t)a + (size_t)k * n];
         const double ek = Q[(size_t)k * n] + Q[(size_t)(n - 1) + (size_t)k * n];
         for (int b = 0; b < n; ++b)
-            V[(size_t)b * n + k] = ek + ((b == 0 || b == n - 1) ? sk + ek : 0.0);
+            V[(size_t)k * n + b] = ek + ((b == 0 || b == n - 1) ? sk + ek : 0.0);
     }
     const size_t nn = (size_t)n * n;
     const int nt = (n + 15) / 16;
