@@ -480,6 +480,7 @@ struct Lat {
     void *X, *T, *W;       // [n * n] work (Z overwrites X)
     double *mean;          // [1] zero-mode coefficient (mean of the reduced rhs)
     double *partW;         // [n] per-mode sums of W o V
+    const int *flag;       // iteration flag: the stages exit once it is set
 };
 
 __device__ __forceinline__ void lat_store(const Lat &L, void *a, int64_t e, double v) {
@@ -702,6 +703,7 @@ constexpr int kGemmWaves = 8;
 constexpr int kGemmChunk = 14;
 template <int STAGE, bool ONESHOT, class TP>
 __global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
+    if (*L.flag != 0) return;
     const int n = L.n, nt = (n + 15) / 16;
     const int ti = (int)(blockIdx.x % nt), tj = (int)(blockIdx.x / nt);
     const TP *A = static_cast<const TP *>(STAGE == 0 ? L.Qi : L.Q);
@@ -724,6 +726,7 @@ __global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
 constexpr int kTriThreads = 512;  // n <= kTriThreads (K <= 513)
 template <class TP>
 __global__ void __launch_bounds__(kTriThreads) k_pc_tri(Lat L) {
+    if (*L.flag != 0) return;
     __shared__ double sa[kTriThreads], sb[kTriThreads], sc[kTriThreads], sd[kTriThreads];
     __shared__ double red[kTriThreads / 64];
     const int n = L.n, k = blockIdx.x, i = threadIdx.x;
@@ -1439,7 +1442,10 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
             continue;
         }
         if (!done && it > maxit) break;
-        batch = std::max(2, std::min(16, (it - i0) / 4));
+        // After the first batch (sized by the previous solve) the remaining
+        // iterations are usually few: small batches limit the launches made
+        // after convergence.
+        batch = (it - i0 < 2 * last_iters) ? 2 : std::max(2, std::min(16, (it - i0) / 4));
     }
     if (A.u1) hipLaunchKernelGGL((k_sum<1>), grid, block, 0, st, m, x, partX);
     if (k28) hipLaunchKernelGGL((k_resid<1, 28>), grid, block, 0, st, A, b, x, S->rpart, partX);
@@ -1632,6 +1638,7 @@ rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
     L.Qi = dQi;
     L.lam = dlam;
     L.V = dV;
+    L.flag = P.flag;
     S->pc_on = true;
     return RBF_OK;
 }
