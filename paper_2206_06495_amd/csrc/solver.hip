@@ -279,6 +279,9 @@ __global__ void __launch_bounds__(kThreads) k_kry_a(EllM A, KDev K, double *__re
             om = (rb[1 * NR + c] != 0.0) ? rb[0 * NR + c] / rb[1 * NR + c] : 0.0;
             rho = -om * rb[2 * NR + c];
             be = (rho / pr[0]) * (al / om);
+            // omega = 0 gives rho = 0, which the breakdown test of k_kry_b turns
+            // into a restart; keep the direction finite meanwhile.
+            if (!isfinite(be)) be = 0.0;
             // sum of p' from exact sums of r, p, v (this half) and t (k_kry_b)
             const double srn = ra[2 * NR + c] - al * ra[4 * NR + c] - om * rb[3 * NR + c];
             sp[c] = srn + be * (ra[3 * NR + c] - om * ra[4 * NR + c]);
@@ -293,10 +296,6 @@ __global__ void __launch_bounds__(kThreads) k_kry_a(EllM A, KDev K, double *__re
                 K.rhrh[c] = ra[1 * NR + c];
             } else {
                 K.rec[((int64_t)(i - 1) * NR + c) * 4 + 2] = om;
-                if (!(om != 0.0) || !isfinite(be)) {  // stall: restart after this update
-                    K.flag[c] = 2;
-                    K.iters[c] = i;
-                }
             }
         }
     }
@@ -592,6 +591,7 @@ __global__ void __launch_bounds__(kThreads) k_pc_dir(PKry K, Lat L, double *__re
         om = (q[1] != 0.0) ? q[0] / q[1] : 0.0;
         rho = -om * q[2];  // (rh, s) = 0 by the choice of alpha
         be = (rho / pr[0]) * (al / om);
+        if (!isfinite(be)) be = 0.0;  // omega = 0: rho = 0, restarted by k_pc_s
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             K.rec[(int64_t)(i - 1) * 4 + 2] = om;
             K.rec[(int64_t)i * 4 + 0] = rho;
@@ -883,6 +883,212 @@ __global__ void __launch_bounds__(kThreads) k_pc_av(EllM A, PKry K, const double
     store_partials<NQ>(acc, MODE == 0 ? K.part3 : K.part6, nb);
 }
 
+// ------------------------------------ viscous solve, explicit vectors --
+// Jacobi right-preconditioned BiCGSTAB for the two velocity components at
+// once (stacked [2][N] vectors): the preconditioned directions p^ = D^-1 p
+// and s^ = D^-1 s are written out, so the two products per iteration
+// gather 16 bytes per neighbour.  Same scalar recurrences, flags and
+// deterministic reductions as the pressure iteration, per component.
+constexpr int kHR = 2;
+struct HKry {
+    double *r, *rh, *p[2], *v, *s, *t, *ph, *sh;  // [2][N] each
+    double *partI;  // init: {rho_0 (2), ||b||^2 (2)}
+    double *part1;  // ||r||^2 (2)
+    double *part3;  // (rh, v) (2)
+    double *part6;  // (t, s), (t, t), (rh, t) (2 each)
+    double *rec;    // [iteration][component] {rho, alpha, omega, ||r||^2}
+    double *bb, *rhrh;
+    int *flag, *iters;
+};
+
+__device__ __forceinline__ bool h_done(const int *flag) { return flag[0] != 0 && flag[1] != 0; }
+
+template <int KT>
+__global__ void __launch_bounds__(kThreads) k_h_init(EllM A, const double *__restrict__ b,
+                                                      const double *__restrict__ x, HKry K) {
+    const int nb = gridDim.x;
+    double acc[2 * kHR] = {};
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= A.n) break;
+        if (row < A.n) {
+            double ax[1][kHR] = {};
+            const double *ws[1] = {A.w};
+            rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherN<kHR>{x, A.n}, ax);
+#pragma unroll
+            for (int c = 0; c < kHR; ++c) {
+                const int64_t o = c * A.n + row;
+                const double rr = b[o] - ax[0][c];
+                K.r[o] = rr;
+                K.rh[o] = rr;
+                acc[c] += rr * rr;
+                acc[kHR + c] += b[o] * b[o];
+            }
+        }
+    }
+    store_partials<2 * kHR>(acc, K.partI, nb);
+    if (blockIdx.x == 0 && threadIdx.x < kHR) {
+        K.flag[threadIdx.x] = 0;
+        K.iters[threadIdx.x] = 0;
+    }
+}
+
+// Finish iteration i-1 and build the new direction (see k_pc_dir).
+__global__ void __launch_bounds__(kThreads) k_h_dir(HKry K, const double *__restrict__ dinv,
+                                                     double *__restrict__ x, int64_t n, int i, int i0) {
+    if (h_done(K.flag)) return;
+    const int nb = gridDim.x;
+    const bool first = (i == i0);
+    const int par = i & 1;
+    double al[kHR] = {}, om[kHR] = {}, be[kHR] = {};
+    bool act[kHR];
+    double q[4 * kHR];
+    if (first) load_partials<2 * kHR>(K.partI, nb, *reinterpret_cast<double(*)[2 * kHR]>(q));
+    else load_partials<3 * kHR>(K.part6, nb, *reinterpret_cast<double(*)[3 * kHR]>(q));
+#pragma unroll
+    for (int c = 0; c < kHR; ++c) {
+        act[c] = K.flag[c] == 0;
+        double rho;
+        if (first) {
+            rho = q[c];
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                K.bb[c] = q[kHR + c];
+                K.rhrh[c] = q[c];
+                K.rec[((int64_t)i * kHR + c) * 4] = rho;
+            }
+        } else {
+            const double *pr = K.rec + ((int64_t)(i - 1) * kHR + c) * 4;
+            al[c] = pr[1];
+            const double ts = q[c], tt = q[kHR + c], rt = q[2 * kHR + c];
+            om[c] = (tt != 0.0) ? ts / tt : 0.0;
+            rho = -om[c] * rt;
+            be[c] = (rho / pr[0]) * (al[c] / om[c]);
+            if (!isfinite(be[c])) be[c] = 0.0;  // omega = 0: rho = 0, restarted by k_h_s
+            if (blockIdx.x == 0 && threadIdx.x == 0 && act[c]) {
+                K.rec[((int64_t)(i - 1) * kHR + c) * 4 + 2] = om[c];
+                K.rec[((int64_t)i * kHR + c) * 4] = rho;
+            }
+        }
+    }
+    const double *pold = K.p[par ^ 1];
+    double *pnew = K.p[par];
+    double acc[kHR] = {};
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= n) break;
+        if (row < n) {
+            const double di = dinv[row];
+#pragma unroll
+            for (int c = 0; c < kHR; ++c) {
+                if (!act[c]) continue;
+                const int64_t o = c * n + row;
+                double rn, pn;
+                if (first) {
+                    rn = K.r[o];
+                    pn = rn;
+                } else {
+                    rn = K.s[o] - om[c] * K.t[o];
+                    x[o] = x[o] + al[c] * K.ph[o] + om[c] * K.sh[o];
+                    K.r[o] = rn;
+                    pn = rn + be[c] * (pold[o] - om[c] * K.v[o]);
+                }
+                pnew[o] = pn;
+                K.ph[o] = di * pn;
+                acc[c] += rn * rn;
+            }
+        }
+    }
+    store_partials<kHR>(acc, K.part1, nb);
+}
+
+// out = A y for both components; MODE 0: partials (rh, out) -> part3;
+// MODE 1: (out, s), (out, out), (rh, out) -> part6.
+template <int KT, int MODE>
+__global__ void __launch_bounds__(kThreads) k_h_av(EllM A, HKry K, const double *__restrict__ y,
+                                                    double *__restrict__ out) {
+    if (h_done(K.flag)) return;
+    const int nb = gridDim.x;
+    constexpr int NQ = (MODE == 0 ? 1 : 3) * kHR;
+    double acc[NQ] = {};
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= A.n) break;
+        if (row < A.n) {
+            double ay[1][kHR] = {};
+            const double *ws[1] = {A.w};
+            rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherN<kHR>{y, A.n}, ay);
+#pragma unroll
+            for (int c = 0; c < kHR; ++c) {
+                const int64_t o = c * A.n + row;
+                const double val = ay[0][c];
+                out[o] = val;
+                const double rh = K.rh[o];
+                if constexpr (MODE == 0) {
+                    acc[c] += rh * val;
+                } else {
+                    const double sv = K.s[o];
+                    acc[c] += val * sv;
+                    acc[kHR + c] += val * val;
+                    acc[2 * kHR + c] += rh * val;
+                }
+            }
+        }
+    }
+    store_partials<NQ>(acc, MODE == 0 ? K.part3 : K.part6, nb);
+}
+
+// Convergence test on ||r_i||, alpha, s = r - alpha v and s^ = D^-1 s.
+__global__ void __launch_bounds__(kThreads) k_h_s(HKry K, const double *__restrict__ dinv,
+                                                   int64_t n, int i, double tol2) {
+    if (h_done(K.flag)) return;
+    const int nb = gridDim.x;
+    double q1[kHR], q3[kHR];
+    load_partials<kHR>(K.part1, nb, q1);
+    load_partials<kHR>(K.part3, nb, q3);
+    double al[kHR];
+    bool act[kHR];
+#pragma unroll
+    for (int c = 0; c < kHR; ++c) {
+        act[c] = K.flag[c] == 0;
+        const double rr = q1[c], rv = q3[c];
+        const double rho = K.rec[((int64_t)i * kHR + c) * 4];
+        al[c] = rho / rv;
+        if (!act[c]) continue;
+        const double bb = K.bb[c], rhrh = K.rhrh[c];
+        const bool bad = !isfinite(rr) || !isfinite(rho);
+        const bool conv = !bad && (rr <= tol2 * fmax(bb, 1e-300) || rr == 0.0);
+        const bool brk = !bad && !conv &&
+                         (!(fabs(rho) > kBreakdown * sqrt(rr * rhrh)) || !isfinite(al[c]));
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            double *rc = K.rec + ((int64_t)i * kHR + c) * 4;
+            rc[1] = al[c];
+            rc[3] = rr;
+            if (bad) K.flag[c] = -1;
+            else if (conv || brk) {
+                K.flag[c] = conv ? 1 : 2;
+                K.iters[c] = i;
+            }
+        }
+        if (bad || conv || brk) act[c] = false;
+    }
+    if (!act[0] && !act[1]) return;
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= n) break;
+        if (row < n) {
+            const double di = dinv[row];
+#pragma unroll
+            for (int c = 0; c < kHR; ++c) {
+                if (!act[c]) continue;
+                const int64_t o = c * n + row;
+                const double sv = K.r[o] - al[c] * K.v[o];
+                K.s[o] = sv;
+                K.sh[o] = di * sv;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------- step kernels --
 // Stage 1: C(q) = -(u o D_x q + v o D_y q), u* = u + dt (3/2 C_j - 1/2 C_{j-1}).
 template <int KT>
@@ -1166,6 +1372,7 @@ struct rbf_solver {
     // lattice preconditioner of the pressure system
     bool pc_on = false;
     bool mixed = false;  // RBF_PRECISION_MIXED
+    HKry hk{};           // viscous solve with explicit vectors
     Lat lat{};
     PKry pk{};
     // pinned host buffers
@@ -1478,6 +1685,103 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
     return rc;
 }
 
+// Viscous solve (both components): Jacobi right-preconditioned BiCGSTAB
+// with explicit preconditioned directions; same contract as
+// bicgstab<2, true>.  Per iteration: k_h_dir, k_h_av (v), k_h_s, k_h_av (t).
+rbf_status hbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double tol, int maxit,
+                     int &last_iters, rbf_solve_stats *stats) {
+    hipStream_t st = S->st;
+    HKry &K = S->hk;
+    const int64_t n = A.n;
+    const int nb = nblocks_rows(n);
+    const dim3 grid(nb), block(kThreads);
+    const double tol2 = tol * tol;
+    const bool k28 = A.k == 28;
+    auto init = [&]() {
+        if (k28) hipLaunchKernelGGL((k_h_init<28>), grid, block, 0, st, A, b, x, K);
+        else hipLaunchKernelGGL((k_h_init<0>), grid, block, 0, st, A, b, x, K);
+    };
+    auto av = [&](int mode, const double *y, double *out) {
+        if (k28) {
+            if (mode == 0) hipLaunchKernelGGL((k_h_av<28, 0>), grid, block, 0, st, A, K, y, out);
+            else hipLaunchKernelGGL((k_h_av<28, 1>), grid, block, 0, st, A, K, y, out);
+        } else {
+            if (mode == 0) hipLaunchKernelGGL((k_h_av<0, 0>), grid, block, 0, st, A, K, y, out);
+            else hipLaunchKernelGGL((k_h_av<0, 1>), grid, block, 0, st, A, K, y, out);
+        }
+    };
+    init();
+    int it = 0, i0 = 0, restarts = 0;
+    rbf_status rc = RBF_OK;
+    int batch = std::max(2, last_iters > 0 ? last_iters : 4);
+    bool done = false;
+    while (!done) {
+        const int stop = std::min(maxit + 1, it + batch);
+        for (; it < stop; ++it) {
+            hipLaunchKernelGGL(k_h_dir, grid, block, 0, st, K, A.dinv, x, n, it, i0);
+            av(0, K.ph, K.v);
+            hipLaunchKernelGGL(k_h_s, grid, block, 0, st, K, A.dinv, n, it, tol2);
+            av(1, K.sh, K.t);
+        }
+        RBF_CHECK_LAUNCH();
+        RBF_HIP(hipMemcpyAsync(S->hflag, K.flag, kHR * sizeof(int), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipMemcpyAsync(S->hflag + kMaxNR, K.iters, kHR * sizeof(int), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        prof_flush(S);
+        done = true;
+        bool restart = false;
+        int brk_at = it;
+        for (int c = 0; c < kHR; ++c) {
+            if (S->hflag[c] == 0) done = false;
+            if (S->hflag[c] == 2) {
+                restart = true;
+                brk_at = std::min(brk_at, S->hflag[kMaxNR + c]);
+            }
+        }
+        if (restart && it <= maxit && restarts < 50) {
+            ++restarts;
+            it = i0 = brk_at;
+            init();
+            done = false;
+            continue;
+        }
+        if (!done && it > maxit) break;
+        batch = 2;
+    }
+    if (k28) hipLaunchKernelGGL((k_resid<kHR, 28>), grid, block, 0, st, A, b, x, S->rpart, S->kh.partX);
+    else hipLaunchKernelGGL((k_resid<kHR, 0>), grid, block, 0, st, A, b, x, S->rpart, S->kh.partX);
+    RBF_CHECK_LAUNCH();
+    RBF_HIP(hipMemcpyAsync(S->hred, S->rpart, (size_t)kHR * nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipMemcpyAsync(S->hred + kMaxNR * kMaxBlocks, K.bb, kHR * sizeof(double), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+    int maxi = 0;
+    for (int c = 0; c < kHR; ++c) {
+        double rr = 0.0;
+        for (int bidx = 0; bidx < nb; ++bidx) rr += S->hred[c * nb + bidx];
+        const double bb = S->hred[kMaxNR * kMaxBlocks + c];
+        const int f = S->hflag[c];
+        const int iters = (f == 1) ? S->hflag[kMaxNR + c] : it;
+        maxi = std::max(maxi, iters);
+        if (stats) {
+            stats[c].iterations = iters;
+            stats[c].converged = (f == 1);
+            stats[c].rel_residual = (bb > 0.0) ? std::sqrt(rr / bb) : std::sqrt(rr);
+            stats[c].restarts = restarts;
+            stats[c].final_flag = f;
+        }
+        if (f == -1) {
+            rbf::set_error("BiCGSTAB: non-finite value (rhs %d, iteration %d)", c, it);
+            rc = RBF_E_NAN;
+        } else if ((f == 0 || f == 2) && rc == RBF_OK) {
+            rbf::set_error("BiCGSTAB: no convergence (rhs %d, %d of %d iterations, %d restarts, flag %d)",
+                           c, it, maxit, restarts, f);
+            rc = RBF_E_NOCONV;
+        }
+    }
+    last_iters = maxi;
+    return rc;
+}
+
 // Pressure solve on the row-scaled bordered system (x: guess in, solution out).
 rbf_status poisson_solve(rbf_solver *S, const double *b, double *x, rbf_solve_stats *stats) {
     EllM P{S->idx_pp, S->p_w, nullptr, S->M, S->k, S->p_u1, S->p_vscale};
@@ -1705,6 +2009,20 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     ALLOC(S->rpart, kMaxNR * kMaxBlocks);
     rbf_status rc;
     if ((rc = alloc_krylov(S, S->kh, 2, N, S->maxit_h)) != RBF_OK) return rc;
+    {
+        HKry &H = S->hk;
+        for (double **q : {&H.r, &H.rh, &H.p[0], &H.p[1], &H.v, &H.s, &H.t, &H.ph, &H.sh})
+            ALLOC(*q, kHR * N);
+        ALLOC(H.partI, 2 * kHR * kMaxBlocks);
+        ALLOC(H.part1, kHR * kMaxBlocks);
+        ALLOC(H.part3, kHR * kMaxBlocks);
+        ALLOC(H.part6, 3 * kHR * kMaxBlocks);
+        ALLOC(H.rec, (int64_t)(S->maxit_h + 2) * kHR * 4);
+        ALLOC(H.bb, kHR);
+        ALLOC(H.rhrh, kHR);
+        ALLOC(H.flag, kHR);
+        ALLOC(H.iters, kHR);
+    }
     if ((rc = alloc_krylov(S, S->kp, 1, M, S->maxit_p)) != RBF_OK) return rc;
     RBF_HIP(hipHostMalloc((void **)&S->hflag, 4 * kMaxNR * sizeof(int), hipHostMallocDefault));
     RBF_HIP(hipHostMalloc((void **)&S->hred, (kMaxNR * kMaxBlocks + kMaxNR) * sizeof(double),
@@ -1797,8 +2115,7 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
     RBF_CHECK_LAUNCH();
     rbf_solve_stats hs[2];
     EllM H{S->idx_vv, S->h_w, S->h_dinv, N, k, nullptr, 0.0};
-    rbf_status rc = bicgstab<2, true>(S, S->kh, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h,
-                                      S->last_iters_h, hs);
+    rbf_status rc = hbicgstab(S, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h, S->last_iters_h, hs);
     if (rc == RBF_OK) {  // history: the oldest buffer takes the new solution
         RBF_HIP(hipMemcpyAsync(S->hh[2], S->uvss, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, st));
         std::swap(S->hh[1], S->hh[2]);
