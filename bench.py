@@ -19,6 +19,12 @@ Workload (one JSON line on stdout):
     k_pc_av (HBM bytes per launch) is reported beside it.
   * mixed: the same steps with FP32 preconditioner arrays, and the relative
     difference of the fields from the FP64 run.
+  * batch: `batch` independent cavities, N uniform in [5000, 60000] V-nodes
+    and Re log-uniform in [100, 5000] (dt = 0.08 h), each solver on its own
+    stream, advanced `batch_steps` steps by rbf_step_batch on one host thread
+    (one instance after another) and on `batch_threads` threads (concurrent),
+    from the same states; aggregate node-steps/s of both and whether the
+    fields agree bit for bit.
   * cpu_baseline: the CPU oracle (SciPy sparse LU solves) on a bounded
     sample: the same cavity at h = 1/200.
 """
@@ -68,6 +74,10 @@ def parse():
     ap.add_argument("--prof-every", type=int, default=25)
     ap.add_argument("--rtol-p", type=float, default=1e-12)
     ap.add_argument("--rtol-h", type=float, default=1e-12)
+    ap.add_argument("--batch", type=int, default=64,
+                    help="independent cavities of the concurrent-instance run (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-threads", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy first (HBM counter calibration)")
     return ap.parse_args()
@@ -245,6 +255,73 @@ def mixed_run(P, args, dev, st64, value64):
                     "residuals, Krylov iteration, weights and projection FP64"}
 
 
+def batch_run(P, args, dev):
+    """Concurrent stepping of many small independent cavities."""
+    import torch
+    rng = np.random.default_rng(args.seed + 2206)
+    inst = []
+    t0 = time.perf_counter()
+    for b in range(args.batch):
+        n_target = rng.uniform(5000.0, 60000.0)
+        K = max(8, int(round((-2.0 + math.sqrt(4.0 + 12.0 * n_target)) / 6.0)))  # N = 3K^2 + 2K
+        re = math.exp(rng.uniform(math.log(100.0), math.log(5000.0)))
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            sub = argparse.Namespace(**vars(args))
+            sub.K, sub.re, sub.dt, sub.seed = K, re, 0.08 / K, args.seed + 1 + b
+            S, st, _, _ = cavity_setup(P, sub, dev)
+        inst.append({"S": S, "st0": st, "K": K, "re": re, "stream": s})
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    nodes = sum(x["S"].N + x["S"].M for x in inst)
+    log(f"batch: {len(inst)} cavities, {nodes} nodes, setup {setup_s:.1f}s")
+    solvers = [x["S"] for x in inst]
+
+    def fresh():
+        out = []
+        for x in inst:
+            with torch.cuda.stream(x["stream"]):
+                out.append({k: (v.clone() if isinstance(v, torch.Tensor) else v)
+                            for k, v in x["st0"].items()})
+        torch.cuda.synchronize()
+        return out
+
+    P.step_batch(solvers, fresh(), 2, nthreads=args.batch_threads)  # warm-up
+    res = {}
+    for label, nt in (("sequential", 1), ("concurrent", args.batch_threads)):
+        states = fresh()
+        t0 = time.perf_counter()
+        try:
+            stats, codes = P.step_batch(solvers, states, args.batch_steps, nthreads=nt)
+        except P.RbfError as e:  # an instance that failed keeps its last committed step
+            stats, codes = e.stats, e.statuses
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        done = sum((x["S"].N + x["S"].M) * s.steps_done for x, s in zip(inst, stats))
+        res[label] = (el, states, stats, codes, done)
+        log(f"batch {label} ({nt} threads): {el:.3f}s, {done / el:.3e} node-steps/s")
+    same = all(torch.equal(a[k], b[k]) for a, b in zip(res["sequential"][1], res["concurrent"][1])
+               for k in ("u", "v", "p", "p_tilde", "cu_prev", "cv_prev"))
+    el_s, el_c = res["sequential"][0], res["concurrent"][0]
+    codes = res["concurrent"][3]
+    failed = [{"instance": b, "K": inst[b]["K"], "re": inst[b]["re"], "status": codes[b],
+               "steps_done": res["concurrent"][2][b].steps_done}
+              for b in range(len(inst)) if codes[b] != 0]
+    its = [s.poisson_iters / max(1, s.steps_done) for s in res["concurrent"][2]]
+    for x in inst:
+        x["S"].close()
+    return {"instances": len(inst), "nodes_total": nodes,
+            "K_range": [min(x["K"] for x in inst), max(x["K"] for x in inst)],
+            "re_range": [min(x["re"] for x in inst), max(x["re"] for x in inst)],
+            "steps": args.batch_steps, "threads": args.batch_threads, "setup_s": setup_s,
+            "sequential_node_steps_per_s": res["sequential"][4] / el_s,
+            "concurrent_node_steps_per_s": res["concurrent"][4] / el_c,
+            "speedup": el_s / el_c, "bit_identical": bool(same),
+            "failed": failed,
+            "poisson_iters_per_step_mean": float(np.mean(its)),
+            "what": "independent lattice cavities, one stream each, rbf_step_batch"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -327,6 +404,10 @@ def main():
         out["mixed"] = mixed_run(P, args, dev, st, value)
     del st
     torch.cuda.empty_cache()
+    if args.batch > 0:
+        log("concurrent instances:", args.batch)
+        out["batch"] = batch_run(P, args, dev)
+        torch.cuda.empty_cache()
     if not args.no_spmv:
         log("operator bench K =", args.spmv_K)
         out["spmv"] = spmv_bench(P, args, dev)

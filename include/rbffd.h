@@ -284,6 +284,27 @@ rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, const rbf_o
 rbf_status rbf_step(rbf_solver *s, int32_t nsteps, rbf_state *state, rbf_step_stats *stats);
 
 /*
+ * rbf_step_batch -- advance `count` independent instances (solvers[b] with
+ * states[b]) by nsteps steps each, concurrently.  The method is that of
+ * rbf_step, per instance; the instances run on nthreads host threads
+ * (nthreads <= 0: 8; never more than count), each taking the next instance
+ * in order and driving rbf_step on the stream its solver was created with,
+ * so that the work of instances on distinct streams overlaps on the device.
+ * Results are those of calling rbf_step on each instance alone.
+ * solvers: host [count] distinct handles; states: host [count];
+ * stats (nullable): host [count]; statuses (nullable): host [count], each
+ * instance's rbf_step status.  Every instance is attempted; a failed one
+ * keeps its last committed step (rbf_step is transactional).
+ * Returns RBF_OK, or the status of the lowest-numbered failed instance, whose
+ * message rbf_last_error reports on the calling thread.
+ * Errors: RBF_E_ARG (NULL or repeated handle, count or nsteps < 0), and
+ * those of rbf_step.
+ */
+rbf_status rbf_step_batch(rbf_solver *const *solvers, int32_t count, int32_t nsteps,
+                          rbf_state *states, rbf_step_stats *stats, rbf_status *statuses,
+                          int32_t nthreads);
+
+/*
  * rbf_solve_pressure -- solve the bordered pressure-Poisson system of
  * eq. (18) described at rbf_solver_create: D_Lap^PP p~ + lam = rhs on
  * interior rows, n . grad p~ = rhs on wall rows, mean(p~) = 0.  rhs: device

@@ -25,7 +25,7 @@ FORCE_SMALL_STENCIL = 0x80000000
 EXPORTED = [
     "rbf_last_error", "rbf_abi_version", "rbf_build_nodes", "rbf_knn",
     "rbf_assemble_weights", "rbf_ell_apply", "rbf_cast_f32", "rbf_solver_create",
-    "rbf_step", "rbf_solve_pressure", "rbf_solver_apply_precond", "rbf_solver_profile",
+    "rbf_step", "rbf_step_batch", "rbf_solve_pressure", "rbf_solver_apply_precond", "rbf_solver_profile",
     "rbf_solver_destroy",
 ]
 
@@ -108,6 +108,10 @@ def _load():
     lib.rbf_step.restype = S
     lib.rbf_step.argtypes = [c_void_p, ctypes.c_int32, ctypes.POINTER(State),
                              ctypes.POINTER(StepStats)]
+    lib.rbf_step_batch.restype = S
+    lib.rbf_step_batch.argtypes = [ctypes.POINTER(c_void_p), ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.POINTER(State), ctypes.POINTER(StepStats),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     lib.rbf_solve_pressure.restype = S
     lib.rbf_solve_pressure.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveStats)]
     lib.rbf_solver_apply_precond.restype = S

@@ -160,16 +160,19 @@ class Solver:
 
     def step(self, state, nsteps=1):
         """Advance the state dict in place; returns the step statistics."""
-        for key, n in (("u", self.N), ("v", self.N), ("cu_prev", self.N), ("cv_prev", self.N),
-                       ("p_tilde", self.M), ("p", self.M)):
-            _dev(state[key], torch.float64, (n,), key)
-        st = _lib.State(*[state[k].data_ptr() for k in ("u", "v", "p_tilde", "p", "cu_prev",
-                                                          "cv_prev")], int(state["step"]))
+        st = self._state_struct(state)
         stats = _lib.StepStats()
         rc = lib.rbf_step(self._h, int(nsteps), ctypes.byref(st), ctypes.byref(stats))
         state["step"] = st.step
         check(rc)
         return stats
+
+    def _state_struct(self, state):
+        for key, n in (("u", self.N), ("v", self.N), ("cu_prev", self.N), ("cv_prev", self.N),
+                       ("p_tilde", self.M), ("p", self.M)):
+            _dev(state[key], torch.float64, (n,), key)
+        return _lib.State(*[state[k].data_ptr() for k in ("u", "v", "p_tilde", "p", "cu_prev",
+                                                            "cv_prev")], int(state["step"]))
 
     def solve_pressure(self, rhs, p_tilde):
         _dev(rhs, torch.float64, (self.M,), "rhs")
@@ -204,3 +207,29 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def step_batch(solvers, states, nsteps=1, nthreads=0):
+    """Advance independent instances concurrently (rbf_step_batch): solvers[b]
+    with the state dict states[b], nsteps steps each, on nthreads host threads
+    (0: the library's default).  Give each solver its own stream (create it
+    under ``torch.cuda.stream(s)``) for their work to overlap.  Returns the
+    per-instance step statistics and statuses; raises RbfError for the
+    lowest-numbered failed instance after all were attempted (its
+    ``statuses`` and ``stats`` attributes hold every instance's)."""
+    n = len(solvers)
+    if len(states) != n:
+        raise ValueError("step_batch: one state per solver")
+    hs = (ctypes.c_void_p * n)(*[s._h for s in solvers])
+    sts = (_lib.State * n)(*[s._state_struct(st) for s, st in zip(solvers, states)])
+    stats = (_lib.StepStats * n)()
+    codes = (ctypes.c_int32 * n)()
+    rc = lib.rbf_step_batch(hs, n, int(nsteps), sts, stats, codes, int(nthreads))
+    for st, c in zip(states, sts):
+        st["step"] = c.step
+    try:
+        check(rc)
+    except _lib.RbfError as e:
+        e.statuses, e.stats = list(codes), list(stats)
+        raise
+    return list(stats), list(codes)

@@ -10,7 +10,11 @@
 // solved by BiCGSTAB (van der Vorst 1992) with two fused ELL SpMV kernels per
 // iteration (see the Krylov section below).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <string>
+#include <system_error>
+#include <thread>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -74,9 +78,12 @@ __device__ __forceinline__ void load_partials(const double *part, int nb, double
 }
 
 // ------------------------------------------------------ Krylov state --
-// BiCGSTAB (van der Vorst 1992), right-preconditioned with D^-1 (Jacobi for
-// H, identity for the row-scaled Poisson matrix), restructured into two
-// SpMV kernels per iteration:
+// BiCGSTAB (van der Vorst 1992), right-preconditioned with D^-1 (Jacobi when
+// JAC, else the identity), for NR right-hand sides sharing every matrix read,
+// restructured into two SpMV kernels per iteration.  Used for the pressure
+// solve without the lattice preconditioner (NR = 1, identity on the
+// row-scaled Poisson matrix); the viscous solve has its own kernels
+// (k_h_*, below).
 //   k_kry_a(i): at every row, finish the update of iteration i-1
 //                 s = r - alpha v,  r' = s - omega t,  x += alpha D^-1 p + omega D^-1 s,
 //               start iteration i
@@ -1332,6 +1339,7 @@ __global__ void k_wall_list(int64_t n, const int8_t *__restrict__ tag, int *__re
 // ====================================================================== host
 struct rbf_solver {
     hipStream_t st = nullptr;
+    int device = 0;  // current device at creation (the stream's device)
     int64_t N = 0, M = 0;
     int k = 0;
     double re = 0, dt = 0, a = 0, rtol_h = 0, rtol_p = 0;
@@ -1357,7 +1365,7 @@ struct rbf_solver {
            *cvn = nullptr;
     double *us = nullptr, *vs = nullptr, *hrhs = nullptr, *uvss = nullptr, *prhs = nullptr;
     // Krylov workspaces: Helmholtz (2 RHS over N), Poisson (1 RHS over M)
-    KDev kh{}, kp{};
+    KDev kp{};
     double *rpart = nullptr;
     int last_iters_h = 0, last_iters_p = 0;
     // optional sampling of the Poisson SpMV duration with HIP events
@@ -1687,7 +1695,8 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
 
 // Viscous solve (both components): Jacobi right-preconditioned BiCGSTAB
 // with explicit preconditioned directions; same contract as
-// bicgstab<2, true>.  Per iteration: k_h_dir, k_h_av (v), k_h_s, k_h_av (t).
+// bicgstab<2, true> for a matrix without the rank-one border (A.u1 unset).
+// Per iteration: k_h_dir, k_h_av (v), k_h_s, k_h_av (t).
 rbf_status hbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double tol, int maxit,
                      int &last_iters, rbf_solve_stats *stats) {
     hipStream_t st = S->st;
@@ -1748,8 +1757,8 @@ rbf_status hbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
         if (!done && it > maxit) break;
         batch = 2;
     }
-    if (k28) hipLaunchKernelGGL((k_resid<kHR, 28>), grid, block, 0, st, A, b, x, S->rpart, S->kh.partX);
-    else hipLaunchKernelGGL((k_resid<kHR, 0>), grid, block, 0, st, A, b, x, S->rpart, S->kh.partX);
+    if (k28) hipLaunchKernelGGL((k_resid<kHR, 28>), grid, block, 0, st, A, b, x, S->rpart, nullptr);
+    else hipLaunchKernelGGL((k_resid<kHR, 0>), grid, block, 0, st, A, b, x, S->rpart, nullptr);
     RBF_CHECK_LAUNCH();
     RBF_HIP(hipMemcpyAsync(S->hred, S->rpart, (size_t)kHR * nb * sizeof(double), hipMemcpyDeviceToHost, st));
     RBF_HIP(hipMemcpyAsync(S->hred + kMaxNR * kMaxBlocks, K.bb, kHR * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -2008,7 +2017,6 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     ALLOC(S->uvss, 2 * N);
     ALLOC(S->rpart, kMaxNR * kMaxBlocks);
     rbf_status rc;
-    if ((rc = alloc_krylov(S, S->kh, 2, N, S->maxit_h)) != RBF_OK) return rc;
     {
         HKry &H = S->hk;
         for (double **q : {&H.r, &H.rh, &H.p[0], &H.p[1], &H.v, &H.s, &H.t, &H.ph, &H.sh})
@@ -2208,6 +2216,11 @@ extern "C" rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, 
             "rbf_solver_create: unknown precond %d", prm->precond);
     rbf_solver *S = new rbf_solver();
     S->st = rbf::as_stream(st);
+    if (hipGetDevice(&S->device) != hipSuccess) {
+        delete S;
+        rbf::set_error("rbf_solver_create: hipGetDevice failed");
+        return RBF_E_DEVICE;
+    }
     rbf_status rc = create_impl(S, grid, ops, u_bc, v_bc, prm);
     if (rc != RBF_OK) {
         rbf_solver_destroy(S);
@@ -2254,6 +2267,62 @@ extern "C" rbf_status rbf_step(rbf_solver *S, int32_t nsteps, rbf_state *state,
         state->step += done;
     }
     RBF_HIP(hipStreamSynchronize(st));
+    return rc;
+}
+
+// Independent instances advanced concurrently: a pool of host threads takes
+// the instances in order, each thread driving rbf_step on the instance's own
+// stream, so that the short kernels and host synchronisations of different
+// instances overlap on the device.
+extern "C" rbf_status rbf_step_batch(rbf_solver *const *solvers, int32_t count, int32_t nsteps,
+                                     rbf_state *states, rbf_step_stats *stats,
+                                     rbf_status *statuses, int32_t nthreads) {
+    rbf::clear_error();
+    RBF_ARG(count >= 0 && nsteps >= 0, "rbf_step_batch: negative count or nsteps");
+    RBF_ARG(count == 0 || (solvers && states), "rbf_step_batch: NULL argument");
+    for (int b = 0; b < count; ++b) {
+        RBF_ARG(solvers[b], "rbf_step_batch: solver %d is NULL", b);
+        for (int c = 0; c < b; ++c)
+            RBF_ARG(solvers[c] != solvers[b], "rbf_step_batch: solver %d repeats solver %d", b, c);
+    }
+    std::vector<rbf_status> rcs(count, RBF_OK);
+    std::vector<std::string> msgs(count);
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        for (;;) {
+            const int b = next.fetch_add(1);
+            if (b >= count) return;
+            rbf_solver *S = solvers[b];
+            rbf_status rc;
+            if (hipSetDevice(S->device) != hipSuccess) {
+                rc = RBF_E_DEVICE;
+                msgs[b] = "hipSetDevice failed";
+            } else {
+                rc = rbf_step(S, nsteps, &states[b], stats ? &stats[b] : nullptr);
+                if (rc != RBF_OK) msgs[b] = rbf_last_error();
+            }
+            rcs[b] = rc;
+        }
+    };
+    const int nt = std::min<int>(count, nthreads > 0 ? nthreads : 8);
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) {
+        try {
+            pool.emplace_back(work);
+        } catch (const std::system_error &) {
+            break;  // fewer threads: the remaining instances run on those started
+        }
+    }
+    work();
+    for (auto &t : pool) t.join();
+    rbf_status rc = RBF_OK;
+    for (int b = 0; b < count; ++b) {
+        if (statuses) statuses[b] = rcs[b];
+        if (rcs[b] != RBF_OK && rc == RBF_OK) {
+            rc = rcs[b];
+            rbf::set_error("rbf_step_batch: instance %d: %s", b, msgs[b].c_str());
+        }
+    }
     return rc;
 }
 

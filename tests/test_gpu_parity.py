@@ -393,3 +393,99 @@ def test_step_error_paths_are_transactional(P, gpu):
     assert ei.value.status == -6  # RBF_E_NAN
     assert st["step"] == 0
     S.close()
+
+
+def _sampled_stencils(xq, xs, rows, ops):
+    """Oracle kNN + weights for the listed evaluation rows only."""
+    idx = oknn.knn_bruteforce(xq[:, rows], xs, 28)
+    return idx, ow.stencil_weights(xq[:, rows], xs, idx, 7, 3, ops)
+
+
+def test_cavity_full_size_sampled(P, gpu):
+    """The bench workload (K=400: N=480,800, M=160,801; Re=1e4, dt=2e-4,
+    tolerances 1e-12), three GPU steps, the third checked on sampled rows
+    with oracle stencils and weights computed for those rows only:
+    advection C_j(u_j) (eq. (15)) and the pressure update (eq. (19)) to
+    1e-10; the viscous solve (eq. (16)) through its residual at sampled rows,
+    u** rebuilt from u_{j+1} and p~_{j+1} (eq. (20)); the bordered Poisson
+    solve (eq. (18)) through its residual, which on interior rows must be the
+    one constant -lam and on wall rows the Neumann value 0."""
+    import torch
+    _say("cavity full size sampled K=400")
+    K, re, dt = 400, 1e4, 2e-4
+    a = dt / (2.0 * re)
+    nd = ri.cavity_nodes(K, 0.3, 0)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, re, dt, rtol_h=1e-12, rtol_p=1e-12)
+    del ops
+    st = S.new_state(to_dev(np.where(nd.v_tag != 0, u_bc, 0.0), gpu),
+                     to_dev(np.where(nd.v_tag != 0, v_bc, 0.0), gpu))
+    S.step(st, 2)
+    before = {k: st[k].cpu().numpy().copy() for k in ("u", "v", "p_tilde", "cu_prev", "cv_prev")}
+    stats = S.step(st, 1)
+    after = {k: st[k].cpu().numpy() for k in ("u", "v", "p_tilde", "p", "cu_prev", "cv_prev")}
+    S.close()
+    torch.cuda.empty_cache()
+    assert stats.last_poisson.converged and stats.last_helmholtz_u.converged
+    xv, xp = nd.xv, nd.xp
+    vwall, pwall = nd.v_tag != 0, nd.p_tag != 0
+    rng = np.random.default_rng(7)
+    rv = np.unique(np.concatenate([rng.choice(np.nonzero(~vwall)[0], 24, replace=False),
+                                   rng.choice(np.nonzero(vwall)[0], 8, replace=False)]))
+    rp = np.unique(np.concatenate([rng.choice(np.nonzero(~pwall)[0], 24, replace=False),
+                                   rng.choice(np.nonzero(pwall)[0], 8, replace=False)]))
+    uj, vj, ptj = before["u"], before["v"], before["p_tilde"]
+    un, vn, ptn = after["u"], after["v"], after["p_tilde"]
+
+    def advect(rows):
+        idx, (wx, wy) = _sampled_stencils(xv, xv, rows, (OP_DX, OP_DY))
+        dxu, dyu = (wx * uj[idx]).sum(0), (wy * uj[idx]).sum(0)
+        dxv, dyv = (wx * vj[idx]).sum(0), (wy * vj[idx]).sum(0)
+        return -(uj[rows] * dxu + vj[rows] * dyu), -(uj[rows] * dxv + vj[rows] * dyv)
+
+    # Stage 1 at the sampled rows: C_j(u_j), C_j(v_j) are the new cu_prev, cv_prev.
+    cu_r, cv_r = advect(rv)
+    for got, ref in ((after["cu_prev"][rv], cu_r), (after["cv_prev"][rv], cv_r)):
+        assert np.max(np.abs(got - ref)) <= 1e-10 * max(1.0, np.max(np.abs(ref)))
+
+    # u** = u_{j+1} + dt D_x^VP p~_{j+1} at the given V rows.
+    def ustar2(rows):
+        idx, (wx, wy) = _sampled_stencils(xv, xp, rows, (OP_DX, OP_DY))
+        return un[rows] + dt * (wx * ptn[idx]).sum(0), vn[rows] + dt * (wy * ptn[idx]).sum(0)
+
+    # Stage 2: H u** = ru on the sampled V rows.
+    idx_l, (wl,) = _sampled_stencils(xv, xv, rv, (OP_LAP,))
+    nb = np.unique(idx_l)
+    pos = {r: i for i, r in enumerate(nb)}
+    cu_n, cv_n = advect(nb)
+    us_n = uj[nb] + dt * (1.5 * cu_n - 0.5 * before["cu_prev"][nb])
+    vs_n = vj[nb] + dt * (1.5 * cv_n - 0.5 * before["cv_prev"][nb])
+    uss_n, vss_n = ustar2(nb)
+    loc = np.vectorize(pos.get)(idx_l)
+    self_ = np.array([pos[r] for r in rv])
+    idx_w, (wxw, wyw) = _sampled_stencils(xv, xp, rv, (OP_DX, OP_DY))
+    for comp, (s_n, x_n, bc, ww) in enumerate(((us_n, uss_n, u_bc, wxw), (vs_n, vss_n, v_bc, wyw))):
+        rhs = np.where(vwall[rv], bc[rv] + dt * (ww * ptj[idx_w]).sum(0),
+                       s_n[self_] + a * (wl * s_n[loc]).sum(0))
+        hx = np.where(vwall[rv], x_n[self_], x_n[self_] - a * (wl * x_n[loc]).sum(0))
+        assert np.max(np.abs(hx - rhs)) <= 1e-9 * max(1.0, np.max(np.abs(rhs))), comp
+
+    # Stage 3: F = D_x^PV u** + D_y^PV v**, D_Lap^PP p~ + lam = F / dt inside,
+    # n . grad p~ = 0 on the walls; p = p~ - a D_Lap^PP p~.
+    idx_pv, (wpx, wpy) = _sampled_stencils(xp, xv, rp, (OP_DX, OP_DY))
+    nbv = np.unique(idx_pv)
+    posv = {r: i for i, r in enumerate(nbv)}
+    uss_v, vss_v = ustar2(nbv)
+    locv = np.vectorize(posv.get)(idx_pv)
+    F = (wpx * uss_v[locv]).sum(0) + (wpy * vss_v[locv]).sum(0)
+    idx_pp, (plap, pdx, pdy) = _sampled_stencils(xp, xp, rp, (OP_LAP, OP_DX, OP_DY))
+    lap = (plap * ptn[idx_pp]).sum(0)
+    scale = np.abs(plap * ptn[idx_pp]).sum(0) + np.abs(F / dt)
+    inner = ~pwall[rp]
+    d = lap[inner] - F[inner] / dt
+    assert np.ptp(d) <= 1e-9 * np.max(scale[inner]), (np.ptp(d), np.max(scale[inner]))
+    nx, ny = nd.p_normal[0][rp], nd.p_normal[1][rp]
+    dn = nx * (pdx * ptn[idx_pp]).sum(0) + ny * (pdy * ptn[idx_pp]).sum(0)
+    dscale = np.abs(pdx * ptn[idx_pp]).sum(0) + np.abs(pdy * ptn[idx_pp]).sum(0)
+    assert np.max(np.abs(dn[~inner])) <= 1e-9 * np.max(dscale[~inner])
+    p_ref = ptn[rp] - a * lap
+    assert np.max(np.abs(after["p"][rp] - p_ref)) <= 1e-10 * max(1e-30, np.max(np.abs(p_ref)))
