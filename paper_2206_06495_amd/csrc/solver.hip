@@ -456,8 +456,9 @@ __global__ void __launch_bounds__(kThreads) k_resid(EllM A, const double *__rest
 // diagonalised by the DCT-II basis Q (T = Q Lam Q^-1): a dense product
 // Q^-1 X on the matrix cores (k_pc_gemm, FP64 MFMA); for each x-mode k the
 // y-direction system (T + lam_k I) w = h^2 t is tridiagonal and is solved by
-// parallel cyclic reduction (k_pc_tri, one workgroup per mode); the product
-// Q W returns to the lattice.  Mode k = 0 is
+// one wavefront per mode (k_pc_tri: elimination inside per-lane chunks, then
+// cyclic reduction across the lanes); the product Q W returns to the
+// lattice.  Mode k = 0 is
 // singular: its right-hand side loses its mean (recorded: it fixes the
 // constant through the border), the last unknown is fixed and the solution
 // shifted to zero mean.
@@ -521,13 +522,15 @@ constexpr int kStall = 30;
 // values val(node) of the vector y being preconditioned: D^-1 y with the
 // wall values moved to the right-hand side.  At a boundary node, returns
 // its term |w - in(w)| (D^-1 y)_w of the boundary sum (0 elsewhere).
+// rself = L.rs[row], loaded by the caller.
 template <class V>
-__device__ __forceinline__ double pc_reduce(const Lat &L, int64_t row, double vself, V val) {
+__device__ __forceinline__ double pc_reduce(const Lat &L, int64_t row, double vself, double rself,
+                                            V val) {
     const int K = L.K, K1 = K + 1;
     const int i = (int)(row % K1), j = (int)(row / K1);
     const bool bi = (i == 0 || i == K), bj = (j == 0 || j == K);
-    if (bi || bj) return ((bi && bj) ? L.h * 1.4142135623730951 : L.h) * (vself / L.rs[row]);
-    double g = vself / L.rs[row];
+    if (bi || bj) return ((bi && bj) ? L.h * 1.4142135623730951 : L.h) * (vself / rself);
+    double g = vself / rself;
     double wsum = 0.0;
     if (i == 1) wsum += val(row - 1) / L.rs[row - 1];
     if (i == K - 1) wsum += val(row + 1) / L.rs[row + 1];
@@ -576,14 +579,54 @@ __global__ void __launch_bounds__(kThreads) k_pc_init(EllM A, const double *__re
 // kernel performs the same update.
 __global__ void __launch_bounds__(kThreads) k_pc_dir(PKry K, Lat L, double *__restrict__ x,
                                                       int64_t m, int i, int i0) {
-    if (K.flag[0] != 0) return;
     const int nb = gridDim.x;
     const bool first = (i == i0);
     const int par = i & 1;
+    const double *pold = K.p[par ^ 1];
+    double *pnew = K.p[par];
+    // Every load that does not depend on another goes out before the first
+    // wait: the flag, the partial sums, the recorded scalars and the vectors
+    // of this thread's first row.
+    const int fl = K.flag[0];
+    double q[3] = {0.0, 0.0, 0.0};
+    if (first) {
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            q[0] += K.partI[b];
+            q[1] += K.partI[nb + b];
+        }
+    } else {
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            q[0] += K.part6[b];
+            q[1] += K.part6[nb + b];
+            q[2] += K.part6[2 * nb + b];
+        }
+    }
+    const double pr0 = first ? 0.0 : K.rec[(int64_t)(i - 1) * 4 + 0];
+    const double pr1 = first ? 0.0 : K.rec[(int64_t)(i - 1) * 4 + 1];
+    const int64_t row0 = row_of(0);
+    double f_r = 0.0, f_s = 0.0, f_t = 0.0, f_po = 0.0, f_v = 0.0, f_ph = 0.0, f_sh = 0.0,
+           f_x = 0.0, f_rs = 1.0;
+    if (row0 < m) {
+        f_rs = L.rs[row0];
+        if (first) {
+            f_r = K.r[row0];
+        } else {
+            f_s = K.s[row0];
+            f_t = K.t[row0];
+            f_po = pold[row0];
+            f_v = K.v[row0];
+            f_ph = K.ph[row0];
+            f_sh = K.sh[row0];
+            f_x = x[row0];
+        }
+    }
+    if (fl != 0) return;
+    {
+        __shared__ double lds[3 * (kThreads / 64)];
+        rbf::block_sum<3>(q, lds);
+    }
     double al = 0.0, om = 0.0, be = 0.0, rho;
     if (first) {
-        double q[2];
-        load_partials<2>(K.partI, nb, q);
         rho = q[0];
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             K.bb[0] = q[1];
@@ -591,21 +634,16 @@ __global__ void __launch_bounds__(kThreads) k_pc_dir(PKry K, Lat L, double *__re
             K.rec[(int64_t)i * 4 + 0] = rho;
         }
     } else {
-        double q[3];
-        load_partials<3>(K.part6, nb, q);
-        const double *pr = K.rec + (int64_t)(i - 1) * 4;
-        al = pr[1];
+        al = pr1;
         om = (q[1] != 0.0) ? q[0] / q[1] : 0.0;
         rho = -om * q[2];  // (rh, s) = 0 by the choice of alpha
-        be = (rho / pr[0]) * (al / om);
+        be = (rho / pr0) * (al / om);
         if (!isfinite(be)) be = 0.0;  // omega = 0: rho = 0, restarted by k_pc_s
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             K.rec[(int64_t)(i - 1) * 4 + 2] = om;
             K.rec[(int64_t)i * 4 + 0] = rho;
         }
     }
-    const double *pold = K.p[par ^ 1];
-    double *pnew = K.p[par];
     auto pval = [&](int64_t j) {
         if (first) return K.r[j];
         const double rn = K.s[j] - om * K.t[j];
@@ -616,19 +654,24 @@ __global__ void __launch_bounds__(kThreads) k_pc_dir(PKry K, Lat L, double *__re
         const int64_t row = row_of(it);
         if (row - threadIdx.x >= m) break;
         if (row < m) {
+            const bool pre = (it == 0);
             double rn, pn;
             if (first) {
-                rn = K.r[row];
+                rn = pre ? f_r : K.r[row];
                 pn = rn;
             } else {
-                rn = K.s[row] - om * K.t[row];
-                x[row] = x[row] + al * K.ph[row] + om * K.sh[row];
+                const double sv = pre ? f_s : K.s[row], tv = pre ? f_t : K.t[row];
+                const double pv = pre ? f_po : pold[row], vv = pre ? f_v : K.v[row];
+                const double phv = pre ? f_ph : K.ph[row], shv = pre ? f_sh : K.sh[row];
+                const double xv = pre ? f_x : x[row];
+                rn = sv - om * tv;
+                x[row] = xv + al * phv + om * shv;
                 K.r[row] = rn;
-                pn = rn + be * (pold[row] - om * K.v[row]);
+                pn = rn + be * (pv - om * vv);
             }
             pnew[row] = pn;
             acc[0] += rn * rn;
-            acc[1] += pc_reduce(L, row, pn, pval);
+            acc[1] += pc_reduce(L, row, pn, pre ? f_rs : L.rs[row], pval);
         }
     }
     store_partials<2>(acc, K.part1, nb);
@@ -638,25 +681,41 @@ __global__ void __launch_bounds__(kThreads) k_pc_dir(PKry K, Lat L, double *__re
 // s = r - alpha v and its reduced right-hand side.
 __global__ void __launch_bounds__(kThreads) k_pc_s(PKry K, Lat L, int64_t m, int i, int i0,
                                                     double tol2) {
-    if (K.flag[0] != 0) return;
     const int nb = gridDim.x;
-    double q1[1], q3[1];
-    load_partials<1>(K.part1, nb, q1);
-    load_partials<1>(K.part3, nb, q3);
-    const double rr = q1[0], rv = q3[0];
+    // Loads first (see k_pc_dir).
+    const int fl = K.flag[0];
+    double q[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        q[0] += K.part1[b];
+        q[1] += K.part3[b];
+    }
     const double rho = K.rec[(int64_t)i * 4];
-    const double al = rho / rv;
     const double bb = K.bb[0], rhrh = K.rhrh[0];
-    const bool bad = !isfinite(rr) || !isfinite(rho);
-    const bool conv = !bad && (rr <= tol2 * fmax(bb, 1e-300) || rr == 0.0);
     // Stagnation: no 0.1% decrease of the best ||r||^2 for kStall iterations
     // is handled like a breakdown (restart from the true residual).  The best
     // value is double-buffered by parity: read from the previous launch,
     // written for the next one.
     const double *bprev = K.best + ((i + 1) & 1) * 2;
+    const double bp0 = bprev[0], bp1 = bprev[1];
+    const int64_t row0 = row_of(0);
+    double f_r = 0.0, f_v = 0.0, f_rs = 1.0;
+    if (row0 < m) {
+        f_r = K.r[row0];
+        f_v = K.v[row0];
+        f_rs = L.rs[row0];
+    }
+    if (fl != 0) return;
+    {
+        __shared__ double lds[2 * (kThreads / 64)];
+        rbf::block_sum<2>(q, lds);
+    }
+    const double rr = q[0], rv = q[1];
+    const double al = rho / rv;
+    const bool bad = !isfinite(rr) || !isfinite(rho);
+    const bool conv = !bad && (rr <= tol2 * fmax(bb, 1e-300) || rr == 0.0);
     const bool fresh = (i == i0);
-    const double best = fresh ? rr : bprev[0];
-    const int best_it = fresh ? i : (int)bprev[1];
+    const double best = fresh ? rr : bp0;
+    const int best_it = fresh ? i : (int)bp1;
     const bool better = fresh || rr < 0.999 * best;
     const bool stall = !better && (i - best_it >= kStall);
     const bool brk = !bad && !conv &&
@@ -681,9 +740,10 @@ __global__ void __launch_bounds__(kThreads) k_pc_s(PKry K, Lat L, int64_t m, int
         const int64_t row = row_of(it);
         if (row - threadIdx.x >= m) break;
         if (row < m) {
-            const double sv = sval(row);
+            const bool pre = (it == 0);
+            const double sv = (pre ? f_r : K.r[row]) - al * (pre ? f_v : K.v[row]);
             K.s[row] = sv;
-            acc[0] += pc_reduce(L, row, sv, sval);
+            acc[0] += pc_reduce(L, row, sv, pre ? f_rs : L.rs[row], sval);
         }
     }
     store_partials<1>(acc, K.partGs, nb);
@@ -697,7 +757,7 @@ __global__ void __launch_bounds__(kThreads) k_pc_pre(Lat L, const double *__rest
     for (int64_t it = 0;; ++it) {
         const int64_t row = row_of(it);
         if (row - threadIdx.x >= m) break;
-        if (row < m) acc[0] += pc_reduce(L, row, y[row], yval);
+        if (row < m) acc[0] += pc_reduce(L, row, y[row], L.rs[row], yval);
     }
     store_partials<1>(acc, partG, gridDim.x);
 }
@@ -710,7 +770,6 @@ constexpr int kGemmWaves = 8;
 constexpr int kGemmChunk = 14;
 template <int STAGE, bool ONESHOT, class TP>
 __global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
-    if (*L.flag != 0) return;
     const int n = L.n, nt = (n + 15) / 16;
     const int ti = (int)(blockIdx.x % nt), tj = (int)(blockIdx.x / nt);
     const TP *A = static_cast<const TP *>(STAGE == 0 ? L.Qi : L.Q);
@@ -721,90 +780,172 @@ __global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
         n, A, B, ti, tj, [&](int i, int j, TP v) {
             if constexpr (STAGE == 0) C[(int64_t)i * n + j] = v;
             else C[i + (int64_t)j * n] = v;
-        });
+        },
+        L.flag);
 }
 
-// For each x-mode k (one workgroup): (T + lam_k I) w = h^2 t along y by
-// parallel cyclic reduction in LDS (log2 n halving steps, every row
-// updated in parallel; the systems are diagonally dominant).  Mode 0 drops
-// its last row (w_{n-1} = 0) after removing the right-hand side's mean,
-// then is shifted to zero mean.  Writes W row-major and the block's sum of
-// W o V into partW[k].
-constexpr int kTriThreads = 512;  // n <= kTriThreads (K <= 513)
+// For each x-mode k (one wavefront): (T + lam_k I) w = h^2 t along y.  The
+// rows are split into nch <= 64 chunks of 2-8 consecutive rows, one per
+// lane.  Each lane eliminates inside its chunk
+// (a downward and an upward sweep that leave every row coupled only to the
+// chunk's first and last unknowns), the first and last rows of all chunks
+// reduce to a tridiagonal system in the chunks' first unknowns, one per
+// lane, solved by cyclic reduction across the wavefront (shuffles), and each
+// lane recovers its rows.  The systems are diagonally dominant, so no
+// pivoting.  Mode 0 is singular: its right-hand side loses its mean
+// (recorded in *L.mean), its last row is dropped (w_{n-1} = 0) and the
+// solution is shifted to zero mean.  Writes W row-major and the sum of
+// W o V over the mode into partW[k].
+constexpr int kTriChunk = 8;  // rows per lane: n <= 64 kTriChunk (K <= 513)
 template <class TP>
-__global__ void __launch_bounds__(kTriThreads) k_pc_tri(Lat L) {
-    if (*L.flag != 0) return;
-    __shared__ double sa[kTriThreads], sb[kTriThreads], sc[kTriThreads], sd[kTriThreads];
-    __shared__ double red[kTriThreads / 64];
-    const int n = L.n, k = blockIdx.x, i = threadIdx.x;
-    const double h2 = L.h * L.h;
+__global__ void __launch_bounds__(64) k_pc_tri(Lat L) {
+    __shared__ double sz[64 * kTriChunk];
+    const int n = L.n, k = blockIdx.x, lane = threadIdx.x;
     const TP *T = static_cast<const TP *>(L.T);
+    // Every global load of the kernel is issued before the flag test, so
+    // that the whole kernel waits on one memory round trip.
+    double tv[kTriChunk], vv[kTriChunk];
+#pragma unroll
+    for (int m = 0; m < kTriChunk; ++m) {
+        const int i = lane + 64 * m;
+        tv[m] = (i < n) ? (double)T[(int64_t)k * n + i] : 0.0;
+        vv[m] = (i < n) ? L.V[(int64_t)k * n + i] : 0.0;
+    }
     const double lamk = L.lam[k];
-    const double t = (i < n) ? (double)T[(int64_t)k * n + i] : 0.0;
+    if (*L.flag != 0) return;
+    double tsum = 0.0;
+#pragma unroll
+    for (int m = 0; m < kTriChunk; ++m) {
+        const int i = lane + 64 * m;
+        if (i < n) sz[i] = tv[m];
+        tsum += tv[m];
+    }
     const int size = (k == 0) ? n - 1 : n;
     double shift = 0.0;
     if (k == 0) {  // block-uniform branch
-        double v[1] = {t};
-        rbf::block_sum<1>(v, red);
-        shift = v[0] / n;
-        if (i == 0) *L.mean = shift;
-    }
-    if (i < size) {
-        const bool end = (i == 0) || (i == n - 1);
-        sa[i] = (i == 0) ? 0.0 : 1.0;
-        sc[i] = (i == size - 1) ? 0.0 : 1.0;
-        sb[i] = (end ? -1.0 : -2.0) + lamk;
-        sd[i] = h2 * (t - shift);
+        shift = rbf::wave_sum(tsum) / n;
+        if (lane == 0) *L.mean = shift;
     }
     __syncthreads();
-    for (int st = 1; st < size; st <<= 1) {
-        // sb holds 1 / b of every row during the step (one division per row).
-        double a2 = 0.0, b2 = 1.0, c2 = 0.0, d2 = 0.0;
-        const double bi = (i < size) ? sb[i] : 1.0;
-        __syncthreads();
-        if (i < size) sb[i] = 1.0 / bi;
-        __syncthreads();
-        if (i < size) {
-            const double ai = sa[i], ci = sc[i], di = sd[i];
-            a2 = 0.0;
-            c2 = 0.0;
-            b2 = bi;
-            d2 = di;
-            if (i - st >= 0) {
-                const double al = -ai * sb[i - st];
-                a2 = al * sa[i - st];
-                b2 += al * sc[i - st];
-                d2 += al * sd[i - st];
+    const double h2 = L.h * L.h;
+    const int nch = min(64, max(1, size / 2));
+    const int base = size > 0 ? size / nch : 0, extra = size > 0 ? size % nch : 0;
+    const bool act = lane < nch && size > 0;
+    const int len = act ? base + (lane < extra ? 1 : 0) : 0;
+    const int r0 = lane * base + min(lane, extra);
+    auto row = [&](int i, double &a, double &b, double &c, double &d) {
+        a = (i == 0) ? 0.0 : 1.0;
+        c = (i == size - 1) ? 0.0 : 1.0;
+        b = ((i == 0 || i == n - 1) ? -1.0 : -2.0) + lamk;
+        d = h2 * (sz[i] - shift);
+    };
+    // Downward sweep: row j >= 1 becomes ap_j x_first + x_j + cp_j x_{j+1} = dp_j
+    // (row 0 normalised: ap_0 couples to the previous chunk's last unknown).
+    double ap[kTriChunk], cp[kTriChunk], dp[kTriChunk];
+    double fa = 0.0, fc = 0.0, fd = 0.0;  // last row: fa x_first + x_last + fc x_next = fd
+#pragma unroll
+    for (int j = 0; j < kTriChunk; ++j) {
+        ap[j] = cp[j] = dp[j] = 0.0;
+        if (j < len) {
+            double a, b, c, d;
+            row(r0 + j, a, b, c, d);
+            if (j < 2) {
+                const double r = 1.0 / b;
+                ap[j] = a * r;
+                cp[j] = c * r;
+                dp[j] = d * r;
+            } else {
+                const double r = 1.0 / (b - a * cp[j - 1]);
+                ap[j] = -a * ap[j - 1] * r;
+                cp[j] = c * r;
+                dp[j] = (d - a * dp[j - 1]) * r;
             }
-            if (i + st < size) {
-                const double ga = -ci * sb[i + st];
-                c2 = ga * sc[i + st];
-                b2 += ga * sa[i + st];
-                d2 += ga * sd[i + st];
+            if (j == len - 1) {
+                fa = ap[j];
+                fc = cp[j];
+                fd = dp[j];
             }
         }
-        __syncthreads();
-        if (i < size) {
-            sa[i] = a2;
-            sb[i] = b2;
-            sc[i] = c2;
-            sd[i] = d2;
-        }
-        __syncthreads();
     }
-    double z = (i < size) ? sd[i] / sb[i] : 0.0;
+    // Upward sweep: rows 1..len-2 become ap_j x_first + x_j + cp_j x_last = dp_j.
+#pragma unroll
+    for (int j = kTriChunk - 3; j >= 1; --j) {
+        if (j <= len - 3) {
+            ap[j] -= cp[j] * ap[j + 1];
+            dp[j] -= cp[j] * dp[j + 1];
+            cp[j] = -cp[j] * cp[j + 1];
+        }
+    }
+    // First row: ea x_prev_last + eb x_first + ec x_last = ed.
+    double ea = ap[0], eb = 1.0, ec = cp[0], ed = dp[0];
+    if (len >= 3) {
+        eb = 1.0 - cp[0] * ap[1];
+        ec = -cp[0] * cp[1];
+        ed = dp[0] - cp[0] * dp[1];
+    }
+    // Eliminate the last unknowns (x_last = fd - fa x_first - fc x_next_first):
+    // A x_prev_first + B x_first + C x_next_first = D, one row per lane.
+    const double fa_m = __shfl(fa, lane > 0 ? lane - 1 : 0, 64);
+    const double fc_m = __shfl(fc, lane > 0 ? lane - 1 : 0, 64);
+    const double fd_m = __shfl(fd, lane > 0 ? lane - 1 : 0, 64);
+    double A = 0.0, B = 1.0, C = 0.0, D = 0.0;
+    if (len == 1) {  // size == 1: a single unknown
+        B = eb;
+        D = ed;
+    } else if (act) {
+        const double em = (lane > 0) ? ea : 0.0;
+        A = -em * fa_m;
+        B = eb - em * fc_m - ec * fa;
+        C = -ec * fc;
+        D = ed - em * fd_m - ec * fd;
+    }
+    for (int st = 1; st < 64; st <<= 1) {
+        const bool lo = lane >= st, hi = lane + st < 64;
+        const int sl = lo ? lane - st : lane, sh = hi ? lane + st : lane;
+        const double am = __shfl(A, sl, 64), bm = __shfl(B, sl, 64), cm = __shfl(C, sl, 64),
+                     dm = __shfl(D, sl, 64);
+        const double aq = __shfl(A, sh, 64), bq = __shfl(B, sh, 64), cq = __shfl(C, sh, 64),
+                     dq = __shfl(D, sh, 64);
+        const double al = lo ? -A / bm : 0.0, ga = hi ? -C / bq : 0.0;
+        const double A2 = lo ? al * am : 0.0, C2 = hi ? ga * cq : 0.0;
+        const double B2 = B + (lo ? al * cm : 0.0) + (hi ? ga * aq : 0.0);
+        const double D2 = D + (lo ? al * dm : 0.0) + (hi ? ga * dq : 0.0);
+        A = A2;
+        B = B2;
+        C = C2;
+        D = D2;
+    }
+    const double x0 = D / B;
+    const double xn = __shfl(x0, lane < 63 ? lane + 1 : lane, 64);
+    const double xl = fd - fa * x0 - fc * xn;
+    __syncthreads();
+    if (k == 0 && lane == 0) sz[n - 1] = 0.0;  // the dropped last unknown of mode 0
+#pragma unroll
+    for (int j = 0; j < kTriChunk; ++j) {
+        if (j < len) {
+            const double z = (j == 0) ? x0 : (j == len - 1) ? xl : dp[j] - ap[j] * x0 - cp[j] * xl;
+            sz[r0 + j] = z;
+        }
+    }
+    __syncthreads();
+    double zmean = 0.0;
     if (k == 0) {
-        double v[1] = {z};
-        rbf::block_sum<1>(v, red);
-        if (i < n) z -= v[0] / n;
+        double s = 0.0;
+        for (int i = lane; i < n; i += 64) s += sz[i];
+        zmean = rbf::wave_sum(s) / n;
     }
-    double zv[1] = {0.0};
-    if (i < n) {
-        static_cast<TP *>(L.W)[(int64_t)k * n + i] = (TP)z;
-        zv[0] = z * L.V[(int64_t)k * n + i];
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < kTriChunk; ++m) {
+        const int i = lane + 64 * m;
+        if (i < n) {
+            const double z = sz[i] - zmean;
+            static_cast<TP *>(L.W)[(int64_t)k * n + i] = (TP)z;
+            acc += z * vv[m];
+        }
     }
-    rbf::block_sum<1>(zv, red);
-    if (i == 0) L.partW[k] = zv[0];
+    acc = rbf::wave_sum(acc);
+    if (lane == 0) L.partW[k] = acc;
 }
 
 // Lattice value of L5^-1 at node (i, j), before the constant shift (Z in X).
@@ -830,20 +971,35 @@ __global__ void __launch_bounds__(kThreads) k_pc_post(Lat L, PKry K, const doubl
                                                        double *__restrict__ out, int64_t m,
                                                        double *partS, const double *partG,
                                                        int nbG) {
-    if (K.flag[0] != 0) return;
     const int Kl = L.K;
-    double bw[1], bg[1];
-    load_partials<1>(L.partW, L.n, bw);
-    load_partials<1>(partG, nbG, bg);
-    const double alpha = (*L.mean / L.c - (bw[0] + bg[0])) / (double)m;
+    // The first row's cell data and the partial sums are loaded before the
+    // flag test (one memory round trip for all of them).
+    const int64_t row0 = row_of(0);
+    int c_0 = 0;
+    double fx_0 = 0.0, fy_0 = 0.0;
+    if (row0 < m) {
+        c_0 = L.cell[row0];
+        fx_0 = L.fx[row0];
+        fy_0 = L.fy[row0];
+    }
+    double bwg[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < L.n; b += blockDim.x) bwg[0] += L.partW[b];
+    for (int b = threadIdx.x; b < nbG; b += blockDim.x) bwg[1] += partG[b];
+    const double mean = *L.mean;
+    if (K.flag[0] != 0) return;
+    {
+        __shared__ double lds[2 * (kThreads / 64)];
+        rbf::block_sum<2>(bwg, lds);
+    }
+    const double alpha = (mean / L.c - (bwg[0] + bwg[1])) / (double)m;
     double acc[1] = {0.0};
     for (int64_t it = 0;; ++it) {
         const int64_t row = row_of(it);
         if (row - threadIdx.x >= m) break;
         if (row < m) {
-            const int c = L.cell[row];
+            const int c = (it == 0) ? c_0 : L.cell[row];
             const int i0 = c % (Kl + 1), j0 = c / (Kl + 1);
-            const double fx = L.fx[row], fy = L.fy[row];
+            const double fx = (it == 0) ? fx_0 : L.fx[row], fy = (it == 0) ? fy_0 : L.fy[row];
             const double z00 = pc_lattice(L, y, i0, j0), z10 = pc_lattice(L, y, i0 + 1, j0);
             const double z01 = pc_lattice(L, y, i0, j0 + 1), z11 = pc_lattice(L, y, i0 + 1, j0 + 1);
             const double z = ((1.0 - fy) * ((1.0 - fx) * z00 + fx * z10) +
@@ -860,27 +1016,65 @@ __global__ void __launch_bounds__(kThreads) k_pc_post(Lat L, PKry K, const doubl
 template <int KT, int MODE>
 __global__ void __launch_bounds__(kThreads) k_pc_av(EllM A, PKry K, const double *__restrict__ y,
                                                      double *__restrict__ out) {
-    if (K.flag[0] != 0) return;
     const int nb = gridDim.x;
+    // Loads first (see k_pc_dir): the flag, the partial sums of the border
+    // term and the first row's stencil indices and vector entries; the
+    // weights and the gathers go out after the flag test, so a launch after
+    // convergence costs one memory round trip.
+    const int fl = K.flag[0];
     double sy[1] = {0.0};
-    if (A.u1) load_partials<1>(K.partS, nb, sy);
+    if (A.u1)
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) sy[0] += K.partS[b];
+    auto rowval = [&](int64_t row, double &ay, double &u1, double &rh, double &sv) {
+        rh = K.rh[row];
+        sv = (MODE == 1) ? K.s[row] : 0.0;
+        u1 = A.u1 ? A.u1[row] * A.vscale : 0.0;
+        double a[1][1] = {};
+        const double *ws[1] = {A.w};
+        rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherN<1>{y, A.n}, a);
+        ay = a[0][0];
+    };
+    const int64_t row0 = row_of(0);
+    const bool has0 = row0 < A.n;
+    constexpr int KP = KT > 0 ? KT : 1;
+    int jj[KP];
+    double f_u1 = 0.0, f_rh = 0.0, f_s = 0.0;
+    if (KT > 0 && has0) {
+#pragma unroll
+        for (int q = 0; q < KP; ++q) jj[q] = rbf::ld_stream(A.idx + (int64_t)q * A.n + row0);
+        f_rh = K.rh[row0];
+        f_s = (MODE == 1) ? K.s[row0] : 0.0;
+        f_u1 = A.u1 ? A.u1[row0] * A.vscale : 0.0;
+    }
+    if (fl != 0) return;
+    if (A.u1) {
+        __shared__ double lds[kThreads / 64];
+        rbf::block_sum<1>(sy, lds);
+    }
     constexpr int NQ = MODE == 0 ? 1 : 3;
     double acc[NQ] = {};
     for (int64_t it = 0;; ++it) {
         const int64_t row = row_of(it);
         if (row - threadIdx.x >= A.n) break;
         if (row < A.n) {
-            double ay[1][1] = {};
-            const double *ws[1] = {A.w};
-            rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherN<1>{y, A.n}, ay);
-            const double u1 = A.u1 ? A.u1[row] * A.vscale : 0.0;
-            const double val = ay[0][0] + u1 * sy[0];
+            double ay = 0.0, u1, rh, sv;
+            if (KT > 0 && it == 0) {
+                double ww[KP];
+#pragma unroll
+                for (int q = 0; q < KP; ++q) ww[q] = rbf::ld_stream(A.w + (int64_t)q * A.n + row0);
+#pragma unroll
+                for (int q = 0; q < KP; ++q) ay = fma(ww[q], y[jj[q]], ay);
+                u1 = f_u1;
+                rh = f_rh;
+                sv = f_s;
+            } else {
+                rowval(row, ay, u1, rh, sv);
+            }
+            const double val = ay + u1 * sy[0];
             out[row] = val;
-            const double rh = K.rh[row];
             if constexpr (MODE == 0) {
                 acc[0] += rh * val;
             } else {
-                const double sv = K.s[row];
                 acc[0] += val * sv;
                 acc[1] += val * val;
                 acc[2] += rh * val;
@@ -1566,10 +1760,10 @@ rbf_status bicgstab(rbf_solver *S, KDev &K, EllM A, const double *b, double *x, 
 }
 
 // One application of the lattice preconditioner's interior solve:
-// T = Q^-1 X, Thomas along y per x-mode, Z = Q W.
+// T = Q^-1 X, tridiagonal solves along y per x-mode, Z = Q W.
 rbf_status pc_apply(rbf_solver *S, bool sample = false) {
     const dim3 g(S->lat.ntiles), b(64 * kGemmWaves);
-    const dim3 gt(S->lat.n), bt(kTriThreads);
+    const dim3 gt(S->lat.n), bt(64);
     // A sample times the first product (its own start and end stamps).
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool timed = sample && prof_pair(S, RBF_PROF_GEMM, e0, e1);
@@ -1858,10 +2052,10 @@ rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
                 "(K+1)^2 lattice of the unit square (row-major, walls tagged)");
         return RBF_OK;
     }
-    if (K - 1 > kTriThreads) {  // the tridiagonal kernel holds one mode per workgroup
+    if (K - 1 > 64 * kTriChunk) {  // the tridiagonal kernel holds one mode per wavefront
         RBF_ARG(mode != RBF_PRECOND_LATTICE,
                 "rbf_solver_create: RBF_PRECOND_LATTICE supports K <= %d (got K = %d)",
-                kTriThreads + 1, K);
+                64 * kTriChunk + 1, K);
         return RBF_OK;
     }
     const int n = K - 1;
