@@ -516,7 +516,7 @@ struct PKry {
 };
 
 // Iterations without progress after which the preconditioned iteration restarts.
-constexpr int kStall = 30;
+constexpr int kStall = 8;
 
 // Reduced right-hand side at interior lattice node `row` = (i, j), from the
 // values val(node) of the vector y being preconditioned: D^-1 y with the
@@ -1562,6 +1562,8 @@ struct rbf_solver {
     KDev kp{};
     double *rpart = nullptr;
     int last_iters_h = 0, last_iters_p = 0;
+    int p_hist[3] = {0, 0, 0};  // iteration counts of the last pressure solves (ring)
+    int p_nhist = 0, p_pos = 0;
     // optional sampling of the Poisson SpMV duration with HIP events
     // Sampled kernel durations (rbf_solver_profile): event pairs recorded
     // around sampled launches, read after the solver's next stream sync.
@@ -1815,7 +1817,15 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
     init();
     int it = 0, i0 = 0, restarts = 0;
     rbf_status rc = RBF_OK;
-    int batch = std::max(2, last_iters > 0 ? last_iters - 1 : 8);
+    // Launch plan.  Launches after convergence exit after their first loads
+    // but still cost a few microseconds each, and every batch ends with a
+    // host synchronisation: the first batch stops a few iterations short of
+    // the fewest among the last three solves, later batches grow 2, 2, 4, 8,
+    // 16 (after a restart, from 4).
+    int expect = 0;
+    for (int q = 0; q < S->p_nhist; ++q) expect = q ? std::min(expect, S->p_hist[q]) : S->p_hist[q];
+    int batch = S->p_nhist ? std::max(2, expect - 4) : 8;
+    int grow = 2, small = 0;
     bool done = false;
     while (!done) {
         const int stop = std::min(maxit + 1, it + batch);
@@ -1848,13 +1858,13 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
             it = i0 = S->hflag[kMaxNR];
             init();
             done = false;
+            batch = 4;
+            grow = 8;
             continue;
         }
         if (!done && it > maxit) break;
-        // After the first batch (sized by the previous solve) the remaining
-        // iterations are usually few: small batches limit the launches made
-        // after convergence.
-        batch = (it - i0 < 2 * last_iters) ? 2 : std::max(2, std::min(16, (it - i0) / 4));
+        batch = grow;
+        if (++small > 1) grow = std::min(16, 2 * grow);
     }
     if (A.u1) hipLaunchKernelGGL((k_sum<1>), grid, block, 0, st, m, x, partX);
     if (k28) hipLaunchKernelGGL((k_resid<1, 28>), grid, block, 0, st, A, b, x, S->rpart, partX);
@@ -1884,6 +1894,11 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
         rc = RBF_E_NOCONV;
     }
     last_iters = iters;
+    if (f == 1) {
+        S->p_hist[S->p_pos] = iters;
+        S->p_pos = (S->p_pos + 1) % 3;
+        S->p_nhist = std::min(3, S->p_nhist + 1);
+    }
     return rc;
 }
 
