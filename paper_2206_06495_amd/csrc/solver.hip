@@ -770,6 +770,9 @@ constexpr int kGemmWaves = 8;
 constexpr int kGemmChunk = 14;
 template <int STAGE, bool ONESHOT, class TP>
 __global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
+    // The flag is tested first: a launch after convergence would otherwise
+    // fetch its whole operand share before exiting.
+    if (*L.flag != 0) return;
     const int n = L.n, nt = (n + 15) / 16;
     const int ti = (int)(blockIdx.x % nt), tj = (int)(blockIdx.x / nt);
     const TP *A = static_cast<const TP *>(STAGE == 0 ? L.Qi : L.Q);
@@ -780,8 +783,7 @@ __global__ void __launch_bounds__(64 * kGemmWaves) k_pc_gemm(Lat L) {
         n, A, B, ti, tj, [&](int i, int j, TP v) {
             if constexpr (STAGE == 0) C[(int64_t)i * n + j] = v;
             else C[i + (int64_t)j * n] = v;
-        },
-        L.flag);
+        });
 }
 
 // For each x-mode k (one wavefront): (T + lam_k I) w = h^2 t along y.  The
@@ -1017,10 +1019,10 @@ template <int KT, int MODE>
 __global__ void __launch_bounds__(kThreads) k_pc_av(EllM A, PKry K, const double *__restrict__ y,
                                                      double *__restrict__ out) {
     const int nb = gridDim.x;
-    // Loads first (see k_pc_dir): the flag, the partial sums of the border
-    // term and the first row's stencil indices and vector entries; the
-    // weights and the gathers go out after the flag test, so a launch after
-    // convergence costs one memory round trip.
+    // The flag and the partial sums of the border term are loaded together
+    // and tested before the row's loads (a launch after convergence then
+    // exits after one short round trip); the first row's indices and
+    // vector entries go out before the partial sums are reduced.
     const int fl = K.flag[0];
     double sy[1] = {0.0};
     if (A.u1)
@@ -1034,6 +1036,7 @@ __global__ void __launch_bounds__(kThreads) k_pc_av(EllM A, PKry K, const double
         rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherN<1>{y, A.n}, a);
         ay = a[0][0];
     };
+    if (fl != 0) return;
     const int64_t row0 = row_of(0);
     const bool has0 = row0 < A.n;
     constexpr int KP = KT > 0 ? KT : 1;
@@ -1046,7 +1049,6 @@ __global__ void __launch_bounds__(kThreads) k_pc_av(EllM A, PKry K, const double
         f_s = (MODE == 1) ? K.s[row0] : 0.0;
         f_u1 = A.u1 ? A.u1[row0] * A.vscale : 0.0;
     }
-    if (fl != 0) return;
     if (A.u1) {
         __shared__ double lds[kThreads / 64];
         rbf::block_sum<1>(sy, lds);
