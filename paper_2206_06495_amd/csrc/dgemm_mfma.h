@@ -48,12 +48,9 @@ struct mfma16<float> {
     static __device__ __forceinline__ int row(int r, int lk) { return 4 * lk + r; }
 };
 
-// gate (nullable): the block returns without a product when *gate != 0;
-// it is read after the first operand loads are issued, so that the test
-// costs no memory round trip of its own.
 template <class T, int TM, int TN, int S, int C, bool ONESHOT, class Epi>
 __device__ __forceinline__ bool mfma_block(int n, const T *__restrict__ A, const T *__restrict__ B,
-                                           int bm, int bn, Epi epi, const int *gate = nullptr) {
+                                           int bm, int bn, Epi epi) {
     using M = mfma16<T>;
     using acc4 = typename M::acc4;
     constexpr int NT = TM * TN;
@@ -79,7 +76,6 @@ __device__ __forceinline__ bool mfma_block(int n, const T *__restrict__ A, const
     acc4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     T a[C], b[C];
     load(s0, a, b);
-    if (gate && *gate != 0) return false;  // uniform over the block
     if constexpr (ONESHOT) {
         // The whole k-share fits in one chunk (per <= C, checked by the
         // caller): every operand load is in flight before the first MFMA.
