@@ -515,7 +515,8 @@ struct PKry {
     int *flag, *iters;
 };
 
-// Iterations without progress after which the preconditioned iteration restarts.
+// Iterations without progress after which the preconditioned iteration
+// restarts; the window doubles after every restart of a solve.
 constexpr int kStall = 8;
 
 // Reduced right-hand side at interior lattice node `row` = (i, j), from the
@@ -680,7 +681,7 @@ __global__ void __launch_bounds__(kThreads) k_pc_dir(PKry K, Lat L, double *__re
 // Iteration i, step 2: convergence test on ||r_i||, alpha = rho / (rh, v),
 // s = r - alpha v and its reduced right-hand side.
 __global__ void __launch_bounds__(kThreads) k_pc_s(PKry K, Lat L, int64_t m, int i, int i0,
-                                                    double tol2) {
+                                                    double tol2, int win) {
     const int nb = gridDim.x;
     // Loads first (see k_pc_dir).
     const int fl = K.flag[0];
@@ -691,7 +692,7 @@ __global__ void __launch_bounds__(kThreads) k_pc_s(PKry K, Lat L, int64_t m, int
     }
     const double rho = K.rec[(int64_t)i * 4];
     const double bb = K.bb[0], rhrh = K.rhrh[0];
-    // Stagnation: no 0.1% decrease of the best ||r||^2 for kStall iterations
+    // Stagnation: no 0.1% decrease of the best ||r||^2 for win iterations
     // is handled like a breakdown (restart from the true residual).  The best
     // value is double-buffered by parity: read from the previous launch,
     // written for the next one.
@@ -717,7 +718,7 @@ __global__ void __launch_bounds__(kThreads) k_pc_s(PKry K, Lat L, int64_t m, int
     const double best = fresh ? rr : bp0;
     const int best_it = fresh ? i : (int)bp1;
     const bool better = fresh || rr < 0.999 * best;
-    const bool stall = !better && (i - best_it >= kStall);
+    const bool stall = !better && (i - best_it >= win);
     const bool brk = !bad && !conv &&
                      (!(fabs(rho) > kBreakdown * sqrt(rr * rhrh)) || !isfinite(al) || stall);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1101,6 +1102,7 @@ struct HKry {
     double *part6;  // (t, s), (t, t), (rh, t) (2 each)
     double *rec;    // [iteration][component] {rho, alpha, omega, ||r||^2}
     double *bb, *rhrh;
+    double *best;   // [parity][component][2] {best ||r||^2, its iteration}
     int *flag, *iters;
 };
 
@@ -1241,8 +1243,10 @@ __global__ void __launch_bounds__(kThreads) k_h_av(EllM A, HKry K, const double 
 }
 
 // Convergence test on ||r_i||, alpha, s = r - alpha v and s^ = D^-1 s.
+// Stagnation (no 0.1% decrease of a component's best ||r||^2 for win
+// iterations) is handled like a breakdown, as in k_pc_s.
 __global__ void __launch_bounds__(kThreads) k_h_s(HKry K, const double *__restrict__ dinv,
-                                                   int64_t n, int i, double tol2) {
+                                                   int64_t n, int i, int i0, double tol2, int win) {
     if (h_done(K.flag)) return;
     const int nb = gridDim.x;
     double q1[kHR], q3[kHR];
@@ -1260,12 +1264,21 @@ __global__ void __launch_bounds__(kThreads) k_h_s(HKry K, const double *__restri
         const double bb = K.bb[c], rhrh = K.rhrh[c];
         const bool bad = !isfinite(rr) || !isfinite(rho);
         const bool conv = !bad && (rr <= tol2 * fmax(bb, 1e-300) || rr == 0.0);
+        const double *bprev = K.best + ((((i + 1) & 1) * kHR) + c) * 2;
+        const bool fresh = (i == i0);
+        const double best = fresh ? rr : bprev[0];
+        const int best_it = fresh ? i : (int)bprev[1];
+        const bool better = fresh || rr < 0.999 * best;
+        const bool stall = !better && (i - best_it >= win);
         const bool brk = !bad && !conv &&
-                         (!(fabs(rho) > kBreakdown * sqrt(rr * rhrh)) || !isfinite(al[c]));
+                         (!(fabs(rho) > kBreakdown * sqrt(rr * rhrh)) || !isfinite(al[c]) || stall);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             double *rc = K.rec + ((int64_t)i * kHR + c) * 4;
             rc[1] = al[c];
             rc[3] = rr;
+            double *bnext = K.best + (((i & 1) * kHR) + c) * 2;
+            bnext[0] = better ? rr : best;
+            bnext[1] = better ? (double)i : (double)best_it;
             if (bad) K.flag[c] = -1;
             else if (conv || brk) {
                 K.flag[c] = conv ? 1 : 2;
@@ -1828,6 +1841,7 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
     for (int q = 0; q < S->p_nhist; ++q) expect = q ? std::min(expect, S->p_hist[q]) : S->p_hist[q];
     int batch = S->p_nhist ? std::max(2, expect - 4) : 8;
     int grow = 2, small = 0;
+    int win = kStall;
     bool done = false;
     while (!done) {
         const int stop = std::min(maxit + 1, it + batch);
@@ -1841,7 +1855,7 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (sample) prof_pair(S, RBF_PROF_SPMV, e0, e1);
             av(0, K.ph, K.v, e0, e1);
-            hipLaunchKernelGGL(k_pc_s, grid, block, 0, st, K, L, m, it, i0, tol2);
+            hipLaunchKernelGGL(k_pc_s, grid, block, 0, st, K, L, m, it, i0, tol2, win);
             if ((rc = pc_apply(S)) != RBF_OK) return rc;
             hipLaunchKernelGGL(k_pc_post, grid, block, 0, st, L, K, K.s, K.sh, m, K.partS,
                                K.partGs, nb);
@@ -1862,6 +1876,7 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
             done = false;
             batch = 4;
             grow = 8;
+            win = std::min(2 * win, 1 << 20);
             continue;
         }
         if (!done && it > maxit) break;
@@ -1934,13 +1949,14 @@ rbf_status hbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
     int it = 0, i0 = 0, restarts = 0;
     rbf_status rc = RBF_OK;
     int batch = std::max(2, last_iters > 0 ? last_iters : 4);
+    int win = kStall;
     bool done = false;
     while (!done) {
         const int stop = std::min(maxit + 1, it + batch);
         for (; it < stop; ++it) {
             hipLaunchKernelGGL(k_h_dir, grid, block, 0, st, K, A.dinv, x, n, it, i0);
             av(0, K.ph, K.v);
-            hipLaunchKernelGGL(k_h_s, grid, block, 0, st, K, A.dinv, n, it, tol2);
+            hipLaunchKernelGGL(k_h_s, grid, block, 0, st, K, A.dinv, n, it, i0, tol2, win);
             av(1, K.sh, K.t);
         }
         RBF_CHECK_LAUNCH();
@@ -1963,6 +1979,7 @@ rbf_status hbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
             it = i0 = brk_at;
             init();
             done = false;
+            win = std::min(2 * win, 1 << 20);
             continue;
         }
         if (!done && it > maxit) break;
@@ -2239,6 +2256,7 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
         ALLOC(H.rec, (int64_t)(S->maxit_h + 2) * kHR * 4);
         ALLOC(H.bb, kHR);
         ALLOC(H.rhrh, kHR);
+        ALLOC(H.best, 2 * kHR * 2);
         ALLOC(H.flag, kHR);
         ALLOC(H.iters, kHR);
     }
