@@ -1500,20 +1500,26 @@ __global__ void k_build_poisson(int64_t m, int k, const int *__restrict__ idx,
 
 // Warm start of the pressure solve by extrapolation in time from the
 // previous solutions: ORDER 1: x0 = 2 x_j - x_{j-1}; ORDER 2:
-// x0 = 3 x_j - 3 x_{j-1} + x_{j-2}; the history shifts by one step.
+// x0 = 3 x_j - 3 x_{j-1} + x_{j-2}; ORDER 3: x0 = 4 x_j - 6 x_{j-1} +
+// 4 x_{j-2} - x_{j-3}; the history shifts by one step.
 template <int ORDER>
 __global__ void k_extrapolate(int64_t n, double *__restrict__ x, double *__restrict__ x1,
-                              double *__restrict__ x2) {
+                              double *__restrict__ x2, double *__restrict__ x3) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= n) return;
     const double t = x[r], t1 = x1[r];
-    if constexpr (ORDER == 2) {
-        x[r] = 3.0 * t - 3.0 * t1 + x2[r];
-        x2[r] = t1;
+    if constexpr (ORDER == 3) {
+        const double t2 = x2[r];
+        x[r] = 4.0 * t - 6.0 * t1 + 4.0 * t2 - x3[r];
+        x3[r] = t2;
+    } else if constexpr (ORDER == 2) {
+        const double t2 = x2[r];
+        x[r] = 3.0 * t - 3.0 * t1 + t2;
+        x3[r] = t2;
     } else {
         x[r] = 2.0 * t - t1;
-        x2[r] = t1;
     }
+    x2[r] = t1;
     x1[r] = t;
 }
 
@@ -1560,7 +1566,7 @@ struct rbf_solver {
            *pv_dy = nullptr, *pp_lap = nullptr, *vp_dx = nullptr, *vp_dy = nullptr;
     double *h_w = nullptr, *h_dinv = nullptr, *p_w = nullptr, *p_dinv = nullptr,
            *p_rowscale = nullptr, *p_rhs_tmp = nullptr, *p_u1 = nullptr, *p_warm = nullptr,
-           *p_prev = nullptr, *p_prev2 = nullptr;
+           *p_prev = nullptr, *p_prev2 = nullptr, *p_prev3 = nullptr;
     int have_prev = 0;  // previous solutions held in p_prev, p_prev2 (within one rbf_step call)
     double *hh[3] = {nullptr, nullptr, nullptr};  // previous viscous solutions [2][N], latest first
     int have_h = 0;
@@ -2232,6 +2238,7 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     ALLOC(S->p_warm, M);
     ALLOC(S->p_prev, M);
     ALLOC(S->p_prev2, M);
+    ALLOC(S->p_prev3, M);
     for (double *&q : S->hh) ALLOC(q, 2 * N);
     ALLOC(S->p_rhs_tmp, M);
     ALLOC(S->p_tag, M);
@@ -2371,14 +2378,18 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
                            S->pv_dy, S->uvss, S->uvss + N, S->p_tag, 1.0 / S->dt,
                            S->p_rowscale, S->prhs);
     });
-    // Initial guess: the previous solution, linearly extrapolated in time
-    // from the two previous steps of this call when available.
-    if (S->have_prev >= 2) {
+    // Initial guess: the previous solutions of this call extrapolated in
+    // time (up to cubic, from the last four).
+    if (S->have_prev >= 3) {
+        hipLaunchKernelGGL(k_extrapolate<3>, dim3(rbf::blocks_for(M, 256)), dim3(256), 0, st, M,
+                           S->p_warm, S->p_prev, S->p_prev2, S->p_prev3);
+    } else if (S->have_prev == 2) {
         hipLaunchKernelGGL(k_extrapolate<2>, dim3(rbf::blocks_for(M, 256)), dim3(256), 0, st, M,
-                           S->p_warm, S->p_prev, S->p_prev2);
+                           S->p_warm, S->p_prev, S->p_prev2, S->p_prev3);
+        S->have_prev = 3;
     } else if (S->have_prev == 1) {
         hipLaunchKernelGGL(k_extrapolate<1>, dim3(rbf::blocks_for(M, 256)), dim3(256), 0, st, M,
-                           S->p_warm, S->p_prev, S->p_prev2);
+                           S->p_warm, S->p_prev, S->p_prev2, S->p_prev3);
         S->have_prev = 2;
     } else {
         RBF_HIP(hipMemcpyAsync(S->p_prev, S->p_warm, M * sizeof(double), hipMemcpyDeviceToDevice, st));
