@@ -512,7 +512,11 @@ struct PKry {
     double *rec;    // per iteration {rho, alpha, omega, ||r||^2}
     double *bb, *rhrh;
     double *best;   // [2][2] {best ||r||^2, its iteration}, by iteration parity
+    // Status block read by the host after each batch in one copy: flag,
+    // iters, then (as doubles) ||r_i||^2 of the last tested iteration i, of
+    // iteration max(i0, i - 4), and ||b||^2.
     int *flag, *iters;
+    double *stat;
 };
 
 // Iterations without progress after which the preconditioned iteration
@@ -728,6 +732,10 @@ __global__ void __launch_bounds__(kThreads) k_pc_s(PKry K, Lat L, int64_t m, int
         double *bnext = K.best + (i & 1) * 2;
         bnext[0] = better ? rr : best;
         bnext[1] = better ? (double)i : (double)best_it;
+        const int back = max(i0, i - 4);
+        K.stat[0] = rr;
+        K.stat[1] = (back == i) ? rr : K.rec[(int64_t)back * 4 + 3];
+        K.stat[2] = bb;
         if (bad) K.flag[0] = -1;
         else if (conv || brk) {
             K.flag[0] = conv ? 1 : 2;
@@ -1841,8 +1849,10 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
     // Launch plan.  Launches after convergence exit after their first loads
     // but still cost a few microseconds each, and every batch ends with a
     // host synchronisation: the first batch stops a few iterations short of
-    // the fewest among the last three solves, later batches grow 2, 2, 4, 8,
-    // 16 (after a restart, from 4).
+    // the fewest among the last three solves; later batches cover the
+    // iterations still needed at the residual's recent rate of decrease
+    // (from the status block), or grow 2, 2, 4, 8, 16 when no rate is known
+    // (after a restart, from 4).
     int expect = 0;
     for (int q = 0; q < S->p_nhist; ++q) expect = q ? std::min(expect, S->p_hist[q]) : S->p_hist[q];
     int batch = S->p_nhist ? std::max(2, expect - 4) : 8;
@@ -1868,16 +1878,17 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
             av(1, K.sh, K.t, nullptr, nullptr);
         }
         RBF_CHECK_LAUNCH();
-        RBF_HIP(hipMemcpyAsync(S->hflag, K.flag, sizeof(int), hipMemcpyDeviceToHost, st));
-        RBF_HIP(hipMemcpyAsync(S->hflag + kMaxNR, K.iters, sizeof(int), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipMemcpyAsync(S->hflag, K.flag, 2 * sizeof(int) + 3 * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
         RBF_HIP(hipStreamSynchronize(st));
         prof_flush(S);
         const int f = S->hflag[0];
+        const double *hs = reinterpret_cast<const double *>(S->hflag + 2);
         done = (f != 0);
         if (f == 2 && it <= maxit && restarts < 50) {
             // Breakdown: restart from the current iterate with rh = r.
             ++restarts;
-            it = i0 = S->hflag[kMaxNR];
+            it = i0 = S->hflag[1];
             init();
             done = false;
             batch = 4;
@@ -1888,6 +1899,15 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
         if (!done && it > maxit) break;
         batch = grow;
         if (++small > 1) grow = std::min(16, 2 * grow);
+        // Every launched iteration ran (no flag): hs[0] is ||r||^2 at it - 1,
+        // hs[1] at max(i0, it - 5).
+        const int span = std::min(4, it - 1 - i0);
+        if (span > 0 && hs[0] > 0.0 && hs[1] > 0.0) {
+            const double rate = std::log(hs[0] / hs[1]) / span;  // per iteration
+            const double need = std::log(tol2 * std::fmax(hs[2], 1e-300) / hs[0]);
+            if (rate < -1e-3 && std::isfinite(rate) && std::isfinite(need))
+                batch = std::max(1, std::min(8, (int)(need / rate)));
+        }
     }
     if (A.u1) hipLaunchKernelGGL((k_sum<1>), grid, block, 0, st, m, x, partX);
     if (k28) hipLaunchKernelGGL((k_resid<1, 28>), grid, block, 0, st, A, b, x, S->rpart, partX);
@@ -1900,7 +1920,7 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
     for (int bidx = 0; bidx < nb; ++bidx) rr += S->hred[bidx];
     const double bb = S->hred[kMaxNR * kMaxBlocks];
     const int f = S->hflag[0];
-    const int iters = (f == 1) ? S->hflag[kMaxNR] : it;
+    const int iters = (f == 1) ? S->hflag[1] : it;
     if (stats) {
         stats->iterations = iters;
         stats->converged = (f == 1);
@@ -2153,8 +2173,9 @@ rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
     ALLOC(P.bb, 1);
     ALLOC(P.rhrh, 1);
     ALLOC(P.best, 4);
-    ALLOC(P.flag, 1);
-    ALLOC(P.iters, 1);
+    ALLOC(P.flag, 8);  // flag, iters, 3 status doubles (see PKry)
+    P.iters = P.flag + 1;
+    P.stat = reinterpret_cast<double *>(P.flag + 2);
     RBF_HIP(hipMemcpyAsync(dcell, cell.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
     RBF_HIP(hipMemcpyAsync(dfx, fx.data(), M * sizeof(double), hipMemcpyHostToDevice, st));
     RBF_HIP(hipMemcpyAsync(dfy, fy.data(), M * sizeof(double), hipMemcpyHostToDevice, st));
