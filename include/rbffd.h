@@ -228,7 +228,7 @@ typedef struct {
 } rbf_state;
 
 typedef struct {
-    int32_t iterations;    /* BiCGSTAB iterations of this solve             */
+    int32_t iterations;    /* BiCGSTAB iterations (or Jacobi sweeps)        */
     int32_t converged;     /* 1 if the tolerance was met                    */
     double rel_residual;   /* ||b - A x|| / ||b|| recomputed at the end     */
     int32_t restarts;      /* restarts after a BiCGSTAB breakdown           */
@@ -250,7 +250,10 @@ typedef struct rbf_solver rbf_solver;
  *
  * Helmholtz (eq. (16)): H = I - a D_Lap^(V,V), a = dt/(2 Re), on interior
  * V rows, identity on wall rows (which carry the Kim-Moin values of
- * eq. (21)); solved by Jacobi-preconditioned BiCGSTAB.
+ * eq. (21)).  When the Jacobi iteration matrix I - D^-1 H (D = diag H) has
+ * infinity norm <= 0.25 (small a, as at the paper's time steps on fine
+ * grids), H is solved by Jacobi sweeps, whose residual test uses the true
+ * residual; otherwise by Jacobi-preconditioned BiCGSTAB.
  * Pressure Poisson (eq. (18)): D_Lap^(P,P) on interior P rows and
  * homogeneous Neumann rows n_x D_x^(P,P) + n_y D_y^(P,P) on wall rows.  The
  * paper states no pressure boundary condition; with Neumann rows the
@@ -343,6 +346,20 @@ rbf_status rbf_solver_apply_precond(rbf_solver *s, const double *y, double *z);
 #define RBF_PROF_N 2
 rbf_status rbf_solver_profile(rbf_solver *s, int32_t sample_every, double *avg_ms,
                               int64_t *count);
+
+/*
+ * rbf_solver_query -- how the solver runs its solves (host struct, filled):
+ * viscous_jacobi 1 when the viscous solve uses Jacobi sweeps (see
+ * rbf_solver_create), jacobi_bound the infinity norm of I - D^-1 H that
+ * decided it, lattice_precond 1 when the pressure solve uses the lattice
+ * preconditioner.  Errors: RBF_E_ARG (NULL argument).
+ */
+typedef struct {
+    int32_t viscous_jacobi;
+    int32_t lattice_precond;
+    double jacobi_bound;
+} rbf_solver_info;
+rbf_status rbf_solver_query(rbf_solver *s, rbf_solver_info *info);
 
 /* Release a solver (NULL is ignored). */
 void rbf_solver_destroy(rbf_solver *s);

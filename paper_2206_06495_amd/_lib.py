@@ -25,7 +25,7 @@ FORCE_SMALL_STENCIL = 0x80000000
 EXPORTED = [
     "rbf_last_error", "rbf_abi_version", "rbf_build_nodes", "rbf_knn",
     "rbf_assemble_weights", "rbf_ell_apply", "rbf_cast_f32", "rbf_solver_create",
-    "rbf_step", "rbf_step_batch", "rbf_solve_pressure", "rbf_solver_apply_precond", "rbf_solver_profile",
+    "rbf_step", "rbf_step_batch", "rbf_solve_pressure", "rbf_solver_apply_precond", "rbf_solver_profile", "rbf_solver_query",
     "rbf_solver_destroy",
 ]
 
@@ -65,6 +65,11 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("restarts", ctypes.c_int32),
                 ("final_flag", ctypes.c_int32)]
+
+
+class SolverInfo(ctypes.Structure):
+    _fields_ = [("viscous_jacobi", ctypes.c_int32), ("lattice_precond", ctypes.c_int32),
+                ("jacobi_bound", ctypes.c_double)]
 
 
 class StepStats(ctypes.Structure):
@@ -118,6 +123,8 @@ def _load():
     lib.rbf_solver_apply_precond.argtypes = [c_void_p, c_void_p, c_void_p]
     lib.rbf_solver_profile.restype = S
     lib.rbf_solver_profile.argtypes = [c_void_p, ctypes.c_int32, c_double_p, c_int64_p]
+    lib.rbf_solver_query.restype = S
+    lib.rbf_solver_query.argtypes = [c_void_p, ctypes.POINTER(SolverInfo)]
     lib.rbf_solver_destroy.restype = None
     lib.rbf_solver_destroy.argtypes = [c_void_p]
     return lib

@@ -197,6 +197,13 @@ class Solver:
         check(lib.rbf_solver_profile(self._h, int(sample_every), avg, cnt))
         return {"gemm": (avg[0], cnt[0]), "spmv": (avg[1], cnt[1])}
 
+    def info(self):
+        """How the solves run: {"viscous_jacobi", "lattice_precond", "jacobi_bound"}."""
+        inf = _lib.SolverInfo()
+        check(lib.rbf_solver_query(self._h, ctypes.byref(inf)))
+        return {"viscous_jacobi": bool(inf.viscous_jacobi),
+                "lattice_precond": bool(inf.lattice_precond), "jacobi_bound": inf.jacobi_bound}
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib.rbf_solver_destroy(self._h)

@@ -1313,6 +1313,110 @@ __global__ void __launch_bounds__(kThreads) k_h_s(HKry K, const double *__restri
     }
 }
 
+// ------------------------------------------------ viscous Jacobi sweeps --
+// When the Jacobi iteration matrix of H has a small infinity norm (max over
+// rows of |1/h_ii| sum_{j != i} |h_ij|, at most kJacobiMax; H = I - a D_Lap
+// with a small a), the viscous solve runs plain Jacobi sweeps: one product
+// per sweep and no inner products to wait for, each sweep contracting the
+// error by that norm or better.  Sweep i: x_{i+1} = x_i + D^-1 (b - H x_i)
+// for both components, with block partials of ||b - H x_i||^2 and ||b||^2;
+// sweep i + 1 first reduces them and stops the iteration (flag) once x_i
+// passes the test, so the residual tested is the true one.
+constexpr double kJacobiMax = 0.25;
+struct JKry {
+    double *x[2];   // [2][N] iterates by parity (x[0] is the caller's x)
+    double *part;   // [2 parities][2 kHR][kMaxBlocks]
+    double *bb;     // ||b||^2 per component
+    int *flag;      // flag, then the index of the accepted iterate
+};
+
+template <int KT>
+__global__ void __launch_bounds__(kThreads) k_h_jac(EllM A, const double *__restrict__ b, JKry J,
+                                                     int i, double tol2) {
+    const int nb = gridDim.x;
+    const int fl = J.flag[0];
+    double q[2 * kHR] = {};
+    if (i > 0) {
+        const double *pp = J.part + (int64_t)((i - 1) & 1) * 2 * kHR * kMaxBlocks;
+        for (int bk = threadIdx.x; bk < nb; bk += blockDim.x)
+#pragma unroll
+            for (int c = 0; c < 2 * kHR; ++c) q[c] += pp[(int64_t)c * kMaxBlocks + bk];
+    }
+    if (fl != 0) return;
+    if (i > 0) {
+        __shared__ double lds[2 * kHR * (kThreads / 64)];
+        rbf::block_sum<2 * kHR>(q, lds);
+        bool conv = true, bad = false;
+#pragma unroll
+        for (int c = 0; c < kHR; ++c) {
+            bad = bad || !isfinite(q[c]);
+            conv = conv && (q[c] <= tol2 * fmax(q[kHR + c], 1e-300) || q[c] == 0.0);
+        }
+        if (bad || conv) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+                for (int c = 0; c < kHR; ++c) J.bb[c] = q[kHR + c];
+                J.flag[1] = i - 1;
+                J.flag[0] = bad ? -1 : 1;
+            }
+            return;
+        }
+    }
+    const double *xin = J.x[i & 1];
+    double *xout = J.x[(i & 1) ^ 1];
+    double acc[2 * kHR] = {};
+    for (int64_t it = 0;; ++it) {
+        const int64_t row = row_of(it);
+        if (row - threadIdx.x >= A.n) break;
+        if (row < A.n) {
+            double ax[1][kHR] = {};
+            const double *ws[1] = {A.w};
+            rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherN<kHR>{xin, A.n}, ax);
+            const double di = A.dinv[row];
+#pragma unroll
+            for (int c = 0; c < kHR; ++c) {
+                const int64_t o = c * A.n + row;
+                const double bv = b[o], rv = bv - ax[0][c];
+                xout[o] = xin[o] + di * rv;
+                acc[c] += rv * rv;
+                acc[kHR + c] += bv * bv;
+            }
+        }
+    }
+    __shared__ double lds2[2 * kHR * (kThreads / 64)];
+    rbf::block_sum<2 * kHR>(acc, lds2);
+    if (threadIdx.x == 0) {
+        double *pp = J.part + (int64_t)(i & 1) * 2 * kHR * kMaxBlocks;
+#pragma unroll
+        for (int c = 0; c < 2 * kHR; ++c) pp[(int64_t)c * kMaxBlocks + blockIdx.x] = acc[c];
+    }
+}
+
+// Block maxima of |1/h_ii| sum_{j != i} |h_ij| (the Jacobi bound above).
+__global__ void __launch_bounds__(256) k_jacobi_bound(int64_t n, int k, const int *__restrict__ idx,
+                                                      const double *__restrict__ hw,
+                                                      const double *__restrict__ dinv,
+                                                      double *__restrict__ part) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double q = 0.0;
+    if (r < n) {
+        double off = 0.0;
+        for (int s = 0; s < k; ++s) {
+            const int64_t o = (int64_t)s * n + r;
+            if (idx[o] != r) off += fabs(hw[o]);
+        }
+        q = fabs(dinv[r]) * off;
+    }
+    __shared__ double m[256];
+    m[threadIdx.x] = q;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) m[threadIdx.x] = fmax(m[threadIdx.x], m[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = m[0];
+}
+
 // ---------------------------------------------------------- step kernels --
 // Stage 1: C(q) = -(u o D_x q + v o D_y q), u* = u + dt (3/2 C_j - 1/2 C_{j-1}).
 template <int KT>
@@ -1606,6 +1710,9 @@ struct rbf_solver {
     bool pc_on = false;
     bool mixed = false;  // RBF_PRECISION_MIXED
     HKry hk{};           // viscous solve with explicit vectors
+    JKry jk{};           // viscous solve by Jacobi sweeps
+    bool h_jacobi = false;  // Jacobi bound of H <= kJacobiMax
+    double h_bound = 0.0;
     Lat lat{};
     PKry pk{};
     // pinned host buffers
@@ -1942,6 +2049,75 @@ rbf_status pbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
         S->p_pos = (S->p_pos + 1) % 3;
         S->p_nhist = std::min(3, S->p_nhist + 1);
     }
+    return rc;
+}
+
+// Viscous solve by Jacobi sweeps (see k_h_jac); same contract as hbicgstab.
+rbf_status hjacobi(rbf_solver *S, EllM A, const double *b, double *x, double tol, int maxit,
+                   int &last_iters, rbf_solve_stats *stats) {
+    hipStream_t st = S->st;
+    JKry J = S->jk;
+    J.x[0] = x;
+    const int64_t n = A.n;
+    const int nb = nblocks_rows(n);
+    const dim3 grid(nb), block(kThreads);
+    const double tol2 = tol * tol;
+    const bool k28 = A.k == 28;
+    RBF_HIP(hipMemsetAsync(J.flag, 0, 2 * sizeof(int), st));
+    // Sweep i tests x_{i-1}; x_maxit is tested by sweep maxit + 1.
+    int it = 0, f = 0;
+    int batch = std::max(2, last_iters + 2);
+    for (;;) {
+        const int stop = std::min(maxit + 2, it + batch);
+        for (; it < stop; ++it) {
+            if (k28) hipLaunchKernelGGL((k_h_jac<28>), grid, block, 0, st, A, b, J, it, tol2);
+            else hipLaunchKernelGGL((k_h_jac<0>), grid, block, 0, st, A, b, J, it, tol2);
+        }
+        RBF_CHECK_LAUNCH();
+        RBF_HIP(hipMemcpyAsync(S->hflag, J.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        f = S->hflag[0];
+        if (f != 0 || it >= maxit + 2) break;
+        batch = 2;
+    }
+    // The accepted iterate, or the newest one when the sweeps ran out.
+    const int fin = (f != 0) ? S->hflag[1] : it;
+    if (fin & 1)
+        RBF_HIP(hipMemcpyAsync(x, J.x[1], kHR * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (k28) hipLaunchKernelGGL((k_resid<kHR, 28>), grid, block, 0, st, A, b, x, S->rpart, nullptr);
+    else hipLaunchKernelGGL((k_resid<kHR, 0>), grid, block, 0, st, A, b, x, S->rpart, nullptr);
+    RBF_CHECK_LAUNCH();
+    // ||b||^2 partials: every sweep that ran wrote them (b is fixed).
+    const double *pb = J.part + (int64_t)((std::max(it, 1) - 1) & 1) * 2 * kHR * kMaxBlocks +
+                       (int64_t)kHR * kMaxBlocks;
+    RBF_HIP(hipMemcpyAsync(S->hred, S->rpart, (size_t)kHR * nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    for (int c = 0; c < kHR; ++c)
+        RBF_HIP(hipMemcpyAsync(S->hred + kMaxNR * nb + c * nb, pb + (int64_t)c * kMaxBlocks,
+                               nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+    rbf_status rc = RBF_OK;
+    for (int c = 0; c < kHR; ++c) {
+        double rr = 0.0, bb = 0.0;
+        for (int bidx = 0; bidx < nb; ++bidx) {
+            rr += S->hred[c * nb + bidx];
+            bb += S->hred[kMaxNR * nb + c * nb + bidx];
+        }
+        if (stats) {
+            stats[c].iterations = fin;
+            stats[c].converged = (f == 1);
+            stats[c].rel_residual = (bb > 0.0) ? std::sqrt(rr / bb) : std::sqrt(rr);
+            stats[c].restarts = 0;
+            stats[c].final_flag = f;
+        }
+    }
+    if (f == -1) {
+        rbf::set_error("Jacobi sweeps: non-finite residual (sweep %d)", fin);
+        rc = RBF_E_NAN;
+    } else if (f != 1) {
+        rbf::set_error("Jacobi sweeps: no convergence (%d of %d sweeps)", it, maxit);
+        rc = RBF_E_NOCONV;
+    }
+    last_iters = fin;
     return rc;
 }
 
@@ -2286,11 +2462,16 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
         ALLOC(H.rhrh, kHR);
         ALLOC(H.best, 2 * kHR * 2);
         ALLOC(H.flag, kHR);
+        JKry &J = S->jk;
+        ALLOC(J.x[1], kHR * N);
+        ALLOC(J.part, 2 * 2 * kHR * kMaxBlocks);
+        ALLOC(J.bb, kHR);
+        ALLOC(J.flag, 2);
         ALLOC(H.iters, kHR);
     }
     if ((rc = alloc_krylov(S, S->kp, 1, M, S->maxit_p)) != RBF_OK) return rc;
     RBF_HIP(hipHostMalloc((void **)&S->hflag, 4 * kMaxNR * sizeof(int), hipHostMallocDefault));
-    RBF_HIP(hipHostMalloc((void **)&S->hred, (kMaxNR * kMaxBlocks + kMaxNR) * sizeof(double),
+    RBF_HIP(hipHostMalloc((void **)&S->hred, (2 * kMaxNR * kMaxBlocks + kMaxNR) * sizeof(double),
                           hipHostMallocDefault));
 
     const size_t ib = sizeof(int), db = sizeof(double);
@@ -2330,6 +2511,21 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     RBF_ARG(herr[0] == 0, "rbf_solver_create: a %s stencil does not contain its own node (or a zero row)",
             (herr[0] & 1) ? "(V,V)" : "(P,P)");
     S->nwall = herr[1];
+    {  // infinity norm of the Jacobi iteration matrix of H
+        const int nbb = (int)rbf::blocks_for(N, 256);
+        double *bpart;
+        ALLOC(bpart, nbb);
+        hipLaunchKernelGGL(k_jacobi_bound, dim3(nbb), dim3(256), 0, st, N, k, S->idx_vv, S->h_w,
+                           S->h_dinv, bpart);
+        RBF_CHECK_LAUNCH();
+        std::vector<double> hb(nbb);
+        RBF_HIP(hipMemcpyAsync(hb.data(), bpart, nbb * sizeof(double), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        double bound = 0.0;
+        for (double v : hb) bound = std::isfinite(v) ? std::max(bound, v) : INFINITY;
+        S->h_bound = bound;
+        S->h_jacobi = bound <= kJacobiMax;
+    }
     // Scale of the zero-mean border: v = gamma / M with gamma = 1 / mean |u1|
     // over interior rows, so the border couples at the scale of the rows.
     std::vector<double> hu(M);
@@ -2380,7 +2576,9 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
     RBF_CHECK_LAUNCH();
     rbf_solve_stats hs[2];
     EllM H{S->idx_vv, S->h_w, S->h_dinv, N, k, nullptr, 0.0};
-    rbf_status rc = hbicgstab(S, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h, S->last_iters_h, hs);
+    rbf_status rc = S->h_jacobi
+                        ? hjacobi(S, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h, S->last_iters_h, hs)
+                        : hbicgstab(S, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h, S->last_iters_h, hs);
     if (rc == RBF_OK) {  // history: the oldest buffer takes the new solution
         RBF_HIP(hipMemcpyAsync(S->hh[2], S->uvss, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, st));
         std::swap(S->hh[1], S->hh[2]);
@@ -2622,6 +2820,15 @@ extern "C" rbf_status rbf_solver_apply_precond(rbf_solver *S, const double *y, d
                        S->pk.partS, S->pk.partGs, nb);
     RBF_CHECK_LAUNCH();
     RBF_HIP(hipStreamSynchronize(st));
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_solver_query(rbf_solver *S, rbf_solver_info *info) {
+    rbf::clear_error();
+    RBF_ARG(S && info, "rbf_solver_query: NULL argument");
+    info->viscous_jacobi = S->h_jacobi ? 1 : 0;
+    info->lattice_precond = S->pc_on ? 1 : 0;
+    info->jacobi_bound = S->h_bound;
     return RBF_OK;
 }
 

@@ -223,6 +223,35 @@ def test_cavity_parity_small_workload(P, gpu, precision):
     S.close()
 
 
+def test_cavity_parity_jacobi_viscous_solve(P, gpu):
+    """K=40 cavity at the bench's Re=1e4 and dt=2e-4 (a = 1e-8): the Jacobi
+    iteration matrix of H has a small infinity norm, so the viscous solve
+    runs Jacobi sweeps; 40 steps against the oracle's LU within 1e-10.  At
+    Re=100, dt=2e-3 (a = 1e-5) the same grid keeps BiCGSTAB."""
+    _say("cavity parity K=40 Jacobi viscous solve")
+    nd = ri.cavity_nodes(40, 0.3, 0)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 1e4, 2e-4, rtol_h=1e-12)
+    info = S.info()
+    _say("solver info", info)
+    assert info["viscous_jacobi"] and info["jacobi_bound"] <= 0.25 and info["lattice_precond"]
+    orc = ocav.CavityOracle(nd, u_bc, v_bc, 1e4, 2e-4)
+    s0 = orc.initial_state()
+    st = S.new_state(to_dev(s0.u, gpu), to_dev(s0.v, gpu))
+    so = s0
+    for chunk in range(2):
+        stats = S.step(st, 20)
+        so = orc.run(20, so)
+        assert stats.last_helmholtz_u.converged and stats.last_helmholtz_u.rel_residual <= 1e-11
+        for key, ref in (("u", so.u), ("v", so.v), ("p", so.p), ("p_tilde", so.pt)):
+            assert rel_err(st[key].cpu().numpy(), ref) <= 1e-10, (chunk, key)
+    S.close()
+    S2, _, _, _ = _gpu_solver(P, nd, gpu, 100.0, 2e-3)
+    info2 = S2.info()
+    _say("solver info at Re=100, dt=2e-3", info2)
+    assert not info2["viscous_jacobi"] and info2["jacobi_bound"] > 0.25
+    S2.close()
+
+
 @pytest.mark.parametrize("precond", ["none", "lattice"])
 def test_solve_pressure_parity(P, gpu, precond):
     _say("solve_pressure", precond)
