@@ -1636,15 +1636,18 @@ __global__ void k_extrapolate(int64_t n, double *__restrict__ x, double *__restr
 }
 
 // Initial guess of the viscous solve from the previous solutions h0
-// (latest), h1, h2 (ORDER 1, 2, 3: constant, linear, quadratic in time).
+// (latest), h1, h2, h3 (ORDER 1-4: constant, linear, quadratic, cubic in
+// time).
 template <int ORDER>
 __global__ void k_guess(int64_t n, double *__restrict__ x, const double *__restrict__ h0,
-                        const double *__restrict__ h1, const double *__restrict__ h2) {
+                        const double *__restrict__ h1, const double *__restrict__ h2,
+                        const double *__restrict__ h3) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= n) return;
     if constexpr (ORDER == 1) x[r] = h0[r];
     else if constexpr (ORDER == 2) x[r] = 2.0 * h0[r] - h1[r];
-    else x[r] = 3.0 * h0[r] - 3.0 * h1[r] + h2[r];
+    else if constexpr (ORDER == 3) x[r] = 3.0 * h0[r] - 3.0 * h1[r] + h2[r];
+    else x[r] = 4.0 * h0[r] - 6.0 * h1[r] + 4.0 * h2[r] - h3[r];
 }
 
 // rhs_scaled = rowscale o rhs (for rbf_solve_pressure).
@@ -1680,7 +1683,7 @@ struct rbf_solver {
            *p_rowscale = nullptr, *p_rhs_tmp = nullptr, *p_u1 = nullptr, *p_warm = nullptr,
            *p_prev = nullptr, *p_prev2 = nullptr, *p_prev3 = nullptr;
     int have_prev = 0;  // previous solutions held in p_prev, p_prev2 (within one rbf_step call)
-    double *hh[3] = {nullptr, nullptr, nullptr};  // previous viscous solutions [2][N], latest first
+    double *hh[4] = {nullptr, nullptr, nullptr, nullptr};  // previous viscous solutions [2][N], latest first
     int have_h = 0;
     double p_vscale = 0.0;
     int8_t *p_tag = nullptr;
@@ -2562,12 +2565,14 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
     // extrapolated in time (wall rows get their values below).
     {
         const dim3 g2(rbf::blocks_for(2 * N, 256)), b2(256);
-        if (S->have_h >= 3)
-            hipLaunchKernelGGL(k_guess<3>, g2, b2, 0, st, 2 * N, S->uvss, S->hh[0], S->hh[1], S->hh[2]);
+        if (S->have_h >= 4)
+            hipLaunchKernelGGL(k_guess<4>, g2, b2, 0, st, 2 * N, S->uvss, S->hh[0], S->hh[1], S->hh[2], S->hh[3]);
+        else if (S->have_h == 3)
+            hipLaunchKernelGGL(k_guess<3>, g2, b2, 0, st, 2 * N, S->uvss, S->hh[0], S->hh[1], S->hh[2], S->hh[3]);
         else if (S->have_h == 2)
-            hipLaunchKernelGGL(k_guess<2>, g2, b2, 0, st, 2 * N, S->uvss, S->hh[0], S->hh[1], S->hh[2]);
+            hipLaunchKernelGGL(k_guess<2>, g2, b2, 0, st, 2 * N, S->uvss, S->hh[0], S->hh[1], S->hh[2], S->hh[3]);
         else if (S->have_h == 1)
-            hipLaunchKernelGGL(k_guess<1>, g2, b2, 0, st, 2 * N, S->uvss, S->hh[0], S->hh[1], S->hh[2]);
+            hipLaunchKernelGGL(k_guess<1>, g2, b2, 0, st, 2 * N, S->uvss, S->hh[0], S->hh[1], S->hh[2], S->hh[3]);
     }
     if (S->nwall > 0)
         hipLaunchKernelGGL(k_wall_rhs, dim3(rbf::blocks_for(S->nwall, kThreads)), blk, 0, st,
@@ -2580,10 +2585,11 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
                         ? hjacobi(S, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h, S->last_iters_h, hs)
                         : hbicgstab(S, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h, S->last_iters_h, hs);
     if (rc == RBF_OK) {  // history: the oldest buffer takes the new solution
-        RBF_HIP(hipMemcpyAsync(S->hh[2], S->uvss, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+        RBF_HIP(hipMemcpyAsync(S->hh[3], S->uvss, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+        std::swap(S->hh[2], S->hh[3]);
         std::swap(S->hh[1], S->hh[2]);
         std::swap(S->hh[0], S->hh[1]);
-        S->have_h = std::min(S->have_h + 1, 3);
+        S->have_h = std::min(S->have_h + 1, 4);
     }
     if (stats) {
         stats->last_helmholtz_u = hs[0];
