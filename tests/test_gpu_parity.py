@@ -230,7 +230,9 @@ def test_cavity_parity_jacobi_viscous_solve(P, gpu):
     Re=100, dt=2e-3 (a = 1e-5) the same grid keeps BiCGSTAB."""
     _say("cavity parity K=40 Jacobi viscous solve")
     nd = ri.cavity_nodes(40, 0.3, 0)
-    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 1e4, 2e-4, rtol_h=1e-12)
+    # Viscous tolerance 1e-13 (the binding's default): at dt = 2e-4 an error
+    # in u** reaches p~ multiplied by 1/dt through F/dt.
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 1e4, 2e-4)
     info = S.info()
     _say("solver info", info)
     assert info["viscous_jacobi"] and info["jacobi_bound"] <= 0.25 and info["lattice_precond"]
@@ -241,7 +243,7 @@ def test_cavity_parity_jacobi_viscous_solve(P, gpu):
     for chunk in range(2):
         stats = S.step(st, 20)
         so = orc.run(20, so)
-        assert stats.last_helmholtz_u.converged and stats.last_helmholtz_u.rel_residual <= 1e-11
+        assert stats.last_helmholtz_u.converged and stats.last_helmholtz_u.rel_residual <= 1e-12
         for key, ref in (("u", so.u), ("v", so.v), ("p", so.p), ("p_tilde", so.pt)):
             assert rel_err(st[key].cpu().numpy(), ref) <= 1e-10, (chunk, key)
     S.close()
