@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--prof-every", type=int, default=25)
     ap.add_argument("--rtol-p", type=float, default=1e-12)
-    ap.add_argument("--rtol-h", type=float, default=1e-12)
+    ap.add_argument("--rtol-h", type=float, default=1e-13)
     ap.add_argument("--batch", type=int, default=64,
                     help="independent cavities of the concurrent-instance run (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=20)
