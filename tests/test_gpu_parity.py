@@ -252,6 +252,15 @@ def test_cavity_parity_jacobi_viscous_solve(P, gpu):
     _say("solver info at Re=100, dt=2e-3", info2)
     assert not info2["viscous_jacobi"] and info2["jacobi_bound"] > 0.25
     S2.close()
+    # One sweep allowed: the sweeps stop with RBF_E_NOCONV and the failed
+    # step is not committed.
+    S3, _, _, _ = _gpu_solver(P, nd, gpu, 1e4, 2e-4, maxit_h=1)
+    st3 = S3.new_state(to_dev(s0.u, gpu), to_dev(s0.v, gpu))
+    with pytest.raises(P.RbfError) as ei:
+        S3.step(st3, 3)
+    assert ei.value.status == -3 and "Jacobi" in str(ei.value)
+    assert st3["step"] < 3
+    S3.close()
 
 
 @pytest.mark.parametrize("precond", ["none", "lattice"])
