@@ -49,8 +49,8 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 # (profiles/k_pc_gemm_cavity_K400_pmc.md): k_pc_gemm<0> and the pressure
 # SpMV k_pc_av<28,0>.  Set to None when the kernel changes until it is
 # measured again.
-GEMM_TRAFFIC_BYTES = 21.97e6
-SPMV_TRAFFIC_BYTES = 59.97e6
+GEMM_TRAFFIC_BYTES = 21.96e6
+SPMV_TRAFFIC_BYTES = 59.95e6
 
 
 def parse():
