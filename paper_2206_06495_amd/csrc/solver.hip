@@ -2087,13 +2087,24 @@ rbf_status hjacobi(rbf_solver *S, EllM A, const double *b, double *x, double tol
     const int fin = (f != 0) ? S->hflag[1] : it;
     if (fin & 1)
         RBF_HIP(hipMemcpyAsync(x, J.x[1], kHR * n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    if (k28) hipLaunchKernelGGL((k_resid<kHR, 28>), grid, block, 0, st, A, b, x, S->rpart, nullptr);
-    else hipLaunchKernelGGL((k_resid<kHR, 0>), grid, block, 0, st, A, b, x, S->rpart, nullptr);
-    RBF_CHECK_LAUNCH();
-    // ||b||^2 partials: every sweep that ran wrote them (b is fixed).
-    const double *pb = J.part + (int64_t)((std::max(it, 1) - 1) & 1) * 2 * kHR * kMaxBlocks +
+    // Statistics: the sweep that produced the accepted iterate's test left
+    // the partials of its true residual and of ||b||^2 (slot fin & 1); after
+    // running out of sweeps the newest iterate's residual is recomputed.
+    const double *pf = J.part + (int64_t)(fin & 1) * 2 * kHR * kMaxBlocks;
+    if (f != 1) {
+        if (k28) hipLaunchKernelGGL((k_resid<kHR, 28>), grid, block, 0, st, A, b, x, S->rpart, nullptr);
+        else hipLaunchKernelGGL((k_resid<kHR, 0>), grid, block, 0, st, A, b, x, S->rpart, nullptr);
+        RBF_CHECK_LAUNCH();
+        RBF_HIP(hipMemcpyAsync(S->hred, S->rpart, (size_t)kHR * nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    } else {
+        for (int c = 0; c < kHR; ++c)
+            RBF_HIP(hipMemcpyAsync(S->hred + c * nb, pf + (int64_t)c * kMaxBlocks, nb * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+    }
+    // ||b||^2 partials (b is fixed): from the same sweep, or from the last
+    // sweep launched when none was accepted (every launched sweep ran).
+    const double *pb = ((f == 1) ? pf : J.part + (int64_t)((std::max(it, 1) - 1) & 1) * 2 * kHR * kMaxBlocks) +
                        (int64_t)kHR * kMaxBlocks;
-    RBF_HIP(hipMemcpyAsync(S->hred, S->rpart, (size_t)kHR * nb * sizeof(double), hipMemcpyDeviceToHost, st));
     for (int c = 0; c < kHR; ++c)
         RBF_HIP(hipMemcpyAsync(S->hred + kMaxNR * nb + c * nb, pb + (int64_t)c * kMaxBlocks,
                                nb * sizeof(double), hipMemcpyDeviceToHost, st));
