@@ -1,14 +1,17 @@
 // Fractional-step Navier-Stokes solver on staggered nodes (Sec. 3):
 //   stage 1  AB2 advection (eqs. (14)-(15))            k_advect
 //   stage 2  Crank-Nicolson viscous step (eq. (16))    k_helm_rhs, k_wall_rhs,
-//            with Kim-Moin wall values (eq. (21))      BiCGSTAB on H (2 RHS)
+//            with Kim-Moin wall values (eq. (21))      Jacobi sweeps or BiCGSTAB
+//                                                      on H (2 RHS)
 //   stage 3  divergence (eq. (17)), pressure Poisson   k_divergence,
 //            (eq. (18)), pressure (eq. (19)) and       BiCGSTAB on the Poisson
 //            velocity correction (eq. (20))            matrix, k_pressure, k_correct
 //
-// The paper factors its implicit matrices once by LU.  Here both systems are
-// solved by BiCGSTAB (van der Vorst 1992) with two fused ELL SpMV kernels per
-// iteration (see the Krylov section below).
+// The paper factors its implicit matrices once by LU.  Here the systems are
+// solved iteratively on the ELL operators: the pressure by BiCGSTAB (van der
+// Vorst 1992) right-preconditioned by a lattice fast-Poisson solve when the
+// P-nodes form a jittered lattice, the viscous system by Jacobi sweeps when
+// H is strongly diagonally dominant, else by Jacobi-preconditioned BiCGSTAB.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
