@@ -2598,13 +2598,6 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
     rbf_status rc = S->h_jacobi
                         ? hjacobi(S, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h, S->last_iters_h, hs)
                         : hbicgstab(S, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h, S->last_iters_h, hs);
-    if (rc == RBF_OK) {  // history: the oldest buffer takes the new solution
-        RBF_HIP(hipMemcpyAsync(S->hh[3], S->uvss, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, st));
-        std::swap(S->hh[2], S->hh[3]);
-        std::swap(S->hh[1], S->hh[2]);
-        std::swap(S->hh[0], S->hh[1]);
-        S->have_h = std::min(S->have_h + 1, 4);
-    }
     if (stats) {
         stats->last_helmholtz_u = hs[0];
         stats->last_helmholtz_v = hs[1];
@@ -2654,7 +2647,18 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
                            S->vp_dy, S->dt, S->ptn, S->uvss, S->un, S->vn);
     });
     RBF_CHECK_LAUNCH();
-    // Commit.
+    // Commit.  The viscous solution joins the history of initial guesses by
+    // pointer rotation; the oldest history buffer becomes the next step's
+    // workspace.
+    {
+        double *oldest = S->hh[3];
+        S->hh[3] = S->hh[2];
+        S->hh[2] = S->hh[1];
+        S->hh[1] = S->hh[0];
+        S->hh[0] = S->uvss;
+        S->uvss = oldest;
+        S->have_h = std::min(S->have_h + 1, 4);
+    }
     std::swap(S->u, S->un);
     std::swap(S->v, S->vn);
     std::swap(S->pt, S->ptn);
