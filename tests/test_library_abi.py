@@ -89,3 +89,16 @@ def test_argument_validation_before_any_device_work(lib):
     lib.rbf_last_error.restype = ctypes.c_char_p
     lib.rbf_ell_apply(10, 0, None, None, None, None, 0, None)
     assert b"k must be" in lib.rbf_last_error()
+    # Batch stepping: argument checks, and an empty batch is a no-op.
+    lib.rbf_step_batch.restype = ctypes.c_int32
+    lib.rbf_step_batch.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    assert lib.rbf_step_batch(None, -1, 1, None, None, None, 0) == -1
+    assert lib.rbf_step_batch(None, 2, 1, None, None, None, 0) == -1
+    assert lib.rbf_step_batch(None, 0, 1, None, None, None, 4) == 0
+    nulls = (ctypes.c_void_p * 2)(None, None)
+    assert lib.rbf_step_batch(nulls, 2, 1, ctypes.c_void_p(1), None, None, 0) == -1
+    assert b"solver 0 is NULL" in lib.rbf_last_error()
+    lib.rbf_solver_query.restype = ctypes.c_int32
+    lib.rbf_solver_query.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.rbf_solver_query(None, None) == -1
