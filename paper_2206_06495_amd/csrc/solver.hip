@@ -1327,13 +1327,25 @@ __global__ void __launch_bounds__(kThreads) k_h_s(HKry K, const double *__restri
 // passes the test, so the residual tested is the true one.
 constexpr double kJacobiMax = 0.25;
 struct JKry {
-    double *x[2];   // [2][N] iterates by parity (x[0] is the caller's x)
+    double *x[2];   // [N][2] iterates by parity, components interleaved so that
+                    // a gathered neighbour is one 16-byte load
+    const double *x0;  // [2][N] the caller's initial guess (iterate 0)
     double *part;   // [2 parities][2 kHR][kMaxBlocks]
     double *bb;     // ||b||^2 per component
     int *flag;      // flag, then the index of the accepted iterate
 };
 
-template <int KT>
+struct GatherI2 {
+    static constexpr int NV = 2;
+    const double2 *x;
+    __device__ __forceinline__ void operator()(int j, double (&v)[2]) const {
+        const double2 t = x[j];
+        v[0] = t.x;
+        v[1] = t.y;
+    }
+};
+
+template <int KT, bool FIRST>
 __global__ void __launch_bounds__(kThreads) k_h_jac(EllM A, const double *__restrict__ b, JKry J,
                                                      int i, double tol2) {
     const int nb = gridDim.x;
@@ -1365,8 +1377,9 @@ __global__ void __launch_bounds__(kThreads) k_h_jac(EllM A, const double *__rest
             return;
         }
     }
-    const double *xin = J.x[i & 1];
-    double *xout = J.x[(i & 1) ^ 1];
+    // Iterate i: the caller's [2][N] guess for i = 0, else J.x[i & 1].
+    const double2 *xin = reinterpret_cast<const double2 *>(J.x[i & 1]);
+    double2 *xout = reinterpret_cast<double2 *>(J.x[(i & 1) ^ 1]);
     double acc[2 * kHR] = {};
     for (int64_t it = 0;; ++it) {
         const int64_t row = row_of(it);
@@ -1374,16 +1387,27 @@ __global__ void __launch_bounds__(kThreads) k_h_jac(EllM A, const double *__rest
         if (row < A.n) {
             double ax[1][kHR] = {};
             const double *ws[1] = {A.w};
-            rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherN<kHR>{xin, A.n}, ax);
+            double xs[kHR];
+            if constexpr (FIRST) {
+                rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherN<kHR>{J.x0, A.n}, ax);
+                xs[0] = J.x0[row];
+                xs[1] = J.x0[A.n + row];
+            } else {
+                rbf::ell_row<KT, 1>(A.idx, ws, A.n, row, A.k, GatherI2{xin}, ax);
+                const double2 t = xin[row];
+                xs[0] = t.x;
+                xs[1] = t.y;
+            }
             const double di = A.dinv[row];
+            double xn[kHR];
 #pragma unroll
             for (int c = 0; c < kHR; ++c) {
-                const int64_t o = c * A.n + row;
-                const double bv = b[o], rv = bv - ax[0][c];
-                xout[o] = xin[o] + di * rv;
+                const double bv = b[c * A.n + row], rv = bv - ax[0][c];
+                xn[c] = xs[c] + di * rv;
                 acc[c] += rv * rv;
                 acc[kHR + c] += bv * bv;
             }
+            xout[row] = make_double2(xn[0], xn[1]);
         }
     }
     __shared__ double lds2[2 * kHR * (kThreads / 64)];
@@ -1393,6 +1417,15 @@ __global__ void __launch_bounds__(kThreads) k_h_jac(EllM A, const double *__rest
 #pragma unroll
         for (int c = 0; c < 2 * kHR; ++c) pp[(int64_t)c * kMaxBlocks + blockIdx.x] = acc[c];
     }
+}
+
+// x ([2][N]) from an interleaved iterate ([N][2]).
+__global__ void k_h_deint(int64_t n, const double2 *__restrict__ xi, double *__restrict__ x) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const double2 t = xi[r];
+    x[r] = t.x;
+    x[n + r] = t.y;
 }
 
 // Block maxima of |1/h_ii| sum_{j != i} |h_ij| (the Jacobi bound above).
@@ -2063,7 +2096,7 @@ rbf_status hjacobi(rbf_solver *S, EllM A, const double *b, double *x, double tol
                    int &last_iters, rbf_solve_stats *stats) {
     hipStream_t st = S->st;
     JKry J = S->jk;
-    J.x[0] = x;
+    J.x0 = x;
     const int64_t n = A.n;
     const int nb = nblocks_rows(n);
     const dim3 grid(nb), block(kThreads);
@@ -2076,8 +2109,13 @@ rbf_status hjacobi(rbf_solver *S, EllM A, const double *b, double *x, double tol
     for (;;) {
         const int stop = std::min(maxit + 2, it + batch);
         for (; it < stop; ++it) {
-            if (k28) hipLaunchKernelGGL((k_h_jac<28>), grid, block, 0, st, A, b, J, it, tol2);
-            else hipLaunchKernelGGL((k_h_jac<0>), grid, block, 0, st, A, b, J, it, tol2);
+            if (it == 0) {
+                if (k28) hipLaunchKernelGGL((k_h_jac<28, true>), grid, block, 0, st, A, b, J, it, tol2);
+                else hipLaunchKernelGGL((k_h_jac<0, true>), grid, block, 0, st, A, b, J, it, tol2);
+            } else {
+                if (k28) hipLaunchKernelGGL((k_h_jac<28, false>), grid, block, 0, st, A, b, J, it, tol2);
+                else hipLaunchKernelGGL((k_h_jac<0, false>), grid, block, 0, st, A, b, J, it, tol2);
+            }
         }
         RBF_CHECK_LAUNCH();
         RBF_HIP(hipMemcpyAsync(S->hflag, J.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -2088,8 +2126,9 @@ rbf_status hjacobi(rbf_solver *S, EllM A, const double *b, double *x, double tol
     }
     // The accepted iterate, or the newest one when the sweeps ran out.
     const int fin = (f != 0) ? S->hflag[1] : it;
-    if (fin & 1)
-        RBF_HIP(hipMemcpyAsync(x, J.x[1], kHR * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (fin > 0)  // iterate fin lives in J.x[fin & 1], interleaved
+        hipLaunchKernelGGL(k_h_deint, dim3(rbf::blocks_for(n, 256)), dim3(256), 0, st, n,
+                           reinterpret_cast<const double2 *>(J.x[fin & 1]), x);
     // Statistics: the sweep that produced the accepted iterate's test left
     // the partials of its true residual and of ||b||^2 (slot fin & 1); after
     // running out of sweeps the newest iterate's residual is recomputed.
@@ -2480,6 +2519,7 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
         ALLOC(H.best, 2 * kHR * 2);
         ALLOC(H.flag, kHR);
         JKry &J = S->jk;
+        ALLOC(J.x[0], kHR * N);
         ALLOC(J.x[1], kHR * N);
         ALLOC(J.part, 2 * 2 * kHR * kMaxBlocks);
         ALLOC(J.bb, kHR);
