@@ -391,6 +391,39 @@ def test_stable_small_cavity_run():
     assert np.max(np.abs(s.u[wall] - orc.u_bc[wall])) < 5e-3
 
 
+def _projection_radius(K):
+    """Spectral radius of the velocity map of eqs. (17), (18) and (20) alone
+    (interior V rows; wall rows held at zero): u -> u - G p~ with
+    A p~ = D u on interior P rows, 0 on wall rows (bordered system)."""
+    import scipy.sparse.linalg as spla
+    nd = ri.cavity_nodes(K, 0.3, 0)
+    ops = oops.CavityOperators(nd, 28, 7, 3)
+    _, chi, B = oops.poisson_matrix(ops)
+    lu = spla.splu(B.tocsc())
+    N = nd.n_v
+    vin = (nd.v_tag == 0).astype(np.float64)
+
+    def mv(x):
+        u, v = x[:N] * vin, x[N:] * vin
+        F = chi * (ops.Dx_pv @ u + ops.Dy_pv @ v)
+        pt = lu.solve(np.concatenate([F, [0.0]]))[:-1]
+        return np.concatenate([(u - ops.Dx_vp @ pt) * vin, (v - ops.Dy_vp @ pt) * vin])
+
+    op = spla.LinearOperator((2 * N, 2 * N), matvec=mv, dtype=np.float64)
+    ev = spla.eigs(op, k=4, which="LM", tol=1e-8, maxiter=5000, return_eigenvectors=False)
+    return float(np.max(np.abs(ev)))
+
+
+def test_projection_spectral_radius():
+    """An exact projection has eigenvalues 0 and 1; with D_Lap^PP in place
+    of D^PV D^VP the projection is approximate.  With the Neumann wall rows
+    its spectral radius is 1 at h = 1/24 (the parity cases' regime) and
+    exceeds 1 at h = 1/60 (observed: 6.9; near-wall modes), which is the
+    divergence of long runs on jittered node sets."""
+    assert _projection_radius(24) <= 1.0 + 1e-6
+    assert _projection_radius(60) > 2.0
+
+
 def test_brute_force_dense_tiny_cavity():
     """K = 5 cavity (N = 85, M = 36): operators from independent 40-digit row
     solves, implicit systems solved densely with numpy.linalg.solve, 5 steps
