@@ -444,6 +444,37 @@ def test_step_error_paths_are_transactional(P, gpu):
     S.close()
 
 
+def test_checkpoint_resume_is_bitwise(P, gpu):
+    """(u, v, p~, p, C_{j-1}(u), C_{j-1}(v), j) is the whole carried state of
+    the scheme (AB2, eq. (14), needs the previous advection terms): saved
+    with torch.save after 6 steps and loaded (weights_only) for a new solver
+    built from the same operators, 6 more steps give fields bit-identical to
+    6 + 6 steps on the first solver.  The Krylov initial guesses are rebuilt
+    within each rbf_step call, the launch plan only decides how many
+    iterations are queued, and every reduction runs in a fixed order."""
+    import io
+    import torch
+    _say("checkpoint / resume K=24")
+    nd = ri.cavity_nodes(24, 0.3, 2)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 400.0, 2e-3)
+    st = S.new_state(to_dev(np.where(nd.v_tag != 0, u_bc, 0.0), gpu), to_dev(v_bc, gpu))
+    S.step(st, 6)
+    buf = io.BytesIO()
+    torch.save(st, buf)
+    S.step(st, 6)
+    grid2, ops2 = gpu_cavity_ops(nd, gpu)
+    S2 = P.Solver(grid2, ops2, to_dev(u_bc, gpu), to_dev(v_bc, gpu), 400.0, 2e-3)
+    buf.seek(0)
+    st2 = torch.load(buf, weights_only=True, map_location=gpu)
+    assert st2["step"] == 6
+    S2.step(st2, 6)
+    assert st2["step"] == st["step"] == 12
+    for key in ("u", "v", "p", "p_tilde", "cu_prev", "cv_prev"):
+        assert torch.equal(st[key], st2[key]), key
+    S.close()
+    S2.close()
+
+
 def _sampled_stencils(xq, xs, rows, ops):
     """Oracle kNN + weights for the listed evaluation rows only."""
     idx = oknn.knn_bruteforce(xq[:, rows], xs, 28)
