@@ -157,6 +157,48 @@ rbf_status rbf_ell_apply(int64_t rows, int32_t k, const int32_t *idx, const void
  */
 rbf_status rbf_cast_f32(const double *src, float *dst, int64_t n, rbf_stream st);
 
+/*
+ * rbf_ell_transpose -- column structure of D^T for one ELL operator, the
+ * transposed product that adjoints of the steps of Sec. 3 apply (the rows of
+ * D^T are the columns of eq. (10)'s matrix: z_c = sum of w_{r,s} y_r over
+ * the entries (s, r) with idx[s][r] == c).
+ *
+ * rows, k, idx: the ELL operator as for rbf_ell_apply (device int32
+ * [k][rows]); ncols: number of columns (every idx must lie in [0, ncols)).
+ * Outputs (device, caller-allocated): colptr int64 [ncols + 1] (column c
+ * holds entries colptr[c] .. colptr[c+1]-1); src int32 [k * rows] (source
+ * row r of each entry) and slot int32 [k * rows] (its slot s), ordered by
+ * increasing (r, s) inside each column.  Every ELL entry appears once,
+ * zero weights included, so the structure serves every weight array of the
+ * same idx (FP64 or FP32).  bad_entry: host; -1, or the lowest ELL position
+ * s * rows + r whose index is outside [0, ncols).
+ * Synchronises the stream (two read-backs) and allocates a workspace of
+ * ncols ints for the duration of the call.  Limits: k in [1, 64],
+ * rows * k < 2^31, ncols < 2^31, at most 4096 entries per column.
+ * Errors: RBF_E_ARG for violated limits or an index out of range (outputs
+ * then undefined); RBF_E_NOMEM / RBF_E_DEVICE from the runtime.
+ */
+rbf_status rbf_ell_transpose(int64_t rows, int32_t k, const int32_t *idx, int64_t ncols,
+                             int64_t *colptr, int32_t *src, int32_t *slot, int64_t *bad_entry,
+                             rbf_stream st);
+
+/*
+ * rbf_ell_apply_transpose -- z = D^T y with the structure of
+ * rbf_ell_transpose: z_c = sum over the entries of column c, in their stored
+ * order (increasing source row), of w[slot][src] * y[src], with fused
+ * multiply-adds; one thread per column, no atomics, so results are
+ * reproducible bit for bit.
+ *
+ * w: device [k][rows] weights (dtype 0: FP64; 1: FP32, as y and z, FP32
+ * accumulation); y: device [rows]; z: device [ncols] (columns without
+ * entries get 0).  No synchronisation.  Errors: RBF_E_ARG for bad sizes,
+ * dtype or NULL pointers.
+ */
+rbf_status rbf_ell_apply_transpose(int64_t rows, int32_t k, const void *w, int64_t ncols,
+                                   const int64_t *colptr, const int32_t *src,
+                                   const int32_t *slot, const void *y, void *z, int32_t dtype,
+                                   rbf_stream st);
+
 /* ---------------------------------------------------------------------------
  * Fractional-step solver (Sec. 3).
  * ------------------------------------------------------------------------- */

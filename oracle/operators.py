@@ -28,6 +28,16 @@ def ell_apply(idx, w, x):
     return np.einsum("sr,sr->r", w, x[idx])
 
 
+def ell_apply_transpose(idx, w, y, ncols):
+    """z = D^T y for the matrix of eq. (10) held as ELL: z_c is the sum of
+    w[s, r] y[r] over the entries with idx[s, r] = c (the transposed product
+    an adjoint of the scheme applies)."""
+    idx = np.asarray(idx)
+    z = np.zeros(ncols)
+    np.add.at(z, idx.ravel(), (np.asarray(w) * np.asarray(y)[None, :]).ravel())
+    return z
+
+
 class StencilSet:
     """Stencils and weights of one (alpha, beta) pair."""
 

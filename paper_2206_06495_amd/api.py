@@ -101,6 +101,46 @@ def ell_apply(idx, w, x, out=None):
     return out
 
 
+class Transpose:
+    """Column structure of D^T for one ELL index array (rbf_ell_transpose):
+    colptr int64 [ncols + 1], src and slot int32 [k * rows]."""
+
+    def __init__(self, idx, ncols):
+        _dev(idx, torch.int32, name="idx")
+        self.k, self.rows = idx.shape
+        self.ncols = int(ncols)
+        dev = idx.device
+        self.colptr = torch.empty(self.ncols + 1, dtype=torch.int64, device=dev)
+        nnz = max(1, self.k * self.rows)
+        self.src = torch.empty(nnz, dtype=torch.int32, device=dev)
+        self.slot = torch.empty(nnz, dtype=torch.int32, device=dev)
+        bad = ctypes.c_int64(-1)
+        rc = lib.rbf_ell_transpose(self.rows, self.k, _ptr(idx), self.ncols, _ptr(self.colptr),
+                                   _ptr(self.src), _ptr(self.slot), ctypes.byref(bad), _stream())
+        self.bad_entry = bad.value
+        check(rc)
+
+    def apply(self, w, y, out=None):
+        """z = D^T y with the weights w [k, rows] of the same operator."""
+        if w.dtype not in (torch.float64, torch.float32):
+            raise ValueError("w must be float64 or float32")
+        _dev(w, w.dtype, (self.k, self.rows), name="w")
+        _dev(y, w.dtype, (self.rows,), name="y")
+        if out is None:
+            out = torch.empty(self.ncols, dtype=w.dtype, device=w.device)
+        _dev(out, w.dtype, (self.ncols,), name="out")
+        dtype = 0 if w.dtype == torch.float64 else 1
+        check(lib.rbf_ell_apply_transpose(self.rows, self.k, _ptr(w), self.ncols, _ptr(self.colptr),
+                                          _ptr(self.src), _ptr(self.slot), _ptr(y), _ptr(out),
+                                          dtype, _stream()))
+        return out
+
+
+def ell_transpose(idx, ncols):
+    """Transposed-product structure of the ELL index array idx [k, rows]."""
+    return Transpose(idx, ncols)
+
+
 def cast_f32(a):
     """FP32 copy of an FP64 device tensor (round to nearest), on the GPU."""
     _dev(a, torch.float64, name="a")

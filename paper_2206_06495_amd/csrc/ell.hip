@@ -1,11 +1,16 @@
 // rbf_ell_apply: y = D x for one slot-major ELL operator (eq. (10) applied
 // to a vector), FP64 or FP32-stored; plus the FP64 -> FP32 cast helper.
+// rbf_ell_transpose / rbf_ell_apply_transpose: z = D^T y through a column
+// structure built once, in a fixed summation order (no floating-point
+// atomics).
 //
 // One thread per row.  For a fixed stencil width all index and weight loads
 // of the row are issued (non-temporal: the operator streams through once)
 // before the gathers of x, which hit in the caches because stencil
 // neighbours are close in memory; blocks are remapped so that every XCD
 // works on one contiguous range of rows (its L2 then holds that range of x).
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -49,6 +54,120 @@ __global__ void k_cast_f32(const double *__restrict__ a, float *__restrict__ b, 
         b[i] = (float)a[i];
 }
 
+// ---------------------------------------------------------- transpose --
+// Column counts: cnt[c + 1] = number of ELL entries (s, r) with
+// idx[s][r] == c (cnt[0] stays 0).  Entries outside [0, ncols) are not
+// counted; the lowest such ELL position goes to *bad.
+__global__ void k_tr_count(int64_t nnz, const int *__restrict__ idx, int64_t ncols,
+                           unsigned long long *cnt, unsigned long long *bad) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = idx[e];
+        if (c < 0 || (int64_t)c >= ncols) atomicMin(bad, (unsigned long long)e);
+        else atomicAdd(cnt + c + 1, 1ull);
+    }
+}
+
+// Longest column: max over c of cnt[c + 1] into *mx.
+__global__ void k_tr_maxlen(int64_t ncols, const int64_t *__restrict__ cnt, unsigned long long *mx) {
+    unsigned long long m = 0;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncols;
+         c += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, (unsigned long long)cnt[c + 1]);
+    atomicMax(mx, m);
+}
+
+// In-place inclusive prefix sum of a[0..n) in one workgroup of kScanT
+// threads: chunks of kScanT * kScanV values, each thread summing kScanV
+// consecutive values, a Hillis-Steele scan of the thread totals in LDS, and
+// a carry across chunks.  Set-up work (one pass over the columns).
+constexpr int kScanT = 1024, kScanV = 8;
+__global__ void __launch_bounds__(kScanT) k_tr_scan(int64_t n, int64_t *a) {
+    __shared__ int64_t tot[2][kScanT];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < n; base += (int64_t)kScanT * kScanV) {
+        const int64_t i0 = base + (int64_t)threadIdx.x * kScanV;
+        int64_t v[kScanV], run = 0;
+#pragma unroll
+        for (int j = 0; j < kScanV; ++j) {
+            v[j] = (i0 + j < n) ? a[i0 + j] : 0;
+            run += v[j];
+            v[j] = run;
+        }
+        int cur = 0;
+        tot[cur][threadIdx.x] = run;
+        __syncthreads();
+        for (int off = 1; off < kScanT; off <<= 1) {
+            const int64_t t = tot[cur][threadIdx.x] +
+                              (threadIdx.x >= off ? tot[cur][threadIdx.x - off] : 0);
+            tot[cur ^ 1][threadIdx.x] = t;
+            cur ^= 1;
+            __syncthreads();
+        }
+        const int64_t before = carry + (threadIdx.x ? tot[cur][threadIdx.x - 1] : 0);
+#pragma unroll
+        for (int j = 0; j < kScanV; ++j)
+            if (i0 + j < n) a[i0 + j] = before + v[j];
+        carry += tot[cur][kScanT - 1];
+        __syncthreads();
+    }
+}
+
+// Scatter: entry (s, r) of column c goes to colptr[c] + (arrival order);
+// the order inside a column is fixed afterwards by k_tr_sort.
+__global__ void k_tr_fill(int64_t rows, int64_t nnz, const int *__restrict__ idx,
+                          const int64_t *__restrict__ colptr, int *cursor, int *src, int *slot) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = idx[e];
+        const int64_t pos = colptr[c] + atomicAdd(cursor + c, 1);
+        src[pos] = (int)(e % rows);
+        slot[pos] = (int)(e / rows);
+    }
+}
+
+// Per column: insertion sort of its entries by (source row, slot).  Columns
+// hold about k entries (at most kMaxColumn, checked before launch), so one
+// thread per column.
+constexpr int64_t kMaxColumn = 4096;
+__global__ void k_tr_sort(int64_t ncols, const int64_t *__restrict__ colptr, int *src, int *slot) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= ncols) return;
+    const int64_t b = colptr[c], e = colptr[c + 1];
+    for (int64_t i = b + 1; i < e; ++i) {
+        const int r = src[i], s = slot[i];
+        int64_t j = i - 1;
+        while (j >= b && (src[j] > r || (src[j] == r && slot[j] > s))) {
+            src[j + 1] = src[j];
+            slot[j + 1] = slot[j];
+            --j;
+        }
+        src[j + 1] = r;
+        slot[j + 1] = s;
+    }
+}
+
+// z_c = sum over the entries of column c, in increasing source row, of
+// w[slot][src] * y[src]: one thread per column, FMA accumulation.
+template <class T>
+__global__ void __launch_bounds__(256) k_ell_apply_t(int64_t rows, int64_t ncols,
+                                                     const int64_t *__restrict__ colptr,
+                                                     const int *__restrict__ src,
+                                                     const int *__restrict__ slot,
+                                                     const T *__restrict__ w,
+                                                     const T *__restrict__ y, T *__restrict__ z) {
+    const uint32_t lb = rbf::xcd_block(blockIdx.x, gridDim.x);
+    const int64_t c = (int64_t)lb * blockDim.x + threadIdx.x;
+    if (c >= ncols) return;
+    const int64_t b = colptr[c], e = colptr[c + 1];
+    T acc = T(0);
+    for (int64_t i = b; i < e; ++i) {
+        const int r = src[i];
+        acc = fma_t<T>(w[(int64_t)slot[i] * rows + r], y[r], acc);
+    }
+    z[c] = acc;
+}
+
 }  // namespace
 
 extern "C" rbf_status rbf_ell_apply(int64_t rows, int32_t k, const int32_t *idx, const void *w,
@@ -84,6 +203,103 @@ extern "C" rbf_status rbf_cast_f32(const double *src, float *dst, int64_t n, rbf
     if (n == 0) return RBF_OK;
     RBF_ARG(src && dst, "rbf_cast_f32: NULL pointer");
     hipLaunchKernelGGL(k_cast_f32, dim3(1024), dim3(256), 0, rbf::as_stream(st_), src, dst, n);
+    RBF_CHECK_LAUNCH();
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_ell_transpose(int64_t rows, int32_t k, const int32_t *idx, int64_t ncols,
+                                        int64_t *colptr, int32_t *src, int32_t *slot,
+                                        int64_t *bad_entry, rbf_stream st_) {
+    rbf::clear_error();
+    RBF_ARG(rows >= 0 && k >= 1 && k <= 64 && rows * k < ((int64_t)1 << 31),
+            "rbf_ell_transpose: rows * k must be below 2^31 and k in [1, 64]");
+    RBF_ARG(ncols >= 0 && ncols < ((int64_t)1 << 31), "rbf_ell_transpose: ncols out of range");
+    RBF_ARG(bad_entry, "rbf_ell_transpose: bad_entry is NULL");
+    *bad_entry = -1;
+    RBF_ARG(colptr, "rbf_ell_transpose: colptr is NULL");
+    hipStream_t st = rbf::as_stream(st_);
+    const int64_t nnz = rows * k;
+    RBF_HIP(hipMemsetAsync(colptr, 0, (size_t)(ncols + 1) * sizeof(int64_t), st));
+    if (nnz == 0) return RBF_OK;
+    RBF_ARG(idx && src && slot, "rbf_ell_transpose: NULL pointer");
+    // Workspace: the bad-entry marker and one arrival counter per column.
+    void *ws = nullptr;
+    const size_t wsb = 256 + (size_t)(ncols > 0 ? ncols : 1) * sizeof(int);
+    RBF_HIP(hipMalloc(&ws, wsb));
+    auto *bad = static_cast<unsigned long long *>(ws);
+    int *cursor = reinterpret_cast<int *>(static_cast<char *>(ws) + 256);
+    rbf_status rc = RBF_OK;
+    unsigned long long hbad = ~0ull;
+    auto run = [&]() -> rbf_status {
+        RBF_HIP(hipMemsetAsync(ws, 0xff, 256, st));
+        RBF_HIP(hipMemsetAsync(cursor, 0, wsb - 256, st));
+        const uint32_t ge = std::min<uint32_t>(rbf::blocks_for(nnz, 256), 8192u);
+        hipLaunchKernelGGL(k_tr_count, dim3(ge), dim3(256), 0, st, nnz, idx, ncols,
+                           reinterpret_cast<unsigned long long *>(colptr), bad);
+        RBF_CHECK_LAUNCH();
+        unsigned long long *mx = bad + 1, hm[2] = {~0ull, 0};
+        RBF_HIP(hipMemsetAsync(mx, 0, sizeof(*mx), st));
+        if (ncols > 0)
+            hipLaunchKernelGGL(k_tr_maxlen, dim3(std::min<uint32_t>(rbf::blocks_for(ncols, 256), 1024u)),
+                               dim3(256), 0, st, ncols, colptr, mx);
+        RBF_CHECK_LAUNCH();
+        RBF_HIP(hipMemcpyAsync(hm, bad, sizeof(hm), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        hbad = hm[0];
+        if (hbad == ~0ull && hm[1] > (unsigned long long)kMaxColumn) {
+            rbf::set_error("rbf_ell_transpose: a column holds %llu entries (at most %lld)", hm[1],
+                           (long long)kMaxColumn);
+            return RBF_E_ARG;
+        }
+        if (hbad != ~0ull) {
+            *bad_entry = (int64_t)hbad;
+            rbf::set_error("rbf_ell_transpose: idx entry %lld (slot %lld, row %lld) is outside [0, %lld)",
+                           (long long)hbad, (long long)(hbad / rows), (long long)(hbad % rows),
+                           (long long)ncols);
+            return RBF_E_ARG;
+        }
+        hipLaunchKernelGGL(k_tr_scan, dim3(1), dim3(kScanT), 0, st, ncols + 1, colptr);
+        hipLaunchKernelGGL(k_tr_fill, dim3(ge), dim3(256), 0, st, (int64_t)rows, nnz, idx, colptr,
+                           cursor, src, slot);
+        if (ncols > 0)
+            hipLaunchKernelGGL(k_tr_sort, dim3(rbf::blocks_for(ncols, 256)), dim3(256), 0, st,
+                               ncols, colptr, src, slot);
+        RBF_CHECK_LAUNCH();
+        RBF_HIP(hipStreamSynchronize(st));
+        return RBF_OK;
+    };
+    rc = run();
+    if (rc != RBF_OK) (void)hipStreamSynchronize(st);
+    const hipError_t fe = hipFree(ws);
+    if (rc == RBF_OK && fe != hipSuccess) {
+        rbf::set_error("rbf_ell_transpose: hipFree failed: %s", hipGetErrorString(fe));
+        rc = RBF_E_DEVICE;
+    }
+    return rc;
+}
+
+extern "C" rbf_status rbf_ell_apply_transpose(int64_t rows, int32_t k, const void *w, int64_t ncols,
+                                              const int64_t *colptr, const int32_t *src,
+                                              const int32_t *slot, const void *y, void *z,
+                                              int32_t dtype, rbf_stream st_) {
+    rbf::clear_error();
+    RBF_ARG(rows >= 0 && k >= 1 && k <= 64 && rows * k < ((int64_t)1 << 31),
+            "rbf_ell_apply_transpose: rows * k must be below 2^31 and k in [1, 64]");
+    RBF_ARG(ncols >= 0 && ncols < ((int64_t)1 << 31), "rbf_ell_apply_transpose: ncols out of range");
+    RBF_ARG(dtype == 0 || dtype == 1, "rbf_ell_apply_transpose: dtype must be 0 (FP64) or 1 (FP32)");
+    if (ncols == 0) return RBF_OK;
+    RBF_ARG(colptr && z && (rows == 0 || (w && src && slot && y)),
+            "rbf_ell_apply_transpose: NULL pointer");
+    hipStream_t st = rbf::as_stream(st_);
+    const dim3 grid(rbf::blocks_for(ncols, 256)), block(256);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_ell_apply_t<double>, grid, block, 0, st, rows, ncols, colptr, src, slot,
+                           static_cast<const double *>(w), static_cast<const double *>(y),
+                           static_cast<double *>(z));
+    else
+        hipLaunchKernelGGL(k_ell_apply_t<float>, grid, block, 0, st, rows, ncols, colptr, src, slot,
+                           static_cast<const float *>(w), static_cast<const float *>(y),
+                           static_cast<float *>(z));
     RBF_CHECK_LAUNCH();
     return RBF_OK;
 }

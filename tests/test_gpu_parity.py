@@ -189,6 +189,83 @@ def test_ell_apply_parity(P, gpu):
     assert float(y.cpu()[0]) == 14.0
 
 
+def _transpose_ref(idx, ncols):
+    """Column structure of D^T by definition: entries (s, r) grouped by
+    column idx[s, r], ordered by (r, s) inside a column."""
+    k, rows = idx.shape
+    s_, r_ = np.meshgrid(np.arange(k), np.arange(rows), indexing="ij")
+    c, r, s = idx.ravel(), r_.ravel(), s_.ravel()
+    order = np.lexsort((s, r, c))
+    colptr = np.concatenate([[0], np.cumsum(np.bincount(c, minlength=ncols))])
+    return colptr, r[order], s[order]
+
+
+def _t_bound(idx, w, y, ncols, u):
+    lens = np.bincount(idx.ravel(), minlength=ncols)
+    mag = np.zeros(ncols)
+    np.add.at(mag, idx.ravel(), np.abs(w * y[None, :]).ravel())
+    return 2.0 * np.maximum(lens, 1) * u * mag + 1e-300
+
+
+def test_ell_transpose_parity(P, gpu):
+    """z = D^T y (the transposed product of the adjoint): the column
+    structure equals its definition exactly; FP64 and FP32 products agree
+    with the oracle within the rounding bound of each column's sum and are
+    bit-identical on repetition; rectangular PV (M x N) and square VV
+    operators, k = 28 and 17, with columns no row references."""
+    import torch
+    _say("ell transpose")
+    nd = ri.cavity_nodes(40, 0.3, 0)
+    xv, xp = to_dev(nd.xv, gpu), to_dev(nd.xp, gpu)
+    for xq, xs, k in ((xp, xv, 28), (xv, xv, 17)):
+        idx = P.knn(xq, xs, k)
+        w = P.assemble_weights(xq, xs, idx, 7, 3, OP_DX | OP_DY, force=True)
+        rows, ncols = xq.shape[1], xs.shape[1] + 3
+        T = P.ell_transpose(idx, ncols)
+        idx_h, w_h = idx.cpu().numpy(), w.cpu().numpy()
+        colptr, src, slot = _transpose_ref(idx_h, ncols)
+        assert np.array_equal(T.colptr.cpu().numpy(), colptr)
+        assert np.array_equal(T.src.cpu().numpy(), src)
+        assert np.array_equal(T.slot.cpu().numpy(), slot)
+        y = ri.random_vector(rows, 21)
+        for o in range(2):
+            z = T.apply(w[o].contiguous(), to_dev(y, gpu))
+            ref = oops.ell_apply_transpose(idx_h, w_h[o], y, ncols)
+            zh = z.cpu().numpy()
+            assert np.all(np.abs(zh - ref) <= _t_bound(idx_h, w_h[o], y, ncols, 2.0 ** -53))
+            assert np.all(zh[ncols - 3:] == 0.0)
+            assert torch.equal(z, T.apply(w[o].contiguous(), to_dev(y, gpu)))
+            w32 = P.cast_f32(w[o].contiguous())
+            y32 = P.cast_f32(to_dev(y, gpu))
+            z32 = T.apply(w32, y32).cpu().numpy().astype(np.float64)
+            w32h = w32.cpu().numpy().astype(np.float64)
+            y32h = y32.cpu().numpy().astype(np.float64)
+            ref32 = oops.ell_apply_transpose(idx_h, w32h, y32h, ncols)
+            assert np.all(np.abs(z32 - ref32) <= _t_bound(idx_h, w32h, y32h, ncols, 2.0 ** -24))
+
+
+def test_ell_transpose_edge_cases(P, gpu):
+    """No rows: every column empty and z = 0.  An index outside
+    [0, ncols) is reported with the lowest offending ELL position; a column
+    with more than 4096 entries is rejected before any entry is placed."""
+    import torch
+    _say("ell transpose edge cases")
+    T = P.ell_transpose(torch.zeros((28, 0), dtype=torch.int32, device=gpu), 4)
+    assert T.colptr.cpu().tolist() == [0] * 5
+    z = T.apply(torch.zeros((28, 0), dtype=torch.float64, device=gpu),
+                torch.zeros(0, dtype=torch.float64, device=gpu))
+    assert z.cpu().tolist() == [0.0] * 4
+    idx = torch.zeros((28, 10), dtype=torch.int32)
+    idx[3, 7] = 6
+    idx[5, 2] = -1
+    with pytest.raises(P.RbfError) as ei:
+        P.ell_transpose(idx.to(gpu), 6)
+    assert ei.value.status == -1 and "entry 37" in str(ei.value)
+    with pytest.raises(P.RbfError) as ei:
+        P.ell_transpose(torch.zeros((28, 200), dtype=torch.int32, device=gpu), 3)
+    assert ei.value.status == -1 and "5600 entries" in str(ei.value)
+
+
 def _gpu_solver(P, nd, gpu, re, dt, **kw):
     grid, ops = gpu_cavity_ops(nd, gpu)
     u_bc, v_bc = ri.cavity_bc(nd.v_tag)

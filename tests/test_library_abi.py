@@ -31,7 +31,7 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("rbf_build_nodes", "rbf_knn", "rbf_assemble_weights", "rbf_ell_apply",
-              "rbf_solver_create", "rbf_step", "rbf_solve_pressure", "rbf_solver_destroy"):
+              "rbf_ell_transpose", "rbf_ell_apply_transpose", "rbf_solver_create", "rbf_step", "rbf_solve_pressure", "rbf_solver_destroy"):
         assert n in names
 
 
@@ -89,6 +89,27 @@ def test_argument_validation_before_any_device_work(lib):
     lib.rbf_last_error.restype = ctypes.c_char_p
     lib.rbf_ell_apply(10, 0, None, None, None, None, 0, None)
     assert b"k must be" in lib.rbf_last_error()
+    # Transposed products: size, dtype and pointer checks; no columns is a no-op.
+    lib.rbf_ell_transpose.restype = ctypes.c_int32
+    lib.rbf_ell_transpose.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    bad = ctypes.c_int64(7)
+    assert lib.rbf_ell_transpose(10, 0, None, 5, None, None, None, ctypes.byref(bad), None) == -1
+    assert lib.rbf_ell_transpose(1 << 27, 28, None, 5, None, None, None, ctypes.byref(bad), None) == -1
+    assert lib.rbf_ell_transpose(10, 28, None, -1, None, None, None, ctypes.byref(bad), None) == -1
+    assert lib.rbf_ell_transpose(10, 28, None, 5, None, None, None, None, None) == -1
+    assert lib.rbf_ell_transpose(10, 28, None, 5, None, None, None, ctypes.byref(bad), None) == -1
+    assert bad.value == -1 and b"colptr" in lib.rbf_last_error()
+    lib.rbf_ell_apply_transpose.restype = ctypes.c_int32
+    lib.rbf_ell_apply_transpose.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int32, ctypes.c_void_p]
+    assert lib.rbf_ell_apply_transpose(10, 28, None, 5, None, None, None, None, None, 2, None) == -1
+    assert lib.rbf_ell_apply_transpose(10, 28, None, 5, None, None, None, None, None, 0, None) == -1
+    assert lib.rbf_ell_apply_transpose(10, 65, None, 5, None, None, None, None, None, 0, None) == -1
+    assert lib.rbf_ell_apply_transpose(10, 28, None, 0, None, None, None, None, None, 0, None) == 0
     # Batch stepping: argument checks, and an empty batch is a no-op.
     lib.rbf_step_batch.restype = ctypes.c_int32
     lib.rbf_step_batch.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,

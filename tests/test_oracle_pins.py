@@ -286,6 +286,31 @@ def test_ell_csr_consistency():
     assert np.allclose(D @ x, oops.ell_apply(ss.idx, ss.w[0], x), rtol=0, atol=1e-12 * np.abs(D).sum())
 
 
+def test_ell_transpose_adjoint_identity_and_brute_force():
+    """D^T of eq. (10)'s matrix: <D x, y> = <x, D^T y> against the forward
+    ELL product (a different code path), and entry-by-entry equality with a
+    dense matrix filled by plain loops on a tiny operator (rectangular, with
+    columns that no row references)."""
+    nd = ri.cavity_nodes(6, 0.3, 1)
+    ops = oops.CavityOperators(nd, 28, 7, 3)
+    idx, w = ops.pv.idx, ops.pv.weights(ow.OP_DX)
+    ncols = nd.n_v + 5
+    x = ri.random_vector(ncols, 3)
+    y = ri.random_vector(nd.n_p, 4)
+    lhs = np.dot(oops.ell_apply(idx, w, x), y)
+    z = oops.ell_apply_transpose(idx, w, y, ncols)
+    rhs = np.dot(x, z)
+    scale = np.sum(np.abs(w * x[idx] * y[None, :]))
+    assert abs(lhs - rhs) <= 64 * 2.0 ** -53 * scale
+    assert np.all(z[nd.n_v:] == 0.0)
+    D = np.zeros((nd.n_p, ncols))
+    for r in range(nd.n_p):
+        for s in range(idx.shape[0]):
+            D[r, idx[s, r]] += w[s, r]
+    ref = D.T @ y
+    assert np.max(np.abs(z - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
 def test_poisson_matrix_structure():
     """Neumann rows and Laplacian rows annihilate constants (polynomial
     reproduction), so A0 is singular; the bordered system is not, and its
