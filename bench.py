@@ -235,6 +235,34 @@ def spmv_bench(P, args, dev):
             ms = a.elapsed_time(b) / args.spmv_reps
             gbs[f"{name}_{prec}"] = {"us": ms * 1e3, "GB/s": bytes_row * rows / (ms * 1e-3) / 1e9}
     out["ell_apply"] = gbs
+    # Transposed product z = D_x^VV^T y: structure built once (timed as
+    # set-up), weights permuted into column order once per precision, then
+    # applications timed like the forward products.
+    idx, w, ncols = ops["dx_vv"]
+    rows = idx.shape[1]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = P.ell_transpose(idx, ncols)
+    torch.cuda.synchronize()
+    tr = {"build_ms": (time.perf_counter() - t0) * 1e3}
+    for prec in ("fp64", "fp32"):
+        ww = T.weights(w if prec == "fp64" else P.cast_f32(w))
+        y = x64 if prec == "fp64" else x32
+        vb = 8 if prec == "fp64" else 4
+        z = torch.empty(ncols, dtype=ww.dtype, device=dev)
+        for _ in range(10):
+            T.apply(ww, y, z)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.spmv_reps):
+            T.apply(ww, y, z)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.spmv_reps
+        # src + wt per entry, y once per row, colptr + z per column.
+        nbytes = 28 * rows * (4 + vb) + rows * vb + ncols * (8 + vb)
+        tr[prec] = {"us": ms * 1e3, "GB/s": nbytes / (ms * 1e-3) / 1e9}
+    out["ell_apply_transpose_dx_vv"] = tr
     return out
 
 

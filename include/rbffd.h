@@ -170,7 +170,7 @@ rbf_status rbf_cast_f32(const double *src, float *dst, int64_t n, rbf_stream st)
  * row r of each entry) and slot int32 [k * rows] (its slot s), ordered by
  * increasing (r, s) inside each column.  Every ELL entry appears once,
  * zero weights included, so the structure serves every weight array of the
- * same idx (FP64 or FP32).  bad_entry: host; -1, or the lowest ELL position
+ * same idx (FP64 or FP32, permuted by rbf_ell_transpose_weights).  bad_entry: host; -1, or the lowest ELL position
  * s * rows + r whose index is outside [0, ncols).
  * Synchronises the stream (two read-backs) and allocates a workspace of
  * ncols ints for the duration of the call.  Limits: k in [1, 64],
@@ -183,20 +183,36 @@ rbf_status rbf_ell_transpose(int64_t rows, int32_t k, const int32_t *idx, int64_
                              rbf_stream st);
 
 /*
- * rbf_ell_apply_transpose -- z = D^T y with the structure of
- * rbf_ell_transpose: z_c = sum over the entries of column c, in their stored
- * order (increasing source row), of w[slot][src] * y[src], with fused
- * multiply-adds; one thread per column, no atomics, so results are
- * reproducible bit for bit.
+ * rbf_ell_transpose_weights -- one weight array of the operator in the
+ * column order of rbf_ell_transpose: wt[e] = w[slot[e]][src[e]] for
+ * e < k * rows (a gather, once per weight array, so that transposed
+ * products read their weights contiguously).
  *
- * w: device [k][rows] weights (dtype 0: FP64; 1: FP32, as y and z, FP32
- * accumulation); y: device [rows]; z: device [ncols] (columns without
- * entries get 0).  No synchronisation.  Errors: RBF_E_ARG for bad sizes,
- * dtype or NULL pointers.
+ * rows, k: the ELL operator; src, slot: from rbf_ell_transpose (device
+ * int32 [k * rows]); w: device [k][rows]; wt: device [k * rows], caller-
+ * allocated.  dtype 0: FP64 w and wt; 1: FP32.  No synchronisation.
+ * Errors: RBF_E_ARG for bad sizes, dtype or NULL pointers.
  */
-rbf_status rbf_ell_apply_transpose(int64_t rows, int32_t k, const void *w, int64_t ncols,
-                                   const int64_t *colptr, const int32_t *src,
-                                   const int32_t *slot, const void *y, void *z, int32_t dtype,
+rbf_status rbf_ell_transpose_weights(int64_t rows, int32_t k, const int32_t *src,
+                                     const int32_t *slot, const void *w, void *wt, int32_t dtype,
+                                     rbf_stream st);
+
+/*
+ * rbf_ell_apply_transpose -- z = D^T y: z_c = sum over the entries e of
+ * column c (colptr[c] <= e < colptr[c+1], from rbf_ell_transpose) of
+ * wt[e] * y[src[e]] (wt from rbf_ell_transpose_weights).  Eight lanes per
+ * column: lane l accumulates entries l, l + 8, ... with fused multiply-adds,
+ * then the eight partial sums are combined by a fixed butterfly; no
+ * atomics, so results are reproducible bit for bit.
+ *
+ * y: device [rows] of the operator; z: device [ncols] (columns without
+ * entries get 0); src, wt and y may be NULL for an operator without rows.
+ * dtype 0: FP64 wt, y, z; 1: FP32 (FP32 accumulation).
+ * No synchronisation.  Errors: RBF_E_ARG for bad sizes, dtype or NULL
+ * pointers.
+ */
+rbf_status rbf_ell_apply_transpose(int64_t ncols, const int64_t *colptr, const int32_t *src,
+                                   const void *wt, const void *y, void *z, int32_t dtype,
                                    rbf_stream st);
 
 /* ---------------------------------------------------------------------------

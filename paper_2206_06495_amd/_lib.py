@@ -25,7 +25,7 @@ FORCE_SMALL_STENCIL = 0x80000000
 EXPORTED = [
     "rbf_last_error", "rbf_abi_version", "rbf_build_nodes", "rbf_knn",
     "rbf_assemble_weights", "rbf_ell_apply", "rbf_cast_f32", "rbf_ell_transpose",
-    "rbf_ell_apply_transpose", "rbf_solver_create",
+    "rbf_ell_transpose_weights", "rbf_ell_apply_transpose", "rbf_solver_create",
     "rbf_step", "rbf_step_batch", "rbf_solve_pressure", "rbf_solver_apply_precond", "rbf_solver_profile", "rbf_solver_query",
     "rbf_solver_destroy",
 ]
@@ -110,9 +110,11 @@ def _load():
     lib.rbf_ell_transpose.restype = S
     lib.rbf_ell_transpose.argtypes = [ctypes.c_int64, ctypes.c_int32, c_void_p, ctypes.c_int64,
                                       c_void_p, c_void_p, c_void_p, c_int64_p, c_void_p]
+    lib.rbf_ell_transpose_weights.restype = S
+    lib.rbf_ell_transpose_weights.argtypes = [ctypes.c_int64, ctypes.c_int32, c_void_p, c_void_p,
+                                              c_void_p, c_void_p, ctypes.c_int32, c_void_p]
     lib.rbf_ell_apply_transpose.restype = S
-    lib.rbf_ell_apply_transpose.argtypes = [ctypes.c_int64, ctypes.c_int32, c_void_p,
-                                            ctypes.c_int64, c_void_p, c_void_p, c_void_p,
+    lib.rbf_ell_apply_transpose.argtypes = [ctypes.c_int64, c_void_p, c_void_p, c_void_p,
                                             c_void_p, c_void_p, ctypes.c_int32, c_void_p]
     lib.rbf_solver_create.restype = S
     lib.rbf_solver_create.argtypes = [ctypes.POINTER(c_void_p), ctypes.POINTER(Grid),

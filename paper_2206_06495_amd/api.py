@@ -120,19 +120,29 @@ class Transpose:
         self.bad_entry = bad.value
         check(rc)
 
-    def apply(self, w, y, out=None):
-        """z = D^T y with the weights w [k, rows] of the same operator."""
+    def weights(self, w):
+        """w [k, rows] (FP64 or FP32) permuted into column order: wt [k * rows]."""
         if w.dtype not in (torch.float64, torch.float32):
             raise ValueError("w must be float64 or float32")
         _dev(w, w.dtype, (self.k, self.rows), name="w")
-        _dev(y, w.dtype, (self.rows,), name="y")
-        if out is None:
-            out = torch.empty(self.ncols, dtype=w.dtype, device=w.device)
-        _dev(out, w.dtype, (self.ncols,), name="out")
+        wt = torch.empty(max(1, self.k * self.rows), dtype=w.dtype, device=w.device)
         dtype = 0 if w.dtype == torch.float64 else 1
-        check(lib.rbf_ell_apply_transpose(self.rows, self.k, _ptr(w), self.ncols, _ptr(self.colptr),
-                                          _ptr(self.src), _ptr(self.slot), _ptr(y), _ptr(out),
-                                          dtype, _stream()))
+        check(lib.rbf_ell_transpose_weights(self.rows, self.k, _ptr(self.src), _ptr(self.slot),
+                                            _ptr(w), _ptr(wt), dtype, _stream()))
+        return wt
+
+    def apply(self, wt, y, out=None):
+        """z = D^T y with column-ordered weights wt (from weights())."""
+        if wt.dtype not in (torch.float64, torch.float32):
+            raise ValueError("wt must be float64 or float32")
+        _dev(wt, wt.dtype, (max(1, self.k * self.rows),), name="wt")
+        _dev(y, wt.dtype, (self.rows,), name="y")
+        if out is None:
+            out = torch.empty(self.ncols, dtype=wt.dtype, device=wt.device)
+        _dev(out, wt.dtype, (self.ncols,), name="out")
+        dtype = 0 if wt.dtype == torch.float64 else 1
+        check(lib.rbf_ell_apply_transpose(self.ncols, _ptr(self.colptr), _ptr(self.src), _ptr(wt),
+                                          _ptr(y), _ptr(out), dtype, _stream()))
         return out
 
 

@@ -1,8 +1,8 @@
 // rbf_ell_apply: y = D x for one slot-major ELL operator (eq. (10) applied
 // to a vector), FP64 or FP32-stored; plus the FP64 -> FP32 cast helper.
-// rbf_ell_transpose / rbf_ell_apply_transpose: z = D^T y through a column
-// structure built once, in a fixed summation order (no floating-point
-// atomics).
+// rbf_ell_transpose / rbf_ell_transpose_weights / rbf_ell_apply_transpose:
+// z = D^T y through a column structure built once and weights permuted into
+// column order, in a fixed summation order (no floating-point atomics).
 //
 // One thread per row.  For a fixed stencil width all index and weight loads
 // of the row are issued (non-temporal: the operator streams through once)
@@ -147,25 +147,44 @@ __global__ void k_tr_sort(int64_t ncols, const int64_t *__restrict__ colptr, int
     }
 }
 
-// z_c = sum over the entries of column c, in increasing source row, of
-// w[slot][src] * y[src]: one thread per column, FMA accumulation.
+// Weights in column order: wt[e] = w[slot[e]][src[e]] (one gather per
+// weight array, so that products read them contiguously).
 template <class T>
-__global__ void __launch_bounds__(256) k_ell_apply_t(int64_t rows, int64_t ncols,
-                                                     const int64_t *__restrict__ colptr,
+__global__ void k_tr_weights(int64_t rows, int64_t nnz, const int *__restrict__ src,
+                             const int *__restrict__ slot, const T *__restrict__ w,
+                             T *__restrict__ wt) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x)
+        wt[e] = w[(int64_t)slot[e] * rows + src[e]];
+}
+
+// z_c = sum of wt[e] * y[src[e]] over the entries e of column c: kTrLanes
+// lanes per column, lane l summing entries l, l + kTrLanes, ... (FMA), then
+// a fixed butterfly over the lanes of the group, so the result does not
+// depend on the launch.  Consecutive lanes read consecutive entries.
+constexpr int kTrLanes = 8;
+template <class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int off = kTrLanes / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+template <class T>
+__global__ void __launch_bounds__(256) k_ell_apply_t(int64_t ncols, const int64_t *__restrict__ colptr,
                                                      const int *__restrict__ src,
-                                                     const int *__restrict__ slot,
-                                                     const T *__restrict__ w,
+                                                     const T *__restrict__ wt,
                                                      const T *__restrict__ y, T *__restrict__ z) {
     const uint32_t lb = rbf::xcd_block(blockIdx.x, gridDim.x);
-    const int64_t c = (int64_t)lb * blockDim.x + threadIdx.x;
-    if (c >= ncols) return;
-    const int64_t b = colptr[c], e = colptr[c + 1];
+    const int64_t g = ((int64_t)lb * blockDim.x + threadIdx.x) / kTrLanes;
+    const int l = threadIdx.x % kTrLanes;
+    // Whole groups leave together (ncols is the same for every lane of a
+    // group), so the shuffles below see complete groups.
+    if (g >= ncols) return;
+    const int64_t b = colptr[g], e = colptr[g + 1];
     T acc = T(0);
-    for (int64_t i = b; i < e; ++i) {
-        const int r = src[i];
-        acc = fma_t<T>(w[(int64_t)slot[i] * rows + r], y[r], acc);
-    }
-    z[c] = acc;
+    for (int64_t i = b + l; i < e; i += kTrLanes) acc = fma_t<T>(wt[i], y[src[i]], acc);
+    acc = group_sum(acc);
+    if (l == 0) z[g] = acc;
 }
 
 }  // namespace
@@ -278,27 +297,45 @@ extern "C" rbf_status rbf_ell_transpose(int64_t rows, int32_t k, const int32_t *
     return rc;
 }
 
-extern "C" rbf_status rbf_ell_apply_transpose(int64_t rows, int32_t k, const void *w, int64_t ncols,
-                                              const int64_t *colptr, const int32_t *src,
-                                              const int32_t *slot, const void *y, void *z,
-                                              int32_t dtype, rbf_stream st_) {
+extern "C" rbf_status rbf_ell_transpose_weights(int64_t rows, int32_t k, const int32_t *src,
+                                                const int32_t *slot, const void *w, void *wt,
+                                                int32_t dtype, rbf_stream st_) {
     rbf::clear_error();
     RBF_ARG(rows >= 0 && k >= 1 && k <= 64 && rows * k < ((int64_t)1 << 31),
-            "rbf_ell_apply_transpose: rows * k must be below 2^31 and k in [1, 64]");
+            "rbf_ell_transpose_weights: rows * k must be below 2^31 and k in [1, 64]");
+    RBF_ARG(dtype == 0 || dtype == 1, "rbf_ell_transpose_weights: dtype must be 0 (FP64) or 1 (FP32)");
+    const int64_t nnz = rows * k;
+    if (nnz == 0) return RBF_OK;
+    RBF_ARG(src && slot && w && wt, "rbf_ell_transpose_weights: NULL pointer");
+    hipStream_t st = rbf::as_stream(st_);
+    const dim3 grid(std::min<uint32_t>(rbf::blocks_for(nnz, 256), 8192u)), block(256);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_tr_weights<double>, grid, block, 0, st, rows, nnz, src, slot,
+                           static_cast<const double *>(w), static_cast<double *>(wt));
+    else
+        hipLaunchKernelGGL(k_tr_weights<float>, grid, block, 0, st, rows, nnz, src, slot,
+                           static_cast<const float *>(w), static_cast<float *>(wt));
+    RBF_CHECK_LAUNCH();
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_ell_apply_transpose(int64_t ncols, const int64_t *colptr,
+                                              const int32_t *src, const void *wt, const void *y,
+                                              void *z, int32_t dtype, rbf_stream st_) {
+    rbf::clear_error();
     RBF_ARG(ncols >= 0 && ncols < ((int64_t)1 << 31), "rbf_ell_apply_transpose: ncols out of range");
     RBF_ARG(dtype == 0 || dtype == 1, "rbf_ell_apply_transpose: dtype must be 0 (FP64) or 1 (FP32)");
     if (ncols == 0) return RBF_OK;
-    RBF_ARG(colptr && z && (rows == 0 || (w && src && slot && y)),
-            "rbf_ell_apply_transpose: NULL pointer");
+    RBF_ARG(colptr && z, "rbf_ell_apply_transpose: NULL pointer");
     hipStream_t st = rbf::as_stream(st_);
-    const dim3 grid(rbf::blocks_for(ncols, 256)), block(256);
+    const dim3 grid(rbf::blocks_for(ncols * kTrLanes, 256)), block(256);
     if (dtype == 0)
-        hipLaunchKernelGGL(k_ell_apply_t<double>, grid, block, 0, st, rows, ncols, colptr, src, slot,
-                           static_cast<const double *>(w), static_cast<const double *>(y),
+        hipLaunchKernelGGL(k_ell_apply_t<double>, grid, block, 0, st, ncols, colptr, src,
+                           static_cast<const double *>(wt), static_cast<const double *>(y),
                            static_cast<double *>(z));
     else
-        hipLaunchKernelGGL(k_ell_apply_t<float>, grid, block, 0, st, rows, ncols, colptr, src, slot,
-                           static_cast<const float *>(w), static_cast<const float *>(y),
+        hipLaunchKernelGGL(k_ell_apply_t<float>, grid, block, 0, st, ncols, colptr, src,
+                           static_cast<const float *>(wt), static_cast<const float *>(y),
                            static_cast<float *>(z));
     RBF_CHECK_LAUNCH();
     return RBF_OK;

@@ -209,7 +209,8 @@ def _t_bound(idx, w, y, ncols, u):
 
 def test_ell_transpose_parity(P, gpu):
     """z = D^T y (the transposed product of the adjoint): the column
-    structure equals its definition exactly; FP64 and FP32 products agree
+    structure and the column-ordered weights equal their definitions
+    exactly; FP64 and FP32 products agree
     with the oracle within the rounding bound of each column's sum and are
     bit-identical on repetition; rectangular PV (M x N) and square VV
     operators, k = 28 and 17, with columns no row references."""
@@ -229,15 +230,18 @@ def test_ell_transpose_parity(P, gpu):
         assert np.array_equal(T.slot.cpu().numpy(), slot)
         y = ri.random_vector(rows, 21)
         for o in range(2):
-            z = T.apply(w[o].contiguous(), to_dev(y, gpu))
+            wt = T.weights(w[o].contiguous())
+            perm = np.asarray(T.src.cpu().numpy(), np.int64) + rows * T.slot.cpu().numpy()
+            assert np.array_equal(wt.cpu().numpy(), w_h[o].ravel()[perm])
+            z = T.apply(wt, to_dev(y, gpu))
             ref = oops.ell_apply_transpose(idx_h, w_h[o], y, ncols)
             zh = z.cpu().numpy()
             assert np.all(np.abs(zh - ref) <= _t_bound(idx_h, w_h[o], y, ncols, 2.0 ** -53))
             assert np.all(zh[ncols - 3:] == 0.0)
-            assert torch.equal(z, T.apply(w[o].contiguous(), to_dev(y, gpu)))
+            assert torch.equal(z, T.apply(wt, to_dev(y, gpu)))
             w32 = P.cast_f32(w[o].contiguous())
             y32 = P.cast_f32(to_dev(y, gpu))
-            z32 = T.apply(w32, y32).cpu().numpy().astype(np.float64)
+            z32 = T.apply(T.weights(w32), y32).cpu().numpy().astype(np.float64)
             w32h = w32.cpu().numpy().astype(np.float64)
             y32h = y32.cpu().numpy().astype(np.float64)
             ref32 = oops.ell_apply_transpose(idx_h, w32h, y32h, ncols)
@@ -252,7 +256,7 @@ def test_ell_transpose_edge_cases(P, gpu):
     _say("ell transpose edge cases")
     T = P.ell_transpose(torch.zeros((28, 0), dtype=torch.int32, device=gpu), 4)
     assert T.colptr.cpu().tolist() == [0] * 5
-    z = T.apply(torch.zeros((28, 0), dtype=torch.float64, device=gpu),
+    z = T.apply(T.weights(torch.zeros((28, 0), dtype=torch.float64, device=gpu)),
                 torch.zeros(0, dtype=torch.float64, device=gpu))
     assert z.cpu().tolist() == [0.0] * 4
     idx = torch.zeros((28, 10), dtype=torch.int32)

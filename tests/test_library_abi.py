@@ -31,7 +31,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("rbf_build_nodes", "rbf_knn", "rbf_assemble_weights", "rbf_ell_apply",
-              "rbf_ell_transpose", "rbf_ell_apply_transpose", "rbf_solver_create", "rbf_step", "rbf_solve_pressure", "rbf_solver_destroy"):
+              "rbf_ell_transpose", "rbf_ell_transpose_weights", "rbf_ell_apply_transpose",
+              "rbf_solver_create", "rbf_step", "rbf_solve_pressure", "rbf_solver_destroy"):
         assert n in names
 
 
@@ -101,15 +102,22 @@ def test_argument_validation_before_any_device_work(lib):
     assert lib.rbf_ell_transpose(10, 28, None, 5, None, None, None, None, None) == -1
     assert lib.rbf_ell_transpose(10, 28, None, 5, None, None, None, ctypes.byref(bad), None) == -1
     assert bad.value == -1 and b"colptr" in lib.rbf_last_error()
+    lib.rbf_ell_transpose_weights.restype = ctypes.c_int32
+    lib.rbf_ell_transpose_weights.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_int32, ctypes.c_void_p]
+    assert lib.rbf_ell_transpose_weights(10, 0, None, None, None, None, 0, None) == -1
+    assert lib.rbf_ell_transpose_weights(10, 28, None, None, None, None, 2, None) == -1
+    assert lib.rbf_ell_transpose_weights(10, 28, None, None, None, None, 0, None) == -1
+    assert lib.rbf_ell_transpose_weights(0, 28, None, None, None, None, 0, None) == 0
     lib.rbf_ell_apply_transpose.restype = ctypes.c_int32
-    lib.rbf_ell_apply_transpose.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
-                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+    lib.rbf_ell_apply_transpose.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_int32, ctypes.c_void_p]
-    assert lib.rbf_ell_apply_transpose(10, 28, None, 5, None, None, None, None, None, 2, None) == -1
-    assert lib.rbf_ell_apply_transpose(10, 28, None, 5, None, None, None, None, None, 0, None) == -1
-    assert lib.rbf_ell_apply_transpose(10, 65, None, 5, None, None, None, None, None, 0, None) == -1
-    assert lib.rbf_ell_apply_transpose(10, 28, None, 0, None, None, None, None, None, 0, None) == 0
+    assert lib.rbf_ell_apply_transpose(5, None, None, None, None, None, 2, None) == -1
+    assert lib.rbf_ell_apply_transpose(5, None, None, None, None, None, 0, None) == -1
+    assert lib.rbf_ell_apply_transpose(-1, None, None, None, None, None, 0, None) == -1
+    assert lib.rbf_ell_apply_transpose(0, None, None, None, None, None, 0, None) == 0
     # Batch stepping: argument checks, and an empty batch is a no-op.
     lib.rbf_step_batch.restype = ctypes.c_int32
     lib.rbf_step_batch.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
