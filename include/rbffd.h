@@ -325,7 +325,9 @@ typedef struct rbf_solver rbf_solver;
  * u_bc, v_bc: device [n_v] boundary velocities (read on wall rows; copied).
  * The solver keeps `st` for all of its work.
  * Errors: RBF_E_ARG (NULL pointers, sizes, dt/re <= 0, unknown precision,
- * unknown precond, RBF_PRECOND_LATTICE on a non-lattice P-grid, a self
+ * unknown precond, RBF_PRECOND_LATTICE on a non-lattice P-grid, a stencil
+ * index outside its source node range (checked on the device before any
+ * other use; the message names the array, slot, row and value), a self
  * index missing from a (V,V) or (P,P) stencil, no interior P node),
  * RBF_E_NOMEM, RBF_E_DEVICE.
  */

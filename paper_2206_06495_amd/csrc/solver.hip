@@ -2454,6 +2454,60 @@ rbf_status copy_in(rbf_solver *S, void *dst, const void *src, size_t bytes) {
     return RBF_OK;
 }
 
+// Lowest ELL position of idx[0, n) outside [0, ns) into *bad (atomic min).
+__global__ void k_idx_range(const int *__restrict__ idx, int64_t n, int64_t ns,
+                            unsigned long long *bad) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = idx[e];
+        if (c < 0 || (int64_t)c >= ns) atomicMin(bad, (unsigned long long)e);
+    }
+}
+
+// Every stencil index of the four operators lies in its source node range;
+// checked before any kernel gathers through them.
+rbf_status check_stencils(hipStream_t st, const rbf_grid *g, const rbf_ops *o) {
+    struct Set {
+        const char *name;
+        const int *idx;
+        int64_t rows, ns;
+    };
+    const Set sets[4] = {{"idx_vv", o->idx_vv, g->n_v, g->n_v},
+                         {"idx_pv", o->idx_pv, g->n_p, g->n_v},
+                         {"idx_pp", o->idx_pp, g->n_p, g->n_p},
+                         {"idx_vp", o->idx_vp, g->n_v, g->n_p}};
+    unsigned long long *bad = nullptr;
+    RBF_HIP(hipMalloc((void **)&bad, 4 * sizeof(unsigned long long)));
+    unsigned long long hb[4];
+    int hv[4] = {0, 0, 0, 0};
+    rbf_status rc = RBF_OK;
+    auto run = [&]() -> rbf_status {
+        RBF_HIP(hipMemsetAsync(bad, 0xff, 4 * sizeof(unsigned long long), st));
+        for (int q = 0; q < 4; ++q) {
+            const int64_t n = sets[q].rows * o->k;
+            hipLaunchKernelGGL(k_idx_range, dim3(std::min<uint32_t>(rbf::blocks_for(n, 256), 4096u)),
+                               dim3(256), 0, st, sets[q].idx, n, sets[q].ns, bad + q);
+        }
+        RBF_CHECK_LAUNCH();
+        RBF_HIP(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        for (int q = 0; q < 4; ++q)
+            if (hb[q] != ~0ull) {
+                RBF_HIP(hipMemcpy(&hv[q], sets[q].idx + hb[q], sizeof(int), hipMemcpyDeviceToHost));
+                rbf::set_error("rbf_solver_create: %s[%llu][%llu] = %d is outside [0, %lld)",
+                               sets[q].name, hb[q] / (unsigned long long)sets[q].rows,
+                               hb[q] % (unsigned long long)sets[q].rows, hv[q],
+                               (long long)sets[q].ns);
+                return RBF_E_ARG;
+            }
+        return RBF_OK;
+    };
+    rc = run();
+    if (rc != RBF_OK) (void)hipStreamSynchronize(st);
+    (void)hipFree(bad);
+    return rc;
+}
+
 rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const double *u_bc,
                        const double *v_bc, const rbf_params *prm) {
     const int64_t N = g->n_v, M = g->n_p;
@@ -2744,7 +2798,8 @@ extern "C" rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, 
         rbf::set_error("rbf_solver_create: hipGetDevice failed");
         return RBF_E_DEVICE;
     }
-    rbf_status rc = create_impl(S, grid, ops, u_bc, v_bc, prm);
+    rbf_status rc = check_stencils(S->st, grid, ops);
+    if (rc == RBF_OK) rc = create_impl(S, grid, ops, u_bc, v_bc, prm);
     if (rc != RBF_OK) {
         rbf_solver_destroy(S);
         return rc;

@@ -525,6 +525,26 @@ def test_step_error_paths_are_transactional(P, gpu):
     S.close()
 
 
+def test_solver_create_rejects_out_of_range_stencils(P, gpu):
+    """A stencil index outside its source node range (one too large in VP,
+    negative in PV) is refused by rbf_solver_create with RBF_E_ARG naming the
+    array, slot and row, before any kernel gathers through it."""
+    _say("stencil range check")
+    nd = ri.cavity_nodes(8, 0.3, 0)
+    grid, ops = gpu_cavity_ops(nd, gpu)
+    u_bc, v_bc = ri.cavity_bc(nd.v_tag)
+    for name, slot, row, val in (("idx_vp", 5, 7, nd.n_p), ("idx_pv", 27, 0, -1)):
+        bad = dict(ops)
+        bad[name] = ops[name].clone()
+        bad[name][slot, row] = val
+        with pytest.raises(P.RbfError) as ei:
+            P.Solver(grid, bad, to_dev(u_bc, gpu), to_dev(v_bc, gpu), 100.0, 2e-3)
+        assert ei.value.status == -1
+        assert f"{name}[{slot}][{row}] = {val}" in str(ei.value), str(ei.value)
+    S = P.Solver(grid, ops, to_dev(u_bc, gpu), to_dev(v_bc, gpu), 100.0, 2e-3)
+    S.close()
+
+
 def test_checkpoint_resume_is_bitwise(P, gpu):
     """(u, v, p~, p, C_{j-1}(u), C_{j-1}(v), j) is the whole carried state of
     the scheme (AB2, eq. (14), needs the previous advection terms): saved
