@@ -424,6 +424,7 @@ def main():
     prof = S.profile(0)
     value = (N + M) * args.steps / el
     umax = float(st["u"].abs().max())
+    diag = S.diagnostics(st)
     log(f"{el:.3f}s  {value:.3e} node-steps/s  poisson iters/step "
         f"{stats.poisson_iters / max(1, args.steps):.1f}  |u|max {umax:.3f}")
     # Dominant kernel: k_pc_gemm, the n x n x n FP64 products of the
@@ -454,6 +455,7 @@ def main():
                    "last_poisson_rel_residual": stats.last.last_poisson.rel_residual
                    if stats.last else None,
                    "segment": args.segment, "restores_in_timed_steps": stats.restarts,
+                   "final_state": diag,
                    "u_abs_max": umax},
         "roofline": {"kernel": f"k_pc_gemm<0> (preconditioner transform, FP64 MFMA, "
                                f"{n}x{n}x{n})",

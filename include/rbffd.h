@@ -421,6 +421,25 @@ typedef struct {
 } rbf_solver_info;
 rbf_status rbf_solver_query(rbf_solver *s, rbf_solver_info *info);
 
+/*
+ * rbf_solver_diagnostics -- per-step health figures of a state (host struct,
+ * filled; for logging and for spotting a diverging run):
+ *   div_max, div_rms   max and root mean square over interior P-nodes of
+ *                      F = D_x^PV u + D_y^PV v (eq. (17) applied to u, v);
+ *   kinetic_energy     (1/2) mean over V-nodes of u^2 + v^2 (unweighted);
+ *   speed_max          max over V-nodes of sqrt(u^2 + v^2);
+ *   cfl                dt * max over V-nodes of sqrt(u^2 + v^2) / d_r, d_r
+ *                      the distance to the nearest other node of the node's
+ *                      (V,V) stencil.
+ * Non-finite velocities give NaN maxima.  state: device u, v [n_v] (the other
+ * fields are not read).  Reductions run in a fixed order (repeatable bit for
+ * bit).  Synchronises the solver's stream.  Errors: RBF_E_ARG (NULL).
+ */
+typedef struct {
+    double div_max, div_rms, kinetic_energy, speed_max, cfl;
+} rbf_diagnostics;
+rbf_status rbf_solver_diagnostics(rbf_solver *s, const rbf_state *state, rbf_diagnostics *out);
+
 /* Release a solver (NULL is ignored). */
 void rbf_solver_destroy(rbf_solver *s);
 

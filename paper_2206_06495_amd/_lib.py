@@ -27,6 +27,7 @@ EXPORTED = [
     "rbf_assemble_weights", "rbf_ell_apply", "rbf_cast_f32", "rbf_ell_transpose",
     "rbf_ell_transpose_weights", "rbf_ell_apply_transpose", "rbf_solver_create",
     "rbf_step", "rbf_step_batch", "rbf_solve_pressure", "rbf_solver_apply_precond", "rbf_solver_profile", "rbf_solver_query",
+    "rbf_solver_diagnostics",
     "rbf_solver_destroy",
 ]
 
@@ -66,6 +67,12 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("restarts", ctypes.c_int32),
                 ("final_flag", ctypes.c_int32)]
+
+
+class Diagnostics(ctypes.Structure):
+    _fields_ = [("div_max", ctypes.c_double), ("div_rms", ctypes.c_double),
+                ("kinetic_energy", ctypes.c_double), ("speed_max", ctypes.c_double),
+                ("cfl", ctypes.c_double)]
 
 
 class SolverInfo(ctypes.Structure):
@@ -135,6 +142,9 @@ def _load():
     lib.rbf_solver_profile.argtypes = [c_void_p, ctypes.c_int32, c_double_p, c_int64_p]
     lib.rbf_solver_query.restype = S
     lib.rbf_solver_query.argtypes = [c_void_p, ctypes.POINTER(SolverInfo)]
+    lib.rbf_solver_diagnostics.restype = S
+    lib.rbf_solver_diagnostics.argtypes = [c_void_p, ctypes.POINTER(State),
+                                           ctypes.POINTER(Diagnostics)]
     lib.rbf_solver_destroy.restype = None
     lib.rbf_solver_destroy.argtypes = [c_void_p]
     return lib

@@ -254,6 +254,14 @@ class Solver:
         return {"viscous_jacobi": bool(inf.viscous_jacobi),
                 "lattice_precond": bool(inf.lattice_precond), "jacobi_bound": inf.jacobi_bound}
 
+    def diagnostics(self, state):
+        """Health figures of a state: {"div_max", "div_rms", "kinetic_energy",
+        "speed_max", "cfl"} (rbf_solver_diagnostics)."""
+        st = self._state_struct(state)
+        d = _lib.Diagnostics()
+        check(lib.rbf_solver_diagnostics(self._h, ctypes.byref(st), ctypes.byref(d)))
+        return {f: getattr(d, f) for f, _ in d._fields_}
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib.rbf_solver_destroy(self._h)

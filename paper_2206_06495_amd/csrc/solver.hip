@@ -1725,6 +1725,9 @@ struct rbf_solver {
     int8_t *p_tag = nullptr;
     int *wall_rows = nullptr;
     double *u_bc = nullptr, *v_bc = nullptr;
+    double *v_hmin = nullptr;    // [N] nearest stencil-neighbour distance (CFL)
+    double *diag_part = nullptr; // [5][kMaxBlocks] diagnostics partials
+    int64_t n_interior_p = 0;
     // state (committed) and step workspace
     double *u = nullptr, *v = nullptr, *pt = nullptr, *p = nullptr, *cu = nullptr, *cv = nullptr;
     double *un = nullptr, *vn = nullptr, *ptn = nullptr, *pn = nullptr, *cun = nullptr,
@@ -2454,6 +2457,98 @@ rbf_status copy_in(rbf_solver *S, void *dst, const void *src, size_t bytes) {
     return RBF_OK;
 }
 
+// ------------------------------------------------------- diagnostics --
+// Maximum that propagates NaN (a non-finite field must show in the result).
+__device__ __forceinline__ double nanmax(double a, double b) {
+    return (a != a || b != b) ? __builtin_nan("") : fmax(a, b);
+}
+__device__ __forceinline__ double block_max(double v) {
+    __shared__ double lds[kThreads / 64];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = lds[0];
+    for (int w = 1; w < kThreads / 64; ++w) m = nanmax(m, lds[w]);
+    __syncthreads();
+    return m;
+}
+
+// Distance from each V-node to its nearest stencil neighbour (CFL scale).
+__global__ void __launch_bounds__(kThreads) k_vhmin(int64_t n, int k, const int *__restrict__ idx,
+                                                     const double *__restrict__ xv,
+                                                     double *__restrict__ hmin) {
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    const double x = xv[r], y = xv[n + r];
+    double d2 = __builtin_inf();
+    for (int s = 0; s < k; ++s) {
+        const int j = idx[(int64_t)s * n + r];
+        if (j == r) continue;
+        const double dx = xv[j] - x, dy = xv[n + j] - y;
+        d2 = fmin(d2, dx * dx + dy * dy);
+    }
+    hmin[r] = sqrt(d2);
+}
+
+// V rows: block partials of sum(u^2 + v^2), max speed, max speed / hmin.
+__global__ void __launch_bounds__(kThreads) k_diag_v(int64_t n, const double *__restrict__ u,
+                                                      const double *__restrict__ v,
+                                                      const double *__restrict__ hmin,
+                                                      double *__restrict__ part) {
+    double s[1] = {0.0}, smax = 0.0, cmax = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * kThreads) {
+        const double q = u[r] * u[r] + v[r] * v[r], sp = sqrt(q);
+        s[0] += q;
+        smax = nanmax(smax, sp);
+        cmax = nanmax(cmax, sp / hmin[r]);
+    }
+    smax = block_max(smax);
+    cmax = block_max(cmax);
+    {
+        __shared__ double lds[kThreads / 64];
+        rbf::block_sum<1>(s, lds);
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s[0];
+        part[gridDim.x + blockIdx.x] = smax;
+        part[2 * gridDim.x + blockIdx.x] = cmax;
+    }
+}
+
+// Interior P rows: F = D_x^PV u + D_y^PV v (eq. (17)); block partials of
+// max |F| and sum F^2.
+template <int KT>
+__global__ void __launch_bounds__(kThreads) k_diag_p(int64_t m, int k, const int *__restrict__ idx,
+                                                      const double *__restrict__ wdx,
+                                                      const double *__restrict__ wdy,
+                                                      const double *__restrict__ u,
+                                                      const double *__restrict__ v,
+                                                      const int8_t *__restrict__ ptag,
+                                                      double *__restrict__ part) {
+    double s2[1] = {0.0}, fmx = 0.0;
+    const double *ws[2] = {wdx, wdy};
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < m;
+         r += (int64_t)gridDim.x * kThreads) {
+        if (ptag[r] != 0) continue;
+        double acc[2][2] = {};
+        rbf::ell_row<KT, 2>(idx, ws, m, r, k, Gather2{u, v}, acc);
+        const double F = acc[0][0] + acc[1][1];
+        fmx = nanmax(fmx, fabs(F));
+        s2[0] += F * F;
+    }
+    fmx = block_max(fmx);
+    {
+        __shared__ double lds[kThreads / 64];
+        rbf::block_sum<1>(s2, lds);
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = fmx;
+        part[gridDim.x + blockIdx.x] = s2[0];
+    }
+}
+
 // Lowest ELL position of idx[0, n) outside [0, ns) into *bad (atomic min).
 __global__ void k_idx_range(const int *__restrict__ idx, int64_t n, int64_t ns,
                             unsigned long long *bad) {
@@ -2552,6 +2647,8 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     ALLOC(S->u_bc, N);
     ALLOC(S->v_bc, N);
     ALLOC(S->wall_rows, N);
+    ALLOC(S->v_hmin, N);
+    ALLOC(S->diag_part, 5 * kMaxBlocks);
     for (double **q : {&S->u, &S->v, &S->cu, &S->cv, &S->un, &S->vn, &S->cun, &S->cvn, &S->us, &S->vs})
         ALLOC(*q, N);
     for (double **q : {&S->pt, &S->p, &S->ptn, &S->pn, &S->prhs}) ALLOC(*q, M);
@@ -2614,6 +2711,8 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
                        S->p_w, S->p_dinv, S->p_rowscale, S->p_u1, err);
     hipLaunchKernelGGL(k_wall_list, dim3(rbf::blocks_for(N, 256)), dim3(256), 0, st, N, g->v_tag,
                        S->wall_rows, cnt);
+    hipLaunchKernelGGL(k_vhmin, dim3(rbf::blocks_for(N, kThreads)), dim3(kThreads), 0, st, N, k,
+                       S->idx_vv, g->xv, S->v_hmin);
     RBF_CHECK_LAUNCH();
     int herr[2] = {0, 0};
     RBF_HIP(hipMemcpyAsync(&herr[0], err, ib, hipMemcpyDeviceToHost, st));
@@ -2650,6 +2749,7 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
             ++ni;
         }
     RBF_ARG(ni > 0, "rbf_solver_create: no interior P-node");
+    S->n_interior_p = ni;
     S->p_vscale = ((double)ni / su) / (double)M;
     // The wall list order from atomics is irrelevant: rows are independent.
     return setup_lattice_pc(S, g, prm->precond);
@@ -2939,6 +3039,46 @@ extern "C" rbf_status rbf_solver_apply_precond(rbf_solver *S, const double *y, d
                        S->pk.partS, S->pk.partGs, nb);
     RBF_CHECK_LAUNCH();
     RBF_HIP(hipStreamSynchronize(st));
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_solver_diagnostics(rbf_solver *S, const rbf_state *state,
+                                             rbf_diagnostics *out) {
+    rbf::clear_error();
+    RBF_ARG(S && state && out && state->u && state->v, "rbf_solver_diagnostics: NULL argument");
+    hipStream_t st = S->st;
+    const int nbv = (int)std::min<int64_t>(kMaxBlocks, rbf::blocks_for(S->N, kThreads));
+    const int nbp = (int)std::min<int64_t>(kMaxBlocks, rbf::blocks_for(S->M, kThreads));
+    double *pv = S->diag_part, *pp = S->diag_part + 3 * kMaxBlocks;
+    hipLaunchKernelGGL(k_diag_v, dim3(nbv), dim3(kThreads), 0, st, S->N, state->u, state->v,
+                       S->v_hmin, pv);
+    if (S->k == 28)
+        hipLaunchKernelGGL(k_diag_p<28>, dim3(nbp), dim3(kThreads), 0, st, S->M, S->k, S->idx_pv,
+                           S->pv_dx, S->pv_dy, state->u, state->v, S->p_tag, pp);
+    else
+        hipLaunchKernelGGL(k_diag_p<0>, dim3(nbp), dim3(kThreads), 0, st, S->M, S->k, S->idx_pv,
+                           S->pv_dx, S->pv_dy, state->u, state->v, S->p_tag, pp);
+    RBF_CHECK_LAUNCH();
+    std::vector<double> hv(3 * (size_t)nbv), hp(2 * (size_t)nbp);
+    RBF_HIP(hipMemcpyAsync(hv.data(), pv, hv.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipMemcpyAsync(hp.data(), pp, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+    auto nmax = [](double a, double b) { return (std::isnan(a) || std::isnan(b)) ? NAN : std::max(a, b); };
+    double ke = 0.0, smax = 0.0, cmax = 0.0, fmx = 0.0, s2 = 0.0;
+    for (int b = 0; b < nbv; ++b) {
+        ke += hv[b];
+        smax = nmax(smax, hv[nbv + b]);
+        cmax = nmax(cmax, hv[2 * nbv + b]);
+    }
+    for (int b = 0; b < nbp; ++b) {
+        fmx = nmax(fmx, hp[b]);
+        s2 += hp[nbp + b];
+    }
+    out->kinetic_energy = 0.5 * ke / (double)S->N;
+    out->speed_max = smax;
+    out->cfl = S->dt * cmax;
+    out->div_max = fmx;
+    out->div_rms = S->n_interior_p > 0 ? std::sqrt(s2 / (double)S->n_interior_p) : 0.0;
     return RBF_OK;
 }
 

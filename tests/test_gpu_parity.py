@@ -545,6 +545,45 @@ def test_solver_create_rejects_out_of_range_stencils(P, gpu):
     S.close()
 
 
+def test_solver_diagnostics(P, gpu):
+    """rbf_solver_diagnostics after 10 steps of the K=24 cavity against
+    their definitions evaluated on the downloaded fields: divergence of
+    eq. (17) on interior P rows (within its summation bound), kinetic
+    energy, maximum speed and CFL number (nearest stencil neighbour
+    distance) to rounding; repeatable bit for bit; a NaN shows as NaN."""
+    import torch
+    _say("diagnostics K=24")
+    nd = ri.cavity_nodes(24, 0.3, 1)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 2e-3)
+    st = S.new_state(to_dev(np.where(nd.v_tag != 0, u_bc, 0.0), gpu), to_dev(v_bc, gpu))
+    S.step(st, 10)
+    d = S.diagnostics(st)
+    assert d == S.diagnostics(st)
+    u, v = st["u"].cpu().numpy(), st["v"].cpu().numpy()
+    idx = ops["idx_pv"].cpu().numpy()
+    wx, wy = ops["pv_dx"].cpu().numpy(), ops["pv_dy"].cpu().numpy()
+    F = oops.ell_apply(idx, wx, u) + oops.ell_apply(idx, wy, v)
+    bound = 4.0 * 28 * 2.0 ** -53 * (np.abs(wx * u[idx]) + np.abs(wy * v[idx])).sum(axis=0)
+    inner = nd.p_tag == 0
+    assert abs(d["div_max"] - np.max(np.abs(F[inner]))) <= np.max(bound[inner])
+    assert abs(d["div_rms"] - np.sqrt(np.mean(F[inner] ** 2))) <= np.max(bound[inner])
+    sp = np.sqrt(u * u + v * v)
+    assert abs(d["kinetic_energy"] - 0.5 * np.mean(u * u + v * v)) <= 1e-14 * d["kinetic_energy"]
+    assert abs(d["speed_max"] - np.max(sp)) <= 4e-16 * np.max(sp)
+    iv = ops["idx_vv"].cpu().numpy()
+    dx = nd.xv[0][iv] - nd.xv[0][None, :]
+    dy = nd.xv[1][iv] - nd.xv[1][None, :]
+    d2 = np.where(iv == np.arange(nd.n_v)[None, :], np.inf, dx * dx + dy * dy)
+    cfl = 2e-3 * np.max(sp / np.sqrt(d2.min(axis=0)))
+    assert abs(d["cfl"] - cfl) <= 1e-14 * cfl
+    bad = dict(st)
+    bad["u"] = st["u"].clone()
+    bad["u"][5] = float("nan")
+    dn = S.diagnostics(bad)
+    assert np.isnan(dn["speed_max"]) and np.isnan(dn["cfl"]) and np.isnan(dn["kinetic_energy"])
+    S.close()
+
+
 def test_checkpoint_resume_is_bitwise(P, gpu):
     """(u, v, p~, p, C_{j-1}(u), C_{j-1}(v), j) is the whole carried state of
     the scheme (AB2, eq. (14), needs the previous advection terms): saved

@@ -118,6 +118,9 @@ def test_argument_validation_before_any_device_work(lib):
     assert lib.rbf_ell_apply_transpose(5, None, None, None, None, None, 0, None) == -1
     assert lib.rbf_ell_apply_transpose(-1, None, None, None, None, None, 0, None) == -1
     assert lib.rbf_ell_apply_transpose(0, None, None, None, None, None, 0, None) == 0
+    lib.rbf_solver_diagnostics.restype = ctypes.c_int32
+    lib.rbf_solver_diagnostics.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.rbf_solver_diagnostics(None, None, None) == -1
     # Batch stepping: argument checks, and an empty batch is a no-op.
     lib.rbf_step_batch.restype = ctypes.c_int32
     lib.rbf_step_batch.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
