@@ -1506,6 +1506,7 @@ __global__ void __launch_bounds__(kThreads) k_helm_rhs(int64_t n, int k, const i
 }
 
 // Kim-Moin wall values (eq. (21)): u** = u_bc + dt D_x^VP p~_j, v** likewise.
+template <int KT>
 __global__ void __launch_bounds__(kThreads) k_wall_rhs(int64_t nwall, const int *__restrict__ rows,
                                                         int64_t n, int k, const int *__restrict__ idx,
                                                         const double *__restrict__ wdx,
@@ -1515,17 +1516,13 @@ __global__ void __launch_bounds__(kThreads) k_wall_rhs(int64_t nwall, const int 
                                                         const double *__restrict__ v_bc, double dt,
                                                         double *__restrict__ rhs,
                                                         double *__restrict__ x0) {
-    const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nwall) return;
     const int64_t r = rows[i];
-    double gx = 0.0, gy = 0.0;
-    for (int s = 0; s < k; ++s) {
-        const int64_t o = (int64_t)s * n + r;
-        const double pj = pt[idx[o]];
-        gx = fma(wdx[o], pj, gx);
-        gy = fma(wdy[o], pj, gy);
-    }
-    const double ru = u_bc[r] + dt * gx, rv = v_bc[r] + dt * gy;
+    double acc[2][1] = {};
+    const double *ws[2] = {wdx, wdy};
+    rbf::ell_row<KT, 2>(idx, ws, n, r, k, GatherN<1>{pt, 0}, acc);
+    const double ru = u_bc[r] + dt * acc[0][0], rv = v_bc[r] + dt * acc[1][0];
     rhs[r] = ru;
     rhs[n + r] = rv;
     x0[r] = ru;
@@ -2783,9 +2780,14 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
             hipLaunchKernelGGL(k_guess<1>, g2, b2, 0, st, 2 * N, S->uvss, S->hh[0], S->hh[1], S->hh[2], S->hh[3]);
     }
     if (S->nwall > 0)
-        hipLaunchKernelGGL(k_wall_rhs, dim3(rbf::blocks_for(S->nwall, kThreads)), blk, 0, st,
-                           S->nwall, S->wall_rows, N, k, S->idx_vp, S->vp_dx, S->vp_dy, S->pt,
-                           S->u_bc, S->v_bc, S->dt, S->hrhs, S->uvss);
+        launch_kt(k, [&](auto KT) {
+            // Wall rows are few and scattered (uncoalesced gathers): small
+            // workgroups spread them over more compute units.
+            hipLaunchKernelGGL((k_wall_rhs<decltype(KT)::value>),
+                               dim3(rbf::blocks_for(S->nwall, 64)), dim3(64), 0, st, S->nwall,
+                               S->wall_rows, N, k, S->idx_vp, S->vp_dx, S->vp_dy, S->pt, S->u_bc,
+                               S->v_bc, S->dt, S->hrhs, S->uvss);
+        });
     RBF_CHECK_LAUNCH();
     rbf_solve_stats hs[2];
     EllM H{S->idx_vv, S->h_w, S->h_dinv, N, k, nullptr, 0.0};
