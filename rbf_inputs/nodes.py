@@ -140,6 +140,56 @@ def cavity_nodes(K, jitter=0.3, seed=0):
                    np.stack([nx, ny]), K, h)
 
 
+def hex_cavity_nodes(K):
+    """Unit-square cavity on a near-equilateral triangulation (the kind of
+    grid DistMesh produces, Sec. 3), unjittered: P-nodes on rows y_j = j/R,
+    R = round(2K / sqrt(3)), spaced h = 1/K and offset by h/2 on odd rows,
+    plus wall vertices at x = 0 and x = 1 on every row; the Delaunay
+    triangulation of those vertices gives the edges and V-nodes are their
+    midpoints.  Tags and normals as in ``cavity_nodes``.  Used to compare
+    node layouts, not by the lattice preconditioner."""
+    from scipy.spatial import Delaunay
+    if K < 2:
+        raise ValueError("K must be >= 2")
+    h = 1.0 / K
+    R = int(round(2.0 * K / np.sqrt(3.0)))
+    px, py, tag = [], [], []
+    for j in range(R + 1):
+        y = j / R
+        if j == 0 or j == R:
+            xs = np.arange(K + 1) * h
+            xs[-1] = 1.0
+            tags = [TAG_WALL] * (K + 1)
+        else:
+            off = 0.5 * h if j % 2 else 0.0
+            inner = [x for x in (np.arange(K + 1) * h + off) if 0.3 * h < x < 1.0 - 0.3 * h]
+            xs = np.array([0.0] + inner + [1.0])
+            tags = [TAG_WALL] + [TAG_INTERIOR] * len(inner) + [TAG_WALL]
+        px += list(xs)
+        py += [y] * len(xs)
+        tag += tags
+    px, py = np.array(px), np.array(py)
+    p_tag = np.array(tag, np.int8)
+    simp = Delaunay(np.stack([px, py], 1)).simplices
+    e = np.concatenate([simp[:, [0, 1]], simp[:, [1, 2]], simp[:, [0, 2]]])
+    e = np.unique(np.sort(e, axis=1), axis=0)
+    ea, eb = e[:, 0], e[:, 1]
+    vx = (px[ea] + px[eb]) * 0.5
+    vy = (py[ea] + py[eb]) * 0.5
+    on_wall = (p_tag[ea] != TAG_INTERIOR) & (p_tag[eb] != TAG_INTERIOR) & (
+        (px[ea] == px[eb]) & ((px[ea] == 0.0) | (px[ea] == 1.0))
+        | (py[ea] == py[eb]) & ((py[ea] == 0.0) | (py[ea] == 1.0)))
+    lid = on_wall & (vy == 1.0)
+    v_tag = np.where(lid, TAG_LID, np.where(on_wall, TAG_WALL, TAG_INTERIOR)).astype(np.int8)
+    nx = np.where(px == 0.0, -1.0, np.where(px == 1.0, 1.0, 0.0))
+    ny = np.where(py == 0.0, -1.0, np.where(py == 1.0, 1.0, 0.0))
+    corner = (nx != 0.0) & (ny != 0.0)
+    nx = np.where(corner, nx * SQRT_HALF, nx)
+    ny = np.where(corner, ny * SQRT_HALF, ny)
+    return NodeSet(np.stack([vx, vy]), v_tag, np.stack([px, py]), p_tag,
+                   np.stack([nx, ny]), K, h)
+
+
 def square_nodes(K, jitter=0.3, seed=0):
     """Operator-bench square: K^2 V-nodes ((i+1/2)h, (j+1/2)h) and K^2
     P-nodes (ih, jh), i, j = 0..K-1, h = 1/K, both jittered; no walls."""

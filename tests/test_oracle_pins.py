@@ -445,12 +445,12 @@ def test_stable_small_cavity_run():
     assert np.max(np.abs(s.u[wall] - orc.u_bc[wall])) < 5e-3
 
 
-def _projection_radius(K):
+def _projection_radius(K, hexagonal=False):
     """Spectral radius of the velocity map of eqs. (17), (18) and (20) alone
     (interior V rows; wall rows held at zero): u -> u - G p~ with
     A p~ = D u on interior P rows, 0 on wall rows (bordered system)."""
     import scipy.sparse.linalg as spla
-    nd = ri.cavity_nodes(K, 0.3, 0)
+    nd = ri.hex_cavity_nodes(K) if hexagonal else ri.cavity_nodes(K, 0.3, 0)
     ops = oops.CavityOperators(nd, 28, 7, 3)
     _, chi, B = oops.poisson_matrix(ops)
     lu = spla.splu(B.tocsc())
@@ -471,11 +471,14 @@ def _projection_radius(K):
 def test_projection_spectral_radius():
     """An exact projection has eigenvalues 0 and 1; with D_Lap^PP in place
     of D^PV D^VP the projection is approximate.  With the Neumann wall rows
-    its spectral radius is 1 at h = 1/24 (the parity cases' regime) and
-    exceeds 1 at h = 1/60 (observed: 6.9; near-wall modes), which is the
-    divergence of long runs on jittered node sets."""
+    its spectral radius on the right-triangle lattice is 1 at h = 1/24 (the
+    parity cases' regime) and exceeds 1 at h = 1/60 (observed: 6.9;
+    near-wall modes), which is the divergence of long runs on those node
+    sets; on a near-equilateral triangulation of the same square (the kind
+    of grid the paper uses) it stays 1 at h = 1/60."""
     assert _projection_radius(24) <= 1.0 + 1e-6
     assert _projection_radius(60) > 2.0
+    assert _projection_radius(60, hexagonal=True) <= 1.0 + 1e-6
 
 
 def test_brute_force_dense_tiny_cavity():
