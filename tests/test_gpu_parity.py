@@ -499,6 +499,26 @@ def test_cavity_parity_unpreconditioned(P, gpu):
     S.close()
 
 
+def test_cavity_parity_near_equilateral_nodes(P, gpu):
+    """A cavity on a near-equilateral triangulation (hexagonal rows, Delaunay
+    edges; not a lattice, so the pressure iteration runs without the lattice
+    preconditioner): 60 steps at Re = 1e3, dt = 1e-3, u, v, p, p~ within
+    1e-10 of the oracle."""
+    _say("cavity parity, near-equilateral nodes K=20")
+    nd = ri.hex_cavity_nodes(20)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 1000.0, 1e-3)
+    assert not S.info()["lattice_precond"]
+    orc = ocav.CavityOracle(nd, u_bc, v_bc, 1000.0, 1e-3)
+    s0 = orc.initial_state()
+    st = S.new_state(to_dev(s0.u, gpu), to_dev(s0.v, gpu))
+    for _ in range(3):
+        S.step(st, 20)
+        s0 = orc.run(20, s0)
+        for key, ref in (("u", s0.u), ("v", s0.v), ("p", s0.p), ("p_tilde", s0.pt)):
+            assert rel_err(st[key].cpu().numpy(), ref) <= 1e-10, (st["step"], key)
+    S.close()
+
+
 def test_step_error_paths_are_transactional(P, gpu):
     import torch
     _say("error paths")
