@@ -170,10 +170,11 @@ rbf_status rbf_cast_f32(const double *src, float *dst, int64_t n, rbf_stream st)
  * row r of each entry) and slot int32 [k * rows] (its slot s), ordered by
  * increasing (r, s) inside each column.  Every ELL entry appears once,
  * zero weights included, so the structure serves every weight array of the
- * same idx (FP64 or FP32, permuted by rbf_ell_transpose_weights).  bad_entry: host; -1, or the lowest ELL position
- * s * rows + r whose index is outside [0, ncols).
- * Synchronises the stream (two read-backs) and allocates a workspace of
- * ncols ints for the duration of the call.  Limits: k in [1, 64],
+ * same idx (FP64 or FP32, permuted by rbf_ell_transpose_weights).
+ * bad_entry: host; -1, or the lowest ELL position s * rows + r whose index
+ * is outside [0, ncols).  Synchronises the stream twice (the range and
+ * column-length check, and the end of the build) and allocates a workspace
+ * of ncols ints for the duration of the call.  Limits: k in [1, 64],
  * rows * k < 2^31, ncols < 2^31, at most 4096 entries per column.
  * Errors: RBF_E_ARG for violated limits or an index out of range (outputs
  * then undefined); RBF_E_NOMEM / RBF_E_DEVICE from the runtime.
