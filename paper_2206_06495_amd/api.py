@@ -254,6 +254,35 @@ class Solver:
         return {"viscous_jacobi": bool(inf.viscous_jacobi),
                 "lattice_precond": bool(inf.lattice_precond), "jacobi_bound": inf.jacobi_bound}
 
+    def run(self, state, nsteps, every=10, log=None):
+        """Advance `state` by `nsteps` in rbf_step calls of `every` steps and,
+        after each call, append one JSON line to the open file `log` (if given)
+        with the step, the Krylov iterations per step and the last solves'
+        relative residuals (rbf_step_stats) and the state's diagnostics
+        (rbf_solver_diagnostics).  Each call starts its initial-guess history
+        afresh, so the chunk size changes the iterates within the solver
+        tolerance.  Returns the list of records."""
+        import json
+        every = max(1, int(every))
+        records = []
+        done = 0
+        while done < nsteps:
+            k = min(every, nsteps - done)
+            s = self.step(state, k)
+            done += k
+            rec = {"step": int(state["step"]),
+                   "poisson_iters_per_step": s.poisson_iters / k,
+                   "helmholtz_iters_per_step": s.helmholtz_iters / k,
+                   "poisson_rel_residual": s.last_poisson.rel_residual,
+                   "helmholtz_rel_residual": max(s.last_helmholtz_u.rel_residual,
+                                                 s.last_helmholtz_v.rel_residual),
+                   **self.diagnostics(state)}
+            records.append(rec)
+            if log is not None:
+                log.write(json.dumps(rec) + "\n")
+                log.flush()
+        return records
+
     def diagnostics(self, state):
         """Health figures of a state: {"div_max", "div_rms", "kinetic_energy",
         "speed_max", "cfl"} (rbf_solver_diagnostics)."""

@@ -648,6 +648,33 @@ def test_solver_diagnostics(P, gpu):
     S.close()
 
 
+def test_run_writes_jsonl_records(P, gpu):
+    """Solver.run: one JSON line per rbf_step call with the step, Krylov
+    statistics and diagnostics; the state equals the one from plain calls of
+    the same chunk size (bit for bit)."""
+    import io
+    import json
+    import torch
+    _say("run / JSONL log")
+    nd = ri.cavity_nodes(12, 0.3, 0)
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 100.0, 2e-3)
+    u0 = to_dev(np.where(nd.v_tag != 0, u_bc, 0.0), gpu)
+    st = S.new_state(u0, to_dev(v_bc, gpu))
+    ref = S.new_state(u0, to_dev(v_bc, gpu))
+    buf = io.StringIO()
+    recs = S.run(st, 25, every=10, log=buf)
+    lines = [json.loads(x) for x in buf.getvalue().splitlines()]
+    assert lines == recs and [r["step"] for r in recs] == [10, 20, 25]
+    for r in recs:
+        assert r["poisson_rel_residual"] <= 1e-12 and r["cfl"] > 0 and r["speed_max"] >= 1.0
+        assert set(r) >= {"div_max", "div_rms", "kinetic_energy", "poisson_iters_per_step"}
+    for k in (10, 10, 5):
+        S.step(ref, k)
+    for key in ("u", "v", "p", "p_tilde", "cu_prev", "cv_prev"):
+        assert torch.equal(st[key], ref[key]), key
+    S.close()
+
+
 def test_checkpoint_resume_is_bitwise(P, gpu):
     """(u, v, p~, p, C_{j-1}(u), C_{j-1}(v), j) is the whole carried state of
     the scheme (AB2, eq. (14), needs the previous advection terms): saved
