@@ -190,6 +190,99 @@ def hex_cavity_nodes(K):
                    np.stack([nx, ny]), K, h)
 
 
+TAG_CYLINDER = 1
+TAG_INFLOW = 3
+TAG_OUTFLOW = 4
+TAG_SIDE = 5
+
+
+def cylinder_nodes(h_wall=0.02, grading=0.008, h_far=0.5, box=(-10.0, 30.0, -10.0, 10.0)):
+    """Staggered nodes for flow past a cylinder (Sec. 5.2 geometry: diameter
+    1 at the origin, in the channel ``box``), graded from spacing ``h_wall``
+    on the cylinder to at most ``h_far`` with h(r) = min(h_far, h_wall +
+    grading (r - 1/2)): P-nodes on rings of radius r_k (r_0 = 1/2, r_{k+1} =
+    r_k + h(r_k) sqrt(3)/2, round(2 pi r_k / h(r_k)) nodes, every other ring
+    rotated by half a spacing) clipped to the channel, plus channel-edge
+    nodes at the local spacing; the Delaunay triangulation of those vertices
+    without the triangles inside the cylinder gives the edges, and V-nodes
+    are their midpoints.  Deterministic (no random draws).  Tags: 0
+    interior, 1 cylinder, 3 inflow (x = x0), 4 outflow (x = x1), 5 sides
+    (y = y0, y1; corners count as sides).  P normals point out of the fluid.
+    The defaults give 132,691 P- and 397,064 V-nodes."""
+    from scipy.spatial import Delaunay
+    x0, x1, y0, y1 = box
+    hr = lambda r: np.minimum(h_far, h_wall + grading * (r - 0.5))  # noqa: E731
+    rmax = max(np.hypot(x, y) for x in (x0, x1) for y in (y0, y1))
+    px, py, tag = [], [], []
+    r, k = 0.5, 0
+    while r < rmax:
+        h = float(hr(r))
+        n = max(8, int(round(2 * np.pi * r / h)))
+        th = (np.arange(n) + 0.5 * (k % 2)) * (2 * np.pi / n)
+        x, y = r * np.cos(th), r * np.sin(th)
+        if k > 0:  # interior rings: clear of the channel edges by half a spacing
+            keep = (x > x0 + 0.5 * h) & (x < x1 - 0.5 * h) & (y > y0 + 0.5 * h) & (y < y1 - 0.5 * h)
+            x, y = x[keep], y[keep]
+        px.append(x)
+        py.append(y)
+        tag.append(np.full(x.size, TAG_CYLINDER if k == 0 else TAG_INTERIOR, np.int8))
+        r += h * np.sqrt(3.0) / 2.0
+        k += 1
+
+    def edge(a, b, fixed, horizontal, t):
+        # nodes from a to b at the local spacing, endpoints included
+        pts = [a]
+        while True:
+            c = pts[-1]
+            q = (c, fixed) if horizontal else (fixed, c)
+            nxt = c + float(hr(np.hypot(*q)))
+            if nxt >= b - 1e-9:
+                if len(pts) > 1 and b - c < 0.5 * (nxt - c):  # no sliver before the corner
+                    pts.pop()
+                break
+            pts.append(nxt)
+        pts = np.array(pts + [b])
+        # spread the last gap evenly over the edge
+        pts = a + (pts - a) * (b - a) / (pts[-1] - a)
+        if horizontal:
+            return pts, np.full(pts.size, fixed), np.full(pts.size, t, np.int8)
+        return np.full(pts.size, fixed), pts, np.full(pts.size, t, np.int8)
+
+    for a, b, fixed, hor, t in ((x0, x1, y0, True, TAG_SIDE), (x0, x1, y1, True, TAG_SIDE),
+                                (y0, y1, x0, False, TAG_INFLOW), (y0, y1, x1, False, TAG_OUTFLOW)):
+        ex, ey, et = edge(a, b, fixed, hor, t)
+        if not hor:  # corners belong to the sides
+            ex, ey, et = ex[1:-1], ey[1:-1], et[1:-1]
+        px.append(ex)
+        py.append(ey)
+        tag.append(et)
+    px, py = np.concatenate(px), np.concatenate(py)
+    p_tag = np.concatenate(tag)
+    simp = Delaunay(np.stack([px, py], 1)).simplices
+    cx, cy = px[simp].mean(axis=1), py[simp].mean(axis=1)
+    simp = simp[np.hypot(cx, cy) > 0.5]
+    e = np.concatenate([simp[:, [0, 1]], simp[:, [1, 2]], simp[:, [0, 2]]])
+    e = np.unique(np.sort(e, axis=1), axis=0)
+    ea, eb = e[:, 0], e[:, 1]
+    vx = (px[ea] + px[eb]) * 0.5
+    vy = (py[ea] + py[eb]) * 0.5
+    on_cyl = (p_tag[ea] == TAG_CYLINDER) & (p_tag[eb] == TAG_CYLINDER)
+    box_a = (p_tag[ea] != TAG_INTERIOR) & (p_tag[ea] != TAG_CYLINDER)
+    box_b = (p_tag[eb] != TAG_INTERIOR) & (p_tag[eb] != TAG_CYLINDER)
+    vert = box_a & box_b & (px[ea] == px[eb]) & ((px[ea] == x0) | (px[ea] == x1))
+    horiz = box_a & box_b & (py[ea] == py[eb]) & ((py[ea] == y0) | (py[ea] == y1))
+    v_tag = np.where(on_cyl, TAG_CYLINDER,
+                     np.where(vert, np.where(px[ea] == x0, TAG_INFLOW, TAG_OUTFLOW),
+                              np.where(horiz, TAG_SIDE, TAG_INTERIOR))).astype(np.int8)
+    rr = np.hypot(px, py)
+    nx = np.where(p_tag == TAG_CYLINDER, -px / rr, 0.0)
+    ny = np.where(p_tag == TAG_CYLINDER, -py / rr, 0.0)
+    nx = np.where(p_tag == TAG_INFLOW, -1.0, np.where(p_tag == TAG_OUTFLOW, 1.0, nx))
+    ny = np.where(p_tag == TAG_SIDE, np.where(py == y0, -1.0, 1.0), ny)
+    return NodeSet(np.stack([vx, vy]), v_tag, np.stack([px, py]), p_tag,
+                   np.stack([nx, ny]), 0, h_wall)
+
+
 def square_nodes(K, jitter=0.3, seed=0):
     """Operator-bench square: K^2 V-nodes ((i+1/2)h, (j+1/2)h) and K^2
     P-nodes (ih, jh), i, j = 0..K-1, h = 1/K, both jittered; no walls."""

@@ -155,6 +155,38 @@ def test_weights_bench_square_sampled(P, gpu):
         assert np.isfinite(wh).all()
 
 
+def test_stencils_and_weights_graded_cylinder_nodes(P, gpu):
+    """The graded cylinder-in-channel node set of the paper's second workload
+    (spacing 0.02 on the cylinder growing to 0.25 at the channel ends;
+    132,691 P + 397,064 V nodes): kNN and weights for all four pairs on the
+    GPU, checked on 400 sampled rows per pair (the 100 nearest the cylinder,
+    the channel edges and random rows) against the oracle: stencils bit for
+    bit, weights within 1e-12 per row."""
+    _say("graded cylinder nodes: kNN + weights")
+    nd = ri.cylinder_nodes()
+    rng = np.random.default_rng(11)
+    pairs = (("vv", nd.xv, nd.xv, nd.v_tag, OP_DX | OP_DY | OP_LAP),
+             ("pv", nd.xp, nd.xv, nd.p_tag, OP_DX | OP_DY),
+             ("pp", nd.xp, nd.xp, nd.p_tag, OP_DX | OP_DY | OP_LAP),
+             ("vp", nd.xv, nd.xp, nd.v_tag, OP_DX | OP_DY))
+    for name, xq, xs, tag, mask in pairs:
+        dq, ds = to_dev(xq, gpu), to_dev(xs, gpu)
+        idx = P.knn(dq, ds, 28)
+        w = P.assemble_weights(dq, ds, idx, 7, 3, mask)
+        near = np.argsort(np.hypot(xq[0], xq[1]))[:100]
+        edge = np.flatnonzero(tag > 1)
+        rows = np.unique(np.concatenate([near, rng.choice(edge, min(100, edge.size), replace=False),
+                                         rng.choice(xq.shape[1], 200, replace=False)]))
+        ref_idx = oknn.knn_bruteforce(xq[:, rows], xs, 28)
+        assert np.array_equal(idx.cpu().numpy()[:, rows], ref_idx), name
+        ops = [c for c in OPS_ALL if mask & c]
+        ref = ow.stencil_weights(xq[:, rows], xs, ref_idx, 7, 3, ops)
+        wh = w.cpu().numpy()
+        for o in range(len(ops)):
+            assert row_rel_err(wh[o][:, rows], ref[o]) <= 1e-12, (name, o)
+        assert np.isfinite(wh).all(), name
+
+
 def _sum_bound(idx, w, x, u):
     return 2.0 * idx.shape[0] * u * np.sum(np.abs(w * x[idx]), axis=0) + 1e-300
 

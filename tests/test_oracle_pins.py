@@ -39,6 +39,37 @@ def test_cavity_node_layout(K):
     assert np.allclose(n[nd.p_tag != 0], 1.0) and np.all(n[nd.p_tag == 0] == 0)
 
 
+def test_cylinder_node_layout():
+    """Graded cylinder-in-channel nodes (Sec. 5.2 geometry): every P-node in
+    the channel and on or outside the cylinder, the cylinder ring exactly at
+    r = 1/2, nearest-neighbour spacing at least half the local target h(r),
+    V-nodes the midpoints of the triangulation's edges (N/M near 3, as in
+    the paper), boundary tags on both ends of each boundary edge and unit
+    outward normals."""
+    h_wall, g = 0.1, 0.05
+    nd = ri.cylinder_nodes(h_wall=h_wall, grading=g)
+    x, y = nd.xp
+    r = np.hypot(x, y)
+    assert np.all((x >= -10) & (x <= 30) & (np.abs(y) <= 10))
+    assert np.all(r >= 0.5 - 1e-12)
+    cyl = nd.p_tag == ri.nodes.TAG_CYLINDER
+    assert np.allclose(r[cyl], 0.5, rtol=0, atol=1e-14) and cyl.sum() == round(np.pi / h_wall)
+    from scipy.spatial import cKDTree
+    d, _ = cKDTree(nd.xp.T).query(nd.xp.T, 2)
+    h = np.minimum(0.5, h_wall + g * (r - 0.5))
+    assert np.min(d[:, 1] / h) >= 0.45
+    assert 2.7 < nd.n_v / nd.n_p < 3.1
+    bnd = nd.p_tag != 0
+    assert np.allclose(np.hypot(*nd.p_normal[:, bnd]), 1.0)
+    assert np.all(nd.p_normal[:, ~bnd] == 0.0)
+    # outward from the fluid: on the cylinder towards its centre
+    assert np.all(np.sum(nd.p_normal[:, cyl] * nd.xp[:, cyl], axis=0) < 0)
+    assert np.all(nd.p_normal[0, nd.p_tag == ri.nodes.TAG_INFLOW] == -1.0)
+    assert np.all(nd.p_normal[0, nd.p_tag == ri.nodes.TAG_OUTFLOW] == 1.0)
+    vb = nd.v_tag != 0
+    assert vb.sum() == bnd.sum()  # closed boundary loops: as many edges as vertices
+
+
 def test_node_generator_is_seeded_and_splitmix():
     # SplitMix64 reference values for seed 0 (Vigna's published generator):
     # the first outputs of the sequence started at state 0.
