@@ -29,6 +29,9 @@ Workload (one JSON line on stdout):
     (one instance after another) and on `batch_threads` threads (concurrent),
     from the same states; aggregate node-steps/s of both and whether the
     fields agree bit for bit.
+  * hex: the same Re and dt on a near-equilateral triangulation at
+    h = 1/100 (no lattice, so no lattice preconditioner): the cost of the
+    general path.
   * cpu_baseline: the CPU oracle (SciPy sparse LU solves) on a bounded
     sample: the same cavity at h = 1/200.
 """
@@ -72,6 +75,10 @@ def parse():
     ap.add_argument("--spmv-K", type=int, default=1000)
     ap.add_argument("--spmv-reps", type=int, default=1000)
     ap.add_argument("--no-spmv", action="store_true")
+    ap.add_argument("--no-hex", action="store_true",
+                    help="skip the near-equilateral (non-lattice) cavity leg")
+    ap.add_argument("--hex-K", type=int, default=100)
+    ap.add_argument("--hex-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run (FP32 preconditioner transforms)")
@@ -390,6 +397,49 @@ def batch_run(P, args, dev):
             "what": "independent lattice cavities, one stream each, rbf_step_batch"}
 
 
+def hex_run(P, args, dev):
+    """The general-triangulation path: the cavity on a near-equilateral
+    triangulation (hexagonal rows, Delaunay edges; stable where the lattice
+    is not) at the same Re and dt, which has no lattice preconditioner."""
+    import torch
+    import rbf_inputs as ri
+    nd = ri.hex_cavity_nodes(args.hex_K)
+    g = {"xv": dev_tensor(nd.xv, dev), "xp": dev_tensor(nd.xp, dev),
+         "v_tag": dev_tensor(nd.v_tag, dev), "p_tag": dev_tensor(nd.p_tag, dev),
+         "p_normal": dev_tensor(nd.p_normal, dev)}
+    ops = {"k": 28}
+    for name, xq, xs, mask in (("vv", g["xv"], g["xv"], 14), ("pv", g["xp"], g["xv"], 6),
+                               ("pp", g["xp"], g["xp"], 14), ("vp", g["xv"], g["xp"], 6)):
+        idx = P.knn(xq, xs, 28)
+        w = P.assemble_weights(xq, xs, idx, 7, 3, mask)
+        ops["idx_" + name] = idx
+        ops[name + "_dx"] = w[0].contiguous()
+        ops[name + "_dy"] = w[1].contiguous()
+        if mask & 8:
+            ops[name + "_lap"] = w[2].contiguous()
+    u_bc = np.where(nd.v_tag == 2, 1.0, 0.0)
+    S = P.Solver(g, ops, dev_tensor(u_bc, dev), dev_tensor(np.zeros_like(u_bc), dev), args.re,
+                 args.dt, rtol_h=args.rtol_h, rtol_p=args.rtol_p, maxit_h=2000, maxit_p=200000)
+    st = S.new_state(dev_tensor(u_bc, dev), dev_tensor(np.zeros_like(u_bc), dev))
+    S.step(st, 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = S.step(st, args.hex_steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"value": (S.N + S.M) * args.hex_steps / el, "unit": "node-steps/s",
+           "ms_per_step": el / args.hex_steps * 1e3, "steps": args.hex_steps,
+           "poisson_iters_per_step": s.poisson_iters / args.hex_steps,
+           "lattice_precond": S.info()["lattice_precond"], "final_state": S.diagnostics(st),
+           "workload": f"cavity on a near-equilateral triangulation, h = 1/{args.hex_K} "
+                       f"(N={S.N} V + M={S.M} P), Re={args.re:g}, dt={args.dt:g}, "
+                       "unpreconditioned pressure iteration"}
+    S.close()
+    log(f"hex: {out['value']:.3e} node-steps/s, {out['poisson_iters_per_step']:.0f} pressure "
+        "iterations per step")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -480,6 +530,10 @@ def main():
     if args.batch > 0:
         log("concurrent instances:", args.batch)
         out["batch"] = batch_run(P, args, dev)
+        torch.cuda.empty_cache()
+    if not args.no_hex:
+        log("near-equilateral cavity K =", args.hex_K)
+        out["hex"] = hex_run(P, args, dev)
         torch.cuda.empty_cache()
     if not args.no_spmv:
         log("operator bench K =", args.spmv_K)
