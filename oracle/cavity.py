@@ -100,30 +100,47 @@ class CavityOracle:
         sol = self.Lp_lu.solve(np.concatenate([rhs, [0.0]]))
         return sol[:-1], sol[-1]
 
-    def step(self, s, stages=None):
-        """Advance one step; returns the new state.  ``stages`` (a dict), if
-        given, receives the intermediate vectors for stage-level checks."""
-        o = self.ops
-        dt, a = self.dt, self.a
-        # Stage 1: AB2 advection.
-        cu, cv = self.advection(s.u, s.v)
-        cu_prev, cv_prev = (cu, cv) if s.step == 0 else (s.cu_prev, s.cv_prev)
-        us = s.u + dt * (1.5 * cu - 0.5 * cu_prev)
-        vs = s.v + dt * (1.5 * cv - 0.5 * cv_prev)
-        # Stage 2: Crank-Nicolson with Kim-Moin wall values.
+    def predictor(self, q, c, c_prev):
+        """Eq. (14): second-order Adams-Bashforth, q + dt (3/2 c - 1/2 c_prev)."""
+        return q + self.dt * (1.5 * c - 0.5 * c_prev)
+
+    def viscous(self, us, vs, pt_j):
+        """Eq. (16) with the Kim-Moin wall values of eq. (21): (I - a D_Lap)
+        u** = (I + a D_Lap) u* on interior rows, u** = u_bc + dt D_x^VP p~_j
+        (v: D_y^VP) on wall rows.  Returns (u**, v**, ru, rv)."""
+        o, dt, a = self.ops, self.dt, self.a
         ru = us + a * (o.L_vv @ us)
         rv = vs + a * (o.L_vv @ vs)
-        ru = np.where(self.vwall, self.u_bc + dt * (o.Dx_vp @ s.pt), ru)
-        rv = np.where(self.vwall, self.v_bc + dt * (o.Dy_vp @ s.pt), rv)
-        uss = self.H_lu.solve(ru)
-        vss = self.H_lu.solve(rv)
-        # Stage 3: divergence, pressure Poisson, pressure and correction.
+        ru = np.where(self.vwall, self.u_bc + dt * (o.Dx_vp @ pt_j), ru)
+        rv = np.where(self.vwall, self.v_bc + dt * (o.Dy_vp @ pt_j), rv)
+        return self.H_lu.solve(ru), self.H_lu.solve(rv), ru, rv
+
+    def pressure_update(self, pt):
+        """Eq. (19): p = p~ - a D_Lap^PP p~."""
+        return pt - self.a * (self.ops.L_pp @ pt)
+
+    def projection(self, uss, vss):
+        """Eqs. (17), (18), (20): F = D^PV [u**, v**], the bordered Poisson
+        solve for p~, and u = u** - dt D^VP p~.  Returns (u, v, p~, F, rhs, lam)."""
+        o, dt = self.ops, self.dt
         F = o.Dx_pv @ uss + o.Dy_pv @ vss
         prhs = self.pressure_rhs(F)
         pt, lam = self.solve_pressure(prhs)
-        p = pt - a * (o.L_pp @ pt)
-        un = uss - dt * (o.Dx_vp @ pt)
-        vn = vss - dt * (o.Dy_vp @ pt)
+        return uss - dt * (o.Dx_vp @ pt), vss - dt * (o.Dy_vp @ pt), pt, F, prhs, lam
+
+    def step(self, s, stages=None):
+        """Advance one step; returns the new state.  ``stages`` (a dict), if
+        given, receives the intermediate vectors for stage-level checks."""
+        # Stage 1: AB2 advection.
+        cu, cv = self.advection(s.u, s.v)
+        cu_prev, cv_prev = (cu, cv) if s.step == 0 else (s.cu_prev, s.cv_prev)
+        us = self.predictor(s.u, cu, cu_prev)
+        vs = self.predictor(s.v, cv, cv_prev)
+        # Stage 2: Crank-Nicolson with Kim-Moin wall values.
+        uss, vss, ru, rv = self.viscous(us, vs, s.pt)
+        # Stage 3: divergence, pressure Poisson, pressure and correction.
+        un, vn, pt, F, prhs, lam = self.projection(uss, vss)
+        p = self.pressure_update(pt)
         if stages is not None:
             stages.update(cu=cu, cv=cv, us=us, vs=vs, ru=ru, rv=rv, uss=uss, vss=vss,
                           F=F, prhs=prhs, lam=lam)

@@ -277,9 +277,9 @@ def test_convergence_order_under_refinement():
 
 
 def test_paper_error_band_at_sqrt2():
-    """Sec. 4 / Sec. 6: at k~ dr = sqrt(2) the modified wavenumber deviates from
-    the spectral limit by at most 1.5% (the paper's grids differ; this is a
-    sanity band, the paper's E(n,m,q) curves exist only in figures)."""
+    """Sec. 4 / Sec. 6: bound of 0.015 on the relative modified-wavenumber
+    error at k~ dr = sqrt(2) over all wave angles (the paper's grids differ;
+    a sanity band only, the paper's E(n,m,q) curves exist only in figures)."""
     band = GOLD["mw_error_max_all"]["value"]
     nd = ri.cavity_nodes(40, 0.3, 0)
     for xq, xs in ((nd.xv, nd.xv), (nd.xp, nd.xp)):
