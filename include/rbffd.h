@@ -75,7 +75,18 @@ int32_t rbf_abi_version(void);
  * midpoints of all triangle edges (cell diagonals alternate in a checkerboard);
  * N = 3K^2 + 2K, M = (K+1)^2.  kind 1: operator-bench square, N = M = K^2,
  * V on jittered cell centres ((i+1/2)/K, (j+1/2)/K), P on jittered vertices
- * (i/K, j/K), i, j = 0..K-1, no walls.  Random numbers: SplitMix64 as a
+ * (i/K, j/K), i, j = 0..K-1, no walls.  kind 2: lid-driven cavity on a
+ * near-equilateral triangulation (the kind of grid DistMesh produces): P rows
+ * y_j = j/R, j = 0..R, R = floor(2K/sqrt(3) + 1/2); walls at rows 0 and R
+ * (x = i/K) and at the ends of every row; even interior rows x = i/K,
+ * i = 1..K-1, odd ones x = (i+1/2)/K, i = 0..K-1; interior vertices at least
+ * 1.5/K from every wall (unjittered position) jittered by
+ * U(-jitter/K, jitter/K) per coordinate; edges: each row's horizontal edges
+ * and, between consecutive rows, the strip triangulation that merges the two
+ * rows in order of unjittered x (ties advance the lower row); V-nodes on the
+ * edge midpoints, ordered by row (horizontal edges, then that row's strip
+ * edges in merge order); N/M about 3; jitter <= 0.4.
+ * Random numbers: SplitMix64 as a
  * counter-based generator (draw c of stream g uses counter (g << 40) | c;
  * stream 0 = V, 1 = P; draws 2n and 2n+1 jitter node n).
  *
@@ -84,8 +95,9 @@ int32_t rbf_abi_version(void);
  *   xv [2][n_v], v_tag [n_v] (0 interior, 1 wall, 2 lid = top wall),
  *   xp [2][n_p], p_tag [n_p] (0 interior, 1 wall),
  *   p_normal [2][n_p] (outward unit normal of wall P-nodes, 0 elsewhere).
- * Errors: RBF_E_ARG for an unknown kind, K < 2 (cavity) or K < 1 (square),
- * jitter outside [0, 0.45], or a partial set of NULL arrays.
+ * Errors: RBF_E_ARG for an unknown kind, K < 2 (cavities) or K < 1 (square),
+ * jitter outside [0, 0.45] (kind 2: [0, 0.4]), or a partial set of NULL
+ * arrays.
  */
 rbf_status rbf_build_nodes(int32_t kind, int32_t K, double jitter, uint64_t seed,
                            int64_t *n_v, double *xv, int8_t *v_tag,
@@ -101,9 +113,13 @@ rbf_status rbf_build_nodes(int32_t kind, int32_t K, double jitter, uint64_t seed
  * d^2 = dx*dx + dy*dy in FP64 with separately rounded products (no fused
  * multiply-add), so ties are broken by the lower index and the result is a
  * unique function of the inputs.  When alpha = beta and nodes are distinct,
- * slot 0 is the node itself.  Synchronises the stream once (bounding box).
- * Errors: RBF_E_ARG if k < 1, k > 64, k > ns, nq < 0, ns < 1 or a NULL
- * pointer with a non-zero size.
+ * slot 0 is the node itself.  Synchronises the stream twice (bounding box,
+ * end of the search).  Device scratch (cell grid, about 34 bytes per source)
+ * is allocated and freed inside the call.
+ * Errors: RBF_E_ARG if k < 1, k > 64, k > ns, nq < 0, ns < 1, a NULL
+ * pointer with a non-zero size, or a NaN or infinite coordinate in either
+ * node set (checked before any search, so no stencil is written);
+ * RBF_E_NOMEM / RBF_E_DEVICE for allocation or device failures.
  */
 rbf_status rbf_knn(const double *xq, int64_t nq, const double *xs, int64_t ns, int32_t k,
                    int32_t *idx, rbf_stream st);
@@ -132,7 +148,9 @@ rbf_status rbf_knn(const double *xq, int64_t nq, const double *xs, int64_t ns, i
  * m odd in [1, 11] (m >= 3 for derivative operators), and
  * k >= (q+1)(q+2) (stability rule of Sec. 4) unless op_mask has bit 31 set.
  * Errors: RBF_E_ARG for violated limits or an empty op_mask;
- * RBF_E_SINGULAR if any row failed (weights of that row are then NaN).
+ * RBF_E_SINGULAR if any row failed: a numerically singular or non-finite
+ * system, or a stencil index outside [0, ns) (tested before any load
+ * through it); the weights of such a row are NaN.
  */
 #define RBF_FORCE_SMALL_STENCIL 0x80000000u
 rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const double *xs, int64_t ns,

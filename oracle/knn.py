@@ -30,9 +30,14 @@ def knn_bruteforce(xq, xs, k, chunk=256):
     for a in range(0, nq, chunk):
         b = min(nq, a + chunk)
         d2 = _d2(xq[0, a:b, None], xq[1, a:b, None], xs[0][None, :], xs[1][None, :])
-        # A stable sort of an index-ordered row sorts by (d2, index).
-        order = np.argsort(d2, axis=1, kind="stable")[:, :k]
-        out[:, a:b] = order.T
+        # Every node whose d2 is at most the k-th smallest d2 of its row is a
+        # candidate (ties at the k-th distance included); the candidates are
+        # ordered by (d2, index) and the first k kept.
+        kth = np.partition(d2, k - 1, axis=1)[:, k - 1]
+        for r in range(b - a):
+            cand = np.nonzero(d2[r] <= kth[r])[0]
+            order = np.lexsort((cand, d2[r, cand]))
+            out[:, a + r] = cand[order[:k]]
     return out
 
 

@@ -12,7 +12,9 @@
 // registers (fully unrolled insertion, static indices) and stops once the
 // k-th best squared distance is strictly below the squared distance to every
 // cell not yet visited.
+#include <algorithm>
 #include <climits>
+#include <cmath>
 
 #include "common.h"
 
@@ -33,9 +35,12 @@ __device__ __forceinline__ int cell_coord(double v, double v0, double inv_c, int
     return c;
 }
 
+// Per-block bounding box of n points plus a non-finite flag: part[5 b + 0..3]
+// = min x, max x, min y, max y over the finite points, part[5 b + 4] = 1 if
+// any coordinate is NaN or infinite (fmin/fmax alone would skip a NaN).
 __global__ void k_bbox_partial(const double *__restrict__ x, int64_t n, double *__restrict__ part) {
-    __shared__ double lds[4 * 16];
-    double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    __shared__ double lds[5 * 16];
+    double v[5] = {INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double px = x[i], py = x[n + i];
@@ -43,16 +48,18 @@ __global__ void k_bbox_partial(const double *__restrict__ x, int64_t n, double *
         v[1] = fmax(v[1], px);
         v[2] = fmin(v[2], py);
         v[3] = fmax(v[3], py);
+        if (!isfinite(px) || !isfinite(py)) v[4] = 1.0;
     }
     for (int off = 32; off >= 1; off >>= 1) {
         v[0] = fmin(v[0], __shfl_xor(v[0], off, 64));
         v[1] = fmax(v[1], __shfl_xor(v[1], off, 64));
         v[2] = fmin(v[2], __shfl_xor(v[2], off, 64));
         v[3] = fmax(v[3], __shfl_xor(v[3], off, 64));
+        v[4] = fmax(v[4], __shfl_xor(v[4], off, 64));
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (lane == 0)
-        for (int q = 0; q < 4; ++q) lds[q * 16 + wid] = v[q];
+        for (int q = 0; q < 5; ++q) lds[q * 16 + wid] = v[q];
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < nw; ++w) {
@@ -60,9 +67,16 @@ __global__ void k_bbox_partial(const double *__restrict__ x, int64_t n, double *
             v[1] = fmax(v[1], lds[16 + w]);
             v[2] = fmin(v[2], lds[32 + w]);
             v[3] = fmax(v[3], lds[48 + w]);
+            v[4] = fmax(v[4], lds[64 + w]);
         }
-        for (int q = 0; q < 4; ++q) part[blockIdx.x * 4 + q] = v[q];
+        for (int q = 0; q < 5; ++q) part[blockIdx.x * 5 + q] = v[q];
     }
+}
+
+__global__ void k_zero_i32(int *__restrict__ a, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0;
 }
 
 __global__ void k_cell_count(const double *__restrict__ x, int64_t n, Grid g,
@@ -192,100 +206,136 @@ __global__ void __launch_bounds__(128) k_query(const double *__restrict__ xq, in
         if (s < k) idx[(int64_t)s * nq + q] = bi[s];
 }
 
-}  // namespace
+// Device buffers of one kNN call besides its inputs and output.
+struct KnnScratch {
+    double *part;  // [2][kBboxBlocks][5] bounding-box partials (sources, queries)
+    int *cell, *count, *start, *fill, *sid;
+    double *sx, *sy;
+};
 
-extern "C" rbf_status rbf_knn(const double *xq, int64_t nq, const double *xs, int64_t ns,
-                              int32_t k, int32_t *idx, rbf_stream st_) {
-    rbf::clear_error();
+constexpr int kBboxBlocks = 256;
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of the cell-grid buffers for ns sources and ncell cells.
+size_t grid_bytes(int64_t ns, int64_t ncell) {
+    return 2 * align256(ns * sizeof(int)) + 2 * align256(ns * sizeof(double)) +
+           2 * align256(ncell * sizeof(int)) + align256((ncell + 1) * sizeof(int));
+}
+
+// Lays the cell-grid buffers out in [base, base + grid_bytes).
+void carve_grid(char *base, int64_t ns, int64_t ncell, KnnScratch &s) {
+    auto take = [&](size_t b) { char *p = base; base += align256(b); return p; };
+    s.cell = (int *)take(ns * sizeof(int));
+    s.sid = (int *)take(ns * sizeof(int));
+    s.sx = (double *)take(ns * sizeof(double));
+    s.sy = (double *)take(ns * sizeof(double));
+    s.count = (int *)take(ncell * sizeof(int));
+    s.fill = (int *)take(ncell * sizeof(int));
+    s.start = (int *)take((ncell + 1) * sizeof(int));
+}
+
+rbf_status knn_check_args(const double *xq, int64_t nq, const double *xs, int64_t ns, int32_t k,
+                          int32_t *idx) {
     RBF_ARG(k >= 1 && k <= 64, "rbf_knn: k must be in [1, 64] (got %d)", k);
     RBF_ARG(ns >= 1 && k <= ns, "rbf_knn: need 1 <= k <= ns (k=%d, ns=%lld)", k, (long long)ns);
     RBF_ARG(nq >= 0 && nq < INT_MAX && ns < INT_MAX, "rbf_knn: sizes out of range");
     RBF_ARG(xs && (nq == 0 || (xq && idx)), "rbf_knn: NULL pointer");
-    if (nq == 0) return RBF_OK;
-    hipStream_t st = rbf::as_stream(st_);
+    return RBF_OK;
+}
 
-    // Bounding box of the sources.
-    const int nbb = 256;
-    double *part = nullptr, *hbb = nullptr;
-    RBF_HIP(hipMalloc(&part, nbb * 4 * sizeof(double)));
-    hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(1024), 0, st, xs, ns, part);
+// Bounding box of the sources and finiteness of both node sets (one stream
+// synchronisation); fills the cell grid g and its cell count.
+rbf_status knn_grid(const double *xq, int64_t nq, const double *xs, int64_t ns, double *part,
+                    hipStream_t st, Grid &g, int64_t &ncell) {
+    hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks), dim3(1024), 0, st, xs, ns, part);
     RBF_CHECK_LAUNCH();
-    double hpart[nbb * 4];
+    hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks), dim3(1024), 0, st, xq, nq,
+                       part + 5 * kBboxBlocks);
+    RBF_CHECK_LAUNCH();
+    double hpart[2 * kBboxBlocks * 5];
     RBF_HIP(hipMemcpyAsync(hpart, part, sizeof(hpart), hipMemcpyDeviceToHost, st));
     RBF_HIP(hipStreamSynchronize(st));
-    RBF_HIP(hipFree(part));
-    (void)hbb;
     double bb[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
-    for (int b = 0; b < nbb; ++b) {
-        bb[0] = fmin(bb[0], hpart[4 * b]);
-        bb[1] = fmax(bb[1], hpart[4 * b + 1]);
-        bb[2] = fmin(bb[2], hpart[4 * b + 2]);
-        bb[3] = fmax(bb[3], hpart[4 * b + 3]);
+    bool bad_src = false, bad_query = false;
+    for (int b = 0; b < kBboxBlocks; ++b) {
+        bb[0] = fmin(bb[0], hpart[5 * b]);
+        bb[1] = fmax(bb[1], hpart[5 * b + 1]);
+        bb[2] = fmin(bb[2], hpart[5 * b + 2]);
+        bb[3] = fmax(bb[3], hpart[5 * b + 3]);
+        bad_src = bad_src || hpart[5 * b + 4] != 0.0;
+        bad_query = bad_query || hpart[5 * (kBboxBlocks + b) + 4] != 0.0;
     }
-    RBF_ARG(std::isfinite(bb[0]) && std::isfinite(bb[1]) && std::isfinite(bb[2]) &&
+    RBF_ARG(!bad_src && std::isfinite(bb[0]) && std::isfinite(bb[1]) && std::isfinite(bb[2]) &&
                 std::isfinite(bb[3]),
             "rbf_knn: non-finite source coordinates");
+    RBF_ARG(!bad_query, "rbf_knn: non-finite query coordinates");
     const double ex = bb[1] - bb[0], ey = bb[3] - bb[2];
     double c = sqrt(fmax(ex * ey, 0.0) * 2.0 / (double)ns);
     c = fmax(c, fmax(ex, ey) / 4096.0);
     if (!(c > 0.0)) c = 1.0;
-    Grid g;
     g.x0 = bb[0];
     g.y0 = bb[2];
     g.c = c;
     g.inv_c = 1.0 / c;
     g.gx = (int)(ex * g.inv_c) + 1;
     g.gy = (int)(ey * g.inv_c) + 1;
-    const int64_t ncell = (int64_t)g.gx * g.gy;
+    ncell = (int64_t)g.gx * g.gy;
+    return RBF_OK;
+}
 
-    int *cell = nullptr, *count = nullptr, *start = nullptr, *fill = nullptr, *sid = nullptr;
-    double *sx = nullptr, *sy = nullptr;
-    rbf_status rc = RBF_OK;
-    auto cleanup = [&]() {
-        hipFree(cell);
-        hipFree(count);
-        hipFree(start);
-        hipFree(fill);
-        hipFree(sid);
-        hipFree(sx);
-        hipFree(sy);
-    };
-    do {
-        if (hipMalloc(&cell, ns * sizeof(int)) != hipSuccess ||
-            hipMalloc(&count, ncell * sizeof(int)) != hipSuccess ||
-            hipMalloc(&start, (ncell + 1) * sizeof(int)) != hipSuccess ||
-            hipMalloc(&fill, ncell * sizeof(int)) != hipSuccess ||
-            hipMalloc(&sid, ns * sizeof(int)) != hipSuccess ||
-            hipMalloc(&sx, ns * sizeof(double)) != hipSuccess ||
-            hipMalloc(&sy, ns * sizeof(double)) != hipSuccess) {
+// Counting sort of the sources by cell, then the queries; synchronises.
+rbf_status knn_search(const double *xq, int64_t nq, const double *xs, int64_t ns, int32_t k,
+                      int32_t *idx, hipStream_t st, const Grid &g, int64_t ncell,
+                      const KnnScratch &s) {
+    const uint32_t zb = (uint32_t)std::min<int64_t>(rbf::blocks_for(ncell, 256), 1024);
+    hipLaunchKernelGGL(k_zero_i32, dim3(zb), dim3(256), 0, st, s.count, ncell);
+    hipLaunchKernelGGL(k_zero_i32, dim3(zb), dim3(256), 0, st, s.fill, ncell);
+    hipLaunchKernelGGL(k_cell_count, dim3(rbf::blocks_for(ns, 256)), dim3(256), 0, st, xs, ns, g,
+                       s.cell, s.count);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, s.count, ncell, s.start);
+    hipLaunchKernelGGL(k_scatter, dim3(rbf::blocks_for(ns, 256)), dim3(256), 0, st, xs, ns,
+                       s.cell, s.start, s.fill, s.sx, s.sy, s.sid);
+    if (k <= 32)
+        hipLaunchKernelGGL(k_query<32>, dim3(rbf::blocks_for(nq, 128)), dim3(128), 0, st, xq, nq,
+                           k, g, s.start, s.sx, s.sy, s.sid, idx);
+    else
+        hipLaunchKernelGGL(k_query<64>, dim3(rbf::blocks_for(nq, 128)), dim3(128), 0, st, xq, nq,
+                           k, g, s.start, s.sx, s.sy, s.sid, idx);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        rbf::set_error("rbf_knn: %s", hipGetErrorString(e));
+        return RBF_E_DEVICE;
+    }
+    return RBF_OK;
+}
+
+}  // namespace
+
+extern "C" rbf_status rbf_knn(const double *xq, int64_t nq, const double *xs, int64_t ns,
+                              int32_t k, int32_t *idx, rbf_stream st_) {
+    rbf::clear_error();
+    rbf_status rc = knn_check_args(xq, nq, xs, ns, k, idx);
+    if (rc != RBF_OK || nq == 0) return rc;
+    hipStream_t st = rbf::as_stream(st_);
+    KnnScratch s{};
+    RBF_HIP(hipMalloc(&s.part, 2 * kBboxBlocks * 5 * sizeof(double)));
+    Grid g;
+    int64_t ncell = 0;
+    rc = knn_grid(xq, nq, xs, ns, s.part, st, g, ncell);
+    char *base = nullptr;
+    if (rc == RBF_OK) {
+        if (hipMalloc(&base, grid_bytes(ns, ncell)) != hipSuccess) {
             rbf::set_error("rbf_knn: device allocation failed");
             rc = RBF_E_NOMEM;
-            break;
+        } else {
+            carve_grid(base, ns, ncell, s);
+            rc = knn_search(xq, nq, xs, ns, k, idx, st, g, ncell, s);
         }
-        if (hipMemsetAsync(count, 0, ncell * sizeof(int), st) != hipSuccess ||
-            hipMemsetAsync(fill, 0, ncell * sizeof(int), st) != hipSuccess) {
-            rbf::set_error("rbf_knn: memset failed");
-            rc = RBF_E_DEVICE;
-            break;
-        }
-        hipLaunchKernelGGL(k_cell_count, dim3(rbf::blocks_for(ns, 256)), dim3(256), 0, st, xs, ns,
-                           g, cell, count);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, count, ncell, start);
-        hipLaunchKernelGGL(k_scatter, dim3(rbf::blocks_for(ns, 256)), dim3(256), 0, st, xs, ns,
-                           cell, start, fill, sx, sy, sid);
-        if (k <= 32)
-            hipLaunchKernelGGL(k_query<32>, dim3(rbf::blocks_for(nq, 128)), dim3(128), 0, st, xq,
-                               nq, k, g, start, sx, sy, sid, idx);
-        else
-            hipLaunchKernelGGL(k_query<64>, dim3(rbf::blocks_for(nq, 128)), dim3(128), 0, st, xq,
-                               nq, k, g, start, sx, sy, sid, idx);
-        hipError_t e = hipGetLastError();
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) {
-            rbf::set_error("rbf_knn: %s", hipGetErrorString(e));
-            rc = RBF_E_DEVICE;
-        }
-    } while (0);
-    cleanup();
+    }
+    hipFree(base);
+    hipFree(s.part);
     return rc;
 }
+

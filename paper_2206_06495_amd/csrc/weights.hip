@@ -131,9 +131,16 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
     const int s = n + kp;
 
     // 1. Stencil in shifted coordinates; exact power-of-two scaling.
+    // A stencil index outside [0, ns) marks the row bad before any load
+    // through it (the lane then reads source 0 instead).
     double dx = 0.0, dy = 0.0, d2 = 0.0;
+    bool bad_index = false;
     if (lane < n) {
-        const int j = idx[(int64_t)lane * nq + row];
+        int j = idx[(int64_t)lane * nq + row];
+        if (j < 0 || (int64_t)j >= ns) {
+            bad_index = true;
+            j = 0;
+        }
         dx = xs[j] - xq[row];
         dy = xs[ns + j] - xq[nq + row];
         d2 = dx * dx + dy * dy;
@@ -144,7 +151,7 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
     int E = 0;
     frexp(d2max, &E);
     const int e = (E >= 0) ? (E + 1) / 2 : -((-E) / 2);
-    bool bad_row = !(d2max > 0.0) || !isfinite(d2max);
+    bool bad_row = !(d2max > 0.0) || !isfinite(d2max) || bad_index;
     const double xt = ldexp(dx, -e), yt = ldexp(dy, -e);
     sx[lane] = xt;
     sy[lane] = yt;
@@ -373,7 +380,7 @@ extern "C" rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const d
     }
     if (hb != ~0ull) {
         *bad_row = (int64_t)hb;
-        rbf::set_error("rbf_assemble_weights: singular or non-finite system at row %lld",
+        rbf::set_error("rbf_assemble_weights: singular or non-finite system, or stencil index outside [0, ns), at row %lld",
                        (long long)hb);
         rc = RBF_E_SINGULAR;
     }

@@ -64,6 +64,62 @@ def test_knn_degenerate_inputs(P, gpu):
         P.knn(to_dev(xq, gpu), to_dev(xs, gpu), 4)  # k > ns
 
 
+def test_knn_rejects_non_finite_coordinates(P, gpu):
+    """A NaN or infinite coordinate in the queries or the sources is refused
+    with RBF_E_ARG by the host-side check, before any search runs, and the
+    output stencils are left untouched."""
+    import ctypes
+    import torch
+    from paper_2206_06495_amd import _lib
+    _say("knn non-finite")
+    nd = ri.cavity_nodes(6, 0.3, 0)
+    for which, bad in (("query", np.nan), ("query", np.inf), ("source", np.nan),
+                       ("source", -np.inf)):
+        xq, xs = nd.xp.copy(), nd.xv.copy()
+        (xq if which == "query" else xs)[1, 3] = bad
+        dq, ds = to_dev(xq, gpu), to_dev(xs, gpu)
+        idx = torch.full((28, xq.shape[1]), -5, dtype=torch.int32, device=gpu)
+        rc = _lib.lib.rbf_knn(ctypes.c_void_p(dq.data_ptr()), xq.shape[1],
+                              ctypes.c_void_p(ds.data_ptr()), xs.shape[1], 28,
+                              ctypes.c_void_p(idx.data_ptr()), None)
+        torch.cuda.synchronize()
+        assert rc == _lib.RBF_E_ARG, (which, bad, rc)
+        assert "non-finite " + which in _lib.lib.rbf_last_error().decode()
+        assert bool((idx == -5).all())
+
+
+def test_weights_out_of_range_index_reported(P, gpu):
+    """A stencil index outside [0, ns) marks its row bad (RBF_E_SINGULAR,
+    lowest such row in bad_row, NaN weights) without a load through it;
+    other rows keep their weights."""
+    import ctypes
+    import torch
+    from paper_2206_06495_amd import _lib
+    _say("weights index range")
+    nd = ri.cavity_nodes(6, 0.3, 0)
+    d = to_dev(nd.xv, gpu)
+    n = nd.n_v
+    idx = P.knn(d, d, 28)
+    good = P.assemble_weights(d, d, idx, 7, 3, 2).cpu().numpy()
+    idx[7, 11] = n            # one past the end
+    idx[2, 40] = -1           # negative
+    idx[0, 90] = 2 ** 31 - 1  # far out
+    w = torch.empty((1, 28, n), dtype=torch.float64, device=gpu)
+    bad = ctypes.c_int64(-7)
+    rc = _lib.lib.rbf_assemble_weights(ctypes.c_void_p(d.data_ptr()), n,
+                                       ctypes.c_void_p(d.data_ptr()), n,
+                                       ctypes.c_void_p(idx.data_ptr()), 28, 7, 3, 2,
+                                       ctypes.c_void_p(w.data_ptr()), ctypes.byref(bad), None)
+    torch.cuda.synchronize()
+    assert rc == _lib.RBF_E_SINGULAR
+    assert bad.value == 11
+    wh = w.cpu().numpy()[0]
+    for r in (11, 40, 90):
+        assert np.isnan(wh[:, r]).all()
+    keep = np.setdiff1d(np.arange(n), [11, 40, 90])
+    assert np.array_equal(wh[:, keep], good[0][:, keep])
+
+
 @pytest.mark.parametrize("K,seed", [(40, 0), (9, 1)])
 def test_weights_cavity_parity(P, gpu, K, seed):
     _say("weights cavity", K, seed)
