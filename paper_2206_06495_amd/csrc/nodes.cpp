@@ -1,7 +1,7 @@
 // rbf_build_nodes: seeded staggered node sets (host code).
 //
 // Stand-in for the DistMesh grids of Sec. 3: P-nodes on the vertices of a
-// triangulation, V-nodes on the edge midpoints.  Randomness is SplitMix64
+// triangulation, V-nodes on the edge midpoints (kinds 0 and 2).  Randomness is SplitMix64
 // (Steele, Lea & Flood 2014) used as a counter-based generator.  Every
 // floating-point expression is evaluated with one rounding per operation
 // (this file is compiled with -ffp-contract=off), so the coordinates are a
@@ -115,6 +115,104 @@ void square(int K, double jit, uint64_t seed, double *xv, int8_t *vtag, double *
     }
 }
 
+// Near-equilateral cavity (kind 2).  Row j of the P-grid (j = 0..R,
+// y_j = j/R) holds n_j nodes; hex_key(j, i) is node i's unjittered x.
+int hex_rows(int K) { return (int)std::floor(2.0 * (double)K / std::sqrt(3.0) + 0.5); }
+
+int hex_row_len(int K, int R, int j) {
+    if (j == 0 || j == R || j % 2 == 0) return K + 1;
+    return K + 2;
+}
+
+double hex_key(int K, int R, int j, int i) {
+    const double h = 1.0 / K;
+    const int n = hex_row_len(K, R, j);
+    if (i == 0) return 0.0;
+    if (i == n - 1) return 1.0;
+    if (j == 0 || j == R || j % 2 == 0) return (double)i * h;
+    return ((double)(i - 1) + 0.5) * h;
+}
+
+void hex_counts(int K, int64_t &N, int64_t &M) {
+    const int R = hex_rows(K);
+    N = 0;
+    M = 0;
+    for (int j = 0; j <= R; ++j) {
+        const int64_t n = hex_row_len(K, R, j);
+        M += n;
+        N += n - 1;  // horizontal edges of the row
+        if (j < R) N += n + hex_row_len(K, R, j + 1) - 1;  // strip edges
+    }
+}
+
+void hex_cavity(int K, double jit, uint64_t seed, double *xv, int8_t *vtag, double *xp,
+                int8_t *ptag, double *pn, int64_t N, int64_t M) {
+    const double h = 1.0 / K;
+    const double amp = jit * h;
+    const int R = hex_rows(K);
+    int64_t v = 0;
+    for (int j = 0; j <= R; ++j) {
+        const int n = hex_row_len(K, R, j);
+        const double y = (j == R) ? 1.0 : (double)j / (double)R;
+        for (int i = 0; i < n; ++i, ++v) {
+            const double x = hex_key(K, R, j, i);
+            const bool wall = j == 0 || j == R || i == 0 || i == n - 1;
+            const double dw = std::fmin(std::fmin(x, y), std::fmin(1.0 - x, 1.0 - y));
+            double px = x, py = y;
+            if (!wall && dw >= 1.5 * h) {
+                double ox, oy;
+                jitter(seed, kStreamP, (uint64_t)v, amp, ox, oy);
+                px = px + ox;
+                py = py + oy;
+            }
+            xp[v] = px;
+            xp[M + v] = py;
+            ptag[v] = wall ? 1 : 0;
+            double nx = 0.0, ny = 0.0;
+            if (wall) {
+                nx = (px == 0.0) ? -1.0 : (px == 1.0 ? 1.0 : 0.0);
+                ny = (py == 0.0) ? -1.0 : (py == 1.0 ? 1.0 : 0.0);
+                if (nx != 0.0 && ny != 0.0) {
+                    nx = nx * kSqrtHalf;
+                    ny = ny * kSqrtHalf;
+                }
+            }
+            pn[v] = nx;
+            pn[M + v] = ny;
+        }
+    }
+    int64_t e = 0;
+    auto emit = [&](int64_t a, int64_t b) {
+        const double ax = xp[a], ay = xp[M + a], bx = xp[b], by = xp[M + b];
+        const double vx = (ax + bx) * 0.5, vy = (ay + by) * 0.5;
+        xv[e] = vx;
+        xv[N + e] = vy;
+        const bool both = ptag[a] != 0 && ptag[b] != 0;
+        const bool wall = both && ((ax == bx && (ax == 0.0 || ax == 1.0)) ||
+                                   (ay == by && (ay == 0.0 || ay == 1.0)));
+        vtag[e] = wall ? (vy == 1.0 ? 2 : 1) : 0;
+        ++e;
+    };
+    int64_t a0 = 0;
+    for (int j = 0; j <= R; ++j) {
+        const int na = hex_row_len(K, R, j);
+        for (int i = 0; i + 1 < na; ++i) emit(a0 + i, a0 + i + 1);
+        if (j == R) break;
+        const int nb = hex_row_len(K, R, j + 1);
+        const int64_t b0 = a0 + na;
+        int ia = 0, ib = 0;
+        emit(a0, b0);
+        while (ia < na - 1 || ib < nb - 1) {
+            if (ia == na - 1) ++ib;
+            else if (ib == nb - 1) ++ia;
+            else if (hex_key(K, R, j, ia + 1) <= hex_key(K, R, j + 1, ib + 1)) ++ia;
+            else ++ib;
+            emit(a0 + ia, b0 + ib);
+        }
+        a0 = b0;
+    }
+}
+
 }  // namespace
 
 extern "C" rbf_status rbf_build_nodes(int32_t kind, int32_t K, double jitter_frac, uint64_t seed,
@@ -131,6 +229,10 @@ extern "C" rbf_status rbf_build_nodes(int32_t kind, int32_t K, double jitter_fra
     } else if (kind == 1) {
         RBF_ARG(K >= 1 && K <= 30000, "rbf_build_nodes: square needs 1 <= K <= 30000");
         N = M = (int64_t)K * K;
+    } else if (kind == 2) {
+        RBF_ARG(K >= 2 && K <= 20000, "rbf_build_nodes: near-equilateral cavity needs 2 <= K <= 20000");
+        RBF_ARG(jitter_frac <= 0.4, "rbf_build_nodes: kind 2 needs jitter <= 0.4 (rows stay apart)");
+        hex_counts(K, N, M);
     } else {
         RBF_ARG(false, "rbf_build_nodes: unknown kind %d", kind);
     }
@@ -141,6 +243,7 @@ extern "C" rbf_status rbf_build_nodes(int32_t kind, int32_t K, double jitter_fra
     RBF_ARG(none || all, "rbf_build_nodes: pass all arrays or none");
     if (none) return RBF_OK;
     if (kind == 0) cavity(K, jitter_frac, seed, xv, v_tag, xp, p_tag, p_normal, N, M);
-    else square(K, jitter_frac, seed, xv, v_tag, xp, p_tag, p_normal, N);
+    else if (kind == 1) square(K, jitter_frac, seed, xv, v_tag, xp, p_tag, p_normal, N);
+    else hex_cavity(K, jitter_frac, seed, xv, v_tag, xp, p_tag, p_normal, N, M);
     return RBF_OK;
 }

@@ -140,40 +140,89 @@ def cavity_nodes(K, jitter=0.3, seed=0):
                    np.stack([nx, ny]), K, h)
 
 
-def hex_cavity_nodes(K):
+def hex_rows(K):
+    """Row count R = floor(2K/sqrt(3) + 1/2) of the near-equilateral cavity:
+    rows y_j = j/R are about sqrt(3)/2 h apart, h = 1/K."""
+    return int(np.floor(2.0 * K / np.sqrt(3.0) + 0.5))
+
+
+def hex_cavity_nodes(K, jitter=0.3, seed=0):
     """Unit-square cavity on a near-equilateral triangulation (the kind of
-    grid DistMesh produces, Sec. 3), unjittered: P-nodes on rows y_j = j/R,
-    R = round(2K / sqrt(3)), spaced h = 1/K and offset by h/2 on odd rows,
-    plus wall vertices at x = 0 and x = 1 on every row; the Delaunay
-    triangulation of those vertices gives the edges and V-nodes are their
-    midpoints.  Tags and normals as in ``cavity_nodes``.  Used to compare
-    node layouts, not by the lattice preconditioner."""
-    from scipy.spatial import Delaunay
+    grid DistMesh produces, Sec. 3; rbf_build_nodes kind 2).
+
+    P-grid, row by row (j = 0..R, y_j = j/R, R = ``hex_rows(K)``, h = 1/K):
+    rows 0 and R are the bottom and top walls with x = i h, i = 0..K; an even
+    interior row holds x = 0, h, 2h, ..., (K-1)h, 1 and an odd one x = 0,
+    h/2, 3h/2, ..., (K-1/2)h, 1 (first and last node on the side walls).
+    Interior vertices whose unjittered distance to the nearest wall is at
+    least 1.5 h are jittered by U(-jitter h, jitter h) per coordinate (draws
+    2v, 2v+1 of stream P for vertex v in this order); the band next to the
+    walls stays on the rows (with jitter there the Kim-Moin wall values of
+    eq. (21) feed a growing near-wall mode).
+    Edges: the horizontal edges of each row, and between rows j and j+1 the
+    strip triangulation obtained by merging the two rows in order of their
+    unjittered x (from the left-wall edge, advance in the lower row while its
+    next x is not greater than the upper row's next x, else in the upper
+    row; each advance adds one edge and one triangle).  Valid for
+    jitter < K/(2R) (about 0.43).
+    V-grid: edge midpoints (a + b) * 0.5, ordered row by row: row j's
+    horizontal edges left to right, then the strip edges of rows (j, j+1) in
+    merge order.  Tags and normals as in ``cavity_nodes``."""
     if K < 2:
         raise ValueError("K must be >= 2")
     h = 1.0 / K
-    R = int(round(2.0 * K / np.sqrt(3.0)))
+    R = hex_rows(K)
+    keys, start = [], []
     px, py, tag = [], [], []
     for j in range(R + 1):
-        y = j / R
+        y = 1.0 if j == R else j / R
+        start.append(len(keys))
         if j == 0 or j == R:
-            xs = np.arange(K + 1) * h
-            xs[-1] = 1.0
-            tags = [TAG_WALL] * (K + 1)
+            xs = [1.0 if i == K else i * h for i in range(K + 1)]
+            tg = [TAG_WALL] * (K + 1)
+        elif j % 2 == 0:
+            xs = [0.0] + [i * h for i in range(1, K)] + [1.0]
+            tg = [TAG_WALL] + [TAG_INTERIOR] * (K - 1) + [TAG_WALL]
         else:
-            off = 0.5 * h if j % 2 else 0.0
-            inner = [x for x in (np.arange(K + 1) * h + off) if 0.3 * h < x < 1.0 - 0.3 * h]
-            xs = np.array([0.0] + inner + [1.0])
-            tags = [TAG_WALL] + [TAG_INTERIOR] * len(inner) + [TAG_WALL]
-        px += list(xs)
+            xs = [0.0] + [(i + 0.5) * h for i in range(K)] + [1.0]
+            tg = [TAG_WALL] + [TAG_INTERIOR] * K + [TAG_WALL]
+        keys += xs
         py += [y] * len(xs)
-        tag += tags
-    px, py = np.array(px), np.array(py)
+        tag += tg
+    start.append(len(keys))
+    key = np.array(keys)
+    px = key.copy()
+    py = np.array(py)
     p_tag = np.array(tag, np.int8)
-    simp = Delaunay(np.stack([px, py], 1)).simplices
-    e = np.concatenate([simp[:, [0, 1]], simp[:, [1, 2]], simp[:, [0, 2]]])
-    e = np.unique(np.sort(e, axis=1), axis=0)
-    ea, eb = e[:, 0], e[:, 1]
+    M = px.size
+    dw = np.minimum(np.minimum(px, py), np.minimum(1.0 - px, 1.0 - py))
+    jit = (p_tag == TAG_INTERIOR) & (dw >= 1.5 * h)
+    ox, oy = _jitter(seed, STREAM_P, np.arange(M), jitter * h)
+    px = np.where(jit, px + ox, px)
+    py = np.where(jit, py + oy, py)
+    ea, eb = [], []
+    for j in range(R + 1):
+        a0, a1 = start[j], start[j + 1]
+        ea += list(range(a0, a1 - 1))
+        eb += list(range(a0 + 1, a1))
+        if j == R:
+            break
+        b1 = start[j + 2]
+        ia, ib = a0, a1
+        ea.append(ia)
+        eb.append(ib)
+        while ia < a1 - 1 or ib < b1 - 1:
+            if ia == a1 - 1:
+                ib += 1
+            elif ib == b1 - 1:
+                ia += 1
+            elif key[ia + 1] <= key[ib + 1]:
+                ia += 1
+            else:
+                ib += 1
+            ea.append(ia)
+            eb.append(ib)
+    ea, eb = np.array(ea), np.array(eb)
     vx = (px[ea] + px[eb]) * 0.5
     vy = (py[ea] + py[eb]) * 0.5
     on_wall = (p_tag[ea] != TAG_INTERIOR) & (p_tag[eb] != TAG_INTERIOR) & (
@@ -181,8 +230,9 @@ def hex_cavity_nodes(K):
         | (py[ea] == py[eb]) & ((py[ea] == 0.0) | (py[ea] == 1.0)))
     lid = on_wall & (vy == 1.0)
     v_tag = np.where(lid, TAG_LID, np.where(on_wall, TAG_WALL, TAG_INTERIOR)).astype(np.int8)
-    nx = np.where(px == 0.0, -1.0, np.where(px == 1.0, 1.0, 0.0))
-    ny = np.where(py == 0.0, -1.0, np.where(py == 1.0, 1.0, 0.0))
+    wall = p_tag != TAG_INTERIOR
+    nx = np.where(wall & (px == 0.0), -1.0, np.where(wall & (px == 1.0), 1.0, 0.0))
+    ny = np.where(wall & (py == 0.0), -1.0, np.where(wall & (py == 1.0), 1.0, 0.0))
     corner = (nx != 0.0) & (ny != 0.0)
     nx = np.where(corner, nx * SQRT_HALF, nx)
     ny = np.where(corner, ny * SQRT_HALF, ny)
@@ -305,9 +355,12 @@ def square_nodes(K, jitter=0.3, seed=0):
 
 
 def build_nodes(kind, K, jitter=0.3, seed=0):
-    """kind 0: cavity; kind 1: bench square."""
+    """kind 0: cavity (right-triangle lattice); kind 1: bench square;
+    kind 2: cavity on the near-equilateral triangulation."""
     if kind == 0:
         return cavity_nodes(K, jitter, seed)
     if kind == 1:
         return square_nodes(K, jitter, seed)
+    if kind == 2:
+        return hex_cavity_nodes(K, jitter, seed)
     raise ValueError(f"unknown node-set kind {kind}")

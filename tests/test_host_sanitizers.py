@@ -61,7 +61,8 @@ def _read(path, nv, npn):
 
 
 @pytest.mark.parametrize("kind,K,jit,seed", [(0, 2, 0.3, 0), (0, 13, 0.3, 3), (0, 40, 0.0, 1),
-                                             (1, 1, 0.3, 0), (1, 25, 0.45, 7)])
+                                             (1, 1, 0.3, 0), (1, 25, 0.45, 7), (2, 2, 0.3, 0),
+                                             (2, 17, 0.4, 5), (2, 60, 0.0, 1)])
 def test_node_builder_clean_under_sanitizers(driver, kind, K, jit, seed):
     exe, out = driver
     path = str(out / f"nodes_{kind}_{K}_{seed}.bin")
@@ -73,9 +74,9 @@ def test_node_builder_clean_under_sanitizers(driver, kind, K, jit, seed):
     assert "runtime error" not in res.stderr and "AddressSanitizer" not in res.stderr
     nv, npn = np.frombuffer(open(path, "rb").read(16), dtype=np.int64)
     xv, xp, pn, vt, pt = _read(path, int(nv), int(npn))
-    nd = ri.cavity_nodes(K, jit, seed) if kind == 0 else ri.square_nodes(K, jit, seed)
+    nd = ri.build_nodes(kind, K, jit, seed)
     assert np.array_equal(xv, nd.xv) and np.array_equal(xp, nd.xp)
-    if kind == 0:
+    if kind != 1:
         assert np.array_equal(vt, nd.v_tag) and np.array_equal(pt, nd.p_tag)
         assert np.array_equal(pn, nd.p_normal)
     else:

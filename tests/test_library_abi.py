@@ -46,7 +46,8 @@ def test_abi_version(lib):
     assert lib.rbf_abi_version() == 2
 
 
-@pytest.mark.parametrize("kind,K,seed", [(0, 7, 0), (0, 40, 3), (1, 50, 1)])
+@pytest.mark.parametrize("kind,K,seed", [(0, 7, 0), (0, 40, 3), (1, 50, 1), (2, 2, 0), (2, 9, 4),
+                                         (2, 101, 2)])
 def test_host_node_builder_matches_input_generator(lib, kind, K, seed):
     """rbf_build_nodes (C, host) and rbf_inputs (NumPy) implement the same
     SplitMix64 recipe independently; coordinates must be bit-identical."""

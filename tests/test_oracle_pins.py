@@ -70,6 +70,73 @@ def test_cylinder_node_layout():
     assert vb.sum() == bnd.sum()  # closed boundary loops: as many edges as vertices
 
 
+@pytest.mark.parametrize("K,jit,seed", [(2, 0.3, 0), (9, 0.4, 3), (40, 0.3, 1)])
+def test_hex_cavity_node_layout(K, jit, seed):
+    """Near-equilateral cavity (kind 2): P rows about sqrt(3)/2 h apart,
+    every node in the square, walls exactly on the walls, interior nodes
+    jittered only at least 1.5 h from the walls and by at most jit h, every
+    V-node the midpoint of two P-nodes, the triangles of the row-merge
+    triangulation all positively oriented (a valid triangulation for this
+    jitter), N = 3M - (boundary vertices) - 3 (Euler's formula for a
+    triangulated disc: E = 3V - B - 3) and unit outward normals."""
+    nd = ri.hex_cavity_nodes(K, jit, seed)
+    ref = ri.hex_cavity_nodes(K, 0.0, seed)
+    h = 1.0 / K
+    R = ri.nodes.hex_rows(K)
+    assert abs(1.0 / R - np.sqrt(3.0) / 2.0 * h) < 0.5 * h / R
+    for x in (nd.xv, nd.xp):
+        assert x.min() >= 0.0 and x.max() <= 1.0
+    on_wall = lambda x: (x[0] == 0) | (x[0] == 1) | (x[1] == 0) | (x[1] == 1)  # noqa: E731
+    assert np.array_equal(nd.p_tag != 0, on_wall(nd.xp))
+    assert np.array_equal(nd.v_tag != 0, on_wall(nd.xv))
+    assert np.all(nd.xv[1][nd.v_tag == ri.TAG_LID] == 1.0) and (nd.v_tag == ri.TAG_LID).sum() == K
+    d = np.abs(nd.xp - ref.xp)
+    assert np.max(d) <= jit * h
+    dw = np.minimum.reduce([ref.xp[0], ref.xp[1], 1 - ref.xp[0], 1 - ref.xp[1]])
+    assert np.all(d[:, dw < 1.5 * h] == 0.0)
+    if K >= 9 and jit > 0:
+        assert np.all(d[:, (dw >= 1.5 * h) & (nd.p_tag == 0)].max(axis=0) > 0)
+    B = int((nd.p_tag != 0).sum())
+    assert nd.n_v == 3 * nd.n_p - B - 3
+    # Edges from the midpoints: each V node is (a + b) / 2 of a P pair.
+    from scipy.spatial import cKDTree
+    _, nb = cKDTree(nd.xp.T).query(nd.xv.T, k=min(8, nd.n_p))
+    for i in range(0, nd.n_v, max(1, nd.n_v // 500)):
+        c = nb[i]
+        mids = (nd.xp[:, c][:, :, None] + nd.xp[:, c][:, None, :]) * 0.5
+        assert ((mids[0] == nd.xv[0, i]) & (mids[1] == nd.xv[1, i])).any(), i
+    # Orientation of the row-merge triangles: recover each V node's edge,
+    # take the triangles as the 3-cycles of the edge graph, and require the
+    # jittered triangles to keep the orientation of the unjittered ones.
+    if K <= 9:
+        edges = set()
+        for i in range(nd.n_v):  # the shortest P pair with this midpoint
+            c = nb[i]
+            best = None
+            for p_ in c:
+                for q_ in c:
+                    if p_ < q_ and (nd.xp[0, p_] + nd.xp[0, q_]) * 0.5 == nd.xv[0, i] and \
+                            (nd.xp[1, p_] + nd.xp[1, q_]) * 0.5 == nd.xv[1, i]:
+                        ln = np.hypot(*(nd.xp[:, p_] - nd.xp[:, q_]))
+                        if best is None or ln < best[0]:
+                            best = (ln, int(p_), int(q_))
+            edges.add(best[1:])
+        assert len(edges) == nd.n_v
+        adj = {}
+        for p_, q_ in edges:
+            adj.setdefault(p_, set()).add(q_)
+            adj.setdefault(q_, set()).add(p_)
+        tris = {tuple(sorted((p_, q_, r_))) for p_, q_ in edges for r_ in adj[p_] & adj[q_]}
+        assert len(tris) == nd.n_v - nd.n_p + 1  # Euler: F = E - V + 1
+        cross = lambda P, t: ((P[0, t[1]] - P[0, t[0]]) * (P[1, t[2]] - P[1, t[0]])  # noqa: E731
+                              - (P[1, t[1]] - P[1, t[0]]) * (P[0, t[2]] - P[0, t[0]]))
+        for t in tris:
+            c0, c1 = cross(ref.xp, t), cross(nd.xp, t)
+            assert c0 != 0 and np.sign(c0) == np.sign(c1), t
+    n = np.hypot(nd.p_normal[0], nd.p_normal[1])
+    assert np.allclose(n[nd.p_tag != 0], 1.0) and np.all(n[nd.p_tag == 0] == 0)
+
+
 def test_node_generator_is_seeded_and_splitmix():
     # SplitMix64 reference values for seed 0 (Vigna's published generator):
     # the first outputs of the sequence started at state 0.
@@ -481,7 +548,7 @@ def _projection_radius(K, hexagonal=False):
     (interior V rows; wall rows held at zero): u -> u - G p~ with
     A p~ = D u on interior P rows, 0 on wall rows (bordered system)."""
     import scipy.sparse.linalg as spla
-    nd = ri.hex_cavity_nodes(K) if hexagonal else ri.cavity_nodes(K, 0.3, 0)
+    nd = ri.hex_cavity_nodes(K, 0.3, 0) if hexagonal else ri.cavity_nodes(K, 0.3, 0)
     ops = oops.CavityOperators(nd, 28, 7, 3)
     _, chi, B = oops.poisson_matrix(ops)
     lu = spla.splu(B.tocsc())
@@ -505,11 +572,29 @@ def test_projection_spectral_radius():
     its spectral radius on the right-triangle lattice is 1 at h = 1/24 (the
     parity cases' regime) and exceeds 1 at h = 1/60 (observed: 6.9;
     near-wall modes), which is the divergence of long runs on those node
-    sets; on a near-equilateral triangulation of the same square (the kind
-    of grid the paper uses) it stays 1 at h = 1/60."""
+    sets; on the jittered near-equilateral triangulation (kind 2, jitter
+    0.3 h) it stays 1 at h = 1/60 and h = 1/100."""
     assert _projection_radius(24) <= 1.0 + 1e-6
     assert _projection_radius(60) > 2.0
     assert _projection_radius(60, hexagonal=True) <= 1.0 + 1e-6
+    assert _projection_radius(100, hexagonal=True) <= 1.0 + 1e-6
+
+
+def test_hex_cavity_long_run_bounded():
+    """Sec. 5.1 reports its cavity runs stable without hyperviscosity.  On the
+    jittered near-equilateral set (kind 2, K = 100, jitter 0.3 h, seed 0) the
+    oracle runs 400 steps at Re = 1e4, dt = 2e-4 with the wall velocities
+    at their boundary values to O(dt^2) and the speed bounded by the lid's."""
+    nd = ri.hex_cavity_nodes(100, 0.3, 0)
+    u_bc, v_bc = ri.cavity_bc(nd.v_tag)
+    orc = ocav.CavityOracle(nd, u_bc, v_bc, 1e4, 2e-4)
+    s = orc.run(400)
+    speed = np.hypot(s.u, s.v)
+    assert np.all(np.isfinite(speed)) and speed.max() < 1.05
+    wall = nd.v_tag != 0
+    assert np.max(np.abs(s.u[wall] - u_bc[wall])) < 1e-3
+    div = orc.divergence(s.u, s.v)[nd.p_tag == 0]
+    assert np.max(np.abs(div)) < 0.05
 
 
 def test_brute_force_dense_tiny_cavity():
