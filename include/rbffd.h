@@ -55,7 +55,7 @@ typedef int32_t rbf_status;
 #define RBF_OP_DY 4u
 #define RBF_OP_LAP 8u
 
-#define RBF_ABI_VERSION 2
+#define RBF_ABI_VERSION 3
 
 typedef void *rbf_stream;
 
@@ -272,29 +272,47 @@ typedef struct {
 
 /* rbf_params.precision:
  * FP64   every stage in FP64;
- * MIXED  the lattice preconditioner's transforms and tridiagonal solves
- *        stored in FP32 (FP32 matrix cores); operators, residuals, the
- *        Krylov iteration, the weights and the projection stay FP64, so the
- *        tolerance still refers to the FP64 residual (the fields differ from
- *        FP64 runs at the tolerance level). */
+ * MIXED  with the lattice preconditioner: its transforms and tridiagonal
+ *        solves stored in FP32 (FP32 matrix cores), everything else FP64;
+ *        with the auxiliary-lattice preconditioner: FP32 inside FP64
+ *        iterative refinement -- each restart cycle of the pressure solve
+ *        forms the residual b - A x in FP64 from the FP64 weights, runs
+ *        flexible GMRES on FP32-stored weights, vectors and transforms (FP64
+ *        dot products) until the residual drops by 1e-4 or the cycle ends,
+ *        and adds the correction to the FP64 iterate.  The weights, the
+ *        outer residuals, the projection and the tolerance stay FP64, so
+ *        the fields differ from FP64 runs at the tolerance level. */
 #define RBF_PRECISION_FP64 0
 #define RBF_PRECISION_MIXED 1
 
 /* rbf_params.precond:
  * AUTO     the lattice preconditioner when the P-nodes form a jittered
  *          (K+1)^2 lattice of the unit square (the cavity layout of
- *          rbf_build_nodes) with K <= 513, none otherwise;
+ *          rbf_build_nodes kind 0) with K <= 513; else the auxiliary-lattice
+ *          preconditioner when the P-nodes' bounding box is a square;
+ *          none otherwise;
  * NONE     unpreconditioned BiCGSTAB on the row-scaled system;
  * LATTICE  the lattice preconditioner, RBF_E_ARG if the P-nodes are not
- *          such a lattice or K > 513.
+ *          such a lattice or K > 513;
+ * AUX      the auxiliary-lattice preconditioner, RBF_E_ARG if the bounding
+ *          box is not a square.
  * The lattice preconditioner is the 5-point Laplacian of the unjittered
  * lattice with one-sided Neumann rows, inverted exactly by a fast Poisson
  * solve (DCT-II along x as dense products on the matrix cores, tridiagonal
  * solves along y), followed by bilinear interpolation to the node
- * positions.  It changes only the iteration, not the system solved. */
+ * positions; BiCGSTAB iterates with it.
+ * The auxiliary-lattice preconditioner (any node set in a square) is a
+ * two-level method: an l1-Jacobi sweep on the stored Poisson rows, the
+ * residual restricted (normalised bilinear weights, interior nodes to
+ * interior lattice points) to a lattice of about two node spacings per cell
+ * and solved there by the same fast Poisson solve with homogeneous Neumann
+ * rows, interpolated back with the border's constant, and a second sweep;
+ * flexible GMRES (restart 30) iterates with it.  Neither changes the
+ * system solved. */
 #define RBF_PRECOND_AUTO 0
 #define RBF_PRECOND_NONE 1
 #define RBF_PRECOND_LATTICE 2
+#define RBF_PRECOND_AUX 3
 
 /* Solver state at step j, device memory owned by the caller. */
 typedef struct {
@@ -397,11 +415,13 @@ rbf_status rbf_solve_pressure(rbf_solver *s, const double *rhs, double *p_tilde,
                               rbf_solve_stats *stats);
 
 /*
- * rbf_solver_apply_precond -- apply the pressure preconditioner once:
- * z = P^-1 y with P^-1 = J (L5 + chi c 1^T)^-1 D^-1 as described at
- * rbf_params.precond (D: the row scale of the stored Poisson rows).  For
+ * rbf_solver_apply_precond -- apply the pressure preconditioner once, z =
+ * P^-1 y: the lattice preconditioner J (L5 + chi c 1^T)^-1 D^-1, or the
+ * auxiliary-lattice two-level preconditioner (both described at
+ * rbf_params.precond; D: the row scale of the stored Poisson rows).  For
  * tests and diagnostics.  y, z: device [n_p], distinct.  Synchronises the
- * solver's stream.  Errors: RBF_E_ARG (NULL, or no lattice preconditioner).
+ * solver's stream.  Errors: RBF_E_ARG (NULL, no preconditioner, or the
+ * auxiliary-lattice preconditioner of a mixed-precision solver).
  */
 rbf_status rbf_solver_apply_precond(rbf_solver *s, const double *y, double *z);
 
@@ -437,6 +457,8 @@ typedef struct {
     int32_t viscous_jacobi;
     int32_t lattice_precond;
     double jacobi_bound;
+    int32_t aux_precond;   /* 1: auxiliary-lattice preconditioner with FGMRES */
+    int32_t aux_cells;     /* its lattice cells per side (0 if unused)       */
 } rbf_solver_info;
 rbf_status rbf_solver_query(rbf_solver *s, rbf_solver_info *info);
 

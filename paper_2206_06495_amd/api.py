@@ -168,7 +168,7 @@ class Solver:
     pp_lap, idx_vp, vp_dx, vp_dy (device, [k, rows]).
     """
 
-    PRECOND = {"auto": 0, "none": 1, "lattice": 2}
+    PRECOND = {"auto": 0, "none": 1, "lattice": 2, "aux": 3}
     PRECISION = {"fp64": 0, "mixed": 1}
 
     def __init__(self, grid, ops, u_bc, v_bc, re, dt, rtol_h=1e-13, rtol_p=1e-12,
@@ -232,7 +232,8 @@ class Solver:
         return stats
 
     def apply_precond(self, y):
-        """z = P^-1 y, one application of the lattice pressure preconditioner."""
+        """z = P^-1 y, one application of the pressure preconditioner (lattice
+        or auxiliary-lattice)."""
         _dev(y, torch.float64, (self.M,), "y")
         z = torch.empty_like(y)
         check(lib.rbf_solver_apply_precond(self._h, _ptr(y), _ptr(z)))
@@ -248,11 +249,13 @@ class Solver:
         return {"gemm": (avg[0], cnt[0]), "spmv": (avg[1], cnt[1])}
 
     def info(self):
-        """How the solves run: {"viscous_jacobi", "lattice_precond", "jacobi_bound"}."""
+        """How the solves run: {"viscous_jacobi", "lattice_precond", "jacobi_bound",
+        "aux_precond", "aux_cells"}."""
         inf = _lib.SolverInfo()
         check(lib.rbf_solver_query(self._h, ctypes.byref(inf)))
         return {"viscous_jacobi": bool(inf.viscous_jacobi),
-                "lattice_precond": bool(inf.lattice_precond), "jacobi_bound": inf.jacobi_bound}
+                "lattice_precond": bool(inf.lattice_precond), "jacobi_bound": inf.jacobi_bound,
+                "aux_precond": bool(inf.aux_precond), "aux_cells": int(inf.aux_cells)}
 
     def run(self, state, nsteps, every=10, log=None):
         """Advance `state` by `nsteps` in rbf_step calls of `every` steps and,

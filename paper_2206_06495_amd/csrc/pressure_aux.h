@@ -1,0 +1,435 @@
+// Pressure solve on general node sets: flexible GMRES (Saad 1993) right-
+// preconditioned by a two-level auxiliary-lattice method.  Included by
+// solver.hip inside its anonymous namespace (it uses the solver's Krylov
+// helpers, the lattice transforms k_pc_gemm / k_pc_tri and rbf_solver).
+//
+// System: the row-scaled bordered Poisson operator of eq. (18),
+//   A x = S A0 x + u1 c (1^T x),   S the row scale, u1 = S chi, c = vscale,
+// A0: D_Lap^PP on interior rows, n . grad on wall rows (see k_build_poisson).
+//
+// Preconditioner z = B^-1 y (one application):
+//   x1 = W y                      W = omega / (l1 norm of A's rows)
+//   r1 = y - A_s x1               A_s: the sparse part of A
+//   g  = R (S^-1 r1)              R: normalised bilinear restriction of the
+//                                 interior-node residuals to the interior
+//                                 points of an auxiliary (Ka+1)^2 lattice
+//                                 over the nodes' bounding square
+//   e  = (L5)^+ (g - lam)         L5: 5-point Laplacian of the lattice with
+//                                 one-sided homogeneous Neumann wall rows,
+//                                 inverted by the fast transform (DCT-II along
+//                                 x, tridiagonal along y); lam = mean of g,
+//                                 e of zero mean
+//   x2 = x1 + J e + mu            J: bilinear interpolation to the nodes
+//                                 (wall lattice values copied inward);
+//                                 mu = (lam / c - sum J e) / m carries the
+//                                 border's constant (the exact form for the
+//                                 bordered operator A0 + chi c 1^T)
+//   z  = x2 + W (y - A_s x2)      post-smoothing
+// The auxiliary lattice is coarser than the nodes (about two node spacings
+// per cell): the smoother removes what the lattice cannot represent, the
+// lattice solve removes the smooth error the smoother cannot.  A_s 1 = 0
+// (the rows reproduce constants), so mu needs no product.
+//
+// Precision: T = double (the FP64 solve) or float (mixed precision: each
+// restart cycle is one step of iterative refinement whose residual
+// b - A x is formed in FP64 from FP64 weights, the cycle itself runs on
+// FP32-stored weights, vectors and transforms with FP64 dot products, and
+// the correction is added to the FP64 iterate).
+//
+// FGMRES(mr) with classical Gram-Schmidt applied twice; the Hessenberg
+// column, the Givens rotations and the residual estimate are updated on the
+// device by one workgroup per step; the host reads a status block after each
+// batch of steps.  All reductions are fixed-order (block partials reduced by
+// one workgroup), so a solve is repeatable bit for bit.
+#pragma once
+
+constexpr int kFgMax = 30;        // restart length (basis vectors per cycle)
+constexpr int kFgChunk = 6;       // dot products accumulated per pass over the rows
+constexpr double kAuxOmega = 1.3; // smoother damping (l1-Jacobi)
+constexpr double kMixedInner = 1e-4;  // mixed: per-cycle residual reduction
+
+template <class T>
+struct AuxOps {
+    const int *idx;
+    const T *w;       // [k][m] row-scaled Poisson weights (sparse part of A)
+    const T *dinv;    // [m] omega / l1 row norm
+    const T *sinv;    // [m] 1 / row scale
+    const int *rptr;  // [n*n + 1] restriction rows (interior lattice points)
+    const int *rcol;  // node indices
+    const T *rval;    // weights, summing to 1 per lattice point
+    int64_t m;
+    int k;
+};
+
+// FGMRES scalars (device).  Basis vector V_j is stored unnormalised with
+// its inverse norm vs[j]; every reader multiplies.
+struct FgScal {
+    double *vs;      // [mr+1] inverse norms
+    double *part;    // [kFgMax + 2][kMaxBlocks] partial sums
+    double *h1, *h2; // [mr+1] Gram-Schmidt coefficients of the two passes
+    double *hn2;     // [1] ||w||^2 after the second pass
+    double *H;       // [(mr+1) * mr] Hessenberg matrix, column-major
+    double *cs, *sn; // [mr] Givens rotations
+    double *g;       // [mr+1] rotated right-hand side
+    double *y;       // [mr] coefficients of the update
+    double *resh;    // [mr+1] |g_{j}| per step of the cycle
+    double *partZ;   // [kMaxBlocks] sums of J e (interpolated correction)
+    double *partO;   // [kMaxBlocks] sums of z (border term of A z)
+    double *one;     // [1] = 1.0 (unit scale of an explicit input vector)
+    // status, read by the host in one copy: flag, step, then (as doubles)
+    // |g_{j+1}| now, 4 steps earlier, the cycle's target, ||b||^2, beta.
+    int *flag, *step;
+    double *stat;
+};
+
+template <class T>
+struct FgDev {
+    T *V;            // [(mr+1)][m]
+    T *Z;            // [mr][m] preconditioned directions
+    T *res, *t1;     // [m] preconditioner work
+    FgScal s;
+};
+
+// -------------------------------------------------------------- kernels --
+template <int KT, class T, class F>
+__device__ __forceinline__ T aux_row(const AuxOps<T> &P, int64_t r, F f) {
+    T acc = 0;
+    if constexpr (KT > 0) {
+        int jj[KT];
+        T ww[KT];
+#pragma unroll
+        for (int q = 0; q < KT; ++q) jj[q] = rbf::ld_stream(P.idx + (int64_t)q * P.m + r);
+#pragma unroll
+        for (int q = 0; q < KT; ++q) ww[q] = rbf::ld_stream(P.w + (int64_t)q * P.m + r);
+#pragma unroll
+        for (int q = 0; q < KT; ++q) acc = fma(ww[q], f(jj[q]), acc);
+    } else {
+        for (int q = 0; q < P.k; ++q)
+            acc = fma(rbf::ld_stream(P.w + (int64_t)q * P.m + r),
+                      f(rbf::ld_stream(P.idx + (int64_t)q * P.m + r)), acc);
+    }
+    return acc;
+}
+
+// Preconditioner stage 1: res = S^-1 (y - A_s W y), y scaled by *ys.
+template <int KT, class T>
+__global__ void __launch_bounds__(kThreads) k_aux_res(AuxOps<T> P, const T *__restrict__ y,
+                                                       const double *ys, T *__restrict__ res,
+                                                       const int *flag) {
+    if (*flag != 0) return;
+    const T sc = (T)*ys;
+    for (int64_t it = 0;; ++it) {
+        const int64_t r = row_of(it);
+        if (r - threadIdx.x >= P.m) break;
+        if (r < P.m) {
+            const T ax = aux_row<KT>(P, r, [&](int j) { return sc * y[j] * P.dinv[j]; });
+            res[r] = P.sinv[r] * (sc * y[r] - ax);
+        }
+    }
+}
+
+// Stage 2: restriction to the interior lattice points, X(q) = sum rval res.
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_aux_restrict(AuxOps<T> P, Lat L,
+                                                            const T *__restrict__ res, int nq) {
+    if (*L.flag != 0) return;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    double g = 0.0;
+    for (int e = P.rptr[q]; e < P.rptr[q + 1]; ++e) g += (double)P.rval[e] * (double)res[P.rcol[e]];
+    lat_store(L, L.X, q, g);
+}
+
+// Lattice value of the transform solve (Z, column-major in X) at lattice
+// node (i, j); wall nodes take their inward neighbour's value (homogeneous
+// one-sided Neumann rows).
+__device__ __forceinline__ double aux_lattice(const Lat &L, int i, int j) {
+    const int ci = min(max(i, 1), L.K - 1), cj = min(max(j, 1), L.K - 1);
+    return lat_load(L, L.X, (int64_t)(ci - 1) + (int64_t)(cj - 1) * L.n);
+}
+
+// Stage 3: t1 = W y + J e, and block sums of J e.
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_aux_interp(AuxOps<T> P, Lat L,
+                                                          const T *__restrict__ y,
+                                                          const double *ys, T *__restrict__ t1,
+                                                          double *partZ) {
+    if (*L.flag != 0) return;
+    const T sc = (T)*ys;
+    const int K1 = L.K + 1;
+    double acc[1] = {0.0};
+    for (int64_t it = 0;; ++it) {
+        const int64_t r = row_of(it);
+        if (r - threadIdx.x >= P.m) break;
+        if (r < P.m) {
+            const int c = L.cell[r];
+            const int i0 = c % K1, j0 = c / K1;
+            const double fx = L.fx[r], fy = L.fy[r];
+            const double z = (1.0 - fy) * ((1.0 - fx) * aux_lattice(L, i0, j0) +
+                                           fx * aux_lattice(L, i0 + 1, j0)) +
+                             fy * ((1.0 - fx) * aux_lattice(L, i0, j0 + 1) +
+                                   fx * aux_lattice(L, i0 + 1, j0 + 1));
+            t1[r] = sc * y[r] * P.dinv[r] + (T)z;
+            acc[0] += z;
+        }
+    }
+    store_partials<1>(acc, partZ, gridDim.x);
+}
+
+// Stage 4: z = t1 + mu + W (y - A_s t1); block sums of z (border term of
+// the product that follows).
+template <int KT, class T>
+__global__ void __launch_bounds__(kThreads) k_aux_post(AuxOps<T> P, Lat L,
+                                                        const T *__restrict__ y, const double *ys,
+                                                        const T *__restrict__ t1,
+                                                        const double *partZ,
+                                                        T *__restrict__ z, double *partO) {
+    if (*L.flag != 0) return;
+    double sz[1];
+    load_partials<1>(partZ, gridDim.x, sz);
+    const double mu = (*L.mean / L.c - sz[0]) / (double)P.m;
+    const T sc = (T)*ys;
+    double acc[1] = {0.0};
+    for (int64_t it = 0;; ++it) {
+        const int64_t r = row_of(it);
+        if (r - threadIdx.x >= P.m) break;
+        if (r < P.m) {
+            const T at = aux_row<KT>(P, r, [&](int j) { return t1[j]; });
+            const T zr = t1[r] + (T)mu + P.dinv[r] * (sc * y[r] - at);
+            z[r] = zr;
+            acc[0] += (double)zr;
+        }
+    }
+    store_partials<1>(acc, partO, gridDim.x);
+}
+
+// Cycle start: r = b - A x in FP64 (FP64 weights and border), V_0 = r;
+// block sums of ||r||^2 and ||b||^2 (rows 0 and 1 of part).
+template <int KT, class T>
+__global__ void __launch_bounds__(kThreads) k_fg_init(EllM A, const double *__restrict__ b,
+                                                       const double *__restrict__ x,
+                                                       const double *partX, T *__restrict__ V0,
+                                                       double *part) {
+    const int nb = gridDim.x;
+    double sx[1] = {0.0};
+    if (A.u1) load_partials<1>(partX, nb, sx);
+    double acc[2] = {0.0, 0.0};
+    for (int64_t it = 0;; ++it) {
+        const int64_t r = row_of(it);
+        if (r - threadIdx.x >= A.n) break;
+        if (r < A.n) {
+            double ax[1][1] = {};
+            const double *ws[1] = {A.w};
+            rbf::ell_row<KT, 1>(A.idx, ws, A.n, r, A.k, GatherN<1>{x, A.n}, ax);
+            const double u1 = A.u1 ? A.u1[r] * A.vscale : 0.0;
+            const double rr = b[r] - (ax[0][0] + u1 * sx[0]);
+            V0[r] = (T)rr;
+            acc[0] += rr * rr;
+            acc[1] += b[r] * b[r];
+        }
+    }
+    double v0[1] = {acc[0]}, v1[1] = {acc[1]};
+    store_partials<1>(v0, part, nb);
+    store_partials<1>(v1, part + kMaxBlocks, nb);
+}
+
+// One workgroup: reduce nq rows of nb block partials (row q at
+// q * kMaxBlocks) into out[q], each row by one wavefront in a fixed order.
+// GATE: exit when the flag is set (inside an Arnoldi step).
+template <bool GATE>
+__global__ void __launch_bounds__(256) k_fg_reduce(const double *part, int nb, int nq,
+                                                   double *out, const int *flag) {
+    if (GATE && *flag != 0) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int q = wid; q < nq; q += 4) {
+        double s = 0.0;
+        for (int b = lane; b < nb; b += 64) s += part[(int64_t)q * kMaxBlocks + b];
+        s = rbf::wave_sum(s);
+        if (lane == 0) out[q] = s;
+    }
+}
+
+// Cycle start, one thread: beta = ||r||, the cycle's target (FP64:
+// tol ||b||; mixed: also kMixedInner beta), convergence of the true
+// residual (flag 1), g = beta e_1.  red: {||r||^2, ||b||^2}; ||b|| is
+// taken from the first cycle.
+__global__ void k_fg_start(FgScal F, const double *red, double tol, int mixed, int first) {
+    const double rr = red[0], bbv = first ? red[1] : F.stat[3];
+    const double beta = sqrt(rr);
+    const double goal = tol * sqrt(fmax(bbv, 1e-300));
+    F.step[0] = 0;
+    F.stat[0] = beta;
+    F.stat[1] = beta;
+    F.stat[3] = bbv;
+    F.stat[4] = beta;
+    F.resh[0] = beta;
+    if (!isfinite(beta)) {
+        F.flag[0] = -1;
+        return;
+    }
+    if (beta <= goal || beta == 0.0) {
+        F.flag[0] = 1;
+        return;
+    }
+    F.stat[2] = mixed ? fmax(goal, kMixedInner * beta) : goal;
+    F.vs[0] = 1.0 / beta;
+    F.g[0] = beta;
+    F.flag[0] = 0;
+}
+
+// Block partial dots (V_i vs_i, w) for i <= j, kFgChunk at a time; w is
+// this thread's rows of the new vector (re-read per chunk).
+template <class T>
+__device__ __forceinline__ void fg_dots(const T *V, const double *vs, const T *w, int64_t m, int j,
+                                        double *part) {
+    for (int i0 = 0; i0 <= j; i0 += kFgChunk) {
+        double acc[kFgChunk];
+#pragma unroll
+        for (int c = 0; c < kFgChunk; ++c) acc[c] = 0.0;
+        for (int64_t it = 0;; ++it) {
+            const int64_t r = row_of(it);
+            if (r - threadIdx.x >= m) break;
+            if (r < m) {
+                const double wr = (double)w[r];
+#pragma unroll
+                for (int c = 0; c < kFgChunk; ++c)
+                    if (i0 + c <= j) acc[c] += (double)V[(int64_t)(i0 + c) * m + r] * wr;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kFgChunk; ++c) acc[c] *= (i0 + c <= j) ? vs[i0 + c] : 0.0;
+        __shared__ double lds[kFgChunk * (kThreads / 64)];
+        rbf::block_sum<kFgChunk>(acc, lds);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < kFgChunk && i0 + c <= j; ++c)
+                part[(int64_t)(i0 + c) * kMaxBlocks + blockIdx.x] = acc[c];
+    }
+}
+
+// Arnoldi step j, product: w = A z_j (sparse part in T plus the border with
+// sum z_j from partO), stored in V[j+1]; block partial dots (V_i vs_i, w).
+template <int KT, class T>
+__global__ void __launch_bounds__(kThreads) k_fg_av(AuxOps<T> P, const double *__restrict__ u1,
+                                                     double vscale, FgDev<T> F, int j) {
+    if (*F.s.flag != 0) return;
+    double sz[1];
+    load_partials<1>(F.s.partO, gridDim.x, sz);
+    const T *z = F.Z + (int64_t)j * P.m;
+    T *w = F.V + (int64_t)(j + 1) * P.m;
+    for (int64_t it = 0;; ++it) {
+        const int64_t r = row_of(it);
+        if (r - threadIdx.x >= P.m) break;
+        if (r < P.m) {
+            const T az = aux_row<KT>(P, r, [&](int c) { return z[c]; });
+            w[r] = (T)((double)az + (u1 ? u1[r] * vscale * sz[0] : 0.0));
+        }
+    }
+    fg_dots(F.V, F.s.vs, w, P.m, j, F.s.part);
+}
+
+// Gram-Schmidt update w -= sum_i h_i vs_i V_i (i <= j); PASS 1: then block
+// partial dots (V_i vs_i, w) for the second pass; PASS 2: then block
+// partial ||w||^2.
+template <class T, int PASS>
+__global__ void __launch_bounds__(kThreads) k_fg_gs(FgDev<T> F, const double *h, int64_t m,
+                                                     int j) {
+    if (*F.s.flag != 0) return;
+    __shared__ double c[kFgMax + 1];
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) c[i] = h[i] * F.s.vs[i];
+    __syncthreads();
+    T *w = F.V + (int64_t)(j + 1) * m;
+    double nrm[1] = {0.0};
+    for (int64_t it = 0;; ++it) {
+        const int64_t r = row_of(it);
+        if (r - threadIdx.x >= m) break;
+        if (r < m) {
+            double wr = (double)w[r];
+            for (int i = 0; i <= j; ++i) wr -= c[i] * (double)F.V[(int64_t)i * m + r];
+            const T wt = (T)wr;
+            w[r] = wt;
+            nrm[0] += (double)wt * (double)wt;
+        }
+    }
+    if constexpr (PASS == 1) {
+        fg_dots(F.V, F.s.vs, w, m, j, F.s.part);
+    } else {
+        store_partials<1>(nrm, F.s.part, gridDim.x);
+    }
+}
+
+// Arnoldi step j, one thread: Hessenberg column j = h1 + h2 with
+// H(j+1, j) = ||w||, previous rotations applied, a new rotation, the
+// residual estimate |g_{j+1}| and the status (4: the cycle's target met or
+// an exact breakdown; 3: the cycle is full; -1: non-finite).
+__global__ void k_fg_tail(FgScal F, int j, int mr) {
+    if (*F.flag != 0) return;
+    double *Hc = F.H + (int64_t)j * (mr + 1);
+    for (int i = 0; i <= j; ++i) Hc[i] = F.h1[i] + F.h2[i];
+    const double hn = sqrt(F.hn2[0]);
+    Hc[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a = Hc[i], b = Hc[i + 1];
+        Hc[i] = F.cs[i] * a + F.sn[i] * b;
+        Hc[i + 1] = -F.sn[i] * a + F.cs[i] * b;
+    }
+    const double a = Hc[j], b = Hc[j + 1];
+    const double den = hypot(a, b);
+    const double c = (den > 0.0) ? a / den : 1.0, s = (den > 0.0) ? b / den : 0.0;
+    F.cs[j] = c;
+    F.sn[j] = s;
+    Hc[j] = den;
+    Hc[j + 1] = 0.0;
+    const double gj = F.g[j];
+    F.g[j] = c * gj;
+    F.g[j + 1] = -s * gj;
+    const double res = fabs(F.g[j + 1]);
+    F.vs[j + 1] = (hn > 0.0) ? 1.0 / hn : 0.0;
+    F.resh[j + 1] = res;
+    F.step[0] = j + 1;
+    F.stat[0] = res;
+    F.stat[1] = F.resh[max(0, j + 1 - 4)];
+    if (!isfinite(res) || !isfinite(den)) F.flag[0] = -1;
+    else if (res <= F.stat[2] || hn == 0.0 || den == 0.0) F.flag[0] = 4;
+    else if (j + 1 >= mr) F.flag[0] = 3;
+}
+
+// End of a cycle of nstep steps, one thread: back substitution H y = g.
+__global__ void k_fg_solve(FgScal F, int nstep, int mr) {
+    for (int i = nstep - 1; i >= 0; --i) {
+        double s = F.g[i];
+        for (int l = i + 1; l < nstep; ++l) s -= F.H[(int64_t)l * (mr + 1) + i] * F.y[l];
+        const double d = F.H[(int64_t)i * (mr + 1) + i];
+        F.y[i] = (d != 0.0) ? s / d : 0.0;
+    }
+}
+
+// x += sum_i y_i Z_i (FP64 iterate).
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_fg_x(const T *__restrict__ Z, const double *ycoef,
+                                                    int nstep, int64_t m, double *__restrict__ x) {
+    for (int64_t r = blockIdx.x * (int64_t)kThreads + threadIdx.x; r < m;
+         r += (int64_t)gridDim.x * kThreads) {
+        double s = x[r];
+        for (int i = 0; i < nstep; ++i) s += ycoef[i] * (double)Z[(int64_t)i * m + r];
+        x[r] = s;
+    }
+}
+
+// l1 row norms of the stored Poisson rows: dinv = omega / sum |w|, and
+// 1 / row scale.
+__global__ void k_aux_rows(int64_t m, int k, const double *__restrict__ w,
+                           const double *__restrict__ rs, double *dinv, double *sinv) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    double s = 0.0;
+    for (int q = 0; q < k; ++q) s += fabs(w[(int64_t)q * m + r]);
+    dinv[r] = (s > 0.0) ? kAuxOmega / s : 0.0;
+    sinv[r] = 1.0 / rs[r];
+}
+
+// FP32 copies for the mixed-precision cycles.
+__global__ void k_aux_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}

@@ -1697,6 +1697,8 @@ __global__ void k_wall_list(int64_t n, const int8_t *__restrict__ tag, int *__re
     list[atomicAdd(count, 1)] = (int)r;
 }
 
+#include "pressure_aux.h"
+
 }  // namespace
 
 // ====================================================================== host
@@ -1754,6 +1756,14 @@ struct rbf_solver {
     double h_bound = 0.0;
     Lat lat{};
     PKry pk{};
+    // two-level auxiliary-lattice preconditioner with FGMRES (general nodes)
+    bool aux_on = false;
+    int aux_K = 0;             // cells per side of the auxiliary lattice
+    AuxOps<double> ax64{};
+    AuxOps<float> ax32{};
+    FgDev<double> fg64{};
+    FgDev<float> fg32{};
+    float *p_w32 = nullptr;    // FP32 Poisson weights (mixed precision)
     // pinned host buffers
     int *hflag = nullptr;
     double *hred = nullptr;
@@ -2278,8 +2288,11 @@ rbf_status hbicgstab(rbf_solver *S, EllM A, const double *b, double *x, double t
 }
 
 // Pressure solve on the row-scaled bordered system (x: guess in, solution out).
+rbf_status aux_solve(rbf_solver *S, EllM A, const double *b, double *x, rbf_solve_stats *stats);
+
 rbf_status poisson_solve(rbf_solver *S, const double *b, double *x, rbf_solve_stats *stats) {
     EllM P{S->idx_pp, S->p_w, nullptr, S->M, S->k, S->p_u1, S->p_vscale};
+    if (S->aux_on) return aux_solve(S, P, b, x, stats);
     if (S->pc_on) return pbicgstab(S, P, b, x, S->rtol_p, S->maxit_p, S->last_iters_p, stats);
     return bicgstab<1, false>(S, S->kp, P, b, x, S->rtol_p, S->maxit_p, S->last_iters_p, stats);
 }
@@ -2329,7 +2342,7 @@ bool is_lattice(const std::vector<double> &xp, const std::vector<int8_t> &tag, i
 
 // Set up the lattice preconditioner if the grid allows it (mode: RBF_PRECOND_*).
 rbf_status setup_lattice_pc(rbf_solver *S, const rbf_grid *g, int mode) {
-    if (mode == RBF_PRECOND_NONE) return RBF_OK;
+    if (mode == RBF_PRECOND_NONE || mode == RBF_PRECOND_AUX) return RBF_OK;
     const int64_t M = S->M;
     hipStream_t st = S->st;
     std::vector<double> hx(2 * M);
@@ -2451,6 +2464,344 @@ void launch_kt(int k, F f) {
 
 rbf_status copy_in(rbf_solver *S, void *dst, const void *src, size_t bytes) {
     RBF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, S->st));
+    return RBF_OK;
+}
+
+// ------------------------------------- auxiliary-lattice pressure path --
+// One application z = B^-1 (ys y) of the two-level preconditioner
+// (pressure_aux.h): smoother, residual, restriction, lattice transform
+// solve, interpolation, smoother.
+template <class T>
+void aux_apply(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, const T *y, const double *ys,
+               T *z) {
+    hipStream_t st = S->st;
+    const dim3 grid(nblocks_rows(P.m)), block(kThreads);
+    const int nq = S->lat.n * S->lat.n;
+    launch_kt(P.k, [&](auto KT) {
+        hipLaunchKernelGGL((k_aux_res<decltype(KT)::value, T>), grid, block, 0, st, P, y, ys, F.res,
+                           F.s.flag);
+    });
+    hipLaunchKernelGGL(k_aux_restrict<T>, dim3(rbf::blocks_for(nq, kThreads)), block, 0, st, P,
+                       S->lat, F.res, nq);
+    pc_apply(S);
+    hipLaunchKernelGGL(k_aux_interp<T>, grid, block, 0, st, P, S->lat, y, ys, F.t1, F.s.partZ);
+    launch_kt(P.k, [&](auto KT) {
+        hipLaunchKernelGGL((k_aux_post<decltype(KT)::value, T>), grid, block, 0, st, P, S->lat, y,
+                           ys, F.t1, F.s.partZ, z, F.s.partO);
+    });
+}
+
+// Flexible GMRES(kFgMax) on the pressure system with the two-level
+// preconditioner (x: guess in, solution out).  Every cycle starts from the
+// FP64 residual; with T = float the cycle is one step of iterative
+// refinement (see pressure_aux.h).  maxit counts Arnoldi steps
+// (preconditioner applications).
+template <class T>
+rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, const double *b,
+                      double *x, double tol, int maxit, int &last_iters, rbf_solve_stats *stats) {
+    hipStream_t st = S->st;
+    const int64_t m = A.n;
+    const int nb = nblocks_rows(m);
+    const dim3 grid(nb), block(kThreads), one(1), red(256);
+    const int mr = kFgMax;
+    const int mixed = std::is_same<T, float>::value ? 1 : 0;
+    FgScal &Fs = F.s;
+    S->lat.flag = Fs.flag;  // the transform stages exit with the Krylov flag
+    int total = 0, cycles = 0, f = 0;
+    bool first = true;
+    // Expected steps of the first cycle: the last solve's count (warm starts
+    // of consecutive steps need about as many).
+    int expect = S->p_nhist ? S->p_hist[(S->p_pos + 2) % 3] : 0;
+    auto status = [&]() -> rbf_status {
+        RBF_HIP(hipMemcpyAsync(S->hflag, Fs.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipMemcpyAsync(S->hflag + 2, Fs.stat, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        return RBF_OK;
+    };
+    rbf_status rc = RBF_OK;
+    for (;;) {
+        if (A.u1) hipLaunchKernelGGL((k_sum<1>), grid, block, 0, st, m, x, S->kp.partX);
+        launch_kt(A.k, [&](auto KT) {
+            hipLaunchKernelGGL((k_fg_init<decltype(KT)::value, T>), grid, block, 0, st, A, b, x,
+                               S->kp.partX, F.V, Fs.part);
+        });
+        hipLaunchKernelGGL(k_fg_reduce<false>, one, red, 0, st, Fs.part, nb, 2, Fs.h1, Fs.flag);
+        hipLaunchKernelGGL(k_fg_start, one, one, 0, st, Fs, Fs.h1, tol, mixed, first ? 1 : 0);
+        first = false;
+        if (total >= maxit) {  // only the convergence test of the iterate
+            if ((rc = status()) != RBF_OK) return rc;
+            f = S->hflag[0];
+            break;
+        }
+        int j = 0;
+        int batch = (cycles == 0 && expect > 0) ? std::max(2, std::min(mr, expect - 2)) : 6;
+        for (;;) {
+            const int stop = std::min(mr, j + batch);
+            for (; j < stop; ++j) {
+                const int64_t o = (int64_t)j * m;
+                aux_apply(S, P, F, F.V + o, Fs.vs + j, F.Z + o);
+                launch_kt(P.k, [&](auto KT) {
+                    hipLaunchKernelGGL((k_fg_av<decltype(KT)::value, T>), grid, block, 0, st, P,
+                                       A.u1, A.vscale, F, j);
+                });
+                hipLaunchKernelGGL(k_fg_reduce<true>, one, red, 0, st, Fs.part, nb, j + 1, Fs.h1,
+                                   Fs.flag);
+                hipLaunchKernelGGL((k_fg_gs<T, 1>), grid, block, 0, st, F, Fs.h1, m, j);
+                hipLaunchKernelGGL(k_fg_reduce<true>, one, red, 0, st, Fs.part, nb, j + 1, Fs.h2,
+                                   Fs.flag);
+                hipLaunchKernelGGL((k_fg_gs<T, 2>), grid, block, 0, st, F, Fs.h2, m, j);
+                hipLaunchKernelGGL(k_fg_reduce<true>, one, red, 0, st, Fs.part, nb, 1, Fs.hn2,
+                                   Fs.flag);
+                hipLaunchKernelGGL(k_fg_tail, one, one, 0, st, Fs, j, mr);
+            }
+            RBF_CHECK_LAUNCH();
+            if ((rc = status()) != RBF_OK) return rc;
+            f = S->hflag[0];
+            if (f != 0 || j >= mr) break;
+            // Next batch from the residual's rate over the last four steps.
+            const double *hs = reinterpret_cast<const double *>(S->hflag + 2);
+            batch = 4;
+            if (hs[0] > 0.0 && hs[1] > hs[0] && hs[2] > 0.0) {
+                const double rate = std::log(hs[0] / hs[1]) / 4.0;
+                const double need = std::log(hs[2] / hs[0]) / rate;
+                if (std::isfinite(need)) batch = std::max(1, std::min(12, (int)std::ceil(need)));
+            }
+        }
+        const int nstep = S->hflag[1];
+        total += nstep;
+        if (f == 1 || f == -1) break;
+        if (nstep <= 0) {  // no step was taken: nothing would change
+            f = 0;
+            break;
+        }
+        hipLaunchKernelGGL(k_fg_solve, one, one, 0, st, Fs, nstep, mr);
+        hipLaunchKernelGGL((k_fg_x<T>), grid, block, 0, st, F.Z, Fs.y, nstep, m, x);
+        ++cycles;
+    }
+    const double *hs = reinterpret_cast<const double *>(S->hflag + 2);
+    const double bb = hs[3], beta = hs[4];
+    if (stats) {
+        stats->iterations = total;
+        stats->converged = (f == 1);
+        stats->rel_residual = (bb > 0.0) ? beta / std::sqrt(bb) : beta;
+        stats->restarts = cycles;
+        stats->final_flag = f;
+    }
+    if (f == -1) {
+        rbf::set_error("FGMRES: non-finite value (after %d steps)", total);
+        rc = RBF_E_NAN;
+    } else if (f != 1) {
+        rbf::set_error("FGMRES: no convergence (%d of %d steps, %d cycles)", total, maxit, cycles);
+        rc = RBF_E_NOCONV;
+    }
+    last_iters = total;
+    if (f == 1) {
+        S->p_hist[S->p_pos] = total;
+        S->p_pos = (S->p_pos + 1) % 3;
+        S->p_nhist = std::min(3, S->p_nhist + 1);
+    }
+    return rc;
+}
+
+rbf_status aux_solve(rbf_solver *S, EllM A, const double *b, double *x, rbf_solve_stats *stats) {
+    if (S->mixed)
+        return fgmres_run<float>(S, S->ax32, S->fg32, A, b, x, S->rtol_p, S->maxit_p,
+                                 S->last_iters_p, stats);
+    return fgmres_run<double>(S, S->ax64, S->fg64, A, b, x, S->rtol_p, S->maxit_p,
+                              S->last_iters_p, stats);
+}
+
+template <class T>
+rbf_status alloc_fg(rbf_solver *S, FgDev<T> &F, int64_t M) {
+    const int mr = kFgMax;
+    ALLOC(F.V, (int64_t)(mr + 1) * M);
+    ALLOC(F.Z, (int64_t)mr * M);
+    ALLOC(F.res, M);
+    ALLOC(F.t1, M);
+    FgScal &s = F.s;
+    ALLOC(s.vs, mr + 1);
+    ALLOC(s.part, (int64_t)(kFgMax + 2) * kMaxBlocks);
+    ALLOC(s.h1, mr + 1);
+    ALLOC(s.h2, mr + 1);
+    ALLOC(s.hn2, 1);
+    ALLOC(s.H, (int64_t)(mr + 1) * mr);
+    ALLOC(s.cs, mr);
+    ALLOC(s.sn, mr);
+    ALLOC(s.g, mr + 1);
+    ALLOC(s.y, mr);
+    ALLOC(s.resh, mr + 1);
+    ALLOC(s.partZ, kMaxBlocks);
+    ALLOC(s.partO, kMaxBlocks);
+    ALLOC(s.one, 1);
+    const double unit = 1.0;
+    RBF_HIP(hipMemcpyAsync(s.one, &unit, sizeof(double), hipMemcpyHostToDevice, S->st));
+    ALLOC(s.flag, 16);  // flag, step, 5 status doubles (8-byte aligned at +2 ints)
+    s.step = s.flag + 1;
+    s.stat = reinterpret_cast<double *>(s.flag + 2);
+    RBF_HIP(hipMemsetAsync(s.flag, 0, 16 * sizeof(int), S->st));
+    return RBF_OK;
+}
+
+// Set up the two-level auxiliary-lattice preconditioner when the P-nodes'
+// bounding box is a square (mode: RBF_PRECOND_*; AUTO uses it when the
+// lattice preconditioner does not apply).
+rbf_status setup_aux_pc(rbf_solver *S, const rbf_grid *g, int mode) {
+    if (mode == RBF_PRECOND_NONE || mode == RBF_PRECOND_LATTICE || S->pc_on) return RBF_OK;
+    const int64_t M = S->M;
+    hipStream_t st = S->st;
+    std::vector<double> hx(2 * M);
+    std::vector<int8_t> ht(M);
+    RBF_HIP(hipMemcpyAsync(hx.data(), g->xp, 2 * M * sizeof(double), hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipMemcpyAsync(ht.data(), g->p_tag, M, hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    for (int64_t v = 0; v < M; ++v) {
+        x0 = std::min(x0, hx[v]);
+        x1 = std::max(x1, hx[v]);
+        y0 = std::min(y0, hx[M + v]);
+        y1 = std::max(y1, hx[M + v]);
+    }
+    const double side = std::max(x1 - x0, y1 - y0);
+    const bool square = side > 0.0 && std::fabs((x1 - x0) - (y1 - y0)) <= 1e-9 * side;
+    // About two node spacings per lattice cell (M ~ 1.15 K^2 nodes on a
+    // near-equilateral set of spacing 1/K: Ka ~ K / 2).
+    int Ka = (int)std::llround(0.465 * std::sqrt((double)M));
+    Ka = std::max(4, std::min(Ka, 64 * kTriChunk + 1));
+    if (!square || M < 64) {
+        RBF_ARG(mode != RBF_PRECOND_AUX,
+                "rbf_solver_create: RBF_PRECOND_AUX needs P-nodes whose bounding box is a square");
+        return RBF_OK;
+    }
+    const int n = Ka - 1, K1 = Ka + 1;
+    const double h = side / Ka;
+    // Cells and bilinear coordinates of every node; restriction lists of the
+    // interior lattice points from the interior nodes.
+    std::vector<int> cell(M);
+    std::vector<double> fx(M), fy(M);
+    std::vector<int> cnt((size_t)n * n + 1, 0);
+    auto corner_q = [&](int i, int j) { return (i >= 1 && i <= Ka - 1 && j >= 1 && j <= Ka - 1) ? (i - 1) * n + (j - 1) : -1; };
+    for (int64_t v = 0; v < M; ++v) {
+        const double sx = (hx[v] - x0) / h, sy = (hx[M + v] - y0) / h;
+        const int i0 = std::min(std::max((int)std::floor(sx), 0), Ka - 1);
+        const int j0 = std::min(std::max((int)std::floor(sy), 0), Ka - 1);
+        cell[v] = j0 * K1 + i0;
+        fx[v] = std::min(std::max(sx - i0, 0.0), 1.0);
+        fy[v] = std::min(std::max(sy - j0, 0.0), 1.0);
+        if (ht[v] != 0) continue;
+        for (int c = 0; c < 4; ++c) {
+            const int q = corner_q(i0 + (c & 1), j0 + (c >> 1));
+            if (q >= 0) ++cnt[q + 1];
+        }
+    }
+    for (size_t q = 0; q < (size_t)n * n; ++q) cnt[q + 1] += cnt[q];
+    std::vector<int> rptr(cnt), rcol(cnt.back());
+    std::vector<double> rval(cnt.back()), wsum((size_t)n * n, 0.0);
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t v = 0; v < M; ++v) {  // node order within each list
+        if (ht[v] != 0) continue;
+        const int i0 = cell[v] % K1, j0 = cell[v] / K1;
+        for (int c = 0; c < 4; ++c) {
+            const int q = corner_q(i0 + (c & 1), j0 + (c >> 1));
+            if (q < 0) continue;
+            const double wx = (c & 1) ? fx[v] : 1.0 - fx[v], wy = (c >> 1) ? fy[v] : 1.0 - fy[v];
+            rcol[fill[q]] = (int)v;
+            rval[fill[q]] = wx * wy;
+            wsum[q] += wx * wy;
+            ++fill[q];
+        }
+    }
+    for (size_t q = 0; q < (size_t)n * n; ++q)
+        for (int e = rptr[q]; e < rptr[q + 1]; ++e) rval[e] = (wsum[q] > 0.0) ? rval[e] / wsum[q] : 0.0;
+    std::vector<double> Q, Qi, lam;
+    dct2_basis(n, Q, Qi, lam);
+    const size_t nn = (size_t)n * n;
+    const int nt = (n + 15) / 16;
+    Lat &L = S->lat;
+    L.ntiles = nt * nt;
+    L.f32 = S->mixed ? 1 : 0;
+    const size_t es = L.f32 ? sizeof(float) : sizeof(double);
+    int *dcell, *drptr, *drcol;
+    double *dfx, *dfy, *dlam, *dV, *drval;
+    void *dQ, *dQi;
+    ALLOC(dcell, M);
+    ALLOC(dfx, M);
+    ALLOC(dfy, M);
+    ALLOC(dlam, n);
+    ALLOC(dV, nn);
+    ALLOC(drptr, nn + 1);
+    ALLOC(drcol, std::max<size_t>(1, rcol.size()));
+    ALLOC(drval, std::max<size_t>(1, rval.size()));
+    rbf_status rc;
+    for (void **a : {&dQ, &dQi, &L.X, &L.T, &L.W})
+        if ((rc = dalloc(S, a, nn * es)) != RBF_OK) return rc;
+    ALLOC(L.mean, 1);
+    ALLOC(L.partW, n);
+    RBF_HIP(hipMemcpyAsync(dcell, cell.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(dfx, fx.data(), M * sizeof(double), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(dfy, fy.data(), M * sizeof(double), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(dlam, lam.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemsetAsync(dV, 0, nn * sizeof(double), st));
+    RBF_HIP(hipMemcpyAsync(drptr, rptr.data(), (nn + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+    if (!rcol.empty()) {
+        RBF_HIP(hipMemcpyAsync(drcol, rcol.data(), rcol.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        RBF_HIP(hipMemcpyAsync(drval, rval.data(), rval.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    std::vector<float> Qf, Qif;
+    const void *hQ = Q.data(), *hQi = Qi.data();
+    if (L.f32) {
+        Qf.assign(Q.begin(), Q.end());
+        Qif.assign(Qi.begin(), Qi.end());
+        hQ = Qf.data();
+        hQi = Qif.data();
+    }
+    RBF_HIP(hipMemcpyAsync(dQ, hQ, nn * es, hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemcpyAsync(dQi, hQi, nn * es, hipMemcpyHostToDevice, st));
+    RBF_HIP(hipMemsetAsync(L.X, 0, nn * es, st));
+    L.K = Ka;
+    L.n = n;
+    L.h = h;
+    L.c = S->p_vscale;
+    L.rs = S->p_rowscale;
+    L.cell = dcell;
+    L.fx = dfx;
+    L.fy = dfy;
+    L.Q = dQ;
+    L.Qi = dQi;
+    L.lam = dlam;
+    L.V = dV;
+    // Row data of the smoother (FP64), and FP32 copies for mixed precision.
+    double *ddinv, *dsinv;
+    ALLOC(ddinv, M);
+    ALLOC(dsinv, M);
+    hipLaunchKernelGGL(k_aux_rows, dim3(rbf::blocks_for(M, 256)), dim3(256), 0, st, M, S->k,
+                       S->p_w, S->p_rowscale, ddinv, dsinv);
+    RBF_CHECK_LAUNCH();
+    S->ax64 = AuxOps<double>{S->idx_pp, S->p_w, ddinv, dsinv, drptr, drcol, drval, M, S->k};
+    if (S->mixed) {
+        float *w32, *dinv32, *sinv32, *rval32;
+        const int64_t nw = (int64_t)S->k * M;
+        ALLOC(w32, nw);
+        ALLOC(dinv32, M);
+        ALLOC(sinv32, M);
+        ALLOC(rval32, std::max<size_t>(1, rval.size()));
+        const dim3 gc(1024), bc(256);
+        hipLaunchKernelGGL(k_aux_to_f32, gc, bc, 0, st, nw, S->p_w, w32);
+        hipLaunchKernelGGL(k_aux_to_f32, gc, bc, 0, st, M, ddinv, dinv32);
+        hipLaunchKernelGGL(k_aux_to_f32, gc, bc, 0, st, M, dsinv, sinv32);
+        if (!rval.empty())
+            hipLaunchKernelGGL(k_aux_to_f32, gc, bc, 0, st, (int64_t)rval.size(), drval, rval32);
+        RBF_CHECK_LAUNCH();
+        S->p_w32 = w32;
+        S->ax32 = AuxOps<float>{S->idx_pp, w32, dinv32, sinv32, drptr, drcol, rval32, M, S->k};
+        if ((rc = alloc_fg(S, S->fg32, M)) != RBF_OK) return rc;
+        L.flag = S->fg32.s.flag;
+    } else {
+        if ((rc = alloc_fg(S, S->fg64, M)) != RBF_OK) return rc;
+        L.flag = S->fg64.s.flag;
+    }
+    RBF_HIP(hipStreamSynchronize(st));
+    S->aux_K = Ka;
+    S->aux_on = true;
     return RBF_OK;
 }
 
@@ -2675,7 +3026,7 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
         ALLOC(H.iters, kHR);
     }
     if ((rc = alloc_krylov(S, S->kp, 1, M, S->maxit_p)) != RBF_OK) return rc;
-    RBF_HIP(hipHostMalloc((void **)&S->hflag, 4 * kMaxNR * sizeof(int), hipHostMallocDefault));
+    RBF_HIP(hipHostMalloc((void **)&S->hflag, 64 * sizeof(int), hipHostMallocDefault));
     RBF_HIP(hipHostMalloc((void **)&S->hred, (2 * kMaxNR * kMaxBlocks + kMaxNR) * sizeof(double),
                           hipHostMallocDefault));
 
@@ -2749,7 +3100,9 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     S->n_interior_p = ni;
     S->p_vscale = ((double)ni / su) / (double)M;
     // The wall list order from atomics is irrelevant: rows are independent.
-    return setup_lattice_pc(S, g, prm->precond);
+    rc = setup_lattice_pc(S, g, prm->precond);
+    if (rc != RBF_OK) return rc;
+    return setup_aux_pc(S, g, prm->precond);
 }
 
 rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
@@ -2891,7 +3244,7 @@ extern "C" rbf_status rbf_solver_create(rbf_solver **out, const rbf_grid *grid, 
     RBF_ARG(prm->precision == RBF_PRECISION_FP64 || prm->precision == RBF_PRECISION_MIXED,
             "rbf_solver_create: unknown precision %d", prm->precision);
     RBF_ARG(prm->precond == RBF_PRECOND_AUTO || prm->precond == RBF_PRECOND_NONE ||
-                prm->precond == RBF_PRECOND_LATTICE,
+                prm->precond == RBF_PRECOND_LATTICE || prm->precond == RBF_PRECOND_AUX,
             "rbf_solver_create: unknown precond %d", prm->precond);
     rbf_solver *S = new rbf_solver();
     S->st = rbf::as_stream(st);
@@ -3029,7 +3382,18 @@ extern "C" rbf_status rbf_solve_pressure(rbf_solver *S, const double *rhs, doubl
 extern "C" rbf_status rbf_solver_apply_precond(rbf_solver *S, const double *y, double *z) {
     rbf::clear_error();
     RBF_ARG(S && y && z, "rbf_solver_apply_precond: NULL argument");
-    RBF_ARG(S->pc_on, "rbf_solver_apply_precond: the solver has no lattice preconditioner");
+    if (S->aux_on) {
+        RBF_ARG(!S->mixed, "rbf_solver_apply_precond: the auxiliary-lattice preconditioner of "
+                           "a mixed-precision solver runs in FP32 inside its solve only");
+        FgDev<double> &F = S->fg64;
+        RBF_HIP(hipMemsetAsync(F.s.flag, 0, sizeof(int), S->st));
+        S->lat.flag = F.s.flag;
+        aux_apply<double>(S, S->ax64, F, y, F.s.one, z);
+        RBF_CHECK_LAUNCH();
+        RBF_HIP(hipStreamSynchronize(S->st));
+        return RBF_OK;
+    }
+    RBF_ARG(S->pc_on, "rbf_solver_apply_precond: the solver has no pressure preconditioner");
     hipStream_t st = S->st;
     const int64_t m = S->M;
     const int nb = nblocks_rows(m);
@@ -3090,6 +3454,8 @@ extern "C" rbf_status rbf_solver_query(rbf_solver *S, rbf_solver_info *info) {
     info->viscous_jacobi = S->h_jacobi ? 1 : 0;
     info->lattice_precond = S->pc_on ? 1 : 0;
     info->jacobi_bound = S->h_bound;
+    info->aux_precond = S->aux_on ? 1 : 0;
+    info->aux_cells = S->aux_K;
     return RBF_OK;
 }
 

@@ -550,7 +550,8 @@ def test_lattice_preconditioner_matches_its_definition(P, gpu, K, precision, tol
 
 def test_lattice_preconditioner_needs_a_lattice(P, gpu):
     """A P-node moved out of its lattice cell: 'lattice' is refused with
-    RBF_E_ARG, 'auto' falls back to the unpreconditioned iteration."""
+    RBF_E_ARG, 'auto' falls back to the auxiliary-lattice preconditioner
+    (the nodes still fill a square)."""
     _say("lattice detection")
     nd = ri.cavity_nodes(12, 0.3, 0)
     v = 5 * 13 + 6
@@ -562,6 +563,7 @@ def test_lattice_preconditioner_needs_a_lattice(P, gpu):
         P.Solver(grid, ops, to_dev(u_bc, gpu), to_dev(v_bc, gpu), 100.0, 1e-3, precond="lattice")
     assert ei.value.status == -1
     S = P.Solver(grid, ops, to_dev(u_bc, gpu), to_dev(v_bc, gpu), 100.0, 1e-3, precond="auto")
+    assert not S.info()["lattice_precond"] and S.info()["aux_precond"]
     orc = ocav.CavityOracle(nd, u_bc, v_bc, 100.0, 1e-3)
     rhs = ri.random_vector(nd.n_p, 7)
     rhs[nd.p_tag != 0] = 0.0
@@ -608,14 +610,14 @@ def test_cavity_parity_unpreconditioned(P, gpu):
 
 
 def test_cavity_parity_near_equilateral_nodes(P, gpu):
-    """A cavity on a near-equilateral triangulation (hexagonal rows, Delaunay
-    edges; not a lattice, so the pressure iteration runs without the lattice
-    preconditioner): 60 steps at Re = 1e3, dt = 1e-3, u, v, p, p~ within
-    1e-10 of the oracle."""
+    """A cavity on the jittered near-equilateral triangulation (node kind 2;
+    not a lattice, so the pressure iteration runs FGMRES with the
+    auxiliary-lattice preconditioner): 60 steps at Re = 1e3, dt = 1e-3, u, v,
+    p, p~ within 1e-10 of the oracle."""
     _say("cavity parity, near-equilateral nodes K=20")
-    nd = ri.hex_cavity_nodes(20)
+    nd = ri.hex_cavity_nodes(20, 0.3, 0)
     S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 1000.0, 1e-3)
-    assert not S.info()["lattice_precond"]
+    assert not S.info()["lattice_precond"] and S.info()["aux_precond"]
     orc = ocav.CavityOracle(nd, u_bc, v_bc, 1000.0, 1e-3)
     s0 = orc.initial_state()
     st = S.new_state(to_dev(s0.u, gpu), to_dev(s0.v, gpu))
@@ -628,13 +630,14 @@ def test_cavity_parity_near_equilateral_nodes(P, gpu):
 
 
 def test_long_run_on_near_equilateral_nodes(P, gpu):
-    """400 steps at the bench's Re = 1e4 and dt = 2e-4 on a near-equilateral
-    K = 60 triangulation (stable there, unlike the right-triangle lattice):
+    """400 steps at the bench's Re = 1e4 and dt = 2e-4 on the jittered
+    near-equilateral K = 60 triangulation (stable there, unlike the
+    right-triangle lattice):
     the fields follow the oracle every 100 steps and the run stays bounded
     (maximum speed, CFL and interior divergence from rbf_solver_diagnostics).
     Observed: fields within 4e-11 of the oracle at every check."""
     _say("long run, near-equilateral nodes K=60")
-    nd = ri.hex_cavity_nodes(60)
+    nd = ri.hex_cavity_nodes(60, 0.3, 0)
     S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 1e4, 2e-4)
     orc = ocav.CavityOracle(nd, u_bc, v_bc, 1e4, 2e-4)
     s0 = orc.initial_state()
