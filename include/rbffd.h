@@ -125,6 +125,22 @@ rbf_status rbf_knn(const double *xq, int64_t nq, const double *xs, int64_t ns, i
                    int32_t *idx, rbf_stream st);
 
 /*
+ * rbf_knn_noalloc -- rbf_knn for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as rbf_knn; the cell grid
+ * lives in a fixed per-device scratch array of 64 MiB (held by each device
+ * the library runs on until the process ends), so no allocation or
+ * deallocation happens in the call.  Capacity: about 30 bytes per source
+ * node, i.e. at most about 2.2 million sources; larger ns is refused with
+ * RBF_E_ARG (message naming the limit) before any search.  Every call on a
+ * device shares that device's array: calls that overlap on one GPU (two
+ * host threads, or two streams) race and must be serialised by the caller.
+ * Synchronises the stream twice, like rbf_knn.
+ */
+rbf_status rbf_knn_noalloc(const double *xq, int64_t nq, const double *xs, int64_t ns, int32_t k,
+                           int32_t *idx, rbf_stream st);
+
+/*
  * rbf_assemble_weights -- local PHS+poly RBF-FD weights (Sec. 2.1, eqs. (3)-(9)).
  *
  * For each query node r, solves the augmented saddle-point system

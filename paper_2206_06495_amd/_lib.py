@@ -23,7 +23,7 @@ OP_ID, OP_DX, OP_DY, OP_LAP = 1, 2, 4, 8
 FORCE_SMALL_STENCIL = 0x80000000
 
 EXPORTED = [
-    "rbf_last_error", "rbf_abi_version", "rbf_build_nodes", "rbf_knn",
+    "rbf_last_error", "rbf_abi_version", "rbf_build_nodes", "rbf_knn", "rbf_knn_noalloc",
     "rbf_assemble_weights", "rbf_ell_apply", "rbf_cast_f32", "rbf_ell_transpose",
     "rbf_ell_transpose_weights", "rbf_ell_apply_transpose", "rbf_solver_create",
     "rbf_step", "rbf_step_batch", "rbf_solve_pressure", "rbf_solver_apply_precond", "rbf_solver_profile", "rbf_solver_query",
@@ -106,6 +106,9 @@ def _load():
     lib.rbf_knn.restype = S
     lib.rbf_knn.argtypes = [c_void_p, ctypes.c_int64, c_void_p, ctypes.c_int64, ctypes.c_int32,
                             c_void_p, c_void_p]
+    lib.rbf_knn_noalloc.restype = S
+    lib.rbf_knn_noalloc.argtypes = [c_void_p, ctypes.c_int64, c_void_p, ctypes.c_int64,
+                                    ctypes.c_int32, c_void_p, c_void_p]
     lib.rbf_assemble_weights.restype = S
     lib.rbf_assemble_weights.argtypes = [c_void_p, ctypes.c_int64, c_void_p, ctypes.c_int64,
                                          c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 
@@ -339,3 +340,65 @@ extern "C" rbf_status rbf_knn(const double *xq, int64_t nq, const double *xs, in
     return rc;
 }
 
+// ------------------------------------------------------ no-allocation form --
+// A fixed per-device scratch array for callers that cannot allocate device
+// memory.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is taken once per device with
+// hipGetSymbolAddress and only that address is used.
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with that device current).
+rbf_status scratch_address(char **out) {
+    int dev = -1;
+    RBF_HIP(hipGetDevice(&dev));
+    RBF_ARG(dev >= 0 && dev < kMaxDevices, "rbf_knn_noalloc: device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        RBF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        RBF_ARG(p != nullptr, "rbf_knn_noalloc: no device address for the scratch array");
+        g_scratch_addr[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return RBF_OK;
+}
+
+}  // namespace
+
+extern "C" rbf_status rbf_knn_noalloc(const double *xq, int64_t nq, const double *xs, int64_t ns,
+                                      int32_t k, int32_t *idx, rbf_stream st_) {
+    rbf::clear_error();
+    rbf_status rc = knn_check_args(xq, nq, xs, ns, k, idx);
+    if (rc != RBF_OK || nq == 0) return rc;
+    const size_t part_bytes = align256(2 * kBboxBlocks * 5 * sizeof(double));
+    // The grid has at most ns/2 + 8193 cells (cell edge >= sqrt(2 area/ns)
+    // and >= the longer box side / 4096), so this bound needs no device work.
+    RBF_ARG(part_bytes + grid_bytes(ns, ns / 2 + 8194) <= kScratchBytes,
+            "rbf_knn_noalloc: %lld sources exceed the %zu-byte scratch array (at most about "
+            "%lld sources)",
+            (long long)ns, kScratchBytes,
+            (long long)((kScratchBytes - part_bytes - 8194 * 12 - 2048) / 30));
+    char *base = nullptr;
+    rc = scratch_address(&base);
+    if (rc != RBF_OK) return rc;
+    hipStream_t st = rbf::as_stream(st_);
+    KnnScratch s{};
+    s.part = reinterpret_cast<double *>(base);
+    Grid g;
+    int64_t ncell = 0;
+    rc = knn_grid(xq, nq, xs, ns, s.part, st, g, ncell);
+    if (rc != RBF_OK) return rc;
+    RBF_ARG(part_bytes + grid_bytes(ns, ncell) <= kScratchBytes,
+            "rbf_knn_noalloc: cell grid of %lld cells exceeds the scratch array",
+            (long long)ncell);
+    carve_grid(base + part_bytes, ns, ncell, s);
+    return knn_search(xq, nq, xs, ns, k, idx, st, g, ncell, s);
+}
