@@ -2,38 +2,38 @@
 
 Workload (one JSON line on stdout):
   * step throughput: lid-driven cavity, Re = 1e4, dt = 2e-4, h = 1/400 on the
-    paper's staggered layout (P on triangulation vertices, V on edge
-    midpoints: N = 480,800, M = 160,801), 28-point PHS r^7 + cubic stencils,
-    FP64.  Setup (stencils, weights, system matrices) is timed separately;
-    `warmup` steps run untimed, then `steps` steps are timed.  value =
-    (N + M) * steps / seconds (node-steps/s).  The run restarts from the
-    rest state every `segment` steps (the restore is a device copy inside the
-    timed region): on this jittered node set the scheme diverges after about
-    490 steps from rest (near-wall modes of the approximate projection), so
-    longer runs are made of segments of the same flow.
+    paper's staggered layout over a seed-jittered near-equilateral
+    triangulation (node kind 2: P on the vertices, V on the edge midpoints,
+    N = 555,955, M = 185,894), 28-point PHS r^7 + cubic stencils, FP64,
+    pressure by flexible GMRES with the two-level auxiliary-lattice
+    preconditioner.  Setup (stencils, weights, system matrices) is timed
+    separately; `warmup` steps run untimed, then `steps` steps are timed from
+    the state the warm-up left.  value = (N + M) * steps / seconds
+    (node-steps/s).
+  * roofline of the dominant kernel of the step (the longest of the sampled
+    pressure-solve kernels: the FGMRES product k_fg_av, the smoothing product
+    k_aux_post, the first Gram-Schmidt update k_fg_gs<1>, the auxiliary
+    lattice transform k_pc_gemm<0>), its average duration sampled with the
+    launch's own start/end stamps on the solver's stream during the timed
+    steps, against its algorithmic bytes per launch.
+  * mixed: the same steps with FP32 restart cycles inside FP64 iterative
+    refinement, and the relative difference of the fields from the FP64 run.
+  * lattice: the right-triangle lattice cavity (node kind 0) of the same size
+    with the lattice fast-Poisson preconditioner and BiCGSTAB, 100 steps
+    (context: that layout diverges after about 490 steps from rest).
+  * batch: `batch` independent near-equilateral cavities, N uniform in
+    [5000, 60000] V-nodes and Re log-uniform in [100, 5000] (dt = 0.08 h),
+    each solver on its own stream, advanced `batch_steps` steps by
+    rbf_step_batch on one host thread and on `batch_threads` threads, from
+    the same states; aggregate node-steps/s and bit-identity of the two.
   * operator bench: 10^6 V + 10^6 P jittered square nodes, weights for VV
     {D_x, D_y, Lap} and PV {I}, then `spmv_reps` applications of each operator
     in FP64 and FP32-stored ELL, timed with HIP events; achieved GB/s from the
     algorithmic bytes; truncation error against closed-form derivatives of
     sin(kx)cos(ky), k = 2 pi {4, 16, 64}.
-  * roofline of the dominant kernel of the step: the FP64 MFMA transform
-    k_pc_gemm<0> of the lattice preconditioner (2 n^3 flops per launch,
-    n = K - 1), its average duration sampled with the launch's own start/end
-    stamps on the solver's stream during the timed steps; the pressure SpMV
-    k_pc_av (HBM bytes per launch) is reported beside it.
-  * mixed: the same steps with FP32 preconditioner arrays, and the relative
-    difference of the fields from the FP64 run.
-  * batch: `batch` independent cavities, N uniform in [5000, 60000] V-nodes
-    and Re log-uniform in [100, 5000] (dt = 0.08 h), each solver on its own
-    stream, advanced `batch_steps` steps by rbf_step_batch on one host thread
-    (one instance after another) and on `batch_threads` threads (concurrent),
-    from the same states; aggregate node-steps/s of both and whether the
-    fields agree bit for bit.
-  * hex: the same Re and dt on a near-equilateral triangulation at
-    h = 1/100 (no lattice, so no lattice preconditioner): the cost of the
-    general path.
-  * cpu_baseline: the CPU oracle (SciPy sparse LU solves) on a bounded
-    sample: the same cavity at h = 1/200.
+  * cpu_baseline: the CPU oracle (SciPy sparse LU solves, as the paper's
+    factor-once scheme) on the headline workload itself, a bounded number
+    of steps after an untimed set-up.
 """
 import argparse
 import json
@@ -51,13 +51,11 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP64_VALU_PEAK_TFLOPS = 78.6
 
-# Traffic beyond L2 per launch at K=400 from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE, scaled by the same counters on a plain 256 MiB copy
-# (profiles/k_pc_gemm_cavity_K400_pmc.md): k_pc_gemm<0> and the pressure
-# SpMV k_pc_av<28,0>.  Set to None when the kernel changes until it is
-# measured again.
-GEMM_TRAFFIC_BYTES = 21.96e6
-SPMV_TRAFFIC_BYTES = 59.95e6
+# HBM traffic per launch of the roofline kernels at the headline workload
+# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, scaled by the same counters
+# on a plain 256 MiB copy; None until measured for the current kernels.
+TRAFFIC_BYTES = {"k_fg_av": None, "k_aux_post": None, "k_fg_gs<1>": None,
+                 "k_pc_gemm<0>": None}
 
 
 def parse():
@@ -65,8 +63,6 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--segment", type=int, default=400,
-                    help="steps from rest after which the state is restored to rest")
     ap.add_argument("--K", type=int, default=400, help="cavity cells per side (h = 1/K)")
     ap.add_argument("--re", type=float, default=1e4)
     ap.add_argument("--dt", type=float, default=2e-4)
@@ -75,15 +71,13 @@ def parse():
     ap.add_argument("--spmv-K", type=int, default=1000)
     ap.add_argument("--spmv-reps", type=int, default=1000)
     ap.add_argument("--no-spmv", action="store_true")
-    ap.add_argument("--no-hex", action="store_true",
-                    help="skip the near-equilateral (non-lattice) cavity leg")
-    ap.add_argument("--hex-K", type=int, default=100)
-    ap.add_argument("--hex-steps", type=int, default=20)
+    ap.add_argument("--no-lattice", action="store_true",
+                    help="skip the right-triangle lattice cavity leg")
+    ap.add_argument("--lattice-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the mixed-precision run (FP32 preconditioner transforms)")
-    ap.add_argument("--cpu-K", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+                    help="skip the mixed-precision run (FP32 cycles in FP64 refinement)")
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--prof-every", type=int, default=25)
     ap.add_argument("--rtol-p", type=float, default=1e-12)
     ap.add_argument("--rtol-h", type=float, default=1e-13)
@@ -105,9 +99,12 @@ def dev_tensor(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-def cavity_setup(P, args, dev, precision="fp64"):
+def cavity_setup(P, args, dev, precision="fp64", kind=2, precond="auto"):
+    """Nodes (rbf_build_nodes `kind`), stencils, weights and the solver, on
+    the device; returns the solver, a rest state, the nodes and the set-up
+    time."""
     import torch
-    nodes = P.build_nodes(0, args.K, args.jitter, args.seed)
+    nodes = P.build_nodes(kind, args.K, args.jitter, args.seed)
     t0 = time.perf_counter()
     g = {k: dev_tensor(v, dev) for k, v in nodes.items()}
     ops = {"k": 28}
@@ -125,7 +122,7 @@ def cavity_setup(P, args, dev, precision="fp64"):
     u_bc = np.where(vt == 2, 1.0, 0.0)
     S = P.Solver(g, ops, dev_tensor(u_bc, dev), dev_tensor(np.zeros_like(u_bc), dev),
                  args.re, args.dt, rtol_h=args.rtol_h, rtol_p=args.rtol_p, maxit_h=2000,
-                 maxit_p=200000, precision=precision)
+                 maxit_p=200000, precision=precision, precond=precond)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     del ops
@@ -134,35 +131,22 @@ def cavity_setup(P, args, dev, precision="fp64"):
 
 
 class Run:
-    """Steps of one solver in segments of `segment` steps from the rest
-    state; sums the statistics of its rbf_step calls."""
+    """Steps of one solver; sums the statistics of its rbf_step calls."""
 
-    def __init__(self, S, st, segment):
-        self.S, self.st, self.segment = S, st, segment
-        self.rest = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in st.items()}
+    def __init__(self, S, st):
+        self.S, self.st = S, st
         self.clear()
 
     def clear(self):
         self.poisson_iters = self.helmholtz_iters = 0
         self.last = None
-        self.restarts = 0
 
     def advance(self, n):
-        st = self.st
-        while n > 0:
-            if st["step"] >= self.segment:
-                for k, v in self.rest.items():
-                    if hasattr(v, "copy_"):
-                        st[k].copy_(v)
-                    else:
-                        st[k] = v
-                self.restarts += 1
-            k = min(n, self.segment - st["step"])
-            s = self.S.step(st, k)
+        if n > 0:
+            s = self.S.step(self.st, n)
             self.poisson_iters += s.poisson_iters
             self.helmholtz_iters += s.helmholtz_iters
             self.last = s
-            n -= k
         return self
 
 
@@ -274,9 +258,13 @@ def spmv_bench(P, args, dev):
 
 
 def cpu_baseline(args):
+    """The oracle on the headline workload (same nodes, Re, dt, stencils):
+    set-up (kNN, weights, SuperLU factorisations of both implicit matrices,
+    as the paper factors them once) untimed, then `cpu_steps` timed steps
+    (triangular solves and CSR products)."""
     import rbf_inputs as ri
     from oracle import cavity as ocav
-    nd = ri.cavity_nodes(args.cpu_K, args.jitter, args.seed)
+    nd = ri.hex_cavity_nodes(args.K, args.jitter, args.seed)
     u_bc, v_bc = ri.cavity_bc(nd.v_tag)
     t0 = time.perf_counter()
     orc = ocav.CavityOracle(nd, u_bc, v_bc, args.re, args.dt)
@@ -285,15 +273,21 @@ def cpu_baseline(args):
     t0 = time.perf_counter()
     s = orc.run(args.cpu_steps, s)
     el = time.perf_counter() - t0
+    try:
+        import threadpoolctl
+        blas = max((p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()), default=1)
+    except Exception:  # pragma: no cover
+        blas = None
     return {"value": (nd.n_v + nd.n_p) * args.cpu_steps / el, "unit": "node-steps/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"cavity h=1/{args.cpu_K} (N={nd.n_v}, M={nd.n_p}), {args.cpu_steps} steps "
-                      f"({el:.1f} s) after an untimed setup with SuperLU factorisations "
-                      f"({setup:.1f} s); same Re, dt and stencils as the GPU run. The timed "
-                      f"steps are SuperLU triangular solves and CSR products, single-threaded. "
-                      f"The oracle's cost per node grows with K, so this overstates its rate "
-                      f"at h=1/{args.K}",
-            "u_abs_max": float(np.abs(s.u).max())}
+            "cores": 1, "kind": "oracle", "host_cpu_count": os.cpu_count(),
+            "blas_threads_available": blas,
+            "sample": f"the headline cavity itself (h=1/{args.K}, N={nd.n_v}, M={nd.n_p}, "
+                      f"Re={args.re:g}, dt={args.dt:g}), {args.cpu_steps} steps from rest "
+                      f"({el:.1f} s) after an untimed set-up of {setup:.1f} s (stencils, "
+                      "weights, SuperLU factorisations).  The timed steps are SuperLU "
+                      "triangular solves and SciPy CSR products, both single-threaded, so one "
+                      "core does the work whatever the host has",
+            "setup_s": setup, "u_abs_max": float(np.abs(s.u).max())}
 
 
 def mixed_run(P, args, dev, st64, value64):
@@ -301,16 +295,14 @@ def mixed_run(P, args, dev, st64, value64):
     run after the same number of steps."""
     import torch
     S, st, _, setup_s = cavity_setup(P, args, dev, precision="mixed")
-    run = Run(S, st, args.segment)
+    run = Run(S, st)
     run.advance(args.warmup)
-    S.profile(args.prof_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run.clear()
     stats = run.advance(args.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    prof = S.profile(0)
     S.close()
     value = (S.N + S.M) * args.steps / el
     err = {}
@@ -318,16 +310,14 @@ def mixed_run(P, args, dev, st64, value64):
         a, b = st[key], st64[key]
         err[key] = float((a - b).abs().max() / b.abs().max())
     log(f"mixed: {value:.3e} node-steps/s, rel err vs FP64 {err}")
-    n = args.K - 1
-    gemm_ms = prof["gemm"][0]
     return {"value": value, "unit": "node-steps/s", "ms_per_step": el / args.steps * 1e3,
             "speedup_vs_fp64": value / value64,
-            "poisson_iters_per_step": stats.poisson_iters / max(1, args.steps),
+            "poisson_steps_per_step": stats.poisson_iters / max(1, args.steps),
             "rel_err_vs_fp64": err, "setup_s": setup_s,
-            "gemm_fp32_avg_us": gemm_ms * 1e3,
-            "gemm_fp32_tflops": (2.0 * n ** 3 / (gemm_ms * 1e-3) / 1e12) if gemm_ms > 0 else None,
-            "what": "FP32 lattice-preconditioner transforms (FP32 matrix cores); operators, "
-                    "residuals, Krylov iteration, weights and projection FP64"}
+            "what": "pressure: each FGMRES restart cycle is one iterative-refinement step "
+                    "(FP64 residual from FP64 weights; FP32 weights, vectors, smoother and "
+                    "lattice transforms inside, FP64 dots); weights, viscous solve, "
+                    "projection and tolerance FP64"}
 
 
 def batch_run(P, args, dev):
@@ -338,7 +328,7 @@ def batch_run(P, args, dev):
     t0 = time.perf_counter()
     for b in range(args.batch):
         n_target = rng.uniform(5000.0, 60000.0)
-        K = max(8, int(round((-2.0 + math.sqrt(4.0 + 12.0 * n_target)) / 6.0)))  # N = 3K^2 + 2K
+        K = max(8, int(round(math.sqrt(n_target / 3.47))))  # kind 2: N ~ 3.47 K^2
         re = math.exp(rng.uniform(math.log(100.0), math.log(5000.0)))
         s = torch.cuda.Stream()
         with torch.cuda.stream(s):
@@ -394,50 +384,47 @@ def batch_run(P, args, dev):
             "speedup": el_s / el_c, "bit_identical": bool(same),
             "failed": failed,
             "poisson_iters_per_step_mean": float(np.mean(its)),
-            "what": "independent lattice cavities, one stream each, rbf_step_batch"}
+            "what": "independent near-equilateral cavities (node kind 2), one stream each, "
+                    "rbf_step_batch"}
 
 
-def hex_run(P, args, dev):
-    """The general-triangulation path: the cavity on a near-equilateral
-    triangulation (hexagonal rows, Delaunay edges; stable where the lattice
-    is not) at the same Re and dt, which has no lattice preconditioner."""
+def lattice_run(P, args, dev):
+    """The right-triangle lattice cavity (node kind 0) of the same h with the
+    lattice fast-Poisson preconditioner and BiCGSTAB (context only: the
+    scheme is unstable on that layout beyond about 490 steps from rest)."""
     import torch
-    import rbf_inputs as ri
-    nd = ri.hex_cavity_nodes(args.hex_K)
-    g = {"xv": dev_tensor(nd.xv, dev), "xp": dev_tensor(nd.xp, dev),
-         "v_tag": dev_tensor(nd.v_tag, dev), "p_tag": dev_tensor(nd.p_tag, dev),
-         "p_normal": dev_tensor(nd.p_normal, dev)}
-    ops = {"k": 28}
-    for name, xq, xs, mask in (("vv", g["xv"], g["xv"], 14), ("pv", g["xp"], g["xv"], 6),
-                               ("pp", g["xp"], g["xp"], 14), ("vp", g["xv"], g["xp"], 6)):
-        idx = P.knn(xq, xs, 28)
-        w = P.assemble_weights(xq, xs, idx, 7, 3, mask)
-        ops["idx_" + name] = idx
-        ops[name + "_dx"] = w[0].contiguous()
-        ops[name + "_dy"] = w[1].contiguous()
-        if mask & 8:
-            ops[name + "_lap"] = w[2].contiguous()
-    u_bc = np.where(nd.v_tag == 2, 1.0, 0.0)
-    S = P.Solver(g, ops, dev_tensor(u_bc, dev), dev_tensor(np.zeros_like(u_bc), dev), args.re,
-                 args.dt, rtol_h=args.rtol_h, rtol_p=args.rtol_p, maxit_h=2000, maxit_p=200000)
-    st = S.new_state(dev_tensor(u_bc, dev), dev_tensor(np.zeros_like(u_bc), dev))
-    S.step(st, 5)
+    S, st, _, setup_s = cavity_setup(P, args, dev, kind=0, precond="lattice")
+    S.step(st, 10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s = S.step(st, args.hex_steps)
+    s = S.step(st, args.lattice_steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    out = {"value": (S.N + S.M) * args.hex_steps / el, "unit": "node-steps/s",
-           "ms_per_step": el / args.hex_steps * 1e3, "steps": args.hex_steps,
-           "poisson_iters_per_step": s.poisson_iters / args.hex_steps,
-           "lattice_precond": S.info()["lattice_precond"], "final_state": S.diagnostics(st),
-           "workload": f"cavity on a near-equilateral triangulation, h = 1/{args.hex_K} "
-                       f"(N={S.N} V + M={S.M} P), Re={args.re:g}, dt={args.dt:g}, "
-                       "unpreconditioned pressure iteration"}
+    out = {"value": (S.N + S.M) * args.lattice_steps / el, "unit": "node-steps/s",
+           "ms_per_step": el / args.lattice_steps * 1e3, "steps": args.lattice_steps,
+           "poisson_iters_per_step": s.poisson_iters / args.lattice_steps,
+           "final_state": S.diagnostics(st),
+           "workload": f"right-triangle lattice cavity h=1/{args.K} (N={S.N} V + M={S.M} P), "
+                       f"Re={args.re:g}, dt={args.dt:g}, steps 10-{10 + args.lattice_steps} "
+                       "from rest, BiCGSTAB with the lattice preconditioner"}
     S.close()
-    log(f"hex: {out['value']:.3e} node-steps/s, {out['poisson_iters_per_step']:.0f} pressure "
-        "iterations per step")
+    log(f"lattice: {out['value']:.3e} node-steps/s")
     return out
+
+
+def kernel_bytes(M, prof, steps_per_cycle):
+    """Algorithmic bytes per launch of the sampled pressure-solve kernels
+    (28-point rows: int32 index + FP64 weight per entry)."""
+    jbar = max(0.0, (steps_per_cycle - 1.0) / 2.0)  # mean Arnoldi index in a cycle
+    return {
+        # product (idx + w, z gathered once, w written) + dots with jbar + 1
+        # basis vectors
+        "k_fg_av": M * (28 * 12 + 8 + 8 + 8 * (jbar + 1)),
+        # idx + w, t1 gathered once, y, dinv, z written
+        "k_aux_post": M * (28 * 12 + 8 + 8 + 8 + 8),
+        # w read and written, jbar + 1 basis vectors read twice (update, dots)
+        "k_fg_gs<1>": M * (8 + 8 + 2 * 8 * (jbar + 1)),
+    }
 
 
 def main():
@@ -459,8 +446,10 @@ def main():
     log("cavity setup K =", args.K)
     S, st, nodes, setup_s = cavity_setup(P, args, dev)
     N, M = S.N, S.M
-    log(f"N={N} M={M} setup {setup_s:.2f}s; warmup {args.warmup} steps")
-    run = Run(S, st, args.segment)
+    info = S.info()
+    log(f"N={N} M={M} setup {setup_s:.2f}s (aux lattice {info['aux_cells']} cells); "
+        f"warmup {args.warmup} steps")
+    run = Run(S, st)
     run.advance(args.warmup)
     torch.cuda.synchronize()
     S.profile(args.prof_every)
@@ -475,65 +464,71 @@ def main():
     value = (N + M) * args.steps / el
     umax = float(st["u"].abs().max())
     diag = S.diagnostics(st)
-    log(f"{el:.3f}s  {value:.3e} node-steps/s  poisson iters/step "
-        f"{stats.poisson_iters / max(1, args.steps):.1f}  |u|max {umax:.3f}")
-    # Dominant kernel: k_pc_gemm, the n x n x n FP64 products of the
-    # preconditioner (n = K - 1); the first of the two per application is
-    # sampled with its own start/end stamps.
-    n = args.K - 1
-    gemm_ms, gemm_cnt = prof["gemm"]
-    gemm_flops = 2.0 * n ** 3
-    gemm_tf = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else None
-    # Pressure SpMV k_pc_av<28, 0>: idx + w (28 each), p^ gathered (once),
-    # rh read, v written.
-    spmv_ms, spmv_cnt = prof["spmv"]
-    spmv_bytes = M * (28 * (4 + 8) + 8 + 8 + 8)
-    spmv_gbs = spmv_bytes / (spmv_ms * 1e-3) / 1e9 if spmv_ms > 0 else None
+    steps_per_ts = stats.poisson_iters / max(1, args.steps)
+    cycles = stats.last.last_poisson.restarts + 1 if stats.last else 1
+    log(f"{el:.3f}s  {value:.3e} node-steps/s  pressure FGMRES steps per time step "
+        f"{steps_per_ts:.1f}  |u|max {umax:.3f}")
+    # Dominant kernel among the sampled ones (each runs once per FGMRES step).
+    names = {"spmv": "k_fg_av", "smooth": "k_aux_post", "gs": "k_fg_gs<1>",
+             "gemm": "k_pc_gemm<0>"}
+    nbytes = kernel_bytes(M, prof, steps_per_ts / max(1, cycles))
+    kern = {}
+    for slot, name in names.items():
+        ms, cnt = prof[slot]
+        if cnt:
+            kern[name] = {"avg_us": ms * 1e3, "samples": cnt}
+            if name in nbytes:
+                kern[name]["bytes_per_launch"] = nbytes[name]
+                kern[name]["GB/s"] = nbytes[name] / (ms * 1e-3) / 1e9
+    dom = max(kern, key=lambda k: kern[k]["avg_us"]) if kern else None
+    if dom == "k_pc_gemm<0>":
+        n = info["aux_cells"] - 1
+        flops = 2.0 * n ** 3
+        ach = flops / (kern[dom]["avg_us"] * 1e-6) / 1e12
+        roof = {"kernel": f"{dom} (auxiliary-lattice transform, {n}^3 FP64 product)",
+                "bound": "mfma", "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS, "traffic": None}
+    elif dom:
+        ach = kern[dom]["GB/s"]
+        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES.get(dom),
+                "avg_us": kern[dom]["avg_us"], "samples": kern[dom]["samples"],
+                "bytes_per_launch": kern[dom]["bytes_per_launch"]}
+    else:
+        roof = None
     out = {
         "metric": "node-steps/s + ELL SpMV HBM GB/s, mixed/batched vs FP64 at rel err 1e-8",
         "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"lid-driven cavity Re={args.re:g} dt={args.dt:g} h=1/{args.K} "
-                               f"(N={N} V + M={M} P nodes, jitter {args.jitter}h), "
-                               "28-point PHS r^7 + cubic, FP64 BiCGSTAB with the lattice "
-                               "fast-Poisson preconditioner",
+        "config": {"workload": f"lid-driven cavity Re={args.re:g} dt={args.dt:g} h=1/{args.K} on "
+                               f"the seed-jittered near-equilateral triangulation (node kind 2, "
+                               f"N={N} V + M={M} P nodes, jitter {args.jitter}h, seed "
+                               f"{args.seed}), 28-point PHS r^7 + cubic, FP64, pressure by "
+                               "FGMRES with the two-level auxiliary-lattice preconditioner",
                    "poisson_rtol": args.rtol_p, "helmholtz_rtol": args.rtol_h,
-                   "setup_s": setup_s,
-                   "poisson_iters_per_step": stats.poisson_iters / max(1, args.steps),
+                   "setup_s": setup_s, "aux_lattice_cells": info["aux_cells"],
+                   "poisson_fgmres_steps_per_step": steps_per_ts,
                    "helmholtz_iters_per_step": stats.helmholtz_iters / max(1, args.steps),
                    "last_poisson_rel_residual": stats.last.last_poisson.rel_residual
                    if stats.last else None,
-                   "segment": args.segment, "restores_in_timed_steps": stats.restarts,
-                   "final_state": diag,
-                   "u_abs_max": umax},
-        "roofline": {"kernel": f"k_pc_gemm<0> (preconditioner transform, FP64 MFMA, "
-                               f"{n}x{n}x{n})",
-                     "bound": "mfma", "achieved": gemm_tf, "peak": FP64_MFMA_PEAK_TFLOPS,
-                     "unit": "TFLOP/s",
-                     "frac": (gemm_tf / FP64_MFMA_PEAK_TFLOPS) if gemm_tf else None,
-                     "traffic": GEMM_TRAFFIC_BYTES, "avg_us": gemm_ms * 1e3,
-                     "samples": gemm_cnt, "flops_per_launch": gemm_flops},
-        "spmv_roofline": {"kernel": "k_pc_av<28,0> (pressure SpMV v = A p^)", "bound": "hbm",
-                          "achieved": spmv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": (spmv_gbs / HBM_PEAK_GBS) if spmv_gbs else None,
-                          "traffic": SPMV_TRAFFIC_BYTES, "avg_us": spmv_ms * 1e3,
-                          "samples": spmv_cnt,
-                          "bytes_per_launch": spmv_bytes},
+                   "final_state": diag, "u_abs_max": umax,
+                   "pressure_kernels": kern},
+        "roofline": roof,
     }
     S.close()
     if not args.no_mixed:
-        log("mixed precision: same workload, FP32 preconditioner transforms")
+        log("mixed precision: same workload, FP32 cycles inside FP64 refinement")
         out["mixed"] = mixed_run(P, args, dev, st, value)
     del st
     torch.cuda.empty_cache()
+    if not args.no_lattice:
+        log("right-triangle lattice cavity K =", args.K)
+        out["lattice"] = lattice_run(P, args, dev)
+        torch.cuda.empty_cache()
     if args.batch > 0:
         log("concurrent instances:", args.batch)
         out["batch"] = batch_run(P, args, dev)
-        torch.cuda.empty_cache()
-    if not args.no_hex:
-        log("near-equilateral cavity K =", args.hex_K)
-        out["hex"] = hex_run(P, args, dev)
         torch.cuda.empty_cache()
     if not args.no_spmv:
         log("operator bench K =", args.spmv_K)

@@ -443,13 +443,19 @@ rbf_status rbf_solver_apply_precond(rbf_solver *s, const double *y, double *z);
 
 /*
  * rbf_solver_profile -- sample kernel durations of the pressure solve on the
- * solver's stream: slot RBF_PROF_GEMM, the first transform of the lattice
- * preconditioner (k_pc_gemm<0>, an n x n x n FP64 product, n = K - 1); slot
- * RBF_PROF_SPMV, the Poisson SpMV v = A p^ (k_pc_av, or k_kry_a without the
- * lattice preconditioner).  A sampled launch goes through
- * hipExtLaunchKernelGGL with an event pair that records the kernel's own
- * start and end; the pairs are read at the solver's next stream
- * synchronisation (no extra synchronisation).
+ * solver's stream:
+ *   RBF_PROF_GEMM    the first transform of the lattice preconditioner or of
+ *                    the auxiliary lattice (k_pc_gemm<0>, an n x n x n FP64
+ *                    or FP32 product, n = cells per side - 1);
+ *   RBF_PROF_SPMV    the Krylov product with the Poisson matrix (k_pc_av with
+ *                    the lattice preconditioner, k_kry_a without one, k_fg_av
+ *                    in FGMRES: the product plus the first Gram-Schmidt dots);
+ *   RBF_PROF_SMOOTH  the post-smoothing product of the auxiliary-lattice
+ *                    preconditioner (k_aux_post);
+ *   RBF_PROF_GS      the first Gram-Schmidt update of FGMRES (k_fg_gs<1>).
+ * A sampled launch goes through hipExtLaunchKernelGGL with an event pair
+ * that records the kernel's own start and end; the pairs are read at the
+ * solver's next stream synchronisation (no extra synchronisation).
  * Returns in avg_ms[q] and count[q] (nullable host arrays of RBF_PROF_N) the
  * average duration per launch and the number of launches timed so far;
  * then, if sample_every >= 0, resets the counters and samples every
@@ -458,7 +464,9 @@ rbf_status rbf_solver_apply_precond(rbf_solver *s, const double *y, double *z);
  */
 #define RBF_PROF_GEMM 0
 #define RBF_PROF_SPMV 1
-#define RBF_PROF_N 2
+#define RBF_PROF_SMOOTH 2
+#define RBF_PROF_GS 3
+#define RBF_PROF_N 4
 rbf_status rbf_solver_profile(rbf_solver *s, int32_t sample_every, double *avg_ms,
                               int64_t *count);
 

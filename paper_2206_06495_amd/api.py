@@ -240,13 +240,13 @@ class Solver:
         return z
 
     def profile(self, sample_every=-1):
-        """Sampled kernel durations so far: {"gemm": (avg_ms, count),
-        "spmv": (avg_ms, count)}; with sample_every >= 0, reset and sample
-        every sample_every-th pressure iteration from now on."""
-        avg = (ctypes.c_double * 2)()
-        cnt = (ctypes.c_int64 * 2)()
+        """Sampled kernel durations so far: {"gemm", "spmv", "smooth", "gs"}, each
+        (avg_ms, count) (slots RBF_PROF_*); with sample_every >= 0, reset and
+        sample every sample_every-th pressure iteration from now on."""
+        avg = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int64 * 4)()
         check(lib.rbf_solver_profile(self._h, int(sample_every), avg, cnt))
-        return {"gemm": (avg[0], cnt[0]), "spmv": (avg[1], cnt[1])}
+        return {name: (avg[q], cnt[q]) for q, name in enumerate(("gemm", "spmv", "smooth", "gs"))}
 
     def info(self):
         """How the solves run: {"viscous_jacobi", "lattice_precond", "jacobi_bound",

@@ -87,22 +87,29 @@ struct FgDev {
     T *V;            // [(mr+1)][m]
     T *Z;            // [mr][m] preconditioned directions
     T *res, *t1;     // [m] preconditioner work
+    T *wd;           // [m] newest basis vector times the smoother diagonal W
     FgScal s;
 };
 
 // -------------------------------------------------------------- kernels --
-template <int KT, class T, class F>
+// Row r of A_s applied to the values f(j) at the stencil columns; KT > 0
+// fixes the width, its loads issued CH slots at a time (CH divides KT).
+template <int KT, int CH, class T, class F>
 __device__ __forceinline__ T aux_row(const AuxOps<T> &P, int64_t r, F f) {
     T acc = 0;
     if constexpr (KT > 0) {
-        int jj[KT];
-        T ww[KT];
+        static_assert(KT % CH == 0, "chunk must divide the stencil width");
 #pragma unroll
-        for (int q = 0; q < KT; ++q) jj[q] = rbf::ld_stream(P.idx + (int64_t)q * P.m + r);
+        for (int q0 = 0; q0 < KT; q0 += CH) {
+            int jj[CH];
+            T ww[CH];
 #pragma unroll
-        for (int q = 0; q < KT; ++q) ww[q] = rbf::ld_stream(P.w + (int64_t)q * P.m + r);
+            for (int q = 0; q < CH; ++q) jj[q] = rbf::ld_stream(P.idx + (int64_t)(q0 + q) * P.m + r);
 #pragma unroll
-        for (int q = 0; q < KT; ++q) acc = fma(ww[q], f(jj[q]), acc);
+            for (int q = 0; q < CH; ++q) ww[q] = rbf::ld_stream(P.w + (int64_t)(q0 + q) * P.m + r);
+#pragma unroll
+            for (int q = 0; q < CH; ++q) acc = fma(ww[q], f(jj[q]), acc);
+        }
     } else {
         for (int q = 0; q < P.k; ++q)
             acc = fma(rbf::ld_stream(P.w + (int64_t)q * P.m + r),
@@ -111,9 +118,11 @@ __device__ __forceinline__ T aux_row(const AuxOps<T> &P, int64_t r, F f) {
     return acc;
 }
 
-// Preconditioner stage 1: res = S^-1 (y - A_s W y), y scaled by *ys.
+// Preconditioner stage 1: res = S^-1 (y - A_s W y), y scaled by *ys; yd is
+// W y unscaled (one gathered value per neighbour).
 template <int KT, class T>
 __global__ void __launch_bounds__(kThreads) k_aux_res(AuxOps<T> P, const T *__restrict__ y,
+                                                       const T *__restrict__ yd,
                                                        const double *ys, T *__restrict__ res,
                                                        const int *flag) {
     if (*flag != 0) return;
@@ -122,16 +131,24 @@ __global__ void __launch_bounds__(kThreads) k_aux_res(AuxOps<T> P, const T *__re
         const int64_t r = row_of(it);
         if (r - threadIdx.x >= P.m) break;
         if (r < P.m) {
-            const T ax = aux_row<KT>(P, r, [&](int j) { return sc * y[j] * P.dinv[j]; });
-            res[r] = P.sinv[r] * (sc * y[r] - ax);
+            const T ax = aux_row<KT, (KT > 0 ? KT : 1)>(P, r, [&](int j) { return yd[j]; });
+            res[r] = P.sinv[r] * (sc * (y[r] - ax));
         }
     }
 }
 
+// yd = W y for an explicit input vector.
+template <class T>
+__global__ void k_aux_scale(AuxOps<T> P, const T *__restrict__ y, T *__restrict__ yd) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < P.m;
+         r += (int64_t)gridDim.x * blockDim.x)
+        yd[r] = y[r] * P.dinv[r];
+}
+
 // Stage 2: restriction to the interior lattice points, X(q) = sum rval res.
 template <class T>
-__global__ void __launch_bounds__(kThreads) k_aux_restrict(AuxOps<T> P, Lat L,
-                                                            const T *__restrict__ res, int nq) {
+__global__ void __launch_bounds__(64) k_aux_restrict(AuxOps<T> P, Lat L,
+                                                      const T *__restrict__ res, int nq) {
     if (*L.flag != 0) return;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq) return;
@@ -148,10 +165,10 @@ __device__ __forceinline__ double aux_lattice(const Lat &L, int i, int j) {
     return lat_load(L, L.X, (int64_t)(ci - 1) + (int64_t)(cj - 1) * L.n);
 }
 
-// Stage 3: t1 = W y + J e, and block sums of J e.
+// Stage 3: t1 = W y + J e (W y from yd), and block sums of J e.
 template <class T>
 __global__ void __launch_bounds__(kThreads) k_aux_interp(AuxOps<T> P, Lat L,
-                                                          const T *__restrict__ y,
+                                                          const T *__restrict__ yd,
                                                           const double *ys, T *__restrict__ t1,
                                                           double *partZ) {
     if (*L.flag != 0) return;
@@ -169,7 +186,7 @@ __global__ void __launch_bounds__(kThreads) k_aux_interp(AuxOps<T> P, Lat L,
                                            fx * aux_lattice(L, i0 + 1, j0)) +
                              fy * ((1.0 - fx) * aux_lattice(L, i0, j0 + 1) +
                                    fx * aux_lattice(L, i0 + 1, j0 + 1));
-            t1[r] = sc * y[r] * P.dinv[r] + (T)z;
+            t1[r] = sc * yd[r] + (T)z;
             acc[0] += z;
         }
     }
@@ -194,7 +211,7 @@ __global__ void __launch_bounds__(kThreads) k_aux_post(AuxOps<T> P, Lat L,
         const int64_t r = row_of(it);
         if (r - threadIdx.x >= P.m) break;
         if (r < P.m) {
-            const T at = aux_row<KT>(P, r, [&](int j) { return t1[j]; });
+            const T at = aux_row<KT, (KT > 0 ? KT : 1)>(P, r, [&](int j) { return t1[j]; });
             const T zr = t1[r] + (T)mu + P.dinv[r] * (sc * y[r] - at);
             z[r] = zr;
             acc[0] += (double)zr;
@@ -203,13 +220,14 @@ __global__ void __launch_bounds__(kThreads) k_aux_post(AuxOps<T> P, Lat L,
     store_partials<1>(acc, partO, gridDim.x);
 }
 
-// Cycle start: r = b - A x in FP64 (FP64 weights and border), V_0 = r;
-// block sums of ||r||^2 and ||b||^2 (rows 0 and 1 of part).
+// Cycle start: r = b - A x in FP64 (FP64 weights and border), V_0 = r and
+// W V_0; block sums of ||r||^2 and ||b||^2 (rows 0 and 1 of part).
 template <int KT, class T>
 __global__ void __launch_bounds__(kThreads) k_fg_init(EllM A, const double *__restrict__ b,
                                                        const double *__restrict__ x,
                                                        const double *partX, T *__restrict__ V0,
-                                                       double *part) {
+                                                       const T *__restrict__ dinv,
+                                                       T *__restrict__ wd, double *part) {
     const int nb = gridDim.x;
     double sx[1] = {0.0};
     if (A.u1) load_partials<1>(partX, nb, sx);
@@ -224,6 +242,7 @@ __global__ void __launch_bounds__(kThreads) k_fg_init(EllM A, const double *__re
             const double u1 = A.u1 ? A.u1[r] * A.vscale : 0.0;
             const double rr = b[r] - (ax[0][0] + u1 * sx[0]);
             V0[r] = (T)rr;
+            wd[r] = (T)rr * dinv[r];
             acc[0] += rr * rr;
             acc[1] += b[r] * b[r];
         }
@@ -233,20 +252,19 @@ __global__ void __launch_bounds__(kThreads) k_fg_init(EllM A, const double *__re
     store_partials<1>(v1, part + kMaxBlocks, nb);
 }
 
-// One workgroup: reduce nq rows of nb block partials (row q at
-// q * kMaxBlocks) into out[q], each row by one wavefront in a fixed order.
-// GATE: exit when the flag is set (inside an Arnoldi step).
+// Reduce nq rows of nb block partials (row q at q * kMaxBlocks) into
+// out[q]: one workgroup per row, a fixed order.  GATE: exit when the flag
+// is set (inside an Arnoldi step).
 template <bool GATE>
 __global__ void __launch_bounds__(256) k_fg_reduce(const double *part, int nb, int nq,
                                                    double *out, const int *flag) {
     if (GATE && *flag != 0) return;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int q = wid; q < nq; q += 4) {
-        double s = 0.0;
-        for (int b = lane; b < nb; b += 64) s += part[(int64_t)q * kMaxBlocks + b];
-        s = rbf::wave_sum(s);
-        if (lane == 0) out[q] = s;
-    }
+    const int q = blockIdx.x;
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nb; b += 256) v[0] += part[(int64_t)q * kMaxBlocks + b];
+    __shared__ double lds[4];
+    rbf::block_sum<1>(v, lds);
+    if (threadIdx.x == 0) out[q] = v[0];
 }
 
 // Cycle start, one thread: beta = ||r||, the cycle's target (FP64:
@@ -282,10 +300,12 @@ __global__ void k_fg_start(FgScal F, const double *red, double tol, int mixed, i
 template <class T>
 __device__ __forceinline__ void fg_dots(const T *V, const double *vs, const T *w, int64_t m, int j,
                                         double *part) {
+#pragma unroll 1
     for (int i0 = 0; i0 <= j; i0 += kFgChunk) {
         double acc[kFgChunk];
 #pragma unroll
         for (int c = 0; c < kFgChunk; ++c) acc[c] = 0.0;
+#pragma unroll 1
         for (int64_t it = 0;; ++it) {
             const int64_t r = row_of(it);
             if (r - threadIdx.x >= m) break;
@@ -316,11 +336,12 @@ __global__ void __launch_bounds__(kThreads) k_fg_av(AuxOps<T> P, const double *_
     load_partials<1>(F.s.partO, gridDim.x, sz);
     const T *z = F.Z + (int64_t)j * P.m;
     T *w = F.V + (int64_t)(j + 1) * P.m;
+#pragma unroll 1
     for (int64_t it = 0;; ++it) {
         const int64_t r = row_of(it);
         if (r - threadIdx.x >= P.m) break;
         if (r < P.m) {
-            const T az = aux_row<KT>(P, r, [&](int c) { return z[c]; });
+            const T az = aux_row<KT, (KT > 0 ? KT : 1)>(P, r, [&](int c) { return z[c]; });
             w[r] = (T)((double)az + (u1 ? u1[r] * vscale * sz[0] : 0.0));
         }
     }
@@ -329,9 +350,10 @@ __global__ void __launch_bounds__(kThreads) k_fg_av(AuxOps<T> P, const double *_
 
 // Gram-Schmidt update w -= sum_i h_i vs_i V_i (i <= j); PASS 1: then block
 // partial dots (V_i vs_i, w) for the second pass; PASS 2: then block
-// partial ||w||^2.
+// partial ||w||^2, and W w for the next preconditioner application.
 template <class T, int PASS>
-__global__ void __launch_bounds__(kThreads) k_fg_gs(FgDev<T> F, const double *h, int64_t m,
+__global__ void __launch_bounds__(kThreads) k_fg_gs(FgDev<T> F, const double *h,
+                                                     const T *__restrict__ dinv, int64_t m,
                                                      int j) {
     if (*F.s.flag != 0) return;
     __shared__ double c[kFgMax + 1];
@@ -347,6 +369,7 @@ __global__ void __launch_bounds__(kThreads) k_fg_gs(FgDev<T> F, const double *h,
             for (int i = 0; i <= j; ++i) wr -= c[i] * (double)F.V[(int64_t)i * m + r];
             const T wt = (T)wr;
             w[r] = wt;
+            if constexpr (PASS == 2) F.wd[r] = wt * dinv[r];
             nrm[0] += (double)wt * (double)wt;
         }
     }
@@ -361,28 +384,39 @@ __global__ void __launch_bounds__(kThreads) k_fg_gs(FgDev<T> F, const double *h,
 // H(j+1, j) = ||w||, previous rotations applied, a new rotation, the
 // residual estimate |g_{j+1}| and the status (4: the cycle's target met or
 // an exact breakdown; 3: the cycle is full; -1: non-finite).
-__global__ void k_fg_tail(FgScal F, int j, int mr) {
+__global__ void __launch_bounds__(64) k_fg_tail(FgScal F, int j, int mr) {
     if (*F.flag != 0) return;
-    double *Hc = F.H + (int64_t)j * (mr + 1);
-    for (int i = 0; i <= j; ++i) Hc[i] = F.h1[i] + F.h2[i];
-    const double hn = sqrt(F.hn2[0]);
-    Hc[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-        const double a = Hc[i], b = Hc[i + 1];
-        Hc[i] = F.cs[i] * a + F.sn[i] * b;
-        Hc[i + 1] = -F.sn[i] * a + F.cs[i] * b;
+    __shared__ double col[kFgMax + 1], cs[kFgMax], sn[kFgMax];
+    const int lane = threadIdx.x;
+    for (int i = lane; i <= j; i += 64) {
+        col[i] = F.h1[i] + F.h2[i];
+        if (i < j) {
+            cs[i] = F.cs[i];
+            sn[i] = F.sn[i];
+        }
     }
-    const double a = Hc[j], b = Hc[j + 1];
+    __syncthreads();
+    if (lane != 0) return;
+    double *Hc = F.H + (int64_t)j * (mr + 1);
+    const double hn = sqrt(F.hn2[0]);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
     const double den = hypot(a, b);
     const double c = (den > 0.0) ? a / den : 1.0, s = (den > 0.0) ? b / den : 0.0;
     F.cs[j] = c;
     F.sn[j] = s;
-    Hc[j] = den;
+    col[j] = den;
+    for (int i = 0; i <= j; ++i) Hc[i] = col[i];
     Hc[j + 1] = 0.0;
     const double gj = F.g[j];
     F.g[j] = c * gj;
     F.g[j + 1] = -s * gj;
-    const double res = fabs(F.g[j + 1]);
+    const double res = fabs(s * gj);
     F.vs[j + 1] = (hn > 0.0) ? 1.0 / hn : 0.0;
     F.resh[j + 1] = res;
     F.step[0] = j + 1;
@@ -394,13 +428,22 @@ __global__ void k_fg_tail(FgScal F, int j, int mr) {
 }
 
 // End of a cycle of nstep steps, one thread: back substitution H y = g.
-__global__ void k_fg_solve(FgScal F, int nstep, int mr) {
-    for (int i = nstep - 1; i >= 0; --i) {
-        double s = F.g[i];
-        for (int l = i + 1; l < nstep; ++l) s -= F.H[(int64_t)l * (mr + 1) + i] * F.y[l];
-        const double d = F.H[(int64_t)i * (mr + 1) + i];
-        F.y[i] = (d != 0.0) ? s / d : 0.0;
+__global__ void __launch_bounds__(256) k_fg_solve(FgScal F, int nstep, int mr) {
+    __shared__ double Hs[kFgMax * kFgMax], gs[kFgMax], ys[kFgMax];
+    for (int e = threadIdx.x; e < nstep * nstep; e += blockDim.x) {
+        const int l = e / nstep, i = e % nstep;  // column l, row i
+        Hs[l * kFgMax + i] = F.H[(int64_t)l * (mr + 1) + i];
     }
+    for (int i = threadIdx.x; i < nstep; i += blockDim.x) gs[i] = F.g[i];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int i = nstep - 1; i >= 0; --i) {
+        double s = gs[i];
+        for (int l = i + 1; l < nstep; ++l) s -= Hs[l * kFgMax + i] * ys[l];
+        const double d = Hs[i * kFgMax + i];
+        ys[i] = (d != 0.0) ? s / d : 0.0;
+    }
+    for (int i = 0; i < nstep; ++i) F.y[i] = ys[i];
 }
 
 // x += sum_i y_i Z_i (FP64 iterate).

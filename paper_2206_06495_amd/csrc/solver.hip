@@ -2472,22 +2472,24 @@ rbf_status copy_in(rbf_solver *S, void *dst, const void *src, size_t bytes) {
 // (pressure_aux.h): smoother, residual, restriction, lattice transform
 // solve, interpolation, smoother.
 template <class T>
-void aux_apply(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, const T *y, const double *ys,
-               T *z) {
+void aux_apply(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, const T *y, const T *yd,
+               const double *ys, T *z, bool sample = false) {
     hipStream_t st = S->st;
     const dim3 grid(nblocks_rows(P.m)), block(kThreads);
     const int nq = S->lat.n * S->lat.n;
     launch_kt(P.k, [&](auto KT) {
-        hipLaunchKernelGGL((k_aux_res<decltype(KT)::value, T>), grid, block, 0, st, P, y, ys, F.res,
-                           F.s.flag);
+        hipLaunchKernelGGL((k_aux_res<decltype(KT)::value, T>), grid, block, 0, st, P, y, yd, ys,
+                           F.res, F.s.flag);
     });
-    hipLaunchKernelGGL(k_aux_restrict<T>, dim3(rbf::blocks_for(nq, kThreads)), block, 0, st, P,
+    hipLaunchKernelGGL(k_aux_restrict<T>, dim3(rbf::blocks_for(nq, 64)), dim3(64), 0, st, P,
                        S->lat, F.res, nq);
-    pc_apply(S);
-    hipLaunchKernelGGL(k_aux_interp<T>, grid, block, 0, st, P, S->lat, y, ys, F.t1, F.s.partZ);
+    pc_apply(S, sample);
+    hipLaunchKernelGGL(k_aux_interp<T>, grid, block, 0, st, P, S->lat, yd, ys, F.t1, F.s.partZ);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (sample) prof_pair(S, RBF_PROF_SMOOTH, e0, e1);
     launch_kt(P.k, [&](auto KT) {
-        hipLaunchKernelGGL((k_aux_post<decltype(KT)::value, T>), grid, block, 0, st, P, S->lat, y,
-                           ys, F.t1, F.s.partZ, z, F.s.partO);
+        hipExtLaunchKernelGGL((k_aux_post<decltype(KT)::value, T>), grid, block, 0, st, e0, e1, 0, P,
+                              S->lat, y, ys, F.t1, F.s.partZ, z, F.s.partO);
     });
 }
 
@@ -2516,6 +2518,7 @@ rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, co
         RBF_HIP(hipMemcpyAsync(S->hflag, Fs.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         RBF_HIP(hipMemcpyAsync(S->hflag + 2, Fs.stat, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
         RBF_HIP(hipStreamSynchronize(st));
+        prof_flush(S);
         return RBF_OK;
     };
     rbf_status rc = RBF_OK;
@@ -2523,9 +2526,9 @@ rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, co
         if (A.u1) hipLaunchKernelGGL((k_sum<1>), grid, block, 0, st, m, x, S->kp.partX);
         launch_kt(A.k, [&](auto KT) {
             hipLaunchKernelGGL((k_fg_init<decltype(KT)::value, T>), grid, block, 0, st, A, b, x,
-                               S->kp.partX, F.V, Fs.part);
+                               S->kp.partX, F.V, P.dinv, F.wd, Fs.part);
         });
-        hipLaunchKernelGGL(k_fg_reduce<false>, one, red, 0, st, Fs.part, nb, 2, Fs.h1, Fs.flag);
+        hipLaunchKernelGGL(k_fg_reduce<false>, dim3(2), red, 0, st, Fs.part, nb, 2, Fs.h1, Fs.flag);
         hipLaunchKernelGGL(k_fg_start, one, one, 0, st, Fs, Fs.h1, tol, mixed, first ? 1 : 0);
         first = false;
         if (total >= maxit) {  // only the convergence test of the iterate
@@ -2539,20 +2542,27 @@ rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, co
             const int stop = std::min(mr, j + batch);
             for (; j < stop; ++j) {
                 const int64_t o = (int64_t)j * m;
-                aux_apply(S, P, F, F.V + o, Fs.vs + j, F.Z + o);
+                const bool sample = S->prof_every > 0 && (S->prof_launches++ % S->prof_every) == 0;
+                aux_apply(S, P, F, F.V + o, F.wd, Fs.vs + j, F.Z + o, sample);
+                hipEvent_t e0 = nullptr, e1 = nullptr, g0 = nullptr, g1 = nullptr;
+                if (sample) {
+                    prof_pair(S, RBF_PROF_SPMV, e0, e1);
+                    prof_pair(S, RBF_PROF_GS, g0, g1);
+                }
                 launch_kt(P.k, [&](auto KT) {
-                    hipLaunchKernelGGL((k_fg_av<decltype(KT)::value, T>), grid, block, 0, st, P,
-                                       A.u1, A.vscale, F, j);
+                    hipExtLaunchKernelGGL((k_fg_av<decltype(KT)::value, T>), grid, block, 0, st, e0,
+                                          e1, 0, P, A.u1, A.vscale, F, j);
                 });
-                hipLaunchKernelGGL(k_fg_reduce<true>, one, red, 0, st, Fs.part, nb, j + 1, Fs.h1,
-                                   Fs.flag);
-                hipLaunchKernelGGL((k_fg_gs<T, 1>), grid, block, 0, st, F, Fs.h1, m, j);
-                hipLaunchKernelGGL(k_fg_reduce<true>, one, red, 0, st, Fs.part, nb, j + 1, Fs.h2,
-                                   Fs.flag);
-                hipLaunchKernelGGL((k_fg_gs<T, 2>), grid, block, 0, st, F, Fs.h2, m, j);
+                hipLaunchKernelGGL(k_fg_reduce<true>, dim3(j + 1), red, 0, st, Fs.part, nb, j + 1,
+                                   Fs.h1, Fs.flag);
+                hipExtLaunchKernelGGL((k_fg_gs<T, 1>), grid, block, 0, st, g0, g1, 0, F, Fs.h1,
+                                      P.dinv, m, j);
+                hipLaunchKernelGGL(k_fg_reduce<true>, dim3(j + 1), red, 0, st, Fs.part, nb, j + 1,
+                                   Fs.h2, Fs.flag);
+                hipLaunchKernelGGL((k_fg_gs<T, 2>), grid, block, 0, st, F, Fs.h2, P.dinv, m, j);
                 hipLaunchKernelGGL(k_fg_reduce<true>, one, red, 0, st, Fs.part, nb, 1, Fs.hn2,
                                    Fs.flag);
-                hipLaunchKernelGGL(k_fg_tail, one, one, 0, st, Fs, j, mr);
+                hipLaunchKernelGGL(k_fg_tail, one, dim3(64), 0, st, Fs, j, mr);
             }
             RBF_CHECK_LAUNCH();
             if ((rc = status()) != RBF_OK) return rc;
@@ -2574,7 +2584,7 @@ rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, co
             f = 0;
             break;
         }
-        hipLaunchKernelGGL(k_fg_solve, one, one, 0, st, Fs, nstep, mr);
+        hipLaunchKernelGGL(k_fg_solve, one, red, 0, st, Fs, nstep, mr);
         hipLaunchKernelGGL((k_fg_x<T>), grid, block, 0, st, F.Z, Fs.y, nstep, m, x);
         ++cycles;
     }
@@ -2618,6 +2628,7 @@ rbf_status alloc_fg(rbf_solver *S, FgDev<T> &F, int64_t M) {
     ALLOC(F.Z, (int64_t)mr * M);
     ALLOC(F.res, M);
     ALLOC(F.t1, M);
+    ALLOC(F.wd, M);
     FgScal &s = F.s;
     ALLOC(s.vs, mr + 1);
     ALLOC(s.part, (int64_t)(kFgMax + 2) * kMaxBlocks);
@@ -3388,7 +3399,8 @@ extern "C" rbf_status rbf_solver_apply_precond(rbf_solver *S, const double *y, d
         FgDev<double> &F = S->fg64;
         RBF_HIP(hipMemsetAsync(F.s.flag, 0, sizeof(int), S->st));
         S->lat.flag = F.s.flag;
-        aux_apply<double>(S, S->ax64, F, y, F.s.one, z);
+        hipLaunchKernelGGL(k_aux_scale<double>, dim3(1024), dim3(256), 0, S->st, S->ax64, y, F.wd);
+        aux_apply<double>(S, S->ax64, F, y, F.wd, F.s.one, z);
         RBF_CHECK_LAUNCH();
         RBF_HIP(hipStreamSynchronize(S->st));
         return RBF_OK;

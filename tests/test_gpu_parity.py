@@ -635,10 +635,13 @@ def test_long_run_on_near_equilateral_nodes(P, gpu):
     right-triangle lattice):
     the fields follow the oracle every 100 steps and the run stays bounded
     (maximum speed, CFL and interior divergence from rbf_solver_diagnostics).
-    Observed: fields within 4e-11 of the oracle at every check."""
+    With the default pressure tolerance 1e-12 p drifts to 1.03e-10 by step
+    200; at 1e-13 the fields stay well inside the bar."""
     _say("long run, near-equilateral nodes K=60")
     nd = ri.hex_cavity_nodes(60, 0.3, 0)
-    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 1e4, 2e-4)
+    # At dt = 2e-4 an error in u** reaches p~ multiplied by 1/dt: the
+    # pressure tolerance is one decade below the binding's default.
+    S, ops, u_bc, v_bc = _gpu_solver(P, nd, gpu, 1e4, 2e-4, rtol_p=1e-13)
     orc = ocav.CavityOracle(nd, u_bc, v_bc, 1e4, 2e-4)
     s0 = orc.initial_state()
     st = S.new_state(to_dev(s0.u, gpu), to_dev(s0.v, gpu))
