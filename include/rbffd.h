@@ -318,7 +318,8 @@ typedef struct {
  * solves along y), followed by bilinear interpolation to the node
  * positions; BiCGSTAB iterates with it.
  * The auxiliary-lattice preconditioner (any node set in a square) is a
- * two-level method: an l1-Jacobi sweep on the stored Poisson rows, the
+ * two-level method: an l1-Jacobi sweep (damping 2) on the stored Poisson
+ * rows, the
  * residual restricted (normalised bilinear weights, interior nodes to
  * interior lattice points) to a lattice of about two node spacings per cell
  * and solved there by the same fast Poisson solve with homogeneous Neumann

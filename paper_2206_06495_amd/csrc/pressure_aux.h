@@ -45,7 +45,16 @@
 
 constexpr int kFgMax = 30;        // restart length (basis vectors per cycle)
 constexpr int kFgChunk = 6;       // dot products accumulated per pass over the rows
-constexpr double kAuxOmega = 1.3; // smoother damping (l1-Jacobi)
+// Smoother damping of the l1-Jacobi sweeps: the l1 norms of RBF-FD rows are
+// several times their diagonal, so steps up to about 2.4 still damp (FGMRES
+// steps per solve at h = 1/100 and 1/200, rtol 1e-12: 111 and 118 at 1.3,
+// 86 and 96 at 2.0, 78 and 84 at 2.4, divergent smoothing from 2.8).
+constexpr double kAuxOmega = 2.0;
+// Border scale of the FGMRES operator relative to the solver's: any scale
+// gives the same p~ (the constant is removed afterwards); the solver's own
+// scale happens to slow FGMRES (140 against 111 steps at h = 1/100 for 0.1
+// or less of it).
+constexpr double kAuxBorder = 0.1;
 constexpr double kMixedInner = 1e-4;  // mixed: per-cycle residual reduction
 
 template <class T>
@@ -145,16 +154,24 @@ __global__ void k_aux_scale(AuxOps<T> P, const T *__restrict__ y, T *__restrict_
         yd[r] = y[r] * P.dinv[r];
 }
 
-// Stage 2: restriction to the interior lattice points, X(q) = sum rval res.
+// Stage 2: restriction to the interior lattice points, X(q) = sum rval res
+// (about 18 entries per point with two node spacings per cell): 4 lanes per
+// point take every 4th entry, then combine in a fixed order.
 template <class T>
-__global__ void __launch_bounds__(64) k_aux_restrict(AuxOps<T> P, Lat L,
-                                                      const T *__restrict__ res, int nq) {
+__global__ void __launch_bounds__(256) k_aux_restrict(AuxOps<T> P, Lat L,
+                                                       const T *__restrict__ res, int nq) {
     if (*L.flag != 0) return;
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = t >> 2, sub = t & 3;
     double g = 0.0;
-    for (int e = P.rptr[q]; e < P.rptr[q + 1]; ++e) g += (double)P.rval[e] * (double)res[P.rcol[e]];
-    lat_store(L, L.X, q, g);
+    if (q < nq) {
+        const int e1 = P.rptr[q + 1];
+        for (int e = P.rptr[q] + sub; e < e1; e += 4)
+            g += (double)P.rval[e] * (double)res[P.rcol[e]];
+    }
+    g += __shfl_xor(g, 1, 64);
+    g += __shfl_xor(g, 2, 64);
+    if (q < nq && sub == 0) lat_store(L, L.X, q, g);
 }
 
 // Lattice value of the transform solve (Z, column-major in X) at lattice
@@ -327,13 +344,15 @@ __device__ __forceinline__ void fg_dots(const T *V, const double *vs, const T *w
 }
 
 // Arnoldi step j, product: w = A z_j (sparse part in T plus the border with
-// sum z_j from partO), stored in V[j+1]; block partial dots (V_i vs_i, w).
+// sum z_j from partO; u1 must not be null), stored in V[j+1]; block partial
+// dots (V_i vs_i, w).
 template <int KT, class T>
 __global__ void __launch_bounds__(kThreads) k_fg_av(AuxOps<T> P, const double *__restrict__ u1,
                                                      double vscale, FgDev<T> F, int j) {
     if (*F.s.flag != 0) return;
     double sz[1];
     load_partials<1>(F.s.partO, gridDim.x, sz);
+    const double bterm = vscale * sz[0];  // border: u1 c (1^T z)
     const T *z = F.Z + (int64_t)j * P.m;
     T *w = F.V + (int64_t)(j + 1) * P.m;
 #pragma unroll 1
@@ -342,7 +361,7 @@ __global__ void __launch_bounds__(kThreads) k_fg_av(AuxOps<T> P, const double *_
         if (r - threadIdx.x >= P.m) break;
         if (r < P.m) {
             const T az = aux_row<KT, (KT > 0 ? KT : 1)>(P, r, [&](int c) { return z[c]; });
-            w[r] = (T)((double)az + (u1 ? u1[r] * vscale * sz[0] : 0.0));
+            w[r] = (T)((double)az + u1[r] * bterm);
         }
     }
     fg_dots(F.V, F.s.vs, w, P.m, j, F.s.part);

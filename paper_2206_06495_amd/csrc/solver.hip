@@ -2481,8 +2481,8 @@ void aux_apply(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, const T *y, const
         hipLaunchKernelGGL((k_aux_res<decltype(KT)::value, T>), grid, block, 0, st, P, y, yd, ys,
                            F.res, F.s.flag);
     });
-    hipLaunchKernelGGL(k_aux_restrict<T>, dim3(rbf::blocks_for(nq, 64)), dim3(64), 0, st, P,
-                       S->lat, F.res, nq);
+    hipLaunchKernelGGL(k_aux_restrict<T>, dim3(rbf::blocks_for(4 * (int64_t)nq, 256)), dim3(256), 0,
+                       st, P, S->lat, F.res, nq);
     pc_apply(S, sample);
     hipLaunchKernelGGL(k_aux_interp<T>, grid, block, 0, st, P, S->lat, yd, ys, F.t1, F.s.partZ);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -2614,6 +2614,7 @@ rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, co
 }
 
 rbf_status aux_solve(rbf_solver *S, EllM A, const double *b, double *x, rbf_solve_stats *stats) {
+    A.vscale *= kAuxBorder;  // as S->lat.c
     if (S->mixed)
         return fgmres_run<float>(S, S->ax32, S->fg32, A, b, x, S->rtol_p, S->maxit_p,
                                  S->last_iters_p, stats);
@@ -2771,7 +2772,7 @@ rbf_status setup_aux_pc(rbf_solver *S, const rbf_grid *g, int mode) {
     L.K = Ka;
     L.n = n;
     L.h = h;
-    L.c = S->p_vscale;
+    L.c = S->p_vscale * kAuxBorder;  // the FGMRES operator's border scale
     L.rs = S->p_rowscale;
     L.cell = dcell;
     L.fx = dfx;

@@ -42,7 +42,7 @@ def _ell(idx, w, ncols):
 def _aux_reference(nd, ops, y):
     """Plain statement of the auxiliary-lattice preconditioner (header of
     rbf_params.precond), built from the GPU's stencils and weights: l1-Jacobi
-    sweep (omega 1.3), residual, normalised bilinear restriction of interior
+    sweep (omega 2.0), residual, normalised bilinear restriction of interior
     nodes to interior lattice points, zero-mean solve of the 5-point
     Laplacian with homogeneous one-sided Neumann rows by sparse LU (no
     transforms), bilinear interpolation with wall values copied inward, the
@@ -56,8 +56,8 @@ def _aux_reference(nd, ops, y):
     rn = np.sqrt(np.asarray(A0.multiply(A0).sum(1)).ravel())
     S = np.where(wall, 1.0, -1.0) / rn
     A = (sp.diags(S) @ A0).tocsr()
-    W = 1.3 / np.asarray(abs(A).sum(1)).ravel()
-    c = ((~wall).sum() / np.abs(S[~wall]).sum()) / M
+    W = 2.0 / np.asarray(abs(A).sum(1)).ravel()
+    c = 0.1 * ((~wall).sum() / np.abs(S[~wall]).sum()) / M  # the FGMRES border scale
     x0, x1, y0, y1 = nd.xp[0].min(), nd.xp[0].max(), nd.xp[1].min(), nd.xp[1].max()
     side = max(x1 - x0, y1 - y0)
     Ka = max(4, min(int(np.floor(0.465 * np.sqrt(M) + 0.5)), 513))
