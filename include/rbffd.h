@@ -506,6 +506,35 @@ typedef struct {
 } rbf_diagnostics;
 rbf_status rbf_solver_diagnostics(rbf_solver *s, const rbf_state *state, rbf_diagnostics *out);
 
+/*
+ * rbf_adjoint_step -- reverse-mode derivative of one rbf_step (the stages of
+ * Sec. 3, eqs. (14)-(21), transposed in reverse order), for gradients of an
+ * objective of a rollout with respect to the viscosity nu = 1/Re and the
+ * wall velocities.
+ *
+ * fwd: the forward state at step j (device arrays as in rbf_step; read
+ * only; fwd->step says whether the AB2 start C_{-1} = C_0 applies).  The
+ * call recomputes the forward step j -> j+1 from it (the same solves as
+ * rbf_step), so a rollout needs only checkpointed states.
+ * adj (in/out): on entry the adjoints of the state at j+1 -- u, v, p_tilde
+ * the adjoints of u_{j+1}, v_{j+1}, p~_{j+1}, and cu_prev, cv_prev the
+ * adjoints of C_j (which the next step reads as its C_{j-1}); on return the
+ * adjoints of the state at j (p and step are not used).
+ * grad_bc: device [2][n_v], accumulated: the adjoints of u_bc and v_bc from
+ * this step (wall rows; the Kim-Moin values of eq. (21) use them).
+ * dnu: host, accumulated: the derivative with respect to nu (through
+ * H = I - (dt nu / 2) D_Lap and the right-hand side of eq. (16)).
+ * The transposed solves: the viscous matrix by Jacobi-scaled BiCGSTAB on
+ * H^T, the bordered pressure system by BiCGSTAB on (A_s + u1 c 1^T)^T (the
+ * transpose of the zero-mean bordered solve), with the solver's tolerances
+ * (pressure: a tenth of rtol_p).  The first call builds the transposed
+ * operators (rbf_ell_transpose).  Synchronises.
+ * Errors: RBF_E_ARG (NULL arguments), RBF_E_NOCONV, RBF_E_NAN, those of
+ * rbf_step for the recomputed forward step.
+ */
+rbf_status rbf_adjoint_step(rbf_solver *s, const rbf_state *fwd, rbf_state *adj, double *grad_bc,
+                            double *dnu);
+
 /* Release a solver (NULL is ignored). */
 void rbf_solver_destroy(rbf_solver *s);
 

@@ -14,8 +14,9 @@ Modules
   operators  global sparse differentiation matrices (Sec. 2.2, eq. (10))
   cavity     fractional-step solver (Sec. 3, eqs. (14)-(21)) with LU solves
   metrics    test-function error and modified wavenumber (Sec. 4, eqs. (22)-(24))
+  adjoint    reverse-mode derivative of the cavity step (transposed stages)
 """
-from . import knn, weights, operators, cavity, metrics  # noqa: F401
+from . import knn, weights, operators, cavity, metrics, adjoint  # noqa: F401
 
 OP_ID = 1
 OP_DX = 2

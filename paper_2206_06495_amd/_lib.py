@@ -27,7 +27,7 @@ EXPORTED = [
     "rbf_assemble_weights", "rbf_ell_apply", "rbf_cast_f32", "rbf_ell_transpose",
     "rbf_ell_transpose_weights", "rbf_ell_apply_transpose", "rbf_solver_create",
     "rbf_step", "rbf_step_batch", "rbf_solve_pressure", "rbf_solver_apply_precond", "rbf_solver_profile", "rbf_solver_query",
-    "rbf_solver_diagnostics",
+    "rbf_solver_diagnostics", "rbf_adjoint_step",
     "rbf_solver_destroy",
 ]
 
@@ -149,6 +149,9 @@ def _load():
     lib.rbf_solver_diagnostics.restype = S
     lib.rbf_solver_diagnostics.argtypes = [c_void_p, ctypes.POINTER(State),
                                            ctypes.POINTER(Diagnostics)]
+    lib.rbf_adjoint_step.restype = S
+    lib.rbf_adjoint_step.argtypes = [c_void_p, ctypes.POINTER(State), ctypes.POINTER(State),
+                                     c_void_p, c_double_p]
     lib.rbf_solver_destroy.restype = None
     lib.rbf_solver_destroy.argtypes = [c_void_p]
     return lib

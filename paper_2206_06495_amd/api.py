@@ -12,7 +12,7 @@ import torch
 from . import _lib
 from ._lib import OP_ID, OP_DX, OP_DY, OP_LAP, check, lib
 
-__all__ = ["build_nodes", "knn", "assemble_weights", "ell_apply", "cast_f32", "Solver",
+__all__ = ["build_nodes", "knn", "assemble_weights", "ell_apply", "cast_f32", "Solver", "LidRollout",
            "OP_ID", "OP_DX", "OP_DY", "OP_LAP"]
 
 
@@ -286,6 +286,24 @@ class Solver:
                 log.flush()
         return records
 
+    def adjoint_step(self, fwd, adj, grad_bc):
+        """rbf_adjoint_step: `adj` (dict of device tensors u, v, p_tilde,
+        cu_prev, cv_prev) holds the adjoints of the state one step after
+        `fwd` on entry and of `fwd` on return; grad_bc (device [2, N])
+        accumulates the boundary-value adjoints.  Returns dJ/dnu of the step."""
+        f = self._state_struct(fwd)
+        for key, n in (("u", self.N), ("v", self.N), ("cu_prev", self.N), ("cv_prev", self.N),
+                       ("p_tilde", self.M)):
+            _dev(adj[key], torch.float64, (n,), "adj " + key)
+        _dev(grad_bc, torch.float64, (2, self.N), "grad_bc")
+        a = _lib.State(adj["u"].data_ptr(), adj["v"].data_ptr(), adj["p_tilde"].data_ptr(),
+                       adj["p_tilde"].data_ptr(), adj["cu_prev"].data_ptr(),
+                       adj["cv_prev"].data_ptr(), 0)
+        dnu = ctypes.c_double(0.0)
+        check(lib.rbf_adjoint_step(self._h, ctypes.byref(f), ctypes.byref(a), _ptr(grad_bc),
+                                   ctypes.byref(dnu)))
+        return dnu.value
+
     def diagnostics(self, state):
         """Health figures of a state: {"div_max", "div_rms", "kinetic_energy",
         "speed_max", "cfl"} (rbf_solver_diagnostics)."""
@@ -330,3 +348,75 @@ def step_batch(solvers, states, nsteps=1, nthreads=0):
         e.statuses, e.stats = list(codes), list(stats)
         raise
     return list(stats), list(codes)
+
+
+class LidRollout:
+    """Differentiable lid-driven cavity rollout: J(nu, coef) = kinetic energy
+    (rbf_solver_diagnostics: 1/2 mean over V-nodes of u^2 + v^2) after
+    `nsteps` steps from rest, with nu = 1/Re and the lid velocity
+    u_lid = sum_k coef[k] modes[k] on the lid V-nodes (modes: device
+    [nmodes, N], zero off the lid).  Calling it returns a torch scalar whose
+    backward runs rbf_adjoint_step backwards through the rollout from
+    checkpoints taken every `every` steps (the states inside a segment are
+    recomputed, one rbf_step each, as the forward pass takes them).
+    grid, ops: as for Solver; solver_kw: further Solver arguments."""
+
+    def __init__(self, grid, ops, modes, dt, nsteps, every=10, **solver_kw):
+        self.grid, self.ops, self.modes = grid, ops, modes
+        self.dt, self.nsteps, self.every = float(dt), int(nsteps), max(1, int(every))
+        self.solver_kw = solver_kw
+        self.N = grid["xv"].shape[1]
+        self.wall = grid["v_tag"] != 0
+
+    def _solver(self, nu, coef):
+        u_bc = (coef.to(self.modes) @ self.modes).contiguous()
+        v_bc = torch.zeros_like(u_bc)
+        S = Solver(self.grid, self.ops, u_bc, v_bc, 1.0 / float(nu), self.dt, **self.solver_kw)
+        st = S.new_state(torch.where(self.wall, u_bc, torch.zeros_like(u_bc)), v_bc)
+        return S, st
+
+    @staticmethod
+    def _clone(st):
+        return {k: (v.clone() if isinstance(v, torch.Tensor) else v) for k, v in st.items()}
+
+    def __call__(self, nu, coef):
+        return _LidRolloutFn.apply(nu, coef, self)
+
+
+class _LidRolloutFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, nu, coef, R):
+        S, st = R._solver(nu, coef)
+        checkpoints = []
+        for j in range(R.nsteps):
+            if j % R.every == 0:
+                checkpoints.append(R._clone(st))
+            S.step(st, 1)
+        J = S.diagnostics(st)["kinetic_energy"]
+        ctx.R, ctx.S, ctx.checkpoints, ctx.final = R, S, checkpoints, st
+        return torch.tensor(J, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        R, S, final = ctx.R, ctx.S, ctx.final
+        N, M = S.N, S.M
+        z = lambda n: torch.zeros(n, dtype=torch.float64, device=S.device)  # noqa: E731
+        adj = {"u": final["u"] / N, "v": final["v"] / N, "p_tilde": z(M), "cu_prev": z(N),
+               "cv_prev": z(N)}
+        grad_bc = torch.zeros((2, N), dtype=torch.float64, device=S.device)
+        dnu = 0.0
+        for c in range(len(ctx.checkpoints) - 1, -1, -1):
+            st = R._clone(ctx.checkpoints[c])
+            seg = [R._clone(st)]
+            stop = min(R.nsteps, (c + 1) * R.every)
+            for _ in range(c * R.every, stop - 1):
+                S.step(st, 1)
+                seg.append(R._clone(st))
+            for fwd in reversed(seg):
+                dnu += S.adjoint_step(fwd, adj, grad_bc)
+        # The initial state's wall values are the boundary data as well.
+        gu = grad_bc[0] + torch.where(R.wall, adj["u"], torch.zeros_like(adj["u"]))
+        S.close()
+        g = float(gJ)
+        d_coef = (R.modes @ gu) * g
+        return torch.tensor(dnu * g, dtype=torch.float64), d_coef.to(torch.float64).cpu(), None

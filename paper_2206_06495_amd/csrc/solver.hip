@@ -1698,6 +1698,7 @@ __global__ void k_wall_list(int64_t n, const int8_t *__restrict__ tag, int *__re
 }
 
 #include "pressure_aux.h"
+#include "adjoint.h"
 
 }  // namespace
 
@@ -1764,6 +1765,20 @@ struct rbf_solver {
     FgDev<double> fg64{};
     FgDev<float> fg32{};
     float *p_w32 = nullptr;    // FP32 Poisson weights (mixed precision)
+    // adjoint step (rbf_adjoint_step): transposed operators and work vectors,
+    // built at its first call
+    struct Adj {
+        bool ready = false;
+        int64_t *cp_vv = nullptr, *cp_vp = nullptr, *cp_pv = nullptr, *cp_pp = nullptr;
+        int *src_vv = nullptr, *src_vp = nullptr, *src_pv = nullptr, *src_pp = nullptr;
+        double *dxT_vv = nullptr, *dyT_vv = nullptr, *lapT_vv = nullptr, *dxT_vp = nullptr,
+               *dyT_vp = nullptr, *dxT_pv = nullptr, *dyT_pv = nullptr, *aT_pp = nullptr;
+        int8_t *vtag = nullptr;  // 1 on wall V rows
+        double *vn[20] = {};     // work vectors over V rows
+        double *pm[8] = {};      // work vectors over P rows
+        double *kr[7] = {};      // Krylov vectors (max(N, M))
+        double *part = nullptr;
+    } adj;
     // pinned host buffers
     int *hflag = nullptr;
     double *hred = nullptr;
@@ -3313,6 +3328,315 @@ extern "C" rbf_status rbf_step(rbf_solver *S, int32_t nsteps, rbf_state *state,
     }
     RBF_HIP(hipStreamSynchronize(st));
     return rc;
+}
+
+// ------------------------------------------------------- adjoint step --
+namespace {
+
+// Column structure and column-ordered weights of the transposes (once).
+rbf_status adj_transpose(rbf_solver *S, int64_t rows, const int *idx, int64_t ncols,
+                         std::initializer_list<std::pair<const double *, double **>> ws,
+                         int64_t **cp, int **src) {
+    const int k = S->k;
+    int *slot;
+    ALLOC(*cp, ncols + 1);
+    ALLOC(*src, (int64_t)k * rows);
+    ALLOC(slot, (int64_t)k * rows);
+    int64_t bad = -1;
+    rbf_status rc = rbf_ell_transpose(rows, k, idx, ncols, *cp, *src, slot, &bad, S->st);
+    if (rc != RBF_OK) return rc;
+    for (auto &pw : ws) {
+        ALLOC(*pw.second, (int64_t)k * rows);
+        if ((rc = rbf_ell_transpose_weights(rows, k, *src, slot, pw.first, *pw.second, 0, S->st)) !=
+            RBF_OK)
+            return rc;
+    }
+    return RBF_OK;
+}
+
+rbf_status adj_setup(rbf_solver *S) {
+    auto &A = S->adj;
+    const int64_t N = S->N, M = S->M;
+    rbf_status rc;
+    if ((rc = adj_transpose(S, N, S->idx_vv, N,
+                            {{S->vv_dx, &A.dxT_vv}, {S->vv_dy, &A.dyT_vv}, {S->vv_lap, &A.lapT_vv}},
+                            &A.cp_vv, &A.src_vv)) != RBF_OK)
+        return rc;
+    if ((rc = adj_transpose(S, N, S->idx_vp, M, {{S->vp_dx, &A.dxT_vp}, {S->vp_dy, &A.dyT_vp}},
+                            &A.cp_vp, &A.src_vp)) != RBF_OK)
+        return rc;
+    if ((rc = adj_transpose(S, M, S->idx_pv, N, {{S->pv_dx, &A.dxT_pv}, {S->pv_dy, &A.dyT_pv}},
+                            &A.cp_pv, &A.src_pv)) != RBF_OK)
+        return rc;
+    if ((rc = adj_transpose(S, M, S->idx_pp, M, {{S->p_w, &A.aT_pp}}, &A.cp_pp, &A.src_pp)) !=
+        RBF_OK)
+        return rc;
+    ALLOC(A.vtag, N);
+    RBF_HIP(hipMemsetAsync(A.vtag, 0, N, S->st));
+    if (S->nwall > 0)
+        hipLaunchKernelGGL(k_adj_wallmask, dim3(rbf::blocks_for(S->nwall, 256)), dim3(256), 0,
+                           S->st, S->nwall, S->wall_rows, A.vtag);
+    for (auto &q : A.vn) ALLOC(q, N);
+    for (auto &q : A.pm) ALLOC(q, M);
+    for (auto &q : A.kr) ALLOC(q, std::max(N, M));
+    ALLOC(A.part, 4 * kMaxBlocks);
+    RBF_HIP(hipStreamSynchronize(S->st));
+    A.ready = true;
+    return RBF_OK;
+}
+
+// NQ dot products (or sums) over n entries, reduced on the host in a fixed
+// order (synchronises).
+template <int NQ>
+rbf_status adj_dots(rbf_solver *S, int64_t n, AdjDots d, double *out) {
+    const int nb = nblocks_rows(n);
+    hipLaunchKernelGGL(k_adj_dots<NQ>, dim3(nb), dim3(kThreads), 0, S->st, n, d, S->adj.part);
+    RBF_CHECK_LAUNCH();
+    for (int q = 0; q < NQ; ++q)
+        RBF_HIP(hipMemcpyAsync(S->hred + q * nb, S->adj.part + (int64_t)q * kMaxBlocks,
+                               nb * sizeof(double), hipMemcpyDeviceToHost, S->st));
+    RBF_HIP(hipStreamSynchronize(S->st));
+    for (int q = 0; q < NQ; ++q) {
+        double acc = 0.0;
+        for (int b = 0; b < nb; ++b) acc += S->hred[q * nb + b];
+        out[q] = acc;
+    }
+    return RBF_OK;
+}
+
+void adj_axpby(rbf_solver *S, int64_t n, double a, const double *x, double b, const double *y,
+               double *out) {
+    hipLaunchKernelGGL(k_adj_axpby, dim3(std::min<int64_t>(1024, rbf::blocks_for(n, 256))),
+                       dim3(256), 0, S->st, n, a, x, b, y, out);
+}
+
+// BiCGSTAB (van der Vorst 1992) for op(x) = b from x = 0, with the
+// Jacobi-type diagonal scaling dinv (nullable) as right preconditioner.
+// Scalars are reduced on the host (a few synchronisations per iteration):
+// these solves run once per adjoint step.
+template <class Op>
+rbf_status adj_bicgstab(rbf_solver *S, int64_t n, Op op, const double *dinv, const double *b,
+                        double *x, double tol, int maxit, const char *what) {
+    auto &K = S->adj.kr;
+    double *r = K[0], *rh = K[1], *p = K[2], *v = K[3], *s = K[4], *t = K[5], *z = K[6];
+    auto prec = [&](const double *in, double *out) {
+        if (dinv) hipLaunchKernelGGL(k_adj_mul, dim3(std::min<int64_t>(1024, rbf::blocks_for(n, 256))),
+                                     dim3(256), 0, S->st, n, dinv, in, out);
+        else RBF_HIP(hipMemcpyAsync(out, in, n * sizeof(double), hipMemcpyDeviceToDevice, S->st));
+        return RBF_OK;
+    };
+    rbf_status rc;
+    RBF_HIP(hipMemsetAsync(x, 0, n * sizeof(double), S->st));
+    RBF_HIP(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, S->st));
+    RBF_HIP(hipMemcpyAsync(rh, b, n * sizeof(double), hipMemcpyDeviceToDevice, S->st));
+    RBF_HIP(hipMemsetAsync(p, 0, n * sizeof(double), S->st));
+    RBF_HIP(hipMemsetAsync(v, 0, n * sizeof(double), S->st));
+    double bb;
+    if ((rc = adj_dots<1>(S, n, AdjDots{{b}, {b}}, &bb)) != RBF_OK) return rc;
+    if (bb == 0.0) return RBF_OK;
+    double rho = 1.0, alpha = 1.0, omega = 1.0;
+    for (int it = 0; it < maxit; ++it) {
+        double q[2];
+        if ((rc = adj_dots<2>(S, n, AdjDots{{rh, r}, {r, r}}, q)) != RBF_OK) return rc;
+        if (!std::isfinite(q[1])) {
+            rbf::set_error("%s: non-finite residual (iteration %d)", what, it);
+            return RBF_E_NAN;
+        }
+        if (q[1] <= tol * tol * bb) return RBF_OK;
+        const double rho1 = q[0];
+        if (it > 0 && std::fabs(rho1) < 1e-300) break;
+        const double beta = (it == 0) ? 0.0 : (rho1 / rho) * (alpha / omega);
+        rho = rho1;
+        adj_axpby(S, n, 1.0, p, -omega, v, p);    // p - omega v
+        adj_axpby(S, n, 1.0, r, beta, p, p);      // r + beta (p - omega v)
+        if ((rc = prec(p, z)) != RBF_OK) return rc;
+        if ((rc = op(z, v)) != RBF_OK) return rc;
+        double rv;
+        if ((rc = adj_dots<1>(S, n, AdjDots{{rh}, {v}}, &rv)) != RBF_OK) return rc;
+        alpha = rho / rv;
+        adj_axpby(S, n, 1.0, r, -alpha, v, s);
+        adj_axpby(S, n, alpha, z, 1.0, x, x);     // x += alpha P p
+        if ((rc = prec(s, z)) != RBF_OK) return rc;
+        if ((rc = op(z, t)) != RBF_OK) return rc;
+        double ts[2];
+        if ((rc = adj_dots<2>(S, n, AdjDots{{t, t}, {s, t}}, ts)) != RBF_OK) return rc;
+        omega = (ts[1] != 0.0) ? ts[0] / ts[1] : 0.0;
+        adj_axpby(S, n, omega, z, 1.0, x, x);     // x += omega P s
+        adj_axpby(S, n, 1.0, s, -omega, t, r);
+        if (omega == 0.0) break;
+    }
+    // Final check of the true residual.
+    if ((rc = op(x, t)) != RBF_OK) return rc;
+    adj_axpby(S, n, 1.0, b, -1.0, t, t);
+    double rr;
+    if ((rc = adj_dots<1>(S, n, AdjDots{{t}, {t}}, &rr)) != RBF_OK) return rc;
+    if (rr <= 100.0 * tol * tol * bb) return RBF_OK;
+    rbf::set_error("%s: no convergence (relative residual %.3e after %d iterations)", what,
+                   std::sqrt(rr / bb), maxit);
+    return RBF_E_NOCONV;
+}
+
+}  // namespace
+
+extern "C" rbf_status rbf_adjoint_step(rbf_solver *S, const rbf_state *fwd, rbf_state *adj,
+                                       double *grad_bc, double *dnu) {
+    rbf::clear_error();
+    RBF_ARG(S && fwd && adj && grad_bc && dnu, "rbf_adjoint_step: NULL argument");
+    RBF_ARG(fwd->u && fwd->v && fwd->p_tilde && fwd->cu_prev && fwd->cv_prev,
+            "rbf_adjoint_step: NULL forward state array");
+    RBF_ARG(adj->u && adj->v && adj->p_tilde && adj->cu_prev && adj->cv_prev,
+            "rbf_adjoint_step: NULL adjoint state array");
+    rbf_status rc;
+    if (!S->adj.ready && (rc = adj_setup(S)) != RBF_OK) return rc;
+    auto &A = S->adj;
+    hipStream_t st = S->st;
+    const int64_t N = S->N, M = S->M;
+    const int k = S->k;
+    const double dt = S->dt, a = S->a;
+    const size_t nb = N * sizeof(double), mb = M * sizeof(double);
+    const bool first = fwd->step == 0;
+    // Forward step j -> j+1 again, from the caller's state, keeping u*, v*
+    // (S->us, S->vs) and u**, v** (S->hh[0] after the commit).
+    RBF_HIP(hipMemcpyAsync(S->u, fwd->u, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->v, fwd->v, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->cu, fwd->cu_prev, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->cv, fwd->cv_prev, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->pt, fwd->p_tilde, mb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(S->p_warm, fwd->p_tilde, mb, hipMemcpyDeviceToDevice, st));
+    S->have_prev = 0;
+    S->have_h = 0;
+    if ((rc = step_once(S, first, nullptr)) != RBF_OK) return rc;
+    const double *us = S->us, *vs = S->vs, *uss = S->hh[0], *vss = S->hh[0] + N;
+    double **V = A.vn, **P = A.pm;
+    double *ub = V[0], *vb = V[1], *rub = V[2], *rvb = V[3], *ri = V[4], *rw = V[5], *si = V[6],
+           *sw = V[7], *t1 = V[8], *t2 = V[9], *usb = V[10], *vsb = V[11], *cub = V[12],
+           *cvb = V[13], *qx = V[14], *qy = V[15], *px = V[16], *py = V[17], *t3 = V[18],
+           *t4 = V[19];
+    double *ptb = P[0], *y = P[1], *w = P[2], *fb = P[3], *m1 = P[4], *m2 = P[5];
+    RBF_HIP(hipMemcpyAsync(ub, adj->u, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(vb, adj->v, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(ptb, adj->p_tilde, mb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(cub, adj->cu_prev, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(cvb, adj->cv_prev, nb, hipMemcpyDeviceToDevice, st));
+    auto tvp = [&](const double *wt, const double *in, double *out) {  // out = D^VP^T in (M)
+        return rbf_ell_apply_transpose(M, A.cp_vp, A.src_vp, wt, in, out, 0, st);
+    };
+    auto tpv = [&](const double *wt, const double *in, double *out) {  // out = D^PV^T in (N)
+        return rbf_ell_apply_transpose(N, A.cp_pv, A.src_pv, wt, in, out, 0, st);
+    };
+    auto tvv = [&](const double *wt, const double *in, double *out) {  // out = D^VV^T in (N)
+        return rbf_ell_apply_transpose(N, A.cp_vv, A.src_vv, wt, in, out, 0, st);
+    };
+    auto fvv = [&](const double *wv, const double *in, double *out) {  // out = D^VV in
+        return rbf_ell_apply(N, k, S->idx_vv, wv, in, out, 0, st);
+    };
+#define ADJ(call)                           \
+    do {                                    \
+        if ((rc = (call)) != RBF_OK) return rc; \
+    } while (0)
+    // (20): p~_bar -= dt (Gx^T u_bar + Gy^T v_bar)
+    ADJ(tvp(A.dxT_vp, ub, m1));
+    ADJ(tvp(A.dyT_vp, vb, m2));
+    adj_axpby(S, M, -dt, m1, 1.0, ptb, ptb);
+    adj_axpby(S, M, -dt, m2, 1.0, ptb, ptb);
+    // (18): (A_s + u1 c 1^T)^T w = p~_bar - mean(p~_bar); rhs_bar = S w
+    double sm;
+    ADJ(adj_dots<1>(S, M, AdjDots{{ptb}, {nullptr}}, &sm));
+    hipLaunchKernelGGL(k_adj_addc, dim3(std::min<int64_t>(1024, rbf::blocks_for(M, 256))), dim3(256),
+                       0, st, M, -sm / (double)M, ptb);
+    RBF_HIP(hipMemcpyAsync(y, ptb, mb, hipMemcpyDeviceToDevice, st));
+    const double c = S->p_vscale;
+    auto pois_t = [&](const double *in, double *out) -> rbf_status {
+        double d;
+        rbf_status r2 = adj_dots<1>(S, M, AdjDots{{S->p_u1}, {in}}, &d);
+        if (r2 != RBF_OK) return r2;
+        r2 = rbf_ell_apply_transpose(M, A.cp_pp, A.src_pp, A.aT_pp, in, out, 0, st);
+        if (r2 != RBF_OK) return r2;
+        hipLaunchKernelGGL(k_adj_addc, dim3(std::min<int64_t>(1024, rbf::blocks_for(M, 256))),
+                           dim3(256), 0, st, M, c * d, out);
+        return RBF_OK;
+    };
+    ADJ(adj_bicgstab(S, M, pois_t, nullptr, y, w, 0.1 * S->rtol_p, std::max(S->maxit_p, 20000),
+                     "rbf_adjoint_step (transposed pressure solve)"));
+    hipLaunchKernelGGL(k_adj_fbar, dim3(std::min<int64_t>(1024, rbf::blocks_for(M, 256))), dim3(256),
+                       0, st, M, S->p_tag, S->p_rowscale, w, 1.0 / dt, fb);
+    // (17): u**_bar = u_bar + Dx^PV^T F_bar, v likewise
+    ADJ(tpv(A.dxT_pv, fb, t1));
+    ADJ(tpv(A.dyT_pv, fb, t2));
+    adj_axpby(S, N, 1.0, ub, 1.0, t1, t1);
+    adj_axpby(S, N, 1.0, vb, 1.0, t2, t2);
+    // (16): r_bar = H^-T u**_bar, H^T x = x - a L^T (chi x)
+    auto helm_t = [&](const double *in, double *out) -> rbf_status {
+        hipLaunchKernelGGL(k_adj_split, dim3(std::min<int64_t>(1024, rbf::blocks_for(N, 256))),
+                           dim3(256), 0, st, N, A.vtag, in, t3, t4);
+        rbf_status r2 = tvv(A.lapT_vv, t3, out);
+        if (r2 != RBF_OK) return r2;
+        adj_axpby(S, N, 1.0, in, -a, out, out);
+        return RBF_OK;
+    };
+    ADJ(adj_bicgstab(S, N, helm_t, S->h_dinv, t1, rub, S->rtol_h, std::max(S->maxit_h, 2000),
+                     "rbf_adjoint_step (transposed viscous solve, u)"));
+    ADJ(adj_bicgstab(S, N, helm_t, S->h_dinv, t2, rvb, S->rtol_h, std::max(S->maxit_h, 2000),
+                     "rbf_adjoint_step (transposed viscous solve, v)"));
+    const dim3 gN(std::min<int64_t>(1024, rbf::blocks_for(N, 256))), b256(256);
+    hipLaunchKernelGGL(k_adj_split, gN, b256, 0, st, N, A.vtag, rub, ri, rw);
+    hipLaunchKernelGGL(k_adj_split, gN, b256, 0, st, N, A.vtag, rvb, si, sw);
+    // d/d nu: dt/2 sum chi r_bar o L (u* + u**)
+    adj_axpby(S, N, 1.0, us, 1.0, uss, t1);
+    adj_axpby(S, N, 1.0, vs, 1.0, vss, t2);
+    ADJ(fvv(S->vv_lap, t1, t3));
+    ADJ(fvv(S->vv_lap, t2, t4));
+    double nq[2];
+    ADJ(adj_dots<2>(S, N, AdjDots{{ri, si}, {t3, t4}}, nq));
+    const double nub = 0.5 * dt * (nq[0] + nq[1]);
+    // (16) right-hand side: u*_bar = chi r + a L^T (chi r); wall rows (21)
+    ADJ(tvv(A.lapT_vv, ri, usb));
+    adj_axpby(S, N, 1.0, ri, a, usb, usb);
+    ADJ(tvv(A.lapT_vv, si, vsb));
+    adj_axpby(S, N, 1.0, si, a, vsb, vsb);
+    adj_axpby(S, N, 1.0, rw, 1.0, grad_bc, grad_bc);
+    adj_axpby(S, N, 1.0, sw, 1.0, grad_bc + N, grad_bc + N);
+    ADJ(tvp(A.dxT_vp, rw, m1));
+    ADJ(tvp(A.dyT_vp, sw, m2));
+    adj_axpby(S, M, dt, m1, dt, m2, m1);  // p~_j_bar
+    // (14): C_j_bar, C_{j-1}_bar (the caller's C_bar arrays were copied in
+    // above, so they can take C_{j-1}_bar now)
+    adj_axpby(S, N, 1.5 * dt, usb, 1.0, cub, cub);
+    adj_axpby(S, N, 1.5 * dt, vsb, 1.0, cvb, cvb);
+    if (first) {  // C_{-1} = C_0
+        adj_axpby(S, N, -0.5 * dt, usb, 1.0, cub, cub);
+        adj_axpby(S, N, -0.5 * dt, vsb, 1.0, cvb, cvb);
+        RBF_HIP(hipMemsetAsync(adj->cu_prev, 0, nb, st));
+        RBF_HIP(hipMemsetAsync(adj->cv_prev, 0, nb, st));
+    } else {
+        adj_axpby(S, N, -0.5 * dt, usb, 0.0, usb, adj->cu_prev);
+        adj_axpby(S, N, -0.5 * dt, vsb, 0.0, vsb, adj->cv_prev);
+    }
+    // (15): u_j_bar, v_j_bar
+    const double *uj = fwd->u, *vj = fwd->v;
+    ADJ(fvv(S->vv_dx, uj, t1));   // Dx u
+    ADJ(fvv(S->vv_dy, uj, t2));   // Dy u
+    ADJ(fvv(S->vv_dx, vj, t3));   // Dx v
+    ADJ(fvv(S->vv_dy, vj, t4));   // Dy v
+    hipLaunchKernelGGL(k_adj_adv, gN, b256, 0, st, N, uj, vj, t1, t2, t3, t4, cub, cvb, usb, vsb, qx,
+                       qy, px, py);
+    ADJ(tvv(A.dxT_vv, qx, t1));
+    ADJ(tvv(A.dyT_vv, qy, t2));
+    adj_axpby(S, N, -1.0, t1, 1.0, usb, usb);
+    adj_axpby(S, N, -1.0, t2, 1.0, usb, usb);
+    ADJ(tvv(A.dxT_vv, px, t1));
+    ADJ(tvv(A.dyT_vv, py, t2));
+    adj_axpby(S, N, -1.0, t1, 1.0, vsb, vsb);
+    adj_axpby(S, N, -1.0, t2, 1.0, vsb, vsb);
+#undef ADJ
+    // Outputs: adjoints of the state at j.
+    RBF_HIP(hipMemcpyAsync(adj->u, usb, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(adj->v, vsb, nb, hipMemcpyDeviceToDevice, st));
+    RBF_HIP(hipMemcpyAsync(adj->p_tilde, m1, mb, hipMemcpyDeviceToDevice, st));
+    RBF_CHECK_LAUNCH();
+    RBF_HIP(hipStreamSynchronize(st));
+    *dnu += nub;
+    return RBF_OK;
 }
 
 // Independent instances advanced concurrently: a pool of host threads takes
