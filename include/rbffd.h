@@ -55,7 +55,7 @@ typedef int32_t rbf_status;
 #define RBF_OP_DY 4u
 #define RBF_OP_LAP 8u
 
-#define RBF_ABI_VERSION 3
+#define RBF_ABI_VERSION 4
 
 typedef void *rbf_stream;
 
@@ -157,9 +157,17 @@ rbf_status rbf_knn_noalloc(const double *xq, int64_t nq, const double *xs, int64
  *
  * xq: device [2][nq]; xs: device [2][ns]; idx: device int32 [k][nq] (from
  * rbf_knn); w: device FP64 [popcount(op_mask)][k][nq], operators in
- * increasing bit order.  bad_row: host, set to the lowest row whose system
- * was numerically singular or non-finite, -1 if none (synchronises the
- * stream to read it back).
+ * increasing bit order.  cond_est: NULL, or device FP64 [nq] that receives
+ * an estimate of the 1-norm condition number ||A_aug||_1 ||A_aug^-1||_1 of
+ * each local system in the shifted and scaled coordinates it is solved in
+ * (the conditioning studied in Sec. 4): ||A_aug||_1 exactly, times Hager's
+ * lower estimate of ||A_aug^-1||_1 with Higham's safeguards (LAPACK xLACON's
+ * method; usually exact, never above the true value up to rounding, and
+ * within a factor of a few in practice), computed from the same LU factors
+ * with at most 11 extra triangular solves per row; NaN for rows reported
+ * bad.  bad_row: host, set to the lowest row whose system was numerically
+ * singular or non-finite, -1 if none (synchronises the stream to read it
+ * back).
  * Limits: 1 <= k, k + (q+1)(q+2)/2 <= 64, q in [-1, 5] (-1: no polynomials),
  * m odd in [1, 11] (m >= 3 for derivative operators), and
  * k >= (q+1)(q+2) (stability rule of Sec. 4) unless op_mask has bit 31 set.
@@ -171,7 +179,8 @@ rbf_status rbf_knn_noalloc(const double *xq, int64_t nq, const double *xs, int64
 #define RBF_FORCE_SMALL_STENCIL 0x80000000u
 rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const double *xs, int64_t ns,
                                 const int32_t *idx, int32_t k, int32_t m, int32_t q,
-                                uint32_t op_mask, double *w, int64_t *bad_row, rbf_stream st);
+                                uint32_t op_mask, double *w, double *cond_est, int64_t *bad_row,
+                                rbf_stream st);
 
 /*
  * rbf_ell_apply -- y = D x for one ELL operator (eq. (10) applied to a vector).
@@ -295,9 +304,14 @@ typedef struct {
  *        forms the residual b - A x in FP64 from the FP64 weights, runs
  *        flexible GMRES on FP32-stored weights, vectors and transforms (FP64
  *        dot products) until the residual drops by 1e-4 or the cycle ends,
- *        and adds the correction to the FP64 iterate.  The weights, the
- *        outer residuals, the projection and the tolerance stay FP64, so
- *        the fields differ from FP64 runs at the tolerance level. */
+ *        and adds the correction to the FP64 iterate.  The viscous solve,
+ *        when H's Jacobi bound is at most 0.25 (rbf_solver_query), is FP32
+ *        inside FP64 refinement too: each outer step forms b - H x in FP64,
+ *        runs two FP32 Jacobi sweeps on FP32-stored weights for the
+ *        correction and adds it to the FP64 iterate; otherwise it stays
+ *        FP64.  The weights, the outer residuals, the projection and the
+ *        tolerances stay FP64, so the fields differ from FP64 runs at the
+ *        tolerance level. */
 #define RBF_PRECISION_FP64 0
 #define RBF_PRECISION_MIXED 1
 
@@ -476,7 +490,9 @@ rbf_status rbf_solver_profile(rbf_solver *s, int32_t sample_every, double *avg_m
  * viscous_jacobi 1 when the viscous solve uses Jacobi sweeps (see
  * rbf_solver_create), jacobi_bound the infinity norm of I - D^-1 H that
  * decided it, lattice_precond 1 when the pressure solve uses the lattice
- * preconditioner.  Errors: RBF_E_ARG (NULL argument).
+ * preconditioner, viscous_mixed 1 when the viscous solve runs FP32 sweeps
+ * inside FP64 iterative refinement (RBF_PRECISION_MIXED with
+ * viscous_jacobi set).  Errors: RBF_E_ARG (NULL argument).
  */
 typedef struct {
     int32_t viscous_jacobi;
@@ -484,6 +500,7 @@ typedef struct {
     double jacobi_bound;
     int32_t aux_precond;   /* 1: auxiliary-lattice preconditioner with FGMRES */
     int32_t aux_cells;     /* its lattice cells per side (0 if unused)       */
+    int32_t viscous_mixed; /* 1: FP32 viscous sweeps inside FP64 refinement  */
 } rbf_solver_info;
 rbf_status rbf_solver_query(rbf_solver *s, rbf_solver_info *info);
 

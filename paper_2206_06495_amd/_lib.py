@@ -78,7 +78,7 @@ class Diagnostics(ctypes.Structure):
 class SolverInfo(ctypes.Structure):
     _fields_ = [("viscous_jacobi", ctypes.c_int32), ("lattice_precond", ctypes.c_int32),
                 ("jacobi_bound", ctypes.c_double), ("aux_precond", ctypes.c_int32),
-                ("aux_cells", ctypes.c_int32)]
+                ("aux_cells", ctypes.c_int32), ("viscous_mixed", ctypes.c_int32)]
 
 
 class StepStats(ctypes.Structure):
@@ -112,7 +112,7 @@ def _load():
     lib.rbf_assemble_weights.restype = S
     lib.rbf_assemble_weights.argtypes = [c_void_p, ctypes.c_int64, c_void_p, ctypes.c_int64,
                                          c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                         ctypes.c_uint32, c_void_p, c_int64_p, c_void_p]
+                                         ctypes.c_uint32, c_void_p, c_void_p, c_int64_p, c_void_p]
     lib.rbf_ell_apply.restype = S
     lib.rbf_ell_apply.argtypes = [ctypes.c_int64, ctypes.c_int32, c_void_p, c_void_p, c_void_p,
                                   c_void_p, ctypes.c_int32, c_void_p]

@@ -68,8 +68,11 @@ def knn(xq, xs, k):
     return idx
 
 
-def assemble_weights(xq, xs, idx, m=7, q=3, op_mask=OP_DX | OP_DY | OP_LAP, force=False):
-    """FP64 weights [nops, k, nq] for the operators in op_mask (bit order)."""
+def assemble_weights(xq, xs, idx, m=7, q=3, op_mask=OP_DX | OP_DY | OP_LAP, force=False,
+                     cond=False):
+    """FP64 weights [nops, k, nq] for the operators in op_mask (bit order);
+    with cond=True also the FP64 [nq] 1-norm condition estimates of the local
+    systems, returned as (w, cond_est)."""
     _dev(xq, torch.float64, name="xq")
     _dev(xs, torch.float64, name="xs")
     _dev(idx, torch.int32, name="idx")
@@ -80,9 +83,11 @@ def assemble_weights(xq, xs, idx, m=7, q=3, op_mask=OP_DX | OP_DY | OP_LAP, forc
     w = torch.empty((max(nops, 1), k, nq), dtype=torch.float64, device=xq.device)
     bad = ctypes.c_int64(-1)
     mask = op_mask | (_lib.FORCE_SMALL_STENCIL if force else 0)
+    c = torch.empty(nq, dtype=torch.float64, device=xq.device) if cond else None
     check(lib.rbf_assemble_weights(_ptr(xq), nq, _ptr(xs), xs.shape[1], _ptr(idx), k, m, q,
-                                   ctypes.c_uint32(mask), _ptr(w), ctypes.byref(bad), _stream()))
-    return w
+                                   ctypes.c_uint32(mask), _ptr(w), _ptr(c) if cond else None,
+                                   ctypes.byref(bad), _stream()))
+    return (w, c) if cond else w
 
 
 def ell_apply(idx, w, x, out=None):
@@ -250,12 +255,13 @@ class Solver:
 
     def info(self):
         """How the solves run: {"viscous_jacobi", "lattice_precond", "jacobi_bound",
-        "aux_precond", "aux_cells"}."""
+        "aux_precond", "aux_cells", "viscous_mixed"}."""
         inf = _lib.SolverInfo()
         check(lib.rbf_solver_query(self._h, ctypes.byref(inf)))
         return {"viscous_jacobi": bool(inf.viscous_jacobi),
                 "lattice_precond": bool(inf.lattice_precond), "jacobi_bound": inf.jacobi_bound,
-                "aux_precond": bool(inf.aux_precond), "aux_cells": int(inf.aux_cells)}
+                "aux_precond": bool(inf.aux_precond), "aux_cells": int(inf.aux_cells),
+                "viscous_mixed": bool(inf.viscous_mixed)}
 
     def run(self, state, nsteps, every=10, log=None):
         """Advance `state` by `nsteps` in rbf_step calls of `every` steps and,

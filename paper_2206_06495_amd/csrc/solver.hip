@@ -1699,6 +1699,7 @@ __global__ void k_wall_list(int64_t n, const int8_t *__restrict__ tag, int *__re
 
 #include "pressure_aux.h"
 #include "adjoint.h"
+#include "viscous_mixed.h"
 
 }  // namespace
 
@@ -1754,6 +1755,8 @@ struct rbf_solver {
     HKry hk{};           // viscous solve with explicit vectors
     JKry jk{};           // viscous solve by Jacobi sweeps
     bool h_jacobi = false;  // Jacobi bound of H <= kJacobiMax
+    HMix hm{};           // mixed precision: FP32 sweeps inside FP64 refinement
+    bool h_mixed = false;
     double h_bound = 0.0;
     Lat lat{};
     PKry pk{};
@@ -2196,6 +2199,95 @@ rbf_status hjacobi(rbf_solver *S, EllM A, const double *b, double *x, double tol
         rc = RBF_E_NAN;
     } else if (f != 1) {
         rbf::set_error("Jacobi sweeps: no convergence (%d of %d sweeps)", it, maxit);
+        rc = RBF_E_NOCONV;
+    }
+    last_iters = fin;
+    return rc;
+}
+
+// Mixed-precision viscous solve (see k_hm_res): outer FP64 residuals with
+// FP32 sweeps between them; same contract as hjacobi, with iterations
+// counting outer refinement steps.
+rbf_status hmixed(rbf_solver *S, EllM A, const double *b, double *x, double tol, int maxit,
+                  int &last_iters, rbf_solve_stats *stats) {
+    hipStream_t st = S->st;
+    HMix X = S->hm;
+    const int64_t n = A.n;
+    const int nb = nblocks_rows(n);
+    const dim3 grid(nb), block(kThreads);
+    const double tol2 = tol * tol;
+    const bool k28 = A.k == 28;
+    hipLaunchKernelGGL(k_hm_clear, dim3(1), dim3(64), 0, st, X.flag);
+    auto sweeps = [&](int i) {
+        for (int s = 0; s < kHMixSweeps; ++s) {
+            const bool test = s == 0, last = s == kHMixSweeps - 1;
+#define HM_SWEEP(KT, T, L) hipLaunchKernelGGL((k_hm_sweep<KT, T, L>), grid, block, 0, st, X, i, s, tol2, nb)
+            if (k28) {
+                if (test && last) HM_SWEEP(28, true, true);
+                else if (test) HM_SWEEP(28, true, false);
+                else if (last) HM_SWEEP(28, false, true);
+                else HM_SWEEP(28, false, false);
+            } else {
+                if (test && last) HM_SWEEP(0, true, true);
+                else if (test) HM_SWEEP(0, true, false);
+                else if (last) HM_SWEEP(0, false, true);
+                else HM_SWEEP(0, false, false);
+            }
+#undef HM_SWEEP
+        }
+    };
+    // Outer iteration i launches r_i (tested by the sweep after it) and its
+    // sweeps; iteration maxit only tests.
+    int i = 0, f = 0;
+    int batch = std::max(1, last_iters + 1);
+    for (;;) {
+        const int stop = std::min(maxit + 1, i + batch);
+        for (; i < stop; ++i) {
+            if (i == 0) {
+                if (k28) hipLaunchKernelGGL((k_hm_res<28, true>), grid, block, 0, st, A, b, x, X, i);
+                else hipLaunchKernelGGL((k_hm_res<0, true>), grid, block, 0, st, A, b, x, X, i);
+            } else {
+                if (k28) hipLaunchKernelGGL((k_hm_res<28, false>), grid, block, 0, st, A, b, x, X, i);
+                else hipLaunchKernelGGL((k_hm_res<0, false>), grid, block, 0, st, A, b, x, X, i);
+            }
+            sweeps(i);
+        }
+        RBF_CHECK_LAUNCH();
+        RBF_HIP(hipMemcpyAsync(S->hflag, X.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        f = S->hflag[0];
+        if (f != 0 || i > maxit) break;
+        batch = 1;
+    }
+    // The iterate X.x is x_fin when accepted (the sweeps after the test exit).
+    const int fin = (f != 0) ? S->hflag[1] : maxit;
+    hipLaunchKernelGGL(k_h_deint, dim3(rbf::blocks_for(n, 256)), dim3(256), 0, st, n, X.x, x);
+    RBF_CHECK_LAUNCH();
+    const double *pf = X.part + (int64_t)(fin & 1) * 2 * kHR * kMaxBlocks;
+    for (int c = 0; c < 2 * kHR; ++c)
+        RBF_HIP(hipMemcpyAsync(S->hred + c * nb, pf + (int64_t)c * kMaxBlocks, nb * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+    RBF_HIP(hipStreamSynchronize(st));
+    rbf_status rc = RBF_OK;
+    for (int c = 0; c < kHR; ++c) {
+        double rr = 0.0, bb = 0.0;
+        for (int bidx = 0; bidx < nb; ++bidx) {
+            rr += S->hred[c * nb + bidx];
+            bb += S->hred[(kHR + c) * nb + bidx];
+        }
+        if (stats) {
+            stats[c].iterations = fin;
+            stats[c].converged = (f == 1);
+            stats[c].rel_residual = (bb > 0.0) ? std::sqrt(rr / bb) : std::sqrt(rr);
+            stats[c].restarts = 0;
+            stats[c].final_flag = f;
+        }
+    }
+    if (f == -1) {
+        rbf::set_error("mixed-precision viscous solve: non-finite residual (outer step %d)", fin);
+        rc = RBF_E_NAN;
+    } else if (f != 1) {
+        rbf::set_error("mixed-precision viscous solve: no convergence (%d outer steps)", maxit);
         rc = RBF_E_NOCONV;
     }
     last_iters = fin;
@@ -3111,6 +3203,28 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
         S->h_bound = bound;
         S->h_jacobi = bound <= kJacobiMax;
     }
+    if (S->mixed && S->h_jacobi) {
+        HMix &X = S->hm;
+        float *w32 = nullptr, *d32 = nullptr;
+        ALLOC(w32, (int64_t)k * N);
+        ALLOC(d32, N);
+        ALLOC(X.x, N);
+        ALLOC(X.r, N);
+        ALLOC(X.d[0], N);
+        ALLOC(X.d[1], N);
+        ALLOC(X.part, 2 * 2 * kHR * kMaxBlocks);
+        ALLOC(X.flag, 2);
+        const dim3 gc(rbf::blocks_for((int64_t)k * N, 256)), bc(256);
+        hipLaunchKernelGGL(k_aux_to_f32, gc, bc, 0, st, (int64_t)k * N, S->h_w, w32);
+        hipLaunchKernelGGL(k_aux_to_f32, dim3(rbf::blocks_for(N, 256)), bc, 0, st, N, S->h_dinv, d32);
+        RBF_CHECK_LAUNCH();
+        X.idx = S->idx_vv;
+        X.w32 = w32;
+        X.dinv32 = d32;
+        X.n = N;
+        X.k = k;
+        S->h_mixed = true;
+    }
     // Scale of the zero-mean border: v = gamma / M with gamma = 1 / mean |u1|
     // over interior rows, so the border couples at the scale of the rows.
     std::vector<double> hu(M);
@@ -3171,7 +3285,9 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
     RBF_CHECK_LAUNCH();
     rbf_solve_stats hs[2];
     EllM H{S->idx_vv, S->h_w, S->h_dinv, N, k, nullptr, 0.0};
-    rbf_status rc = S->h_jacobi
+    rbf_status rc = S->h_mixed
+                        ? hmixed(S, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h, S->last_iters_h, hs)
+                    : S->h_jacobi
                         ? hjacobi(S, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h, S->last_iters_h, hs)
                         : hbicgstab(S, H, S->hrhs, S->uvss, S->rtol_h, S->maxit_h, S->last_iters_h, hs);
     if (stats) {
@@ -3789,6 +3905,7 @@ extern "C" rbf_status rbf_solver_query(rbf_solver *S, rbf_solver_info *info) {
     rbf::clear_error();
     RBF_ARG(S && info, "rbf_solver_query: NULL argument");
     info->viscous_jacobi = S->h_jacobi ? 1 : 0;
+    info->viscous_mixed = S->h_mixed ? 1 : 0;
     info->lattice_precond = S->pc_on ? 1 : 0;
     info->jacobi_bound = S->h_bound;
     info->aux_precond = S->aux_on ? 1 : 0;

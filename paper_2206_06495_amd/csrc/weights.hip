@@ -25,6 +25,16 @@
 // r^m = (d^2)^((m-1)/2) * r as a left-to-right product chain.
 // A system is reported singular when a pivot is not larger than
 // 16 eps max|A_aug| (e.g. duplicated stencil nodes) or a weight is not finite.
+//
+// Optional 1-norm condition estimate of the local system (Sec. 4 studies the
+// conditioning of these matrices): ||A_aug||_1 exactly (A_aug is symmetric,
+// so its largest absolute column sum is its largest absolute row sum) times a
+// lower estimate of ||A_aug^-1||_1 from Hager's method with Higham's
+// safeguards (Hager 1984; Higham 1988, ACM TOMS 14, the algorithm of
+// LAPACK's xLACON): at most five power-like steps x -> sign(A^-1 x) ->
+// A^-T sign(..) -> unit vector at the largest entry, then the alternating
+// test vector.  A^-T = A^-1 here, so every step is one solve with the LU
+// factors.
 #include <climits>
 
 #include "common.h"
@@ -71,6 +81,110 @@ __device__ __forceinline__ void mono_exp(int t, int &a, int &b) {
     while ((d + 1) * (d + 2) / 2 <= t) ++d;
     b = t - d * (d + 1) / 2;
     a = d - b;
+}
+
+// Wave-uniform sum of v over the 64 lanes (lane 0's butterfly result).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return readlane_d(v, 0);
+}
+
+// Lane index of the largest |v| among lanes < s (lowest lane on ties),
+// wave-uniform.
+__device__ __forceinline__ int wave_argmax_abs(double v, int lane, int s) {
+    double c = (lane < s) ? fabs(v) : -1.0;
+    int cl = lane;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(c, off, 64);
+        const int ol = __shfl_xor(cl, off, 64);
+        const bool take = ov > c || (ov == c && ol < cl);
+        c = take ? ov : c;
+        cl = take ? ol : cl;
+    }
+    return __builtin_amdgcn_readfirstlane(cl);
+}
+
+// Solve A x = r with the factors of k_weights' LU: lane i holds r_i and
+// receives x_i (0 beyond s).  a holds the multipliers of the steps that
+// eliminated this lane's row and its row of U; pl[kk] is the lane that
+// pivoted at step kk.
+template <int SMAX>
+__device__ __forceinline__ double lu_solve_lane(double r, const double (&a)[SMAX], int mystep,
+                                                double myinv, const int *pl, int s, int lane) {
+#pragma unroll
+    for (int kk = 0; kk < SMAX; ++kk) {
+        if (kk < s) {
+            const double yk = readlane_d(r, pl[kk]);
+            if (mystep > kk && mystep != INT_MAX) r = fma(-a[kk], yk, r);
+        }
+    }
+    double x = 0.0;
+#pragma unroll
+    for (int kk = SMAX - 1; kk >= 0; --kk) {
+        if (kk < s) {
+            const double xk = readlane_d(r * myinv, pl[kk]);
+            if (mystep < kk) r = fma(-a[kk], xk, r);
+            if (lane == kk) x = xk;
+        }
+    }
+    return x;
+}
+
+// Lower estimate of ||A^-1||_1 for the factored symmetric A (size s).
+// One solve per pass of the loop; `state` follows the steps of the method.
+template <int SMAX>
+__device__ double inv_norm1_estimate(const double (&a)[SMAX], int mystep, double myinv,
+                                     const int *pl, int s, int lane) {
+    const bool live = lane < s;
+    double x = live ? 1.0 / (double)s : 0.0;
+    double est = 0.0, xi = 0.0;
+    int state = 1, iter = 0, j = 0;
+    for (int pass = 0; pass < 16 && state != 0; ++pass) {
+        const double y = lu_solve_lane<SMAX>(x, a, mystep, myinv, pl, s, lane);
+        const double sg = (y >= 0.0) ? 1.0 : -1.0;
+        if (state == 1) {  // y = A^-1 (1/s): first estimate, then z = A^-T sign(y)
+            est = wave_sum(fabs(y));
+            xi = live ? sg : 0.0;
+            x = xi;
+            state = 2;
+        } else if (state == 2) {  // y holds z: restart from the unit vector at max |z|
+            j = wave_argmax_abs(y, lane, s);
+            iter = 2;
+            x = (lane == j) ? 1.0 : 0.0;
+            state = 3;
+        } else if (state == 3) {  // y = A^-1 e_j
+            const double old = est;
+            est = wave_sum(fabs(y));
+            const bool same = __all(!live || sg == xi);
+            if (same || est <= old) {
+                state = 5;
+                x = live ? ((lane & 1) ? -1.0 : 1.0) * (1.0 + (double)lane / (double)(s - 1)) : 0.0;
+            } else {
+                xi = live ? sg : 0.0;
+                x = xi;
+                state = 4;
+            }
+        } else if (state == 4) {  // y holds z = A^-T sign(..)
+            const int jlast = j;
+            j = wave_argmax_abs(y, lane, s);
+            const double zl = readlane_d(fabs(y), jlast), zj = readlane_d(fabs(y), j);
+            if (zl != zj && iter < 5) {
+                ++iter;
+                x = (lane == j) ? 1.0 : 0.0;
+                state = 3;
+            } else {
+                state = 5;
+                x = live ? ((lane & 1) ? -1.0 : 1.0) * (1.0 + (double)lane / (double)(s - 1)) : 0.0;
+            }
+        } else {  // state 5: alternating test vector
+            const double t = 2.0 * wave_sum(fabs(y)) / (3.0 * (double)s);
+            est = fmax(est, t);
+            state = 0;
+        }
+    }
+    return est;
 }
 
 // L applied to phi(||x - x_j||) at x_0 = 0, for a stencil node at (x, y).
@@ -120,6 +234,7 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
                                                 const double *__restrict__ xs, int64_t ns,
                                                 const int *__restrict__ idx, int n, int m, int q,
                                                 OpSet ops, double *__restrict__ w,
+                                                double *__restrict__ cond,
                                                 unsigned long long *__restrict__ bad) {
     __shared__ double sx[64], sy[64];
     __shared__ double sol[kMaxOps][SMAX];
@@ -185,6 +300,15 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
     const double tiny = 16.0 * __DBL_EPSILON__ * amax;
+    double anorm = 0.0;  // ||A_aug||_1 (largest absolute row sum; A_aug symmetric)
+    if (cond) {
+        double rs = 0.0;
+#pragma unroll
+        for (int j = 0; j < SMAX; ++j) rs += fabs(a[j]);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off, 64));
+        anorm = readlane_d(rs, 0);
+    }
 
     // 3. LU with partial pivoting across lanes.
     int mystep = (lane < s) ? INT_MAX : -1;  // INT_MAX: row not yet a pivot
@@ -315,6 +439,11 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
     }
     // A row is bad if any lane saw a problem.
     const bool any_bad = __any(bad_row);
+    if (cond) {
+        double c = NAN;
+        if (!any_bad) c = anorm * inv_norm1_estimate<SMAX>(a, mystep, myinv, pl, s, lane);
+        if (lane == 0) cond[row] = c;
+    }
     if (any_bad) {
         if (lane < n) {
             for (int o = 0; o < ops.n; ++o) w[((int64_t)o * n + lane) * nq + row] = NAN;
@@ -328,7 +457,7 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
 extern "C" rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const double *xs,
                                            int64_t ns, const int32_t *idx, int32_t k, int32_t m,
                                            int32_t q, uint32_t op_mask, double *w,
-                                           int64_t *bad_row, rbf_stream st_) {
+                                           double *cond_est, int64_t *bad_row, rbf_stream st_) {
     rbf::clear_error();
     const bool force = (op_mask & RBF_FORCE_SMALL_STENCIL) != 0;
     op_mask &= ~RBF_FORCE_SMALL_STENCIL;
@@ -364,10 +493,10 @@ extern "C" rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const d
     if (e == hipSuccess) {
         if (k + kp <= 40)
             hipLaunchKernelGGL(k_weights<40>, dim3((uint32_t)nq), dim3(64), 0, st, xq, nq, xs, ns,
-                               idx, k, m, q, ops, w, dbad);
+                               idx, k, m, q, ops, w, cond_est, dbad);
         else
             hipLaunchKernelGGL(k_weights<64>, dim3((uint32_t)nq), dim3(64), 0, st, xq, nq, xs, ns,
-                               idx, k, m, q, ops, w, dbad);
+                               idx, k, m, q, ops, w, cond_est, dbad);
         e = hipGetLastError();
     }
     unsigned long long hb = ~0ull;

@@ -159,6 +159,41 @@ def test_aux_cavity_parity(P, gpu, precision, tol):
     S.close()
 
 
+def test_mixed_viscous_refinement_parity(P, gpu):
+    """Mixed precision with the viscous solve in FP32 sweeps inside FP64
+    refinement as well (H's Jacobi bound 0.0035 at K = 60, Re = 1e4,
+    dt = 2e-4): u, v, p, p~ against the oracle every 50 steps over 100 steps
+    within 1e-8, and against the FP64 GPU run."""
+    _say("mixed viscous refinement K=60")
+    nd = ri.hex_cavity_nodes(60, 0.3, 0)
+    S, ops, u_bc, v_bc = _solver(P, nd, gpu, 1e4, 2e-4, precision="mixed")
+    F, _, _, _ = _solver(P, nd, gpu, 1e4, 2e-4, precision="fp64")
+    inf = S.info()
+    assert inf["viscous_jacobi"] and inf["viscous_mixed"] and inf["aux_precond"], inf
+    assert not F.info()["viscous_mixed"]
+    orc = ocav.CavityOracle(nd, u_bc, v_bc, 1e4, 2e-4)
+    so = orc.initial_state()
+    st = S.new_state(to_dev(so.u, gpu), to_dev(so.v, gpu))
+    sf = F.new_state(to_dev(so.u, gpu), to_dev(so.v, gpu))
+    worst = worst_f = 0.0
+    for _ in range(2):
+        stats = S.step(st, 50)
+        F.step(sf, 50)
+        so = orc.run(50, so)
+        for key, ref in (("u", so.u), ("v", so.v), ("p", so.p), ("p_tilde", so.pt)):
+            got = st[key].cpu().numpy()
+            e = rel_err(got, ref)
+            ef = rel_err(got, sf[key].cpu().numpy())
+            worst, worst_f = max(worst, e), max(worst_f, ef)
+            assert e <= 1e-8 and ef <= 1e-8, (st["step"], key, e, ef)
+        h = stats.last_helmholtz_u
+        assert h.converged and h.rel_residual <= 1e-13, (h.iterations, h.rel_residual)
+    _say("worst vs oracle", worst, "vs FP64 run", worst_f,
+         "viscous outer steps per time step", stats.helmholtz_iters / 50)
+    S.close()
+    F.close()
+
+
 def test_aux_iterations_flat_in_h(P, gpu):
     """Preconditioner applications of a cold pressure solve (random right-hand
     side, rtol 1e-10) stay near 80-90 from h = 1/50 to h = 1/200 (the

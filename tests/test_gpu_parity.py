@@ -105,17 +105,20 @@ def test_weights_out_of_range_index_reported(P, gpu):
     idx[2, 40] = -1           # negative
     idx[0, 90] = 2 ** 31 - 1  # far out
     w = torch.empty((1, 28, n), dtype=torch.float64, device=gpu)
+    c = torch.empty(n, dtype=torch.float64, device=gpu)
     bad = ctypes.c_int64(-7)
     rc = _lib.lib.rbf_assemble_weights(ctypes.c_void_p(d.data_ptr()), n,
                                        ctypes.c_void_p(d.data_ptr()), n,
                                        ctypes.c_void_p(idx.data_ptr()), 28, 7, 3, 2,
-                                       ctypes.c_void_p(w.data_ptr()), ctypes.byref(bad), None)
+                                       ctypes.c_void_p(w.data_ptr()),
+                                       ctypes.c_void_p(c.data_ptr()), ctypes.byref(bad), None)
     torch.cuda.synchronize()
     assert rc == _lib.RBF_E_SINGULAR
     assert bad.value == 11
     wh = w.cpu().numpy()[0]
+    ch = c.cpu().numpy()
     for r in (11, 40, 90):
-        assert np.isnan(wh[:, r]).all()
+        assert np.isnan(wh[:, r]).all() and np.isnan(ch[r])
     keep = np.setdiff1d(np.arange(n), [11, 40, 90])
     assert np.array_equal(wh[:, keep], good[0][:, keep])
 
@@ -152,6 +155,34 @@ def test_weights_parameter_variants(P, gpu, n, m, q, mask):
     ref = ow.stencil_weights(xq, xs, idx.cpu().numpy(), m, q, ops, force=True)
     for o in range(len(ops)):
         assert row_rel_err(w[o], ref[o]) <= 1e-12, (ops[o], row_rel_err(w[o], ref[o]))
+
+
+@pytest.mark.parametrize("n,m,q", [(28, 7, 3), (12, 3, 1), (40, 7, 4), (28, 7, -1)])
+def test_weights_condition_estimate(P, gpu, n, m, q):
+    """cond_est (Sec. 4's conditioning of the local systems) against the
+    1-norm condition number of the oracle's augmented matrix in the same
+    local coordinates, numpy.linalg.cond(A_aug, 1): Hager's estimate is a
+    lower bound of ||A^-1||_1, usually exact; the weights do not change when
+    the estimate is asked for."""
+    _say("weights condition estimate", n, m, q)
+    nd = ri.cavity_nodes(12, 0.3, 2)
+    xq, xs = nd.xv, nd.xp
+    dq, ds = to_dev(xq, gpu), to_dev(xs, gpu)
+    idx = P.knn(dq, ds, n)
+    force = q >= 0 and n < (q + 1) * (q + 2)
+    w0 = P.assemble_weights(dq, ds, idx, m, q, 6, force=force)
+    w1, c = P.assemble_weights(dq, ds, idx, m, q, 6, force=force, cond=True)
+    assert bool((w0 == w1).all())
+    est = c.cpu().numpy()
+    xt, yt, _ = ow.local_coordinates(xq, xs, idx.cpu().numpy())
+    A, _ = ow.augmented_system(xt, yt, m, q, [ow.OP_DX, ow.OP_DY])
+    true = np.linalg.cond(A, 1)
+    ratio = est / true
+    _say("cond range", true.min(), true.max(), "ratio min/median", ratio.min(), np.median(ratio))
+    assert np.all(np.isfinite(est))
+    assert ratio.max() <= 1.0 + 1e-3
+    assert ratio.min() >= 0.1
+    assert np.mean(ratio >= 0.5) >= 0.9
 
 
 def test_weights_argument_checks(P, gpu):
@@ -214,7 +245,7 @@ def test_weights_bench_square_sampled(P, gpu):
 def test_stencils_and_weights_graded_cylinder_nodes(P, gpu):
     """The graded cylinder-in-channel node set of the paper's second workload
     (spacing 0.02 on the cylinder growing to 0.25 at the channel ends;
-    132,691 P + 397,064 V nodes): kNN and weights for all four pairs on the
+    132,692 P + 397,066 V nodes): kNN and weights for all four pairs on the
     GPU, checked on 400 sampled rows per pair (the 100 nearest the cylinder,
     the channel edges and random rows) against the oracle: stencils bit for
     bit, weights within 1e-12 per row."""
