@@ -33,6 +33,10 @@ Workload (one JSON line on stdout):
     sin(kx)cos(ky), k = 2 pi {4, 16, 64}, over interior rows and over all
     rows; the distribution of the 1-norm condition estimates of the VV
     systems.
+  * cylinder: flow past a cylinder (Sec. 5.2) on the graded channel set
+    (N = 397,066 V + M = 132,692 P), Re = 100, dt = 2e-3, uniform inflow,
+    symmetry sides, convective outflow; `cyl_steps` steps from an impulsive
+    start, node-steps/s and the drag and lift coefficients every 10 steps.
   * cpu_baseline: the CPU oracle (SciPy sparse LU solves, as the paper's
     factor-once scheme) on a bounded sample of the headline workload: the
     same node kind, Re, dt, jitter and stencils at h = 1/100 (`--cpu-K`;
@@ -94,6 +98,11 @@ def parse():
                     help="independent cavities of the concurrent-instance run (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-threads", type=int, default=8)
+    ap.add_argument("--no-cylinder", action="store_true",
+                    help="skip the cylinder-flow leg")
+    ap.add_argument("--cyl-steps", type=int, default=50)
+    ap.add_argument("--cyl-re", type=float, default=100.0)
+    ap.add_argument("--cyl-dt", type=float, default=2e-3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy first (HBM counter calibration)")
     return ap.parse_args()
@@ -108,17 +117,12 @@ def dev_tensor(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-def cavity_setup(P, args, dev, precision="fp64", kind=2, precond="auto"):
-    """Nodes (rbf_build_nodes `kind`), stencils, weights and the solver, on
-    the device; returns the solver, a rest state, the nodes and the set-up
-    time."""
-    import torch
-    nodes = P.build_nodes(kind, args.K, args.jitter, args.seed)
-    t0 = time.perf_counter()
-    g = {k: dev_tensor(v, dev) for k, v in nodes.items()}
+def build_ops(P, xv, xp):
+    """28-point stencils and PHS r^7 + cubic weights of the four stencil
+    sets (VV: D_x, D_y, Lap; PV: D_x, D_y; PP: D_x, D_y, Lap; VP: D_x, D_y)."""
     ops = {"k": 28}
-    for name, xq, xs, mask in (("vv", g["xv"], g["xv"], 14), ("pv", g["xp"], g["xv"], 6),
-                               ("pp", g["xp"], g["xp"], 14), ("vp", g["xv"], g["xp"], 6)):
+    for name, xq, xs, mask in (("vv", xv, xv, 14), ("pv", xp, xv, 6),
+                               ("pp", xp, xp, 14), ("vp", xv, xp, 6)):
         idx = P.knn(xq, xs, 28)
         w = P.assemble_weights(xq, xs, idx, 7, 3, mask)
         ops["idx_" + name] = idx
@@ -127,6 +131,18 @@ def cavity_setup(P, args, dev, precision="fp64", kind=2, precond="auto"):
         if mask & 8:
             ops[name + "_lap"] = w[2].contiguous()
         del w
+    return ops
+
+
+def cavity_setup(P, args, dev, precision="fp64", kind=2, precond="auto"):
+    """Nodes (rbf_build_nodes `kind`), stencils, weights and the solver, on
+    the device; returns the solver, a rest state, the nodes and the set-up
+    time."""
+    import torch
+    nodes = P.build_nodes(kind, args.K, args.jitter, args.seed)
+    t0 = time.perf_counter()
+    g = {k: dev_tensor(v, dev) for k, v in nodes.items()}
+    ops = build_ops(P, g["xv"], g["xp"])
     vt = nodes["v_tag"]
     u_bc = np.where(vt == 2, 1.0, 0.0)
     S = P.Solver(g, ops, dev_tensor(u_bc, dev), dev_tensor(np.zeros_like(u_bc), dev),
@@ -406,6 +422,59 @@ def batch_run(P, args, dev):
                     "rbf_step_batch"}
 
 
+def cylinder_run(P, args, dev):
+    """Flow past a cylinder (Sec. 5.2) on the graded channel nodes of
+    rbf_inputs.cylinder_nodes (channel [-10, 30] x [-10, 10], spacing 0.02
+    on the cylinder): uniform inflow, symmetry sides, convective outflow,
+    impulsive start from U_0 = (1, 0); `cyl_steps` timed steps after 5, with
+    drag and lift (rbf_solver_forces, Simpson's rule) every 10 steps."""
+    import torch
+    import rbf_inputs as ri
+    nd = ri.cylinder_nodes()
+    xv, xp = dev_tensor(nd.xv, dev), dev_tensor(nd.xp, dev)
+    grid = {"xv": xv, "xp": xp, "v_tag": torch.from_numpy(nd.v_tag).to(dev),
+            "p_tag": torch.from_numpy(nd.p_tag).to(dev), "p_normal": dev_tensor(nd.p_normal, dev)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ops = build_ops(P, xv, xp)
+    u_bc = np.where(nd.v_tag == 3, 1.0, 0.0)
+    S = P.Solver(grid, ops, dev_tensor(u_bc, dev), dev_tensor(np.zeros(nd.n_v), dev),
+                 args.cyl_re, args.cyl_dt, u_conv=1.0)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    u0 = np.where(nd.v_tag == 1, 0.0, 1.0)
+    st = S.new_state(dev_tensor(u0, dev), dev_tensor(np.zeros(nd.n_v), dev))
+    out = {"workload": f"cylinder D=1 in [-10,30]x[-10,10], N={S.N} V + M={S.M} P graded from "
+                       f"0.02 on the cylinder, Re={args.cyl_re:g}, dt={args.cyl_dt:g}, uniform "
+                       "inflow, symmetry sides, convective outflow, impulsive start",
+           "setup_s": setup_s, "aux_lattice_cells": S.info()["aux_cells"]}
+    try:
+        S.step(st, 5)
+        torch.cuda.synchronize()
+        series = []
+        t0 = time.perf_counter()
+        iters = 0
+        for c in range(0, args.cyl_steps, 10):
+            n = min(10, args.cyl_steps - c)
+            s = S.step(st, n)
+            iters += s.poisson_iters
+            fx, fy = S.forces(grid, st)
+            series.append({"step": int(st["step"]), "t": st["step"] * args.cyl_dt,
+                           "C_D": 2.0 * fx, "C_L": 2.0 * fy})
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out.update({"value": (S.N + S.M) * args.cyl_steps / el, "unit": "node-steps/s",
+                    "ms_per_step": el / args.cyl_steps * 1e3, "steps": args.cyl_steps,
+                    "poisson_fgmres_steps_per_step": iters / args.cyl_steps,
+                    "forces": series, "final_state": S.diagnostics(st)})
+    except P.RbfError as e:
+        out["error"] = f"step {st['step']}: {e}"
+    S.close()
+    log(f"cylinder: {out.get('value', float('nan')):.3e} node-steps/s "
+        f"{out.get('forces', [{}])[-1] if out.get('forces') else out.get('error')}")
+    return out
+
+
 def lattice_run(P, args, dev):
     """The right-triangle lattice cavity (node kind 0) of the same h with the
     lattice fast-Poisson preconditioner and BiCGSTAB (context only: the
@@ -543,6 +612,10 @@ def main():
     if not args.no_lattice:
         log("right-triangle lattice cavity K =", args.K)
         out["lattice"] = lattice_run(P, args, dev)
+        torch.cuda.empty_cache()
+    if not args.no_cylinder:
+        log("cylinder flow")
+        out["cylinder"] = cylinder_run(P, args, dev)
         torch.cuda.empty_cache()
     if args.batch > 0:
         log("concurrent instances:", args.batch)

@@ -263,12 +263,27 @@ rbf_status rbf_ell_apply_transpose(int64_t ncols, const int64_t *colptr, const i
  * Fractional-step solver (Sec. 3).
  * ------------------------------------------------------------------------- */
 
+/* V-node tags with a boundary condition other than Dirichlet values (the
+ * channel of Sec. 5.2; every boundary row enters u** through the Kim-Moin
+ * form of eq. (21), u** = u_bc^{j+1} + dt D^VP p~_j, with u_bc^{j+1}):
+ *   RBF_VTAG_OUTFLOW   convective outflow dq/dt + u_conv dq/dx = 0 for
+ *                      q = u, v, explicit Euler from step j:
+ *                      q_bc = q_j - dt u_conv (D_x^VV q_j);
+ *   RBF_VTAG_SYMMETRY  v_bc = 0 and u_bc from du/dy = 0: the node's own
+ *                      D_y^VV row solved for its value with the neighbours'
+ *                      values at step j.
+ * Any other non-zero tag is a Dirichlet row with the values u_bc, v_bc
+ * given to rbf_solver_create (inflow, no slip, a moving lid). */
+#define RBF_VTAG_OUTFLOW 4
+#define RBF_VTAG_SYMMETRY 5
+
 /* Node sets and boundary data, all device memory. */
 typedef struct {
     int64_t n_v, n_p;
     const double *xv;       /* [2][n_v]                                      */
     const double *xp;       /* [2][n_p]                                      */
-    const int8_t *v_tag;    /* [n_v]: 0 interior, != 0 wall (Dirichlet)     */
+    const int8_t *v_tag;    /* [n_v]: 0 interior, RBF_VTAG_OUTFLOW,
+                               RBF_VTAG_SYMMETRY, other != 0 Dirichlet     */
     const int8_t *p_tag;    /* [n_p]: 0 interior, != 0 wall (Neumann)        */
     const double *p_normal; /* [2][n_p] outward unit normal at wall P-nodes  */
 } rbf_grid;
@@ -293,6 +308,7 @@ typedef struct {
     int32_t maxit_p;
     int32_t precision;/* RBF_PRECISION_*                                     */
     int32_t precond;  /* pressure-solve preconditioner, RBF_PRECOND_*        */
+    double u_conv;    /* convection velocity of RBF_VTAG_OUTFLOW rows        */
 } rbf_params;
 
 /* rbf_params.precision:
@@ -522,6 +538,25 @@ typedef struct {
     double div_max, div_rms, kinetic_energy, speed_max, cfl;
 } rbf_diagnostics;
 rbf_status rbf_solver_diagnostics(rbf_solver *s, const rbf_state *state, rbf_diagnostics *out);
+
+/*
+ * rbf_solver_forces -- force on a circular body (Sec. 5.2: drag and lift of
+ * the cylinder): F = closed integral over the body of
+ * (-p I + (1/Re)(grad U + grad U^T)) n ds, n the unit normal pointing out of
+ * the body, the pressure p of the state (eq. (19)) taken at the P-nodes
+ * tagged `tag`, the velocity gradients (D_x^VV, D_y^VV rows) at the V-nodes
+ * tagged `tag`; each set is ordered by its angle about (cx, cy) in
+ * [0, 2 pi) and integrated by the periodic composite Simpson's rule (4/3
+ * and 2/3 of the angle step, 2/3 at the first node, times `radius`), so
+ * both counts must be even and the nodes equally spaced in angle.
+ * C_D = 2 F_x / (rho U^2 D) and C_L likewise.  grid: the solver's node sets
+ * (device; read at the first call and when tag or circle change); state:
+ * device u, v, p.  force: host [2] = (F_x, F_y).  Synchronises the solver's
+ * stream.  Errors: RBF_E_ARG (NULL argument, sizes differing from the
+ * solver's, tag 0, a non-finite circle, odd or zero counts).
+ */
+rbf_status rbf_solver_forces(rbf_solver *s, const rbf_grid *grid, const rbf_state *state,
+                             int32_t tag, double cx, double cy, double radius, double *force);
 
 /*
  * rbf_adjoint_step -- reverse-mode derivative of one rbf_step (the stages of

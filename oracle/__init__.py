@@ -15,8 +15,10 @@ Modules
   cavity     fractional-step solver (Sec. 3, eqs. (14)-(21)) with LU solves
   metrics    test-function error and modified wavenumber (Sec. 4, eqs. (22)-(24))
   adjoint    reverse-mode derivative of the cavity step (transposed stages)
+  cylinder   the step on the cylinder channel (Sec. 5.2): open boundary rows,
+             drag and lift by Simpson's rule
 """
-from . import knn, weights, operators, cavity, metrics, adjoint  # noqa: F401
+from . import knn, weights, operators, cavity, metrics, adjoint, cylinder  # noqa: F401
 
 OP_ID = 1
 OP_DX = 2

@@ -27,7 +27,7 @@ EXPORTED = [
     "rbf_assemble_weights", "rbf_ell_apply", "rbf_cast_f32", "rbf_ell_transpose",
     "rbf_ell_transpose_weights", "rbf_ell_apply_transpose", "rbf_solver_create",
     "rbf_step", "rbf_step_batch", "rbf_solve_pressure", "rbf_solver_apply_precond", "rbf_solver_profile", "rbf_solver_query",
-    "rbf_solver_diagnostics", "rbf_adjoint_step",
+    "rbf_solver_diagnostics", "rbf_solver_forces", "rbf_adjoint_step",
     "rbf_solver_destroy",
 ]
 
@@ -55,7 +55,8 @@ class Params(ctypes.Structure):
     _fields_ = [("re", ctypes.c_double), ("dt", ctypes.c_double),
                 ("rtol_h", ctypes.c_double), ("rtol_p", ctypes.c_double),
                 ("maxit_h", ctypes.c_int32), ("maxit_p", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("u_conv", ctypes.c_double)]
 
 
 class State(ctypes.Structure):
@@ -149,6 +150,10 @@ def _load():
     lib.rbf_solver_diagnostics.restype = S
     lib.rbf_solver_diagnostics.argtypes = [c_void_p, ctypes.POINTER(State),
                                            ctypes.POINTER(Diagnostics)]
+    lib.rbf_solver_forces.restype = S
+    lib.rbf_solver_forces.argtypes = [c_void_p, ctypes.POINTER(Grid), ctypes.POINTER(State),
+                                      ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     lib.rbf_adjoint_step.restype = S
     lib.rbf_adjoint_step.argtypes = [c_void_p, ctypes.POINTER(State), ctypes.POINTER(State),
                                      c_void_p, c_double_p]

@@ -177,7 +177,7 @@ class Solver:
     PRECISION = {"fp64": 0, "mixed": 1}
 
     def __init__(self, grid, ops, u_bc, v_bc, re, dt, rtol_h=1e-13, rtol_p=1e-12,
-                 maxit_h=2000, maxit_p=20000, precond="auto", precision="fp64"):
+                 maxit_h=2000, maxit_p=20000, precond="auto", precision="fp64", u_conv=1.0):
         N = grid["xv"].shape[1]
         M = grid["xp"].shape[1]
         self.N, self.M = N, M
@@ -201,7 +201,8 @@ class Solver:
             "idx_vv", "vv_dx", "vv_dy", "vv_lap", "idx_pv", "pv_dx", "pv_dy",
             "idx_pp", "pp_dx", "pp_dy", "pp_lap", "idx_vp", "vp_dx", "vp_dy")])
         prm = _lib.Params(float(re), float(dt), float(rtol_h), float(rtol_p), int(maxit_h),
-                          int(maxit_p), self.PRECISION[precision], self.PRECOND[precond])
+                          int(maxit_p), self.PRECISION[precision], self.PRECOND[precond],
+                          float(u_conv))
         h = ctypes.c_void_p()
         check(lib.rbf_solver_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(o),
                                     _ptr(u_bc), _ptr(v_bc), ctypes.byref(prm), _stream()))
@@ -252,6 +253,18 @@ class Solver:
         cnt = (ctypes.c_int64 * 4)()
         check(lib.rbf_solver_profile(self._h, int(sample_every), avg, cnt))
         return {name: (avg[q], cnt[q]) for q, name in enumerate(("gemm", "spmv", "smooth", "gs"))}
+
+    def forces(self, grid, state, tag=1, center=(0.0, 0.0), radius=0.5):
+        """(F_x, F_y) on the circular body whose nodes carry `tag`
+        (rbf_solver_forces); C_D, C_L = 2 F / (rho U^2 D)."""
+        g = _lib.Grid(self.N, self.M, grid["xv"].data_ptr(), grid["xp"].data_ptr(),
+                      grid["v_tag"].data_ptr(), grid["p_tag"].data_ptr(),
+                      grid["p_normal"].data_ptr())
+        st = self._state_struct(state)
+        f = (ctypes.c_double * 2)()
+        check(lib.rbf_solver_forces(self._h, ctypes.byref(g), ctypes.byref(st), int(tag),
+                                    float(center[0]), float(center[1]), float(radius), f))
+        return f[0], f[1]
 
     def info(self):
         """How the solves run: {"viscous_jacobi", "lattice_precond", "jacobi_bound",

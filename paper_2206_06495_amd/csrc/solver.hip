@@ -1505,7 +1505,44 @@ __global__ void __launch_bounds__(kThreads) k_helm_rhs(int64_t n, int k, const i
     x0[n + r] = rv;
 }
 
-// Kim-Moin wall values (eq. (21)): u** = u_bc + dt D_x^VP p~_j, v** likewise.
+// Open boundary rows (channel flows; the cavity has none).  Tag
+// RBF_VTAG_OUTFLOW: convective outflow dq/dt + uc dq/dx = 0, explicit Euler
+// from step j: q_bc = q_j - dt uc (D_x^VV q_j) for q = u, v.  Tag
+// RBF_VTAG_SYMMETRY: v_bc = 0 and u_bc solves the node's own D_y^VV row for
+// du/dy = 0 with the neighbours' values at step j.
+struct OpenBc {
+    const int8_t *vtag;     // [N] V-node tags (nullptr: no open rows)
+    const int *idx;         // (V,V) stencils
+    const double *wdx, *wdy;
+    const double *u, *v;    // state at step j
+    double uc;              // convection velocity of the outflow rows
+};
+
+template <int KT>
+__device__ __forceinline__ void open_bc_values(const OpenBc &B, int64_t n, int k, int64_t r,
+                                               double &ub, double &vb, double dt) {
+    const int t = B.vtag[r];
+    if (t == RBF_VTAG_OUTFLOW) {
+        double acc[1][2] = {};
+        const double *ws[1] = {B.wdx};
+        rbf::ell_row<KT, 1>(B.idx, ws, n, r, k, Gather2{B.u, B.v}, acc);
+        ub = B.u[r] - dt * B.uc * acc[0][0];
+        vb = B.v[r] - dt * B.uc * acc[0][1];
+    } else if (t == RBF_VTAG_SYMMETRY) {
+        double diag = 0.0, off = 0.0;
+        for (int q = 0; q < k; ++q) {
+            const int j = B.idx[(int64_t)q * n + r];
+            const double w = B.wdy[(int64_t)q * n + r];
+            if (j == r) diag += w;
+            else off = fma(w, B.u[j], off);
+        }
+        ub = -off / diag;
+        vb = 0.0;
+    }
+}
+
+// Kim-Moin wall values (eq. (21)): u** = u_bc + dt D_x^VP p~_j, v** likewise,
+// with u_bc, v_bc of the open rows computed from the state at step j.
 template <int KT>
 __global__ void __launch_bounds__(kThreads) k_wall_rhs(int64_t nwall, const int *__restrict__ rows,
                                                         int64_t n, int k, const int *__restrict__ idx,
@@ -1515,14 +1552,16 @@ __global__ void __launch_bounds__(kThreads) k_wall_rhs(int64_t nwall, const int 
                                                         const double *__restrict__ u_bc,
                                                         const double *__restrict__ v_bc, double dt,
                                                         double *__restrict__ rhs,
-                                                        double *__restrict__ x0) {
+                                                        double *__restrict__ x0, OpenBc B) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nwall) return;
     const int64_t r = rows[i];
     double acc[2][1] = {};
     const double *ws[2] = {wdx, wdy};
     rbf::ell_row<KT, 2>(idx, ws, n, r, k, GatherN<1>{pt, 0}, acc);
-    const double ru = u_bc[r] + dt * acc[0][0], rv = v_bc[r] + dt * acc[1][0];
+    double ub = u_bc[r], vb = v_bc[r];
+    if (B.vtag) open_bc_values<KT>(B, n, k, r, ub, vb, dt);
+    const double ru = ub + dt * acc[0][0], rv = vb + dt * acc[1][0];
     rhs[r] = ru;
     rhs[n + r] = rv;
     x0[r] = ru;
@@ -1725,6 +1764,15 @@ struct rbf_solver {
     double p_vscale = 0.0;
     int8_t *p_tag = nullptr;
     int *wall_rows = nullptr;
+    int8_t *v_tag_open = nullptr;  // [N] V tags when open boundary rows exist
+    struct Forces {  // body rows and quadrature of rbf_solver_forces (cached)
+        bool ready = false;
+        int tag = 0, np = 0, nv = 0, cap = 0;
+        double cx = 0, cy = 0, radius = 0;
+        int *prow = nullptr, *vrow = nullptr;
+        double *pq = nullptr, *vq = nullptr, *out = nullptr;
+    } forces;
+    double u_conv = 0.0;           // convection velocity of outflow rows
     double *u_bc = nullptr, *v_bc = nullptr;
     double *v_hmin = nullptr;    // [N] nearest stencil-neighbour distance (CFL)
     double *diag_part = nullptr; // [5][kMaxBlocks] diagnostics partials
@@ -2780,19 +2828,21 @@ rbf_status setup_aux_pc(rbf_solver *S, const rbf_grid *g, int mode) {
         y0 = std::min(y0, hx[M + v]);
         y1 = std::max(y1, hx[M + v]);
     }
-    const double side = std::max(x1 - x0, y1 - y0);
-    const bool square = side > 0.0 && std::fabs((x1 - x0) - (y1 - y0)) <= 1e-9 * side;
+    const double wx = x1 - x0, wy = y1 - y0;
+    // Ka x Ka cells over the bounding box (cells of wx/Ka by wy/Ka; the
+    // box's aspect ratio is limited so that the cells stay usable).
+    const bool box_ok = wx > 0.0 && wy > 0.0 && wx <= 8.0 * wy && wy <= 8.0 * wx;
     // About two node spacings per lattice cell (M ~ 1.15 K^2 nodes on a
     // near-equilateral set of spacing 1/K: Ka ~ K / 2).
     int Ka = (int)std::llround(0.465 * std::sqrt((double)M));
     Ka = std::max(4, std::min(Ka, 64 * kTriChunk + 1));
-    if (!square || M < 64) {
+    if (!box_ok || M < 64) {
         RBF_ARG(mode != RBF_PRECOND_AUX,
-                "rbf_solver_create: RBF_PRECOND_AUX needs P-nodes whose bounding box is a square");
+                "rbf_solver_create: RBF_PRECOND_AUX needs P-nodes whose bounding box has sides within a factor 8 of each other");
         return RBF_OK;
     }
     const int n = Ka - 1, K1 = Ka + 1;
-    const double h = side / Ka;
+    const double hxa = wx / Ka, hya = wy / Ka;
     // Cells and bilinear coordinates of every node; restriction lists of the
     // interior lattice points from the interior nodes.
     std::vector<int> cell(M);
@@ -2800,7 +2850,7 @@ rbf_status setup_aux_pc(rbf_solver *S, const rbf_grid *g, int mode) {
     std::vector<int> cnt((size_t)n * n + 1, 0);
     auto corner_q = [&](int i, int j) { return (i >= 1 && i <= Ka - 1 && j >= 1 && j <= Ka - 1) ? (i - 1) * n + (j - 1) : -1; };
     for (int64_t v = 0; v < M; ++v) {
-        const double sx = (hx[v] - x0) / h, sy = (hx[M + v] - y0) / h;
+        const double sx = (hx[v] - x0) / hxa, sy = (hx[M + v] - y0) / hya;
         const int i0 = std::min(std::max((int)std::floor(sx), 0), Ka - 1);
         const int j0 = std::min(std::max((int)std::floor(sy), 0), Ka - 1);
         cell[v] = j0 * K1 + i0;
@@ -2833,6 +2883,9 @@ rbf_status setup_aux_pc(rbf_solver *S, const rbf_grid *g, int mode) {
         for (int e = rptr[q]; e < rptr[q + 1]; ++e) rval[e] = (wsum[q] > 0.0) ? rval[e] / wsum[q] : 0.0;
     std::vector<double> Q, Qi, lam;
     dct2_basis(n, Q, Qi, lam);
+    // Anisotropic cells: (T_x / hx^2 + T_y / hy^2) e = g becomes, per x-mode
+    // k, (T_y + (hy/hx)^2 lam_k) w = hy^2 t.
+    for (double &l : lam) l *= (hya / hxa) * (hya / hxa);
     const size_t nn = (size_t)n * n;
     const int nt = (n + 15) / 16;
     Lat &L = S->lat;
@@ -2878,7 +2931,7 @@ rbf_status setup_aux_pc(rbf_solver *S, const rbf_grid *g, int mode) {
     RBF_HIP(hipMemsetAsync(L.X, 0, nn * es, st));
     L.K = Ka;
     L.n = n;
-    L.h = h;
+    L.h = hya;
     L.c = S->p_vscale * kAuxBorder;  // the FGMRES operator's border scale
     L.rs = S->p_rowscale;
     L.cell = dcell;
@@ -3188,6 +3241,20 @@ rbf_status create_impl(rbf_solver *S, const rbf_grid *g, const rbf_ops *o, const
     RBF_ARG(herr[0] == 0, "rbf_solver_create: a %s stencil does not contain its own node (or a zero row)",
             (herr[0] & 1) ? "(V,V)" : "(P,P)");
     S->nwall = herr[1];
+    {  // open boundary rows (outflow, symmetry): keep the tags on the device
+        std::vector<int8_t> vt(N);
+        RBF_HIP(hipMemcpyAsync(vt.data(), g->v_tag, N, hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        bool open = false;
+        for (int64_t r = 0; r < N && !open; ++r)
+            open = vt[r] == RBF_VTAG_OUTFLOW || vt[r] == RBF_VTAG_SYMMETRY;
+        if (open) {
+            RBF_ARG(std::isfinite(prm->u_conv), "rbf_solver_create: u_conv must be finite");
+            ALLOC(S->v_tag_open, N);
+            RBF_HIP(hipMemcpyAsync(S->v_tag_open, vt.data(), N, hipMemcpyHostToDevice, st));
+            S->u_conv = prm->u_conv;
+        }
+    }
     {  // infinity norm of the Jacobi iteration matrix of H
         const int nbb = (int)rbf::blocks_for(N, 256);
         double *bpart;
@@ -3280,7 +3347,9 @@ rbf_status step_once(rbf_solver *S, bool first, rbf_step_stats *stats) {
             hipLaunchKernelGGL((k_wall_rhs<decltype(KT)::value>),
                                dim3(rbf::blocks_for(S->nwall, 64)), dim3(64), 0, st, S->nwall,
                                S->wall_rows, N, k, S->idx_vp, S->vp_dx, S->vp_dy, S->pt, S->u_bc,
-                               S->v_bc, S->dt, S->hrhs, S->uvss);
+                               S->v_bc, S->dt, S->hrhs, S->uvss,
+                               OpenBc{S->v_tag_open, S->idx_vv, S->vv_dx, S->vv_dy, S->u, S->v,
+                                      S->u_conv});
         });
     RBF_CHECK_LAUNCH();
     rbf_solve_stats hs[2];
@@ -3598,6 +3667,7 @@ extern "C" rbf_status rbf_adjoint_step(rbf_solver *S, const rbf_state *fwd, rbf_
                                        double *grad_bc, double *dnu) {
     rbf::clear_error();
     RBF_ARG(S && fwd && adj && grad_bc && dnu, "rbf_adjoint_step: NULL argument");
+    RBF_ARG(!S->v_tag_open, "rbf_adjoint_step: needs Dirichlet boundary rows only (no outflow or symmetry rows)");
     RBF_ARG(fwd->u && fwd->v && fwd->p_tilde && fwd->cu_prev && fwd->cv_prev,
             "rbf_adjoint_step: NULL forward state array");
     RBF_ARG(adj->u && adj->v && adj->p_tilde && adj->cu_prev && adj->cv_prev,
@@ -3857,6 +3927,143 @@ extern "C" rbf_status rbf_solver_apply_precond(rbf_solver *S, const double *y, d
     hipLaunchKernelGGL(k_pc_post, dim3(nb), dim3(kThreads), 0, st, S->lat, S->pk, y, z, m,
                        S->pk.partS, S->pk.partGs, nb);
     RBF_CHECK_LAUNCH();
+    RBF_HIP(hipStreamSynchronize(st));
+    return RBF_OK;
+}
+
+namespace {
+
+// Force on a body (rbf_solver_forces): pressure part over the body's
+// P-nodes, viscous part over its V-nodes; each node carries its quadrature
+// weight and the unit normal pointing out of the body.  One workgroup, fixed
+// summation order.
+template <int KT>
+__global__ void __launch_bounds__(256) k_forces(int np, const int *__restrict__ prow,
+                                                const double *__restrict__ pq, int nv,
+                                                const int *__restrict__ vrow,
+                                                const double *__restrict__ vq, int64_t n, int k,
+                                                const int *__restrict__ idx,
+                                                const double *__restrict__ wdx,
+                                                const double *__restrict__ wdy,
+                                                const double *__restrict__ u,
+                                                const double *__restrict__ v,
+                                                const double *__restrict__ p, double inv_re,
+                                                double *out) {
+    double f[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        const double w = pq[3 * i], nx = pq[3 * i + 1], ny = pq[3 * i + 2];
+        const double pv = p[prow[i]];
+        f[0] -= w * pv * nx;
+        f[1] -= w * pv * ny;
+    }
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        const double w = vq[3 * i], nx = vq[3 * i + 1], ny = vq[3 * i + 2];
+        double g[2][2] = {};
+        const double *ws[2] = {wdx, wdy};
+        rbf::ell_row<KT, 2>(idx, ws, n, vrow[i], k, Gather2{u, v}, g);
+        // g[0] = (u_x, v_x), g[1] = (u_y, v_y)
+        const double sxy = g[1][0] + g[0][1];
+        f[0] += w * inv_re * (2.0 * g[0][0] * nx + sxy * ny);
+        f[1] += w * inv_re * (sxy * nx + 2.0 * g[1][1] * ny);
+    }
+    __shared__ double lds[2 * (256 / 64)];
+    rbf::block_sum<2>(f, lds);
+    if (threadIdx.x == 0) {
+        out[0] = f[0];
+        out[1] = f[1];
+    }
+}
+
+// Rows of one tag ordered by angle about (cx, cy) in [0, 2 pi), with their
+// periodic composite Simpson weight (4/3, 2/3 of the angle step times the
+// radius, 2/3 at the first) and outward body normal (cos, sin of the
+// angle).  False if the count is odd or zero.
+bool ring_rule(const std::vector<double> &xy, int64_t n, const std::vector<int8_t> &tag, int t,
+               double cx, double cy, double radius, std::vector<int> &rows,
+               std::vector<double> &q) {
+    std::vector<std::pair<double, int>> a;
+    const double two_pi = 6.283185307179586476925;
+    for (int64_t r = 0; r < n; ++r) {
+        if (tag[r] != t) continue;
+        double th = std::atan2(xy[n + r] - cy, xy[r] - cx);
+        if (th < 0.0) th += two_pi;
+        a.push_back({th, (int)r});
+    }
+    if (a.empty() || (a.size() % 2) != 0) return false;
+    std::stable_sort(a.begin(), a.end(),
+                     [](const std::pair<double, int> &l, const std::pair<double, int> &r) { return l.first < r.first; });
+    const double d = two_pi / (double)a.size();
+    rows.resize(a.size());
+    q.resize(3 * a.size());
+    for (size_t i = 0; i < a.size(); ++i) {
+        rows[i] = a[i].second;
+        q[3 * i] = ((i % 2) ? 4.0 * d / 3.0 : 2.0 * d / 3.0) * radius;
+        q[3 * i + 1] = std::cos(a[i].first);
+        q[3 * i + 2] = std::sin(a[i].first);
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" rbf_status rbf_solver_forces(rbf_solver *S, const rbf_grid *g, const rbf_state *state,
+                                        int32_t tag, double cx, double cy, double radius,
+                                        double *force) {
+    rbf::clear_error();
+    RBF_ARG(S && g && state && force && state->u && state->v && state->p && g->xv && g->xp &&
+                g->v_tag && g->p_tag,
+            "rbf_solver_forces: NULL argument");
+    RBF_ARG(g->n_v == S->N && g->n_p == S->M, "rbf_solver_forces: grid sizes differ from the solver's");
+    RBF_ARG(tag != 0 && std::isfinite(cx) && std::isfinite(cy) && std::isfinite(radius) && radius > 0.0,
+            "rbf_solver_forces: tag must be non-zero and the circle finite");
+    hipStream_t st = S->st;
+    auto &F = S->forces;
+    if (!F.ready || F.tag != tag || F.cx != cx || F.cy != cy || F.radius != radius) {
+        const int64_t N = S->N, M = S->M;
+        std::vector<double> xv(2 * N), xp(2 * M);
+        std::vector<int8_t> tv(N), tp(M);
+        RBF_HIP(hipMemcpyAsync(xv.data(), g->xv, 2 * N * sizeof(double), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipMemcpyAsync(xp.data(), g->xp, 2 * M * sizeof(double), hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipMemcpyAsync(tv.data(), g->v_tag, N, hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipMemcpyAsync(tp.data(), g->p_tag, M, hipMemcpyDeviceToHost, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        std::vector<int> pr, vr;
+        std::vector<double> pq, vq;
+        RBF_ARG(ring_rule(xp, M, tp, tag, cx, cy, radius, pr, pq) &&
+                    ring_rule(xv, N, tv, tag, cx, cy, radius, vr, vq),
+                "rbf_solver_forces: the body's P-nodes and V-nodes must be non-empty even counts (composite Simpson's rule)");
+        if (F.cap < (int)std::max(pr.size(), vr.size())) {
+            const int cap = (int)std::max(pr.size(), vr.size());
+            ALLOC(F.prow, cap);
+            ALLOC(F.vrow, cap);
+            ALLOC(F.pq, 3 * cap);
+            ALLOC(F.vq, 3 * cap);
+            ALLOC(F.out, 2);
+            F.cap = cap;
+        }
+        RBF_HIP(hipMemcpyAsync(F.prow, pr.data(), pr.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        RBF_HIP(hipMemcpyAsync(F.vrow, vr.data(), vr.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        RBF_HIP(hipMemcpyAsync(F.pq, pq.data(), pq.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        RBF_HIP(hipMemcpyAsync(F.vq, vq.data(), vq.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        RBF_HIP(hipStreamSynchronize(st));
+        F.np = (int)pr.size();
+        F.nv = (int)vr.size();
+        F.tag = tag;
+        F.cx = cx;
+        F.cy = cy;
+        F.radius = radius;
+        F.ready = true;
+    }
+    if (S->k == 28)
+        hipLaunchKernelGGL(k_forces<28>, dim3(1), dim3(256), 0, st, F.np, F.prow, F.pq, F.nv, F.vrow,
+                           F.vq, S->N, S->k, S->idx_vv, S->vv_dx, S->vv_dy, state->u, state->v,
+                           state->p, 1.0 / S->re, F.out);
+    else
+        hipLaunchKernelGGL(k_forces<0>, dim3(1), dim3(256), 0, st, F.np, F.prow, F.pq, F.nv, F.vrow,
+                           F.vq, S->N, S->k, S->idx_vv, S->vv_dx, S->vv_dy, state->u, state->v,
+                           state->p, 1.0 / S->re, F.out);
+    RBF_CHECK_LAUNCH();
+    RBF_HIP(hipMemcpyAsync(force, F.out, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     RBF_HIP(hipStreamSynchronize(st));
     return RBF_OK;
 }

@@ -251,14 +251,15 @@ def cylinder_nodes(h_wall=0.02, grading=0.008, h_far=0.5, box=(-10.0, 30.0, -10.
     1 at the origin, in the channel ``box``), graded from spacing ``h_wall``
     on the cylinder to at most ``h_far`` with h(r) = min(h_far, h_wall +
     grading (r - 1/2)): P-nodes on rings of radius r_k (r_0 = 1/2, r_{k+1} =
-    r_k + h(r_k) sqrt(3)/2, round(2 pi r_k / h(r_k)) nodes, every other ring
+    r_k + h(r_k) sqrt(3)/2, round(2 pi r_k / h(r_k)) nodes (an even number,
+    2 round(pi r_0 / h(r_0)), on the cylinder itself), every other ring
     rotated by half a spacing) clipped to the channel, plus channel-edge
     nodes at the local spacing; the Delaunay triangulation of those vertices
     without the triangles inside the cylinder gives the edges, and V-nodes
     are their midpoints.  Deterministic (no random draws).  Tags: 0
     interior, 1 cylinder, 3 inflow (x = x0), 4 outflow (x = x1), 5 sides
     (y = y0, y1; corners count as sides).  P normals point out of the fluid.
-    The defaults give 132,691 P- and 397,064 V-nodes."""
+    The defaults give 132,692 P- and 397,066 V-nodes."""
     from scipy.spatial import Delaunay
     x0, x1, y0, y1 = box
     hr = lambda r: np.minimum(h_far, h_wall + grading * (r - 0.5))  # noqa: E731
@@ -268,6 +269,8 @@ def cylinder_nodes(h_wall=0.02, grading=0.008, h_far=0.5, box=(-10.0, 30.0, -10.
     while r < rmax:
         h = float(hr(r))
         n = max(8, int(round(2 * np.pi * r / h)))
+        if k == 0:  # an even count on the cylinder (composite Simpson's rule)
+            n = 2 * max(4, int(round(np.pi * r / h)))
         th = (np.arange(n) + 0.5 * (k % 2)) * (2 * np.pi / n)
         x, y = r * np.cos(th), r * np.sin(th)
         if k > 0:  # interior rings: clear of the channel edges by half a spacing

@@ -53,7 +53,7 @@ def test_cylinder_node_layout():
     assert np.all((x >= -10) & (x <= 30) & (np.abs(y) <= 10))
     assert np.all(r >= 0.5 - 1e-12)
     cyl = nd.p_tag == ri.nodes.TAG_CYLINDER
-    assert np.allclose(r[cyl], 0.5, rtol=0, atol=1e-14) and cyl.sum() == round(np.pi / h_wall)
+    assert np.allclose(r[cyl], 0.5, rtol=0, atol=1e-14) and cyl.sum() == 2 * round(np.pi * 0.5 / h_wall)
     from scipy.spatial import cKDTree
     d, _ = cKDTree(nd.xp.T).query(nd.xp.T, 2)
     h = np.minimum(0.5, h_wall + g * (r - 0.5))
