@@ -56,6 +56,59 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Cross-lane reductions without LDS traffic: DPP moves inside each 16-lane
+// row (rotations by 8 and 4, then quad swaps of 2 and 1 leave every lane of
+// a row with the row's result), then the four rows' results read by
+// v_readlane and combined uniformly.  Exact maxima, so the reduction order
+// does not matter; ties of the arg-max go to the lowest lane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void dpp_argmax_step(double &c, int &cl) {
+    const double ov = dpp_d<CTRL>(c);
+    const int ol = __builtin_amdgcn_update_dpp(0, cl, CTRL, 0xF, 0xF, false);
+    const bool take = ov > c || (ov == c && ol < cl);
+    c = take ? ov : c;
+    cl = take ? ol : cl;
+}
+
+constexpr int kDppRor8 = 0x128, kDppRor4 = 0x124, kDppSwap2 = 0x4E, kDppSwap1 = 0xB1;
+
+// Lane of the largest c over the wave (lowest lane on ties), wave-uniform.
+__device__ __forceinline__ int wave_argmax(double c, int lane) {
+    int cl = lane;
+    dpp_argmax_step<kDppRor8>(c, cl);
+    dpp_argmax_step<kDppRor4>(c, cl);
+    dpp_argmax_step<kDppSwap2>(c, cl);
+    dpp_argmax_step<kDppSwap1>(c, cl);
+    double bv = readlane_d(c, 0);
+    int bl = __builtin_amdgcn_readlane(cl, 0);
+#pragma unroll
+    for (int r = 16; r < 64; r += 16) {
+        const double v = readlane_d(c, r);
+        const int l = __builtin_amdgcn_readlane(cl, r);
+        const bool take = v > bv || (v == bv && l < bl);
+        bv = take ? v : bv;
+        bl = take ? l : bl;
+    }
+    return __builtin_amdgcn_readfirstlane(bl);
+}
+
+// Largest v over the wave (fmax: NaN only if every lane is NaN), uniform.
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, dpp_d<kDppRor8>(v));
+    v = fmax(v, dpp_d<kDppRor4>(v));
+    v = fmax(v, dpp_d<kDppSwap2>(v));
+    v = fmax(v, dpp_d<kDppSwap1>(v));
+    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
 __device__ __forceinline__ double ipow(double b, int n) {
     if (n == 0) return 1.0;
     double t = b;
@@ -229,7 +282,11 @@ __device__ __forceinline__ double system_entry(int lane, int j, int n, int s, in
     return 0.0;
 }
 
-template <int SMAX>
+// SMAX bounds the system size; FIXED: the number of operators is exactly
+// NOPS (fewer right-hand sides held per lane, no guards on them); COND: the
+// condition estimate is computed (a separate instantiation, so that the
+// plain solve does not carry its registers).
+template <int SMAX, bool FIXED, int NOPS, bool COND>
 __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, int64_t nq,
                                                 const double *__restrict__ xs, int64_t ns,
                                                 const int *__restrict__ idx, int n, int m, int q,
@@ -237,13 +294,15 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
                                                 double *__restrict__ cond,
                                                 unsigned long long *__restrict__ bad) {
     __shared__ double sx[64], sy[64];
-    __shared__ double sol[kMaxOps][SMAX];
+    constexpr int NO = FIXED ? NOPS : kMaxOps;  // right-hand sides held per lane
+    __shared__ double sol[NO][SMAX];
     __shared__ int pl[SMAX];
 
     const int64_t row = blockIdx.x;
     const int lane = threadIdx.x;
     const int kp = (q < 0) ? 0 : (q + 1) * (q + 2) / 2;
     const int s = n + kp;
+    const int nops = FIXED ? NOPS : ops.n;
 
     // 1. Stencil in shifted coordinates; exact power-of-two scaling.
     // A stencil index outside [0, ns) marks the row bad before any load
@@ -260,9 +319,7 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
         dy = xs[ns + j] - xq[nq + row];
         d2 = dx * dx + dy * dy;
     }
-    double d2max = d2;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) d2max = fmax(d2max, __shfl_xor(d2max, off, 64));
+    const double d2max = wave_max(d2);
     int E = 0;
     frexp(d2max, &E);
     const int e = (E >= 0) ? (E + 1) / 2 : -((-E) / 2);
@@ -275,33 +332,28 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
     // 2. This lane's row of [A P; P^T 0] and its right-hand sides.
     int ea = 0, eb = 0;
     if (lane >= n && lane < s) mono_exp(lane - n, ea, eb);
-    double a[SMAX], b[kMaxOps];
+    double a[SMAX], b[NO];
 #pragma unroll
     for (int j = 0; j < SMAX; ++j) a[j] = system_entry(lane, j, n, s, m, xt, yt, ea, eb, sx, sy);
-    if (lane < n) {
+    // This lane's right-hand sides (recomputed, not kept, for the
+    // refinement's residual).
+    auto rhs = [&](int o) {
+        if (o >= nops) return 0.0;
+        if (lane < n) return rhs_phs(xt, yt, m, ops.code[o]);
+        if (lane < s) return rhs_poly(ea, eb, ops.code[o]);
+        return 0.0;
+    };
 #pragma unroll
-        for (int o = 0; o < kMaxOps; ++o)
-            b[o] = (o < ops.n) ? rhs_phs(xt, yt, m, ops.code[o]) : 0.0;
-    } else if (lane < s) {
-#pragma unroll
-        for (int o = 0; o < kMaxOps; ++o) b[o] = (o < ops.n) ? rhs_poly(ea, eb, ops.code[o]) : 0.0;
-    } else {
-#pragma unroll
-        for (int o = 0; o < kMaxOps; ++o) b[o] = 0.0;
-    }
-    double b0[kMaxOps];
-#pragma unroll
-    for (int o = 0; o < kMaxOps; ++o) b0[o] = b[o];
+    for (int o = 0; o < NO; ++o) b[o] = rhs(o);
 
     // Scale for the singularity test: largest entry of the whole matrix.
     double amax = 0.0;
 #pragma unroll
     for (int j = 0; j < SMAX; ++j) amax = fmax(amax, fabs(a[j]));
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    amax = wave_max(amax);
     const double tiny = 16.0 * __DBL_EPSILON__ * amax;
     double anorm = 0.0;  // ||A_aug||_1 (largest absolute row sum; A_aug symmetric)
-    if (cond) {
+    if constexpr (COND) {
         double rs = 0.0;
 #pragma unroll
         for (int j = 0; j < SMAX; ++j) rs += fabs(a[j]);
@@ -316,17 +368,7 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
 #pragma unroll
     for (int kk = 0; kk < SMAX; ++kk) {
         if (kk < s) {
-            double cand = (mystep == INT_MAX) ? fabs(a[kk]) : -1.0;
-            int cl = lane;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double ov = __shfl_xor(cand, off, 64);
-                const int ol = __shfl_xor(cl, off, 64);
-                const bool take = ov > cand || (ov == cand && ol < cl);
-                cand = take ? ov : cand;
-                cl = take ? ol : cl;
-            }
-            const int piv = __builtin_amdgcn_readfirstlane(cl);
+            const int piv = wave_argmax((mystep == INT_MAX) ? fabs(a[kk]) : -1.0, lane);
             const double pv = readlane_d(a[kk], piv);
             if (!(fabs(pv) > tiny) || !isfinite(pv)) bad_row = true;
             const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
@@ -343,7 +385,8 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
 #pragma unroll
             for (int j = kk + 1; j < SMAX; ++j) a[j] = fma(-l, readlane_d(a[j], piv), a[j]);
 #pragma unroll
-            for (int o = 0; o < kMaxOps; ++o) b[o] = fma(-l, readlane_d(b[o], piv), b[o]);
+            for (int o = 0; o < NO; ++o)
+                if (o < nops) b[o] = fma(-l, readlane_d(b[o], piv), b[o]);
         }
     }
 
@@ -353,8 +396,8 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
         if (kk < s) {
             const int pk = pl[kk];
 #pragma unroll
-            for (int o = 0; o < kMaxOps; ++o) {
-                if (o < ops.n) {
+            for (int o = 0; o < NO; ++o) {
+                if (o < nops) {
                     const double xk = readlane_d(b[o] * myinv, pk);
                     if (mystep < kk) b[o] = fma(-a[kk], xk, b[o]);
                     if (lane == 0) sol[o][kk] = xk;
@@ -367,10 +410,10 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
     // 5. One refinement step: r = b0 - A0 x in double-FP64, solve with LU.
     // Entries are recomputed (same operations as in step 2) one column at a
     // time; each right-hand side accumulates over j in increasing order.
-    double r[kMaxOps], hi[kMaxOps], lo[kMaxOps];
+    double r[NO], hi[NO], lo[NO];
 #pragma unroll
-    for (int o = 0; o < kMaxOps; ++o) {
-        hi[o] = b0[o];
+    for (int o = 0; o < NO; ++o) {
+        hi[o] = rhs(o);
         lo[o] = 0.0;
     }
     if (lane < s) {
@@ -379,8 +422,8 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
             if (j < s) {
                 const double aj = system_entry(lane, j, n, s, m, xt, yt, ea, eb, sx, sy);
 #pragma unroll
-                for (int o = 0; o < kMaxOps; ++o) {
-                    if (o < ops.n) {
+                for (int o = 0; o < NO; ++o) {
+                    if (o < nops) {
                         const double xj = sol[o][j];
                         const double p = aj * xj;
                         const double pe = fma(aj, xj, -p);
@@ -395,15 +438,15 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
         }
     }
 #pragma unroll
-    for (int o = 0; o < kMaxOps; ++o) r[o] = hi[o] + lo[o];
+    for (int o = 0; o < NO; ++o) r[o] = hi[o] + lo[o];
     // Forward substitution with the stored multipliers (virtual pivoting).
 #pragma unroll
     for (int kk = 0; kk < SMAX; ++kk) {
         if (kk < s) {
             const int pk = pl[kk];
 #pragma unroll
-            for (int o = 0; o < kMaxOps; ++o) {
-                if (o < ops.n) {
+            for (int o = 0; o < NO; ++o) {
+                if (o < nops) {
                     const double yk = readlane_d(r[o], pk);
                     if (mystep > kk && mystep != INT_MAX) r[o] = fma(-a[kk], yk, r[o]);
                 }
@@ -415,8 +458,8 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
         if (kk < s) {
             const int pk = pl[kk];
 #pragma unroll
-            for (int o = 0; o < kMaxOps; ++o) {
-                if (o < ops.n) {
+            for (int o = 0; o < NO; ++o) {
+                if (o < nops) {
                     const double dk = readlane_d(r[o] * myinv, pk);
                     if (mystep < kk) r[o] = fma(-a[kk], dk, r[o]);
                     if (lane == 0) sol[o][kk] += dk;
@@ -429,8 +472,8 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
     // 6. Weights in physical units; NaN for failed rows.
     if (lane < n) {
 #pragma unroll
-        for (int o = 0; o < kMaxOps; ++o) {
-            if (o < ops.n) {
+        for (int o = 0; o < NO; ++o) {
+            if (o < nops) {
                 double v = ldexp(sol[o][lane], -e * ops.order[o]);
                 if (!isfinite(v)) bad_row = true;
                 w[((int64_t)o * n + lane) * nq + row] = v;
@@ -439,14 +482,14 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
     }
     // A row is bad if any lane saw a problem.
     const bool any_bad = __any(bad_row);
-    if (cond) {
+    if constexpr (COND) {
         double c = NAN;
         if (!any_bad) c = anorm * inv_norm1_estimate<SMAX>(a, mystep, myinv, pl, s, lane);
         if (lane == 0) cond[row] = c;
     }
     if (any_bad) {
         if (lane < n) {
-            for (int o = 0; o < ops.n; ++o) w[((int64_t)o * n + lane) * nq + row] = NAN;
+            for (int o = 0; o < nops; ++o) w[((int64_t)o * n + lane) * nq + row] = NAN;
         }
         if (lane == 0) atomicMin(bad, (unsigned long long)row);
     }
@@ -491,12 +534,21 @@ extern "C" rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const d
     rbf_status rc = RBF_OK;
     hipError_t e = hipMemcpyAsync(dbad, &init, sizeof(init), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
-        if (k + kp <= 40)
-            hipLaunchKernelGGL(k_weights<40>, dim3((uint32_t)nq), dim3(64), 0, st, xq, nq, xs, ns,
-                               idx, k, m, q, ops, w, cond_est, dbad);
-        else
-            hipLaunchKernelGGL(k_weights<64>, dim3((uint32_t)nq), dim3(64), 0, st, xq, nq, xs, ns,
-                               idx, k, m, q, ops, w, cond_est, dbad);
+#define RBF_WLAUNCH(SM, FX, NP)                                                                   \
+    do {                                                                                          \
+        if (cond_est)                                                                             \
+            hipLaunchKernelGGL((k_weights<SM, FX, NP, true>), dim3((uint32_t)nq), dim3(64), 0, st, xq, \
+                               nq, xs, ns, idx, k, m, q, ops, w, cond_est, dbad);                 \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_weights<SM, FX, NP, false>), dim3((uint32_t)nq), dim3(64), 0, st, \
+                               xq, nq, xs, ns, idx, k, m, q, ops, w, cond_est, dbad);             \
+    } while (0)
+        if (k + kp <= 38 && ops.n == 1) RBF_WLAUNCH(38, true, 1);
+        else if (k + kp <= 38 && ops.n == 2) RBF_WLAUNCH(38, true, 2);
+        else if (k + kp <= 38 && ops.n == 3) RBF_WLAUNCH(38, true, 3);
+        else if (k + kp <= 40) RBF_WLAUNCH(40, false, kMaxOps);
+        else RBF_WLAUNCH(64, false, kMaxOps);
+#undef RBF_WLAUNCH
         e = hipGetLastError();
     }
     unsigned long long hb = ~0ull;

@@ -210,7 +210,8 @@ def test_weights_singular_row_reported(P, gpu):
     rc = _lib.lib.rbf_assemble_weights(ctypes.c_void_p(d.data_ptr()), xs.shape[1],
                                        ctypes.c_void_p(d.data_ptr()), xs.shape[1],
                                        ctypes.c_void_p(idx.data_ptr()), 28, 7, 3, 2,
-                                       ctypes.c_void_p(w.data_ptr()), ctypes.byref(bad), None)
+                                       ctypes.c_void_p(w.data_ptr()), None, ctypes.byref(bad),
+                                       None)
     torch.cuda.synchronize()
     assert rc == _lib.RBF_E_SINGULAR
     idxh = idx.cpu().numpy()
