@@ -2632,19 +2632,40 @@ void aux_apply(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, const T *y, const
     hipStream_t st = S->st;
     const dim3 grid(nblocks_rows(P.m)), block(kThreads);
     const int nq = S->lat.n * S->lat.n;
+    // Pre-smoothing: x1 = W y (implicit, yd), further sweeps into F.x1.
+    const T *u = yd;
+    const double *us = ys;
+    static_assert(kAuxSweeps == 1 || kAuxSweeps == 2, "one or two smoothing sweeps");
+    if constexpr (kAuxSweeps == 2) {
+        launch_kt(P.k, [&](auto KT) {
+            hipLaunchKernelGGL((k_aux_pre<decltype(KT)::value, T>), grid, block, 0, st, P, y, yd, ys,
+                               F.x1, F.s.flag);
+        });
+        u = F.x1;
+        us = F.s.one;
+    }
     launch_kt(P.k, [&](auto KT) {
-        hipLaunchKernelGGL((k_aux_res<decltype(KT)::value, T>), grid, block, 0, st, P, y, yd, ys,
+        hipLaunchKernelGGL((k_aux_res<decltype(KT)::value, T>), grid, block, 0, st, P, y, ys, u, us,
                            F.res, F.s.flag);
     });
     hipLaunchKernelGGL(k_aux_restrict<T>, dim3(rbf::blocks_for(4 * (int64_t)nq, 256)), dim3(256), 0,
                        st, P, S->lat, F.res, nq);
     pc_apply(S, sample);
-    hipLaunchKernelGGL(k_aux_interp<T>, grid, block, 0, st, P, S->lat, yd, ys, F.t1, F.s.partZ);
+    hipLaunchKernelGGL(k_aux_interp<T>, grid, block, 0, st, P, S->lat, u, us, F.t1, F.s.partZ);
+    // Post-smoothing: the first sweep adds the border's constant.
+    T *zin = F.t1;
+    if constexpr (kAuxSweeps == 2) {
+        launch_kt(P.k, [&](auto KT) {
+            hipLaunchKernelGGL((k_aux_post<decltype(KT)::value, T, true>), grid, block, 0, st, P,
+                               S->lat, y, ys, F.t1, F.s.partZ, F.z1, F.s.partO);
+        });
+        zin = F.z1;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (sample) prof_pair(S, RBF_PROF_SMOOTH, e0, e1);
     launch_kt(P.k, [&](auto KT) {
-        hipExtLaunchKernelGGL((k_aux_post<decltype(KT)::value, T>), grid, block, 0, st, e0, e1, 0, P,
-                              S->lat, y, ys, F.t1, F.s.partZ, z, F.s.partO);
+        hipExtLaunchKernelGGL((k_aux_post<decltype(KT)::value, T, kAuxSweeps == 1>), grid, block, 0,
+                              st, e0, e1, 0, P, S->lat, y, ys, zin, F.s.partZ, z, F.s.partO);
     });
 }
 
@@ -2785,6 +2806,8 @@ rbf_status alloc_fg(rbf_solver *S, FgDev<T> &F, int64_t M) {
     ALLOC(F.res, M);
     ALLOC(F.t1, M);
     ALLOC(F.wd, M);
+    ALLOC(F.x1, M);
+    ALLOC(F.z1, M);
     FgScal &s = F.s;
     ALLOC(s.vs, mr + 1);
     ALLOC(s.part, (int64_t)(kFgMax + 2) * kMaxBlocks);

@@ -41,12 +41,13 @@ def _ell(idx, w, ncols):
 
 def _aux_reference(nd, ops, y):
     """Plain statement of the auxiliary-lattice preconditioner (header of
-    rbf_params.precond), built from the GPU's stencils and weights: l1-Jacobi
-    sweep (omega 2.0), residual, normalised bilinear restriction of interior
-    nodes to interior lattice points, zero-mean solve of the 5-point
-    Laplacian with homogeneous one-sided Neumann rows by sparse LU (no
+    rbf_params.precond), built from the GPU's stencils and weights: two
+    l1-Jacobi sweeps (omega 2.0) from zero, residual, normalised bilinear
+    restriction of interior nodes to interior lattice points, zero-mean
+    solve of the 5-point Laplacian (cells of the bounding box divided into
+    Ka x Ka) with homogeneous one-sided Neumann rows by sparse LU (no
     transforms), bilinear interpolation with wall values copied inward, the
-    border's constant, second sweep."""
+    border's constant, two more sweeps."""
     M = nd.n_p
     idx = ops["idx_pp"].cpu().numpy()
     wall = nd.p_tag != 0
@@ -59,10 +60,9 @@ def _aux_reference(nd, ops, y):
     W = 2.0 / np.asarray(abs(A).sum(1)).ravel()
     c = 0.1 * ((~wall).sum() / np.abs(S[~wall]).sum()) / M  # the FGMRES border scale
     x0, x1, y0, y1 = nd.xp[0].min(), nd.xp[0].max(), nd.xp[1].min(), nd.xp[1].max()
-    side = max(x1 - x0, y1 - y0)
     Ka = max(4, min(int(np.floor(0.465 * np.sqrt(M) + 0.5)), 513))
-    h, n = side / Ka, Ka - 1
-    sx, sy = (nd.xp[0] - x0) / h, (nd.xp[1] - y0) / h
+    hx, hy, n = (x1 - x0) / Ka, (y1 - y0) / Ka, Ka - 1
+    sx, sy = (nd.xp[0] - x0) / hx, (nd.xp[1] - y0) / hy
     i0 = np.clip(np.floor(sx).astype(int), 0, Ka - 1)
     j0 = np.clip(np.floor(sy).astype(int), 0, Ka - 1)
     fx, fy = np.clip(sx - i0, 0, 1), np.clip(sy - j0, 0, 1)
@@ -80,8 +80,8 @@ def _aux_reference(nd, ops, y):
     # interior Laplacian with Neumann ends (wall values copied inward)
     T = sp.diags([np.ones(n - 1), -2 * np.ones(n), np.ones(n - 1)], [-1, 0, 1]).tolil()
     T[0, 0] = T[n - 1, n - 1] = -1
-    T = T.tocsr() / h ** 2
-    L5 = (sp.kron(T, sp.identity(n)) + sp.kron(sp.identity(n), T)).tocsc()
+    T = T.tocsr()
+    L5 = (sp.kron(T / hx ** 2, sp.identity(n)) + sp.kron(sp.identity(n), T / hy ** 2)).tocsc()
     B = sp.bmat([[L5, np.ones((n * n, 1))], [np.ones((1, n * n)), None]], format="csc")
     lu = spla.splu(B)
 
@@ -90,6 +90,7 @@ def _aux_reference(nd, ops, y):
         return e[(ci - 1) * n + (cj - 1)]
 
     x1v = W * y
+    x1v = x1v + W * (y - A @ x1v)
     r1 = y - A @ x1v
     g = Rm @ (r1 / S)
     lam = g.mean()
@@ -98,7 +99,8 @@ def _aux_reference(nd, ops, y):
           + fy * ((1 - fx) * lat(e, i0, j0 + 1) + fx * lat(e, i0 + 1, j0 + 1)))
     t1 = x1v + Je
     mu = (lam / c - Je.sum()) / M
-    return t1 + mu + W * (y - A @ t1)
+    z = t1 + mu + W * (y - A @ t1)
+    return z + W * (y - A @ z)
 
 
 @pytest.mark.parametrize("K", [9, 24, 61])
