@@ -34,9 +34,11 @@ Workload (one JSON line on stdout):
     rows; the distribution of the 1-norm condition estimates of the VV
     systems.
   * cylinder: flow past a cylinder (Sec. 5.2) on the graded channel set
-    (N = 397,066 V + M = 132,692 P), Re = 100, dt = 2e-3, uniform inflow,
+    (N = 396,685 V + M = 132,565 P), Re = 100, dt = 2e-3, uniform inflow,
     symmetry sides, convective outflow; `cyl_steps` steps from an impulsive
-    start, node-steps/s and the drag and lift coefficients every 10 steps.
+    start (with a small transverse disturbance), node-steps/s, the drag and
+    lift coefficients every 10 steps and, for runs long enough to shed, the
+    mean drag, the force amplitudes and the Strouhal number.
   * cpu_baseline: the CPU oracle (SciPy sparse LU solves, as the paper's
     factor-once scheme) on a bounded sample of the headline workload: the
     same node kind, Re, dt, jitter and stencils at h = 1/100 (`--cpu-K`;
@@ -103,6 +105,7 @@ def parse():
     ap.add_argument("--cyl-steps", type=int, default=50)
     ap.add_argument("--cyl-re", type=float, default=100.0)
     ap.add_argument("--cyl-dt", type=float, default=2e-3)
+    ap.add_argument("--cyl-perturb", type=float, default=0.1)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy first (HBM counter calibration)")
     return ap.parse_args()
@@ -422,12 +425,39 @@ def batch_run(P, args, dev):
                     "rbf_step_batch"}
 
 
+def shedding_stats(series, dt):
+    """Mean and amplitude of C_D, amplitude of C_L and the Strouhal number
+    St = f D / U (D = U = 1) from the second half of a force series, f from
+    the upward zero crossings of C_L - mean (linear interpolation); None
+    when fewer than three crossings."""
+    if len(series) < 8:
+        return None
+    half = series[len(series) // 2:]
+    t = np.array([r["t"] for r in half])
+    cd = np.array([r["C_D"] for r in half])
+    cl = np.array([r["C_L"] for r in half])
+    c = cl - cl.mean()
+    up = [t[i] - c[i] * (t[i + 1] - t[i]) / (c[i + 1] - c[i])
+          for i in range(len(c) - 1) if c[i] < 0.0 <= c[i + 1]]
+    if len(up) < 3:
+        return None
+    period = (up[-1] - up[0]) / (len(up) - 1)
+    return {"St": float(1.0 / period), "C_D_mean": float(cd.mean()),
+            "C_D_amp": float(0.5 * (cd.max() - cd.min())),
+            "C_L_amp": float(0.5 * (cl.max() - cl.min())), "periods": len(up) - 1,
+            "window_t": [float(t[0]), float(t[-1])]}
+
+
 def cylinder_run(P, args, dev):
     """Flow past a cylinder (Sec. 5.2) on the graded channel nodes of
     rbf_inputs.cylinder_nodes (channel [-10, 30] x [-10, 10], spacing 0.02
     on the cylinder): uniform inflow, symmetry sides, convective outflow,
-    impulsive start from U_0 = (1, 0); `cyl_steps` timed steps after 5, with
-    drag and lift (rbf_solver_forces, Simpson's rule) every 10 steps."""
+    start from U_0 = (1, 0) plus `cyl_perturb` times a smooth transverse
+    blob behind the cylinder (v = eps exp(-((x - 1.5)^2 + y^2)), which seeds
+    the shedding that the paper's asymmetric grids seed by themselves);
+    `cyl_steps` timed steps after 5, drag and lift (rbf_solver_forces,
+    Simpson's rule) every 10 steps, and the shedding statistics of the
+    second half of the run when it holds three or more periods."""
     import torch
     import rbf_inputs as ri
     nd = ri.cylinder_nodes()
@@ -442,16 +472,19 @@ def cylinder_run(P, args, dev):
                  args.cyl_re, args.cyl_dt, u_conv=1.0)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    x, y = nd.xv
     u0 = np.where(nd.v_tag == 1, 0.0, 1.0)
-    st = S.new_state(dev_tensor(u0, dev), dev_tensor(np.zeros(nd.n_v), dev))
+    v0 = np.where(nd.v_tag == 0, args.cyl_perturb * np.exp(-((x - 1.5) ** 2 + y ** 2)), 0.0)
+    st = S.new_state(dev_tensor(u0, dev), dev_tensor(v0, dev))
     out = {"workload": f"cylinder D=1 in [-10,30]x[-10,10], N={S.N} V + M={S.M} P graded from "
                        f"0.02 on the cylinder, Re={args.cyl_re:g}, dt={args.cyl_dt:g}, uniform "
-                       "inflow, symmetry sides, convective outflow, impulsive start",
+                       "inflow, symmetry sides, convective outflow, start from U_0 = (1, 0) + "
+                       f"{args.cyl_perturb:g} transverse blob",
            "setup_s": setup_s, "aux_lattice_cells": S.info()["aux_cells"]}
+    series = []
     try:
         S.step(st, 5)
         torch.cuda.synchronize()
-        series = []
         t0 = time.perf_counter()
         iters = 0
         for c in range(0, args.cyl_steps, 10):
@@ -461,17 +494,22 @@ def cylinder_run(P, args, dev):
             fx, fy = S.forces(grid, st)
             series.append({"step": int(st["step"]), "t": st["step"] * args.cyl_dt,
                            "C_D": 2.0 * fx, "C_L": 2.0 * fy})
+            if len(series) % 500 == 0:
+                log(f"cylinder step {st['step']}: C_D {2 * fx:.4f} C_L {2 * fy:.4f}")
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         out.update({"value": (S.N + S.M) * args.cyl_steps / el, "unit": "node-steps/s",
                     "ms_per_step": el / args.cyl_steps * 1e3, "steps": args.cyl_steps,
                     "poisson_fgmres_steps_per_step": iters / args.cyl_steps,
-                    "forces": series, "final_state": S.diagnostics(st)})
+                    "final_state": S.diagnostics(st)})
     except P.RbfError as e:
         out["error"] = f"step {st['step']}: {e}"
+    keep = max(1, len(series) // 50)
+    out["forces"] = series[::keep] + (series[-1:] if series and (len(series) - 1) % keep else [])
+    out["shedding"] = shedding_stats(series, args.cyl_dt)
     S.close()
-    log(f"cylinder: {out.get('value', float('nan')):.3e} node-steps/s "
-        f"{out.get('forces', [{}])[-1] if out.get('forces') else out.get('error')}")
+    log(f"cylinder: {out.get('value', float('nan')):.3e} node-steps/s, last "
+        f"{series[-1] if series else None}, shedding {out['shedding']}")
     return out
 
 

@@ -253,13 +253,15 @@ def cylinder_nodes(h_wall=0.02, grading=0.008, h_far=0.5, box=(-10.0, 30.0, -10.
     grading (r - 1/2)): P-nodes on rings of radius r_k (r_0 = 1/2, r_{k+1} =
     r_k + h(r_k) sqrt(3)/2, round(2 pi r_k / h(r_k)) nodes (an even number,
     2 round(pi r_0 / h(r_0)), on the cylinder itself), every other ring
-    rotated by half a spacing) clipped to the channel, plus channel-edge
-    nodes at the local spacing; the Delaunay triangulation of those vertices
+    rotated by half a spacing) kept 1.5 local spacings clear of the channel
+    edges, plus channel-edge nodes at the local spacing and a regular row
+    beside each edge (gap midpoints moved inward by sqrt(3)/2 of the gap; a
+    clipped-ring layer at the edges gives a growing mode there); the Delaunay triangulation of those vertices
     without the triangles inside the cylinder gives the edges, and V-nodes
     are their midpoints.  Deterministic (no random draws).  Tags: 0
     interior, 1 cylinder, 3 inflow (x = x0), 4 outflow (x = x1), 5 sides
     (y = y0, y1; corners count as sides).  P normals point out of the fluid.
-    The defaults give 132,692 P- and 397,066 V-nodes."""
+    The defaults give 132,565 P- and 396,685 V-nodes."""
     from scipy.spatial import Delaunay
     x0, x1, y0, y1 = box
     hr = lambda r: np.minimum(h_far, h_wall + grading * (r - 0.5))  # noqa: E731
@@ -274,7 +276,7 @@ def cylinder_nodes(h_wall=0.02, grading=0.008, h_far=0.5, box=(-10.0, 30.0, -10.
         th = (np.arange(n) + 0.5 * (k % 2)) * (2 * np.pi / n)
         x, y = r * np.cos(th), r * np.sin(th)
         if k > 0:  # interior rings: clear of the channel edges by half a spacing
-            keep = (x > x0 + 0.5 * h) & (x < x1 - 0.5 * h) & (y > y0 + 0.5 * h) & (y < y1 - 0.5 * h)
+            keep = (x > x0 + 1.5 * h) & (x < x1 - 1.5 * h) & (y > y0 + 1.5 * h) & (y < y1 - 1.5 * h)
             x, y = x[keep], y[keep]
         px.append(x)
         py.append(y)
@@ -304,6 +306,22 @@ def cylinder_nodes(h_wall=0.02, grading=0.008, h_far=0.5, box=(-10.0, 30.0, -10.
     for a, b, fixed, hor, t in ((x0, x1, y0, True, TAG_SIDE), (x0, x1, y1, True, TAG_SIDE),
                                 (y0, y1, x0, False, TAG_INFLOW), (y0, y1, x1, False, TAG_OUTFLOW)):
         ex, ey, et = edge(a, b, fixed, hor, t)
+        # A regular row along the edge: the midpoints of the edge's gaps moved
+        # inward by sqrt(3)/2 of the gap (near-equilateral triangles at the
+        # wall; ring nodes keep 1.5 spacings from the edges).
+        if hor:
+            gap = ex[1:] - ex[:-1]
+            mx = 0.5 * (ex[1:] + ex[:-1])
+            my = fixed + (1.0 if fixed == y0 else -1.0) * gap * np.sqrt(3.0) / 2.0
+            ok = (mx > x0 + 0.75 * gap) & (mx < x1 - 0.75 * gap)
+        else:
+            gap = ey[1:] - ey[:-1]
+            my = 0.5 * (ey[1:] + ey[:-1])
+            mx = fixed + (1.0 if fixed == x0 else -1.0) * gap * np.sqrt(3.0) / 2.0
+            ok = (my > y0 + 0.75 * gap) & (my < y1 - 0.75 * gap)
+        px.append(mx[ok])
+        py.append(my[ok])
+        tag.append(np.zeros(int(ok.sum()), np.int8))
         if not hor:  # corners belong to the sides
             ex, ey, et = ex[1:-1], ey[1:-1], et[1:-1]
         px.append(ex)

@@ -47,6 +47,21 @@ def test_kernel_bytes():
     assert b["k_fg_gs<1>"] == M * (16 + 16 * 11)
 
 
+def test_shedding_statistics():
+    """Strouhal number from the upward zero crossings of C_L over the second
+    half of the series, and the force amplitudes, for a synthetic limit
+    cycle; None before three periods."""
+    import numpy as np
+    t = np.arange(0.0, 100.0, 0.02)
+    cl = 0.3 * np.sin(2 * np.pi * 0.17 * t + 0.4)
+    cd = 1.35 + 0.01 * np.sin(4 * np.pi * 0.17 * t)
+    ser = [{"t": a, "C_D": b, "C_L": c} for a, b, c in zip(t, cd, cl)]
+    r = bench.shedding_stats(ser, 0.02)
+    assert abs(r["St"] - 0.17) < 1e-6 and abs(r["C_D_mean"] - 1.35) < 1e-3
+    assert abs(r["C_L_amp"] - 0.3) < 1e-3 and abs(r["C_D_amp"] - 0.01) < 1e-4
+    assert bench.shedding_stats(ser[:700], 0.02) is None
+
+
 def test_more_than_one_gpu_is_refused():
     res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                          capture_output=True, text=True, timeout=300)

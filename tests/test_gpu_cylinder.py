@@ -1,17 +1,19 @@
 """Flow past a cylinder (Sec. 5.2) through the C ABI, against the oracle.
 
-Coarse graded cylinder-in-channel nodes (diameter 1 at the origin, channel
-[-4, 8] x [-4, 4], spacing 0.1 on the cylinder growing by 0.1 per unit of
-radius: N = 3,218 V + M = 1,111 P), uniform inflow, symmetry sides,
-convective outflow (rbf_grid tags RBF_VTAG_SYMMETRY and RBF_VTAG_OUTFLOW),
-no slip on the cylinder, impulsive start from U_0 = (1, 0).  u, v, p, p~
-and the drag and lift of rbf_solver_forces against oracle.cylinder within
-1e-10 every 2 steps over an 8-step window (Re = 1000, dt = 5e-3, pressure
-tolerance 1e-13).  The window is short because on these ring-and-Delaunay
-node sets the scheme has growing modes near the curved wall (the lift
-coefficient, 0.015 after 4 steps, reaches 0.36 after 10), which amplify the
-solver-tolerance differences between the two sides (forces 1.2e-10 after
-10 steps, fields 3e-10 after 15).
+Graded cylinder-in-channel nodes (diameter 1 at the origin, channel
+[-2.5, 5] x [-2.5, 2.5], spacing 0.03 on the cylinder -- the paper's --
+growing by 0.05 per unit of radius: N = 13,961 V + M = 4,736 P), uniform
+inflow, symmetry sides, convective outflow (rbf_grid tags RBF_VTAG_SYMMETRY
+and RBF_VTAG_OUTFLOW), no slip on the cylinder, impulsive start from
+U_0 = (1, 0), Re = 100, dt = 5e-3, solver tolerances 1e-13 (pressure) and
+1e-14 (viscous).  u, v, p, p~ and the drag and lift of rbf_solver_forces
+against oracle.cylinder within 1e-10 every 20 steps over 60 steps
+(t = 0.3).  The window is bounded because the wake's asymmetric mode grows
+from the start and amplifies the rounding-level differences between the
+two sides: the pressure differs by 1.9e-10 of its largest value after 80
+steps (and by 1.3e-10 after 40 steps at dt = 2e-3, where differences in
+u** reach p~ times 1/dt).  Coarser cylinders, 0.05 or 0.1 on the wall,
+carry growing modes at the wall within tens of steps.
 """
 import numpy as np
 import pytest
@@ -22,7 +24,8 @@ from tests.helpers import rel_err, to_dev, gpu_cavity_ops
 
 pytestmark = pytest.mark.gpu
 
-BOX = (-4.0, 8.0, -4.0, 4.0)
+BOX = (-2.5, 5.0, -2.5, 2.5)
+H_WALL, GRADING = 0.03, 0.05
 
 
 def _say(*a):
@@ -37,19 +40,19 @@ def P(gpu):
 
 def test_cylinder_flow_against_oracle(P, gpu):
     _say("cylinder flow, coarse channel")
-    nd = ri.cylinder_nodes(h_wall=0.1, grading=0.1, box=BOX)
-    re, dt = 1000.0, 5e-3
+    nd = ri.cylinder_nodes(h_wall=H_WALL, grading=GRADING, box=BOX)
+    re, dt = 100.0, 5e-3
     grid, ops = gpu_cavity_ops(nd, gpu)
     orc = oc.ChannelOracle(nd, re, dt)
     S = P.Solver(grid, ops, to_dev(orc.u_bc, gpu), to_dev(orc.v_bc, gpu), re, dt, u_conv=1.0,
-                 rtol_p=1e-13)
+                 rtol_p=1e-13, rtol_h=1e-14)
     assert S.info()["aux_precond"]
     so = orc.initial_state()
     st = S.new_state(to_dev(so.u, gpu), to_dev(so.v, gpu))
     worst = worst_f = 0.0
-    for _ in range(4):
-        stats = S.step(st, 2)
-        so = orc.run(2, so)
+    for _ in range(3):
+        stats = S.step(st, 20)
+        so = orc.run(20, so)
         for key, ref in (("u", so.u), ("v", so.v), ("p", so.p), ("p_tilde", so.pt)):
             e = rel_err(st[key].cpu().numpy(), ref)
             worst = max(worst, e)
@@ -60,16 +63,16 @@ def test_cylinder_flow_against_oracle(P, gpu):
         worst_f = max(worst_f, ef)
         assert ef <= 1e-10, (st["step"], fg, fo)
         _say("step", st["step"], "C_D, C_L", 2 * fg, "pressure steps per time step",
-             stats.poisson_iters / 2)
+             stats.poisson_iters / 20)
     _say("worst field error", worst, "worst force error", worst_f)
     S.close()
 
 
 def test_forces_argument_checks(P, gpu):
-    nd = ri.cylinder_nodes(h_wall=0.1, grading=0.1, box=BOX)
+    nd = ri.cylinder_nodes(h_wall=H_WALL, grading=GRADING, box=BOX)
     grid, ops = gpu_cavity_ops(nd, gpu)
-    orc = oc.ChannelOracle(nd, 100.0, 1e-2)
-    S = P.Solver(grid, ops, to_dev(orc.u_bc, gpu), to_dev(orc.v_bc, gpu), 100.0, 1e-2)
+    orc = oc.ChannelOracle(nd, 100.0, 2e-3)
+    S = P.Solver(grid, ops, to_dev(orc.u_bc, gpu), to_dev(orc.v_bc, gpu), 100.0, 2e-3)
     so = orc.initial_state()
     st = S.new_state(to_dev(so.u, gpu), to_dev(so.v, gpu))
     with pytest.raises(P.RbfError) as ei:
