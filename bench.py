@@ -66,7 +66,7 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 # counters on a plain 256 MiB copy (2.0 and 1.0), mean over the working
 # launches of 3 steps from rest (mean Arnoldi index 13.8 for k_fg_av and
 # k_fg_gs<1>); None for a kernel changed since it was measured.
-TRAFFIC_BYTES = {"k_fg_av": 91.18e6, "k_aux_post": None, "k_fg_gs<1>": 35.04e6,
+TRAFFIC_BYTES = {"k_fg_av": 91.09e6, "k_aux_post": 68.72e6, "k_fg_gs<1>": 41.49e6,
                  "k_pc_gemm<0>": 5.53e6}
 
 
