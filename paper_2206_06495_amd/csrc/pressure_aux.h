@@ -433,15 +433,21 @@ __global__ void __launch_bounds__(kThreads) k_fg_gs(FgDev<T> F, const double *h,
     }
 }
 
-// Arnoldi step j, one thread: Hessenberg column j = h1 + h2 with
+// Arnoldi step j, one workgroup: Hessenberg column j = h1 + h2 with
 // H(j+1, j) = ||w||, previous rotations applied, a new rotation, the
 // residual estimate |g_{j+1}| and the status (4: the cycle's target met or
 // an exact breakdown; 3: the cycle is full; -1: non-finite).
-__global__ void __launch_bounds__(64) k_fg_tail(FgScal F, int j, int mr) {
+// ||w||^2 is reduced here from the block partials of k_fg_gs<2> (row 0 of
+// part, nb blocks), in the order k_fg_reduce uses.
+__global__ void __launch_bounds__(256) k_fg_tail(FgScal F, int j, int mr, int nb) {
     if (*F.flag != 0) return;
     __shared__ double col[kFgMax + 1], cs[kFgMax], sn[kFgMax];
     const int lane = threadIdx.x;
-    for (int i = lane; i <= j; i += 64) {
+    double v[1] = {0.0};
+    for (int b = lane; b < nb; b += 256) v[0] += F.part[b];
+    __shared__ double lds[4];
+    rbf::block_sum<1>(v, lds);
+    for (int i = lane; i <= j; i += 256) {
         col[i] = F.h1[i] + F.h2[i];
         if (i < j) {
             cs[i] = F.cs[i];
@@ -451,7 +457,8 @@ __global__ void __launch_bounds__(64) k_fg_tail(FgScal F, int j, int mr) {
     __syncthreads();
     if (lane != 0) return;
     double *Hc = F.H + (int64_t)j * (mr + 1);
-    const double hn = sqrt(F.hn2[0]);
+    F.hn2[0] = v[0];
+    const double hn = sqrt(v[0]);
     col[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
         const double a = col[i], b = col[i + 1];

@@ -2736,9 +2736,7 @@ rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, co
                 hipLaunchKernelGGL(k_fg_reduce<true>, dim3(j + 1), red, 0, st, Fs.part, nb, j + 1,
                                    Fs.h2, Fs.flag);
                 hipLaunchKernelGGL((k_fg_gs<T, 2>), grid, block, 0, st, F, Fs.h2, P.dinv, m, j);
-                hipLaunchKernelGGL(k_fg_reduce<true>, one, red, 0, st, Fs.part, nb, 1, Fs.hn2,
-                                   Fs.flag);
-                hipLaunchKernelGGL(k_fg_tail, one, dim3(64), 0, st, Fs, j, mr);
+                hipLaunchKernelGGL(k_fg_tail, one, red, 0, st, Fs, j, mr, nb);
             }
             RBF_CHECK_LAUNCH();
             if ((rc = status()) != RBF_OK) return rc;
