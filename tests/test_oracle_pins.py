@@ -68,6 +68,12 @@ def test_cylinder_node_layout():
     assert np.all(nd.p_normal[0, nd.p_tag == ri.nodes.TAG_OUTFLOW] == 1.0)
     vb = nd.v_tag != 0
     assert vb.sum() == bnd.sum()  # closed boundary loops: as many edges as vertices
+    # The spacing follows h(r) along the wake centreline too (radial grading
+    # only, no separate wake band): nearest-neighbour distances within 15 %.
+    for xc in (2.0, 5.0, 10.0):
+        m = (np.abs(y) < 0.3) & (np.abs(x - xc) < 0.5)
+        hc = min(0.5, h_wall + g * (xc - 0.5))
+        assert m.any() and abs(d[m, 1].mean() / hc - 1.0) < 0.15, (xc, d[m, 1].mean(), hc)
 
 
 @pytest.mark.parametrize("K,jit,seed", [(2, 0.3, 0), (9, 0.4, 3), (40, 0.3, 1)])
