@@ -27,9 +27,10 @@ Workload (one JSON line on stdout):
     rbf_step_batch on one host thread and on `batch_threads` threads, from
     the same states; aggregate node-steps/s and bit-identity of the two.
   * operator bench: 10^6 V + 10^6 P jittered square nodes, weights for VV
-    {D_x, D_y, Lap} and PV {I}, then `spmv_reps` applications of each operator
-    in FP64 and FP32-stored ELL, timed with HIP events; achieved GB/s from the
-    algorithmic bytes; truncation error against closed-form derivatives of
+    {D_x, D_y, Lap} and PV {I}, the launch shape of each operator size and
+    precision chosen by the library's autotuner, then `spmv_reps`
+    applications of each operator in FP64 and FP32-stored ELL, timed with
+    HIP events; achieved GB/s from the algorithmic bytes; truncation error against closed-form derivatives of
     sin(kx)cos(ky), k = 2 pi {4, 16, 64}, over interior rows and over all
     rows; the distribution of the 1-norm condition estimates of the VV
     systems.
@@ -244,6 +245,17 @@ def spmv_bench(P, args, dev):
     gbs = {}
     x64 = dev_tensor(ri.random_vector(xv.shape[1], 1), dev)
     x32 = P.cast_f32(x64)
+    # Launch shape of each operator size and precision chosen by the
+    # library's autotuner (rbf_ell_autotune); the timings below use it.
+    tune = {}
+    for prec in ("fp64", "fp32"):
+        for name in ("dx_vv", "id_pv"):
+            idx, w, _ = ops[name]
+            w = P.cast_f32(w) if prec == "fp32" else w
+            shape, ms = P.ell_autotune(idx, w, x32 if prec == "fp32" else x64, reps=20)
+            tune[f"{name}_{prec}"] = {"shape": P.ELL_SHAPES[shape], "us": ms[shape] * 1e3,
+                                      "default_us": ms[0] * 1e3}
+    out["ell_autotune"] = tune
     for prec in ("fp64", "fp32"):
         for name, (idx, w, ncols) in ops.items():
             rows = idx.shape[1]

@@ -188,10 +188,32 @@ rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const double *xs, 
  * rows: number of rows; k: entries per row; idx: device int32 [k][rows];
  * w: device [k][rows]; x: device vector indexed by idx; y: device [rows].
  * dtype 0: w, x, y FP64, FP64 accumulation; dtype 1: w, x, y FP32, FP32
- * accumulation.  No synchronisation.  Errors: RBF_E_ARG for bad sizes/dtype.
+ * accumulation.  Launch shape: the one rbf_ell_autotune recorded for this
+ * (dtype, k, rows), else the default.  No synchronisation.  Errors:
+ * RBF_E_ARG for bad sizes/dtype.
  */
 rbf_status rbf_ell_apply(int64_t rows, int32_t k, const int32_t *idx, const void *w,
                          const void *x, void *y, int32_t dtype, rbf_stream st);
+
+/*
+ * rbf_ell_autotune -- choose the launch shape of rbf_ell_apply for one
+ * operator size by timing (for the 28-wide operators of Sec. 4; other
+ * widths keep the default shape).  Shapes: block size 64, 128, 256 or
+ * 512 threads (one row per thread) x blocks remapped to one contiguous row
+ * range per XCD or not x operator loads non-temporal or not; shape 0 is the
+ * default (256, remapped, non-temporal).  Every shape sums each row in the
+ * same order, so results are bit-identical across shapes.  Each shape runs
+ * once untimed and `reps` times timed with HIP events on `st`; the fastest
+ * (the lower shape on ties) is recorded for (dtype, k, rows) in a
+ * process-wide table that later rbf_ell_apply calls of that size use.
+ * Arguments as rbf_ell_apply (y is overwritten); shape: host, the chosen
+ * shape; ms: NULL or host [16], the mean time per application of each
+ * shape (-1 where not timed).  Synchronises the stream.  Errors: RBF_E_ARG
+ * (sizes, dtype, reps outside [1, 10000], NULL), RBF_E_DEVICE.
+ */
+rbf_status rbf_ell_autotune(int64_t rows, int32_t k, const int32_t *idx, const void *w,
+                            const void *x, void *y, int32_t dtype, int32_t reps, int32_t *shape,
+                            float *ms, rbf_stream st);
 
 /*
  * rbf_cast_f32 -- dst[i] = (float)src[i] (round to nearest) for i < n; used

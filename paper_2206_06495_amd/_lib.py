@@ -24,7 +24,7 @@ FORCE_SMALL_STENCIL = 0x80000000
 
 EXPORTED = [
     "rbf_last_error", "rbf_abi_version", "rbf_build_nodes", "rbf_knn", "rbf_knn_noalloc",
-    "rbf_assemble_weights", "rbf_ell_apply", "rbf_cast_f32", "rbf_ell_transpose",
+    "rbf_assemble_weights", "rbf_ell_apply", "rbf_ell_autotune", "rbf_cast_f32", "rbf_ell_transpose",
     "rbf_ell_transpose_weights", "rbf_ell_apply_transpose", "rbf_solver_create",
     "rbf_step", "rbf_step_batch", "rbf_solve_pressure", "rbf_solver_apply_precond", "rbf_solver_profile", "rbf_solver_query",
     "rbf_solver_diagnostics", "rbf_solver_forces", "rbf_adjoint_step",
@@ -117,6 +117,11 @@ def _load():
     lib.rbf_ell_apply.restype = S
     lib.rbf_ell_apply.argtypes = [ctypes.c_int64, ctypes.c_int32, c_void_p, c_void_p, c_void_p,
                                   c_void_p, ctypes.c_int32, c_void_p]
+    lib.rbf_ell_autotune.restype = S
+    lib.rbf_ell_autotune.argtypes = [ctypes.c_int64, ctypes.c_int32, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
+                                     c_void_p]
     lib.rbf_cast_f32.restype = S
     lib.rbf_cast_f32.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_void_p]
     lib.rbf_ell_transpose.restype = S

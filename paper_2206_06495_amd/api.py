@@ -12,7 +12,7 @@ import torch
 from . import _lib
 from ._lib import OP_ID, OP_DX, OP_DY, OP_LAP, check, lib
 
-__all__ = ["build_nodes", "knn", "assemble_weights", "ell_apply", "cast_f32", "Solver", "LidRollout",
+__all__ = ["build_nodes", "knn", "assemble_weights", "ell_apply", "ell_autotune", "ELL_SHAPES", "cast_f32", "Solver", "LidRollout",
            "OP_ID", "OP_DX", "OP_DY", "OP_LAP"]
 
 
@@ -88,6 +88,29 @@ def assemble_weights(xq, xs, idx, m=7, q=3, op_mask=OP_DX | OP_DY | OP_LAP, forc
                                    ctypes.c_uint32(mask), _ptr(w), _ptr(c) if cond else None,
                                    ctypes.byref(bad), _stream()))
     return (w, c) if cond else w
+
+
+ELL_SHAPES = [(b, xcd, nt) for nt in (True, False) for xcd in (True, False)
+              for b in (256, 64, 128, 512)]  # (block, XCD remap, non-temporal), shape order
+
+
+def ell_autotune(idx, w, x, reps=20):
+    """Time the launch shapes of ell_apply for this operator size and record
+    the fastest for later ell_apply calls (rbf_ell_autotune); returns
+    (shape, [ms per application of each shape])."""
+    _dev(idx, torch.int32, name="idx")
+    k, rows = idx.shape
+    if w.dtype not in (torch.float64, torch.float32):
+        raise ValueError("w must be float64 or float32")
+    _dev(w, w.dtype, (k, rows), name="w")
+    _dev(x, w.dtype, name="x")
+    y = torch.empty(rows, dtype=w.dtype, device=w.device)
+    shape = ctypes.c_int32(-1)
+    ms = (ctypes.c_float * 16)()
+    check(lib.rbf_ell_autotune(rows, k, _ptr(idx), _ptr(w), _ptr(x), _ptr(y),
+                               0 if w.dtype == torch.float64 else 1, int(reps),
+                               ctypes.byref(shape), ms, _stream()))
+    return shape.value, list(ms)
 
 
 def ell_apply(idx, w, x, out=None):

@@ -10,6 +10,9 @@
 // neighbours are close in memory; blocks are remapped so that every XCD
 // works on one contiguous range of rows (its L2 then holds that range of x).
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "common.h"
 
@@ -22,11 +25,21 @@ __device__ __forceinline__ double fma_t<double>(double a, double b, double c) { 
 template <>
 __device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return fmaf(a, b, c); }
 
-template <class T, int KT>
-__global__ void __launch_bounds__(256) k_ell_apply(int64_t rows, int k, const int *__restrict__ idx,
+// Launch shape of the fixed-width product (chosen by rbf_ell_autotune):
+// XCD: blocks remapped to one contiguous row range per XCD; NT: operator
+// loads non-temporal.  The row's summation order is the same in every
+// shape, so every shape gives the same bits.
+template <class T, bool NT>
+__device__ __forceinline__ T ell_load(const T *p) {
+    if constexpr (NT) return rbf::ld_stream(p);
+    else return *p;
+}
+
+template <class T, int KT, bool XCD = true, bool NT = true>
+__global__ void __launch_bounds__(512) k_ell_apply(int64_t rows, int k, const int *__restrict__ idx,
                                                    const T *__restrict__ w, const T *__restrict__ x,
                                                    T *__restrict__ y) {
-    const uint32_t lb = rbf::xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t lb = XCD ? rbf::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const int64_t r = (int64_t)lb * blockDim.x + threadIdx.x;
     if (r >= rows) return;
     T acc = T(0);
@@ -34,9 +47,9 @@ __global__ void __launch_bounds__(256) k_ell_apply(int64_t rows, int k, const in
         int jj[KT];
         T ww[KT];
 #pragma unroll
-        for (int s = 0; s < KT; ++s) jj[s] = rbf::ld_stream(idx + (int64_t)s * rows + r);
+        for (int s = 0; s < KT; ++s) jj[s] = ell_load<int, NT>(idx + (int64_t)s * rows + r);
 #pragma unroll
-        for (int s = 0; s < KT; ++s) ww[s] = rbf::ld_stream(w + (int64_t)s * rows + r);
+        for (int s = 0; s < KT; ++s) ww[s] = ell_load<T, NT>(w + (int64_t)s * rows + r);
 #pragma unroll
         for (int s = 0; s < KT; ++s) acc = fma_t<T>(ww[s], x[jj[s]], acc);
     } else {
@@ -189,6 +202,111 @@ __global__ void __launch_bounds__(256) k_ell_apply_t(int64_t ncols, const int64_
 
 }  // namespace
 
+namespace {
+
+// Launch shapes of the 28-wide product: block size x XCD remap x operator
+// load kind.  Shape 0 is the default (256 threads, remap, non-temporal).
+constexpr int kEllShapes = 16;
+struct EllShape {
+    int block;
+    bool xcd, nt;
+};
+constexpr EllShape kShapes[kEllShapes] = {
+    {256, true, true},   {64, true, true},   {128, true, true},   {512, true, true},
+    {256, false, true},  {64, false, true},  {128, false, true},  {512, false, true},
+    {256, true, false},  {64, true, false},  {128, true, false},  {512, true, false},
+    {256, false, false}, {64, false, false}, {128, false, false}, {512, false, false}};
+
+// Tuned shapes, per (dtype, k, rows) (process-wide).
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int64_t>, int> g_tuned;
+
+int tuned_shape(int dtype, int k, int64_t rows) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(dtype, k, rows));
+    return it == g_tuned.end() ? 0 : it->second;
+}
+
+template <class T>
+void launch_ell_28(int shape, int64_t rows, const int32_t *idx, const T *W, const T *X, T *Y,
+                   hipStream_t st) {
+    const EllShape sh = kShapes[shape];
+    const dim3 grid(rbf::blocks_for(rows, sh.block)), block(sh.block);
+#define RBF_ELL(XC, NTL) \
+    hipLaunchKernelGGL((k_ell_apply<T, 28, XC, NTL>), grid, block, 0, st, rows, 28, idx, W, X, Y)
+    if (sh.xcd && sh.nt) RBF_ELL(true, true);
+    else if (!sh.xcd && sh.nt) RBF_ELL(false, true);
+    else if (sh.xcd) RBF_ELL(true, false);
+    else RBF_ELL(false, false);
+#undef RBF_ELL
+}
+
+}  // namespace
+
+extern "C" rbf_status rbf_ell_autotune(int64_t rows, int32_t k, const int32_t *idx, const void *w,
+                                       const void *x, void *y, int32_t dtype, int32_t reps,
+                                       int32_t *shape, float *ms, rbf_stream st_) {
+    rbf::clear_error();
+    RBF_ARG(rows > 0 && rows < (int64_t)1 << 31, "rbf_ell_autotune: rows out of range");
+    RBF_ARG(k >= 1 && k <= 64, "rbf_ell_autotune: k must be in [1, 64]");
+    RBF_ARG(dtype == 0 || dtype == 1, "rbf_ell_autotune: dtype must be 0 (FP64) or 1 (FP32)");
+    RBF_ARG(reps >= 1 && reps <= 10000, "rbf_ell_autotune: reps must be in [1, 10000]");
+    RBF_ARG(idx && w && x && y && shape, "rbf_ell_autotune: NULL pointer");
+    hipStream_t st = rbf::as_stream(st_);
+    if (k != 28) {  // one shape for the generic width
+        *shape = 0;
+        if (ms)
+            for (int v = 0; v < kEllShapes; ++v) ms[v] = (v == 0) ? 0.0f : -1.0f;
+        return RBF_OK;
+    }
+    hipEvent_t e0, e1;
+    RBF_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        rbf::set_error("rbf_ell_autotune: event creation failed");
+        return RBF_E_DEVICE;
+    }
+    float best = INFINITY;
+    int bi = 0;
+    hipError_t err = hipSuccess;
+    for (int v = 0; v < kEllShapes && err == hipSuccess; ++v) {
+        auto run = [&]() {
+            if (dtype == 0)
+                launch_ell_28<double>(v, rows, idx, static_cast<const double *>(w),
+                                      static_cast<const double *>(x), static_cast<double *>(y), st);
+            else
+                launch_ell_28<float>(v, rows, idx, static_cast<const float *>(w),
+                                     static_cast<const float *>(x), static_cast<float *>(y), st);
+        };
+        run();  // warm-up
+        err = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) run();
+        if (err == hipSuccess) err = hipGetLastError();
+        if (err == hipSuccess) err = hipEventRecord(e1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        t /= (float)reps;
+        if (ms) ms[v] = t;
+        if (t < best) {  // strict: ties keep the earlier (default-first) shape
+            best = t;
+            bi = v;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (err != hipSuccess) {
+        rbf::set_error("rbf_ell_autotune: %s", hipGetErrorString(err));
+        return RBF_E_DEVICE;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[std::make_tuple((int)dtype, (int)k, rows)] = bi;
+    }
+    *shape = bi;
+    return RBF_OK;
+}
+
 extern "C" rbf_status rbf_ell_apply(int64_t rows, int32_t k, const int32_t *idx, const void *w,
                                     const void *x, void *y, int32_t dtype, rbf_stream st_) {
     rbf::clear_error();
@@ -198,19 +316,28 @@ extern "C" rbf_status rbf_ell_apply(int64_t rows, int32_t k, const int32_t *idx,
     if (rows == 0) return RBF_OK;
     RBF_ARG(idx && w && x && y, "rbf_ell_apply: NULL pointer");
     hipStream_t st = rbf::as_stream(st_);
+    if (k == 28) {
+        const int shape = tuned_shape(dtype, k, rows);
+        if (dtype == 0)
+            launch_ell_28<double>(shape, rows, idx, static_cast<const double *>(w),
+                                  static_cast<const double *>(x), static_cast<double *>(y), st);
+        else
+            launch_ell_28<float>(shape, rows, idx, static_cast<const float *>(w),
+                                 static_cast<const float *>(x), static_cast<float *>(y), st);
+        RBF_CHECK_LAUNCH();
+        return RBF_OK;
+    }
     const dim3 grid(rbf::blocks_for(rows, 256)), block(256);
     if (dtype == 0) {
         auto W = static_cast<const double *>(w);
         auto X = static_cast<const double *>(x);
         auto Y = static_cast<double *>(y);
-        if (k == 28) hipLaunchKernelGGL((k_ell_apply<double, 28>), grid, block, 0, st, rows, k, idx, W, X, Y);
-        else hipLaunchKernelGGL((k_ell_apply<double, 0>), grid, block, 0, st, rows, k, idx, W, X, Y);
+        hipLaunchKernelGGL((k_ell_apply<double, 0>), grid, block, 0, st, rows, k, idx, W, X, Y);
     } else {
         auto W = static_cast<const float *>(w);
         auto X = static_cast<const float *>(x);
         auto Y = static_cast<float *>(y);
-        if (k == 28) hipLaunchKernelGGL((k_ell_apply<float, 28>), grid, block, 0, st, rows, k, idx, W, X, Y);
-        else hipLaunchKernelGGL((k_ell_apply<float, 0>), grid, block, 0, st, rows, k, idx, W, X, Y);
+        hipLaunchKernelGGL((k_ell_apply<float, 0>), grid, block, 0, st, rows, k, idx, W, X, Y);
     }
     RBF_CHECK_LAUNCH();
     return RBF_OK;

@@ -327,6 +327,32 @@ def _t_bound(idx, w, y, ncols, u):
     return 2.0 * np.maximum(lens, 1) * u * mag + 1e-300
 
 
+def test_ell_autotune(P, gpu):
+    """rbf_ell_autotune times the 16 launch shapes of the 28-wide product,
+    records the fastest, and ell_apply then uses it: results bit-identical
+    to the default shape (same per-row summation order) in FP64 and FP32;
+    other widths keep the default shape."""
+    import torch
+    _say("ell autotune")
+    nd = ri.square_nodes(200, 0.3, 1)
+    xv = to_dev(nd.xv, gpu)
+    idx = P.knn(xv, xv, 28)
+    w = P.assemble_weights(xv, xv, idx, 7, 3, 2)[0].contiguous()
+    x = to_dev(ri.random_vector(nd.xv.shape[1], 3), gpu)
+    for ww, xx in ((w, x), (P.cast_f32(w), P.cast_f32(x))):
+        y0 = P.ell_apply(idx, ww, xx)
+        shape, ms = P.ell_autotune(idx, ww, xx, reps=5)
+        assert len(ms) == 16 and all(t > 0.0 for t in ms), ms
+        assert shape == int(np.argmin(ms)), (shape, ms)
+        y1 = P.ell_apply(idx, ww, xx)
+        torch.cuda.synchronize()
+        assert bool((y0 == y1).all())
+        _say("dtype", ww.dtype, "shape", shape, P.ELL_SHAPES[shape], "ms", min(ms), "default", ms[0])
+    i17 = idx[:17].contiguous()
+    shape, ms = P.ell_autotune(i17, w[:17].contiguous(), x, reps=2)
+    assert shape == 0 and ms[0] == 0.0 and all(t == -1.0 for t in ms[1:])
+
+
 def test_ell_transpose_parity(P, gpu):
     """z = D^T y (the transposed product of the adjoint): the column
     structure and the column-ordered weights equal their definitions
