@@ -266,10 +266,11 @@ rbf_status rbf_ell_transpose_weights(int64_t rows, int32_t k, const int32_t *src
 /*
  * rbf_ell_apply_transpose -- z = D^T y: z_c = sum over the entries e of
  * column c (colptr[c] <= e < colptr[c+1], from rbf_ell_transpose) of
- * wt[e] * y[src[e]] (wt from rbf_ell_transpose_weights).  Eight lanes per
- * column: lane l accumulates entries l, l + 8, ... with fused multiply-adds,
- * then the eight partial sums are combined by a fixed butterfly; no
- * atomics, so results are reproducible bit for bit.
+ * wt[e] * y[src[e]] (wt from rbf_ell_transpose_weights).  One wavefront
+ * per 64 consecutive columns walks their contiguous entries in chunks with
+ * coalesced loads, stages the products wt[e] * y[src[e]] in LDS, and each
+ * lane adds its column's products in entry order; no atomics, so results
+ * are reproducible bit for bit.
  *
  * y: device [rows] of the operator; z: device [ncols] (columns without
  * entries get 0); src, wt and y may be NULL for an operator without rows.

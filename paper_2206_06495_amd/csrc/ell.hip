@@ -171,33 +171,44 @@ __global__ void k_tr_weights(int64_t rows, int64_t nnz, const int *__restrict__ 
         wt[e] = w[(int64_t)slot[e] * rows + src[e]];
 }
 
-// z_c = sum of wt[e] * y[src[e]] over the entries e of column c: kTrLanes
-// lanes per column, lane l summing entries l, l + kTrLanes, ... (FMA), then
-// a fixed butterfly over the lanes of the group, so the result does not
-// depend on the launch.  Consecutive lanes read consecutive entries.
-constexpr int kTrLanes = 8;
+// z_c = sum of wt[e] * y[src[e]] over the entries e of column c.  One
+// wavefront per 64 consecutive columns, whose entries are one contiguous
+// range: the wave walks that range in chunks of kTrChunk entries with
+// coalesced loads (lane l takes entries l, l + 64, ...), writes the
+// products wt[e] * y[src[e]] to LDS, and then every lane adds the products
+// of its own column in entry order.  The order of the additions is fixed
+// by the column structure alone, so results are reproducible bit for bit.
+constexpr int kTrChunk = 512;
+constexpr int kTrWaves = 4;
 template <class T>
-__device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int off = kTrLanes / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-template <class T>
-__global__ void __launch_bounds__(256) k_ell_apply_t(int64_t ncols, const int64_t *__restrict__ colptr,
-                                                     const int *__restrict__ src,
-                                                     const T *__restrict__ wt,
-                                                     const T *__restrict__ y, T *__restrict__ z) {
+__global__ void __launch_bounds__(64 * kTrWaves) k_ell_apply_t(int64_t ncols,
+                                                               const int64_t *__restrict__ colptr,
+                                                               const int *__restrict__ src,
+                                                               const T *__restrict__ wt,
+                                                               const T *__restrict__ y,
+                                                               T *__restrict__ z) {
+    __shared__ T prod[kTrWaves][kTrChunk];
     const uint32_t lb = rbf::xcd_block(blockIdx.x, gridDim.x);
-    const int64_t g = ((int64_t)lb * blockDim.x + threadIdx.x) / kTrLanes;
-    const int l = threadIdx.x % kTrLanes;
-    // Whole groups leave together (ncols is the same for every lane of a
-    // group), so the shuffles below see complete groups.
-    if (g >= ncols) return;
-    const int64_t b = colptr[g], e = colptr[g + 1];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t c0 = ((int64_t)lb * kTrWaves + wv) * 64;
+    if (c0 >= ncols) return;  // whole waves leave together
+    const int64_t c = c0 + lane;
+    const int64_t cend = min(c0 + 64, ncols);
+    const int64_t E0 = colptr[c0], E1 = colptr[cend];
+    const int64_t b = (c < ncols) ? colptr[c] : E1, e = (c < ncols) ? colptr[c + 1] : E1;
+    T *pw = prod[wv];
     T acc = T(0);
-    for (int64_t i = b + l; i < e; i += kTrLanes) acc = fma_t<T>(wt[i], y[src[i]], acc);
-    acc = group_sum(acc);
-    if (l == 0) z[g] = acc;
+    for (int64_t ch = E0; ch < E1; ch += kTrChunk) {
+        const int64_t n = min((int64_t)kTrChunk, E1 - ch);
+#pragma unroll 4
+        for (int t = lane; t < n; t += 64) pw[t] = wt[ch + t] * y[src[ch + t]];
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS writes are done
+        __builtin_amdgcn_wave_barrier();
+        const int64_t lo = max(b, ch), hi = min(e, ch + n);
+        for (int64_t i = lo; i < hi; ++i) acc += pw[i - ch];
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (c < ncols) z[c] = acc;
 }
 
 }  // namespace
@@ -455,7 +466,7 @@ extern "C" rbf_status rbf_ell_apply_transpose(int64_t ncols, const int64_t *colp
     if (ncols == 0) return RBF_OK;
     RBF_ARG(colptr && z, "rbf_ell_apply_transpose: NULL pointer");
     hipStream_t st = rbf::as_stream(st_);
-    const dim3 grid(rbf::blocks_for(ncols * kTrLanes, 256)), block(256);
+    const dim3 grid(rbf::blocks_for(ncols, 64 * kTrWaves)), block(64 * kTrWaves);
     if (dtype == 0)
         hipLaunchKernelGGL(k_ell_apply_t<double>, grid, block, 0, st, ncols, colptr, src,
                            static_cast<const double *>(wt), static_cast<const double *>(y),
