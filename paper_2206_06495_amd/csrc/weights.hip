@@ -6,16 +6,20 @@
 // phi(||x - x_j||) and to the monomials at x = x_0; w is kept.
 //
 // One wavefront (64 lanes) solves one system.  Lane i owns row i of the
-// augmented matrix (s = n + K_p <= 64 rows) in registers; LU with partial
-// pivoting runs across lanes: the pivot is found by a butterfly arg-max over
-// the wave, its row is broadcast with v_readlane (scalar operands of the
-// updates), and every other unfinished row eliminates with it (row swaps are
-// virtual: each lane remembers the step at which its row became pivot).
-// The residual of the refinement step recomputes the lane's row of the
-// original matrix instead of keeping a copy in registers.  All right-hand sides (one per operator) are
-// eliminated together.  One step of iterative refinement with a residual
-// accumulated in double-FP64 arithmetic (exact products via fma) brings the
-// solution to within a few ulps of the exact solution of the FP64 system.
+// augmented matrix (s = n + K_p <= 64 rows) in registers; the monomials of
+// the P block are computed once per stencil node and shared through LDS.
+// LU with partial pivoting runs across lanes: the pivot is found by one
+// unsigned maximum reduction over the wave (the lane number packed into the
+// low bits of a key made of the value's high word), the pivot lane writes
+// the rest of its row to LDS, every lane reads it as broadcasts and every
+// other unfinished row eliminates with it (row swaps are virtual: each lane
+// remembers the step at which its row became pivot).  The residual of the
+// refinement step recomputes the lane's row of the original matrix (a copy
+// in LDS would cost more in occupancy than the recomputation).  All
+// right-hand sides (one per operator) are eliminated together.  One step of
+// iterative refinement with a residual accumulated in double-FP64
+// arithmetic (exact products via fma) brings the solution to within a few
+// ulps of the exact solution of the FP64 system.
 //
 // Local coordinates: x~ = (x_j - x_0) * 2^-e with e = ceil(E/2),
 // max_j |x_j - x_0|^2 = f 2^E, 1/2 <= f < 1 (exact scaling); weights are
@@ -43,6 +47,7 @@ namespace {
 
 constexpr int kMaxOps = 4;
 
+
 struct OpSet {
     int n;               // number of operators
     int code[kMaxOps];   // RBF_OP_* codes
@@ -56,11 +61,11 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Cross-lane reductions without LDS traffic: DPP moves inside each 16-lane
+// Cross-lane maximum without LDS traffic: DPP moves inside each 16-lane
 // row (rotations by 8 and 4, then quad swaps of 2 and 1 leave every lane of
 // a row with the row's result), then the four rows' results read by
 // v_readlane and combined uniformly.  Exact maxima, so the reduction order
-// does not matter; ties of the arg-max go to the lowest lane.
+// does not matter.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
     const long long b = __double_as_longlong(v);
@@ -69,36 +74,7 @@ __device__ __forceinline__ double dpp_d(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int CTRL>
-__device__ __forceinline__ void dpp_argmax_step(double &c, int &cl) {
-    const double ov = dpp_d<CTRL>(c);
-    const int ol = __builtin_amdgcn_update_dpp(0, cl, CTRL, 0xF, 0xF, false);
-    const bool take = ov > c || (ov == c && ol < cl);
-    c = take ? ov : c;
-    cl = take ? ol : cl;
-}
-
 constexpr int kDppRor8 = 0x128, kDppRor4 = 0x124, kDppSwap2 = 0x4E, kDppSwap1 = 0xB1;
-
-// Lane of the largest c over the wave (lowest lane on ties), wave-uniform.
-__device__ __forceinline__ int wave_argmax(double c, int lane) {
-    int cl = lane;
-    dpp_argmax_step<kDppRor8>(c, cl);
-    dpp_argmax_step<kDppRor4>(c, cl);
-    dpp_argmax_step<kDppSwap2>(c, cl);
-    dpp_argmax_step<kDppSwap1>(c, cl);
-    double bv = readlane_d(c, 0);
-    int bl = __builtin_amdgcn_readlane(cl, 0);
-#pragma unroll
-    for (int r = 16; r < 64; r += 16) {
-        const double v = readlane_d(c, r);
-        const int l = __builtin_amdgcn_readlane(cl, r);
-        const bool take = v > bv || (v == bv && l < bl);
-        bv = take ? v : bv;
-        bl = take ? l : bl;
-    }
-    return __builtin_amdgcn_readfirstlane(bl);
-}
 
 // Largest v over the wave (fmax: NaN only if every lane is NaN), uniform.
 __device__ __forceinline__ double wave_max(double v) {
@@ -159,26 +135,35 @@ __device__ __forceinline__ int wave_argmax_abs(double v, int lane, int s) {
     return __builtin_amdgcn_readfirstlane(cl);
 }
 
+// Lane whose row was chosen as pivot at elimination step kk (wave-uniform):
+// exactly one lane holds mystep == kk once the factorisation is done.
+__device__ __forceinline__ int step_lane(int mystep, int kk) {
+    const unsigned long long m = __ballot(mystep == kk);
+    return m ? __builtin_ctzll(m) : 0;
+}
+
 // Solve A x = r with the factors of k_weights' LU: lane i holds r_i and
 // receives x_i (0 beyond s).  a holds the multipliers of the steps that
-// eliminated this lane's row and its row of U; pl[kk] is the lane that
-// pivoted at step kk.
+// eliminated this lane's row (steps before mystep) and its row of U (steps
+// after it); the masks turn the entries of the other factor into zero
+// multipliers instead of selecting results.
 template <int SMAX>
 __device__ __forceinline__ double lu_solve_lane(double r, const double (&a)[SMAX], int mystep,
-                                                double myinv, const int *pl, int s, int lane) {
+                                                double myinv, int s, int lane) {
 #pragma unroll
     for (int kk = 0; kk < SMAX; ++kk) {
         if (kk < s) {
-            const double yk = readlane_d(r, pl[kk]);
-            if (mystep > kk && mystep != INT_MAX) r = fma(-a[kk], yk, r);
+            const double lk = (mystep > kk && mystep != INT_MAX) ? a[kk] : 0.0;
+            r = fma(-lk, readlane_d(r, step_lane(mystep, kk)), r);
         }
     }
     double x = 0.0;
 #pragma unroll
     for (int kk = SMAX - 1; kk >= 0; --kk) {
         if (kk < s) {
-            const double xk = readlane_d(r * myinv, pl[kk]);
-            if (mystep < kk) r = fma(-a[kk], xk, r);
+            const double uk = (mystep < kk) ? a[kk] : 0.0;
+            const double xk = readlane_d(r * myinv, step_lane(mystep, kk));
+            r = fma(-uk, xk, r);
             if (lane == kk) x = xk;
         }
     }
@@ -188,14 +173,14 @@ __device__ __forceinline__ double lu_solve_lane(double r, const double (&a)[SMAX
 // Lower estimate of ||A^-1||_1 for the factored symmetric A (size s).
 // One solve per pass of the loop; `state` follows the steps of the method.
 template <int SMAX>
-__device__ double inv_norm1_estimate(const double (&a)[SMAX], int mystep, double myinv,
-                                     const int *pl, int s, int lane) {
+__device__ double inv_norm1_estimate(const double (&a)[SMAX], int mystep, double myinv, int s,
+                                     int lane) {
     const bool live = lane < s;
     double x = live ? 1.0 / (double)s : 0.0;
     double est = 0.0, xi = 0.0;
     int state = 1, iter = 0, j = 0;
     for (int pass = 0; pass < 16 && state != 0; ++pass) {
-        const double y = lu_solve_lane<SMAX>(x, a, mystep, myinv, pl, s, lane);
+        const double y = lu_solve_lane<SMAX>(x, a, mystep, myinv, s, lane);
         const double sg = (y >= 0.0) ? 1.0 : -1.0;
         if (state == 1) {  // y = A^-1 (1/s): first estimate, then z = A^-T sign(y)
             est = wave_sum(fabs(y));
@@ -259,27 +244,24 @@ __device__ __forceinline__ double rhs_poly(int a, int b, int code) {
     return ((a == 2 && b == 0) || (a == 0 && b == 2)) ? 2.0 : 0.0;
 }
 
-// Entry (lane, j) of [A P; P^T 0] (0 beyond s) in local coordinates; sx, sy
-// hold the scaled stencil offsets of all lanes, (xt, yt) this lane's own,
-// (ea, eb) its monomial exponents when n <= lane < s.
-__device__ __forceinline__ double system_entry(int lane, int j, int n, int s, int m, double xt,
-                                               double yt, int ea, int eb, const double *sx,
-                                               const double *sy) {
-    if (lane < n) {
-        if (j < n) {
-            const double ddx = xt - sx[j], ddy = yt - sy[j];
-            const double dd = ddx * ddx + ddy * ddy;
-            return ipow(dd, (m - 1) / 2) * sqrt(dd);
-        }
-        if (j < s) {
-            int ja, jb;
-            mono_exp(j - n, ja, jb);
-            return pow_chain(xt, ja) * pow_chain(yt, jb);
-        }
-        return 0.0;
-    }
-    if (lane < s && j < n) return pow_chain(sx[j], ea) * pow_chain(sy[j], eb);
-    return 0.0;
+// Lane of the largest c >= 0 over the wave (lanes with c < 0 or NaN are not
+// candidates), up to a relative 2^-14: the key is the high word of c (sign,
+// exponent, 20 mantissa bits) with its low six bits replaced by 63 - lane,
+// so one unsigned maximum reduction yields a lane whose value is within
+// 2^-14 of the largest (ties in the key go to the lowest lane).  Partial
+// pivoting needs no more: the multipliers stay below 1 + 2^-14.
+__device__ __forceinline__ int wave_argmax_packed(double c, int lane) {
+    const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(c) >> 32);
+    unsigned key = (c >= 0.0) ? ((hi & ~63u) | (unsigned)(63 - lane)) : 0u;
+    key = max(key, (unsigned)__builtin_amdgcn_update_dpp(0, (int)key, kDppRor8, 0xF, 0xF, false));
+    key = max(key, (unsigned)__builtin_amdgcn_update_dpp(0, (int)key, kDppRor4, 0xF, 0xF, false));
+    key = max(key, (unsigned)__builtin_amdgcn_update_dpp(0, (int)key, kDppSwap2, 0xF, 0xF, false));
+    key = max(key, (unsigned)__builtin_amdgcn_update_dpp(0, (int)key, kDppSwap1, 0xF, 0xF, false));
+    const unsigned k0 = (unsigned)__builtin_amdgcn_readlane((int)key, 0);
+    const unsigned k1 = (unsigned)__builtin_amdgcn_readlane((int)key, 16);
+    const unsigned k2 = (unsigned)__builtin_amdgcn_readlane((int)key, 32);
+    const unsigned k3 = (unsigned)__builtin_amdgcn_readlane((int)key, 48);
+    return 63 - (int)(max(max(k0, k1), max(k2, k3)) & 63u);
 }
 
 // SMAX bounds the system size; FIXED: the number of operators is exactly
@@ -287,17 +269,22 @@ __device__ __forceinline__ double system_entry(int lane, int j, int n, int s, in
 // condition estimate is computed (a separate instantiation, so that the
 // plain solve does not carry its registers).
 template <int SMAX, bool FIXED, int NOPS, bool COND>
-__global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, int64_t nq,
+__device__ __forceinline__ void weights_system(const double *__restrict__ xq, int64_t nq,
                                                 const double *__restrict__ xs, int64_t ns,
                                                 const int *__restrict__ idx, int n, int m, int q,
                                                 OpSet ops, double *__restrict__ w,
                                                 double *__restrict__ cond,
                                                 unsigned long long *__restrict__ bad) {
+    // Right-hand sides held per lane; those beyond the operator count are
+    // zero and stay zero, so the loops run over all NO without guards.
+    constexpr int NO = FIXED ? NOPS : kMaxOps;
+    // k_p < n and n + k_p <= SMAX bound the monomial count by SMAX / 2.
+    constexpr int KPS = (SMAX / 2 < 21) ? SMAX / 2 : 21;
+    static_assert(SMAX <= 64, "one row per lane");
     __shared__ double sx[64], sy[64];
-    constexpr int NO = FIXED ? NOPS : kMaxOps;  // right-hand sides held per lane
+    __shared__ double smono[KPS][SMAX];     // monomial t at stencil node i < n
+    __shared__ double prow[2][SMAX + NO];   // pivot row of a step (alternate buffers)
     __shared__ double sol[NO][SMAX];
-    __shared__ int pl[SMAX];
-
     const int64_t row = blockIdx.x;
     const int lane = threadIdx.x;
     const int kp = (q < 0) ? 0 : (q + 1) * (q + 2) / 2;
@@ -327,14 +314,40 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
     const double xt = ldexp(dx, -e), yt = ldexp(dy, -e);
     sx[lane] = xt;
     sy[lane] = yt;
+    // The monomials of this lane's node: slot t has fixed exponents, so the
+    // products fold to straight-line code; the P block reads them back.
+    if (lane < n) {
+#pragma unroll
+        for (int t = 0; t < KPS; ++t) {
+            if (t < kp) {
+                int ta, tb;
+                mono_exp(t, ta, tb);
+                smono[t][lane] = pow_chain(xt, ta) * pow_chain(yt, tb);
+            }
+        }
+    }
     __syncthreads();
 
-    // 2. This lane's row of [A P; P^T 0] and its right-hand sides.
+    // 2. This lane's row of [A P; P^T 0] and its right-hand sides.  Entry
+    // (lane, j) for j < s (0 for lanes >= s); the branches on j are uniform.
+    const int tl = (lane >= n && lane < s) ? lane - n : 0;  // P^T row: monomial slot
+    const int nl = (lane < n) ? lane : 0;
+    auto entry = [&](int j) -> double {
+        if (j < n) {
+            const double ddx = xt - sx[j], ddy = yt - sy[j];
+            const double dd = ddx * ddx + ddy * ddy;
+            const double phi = ipow(dd, (m - 1) / 2) * sqrt(dd);
+            const double pt = smono[tl][j];
+            return (lane < n) ? phi : ((lane < s) ? pt : 0.0);
+        }
+        const double pj = smono[j - n][nl];
+        return (lane < n) ? pj : 0.0;
+    };
     int ea = 0, eb = 0;
     if (lane >= n && lane < s) mono_exp(lane - n, ea, eb);
     double a[SMAX], b[NO];
 #pragma unroll
-    for (int j = 0; j < SMAX; ++j) a[j] = system_entry(lane, j, n, s, m, xt, yt, ea, eb, sx, sy);
+    for (int j = 0; j < SMAX; ++j) a[j] = (j < s) ? entry(j) : 0.0;
     // This lane's right-hand sides (recomputed, not kept, for the
     // refinement's residual).
     auto rhs = [&](int o) {
@@ -362,31 +375,46 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
         anorm = readlane_d(rs, 0);
     }
 
-    // 3. LU with partial pivoting across lanes.
+    // 3. LU with partial pivoting across lanes.  The pivot lane writes the
+    // rest of its row and its right-hand sides to LDS; every lane reads them
+    // as broadcasts (two buffers, so one barrier per step orders the reads of
+    // a step before the writes two steps later).
     int mystep = (lane < s) ? INT_MAX : -1;  // INT_MAX: row not yet a pivot
     double myinv = 0.0;
 #pragma unroll
     for (int kk = 0; kk < SMAX; ++kk) {
         if (kk < s) {
-            const int piv = wave_argmax((mystep == INT_MAX) ? fabs(a[kk]) : -1.0, lane);
-            const double pv = readlane_d(a[kk], piv);
+            double *pr = prow[kk & 1];
+            const int piv = wave_argmax_packed((mystep == INT_MAX) ? fabs(a[kk]) : -1.0, lane);
+            if (lane == piv) {
+                if (mystep != INT_MAX) bad_row = true;  // no candidate left (non-finite column)
+                mystep = kk;
+#pragma unroll
+                for (int j = kk; j < SMAX; ++j) pr[j] = a[j];
+#pragma unroll
+                for (int o = 0; o < NO; ++o) pr[SMAX + o] = b[o];
+            }
+            __syncthreads();
+            const double pv = pr[kk];
             if (!(fabs(pv) > tiny) || !isfinite(pv)) bad_row = true;
-            const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
-            const bool elim = (mystep == INT_MAX) && lane != piv;
+            // 1 / pv: hardware reciprocal and two Newton steps (a last-bit
+            // error here is removed by the refinement step).
+            double inv = 0.0;
+            if (pv != 0.0) {
+                double x = __builtin_amdgcn_rcp(pv);
+                x = fma(x, fma(-pv, x, 1.0), x);
+                inv = fma(x, fma(-pv, x, 1.0), x);
+            }
+            if (lane == piv) myinv = inv;
+            const bool elim = (mystep == INT_MAX);
             // Rows that do not eliminate use the multiplier 0: fma(-0, p, a)
             // returns a unchanged for finite p, so no per-entry select.
             const double l = elim ? a[kk] * inv : 0.0;
-            if (lane == piv) {
-                mystep = kk;
-                myinv = inv;
-                pl[kk] = lane;
-            }
             if (elim) a[kk] = l;  // multiplier, kept for the refinement solve
 #pragma unroll
-            for (int j = kk + 1; j < SMAX; ++j) a[j] = fma(-l, readlane_d(a[j], piv), a[j]);
+            for (int j = kk + 1; j < SMAX; ++j) a[j] = fma(-l, pr[j], a[j]);
 #pragma unroll
-            for (int o = 0; o < NO; ++o)
-                if (o < nops) b[o] = fma(-l, readlane_d(b[o], piv), b[o]);
+            for (int o = 0; o < NO; ++o) b[o] = fma(-l, pr[SMAX + o], b[o]);
         }
     }
 
@@ -394,14 +422,13 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
 #pragma unroll
     for (int kk = SMAX - 1; kk >= 0; --kk) {
         if (kk < s) {
-            const int pk = pl[kk];
+            const int pk = step_lane(mystep, kk);
+            const double uk = (mystep < kk) ? a[kk] : 0.0;
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
-                if (o < nops) {
-                    const double xk = readlane_d(b[o] * myinv, pk);
-                    if (mystep < kk) b[o] = fma(-a[kk], xk, b[o]);
-                    if (lane == 0) sol[o][kk] = xk;
-                }
+                const double xk = readlane_d(b[o] * myinv, pk);
+                b[o] = fma(-uk, xk, b[o]);
+                if (lane == 0) sol[o][kk] = xk;
             }
         }
     }
@@ -416,24 +443,20 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
         hi[o] = rhs(o);
         lo[o] = 0.0;
     }
-    if (lane < s) {
 #pragma unroll
-        for (int j = 0; j < SMAX; ++j) {
-            if (j < s) {
-                const double aj = system_entry(lane, j, n, s, m, xt, yt, ea, eb, sx, sy);
+    for (int j = 0; j < SMAX; ++j) {
+        if (j < s) {
+            const double aj = entry(j);
 #pragma unroll
-                for (int o = 0; o < NO; ++o) {
-                    if (o < nops) {
-                        const double xj = sol[o][j];
-                        const double p = aj * xj;
-                        const double pe = fma(aj, xj, -p);
-                        const double t = hi[o] - p;
-                        const double bv = t - hi[o];
-                        const double err = (hi[o] - (t - bv)) + (-p - bv);
-                        hi[o] = t;
-                        lo[o] = lo[o] + (err - pe);
-                    }
-                }
+            for (int o = 0; o < NO; ++o) {
+                const double xj = sol[o][j];
+                const double p = aj * xj;
+                const double pe = fma(aj, xj, -p);
+                const double t = hi[o] - p;
+                const double bv = t - hi[o];
+                const double err = (hi[o] - (t - bv)) + (-p - bv);
+                hi[o] = t;
+                lo[o] = lo[o] + (err - pe);
             }
         }
     }
@@ -443,27 +466,22 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
 #pragma unroll
     for (int kk = 0; kk < SMAX; ++kk) {
         if (kk < s) {
-            const int pk = pl[kk];
+            const int pk = step_lane(mystep, kk);
+            const double lk = (mystep > kk && mystep != INT_MAX) ? a[kk] : 0.0;
 #pragma unroll
-            for (int o = 0; o < NO; ++o) {
-                if (o < nops) {
-                    const double yk = readlane_d(r[o], pk);
-                    if (mystep > kk && mystep != INT_MAX) r[o] = fma(-a[kk], yk, r[o]);
-                }
-            }
+            for (int o = 0; o < NO; ++o) r[o] = fma(-lk, readlane_d(r[o], pk), r[o]);
         }
     }
 #pragma unroll
     for (int kk = SMAX - 1; kk >= 0; --kk) {
         if (kk < s) {
-            const int pk = pl[kk];
+            const int pk = step_lane(mystep, kk);
+            const double uk = (mystep < kk) ? a[kk] : 0.0;
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
-                if (o < nops) {
-                    const double dk = readlane_d(r[o] * myinv, pk);
-                    if (mystep < kk) r[o] = fma(-a[kk], dk, r[o]);
-                    if (lane == 0) sol[o][kk] += dk;
-                }
+                const double dk = readlane_d(r[o] * myinv, pk);
+                r[o] = fma(-uk, dk, r[o]);
+                if (lane == 0) sol[o][kk] += dk;
             }
         }
     }
@@ -484,7 +502,7 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
     const bool any_bad = __any(bad_row);
     if constexpr (COND) {
         double c = NAN;
-        if (!any_bad) c = anorm * inv_norm1_estimate<SMAX>(a, mystep, myinv, pl, s, lane);
+        if (!any_bad) c = anorm * inv_norm1_estimate<SMAX>(a, mystep, myinv, s, lane);
         if (lane == 0) cond[row] = c;
     }
     if (any_bad) {
@@ -493,6 +511,26 @@ __global__ void __launch_bounds__(64) k_weights(const double *__restrict__ xq, i
         }
         if (lane == 0) atomicMin(bad, (unsigned long long)row);
     }
+}
+
+// The plain solve for systems of at most 40 rows is compiled for four waves
+// per SIMD (at most 128 VGPRs, a few of them spilled to scratch): the extra
+// wave hides more of the latency of the elimination steps than three waves
+// without spills.  The other forms keep the compiler's own register budget.
+template <int SMAX, bool FIXED, int NOPS>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+k_weights(const double *__restrict__ xq, int64_t nq, const double *__restrict__ xs, int64_t ns,
+          const int *__restrict__ idx, int n, int m, int q, OpSet ops, double *__restrict__ w,
+          double *__restrict__ cond, unsigned long long *__restrict__ bad) {
+    weights_system<SMAX, FIXED, NOPS, false>(xq, nq, xs, ns, idx, n, m, q, ops, w, cond, bad);
+}
+
+template <int SMAX, bool FIXED, int NOPS, bool COND>
+__global__ void __launch_bounds__(64)
+k_weights_any(const double *__restrict__ xq, int64_t nq, const double *__restrict__ xs, int64_t ns,
+              const int *__restrict__ idx, int n, int m, int q, OpSet ops, double *__restrict__ w,
+              double *__restrict__ cond, unsigned long long *__restrict__ bad) {
+    weights_system<SMAX, FIXED, NOPS, COND>(xq, nq, xs, ns, idx, n, m, q, ops, w, cond, bad);
 }
 
 }  // namespace
@@ -537,11 +575,14 @@ extern "C" rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const d
 #define RBF_WLAUNCH(SM, FX, NP)                                                                   \
     do {                                                                                          \
         if (cond_est)                                                                             \
-            hipLaunchKernelGGL((k_weights<SM, FX, NP, true>), dim3((uint32_t)nq), dim3(64), 0, st, xq, \
+            hipLaunchKernelGGL((k_weights_any<SM, FX, NP, true>), dim3((uint32_t)nq), dim3(64), 0, \
+                               st, xq, nq, xs, ns, idx, k, m, q, ops, w, cond_est, dbad);         \
+        else if constexpr (SM <= 40)                                                              \
+            hipLaunchKernelGGL((k_weights<SM, FX, NP>), dim3((uint32_t)nq), dim3(64), 0, st, xq,   \
                                nq, xs, ns, idx, k, m, q, ops, w, cond_est, dbad);                 \
         else                                                                                      \
-            hipLaunchKernelGGL((k_weights<SM, FX, NP, false>), dim3((uint32_t)nq), dim3(64), 0, st, \
-                               xq, nq, xs, ns, idx, k, m, q, ops, w, cond_est, dbad);             \
+            hipLaunchKernelGGL((k_weights_any<SM, FX, NP, false>), dim3((uint32_t)nq), dim3(64), 0, \
+                               st, xq, nq, xs, ns, idx, k, m, q, ops, w, cond_est, dbad);         \
     } while (0)
         if (k + kp <= 38 && ops.n == 1) RBF_WLAUNCH(38, true, 1);
         else if (k + kp <= 38 && ops.n == 2) RBF_WLAUNCH(38, true, 2);
