@@ -140,6 +140,27 @@ def test_weights_cavity_parity(P, gpu, K, seed):
     _say("worst weight error", worst)
 
 
+@pytest.mark.parametrize("kind,K", [("cavity", 12), ("hex", 10), ("square", 16)])
+def test_weights_unjittered_sets(P, gpu, kind, K):
+    """Node sets without jitter: a local system then holds many equal
+    entries, so the elimination meets exactly tied pivot candidates (taken
+    by the lowest lane); the weights stay within 1e-12 of the oracle."""
+    _say("weights unjittered", kind, K)
+    nd = {"cavity": lambda: ri.cavity_nodes(K, 0.0, 0), "hex": lambda: ri.hex_cavity_nodes(K, 0.0, 0),
+          "square": lambda: ri.square_nodes(K, 0.0, 0)}[kind]()
+    worst = 0.0
+    for name, (xq, xs) in _pairs(nd).items():
+        dq, ds = to_dev(xq, gpu), to_dev(xs, gpu)
+        idx = P.knn(dq, ds, 28)
+        w = P.assemble_weights(dq, ds, idx, 7, 3, 15).cpu().numpy()
+        ref = ow.stencil_weights(xq, xs, idx.cpu().numpy(), 7, 3, OPS_ALL)
+        for o in range(4):
+            e = row_rel_err(w[o], ref[o])
+            worst = max(worst, e)
+            assert e <= 1e-12, (name, o, e)
+    _say("worst weight error", worst)
+
+
 @pytest.mark.parametrize("n,m,q,mask", [(28, 7, -1, 15), (12, 3, 1, 15), (20, 5, 2, 7),
                                         (36, 9, 4, 15), (45, 7, 3, 8), (28, 1, 2, 1),
                                         (40, 9, 3, 6), (43, 7, 5, 15)])
