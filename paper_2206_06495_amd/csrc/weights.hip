@@ -5,7 +5,10 @@
 // P_jt = the monomials of degree <= q at x_j, right-hand sides L applied to
 // phi(||x - x_j||) and to the monomials at x = x_0; w is kept.
 //
-// One wavefront (64 lanes) solves one system.  Lane i owns row i of the
+// The paper's stencil (n = 28, cubic polynomials) without the condition
+// estimate goes to k_weights_pair (two systems per wavefront, further
+// below); every other form to k_weights:
+// one wavefront (64 lanes) solves one system.  Lane i owns row i of the
 // augmented matrix (s = n + K_p <= 64 rows) in registers; the monomials of
 // the P block are computed once per stencil node and shared through LDS.
 // LU with partial pivoting runs across lanes: the pivot is found by one
@@ -533,6 +536,395 @@ k_weights_any(const double *__restrict__ xq, int64_t nq, const double *__restric
     weights_system<SMAX, FIXED, NOPS, COND>(xq, nq, xs, ns, idx, n, m, q, ops, w, cond, bad);
 }
 
+// ---------------------------------------------------------------------------
+// Two systems per wavefront for the paper's stencil (n = 28 nodes, cubic
+// polynomials, K_p = 10): lanes 0-31 solve system 2b, lanes 32-63 system
+// 2b + 1, lane l of a half owning row l of the RBF block A.  Block
+// elimination of [A P; P^T 0] [w; c] = [f; g]:
+//   LU of A with partial pivoting (rows of the half) carried through the
+//   columns [P | f], back substitution gives X = A^-1 P and y = A^-1 f;
+//   the Schur system S c = P^T y - g with S = P^T X (10 x 10) is formed by
+//   dot products over LDS and solved with partial pivoting; w = y - X c.
+// One refinement step as in the one-system kernel: the residual of the
+// whole saddle-point system in double-FP64 (entries recomputed), then the
+// same block solve for the correction.  A and the augmented matrix have
+// comparable condition numbers on these stencils and S is far better
+// conditioned, so the block order loses nothing the refinement does not
+// recover.
+constexpr int kPairN = 28, kPairKP = 10;
+
+// Largest v within each 32-lane half (every lane gets its half's value).
+__device__ __forceinline__ double half_max(double v, int lane) {
+    v = fmax(v, dpp_d<kDppRor8>(v));
+    v = fmax(v, dpp_d<kDppRor4>(v));
+    v = fmax(v, dpp_d<kDppSwap2>(v));
+    v = fmax(v, dpp_d<kDppSwap1>(v));
+    const double h0 = fmax(readlane_d(v, 0), readlane_d(v, 16));
+    const double h1 = fmax(readlane_d(v, 32), readlane_d(v, 48));
+    return (lane < 32) ? h0 : h1;
+}
+
+// Pivot key of a candidate c >= 0 (0: no candidate): the high word of c
+// with its low six bits replaced by 63 - lane, as in wave_argmax_packed.
+__device__ __forceinline__ unsigned pivot_key(double c, bool cand, int lane) {
+    const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(c) >> 32);
+    return (cand && c >= 0.0) ? ((hi & ~63u) | (unsigned)(63 - lane)) : 0u;
+}
+
+// Lane of the largest key within each half; the half's idle lane 31 when
+// no lane of the half is a candidate.
+__device__ __forceinline__ int half_argmax_key(unsigned key, int lane) {
+    key = max(key, (unsigned)__builtin_amdgcn_update_dpp(0, (int)key, kDppRor8, 0xF, 0xF, false));
+    key = max(key, (unsigned)__builtin_amdgcn_update_dpp(0, (int)key, kDppRor4, 0xF, 0xF, false));
+    key = max(key, (unsigned)__builtin_amdgcn_update_dpp(0, (int)key, kDppSwap2, 0xF, 0xF, false));
+    key = max(key, (unsigned)__builtin_amdgcn_update_dpp(0, (int)key, kDppSwap1, 0xF, 0xF, false));
+    const unsigned h0 = max((unsigned)__builtin_amdgcn_readlane((int)key, 0),
+                            (unsigned)__builtin_amdgcn_readlane((int)key, 16));
+    const unsigned h1 = max((unsigned)__builtin_amdgcn_readlane((int)key, 32),
+                            (unsigned)__builtin_amdgcn_readlane((int)key, 48));
+    const unsigned km = (lane < 32) ? h0 : h1;
+    return km ? 63 - (int)(km & 63u) : (lane & 32) + 31;
+}
+
+// 1 / p: hardware reciprocal and two Newton steps (0 for p = 0).
+__device__ __forceinline__ double recip_nr(double p) {
+    if (p == 0.0) return 0.0;
+    double x = __builtin_amdgcn_rcp(p);
+    x = fma(x, fma(-p, x, 1.0), x);
+    return fma(x, fma(-p, x, 1.0), x);
+}
+
+// hi + lo -= a * x, exactly rounded product and compensated sum (the
+// refinement residual's double-FP64 accumulation).
+__device__ __forceinline__ void dd_sub_prod(double &hi, double &lo, double a, double x) {
+    const double p = a * x;
+    const double pe = fma(a, x, -p);
+    const double t = hi - p;
+    const double bv = t - hi;
+    const double err = (hi - (t - bv)) + (-p - bv);
+    hi = t;
+    lo = lo + (err - pe);
+}
+
+template <int NO>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+k_weights_pair(const double *__restrict__ xq, int64_t nq, const double *__restrict__ xs,
+               int64_t ns, const int *__restrict__ idx, int m, OpSet ops,
+               double *__restrict__ w, unsigned long long *__restrict__ bad) {
+    constexpr int N = kPairN, KP = kPairKP, R = KP + NO;
+    __shared__ double sx[2][32], sy[2][32];
+    __shared__ double prow[2][2][N + R];  // [buffer][half] pivot row of a step
+    __shared__ double sz[2][N][R];        // [half][unknown] X = A^-1 P | y = A^-1 f
+    __shared__ double sp[2][N][KP];       // [half][node] monomials
+    __shared__ double ss[2][KP][R];       // [half] rows of [S | P^T y - g]
+    __shared__ double sc[2][KP][NO];      // [half] c (then its correction)
+    __shared__ double sw[2][N][NO];       // [half] w
+    __shared__ double sr[2][KP][NO];      // [half] constraint residuals, then S right-hand sides
+    const int lane = threadIdx.x, h = lane >> 5, l = lane & 31;
+    const int64_t row = (int64_t)blockIdx.x * 2 + h;
+    const bool valid = row < nq;
+    const bool live = valid && l < N;
+    const int ln = (l < N) ? l : N - 1;   // stand-in row index for idle lanes
+    const int lk = (l < KP) ? l : KP - 1;
+
+    // 1. Stencil offsets, exact power-of-two scaling per system.
+    double dx = 0.0, dy = 0.0, d2 = 0.0;
+    bool bad_row = false;
+    if (live) {
+        int j = idx[(int64_t)l * nq + row];
+        if (j < 0 || (int64_t)j >= ns) {
+            bad_row = true;
+            j = 0;
+        }
+        dx = xs[j] - xq[row];
+        dy = xs[ns + j] - xq[nq + row];
+        d2 = dx * dx + dy * dy;
+    }
+    const double d2max = half_max(d2, lane);
+    int E = 0;
+    frexp(d2max, &E);
+    const int e = (E >= 0) ? (E + 1) / 2 : -((-E) / 2);
+    if (valid && (!(d2max > 0.0) || !isfinite(d2max))) bad_row = true;
+    const double xt = ldexp(dx, -e), yt = ldexp(dy, -e);
+    sx[h][l] = xt;
+    sy[h][l] = yt;
+    // This node's monomials (fixed exponents per slot), kept in LDS.
+#pragma unroll
+    for (int t = 0; t < KP; ++t) {
+        int ta, tb;
+        mono_exp(t, ta, tb);
+        if (l < N) sp[h][l][t] = pow_chain(xt, ta) * pow_chain(yt, tb);
+    }
+    __syncthreads();
+
+    // 2. Row l of A (recomputed the same way for the residual), of P, and of f.
+    auto phi = [&](int j) {
+        const double ddx = xt - sx[h][j], ddy = yt - sy[h][j];
+        const double dd = ddx * ddx + ddy * ddy;
+        return ipow(dd, (m - 1) / 2) * sqrt(dd);
+    };
+    auto rhsf = [&](int o) { return live ? rhs_phs(xt, yt, m, ops.code[o]) : 0.0; };
+    auto rhsg = [&](int t, int o) {
+        int ta, tb;
+        mono_exp(t, ta, tb);
+        return rhs_poly(ta, tb, ops.code[o]);
+    };
+    double a[N], pc[KP], b[NO];
+    double amax = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        a[j] = live ? phi(j) : 0.0;
+        amax = fmax(amax, fabs(a[j]));
+    }
+#pragma unroll
+    for (int t = 0; t < KP; ++t) {
+        pc[t] = live ? sp[h][ln][t] : 0.0;
+        amax = fmax(amax, fabs(pc[t]));
+    }
+#pragma unroll
+    for (int o = 0; o < NO; ++o) b[o] = rhsf(o);
+    const double tiny = 16.0 * __DBL_EPSILON__ * half_max(amax, lane);
+
+    // 3. LU of A with partial pivoting over the half's rows, carried through
+    // [P | f]; the pivot row goes through LDS (two buffers, one barrier per
+    // step).
+    int mystep = live ? INT_MAX : -1;
+    double myinv = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < N; ++kk) {
+        double *pr = prow[kk & 1][h];
+        const int piv = half_argmax_key(pivot_key(fabs(a[kk]), mystep == INT_MAX, lane), lane);
+        if (lane == piv) {
+            if (mystep != INT_MAX) bad_row = true;  // no candidate left in this column
+            mystep = kk;
+#pragma unroll
+            for (int j = kk; j < N; ++j) pr[j] = a[j];
+#pragma unroll
+            for (int t = 0; t < KP; ++t) pr[N + t] = pc[t];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) pr[N + KP + o] = b[o];
+        }
+        __syncthreads();
+        const double pv = pr[kk];
+        if (!(fabs(pv) > tiny) || !isfinite(pv)) bad_row = true;
+        const double inv = recip_nr(pv);
+        if (lane == piv) myinv = inv;
+        const bool elim = (mystep == INT_MAX);
+        const double lm = elim ? a[kk] * inv : 0.0;
+        if (elim) a[kk] = lm;
+#pragma unroll
+        for (int j = kk + 1; j < N; ++j) a[j] = fma(-lm, pr[j], a[j]);
+#pragma unroll
+        for (int t = 0; t < KP; ++t) pc[t] = fma(-lm, pr[N + t], pc[t]);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) b[o] = fma(-lm, pr[N + KP + o], b[o]);
+    }
+
+    // 4. Back substitution: unknown kk is solved in the pivot lane of step
+    // kk, which stores row kk of [X | y] in LDS for the other lanes.
+#pragma unroll
+    for (int kk = N - 1; kk >= 0; --kk) {
+        if (mystep == kk) {
+#pragma unroll
+            for (int t = 0; t < KP; ++t) sz[h][kk][t] = pc[t] * myinv;
+#pragma unroll
+            for (int o = 0; o < NO; ++o) sz[h][kk][KP + o] = b[o] * myinv;
+        }
+        __syncthreads();
+        const double uk = (mystep < kk) ? a[kk] : 0.0;
+#pragma unroll
+        for (int t = 0; t < KP; ++t) pc[t] = fma(-uk, sz[h][kk][t], pc[t]);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) b[o] = fma(-uk, sz[h][kk][KP + o], b[o]);
+    }
+
+    // 5. [S | P^T y - g] by dot products over the nodes, 32 entries a round.
+#pragma unroll 1
+    for (int e0 = 0; e0 < KP * R; e0 += 32) {
+        const int en = e0 + l;
+        const int ec = (en < KP * R) ? en : 0;
+        const int t = ec / R, c = ec - t * R;
+        double acc = 0.0;
+#pragma unroll 4
+        for (int j = 0; j < N; ++j) acc = fma(sp[h][j][t], sz[h][j][c], acc);
+        if (c >= KP) acc -= rhsg(t, c - KP);
+        if (en < KP * R) ss[h][t][c] = acc;
+    }
+    __syncthreads();
+
+    // 6. S c = P^T y - g: lanes 0..KP-1 of each half own the rows.
+    double srow[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) srow[c] = (l < KP) ? ss[h][lk][c] : 0.0;
+    int mys = (valid && l < KP) ? INT_MAX : -1;
+    double sinv = 0.0;
+    auto s_factor = [&]() {
+#pragma unroll
+        for (int kk = 0; kk < KP; ++kk) {
+            double *pr = prow[kk & 1][h];
+            const int piv = half_argmax_key(pivot_key(fabs(srow[kk]), mys == INT_MAX, lane), lane);
+            if (lane == piv) {
+                if (mys != INT_MAX) bad_row = true;
+                mys = kk;
+#pragma unroll
+                for (int c = kk; c < R; ++c) pr[c] = srow[c];
+            }
+            __syncthreads();
+            const double pv = pr[kk];
+            if (!(pv != 0.0) || !isfinite(pv)) bad_row = true;
+            const double inv = recip_nr(pv);
+            if (lane == piv) sinv = inv;
+            const bool elim = (mys == INT_MAX);
+            const double lm = elim ? srow[kk] * inv : 0.0;
+            if (elim) srow[kk] = lm;
+#pragma unroll
+            for (int c = kk + 1; c < R; ++c) srow[c] = fma(-lm, pr[c], srow[c]);
+        }
+    };
+    s_factor();
+    // Back substitution of the S system into sc (right-hand sides in
+    // srow[KP..]); S's factors stay in srow[0..KP-1] for the correction.
+    auto s_back = [&](double (&rs)[NO]) {
+#pragma unroll
+        for (int kk = KP - 1; kk >= 0; --kk) {
+            if (mys == kk) {
+#pragma unroll
+                for (int o = 0; o < NO; ++o) sc[h][kk][o] = rs[o] * sinv;
+            }
+            __syncthreads();
+            const double uk = (mys < kk) ? srow[kk] : 0.0;
+#pragma unroll
+            for (int o = 0; o < NO; ++o) rs[o] = fma(-uk, sc[h][kk][o], rs[o]);
+        }
+    };
+    double rs[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) rs[o] = srow[KP + o];
+    s_back(rs);
+    __syncthreads();
+
+    // 7. w = y - X c for node l.
+    double wv[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        double s = sz[h][ln][KP + o];
+#pragma unroll
+        for (int t = 0; t < KP; ++t) s = fma(-sz[h][ln][t], sc[h][t][o], s);
+        wv[o] = s;
+        if (l < N) sw[h][l][o] = s;
+    }
+    __syncthreads();
+
+    // 8. Residual of the saddle-point system in double-FP64: RBF rows in
+    // lanes 0..N-1, constraint rows (t, o) in lanes t * NO + o.
+    double r[NO];
+    {
+        double hi[NO], lo[NO];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            hi[o] = rhsf(o);
+            lo[o] = 0.0;
+        }
+#pragma unroll 2
+        for (int j = 0; j < N; ++j) {
+            const double aj = live ? phi(j) : 0.0;
+#pragma unroll
+            for (int o = 0; o < NO; ++o) dd_sub_prod(hi[o], lo[o], aj, sw[h][j][o]);
+        }
+#pragma unroll
+        for (int t = 0; t < KP; ++t) {
+            const double pt = live ? sp[h][ln][t] : 0.0;
+#pragma unroll
+            for (int o = 0; o < NO; ++o) dd_sub_prod(hi[o], lo[o], pt, sc[h][t][o]);
+        }
+#pragma unroll
+        for (int o = 0; o < NO; ++o) r[o] = hi[o] + lo[o];
+    }
+    {
+        const int en = (l < KP * NO) ? l : 0;
+        const int t = en / NO, o = en - t * NO;
+        double hi = rhsg(t, o), lo = 0.0;
+#pragma unroll 4
+        for (int j = 0; j < N; ++j) dd_sub_prod(hi, lo, sp[h][j][t], sw[h][j][o]);
+        __syncthreads();  // every lane has read sc and sw
+        if (l < KP * NO) sr[h][t][o] = hi + lo;
+    }
+
+    // 9. Correction: y' = A^-1 r (stored factors), S c' = P^T y' - r_c,
+    // w' = y' - X c'.
+#pragma unroll
+    for (int kk = 0; kk < N; ++kk) {
+        double *pr = prow[kk & 1][h];
+        if (mystep == kk) {
+#pragma unroll
+            for (int o = 0; o < NO; ++o) pr[o] = r[o];
+        }
+        __syncthreads();
+        const double lkk = (mystep > kk && mystep != INT_MAX) ? a[kk] : 0.0;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) r[o] = fma(-lkk, pr[o], r[o]);
+    }
+#pragma unroll
+    for (int kk = N - 1; kk >= 0; --kk) {
+        if (mystep == kk) {
+#pragma unroll
+            for (int o = 0; o < NO; ++o) sz[h][kk][KP + o] = r[o] * myinv;
+        }
+        __syncthreads();
+        const double uk = (mystep < kk) ? a[kk] : 0.0;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) r[o] = fma(-uk, sz[h][kk][KP + o], r[o]);
+    }
+    {
+        const int en = (l < KP * NO) ? l : 0;
+        const int t = en / NO, o = en - t * NO;
+        double acc = -sr[h][t][o];
+#pragma unroll 4
+        for (int j = 0; j < N; ++j) acc = fma(sp[h][j][t], sz[h][j][KP + o], acc);
+        __syncthreads();  // every lane has read sr
+        if (l < KP * NO) sr[h][t][o] = acc;
+    }
+    __syncthreads();
+    // Forward substitution with S's multipliers, then back substitution.
+#pragma unroll
+    for (int o = 0; o < NO; ++o) rs[o] = (l < KP) ? sr[h][lk][o] : 0.0;
+#pragma unroll
+    for (int kk = 0; kk < KP; ++kk) {
+        double *pr = prow[kk & 1][h];
+        if (mys == kk) {
+#pragma unroll
+            for (int o = 0; o < NO; ++o) pr[o] = rs[o];
+        }
+        __syncthreads();
+        const double lkk = (mys > kk && mys != INT_MAX) ? srow[kk] : 0.0;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) rs[o] = fma(-lkk, pr[o], rs[o]);
+    }
+    s_back(rs);
+    __syncthreads();
+
+    // 10. Weights in physical units; NaN for failed systems.
+    const unsigned long long bm = __ballot(bad_row);
+    const bool any_bad = valid && ((h ? (bm >> 32) : (bm & 0xffffffffull)) != 0);
+    bool nonfinite = false;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        double s = sz[h][ln][KP + o];
+#pragma unroll
+        for (int t = 0; t < KP; ++t) s = fma(-sz[h][ln][t], sc[h][t][o], s);
+        const double v = ldexp(wv[o] + s, -e * ops.order[o]);
+        if (!isfinite(v)) nonfinite = true;
+        if (live) w[((int64_t)o * N + l) * nq + row] = any_bad ? NAN : v;
+    }
+    const unsigned long long nm = __ballot(live && nonfinite);
+    const bool half_nonfinite = (h ? (nm >> 32) : (nm & 0xffffffffull)) != 0;
+    if (valid && half_nonfinite && !any_bad && live) {
+#pragma unroll
+        for (int o = 0; o < NO; ++o) w[((int64_t)o * N + l) * nq + row] = NAN;
+    }
+    if (valid && (any_bad || half_nonfinite) && l == 0) atomicMin(bad, (unsigned long long)row);
+}
+
 }  // namespace
 
 extern "C" rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const double *xs,
@@ -584,7 +976,17 @@ extern "C" rbf_status rbf_assemble_weights(const double *xq, int64_t nq, const d
             hipLaunchKernelGGL((k_weights_any<SM, FX, NP, false>), dim3((uint32_t)nq), dim3(64), 0, \
                                st, xq, nq, xs, ns, idx, k, m, q, ops, w, cond_est, dbad);         \
     } while (0)
-        if (k + kp <= 38 && ops.n == 1) RBF_WLAUNCH(38, true, 1);
+        // The paper's stencil without the condition estimate: two systems
+        // per wavefront.
+        const bool pair = !cond_est && k == kPairN && q == 3 && ops.n >= 1 && ops.n <= 3;
+        const dim3 pgrid((uint32_t)((nq + 1) / 2)), pblock(64);
+        if (pair && ops.n == 1)
+            hipLaunchKernelGGL(k_weights_pair<1>, pgrid, pblock, 0, st, xq, nq, xs, ns, idx, m, ops, w, dbad);
+        else if (pair && ops.n == 2)
+            hipLaunchKernelGGL(k_weights_pair<2>, pgrid, pblock, 0, st, xq, nq, xs, ns, idx, m, ops, w, dbad);
+        else if (pair)
+            hipLaunchKernelGGL(k_weights_pair<3>, pgrid, pblock, 0, st, xq, nq, xs, ns, idx, m, ops, w, dbad);
+        else if (k + kp <= 38 && ops.n == 1) RBF_WLAUNCH(38, true, 1);
         else if (k + kp <= 38 && ops.n == 2) RBF_WLAUNCH(38, true, 2);
         else if (k + kp <= 38 && ops.n == 3) RBF_WLAUNCH(38, true, 3);
         else if (k + kp <= 40) RBF_WLAUNCH(40, false, kMaxOps);
