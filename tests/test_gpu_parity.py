@@ -161,6 +161,24 @@ def test_weights_unjittered_sets(P, gpu, kind, K):
     _say("worst weight error", worst)
 
 
+def test_weights_pairing_independent(P, gpu):
+    """The paper's stencil is solved two systems per wavefront: a system's
+    weights must not depend on which system shares its wavefront, nor on an
+    empty second half (odd counts).  Subsets of 1, 2, 3 and 5 queries taken
+    at odd offsets reproduce the full assembly's rows bit for bit."""
+    nd = ri.hex_cavity_nodes(12, 0.3, 5)
+    dq, ds = to_dev(nd.xv, gpu), to_dev(nd.xp, gpu)
+    idx = P.knn(dq, ds, 28)
+    full = P.assemble_weights(dq, ds, idx, 7, 3, 6).cpu().numpy()
+    ref = ow.stencil_weights(nd.xv, nd.xp, idx.cpu().numpy(), 7, 3, [OP_DX, OP_DY])
+    for o in range(2):
+        assert row_rel_err(full[o], ref[o]) <= 1e-12
+    for start, cnt in ((0, 1), (7, 1), (3, 2), (11, 3), (101, 5)):
+        sub = P.assemble_weights(dq[:, start:start + cnt].contiguous(), ds,
+                                 idx[:, start:start + cnt].contiguous(), 7, 3, 6).cpu().numpy()
+        assert np.array_equal(sub, full[:, :, start:start + cnt]), (start, cnt)
+
+
 @pytest.mark.parametrize("n,m,q,mask", [(28, 7, -1, 15), (12, 3, 1, 15), (20, 5, 2, 7),
                                         (36, 9, 4, 15), (45, 7, 3, 8), (28, 1, 2, 1),
                                         (40, 9, 3, 6), (43, 7, 5, 15)])
