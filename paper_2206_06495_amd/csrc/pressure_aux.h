@@ -138,6 +138,45 @@ __device__ __forceinline__ T aux_row(const AuxOps<T> &P, int64_t r, F f) {
     return acc;
 }
 
+// Two lanes per row for the 28-entry stencils of the smoothing products:
+// lanes l and l + 32 of a wave take the two halves of row l's stencil, so a
+// launch has twice the waves (and loads in flight) of one lane per row.
+constexpr int kRowsPerBlock2 = kThreads / 2;
+
+// This lane's row in the two-lanes-per-row layout (one row pair per thread,
+// no grid-stride loop) and the half of the stencil it takes.
+__device__ __forceinline__ int64_t row2_of(int &half) {
+    const int lane = threadIdx.x & 63;
+    half = lane >> 5;
+    return (int64_t)rbf::xcd_block(blockIdx.x, gridDim.x) * kRowsPerBlock2 +
+           (threadIdx.x >> 6) * 32 + (lane & 31);
+}
+
+// Row r of the sparse part applied to f, each lane summing its half of the
+// stencil; both lanes of the pair return the row's sum (half 0 + half 1).
+template <int KT, class T, class F>
+__device__ __forceinline__ T aux_row2(const AuxOps<T> &P, int64_t r, int half, F f) {
+    static_assert(KT > 0 && KT % 2 == 0, "two halves of a fixed stencil");
+    constexpr int H = KT / 2;
+    int jj[H];
+    T ww[H];
+#pragma unroll
+    for (int q = 0; q < H; ++q) jj[q] = P.idx[(int64_t)(half * H + q) * P.m + r];
+#pragma unroll
+    for (int q = 0; q < H; ++q) ww[q] = P.w[(int64_t)(half * H + q) * P.m + r];
+    T acc = 0;
+#pragma unroll
+    for (int q = 0; q < H; ++q) acc = fma(ww[q], f(jj[q]), acc);
+    return acc + __shfl_xor(acc, 32, 64);
+}
+
+// Grid of the smoothing products: one row pair per thread for KT > 0, the
+// grid-stride row loop otherwise.
+template <int KT>
+inline dim3 aux_grid(int64_t m, int nb) {
+    return (KT > 0) ? dim3(rbf::blocks_for(m, kRowsPerBlock2)) : dim3(nb);
+}
+
 // Pre-smoothing sweep from x = W y: x1 = sc (yd + W (y - A_s yd)), y
 // scaled by sc = *ys, yd = W y unscaled (one gathered value per neighbour).
 template <int KT, class T>
@@ -147,12 +186,20 @@ __global__ void __launch_bounds__(kThreads) k_aux_pre(AuxOps<T> P, const T *__re
                                                        const int *flag) {
     if (*flag != 0) return;
     const T sc = (T)*ys;
-    for (int64_t it = 0;; ++it) {
-        const int64_t r = row_of(it);
-        if (r - threadIdx.x >= P.m) break;
-        if (r < P.m) {
-            const T ax = aux_row<KT, (KT > 0 ? KT : 1)>(P, r, [&](int j) { return yd[j]; });
-            x1[r] = sc * (yd[r] + P.dinv[r] * (y[r] - ax));
+    if constexpr (KT > 0) {
+        int half;
+        const int64_t r = row2_of(half);
+        const int64_t rr = (r < P.m) ? r : P.m - 1;
+        const T ax = aux_row2<KT>(P, rr, half, [&](int j) { return yd[j]; });
+        if (half == 0 && r < P.m) x1[r] = sc * (yd[r] + P.dinv[r] * (y[r] - ax));
+    } else {
+        for (int64_t it = 0;; ++it) {
+            const int64_t r = row_of(it);
+            if (r - threadIdx.x >= P.m) break;
+            if (r < P.m) {
+                const T ax = aux_row<KT, 1>(P, r, [&](int j) { return yd[j]; });
+                x1[r] = sc * (yd[r] + P.dinv[r] * (y[r] - ax));
+            }
         }
     }
 }
@@ -166,12 +213,20 @@ __global__ void __launch_bounds__(kThreads) k_aux_res(AuxOps<T> P, const T *__re
                                                        const int *flag) {
     if (*flag != 0) return;
     const T sc = (T)*ys, su = (T)*us;
-    for (int64_t it = 0;; ++it) {
-        const int64_t r = row_of(it);
-        if (r - threadIdx.x >= P.m) break;
-        if (r < P.m) {
-            const T ax = aux_row<KT, (KT > 0 ? KT : 1)>(P, r, [&](int j) { return u[j]; });
-            res[r] = P.sinv[r] * (sc * y[r] - su * ax);
+    if constexpr (KT > 0) {
+        int half;
+        const int64_t r = row2_of(half);
+        const int64_t rr = (r < P.m) ? r : P.m - 1;
+        const T ax = aux_row2<KT>(P, rr, half, [&](int j) { return u[j]; });
+        if (half == 0 && r < P.m) res[r] = P.sinv[r] * (sc * y[r] - su * ax);
+    } else {
+        for (int64_t it = 0;; ++it) {
+            const int64_t r = row_of(it);
+            if (r - threadIdx.x >= P.m) break;
+            if (r < P.m) {
+                const T ax = aux_row<KT, 1>(P, r, [&](int j) { return u[j]; });
+                res[r] = P.sinv[r] * (sc * y[r] - su * ax);
+            }
         }
     }
 }

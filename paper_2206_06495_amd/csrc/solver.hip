@@ -2638,15 +2638,17 @@ void aux_apply(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, const T *y, const
     static_assert(kAuxSweeps == 1 || kAuxSweeps == 2, "one or two smoothing sweeps");
     if constexpr (kAuxSweeps == 2) {
         launch_kt(P.k, [&](auto KT) {
-            hipLaunchKernelGGL((k_aux_pre<decltype(KT)::value, T>), grid, block, 0, st, P, y, yd, ys,
+            hipLaunchKernelGGL((k_aux_pre<decltype(KT)::value, T>),
+                               aux_grid<decltype(KT)::value>(P.m, grid.x), block, 0, st, P, y, yd, ys,
                                F.x1, F.s.flag);
         });
         u = F.x1;
         us = F.s.one;
     }
     launch_kt(P.k, [&](auto KT) {
-        hipLaunchKernelGGL((k_aux_res<decltype(KT)::value, T>), grid, block, 0, st, P, y, ys, u, us,
-                           F.res, F.s.flag);
+        hipLaunchKernelGGL((k_aux_res<decltype(KT)::value, T>),
+                           aux_grid<decltype(KT)::value>(P.m, grid.x), block, 0, st, P, y, ys, u,
+                           us, F.res, F.s.flag);
     });
     hipLaunchKernelGGL(k_aux_restrict<T>, dim3(rbf::blocks_for(4 * (int64_t)nq, 256)), dim3(256), 0,
                        st, P, S->lat, F.res, nq);
