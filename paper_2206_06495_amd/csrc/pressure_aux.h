@@ -456,6 +456,77 @@ __global__ void __launch_bounds__(kThreads) k_fg_av(AuxOps<T> P, const double *_
     fg_dots(F.V, F.s.vs, w, P.m, j, F.s.part);
 }
 
+// The same step for 28-entry stencils with two lanes per row: blocks of
+// 2 kThreads threads on the same grid (and the same kThreads rows per block
+// and grid-stride iteration), so the partial sums keep their count; lanes l
+// and l + 32 of a wave take the two halves of row l's stencil, and in the
+// dot products each half of the wave takes kFgChunk of the basis vectors,
+// 2 kFgChunk per pass over the rows.
+constexpr int kAvThreads = 2 * kThreads;
+
+template <class T>
+__global__ void __launch_bounds__(kAvThreads) k_fg_av2(AuxOps<T> P, const double *__restrict__ u1,
+                                                       double vscale, FgDev<T> F, int j) {
+    if (*F.s.flag != 0) return;
+    constexpr int NW = kAvThreads / 64;
+    __shared__ double lds[2 * kFgChunk * NW];
+    const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
+    const int nb = gridDim.x;
+    double sz[1] = {0.0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) sz[0] += F.s.partO[b];
+    rbf::block_sum<1>(sz, lds);
+    const double bterm = vscale * sz[0];  // border: u1 c (1^T z)
+    const T *z = F.Z + (int64_t)j * P.m;
+    T *w = F.V + (int64_t)(j + 1) * P.m;
+    const int64_t bx = rbf::xcd_block(blockIdx.x, nb);
+    auto row = [&](int64_t it) { return (bx + it * nb) * kThreads + wv * 32 + (lane & 31); };
+#pragma unroll 1
+    for (int64_t it = 0;; ++it) {
+        if ((bx + it * nb) * kThreads >= P.m) break;
+        const int64_t r = row(it);
+        const int64_t rr = (r < P.m) ? r : P.m - 1;
+        const T az = aux_row2<28>(P, rr, half, [&](int c) { return z[c]; });
+        if (half == 0 && r < P.m) w[r] = (T)((double)az + u1[r] * bterm);
+    }
+    __syncthreads();  // rows written by the other half are read below
+#pragma unroll 1
+    for (int i0 = 0; i0 <= j; i0 += 2 * kFgChunk) {
+        const int ib = i0 + half * kFgChunk;
+        double acc[kFgChunk];
+#pragma unroll
+        for (int c = 0; c < kFgChunk; ++c) acc[c] = 0.0;
+#pragma unroll 1
+        for (int64_t it = 0;; ++it) {
+            if ((bx + it * nb) * kThreads >= P.m) break;
+            const int64_t r = row(it);
+            if (r < P.m) {
+                const double wr = (double)w[r];
+#pragma unroll
+                for (int c = 0; c < kFgChunk; ++c)
+                    if (ib + c <= j) acc[c] += (double)F.V[(int64_t)(ib + c) * P.m + r] * wr;
+            }
+        }
+        // Sum within each half of the wave, then over the waves in a fixed order.
+#pragma unroll
+        for (int c = 0; c < kFgChunk; ++c)
+#pragma unroll
+            for (int off = 16; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+        if ((lane & 31) == 0) {
+#pragma unroll
+            for (int c = 0; c < kFgChunk; ++c) lds[(half * kFgChunk + c) * NW + wv] = acc[c];
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * kFgChunk && i0 + (int)threadIdx.x <= j) {
+            const int q = threadIdx.x;
+            double t = 0.0;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) t += lds[q * NW + v];
+            F.s.part[(int64_t)(i0 + q) * kMaxBlocks + blockIdx.x] = t * F.s.vs[i0 + q];
+        }
+        __syncthreads();
+    }
+}
+
 // Gram-Schmidt update w -= sum_i h_i vs_i V_i (i <= j); PASS 1: then block
 // partial dots (V_i vs_i, w) for the second pass; PASS 2: then block
 // partial ||w||^2, and W w for the next preconditioner application.

@@ -2727,10 +2727,12 @@ rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, co
                     prof_pair(S, RBF_PROF_SPMV, e0, e1);
                     prof_pair(S, RBF_PROF_GS, g0, g1);
                 }
-                launch_kt(P.k, [&](auto KT) {
-                    hipExtLaunchKernelGGL((k_fg_av<decltype(KT)::value, T>), grid, block, 0, st, e0,
-                                          e1, 0, P, A.u1, A.vscale, F, j);
-                });
+                if (P.k == 28)
+                    hipExtLaunchKernelGGL((k_fg_av2<T>), grid, dim3(kAvThreads), 0, st, e0, e1, 0, P,
+                                          A.u1, A.vscale, F, j);
+                else
+                    hipExtLaunchKernelGGL((k_fg_av<0, T>), grid, block, 0, st, e0, e1, 0, P, A.u1,
+                                          A.vscale, F, j);
                 hipLaunchKernelGGL(k_fg_reduce<true>, dim3(j + 1), red, 0, st, Fs.part, nb, j + 1,
                                    Fs.h1, Fs.flag);
                 hipExtLaunchKernelGGL((k_fg_gs<T, 1>), grid, block, 0, st, g0, g1, 0, F, Fs.h1,
