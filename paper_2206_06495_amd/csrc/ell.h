@@ -59,4 +59,29 @@ __device__ __forceinline__ void ell_row(const int *__restrict__ idx, const doubl
     }
 }
 
+// Half of row r's stencil for a two-lanes-per-row layout: slots
+// half * KT/2 .. (half + 1) * KT/2 - 1 (KT > 0, even); the caller adds the
+// two lanes' sums.
+template <int KT, class Gather>
+__device__ __forceinline__ void ell_half_row(const int *__restrict__ idx,
+                                             const double *__restrict__ w, int64_t rows,
+                                             int64_t r, int half, Gather g,
+                                             double (&acc)[Gather::NV]) {
+    static_assert(KT > 0 && KT % 2 == 0, "two halves of a fixed stencil");
+    constexpr int H = KT / 2;
+    int jj[H];
+    double ww[H];
+#pragma unroll
+    for (int s = 0; s < H; ++s) jj[s] = ld_stream(idx + (int64_t)(half * H + s) * rows + r);
+#pragma unroll
+    for (int s = 0; s < H; ++s) ww[s] = ld_stream(w + (int64_t)(half * H + s) * rows + r);
+#pragma unroll
+    for (int s = 0; s < H; ++s) {
+        double v[Gather::NV];
+        g(jj[s], v);
+#pragma unroll
+        for (int c = 0; c < Gather::NV; ++c) acc[c] = fma(ww[s], v[c], acc[c]);
+    }
+}
+
 }  // namespace rbf

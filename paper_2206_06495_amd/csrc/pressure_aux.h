@@ -326,6 +326,46 @@ __global__ void __launch_bounds__(kThreads) k_aux_post(AuxOps<T> P, Lat L,
     store_partials<1>(acc, partO, gridDim.x);
 }
 
+// The same sweep for 28-entry stencils with two lanes per row: blocks of
+// 2 kThreads threads on the same grid and rows per block as k_aux_post, so
+// the block sums of z keep their count.
+template <class T, bool MU>
+__global__ void __launch_bounds__(2 * kThreads) k_aux_post2(AuxOps<T> P, Lat L,
+                                                           const T *__restrict__ y,
+                                                           const double *ys,
+                                                           const T *__restrict__ t1,
+                                                           const double *partZ,
+                                                           T *__restrict__ z, double *partO) {
+    if (*L.flag != 0) return;
+    __shared__ double lds[2 * kThreads / 64];
+    const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
+    const int nb = gridDim.x;
+    double mu = 0.0;
+    if constexpr (MU) {
+        double sz[1] = {0.0};
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) sz[0] += partZ[b];
+        rbf::block_sum<1>(sz, lds);
+        mu = (*L.mean / L.c - sz[0]) / (double)P.m;
+    }
+    const T sc = (T)*ys;
+    double acc[1] = {0.0};
+    const int64_t bx = rbf::xcd_block(blockIdx.x, nb);
+#pragma unroll 1
+    for (int64_t it = 0;; ++it) {
+        if ((bx + it * nb) * kThreads >= P.m) break;
+        const int64_t r = (bx + it * nb) * kThreads + wv * 32 + (lane & 31);
+        const int64_t rr = (r < P.m) ? r : P.m - 1;
+        const T at = aux_row2<28>(P, rr, half, [&](int j) { return t1[j]; });
+        if (half == 0 && r < P.m) {
+            const T zr = t1[r] + (T)mu + P.dinv[r] * (sc * y[r] - at);
+            z[r] = zr;
+            acc[0] += (double)zr;
+        }
+    }
+    rbf::block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partO[blockIdx.x] = acc[0];
+}
+
 // Cycle start: r = b - A x in FP64 (FP64 weights and border), V_0 = r and
 // W V_0; block sums of ||r||^2 and ||b||^2 (rows 0 and 1 of part).
 template <int KT, class T>

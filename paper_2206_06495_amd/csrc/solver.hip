@@ -1419,6 +1419,90 @@ __global__ void __launch_bounds__(kThreads) k_h_jac(EllM A, const double *__rest
     }
 }
 
+// The same sweep for 28-entry stencils with two lanes per row: blocks of
+// 2 kThreads threads on the same grid and rows per block, so the block
+// partial sums keep their count; lanes l and l + 32 of a wave take the two
+// halves of row l's stencil.
+template <bool FIRST>
+__global__ void __launch_bounds__(2 * kThreads) k_h_jac2(EllM A, const double *__restrict__ b,
+                                                        JKry J, int i, double tol2) {
+    constexpr int NW = 2 * kThreads / 64;
+    __shared__ double lds[2 * kHR * NW];
+    const int nb = gridDim.x;
+    const int fl = J.flag[0];
+    double q[2 * kHR] = {};
+    if (i > 0) {
+        const double *pp = J.part + (int64_t)((i - 1) & 1) * 2 * kHR * kMaxBlocks;
+        for (int bk = threadIdx.x; bk < nb; bk += blockDim.x)
+#pragma unroll
+            for (int c = 0; c < 2 * kHR; ++c) q[c] += pp[(int64_t)c * kMaxBlocks + bk];
+    }
+    if (fl != 0) return;
+    if (i > 0) {
+        rbf::block_sum<2 * kHR>(q, lds);
+        bool conv = true, bad = false;
+#pragma unroll
+        for (int c = 0; c < kHR; ++c) {
+            bad = bad || !isfinite(q[c]);
+            conv = conv && (q[c] <= tol2 * fmax(q[kHR + c], 1e-300) || q[c] == 0.0);
+        }
+        if (bad || conv) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+                for (int c = 0; c < kHR; ++c) J.bb[c] = q[kHR + c];
+                J.flag[1] = i - 1;
+                J.flag[0] = bad ? -1 : 1;
+            }
+            return;
+        }
+    }
+    const double2 *xin = reinterpret_cast<const double2 *>(J.x[i & 1]);
+    double2 *xout = reinterpret_cast<double2 *>(J.x[(i & 1) ^ 1]);
+    const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
+    const int64_t bx = rbf::xcd_block(blockIdx.x, nb);
+    double acc[2 * kHR] = {};
+#pragma unroll 1
+    for (int64_t it = 0;; ++it) {
+        if ((bx + it * nb) * kThreads >= A.n) break;
+        const int64_t row = (bx + it * nb) * kThreads + wv * 32 + (lane & 31);
+        const int64_t rr = (row < A.n) ? row : A.n - 1;
+        double ax[kHR] = {};
+        if constexpr (FIRST)
+            rbf::ell_half_row<28>(A.idx, A.w, A.n, rr, half, GatherN<kHR>{J.x0, A.n}, ax);
+        else
+            rbf::ell_half_row<28>(A.idx, A.w, A.n, rr, half, GatherI2{xin}, ax);
+#pragma unroll
+        for (int c = 0; c < kHR; ++c) ax[c] += __shfl_xor(ax[c], 32, 64);
+        if (half == 0 && row < A.n) {
+            double xs[kHR];
+            if constexpr (FIRST) {
+                xs[0] = J.x0[row];
+                xs[1] = J.x0[A.n + row];
+            } else {
+                const double2 t = xin[row];
+                xs[0] = t.x;
+                xs[1] = t.y;
+            }
+            const double di = A.dinv[row];
+            double xn[kHR];
+#pragma unroll
+            for (int c = 0; c < kHR; ++c) {
+                const double bv = b[c * A.n + row], rv = bv - ax[c];
+                xn[c] = xs[c] + di * rv;
+                acc[c] += rv * rv;
+                acc[kHR + c] += bv * bv;
+            }
+            xout[row] = make_double2(xn[0], xn[1]);
+        }
+    }
+    rbf::block_sum<2 * kHR>(acc, lds);
+    if (threadIdx.x == 0) {
+        double *pp = J.part + (int64_t)(i & 1) * 2 * kHR * kMaxBlocks;
+#pragma unroll
+        for (int c = 0; c < 2 * kHR; ++c) pp[(int64_t)c * kMaxBlocks + blockIdx.x] = acc[c];
+    }
+}
+
 // x ([2][N]) from an interleaved iterate ([N][2]).
 __global__ void k_h_deint(int64_t n, const double2 *__restrict__ xi, double *__restrict__ x) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -2186,10 +2270,10 @@ rbf_status hjacobi(rbf_solver *S, EllM A, const double *b, double *x, double tol
         const int stop = std::min(maxit + 2, it + batch);
         for (; it < stop; ++it) {
             if (it == 0) {
-                if (k28) hipLaunchKernelGGL((k_h_jac<28, true>), grid, block, 0, st, A, b, J, it, tol2);
+                if (k28) hipLaunchKernelGGL((k_h_jac2<true>), grid, dim3(2 * kThreads), 0, st, A, b, J, it, tol2);
                 else hipLaunchKernelGGL((k_h_jac<0, true>), grid, block, 0, st, A, b, J, it, tol2);
             } else {
-                if (k28) hipLaunchKernelGGL((k_h_jac<28, false>), grid, block, 0, st, A, b, J, it, tol2);
+                if (k28) hipLaunchKernelGGL((k_h_jac2<false>), grid, dim3(2 * kThreads), 0, st, A, b, J, it, tol2);
                 else hipLaunchKernelGGL((k_h_jac<0, false>), grid, block, 0, st, A, b, J, it, tol2);
             }
         }
@@ -2657,18 +2741,22 @@ void aux_apply(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, const T *y, const
     // Post-smoothing: the first sweep adds the border's constant.
     T *zin = F.t1;
     if constexpr (kAuxSweeps == 2) {
-        launch_kt(P.k, [&](auto KT) {
-            hipLaunchKernelGGL((k_aux_post<decltype(KT)::value, T, true>), grid, block, 0, st, P,
-                               S->lat, y, ys, F.t1, F.s.partZ, F.z1, F.s.partO);
-        });
+        if (P.k == 28)
+            hipLaunchKernelGGL((k_aux_post2<T, true>), grid, dim3(2 * kThreads), 0, st, P, S->lat, y,
+                               ys, F.t1, F.s.partZ, F.z1, F.s.partO);
+        else
+            hipLaunchKernelGGL((k_aux_post<0, T, true>), grid, block, 0, st, P, S->lat, y, ys, F.t1,
+                               F.s.partZ, F.z1, F.s.partO);
         zin = F.z1;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (sample) prof_pair(S, RBF_PROF_SMOOTH, e0, e1);
-    launch_kt(P.k, [&](auto KT) {
-        hipExtLaunchKernelGGL((k_aux_post<decltype(KT)::value, T, kAuxSweeps == 1>), grid, block, 0,
-                              st, e0, e1, 0, P, S->lat, y, ys, zin, F.s.partZ, z, F.s.partO);
-    });
+    if (P.k == 28)
+        hipExtLaunchKernelGGL((k_aux_post2<T, kAuxSweeps == 1>), grid, dim3(2 * kThreads), 0, st, e0,
+                              e1, 0, P, S->lat, y, ys, zin, F.s.partZ, z, F.s.partO);
+    else
+        hipExtLaunchKernelGGL((k_aux_post<0, T, kAuxSweeps == 1>), grid, block, 0, st, e0, e1, 0, P,
+                              S->lat, y, ys, zin, F.s.partZ, z, F.s.partO);
 }
 
 // Flexible GMRES(kFgMax) on the pressure system with the two-level

@@ -42,7 +42,7 @@ def test_run_sums_statistics():
 def test_kernel_bytes():
     M = 1000
     b = bench.kernel_bytes(M, {}, 21.0)  # mean Arnoldi index 10: 11 basis vectors
-    assert b["k_aux_post"] == M * 368
+    assert b["k_aux_post2"] == M * 368
     assert b["k_fg_av2"] == M * (352 + 8 * 11)
     assert b["k_fg_gs<1>"] == M * (16 + 16 * 11)
 
