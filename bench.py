@@ -67,7 +67,7 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 # counters on a plain 256 MiB copy (2.0 and 1.0), mean over the working
 # launches of 3 steps from rest (mean Arnoldi index 13.8 for k_fg_av2 and
 # k_fg_gs<1>); None for a kernel changed since it was measured.
-TRAFFIC_BYTES = {"k_fg_av2": 90.90e6, "k_aux_post2": 69.00e6, "k_fg_gs<1>": 41.49e6,
+TRAFFIC_BYTES = {"k_fg_av2": 90.91e6, "k_aux_post2": 69.01e6, "k_fg_gs<1>": 38.27e6,
                  "k_pc_gemm<0>": 5.53e6}
 
 

@@ -570,32 +570,81 @@ __global__ void __launch_bounds__(kAvThreads) k_fg_av2(AuxOps<T> P, const double
 // Gram-Schmidt update w -= sum_i h_i vs_i V_i (i <= j); PASS 1: then block
 // partial dots (V_i vs_i, w) for the second pass; PASS 2: then block
 // partial ||w||^2, and W w for the next preconditioner application.
+// Blocks of 2 kThreads threads on the kThreads-rows grid: lanes l and l + 32
+// of a wave share row l, each summing the update over half of the basis
+// (i even or odd) and, in PASS 1, taking kFgChunk of the 2 kFgChunk dots of
+// each pass over the rows.
 template <class T, int PASS>
-__global__ void __launch_bounds__(kThreads) k_fg_gs(FgDev<T> F, const double *h,
-                                                     const T *__restrict__ dinv, int64_t m,
-                                                     int j) {
+__global__ void __launch_bounds__(2 * kThreads) k_fg_gs(FgDev<T> F, const double *h,
+                                                         const T *__restrict__ dinv, int64_t m,
+                                                         int j) {
     if (*F.s.flag != 0) return;
+    constexpr int NW = 2 * kThreads / 64;
     __shared__ double c[kFgMax + 1];
+    __shared__ double lds[2 * kFgChunk * NW];
     for (int i = threadIdx.x; i <= j; i += blockDim.x) c[i] = h[i] * F.s.vs[i];
     __syncthreads();
+    const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
+    const int nb = gridDim.x;
+    const int64_t bx = rbf::xcd_block(blockIdx.x, nb);
+    auto row = [&](int64_t it) { return (bx + it * nb) * kThreads + wv * 32 + (lane & 31); };
     T *w = F.V + (int64_t)(j + 1) * m;
     double nrm[1] = {0.0};
+#pragma unroll 1
     for (int64_t it = 0;; ++it) {
-        const int64_t r = row_of(it);
-        if (r - threadIdx.x >= m) break;
-        if (r < m) {
-            double wr = (double)w[r];
-            for (int i = 0; i <= j; ++i) wr -= c[i] * (double)F.V[(int64_t)i * m + r];
-            const T wt = (T)wr;
+        if ((bx + it * nb) * kThreads >= m) break;
+        const int64_t r = row(it);
+        const int64_t rr = (r < m) ? r : m - 1;
+        double s = 0.0;
+        for (int i = half; i <= j; i += 2) s += c[i] * (double)F.V[(int64_t)i * m + rr];
+        s += __shfl_xor(s, 32, 64);
+        if (half == 0 && r < m) {
+            const T wt = (T)((double)w[r] - s);
             w[r] = wt;
             if constexpr (PASS == 2) F.wd[r] = wt * dinv[r];
             nrm[0] += (double)wt * (double)wt;
         }
     }
     if constexpr (PASS == 1) {
-        fg_dots(F.V, F.s.vs, w, m, j, F.s.part);
+        __syncthreads();  // rows written by the other half are read below
+#pragma unroll 1
+        for (int i0 = 0; i0 <= j; i0 += 2 * kFgChunk) {
+            const int ib = i0 + half * kFgChunk;
+            double acc[kFgChunk];
+#pragma unroll
+            for (int q = 0; q < kFgChunk; ++q) acc[q] = 0.0;
+#pragma unroll 1
+            for (int64_t it = 0;; ++it) {
+                if ((bx + it * nb) * kThreads >= m) break;
+                const int64_t r = row(it);
+                if (r < m) {
+                    const double wr = (double)w[r];
+#pragma unroll
+                    for (int q = 0; q < kFgChunk; ++q)
+                        if (ib + q <= j) acc[q] += (double)F.V[(int64_t)(ib + q) * m + r] * wr;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kFgChunk; ++q)
+#pragma unroll
+                for (int off = 16; off >= 1; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
+            if ((lane & 31) == 0) {
+#pragma unroll
+                for (int q = 0; q < kFgChunk; ++q) lds[(half * kFgChunk + q) * NW + wv] = acc[q];
+            }
+            __syncthreads();
+            if (threadIdx.x < 2 * kFgChunk && i0 + (int)threadIdx.x <= j) {
+                const int q = threadIdx.x;
+                double t = 0.0;
+#pragma unroll
+                for (int v = 0; v < NW; ++v) t += lds[q * NW + v];
+                F.s.part[(int64_t)(i0 + q) * kMaxBlocks + blockIdx.x] = t * F.s.vs[i0 + q];
+            }
+            __syncthreads();
+        }
     } else {
-        store_partials<1>(nrm, F.s.part, gridDim.x);
+        rbf::block_sum<1>(nrm, lds);
+        if (threadIdx.x == 0) F.s.part[blockIdx.x] = nrm[0];
     }
 }
 

@@ -2823,11 +2823,12 @@ rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, co
                                           A.vscale, F, j);
                 hipLaunchKernelGGL(k_fg_reduce<true>, dim3(j + 1), red, 0, st, Fs.part, nb, j + 1,
                                    Fs.h1, Fs.flag);
-                hipExtLaunchKernelGGL((k_fg_gs<T, 1>), grid, block, 0, st, g0, g1, 0, F, Fs.h1,
-                                      P.dinv, m, j);
+                hipExtLaunchKernelGGL((k_fg_gs<T, 1>), grid, dim3(2 * kThreads), 0, st, g0, g1, 0, F,
+                                      Fs.h1, P.dinv, m, j);
                 hipLaunchKernelGGL(k_fg_reduce<true>, dim3(j + 1), red, 0, st, Fs.part, nb, j + 1,
                                    Fs.h2, Fs.flag);
-                hipLaunchKernelGGL((k_fg_gs<T, 2>), grid, block, 0, st, F, Fs.h2, P.dinv, m, j);
+                hipLaunchKernelGGL((k_fg_gs<T, 2>), grid, dim3(2 * kThreads), 0, st, F, Fs.h2, P.dinv, m,
+                                   j);
                 hipLaunchKernelGGL(k_fg_tail, one, red, 0, st, Fs, j, mr, nb);
             }
             RBF_CHECK_LAUNCH();
