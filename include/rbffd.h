@@ -502,10 +502,12 @@ rbf_status rbf_solver_apply_precond(rbf_solver *s, const double *y, double *z);
  *                    the auxiliary lattice (k_pc_gemm<0>, an n x n x n FP64
  *                    or FP32 product, n = cells per side - 1);
  *   RBF_PROF_SPMV    the Krylov product with the Poisson matrix (k_pc_av with
- *                    the lattice preconditioner, k_kry_a without one, k_fg_av
- *                    in FGMRES: the product plus the first Gram-Schmidt dots);
+ *                    the lattice preconditioner, k_kry_a without one, k_fg_av2
+ *                    in FGMRES (k_fg_av for stencils other than 28 nodes): the
+ *                    product plus the first Gram-Schmidt dots);
  *   RBF_PROF_SMOOTH  the post-smoothing product of the auxiliary-lattice
- *                    preconditioner (k_aux_post);
+ *                    preconditioner (k_aux_post2; k_aux_post for stencils
+ *                    other than 28 nodes);
  *   RBF_PROF_GS      the first Gram-Schmidt update of FGMRES (k_fg_gs<1>).
  * A sampled launch goes through hipExtLaunchKernelGGL with an event pair
  * that records the kernel's own start and end; the pairs are read at the
