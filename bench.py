@@ -65,10 +65,10 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 # Traffic beyond L2 per launch of the roofline kernels at the headline
 # workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE scaled by the same
 # counters on a plain 256 MiB copy (2.0 and 1.0), mean over the working
-# launches of 3 steps from rest (mean Arnoldi index 13.8 for k_fg_av2 and
+# launches of 3 steps from rest (mean Arnoldi index 12.0 for k_fg_av2 and
 # k_fg_gs<1>); None for a kernel changed since it was measured.
-TRAFFIC_BYTES = {"k_fg_av2": 90.91e6, "k_aux_post2": 69.01e6, "k_fg_gs<1>": 38.27e6,
-                 "k_pc_gemm<0>": 5.53e6}
+TRAFFIC_BYTES = {"k_fg_av2": 88.18e6, "k_aux_post2": 69.05e6, "k_fg_gs<1>": 33.56e6,
+                 "k_pc_gemm<0>": 22.76e6}
 
 
 def parse():

@@ -374,7 +374,7 @@ typedef struct {
  * two-level method: an l1-Jacobi sweep (damping 2) on the stored Poisson
  * rows, the
  * residual restricted (normalised bilinear weights, interior nodes to
- * interior lattice points) to a lattice of about two node spacings per cell
+ * interior lattice points) to a lattice of about one node spacing per cell
  * and solved there by the same fast Poisson solve with homogeneous Neumann
  * rows, interpolated back with the border's constant, and a second sweep;
  * flexible GMRES (restart 30) iterates with it.  Neither changes the

@@ -60,7 +60,7 @@ def _aux_reference(nd, ops, y):
     W = 2.0 / np.asarray(abs(A).sum(1)).ravel()
     c = 0.1 * ((~wall).sum() / np.abs(S[~wall]).sum()) / M  # the FGMRES border scale
     x0, x1, y0, y1 = nd.xp[0].min(), nd.xp[0].max(), nd.xp[1].min(), nd.xp[1].max()
-    Ka = max(4, min(int(np.floor(0.465 * np.sqrt(M) + 0.5)), 513))
+    Ka = max(4, min(int(np.floor(0.95 * np.sqrt(M) + 0.5)), 513))
     hx, hy, n = (x1 - x0) / Ka, (y1 - y0) / Ka, Ka - 1
     sx, sy = (nd.xp[0] - x0) / hx, (nd.xp[1] - y0) / hy
     i0 = np.clip(np.floor(sx).astype(int), 0, Ka - 1)
