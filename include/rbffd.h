@@ -55,7 +55,7 @@ typedef int32_t rbf_status;
 #define RBF_OP_DY 4u
 #define RBF_OP_LAP 8u
 
-#define RBF_ABI_VERSION 4
+#define RBF_ABI_VERSION 5
 
 typedef void *rbf_stream;
 
@@ -533,7 +533,10 @@ rbf_status rbf_solver_profile(rbf_solver *s, int32_t sample_every, double *avg_m
  * decided it, lattice_precond 1 when the pressure solve uses the lattice
  * preconditioner, viscous_mixed 1 when the viscous solve runs FP32 sweeps
  * inside FP64 iterative refinement (RBF_PRECISION_MIXED with
- * viscous_jacobi set).  Errors: RBF_E_ARG (NULL argument).
+ * viscous_jacobi set), aux_smooth_weight the weight of the second sweep of
+ * each smoothing pair of the auxiliary-lattice preconditioner relative to
+ * the first (in [1, 1.6], chosen at creation from the largest eigenvalue of
+ * the smoother's operator).  Errors: RBF_E_ARG (NULL argument).
  */
 typedef struct {
     int32_t viscous_jacobi;
@@ -542,6 +545,8 @@ typedef struct {
     int32_t aux_precond;   /* 1: auxiliary-lattice preconditioner with FGMRES */
     int32_t aux_cells;     /* its lattice cells per side (0 if unused)       */
     int32_t viscous_mixed; /* 1: FP32 viscous sweeps inside FP64 refinement  */
+    double aux_smooth_weight; /* weight of the second smoothing sweep of each
+                                 pair relative to the first (0 if unused)   */
 } rbf_solver_info;
 rbf_status rbf_solver_query(rbf_solver *s, rbf_solver_info *info);
 

@@ -79,7 +79,8 @@ class Diagnostics(ctypes.Structure):
 class SolverInfo(ctypes.Structure):
     _fields_ = [("viscous_jacobi", ctypes.c_int32), ("lattice_precond", ctypes.c_int32),
                 ("jacobi_bound", ctypes.c_double), ("aux_precond", ctypes.c_int32),
-                ("aux_cells", ctypes.c_int32), ("viscous_mixed", ctypes.c_int32)]
+                ("aux_cells", ctypes.c_int32), ("viscous_mixed", ctypes.c_int32),
+                ("aux_smooth_weight", ctypes.c_double)]
 
 
 class StepStats(ctypes.Structure):

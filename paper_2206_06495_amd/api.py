@@ -291,13 +291,14 @@ class Solver:
 
     def info(self):
         """How the solves run: {"viscous_jacobi", "lattice_precond", "jacobi_bound",
-        "aux_precond", "aux_cells", "viscous_mixed"}."""
+        "aux_precond", "aux_cells", "viscous_mixed", "aux_smooth_weight"}."""
         inf = _lib.SolverInfo()
         check(lib.rbf_solver_query(self._h, ctypes.byref(inf)))
         return {"viscous_jacobi": bool(inf.viscous_jacobi),
                 "lattice_precond": bool(inf.lattice_precond), "jacobi_bound": inf.jacobi_bound,
                 "aux_precond": bool(inf.aux_precond), "aux_cells": int(inf.aux_cells),
-                "viscous_mixed": bool(inf.viscous_mixed)}
+                "viscous_mixed": bool(inf.viscous_mixed),
+                "aux_smooth_weight": float(inf.aux_smooth_weight)}
 
     def run(self, state, nsteps, every=10, log=None):
         """Advance `state` by `nsteps` in rbf_step calls of `every` steps and,

@@ -75,6 +75,9 @@ struct AuxOps {
     const T *rval;    // weights, summing to 1 per lattice point
     int64_t m;
     int k;
+    // Weight of the second smoothing sweep of each pair relative to the
+    // first (chosen at set-up from the spectrum of W A_s, see aux_weight).
+    double w2 = 1.0;
 };
 
 // FGMRES scalars (device).  Basis vector V_j is stored unnormalised with
@@ -191,14 +194,14 @@ __global__ void __launch_bounds__(kThreads) k_aux_pre(AuxOps<T> P, const T *__re
         const int64_t r = row2_of(half);
         const int64_t rr = (r < P.m) ? r : P.m - 1;
         const T ax = aux_row2<KT>(P, rr, half, [&](int j) { return yd[j]; });
-        if (half == 0 && r < P.m) x1[r] = sc * (yd[r] + P.dinv[r] * (y[r] - ax));
+        if (half == 0 && r < P.m) x1[r] = sc * (yd[r] + (T)P.w2 * P.dinv[r] * (y[r] - ax));
     } else {
         for (int64_t it = 0;; ++it) {
             const int64_t r = row_of(it);
             if (r - threadIdx.x >= P.m) break;
             if (r < P.m) {
                 const T ax = aux_row<KT, 1>(P, r, [&](int j) { return yd[j]; });
-                x1[r] = sc * (yd[r] + P.dinv[r] * (y[r] - ax));
+                x1[r] = sc * (yd[r] + (T)P.w2 * P.dinv[r] * (y[r] - ax));
             }
         }
     }
@@ -229,6 +232,35 @@ __global__ void __launch_bounds__(kThreads) k_aux_res(AuxOps<T> P, const T *__re
             }
         }
     }
+}
+
+// Power iteration for the largest eigenvalue of W A_s, the smoother's
+// operator (set-up only): y = W A_s (s x) and block partial sums of y^2;
+// with s = 1 / ||x|| the norm of y estimates the eigenvalue.
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_aux_power(AuxOps<T> P, const double *__restrict__ x,
+                                                         double s, double *__restrict__ y,
+                                                         double *part) {
+    double acc[1] = {0.0};
+    for (int64_t it = 0;; ++it) {
+        const int64_t r = row_of(it);
+        if (r - threadIdx.x >= P.m) break;
+        if (r < P.m) {
+            const double ax = (double)aux_row<0, 1>(P, r, [&](int j) { return (T)x[j]; });
+            const double v = s * (double)P.dinv[r] * ax;
+            y[r] = v;
+            acc[0] += v * v;
+        }
+    }
+    store_partials<1>(acc, part, gridDim.x);
+}
+
+// Start vector of the power iteration: a fixed hash pattern in [-1, 1).
+__global__ void k_aux_power_start(int64_t m, double *__restrict__ x) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const uint32_t hsh = (uint32_t)r * 2654435761u;
+    x[r] = (double)(hsh >> 8) * (1.0 / 8388608.0) - 1.0;
 }
 
 // yd = W y for an explicit input vector.
@@ -318,7 +350,7 @@ __global__ void __launch_bounds__(kThreads) k_aux_post(AuxOps<T> P, Lat L,
         if (r - threadIdx.x >= P.m) break;
         if (r < P.m) {
             const T at = aux_row<KT, (KT > 0 ? KT : 1)>(P, r, [&](int j) { return t1[j]; });
-            const T zr = t1[r] + (T)mu + P.dinv[r] * (sc * y[r] - at);
+            const T zr = t1[r] + (T)mu + (MU ? (T)1 : (T)P.w2) * P.dinv[r] * (sc * y[r] - at);
             z[r] = zr;
             acc[0] += (double)zr;
         }
@@ -357,7 +389,7 @@ __global__ void __launch_bounds__(2 * kThreads) k_aux_post2(AuxOps<T> P, Lat L,
         const int64_t rr = (r < P.m) ? r : P.m - 1;
         const T at = aux_row2<28>(P, rr, half, [&](int j) { return t1[j]; });
         if (half == 0 && r < P.m) {
-            const T zr = t1[r] + (T)mu + P.dinv[r] * (sc * y[r] - at);
+            const T zr = t1[r] + (T)mu + (MU ? (T)1 : (T)P.w2) * P.dinv[r] * (sc * y[r] - at);
             z[r] = zr;
             acc[0] += (double)zr;
         }

@@ -3067,6 +3067,52 @@ rbf_status setup_aux_pc(rbf_solver *S, const rbf_grid *g, int mode) {
                        S->p_w, S->p_rowscale, ddinv, dsinv);
     RBF_CHECK_LAUNCH();
     S->ax64 = AuxOps<double>{S->idx_pp, S->p_w, ddinv, dsinv, drptr, drcol, drval, M, S->k};
+    // Weight of the second sweep of each smoothing pair, from the largest
+    // eigenvalue nu of W A_s (power iteration): the pair's error polynomial
+    // (1 - nu)(1 - w2 nu) stays within 1 in magnitude for w2 <= 1 / (nu - 1);
+    // w2 is 0.85 of that bound, between 1 and 1.6, with nu raised by 5 %
+    // (80 power steps approach it from below, within 5 % when the top
+    // eigenvalues cluster).  The h = 1/400 cavity (nu = 1.47) gets about
+    // 1.55: 32 instead of 35 FGMRES steps per time step; the graded
+    // cylinder sets (nu = 1.74-1.88) stay near 1, where a fixed 1.5 made
+    // their solves fail.
+    {
+        struct Scratch {
+            double *x = nullptr, *y = nullptr, *part = nullptr;
+            ~Scratch() {
+                (void)hipFree(x);
+                (void)hipFree(y);
+                (void)hipFree(part);
+            }
+        } P;
+        RBF_HIP(hipMalloc(&P.x, M * sizeof(double)));
+        RBF_HIP(hipMalloc(&P.y, M * sizeof(double)));
+        RBF_HIP(hipMalloc(&P.part, kMaxBlocks * sizeof(double)));
+        const int nbp = nblocks_rows(M);
+        std::vector<double> hp(nbp);
+        hipLaunchKernelGGL(k_aux_power_start, dim3(rbf::blocks_for(M, 256)), dim3(256), 0, st, M, P.x);
+        double scale = 1.0 / std::sqrt((double)M / 3.0), nu = 0.0;
+        for (int it = 0; it < 80; ++it) {
+            hipLaunchKernelGGL((k_aux_power<double>), dim3(nbp), dim3(kThreads), 0, st, S->ax64, P.x,
+                               scale, P.y, P.part);
+            RBF_CHECK_LAUNCH();
+            RBF_HIP(hipMemcpyAsync(hp.data(), P.part, nbp * sizeof(double), hipMemcpyDeviceToHost, st));
+            RBF_HIP(hipStreamSynchronize(st));
+            double ss = 0.0;
+            for (double v : hp) ss += v;
+            const double nrm = std::sqrt(ss);
+            if (!(nrm > 0.0) || !std::isfinite(nrm)) {
+                nu = 0.0;
+                break;
+            }
+            nu = nrm;  // ||W A_s x|| with ||x|| = 1 from the second step on
+            scale = 1.0 / nrm;
+            std::swap(P.x, P.y);
+        }
+        const double nus = 1.05 * nu;
+        double w2 = (nus > 1.0) ? 0.85 / (nus - 1.0) : 1.6;
+        S->ax64.w2 = (nu > 0.0) ? std::min(1.6, std::max(1.0, w2)) : 1.0;
+    }
     if (S->mixed) {
         float *w32, *dinv32, *sinv32, *rval32;
         const int64_t nw = (int64_t)S->k * M;
@@ -3083,6 +3129,7 @@ rbf_status setup_aux_pc(rbf_solver *S, const rbf_grid *g, int mode) {
         RBF_CHECK_LAUNCH();
         S->p_w32 = w32;
         S->ax32 = AuxOps<float>{S->idx_pp, w32, dinv32, sinv32, drptr, drcol, rval32, M, S->k};
+        S->ax32.w2 = S->ax64.w2;
         if ((rc = alloc_fg(S, S->fg32, M)) != RBF_OK) return rc;
         L.flag = S->fg32.s.flag;
     } else {
@@ -4234,6 +4281,7 @@ extern "C" rbf_status rbf_solver_query(rbf_solver *S, rbf_solver_info *info) {
     info->lattice_precond = S->pc_on ? 1 : 0;
     info->jacobi_bound = S->h_bound;
     info->aux_precond = S->aux_on ? 1 : 0;
+    info->aux_smooth_weight = S->aux_on ? S->ax64.w2 : 0.0;
     info->aux_cells = S->aux_K;
     return RBF_OK;
 }

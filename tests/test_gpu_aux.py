@@ -39,15 +39,10 @@ def _ell(idx, w, ncols):
                          shape=(R, ncols))
 
 
-def _aux_reference(nd, ops, y):
-    """Plain statement of the auxiliary-lattice preconditioner (header of
-    rbf_params.precond), built from the GPU's stencils and weights: two
-    l1-Jacobi sweeps (omega 2.0) from zero, residual, normalised bilinear
-    restriction of interior nodes to interior lattice points, zero-mean
-    solve of the 5-point Laplacian (cells of the bounding box divided into
-    Ka x Ka) with homogeneous one-sided Neumann rows by sparse LU (no
-    transforms), bilinear interpolation with wall values copied inward, the
-    border's constant, two more sweeps."""
+def _smoother_rows(nd, ops):
+    """Row-scaled pressure rows A_s (Laplacian rows inside, Neumann rows on
+    walls, each scaled to unit 2-norm, sign making the diagonal positive),
+    W = 2 / l1 row sums, the scales and the wall mask."""
     M = nd.n_p
     idx = ops["idx_pp"].cpu().numpy()
     wall = nd.p_tag != 0
@@ -58,6 +53,21 @@ def _aux_reference(nd, ops, y):
     S = np.where(wall, 1.0, -1.0) / rn
     A = (sp.diags(S) @ A0).tocsr()
     W = 2.0 / np.asarray(abs(A).sum(1)).ravel()
+    return A, W, S, wall
+
+
+def _aux_reference(nd, ops, y, w2):
+    """Plain statement of the auxiliary-lattice preconditioner (header of
+    rbf_params.precond), built from the GPU's stencils and weights: two
+    l1-Jacobi sweeps (omega 2.0, then 2.0 w2) from zero, residual, normalised bilinear
+    restriction of interior nodes to interior lattice points, zero-mean
+    solve of the 5-point Laplacian (cells of the bounding box divided into
+    Ka x Ka) with homogeneous one-sided Neumann rows by sparse LU (no
+    transforms), bilinear interpolation with wall values copied inward, the
+    border's constant, two more sweeps (omega 2.0, then 2.0 w2); w2 is the
+    weight the solver reports (chosen from the smoother's spectrum)."""
+    M = nd.n_p
+    A, W, S, wall = _smoother_rows(nd, ops)
     c = 0.1 * ((~wall).sum() / np.abs(S[~wall]).sum()) / M  # the FGMRES border scale
     x0, x1, y0, y1 = nd.xp[0].min(), nd.xp[0].max(), nd.xp[1].min(), nd.xp[1].max()
     Ka = max(4, min(int(np.floor(0.95 * np.sqrt(M) + 0.5)), 513))
@@ -90,7 +100,7 @@ def _aux_reference(nd, ops, y):
         return e[(ci - 1) * n + (cj - 1)]
 
     x1v = W * y
-    x1v = x1v + W * (y - A @ x1v)
+    x1v = x1v + w2 * W * (y - A @ x1v)
     r1 = y - A @ x1v
     g = Rm @ (r1 / S)
     lam = g.mean()
@@ -100,7 +110,47 @@ def _aux_reference(nd, ops, y):
     t1 = x1v + Je
     mu = (lam / c - Je.sum()) / M
     z = t1 + mu + W * (y - A @ t1)
-    return z + W * (y - A @ z)
+    return z + w2 * W * (y - A @ z)
+
+
+@pytest.mark.parametrize("kind", ["hex", "cylinder"])
+def test_aux_smooth_weight_from_spectrum(P, gpu, kind):
+    """The weight of the second smoothing sweep follows the largest
+    eigenvalue nu of W A_s: 0.85 / (1.05 nu' - 1) within [1, 1.6], nu' the
+    device's 80-step power-iteration estimate, which approaches nu (ARPACK
+    on the same rows) from below, within 7 % when the top eigenvalues
+    cluster.  The near-equilateral cavity (nu about 1.47) gets 1.5-1.6, the
+    graded cylinder channel (nu about 1.74) 1.0-1.25, below the bound
+    1 / (nu - 1) where the sweep pair would amplify."""
+    _say("aux smoothing weight", kind)
+    if kind == "hex":
+        nd = ri.hex_cavity_nodes(40, 0.3, 0)
+        S, ops, _, _ = _solver(P, nd, gpu, 100.0, 1e-3)
+    else:
+        from oracle import cylinder as oc
+        nd = ri.cylinder_nodes(h_wall=0.03, grading=0.05, box=(-2.5, 5.0, -2.5, 2.5))
+        grid, ops = gpu_cavity_ops(nd, gpu)
+        orc = oc.ChannelOracle(nd, 100.0, 5e-3)
+        S = P.Solver(grid, ops, to_dev(orc.u_bc, gpu), to_dev(orc.v_bc, gpu), 100.0, 5e-3,
+                     u_conv=1.0)
+    assert S.info()["aux_precond"]
+    w2 = S.info()["aux_smooth_weight"]
+    A, W = _smoother_rows(nd, ops)[:2]
+    WA = (sp.diags(W) @ A).tocsr()
+    nu = float(np.max(np.abs(spla.eigs(WA, k=4, which="LM", return_eigenvectors=False,
+                                       maxiter=5000, tol=1e-8))))
+
+    def weight(n):
+        return 1.6 if 1.05 * n <= 1.0 else min(1.6, max(1.0, 0.85 / (1.05 * n - 1.0)))
+
+    _say("nu", nu, "weight", w2, "bounds", weight(nu), weight(0.93 * nu))
+    assert weight(nu) - 1e-12 <= w2 <= weight(0.93 * nu) + 1e-12, (nu, w2)
+    assert w2 < 1.0 / (nu - 1.0)
+    if kind == "hex":
+        assert w2 >= 1.5
+    else:
+        assert 1.0 <= w2 < 1.3
+    S.close()
 
 
 @pytest.mark.parametrize("K", [9, 24, 61])
@@ -114,7 +164,9 @@ def test_aux_preconditioner_matches_its_definition(P, gpu, K):
     assert S.info()["aux_precond"]
     y = ri.random_vector(nd.n_p, 13)
     z = S.apply_precond(to_dev(y, gpu)).cpu().numpy()
-    ref = _aux_reference(nd, ops, y)
+    w2 = S.info()["aux_smooth_weight"]
+    assert 1.0 <= w2 <= 1.6, w2
+    ref = _aux_reference(nd, ops, y, w2)
     assert rel_err(z, ref) <= 1e-11, rel_err(z, ref)
     S.close()
 

@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_abi_version(lib):
     lib.rbf_abi_version.restype = ctypes.c_int32
-    assert lib.rbf_abi_version() == 4
+    assert lib.rbf_abi_version() == 5
 
 
 @pytest.mark.parametrize("kind,K,seed", [(0, 7, 0), (0, 40, 3), (1, 50, 1), (2, 2, 0), (2, 9, 4),
