@@ -65,10 +65,10 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 # Traffic beyond L2 per launch of the roofline kernels at the headline
 # workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE scaled by the same
 # counters on a plain 256 MiB copy (2.0 and 1.0), mean over the working
-# launches of 3 steps from rest (mean Arnoldi index 12.0 for k_fg_av2 and
+# launches of 3 steps from rest (mean Arnoldi index 11.9 for k_fg_av2 and
 # k_fg_gs<1>); None for a kernel changed since it was measured.
-TRAFFIC_BYTES = {"k_fg_av2": 88.18e6, "k_aux_post2": 69.05e6, "k_fg_gs<1>": 33.56e6,
-                 "k_pc_gemm<0>": 22.76e6}
+TRAFFIC_BYTES = {"k_fg_av2": 88.03e6, "k_aux_post2": 69.01e6, "k_fg_gs<1>": 34.29e6,
+                 "k_pc_gemm<0>": 22.75e6}
 
 
 def parse():
@@ -492,7 +492,8 @@ def cylinder_run(P, args, dev):
                        f"0.02 on the cylinder, Re={args.cyl_re:g}, dt={args.cyl_dt:g}, uniform "
                        "inflow, symmetry sides, convective outflow, start from U_0 = (1, 0) + "
                        f"{args.cyl_perturb:g} transverse blob",
-           "setup_s": setup_s, "aux_lattice_cells": S.info()["aux_cells"]}
+           "setup_s": setup_s, "aux_lattice_cells": S.info()["aux_cells"],
+           "aux_smooth_weight": S.info()["aux_smooth_weight"]}
     series = []
     try:
         S.step(st, 5)
@@ -645,6 +646,7 @@ def main():
                                "FGMRES with the two-level auxiliary-lattice preconditioner",
                    "poisson_rtol": args.rtol_p, "helmholtz_rtol": args.rtol_h,
                    "setup_s": setup_s, "aux_lattice_cells": info["aux_cells"],
+                   "aux_smooth_weight": info["aux_smooth_weight"],
                    "poisson_fgmres_steps_per_step": steps_per_ts,
                    "helmholtz_iters_per_step": stats.helmholtz_iters / max(1, args.steps),
                    "last_poisson_rel_residual": stats.last.last_poisson.rel_residual
