@@ -71,6 +71,37 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// A double moved across lanes by one DPP control (both 32-bit halves with
+// the same pattern; every lane active).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double readlane_double(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sums over the two halves of the wave (lanes 0-31 and 32-63), without LDS:
+// DPP rotations by 8 and 4 inside each 16-lane row, then quad swaps by 2
+// and 1, leave every lane with its row's sum; lanes 0 + 16 and 32 + 48 are
+// then read as uniform values.  A fixed order of additions: deterministic.
+// Every lane must be active.
+__device__ __forceinline__ void half_wave_sums(double v, double &lo, double &hi) {
+    v += dpp_move<0x128>(v);  // row_ror:8
+    v += dpp_move<0x124>(v);  // row_ror:4
+    v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+    lo = readlane_double(v, 0) + readlane_double(v, 16);
+    hi = readlane_double(v, 32) + readlane_double(v, 48);
+}
+
 // Block sum of NV doubles per thread; every thread returns the totals.
 // `lds` must hold NV * (blockDim.x / 64) doubles.  Deterministic.
 template <int NV>

@@ -531,17 +531,62 @@ __global__ void __launch_bounds__(kThreads) k_fg_av(AuxOps<T> P, const double *_
 // The same step for 28-entry stencils with two lanes per row: blocks of
 // 2 kThreads threads on the same grid (and the same kThreads rows per block
 // and grid-stride iteration), so the partial sums keep their count; lanes l
-// and l + 32 of a wave take the two halves of row l's stencil, and in the
-// dot products each half of the wave takes kFgChunk of the basis vectors,
-// 2 kFgChunk per pass over the rows.
+// and l + 32 of a wave take the two halves of row l's stencil.  The dots are
+// taken in the same pass over the rows: lane l + 32 h multiplies w by the
+// basis vectors i = 2c + h (slot c), so that each vector is read once, and
+// the slots are summed per half-wave by DPP, then over the waves in a fixed
+// order.
 constexpr int kAvThreads = 2 * kThreads;
+constexpr int kFgSlots = (kFgMax + 1) / 2;  // basis vectors per half-wave
+
+// Slot sums in LDS: column wv of lds (2 kFgSlots rows of NW) holds wave
+// wv's running sums of the basis vectors i = 2c (half 0) and 2c + 1
+// (half 1), owned by the wave's lane 0.  fg_slot_add adds one pass's
+// products (half-wave sums by DPP; every lane must be active);
+// fg_slot_partials sums the waves in a fixed order and writes the block
+// partials of rows i <= j of part, scaled by vs_i.
+template <int NW>
+__device__ __forceinline__ void fg_slot_zero(int ns, double *lds) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int i = 0; i < 2 * ns; ++i) lds[i * NW + wv] = 0.0;
+}
+
+template <int NW>
+__device__ __forceinline__ void fg_slot_add(const double (&prod)[kFgSlots], int ns, double *lds) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < kFgSlots; ++c) {
+        if (c < ns) {
+            double se, so;
+            rbf::half_wave_sums(prod[c], se, so);
+            if (lane == 0) {
+                lds[(2 * c) * NW + wv] += se;
+                lds[(2 * c + 1) * NW + wv] += so;
+            }
+        }
+    }
+}
+
+template <int NW>
+__device__ __forceinline__ void fg_slot_partials(int j, const double *vs, double *part,
+                                                 const double *lds) {
+    __syncthreads();
+    if ((int)threadIdx.x <= j) {
+        const int q = threadIdx.x;
+        double t = 0.0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) t += lds[q * NW + v];
+        part[(int64_t)q * kMaxBlocks + blockIdx.x] = t * vs[q];
+    }
+}
 
 template <class T>
-__global__ void __launch_bounds__(kAvThreads) k_fg_av2(AuxOps<T> P, const double *__restrict__ u1,
+__global__ void __launch_bounds__(kAvThreads) __attribute__((amdgpu_waves_per_eu(4))) k_fg_av2(AuxOps<T> P, const double *__restrict__ u1,
                                                        double vscale, FgDev<T> F, int j) {
     if (*F.s.flag != 0) return;
     constexpr int NW = kAvThreads / 64;
-    __shared__ double lds[2 * kFgChunk * NW];
+    __shared__ double lds[2 * kFgSlots * NW];
     const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
     const int nb = gridDim.x;
     double sz[1] = {0.0};
@@ -550,130 +595,94 @@ __global__ void __launch_bounds__(kAvThreads) k_fg_av2(AuxOps<T> P, const double
     const double bterm = vscale * sz[0];  // border: u1 c (1^T z)
     const T *z = F.Z + (int64_t)j * P.m;
     T *w = F.V + (int64_t)(j + 1) * P.m;
+    const int ns = (j + 2) >> 1;
+    fg_slot_zero<NW>(ns, lds);
     const int64_t bx = rbf::xcd_block(blockIdx.x, nb);
-    auto row = [&](int64_t it) { return (bx + it * nb) * kThreads + wv * 32 + (lane & 31); };
 #pragma unroll 1
     for (int64_t it = 0;; ++it) {
         if ((bx + it * nb) * kThreads >= P.m) break;
-        const int64_t r = row(it);
+        const int64_t r = (bx + it * nb) * kThreads + wv * 32 + (lane & 31);
         const int64_t rr = (r < P.m) ? r : P.m - 1;
         const T az = aux_row2<28>(P, rr, half, [&](int c) { return z[c]; });
-        if (half == 0 && r < P.m) w[r] = (T)((double)az + u1[r] * bterm);
-    }
-    __syncthreads();  // rows written by the other half are read below
-#pragma unroll 1
-    for (int i0 = 0; i0 <= j; i0 += 2 * kFgChunk) {
-        const int ib = i0 + half * kFgChunk;
-        double acc[kFgChunk];
+        const T wt = (T)((double)az + u1[rr] * bterm);
+        // The basis is read after the product, so that the two sets of
+        // loads in flight do not share the registers.  Slot c of half 1
+        // reads V[j+1] (this row of w, not yet stored) when 2c + 1 > j; that
+        // value is not used.
+        __builtin_amdgcn_sched_barrier(0);
+        const T *Vh = F.V + (int64_t)half * P.m + rr;
+        const double wr = (r < P.m) ? (double)wt : 0.0;
+        double prod[kFgSlots];
 #pragma unroll
-        for (int c = 0; c < kFgChunk; ++c) acc[c] = 0.0;
-#pragma unroll 1
-        for (int64_t it = 0;; ++it) {
-            if ((bx + it * nb) * kThreads >= P.m) break;
-            const int64_t r = row(it);
-            if (r < P.m) {
-                const double wr = (double)w[r];
-#pragma unroll
-                for (int c = 0; c < kFgChunk; ++c)
-                    if (ib + c <= j) acc[c] += (double)F.V[(int64_t)(ib + c) * P.m + r] * wr;
+        for (int c = 0; c < kFgSlots; ++c) {
+            prod[c] = 0.0;
+            if (c < ns) {
+                const double v = (double)Vh[(int64_t)(2 * c) * P.m];
+                if (2 * c + half <= j) prod[c] = v * wr;
             }
         }
-        // Sum within each half of the wave, then over the waves in a fixed order.
-#pragma unroll
-        for (int c = 0; c < kFgChunk; ++c)
-#pragma unroll
-            for (int off = 16; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
-        if ((lane & 31) == 0) {
-#pragma unroll
-            for (int c = 0; c < kFgChunk; ++c) lds[(half * kFgChunk + c) * NW + wv] = acc[c];
-        }
-        __syncthreads();
-        if (threadIdx.x < 2 * kFgChunk && i0 + (int)threadIdx.x <= j) {
-            const int q = threadIdx.x;
-            double t = 0.0;
-#pragma unroll
-            for (int v = 0; v < NW; ++v) t += lds[q * NW + v];
-            F.s.part[(int64_t)(i0 + q) * kMaxBlocks + blockIdx.x] = t * F.s.vs[i0 + q];
-        }
-        __syncthreads();
+        if (half == 0 && r < P.m) w[r] = wt;
+        fg_slot_add<NW>(prod, ns, lds);
     }
+    fg_slot_partials<NW>(j, F.s.vs, F.s.part, lds);
 }
 
 // Gram-Schmidt update w -= sum_i h_i vs_i V_i (i <= j); PASS 1: then block
 // partial dots (V_i vs_i, w) for the second pass; PASS 2: then block
 // partial ||w||^2, and W w for the next preconditioner application.
 // Blocks of 2 kThreads threads on the kThreads-rows grid: lanes l and l + 32
-// of a wave share row l, each summing the update over half of the basis
-// (i even or odd) and, in PASS 1, taking kFgChunk of the 2 kFgChunk dots of
-// each pass over the rows.
+// of a wave share row l, each reading the basis vectors of one parity
+// (slot c: i = 2c + h), which serve both the update and, in PASS 1, the
+// dots with the updated w.
 template <class T, int PASS>
-__global__ void __launch_bounds__(2 * kThreads) k_fg_gs(FgDev<T> F, const double *h,
+__global__ void __launch_bounds__(2 * kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_fg_gs(FgDev<T> F, const double *h,
                                                          const T *__restrict__ dinv, int64_t m,
                                                          int j) {
     if (*F.s.flag != 0) return;
     constexpr int NW = 2 * kThreads / 64;
     __shared__ double c[kFgMax + 1];
-    __shared__ double lds[2 * kFgChunk * NW];
+    __shared__ double lds[2 * kFgSlots * NW];
     for (int i = threadIdx.x; i <= j; i += blockDim.x) c[i] = h[i] * F.s.vs[i];
     __syncthreads();
     const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
     const int nb = gridDim.x;
+    const int ns = (j + 2) >> 1;
     const int64_t bx = rbf::xcd_block(blockIdx.x, nb);
-    auto row = [&](int64_t it) { return (bx + it * nb) * kThreads + wv * 32 + (lane & 31); };
     T *w = F.V + (int64_t)(j + 1) * m;
     double nrm[1] = {0.0};
+    if constexpr (PASS == 1) fg_slot_zero<NW>(ns, lds);
 #pragma unroll 1
     for (int64_t it = 0;; ++it) {
         if ((bx + it * nb) * kThreads >= m) break;
-        const int64_t r = row(it);
+        const int64_t r = (bx + it * nb) * kThreads + wv * 32 + (lane & 31);
         const int64_t rr = (r < m) ? r : m - 1;
+        // Slot q of half 1 reads V[j+1] = w when 2q + 1 > j (not used).
+        const T *Vh = F.V + (int64_t)half * m + rr;
+        double vv[kFgSlots];
+#pragma unroll
+        for (int q = 0; q < kFgSlots; ++q) vv[q] = (q < ns) ? (double)Vh[(int64_t)(2 * q) * m] : 0.0;
         double s = 0.0;
-        for (int i = half; i <= j; i += 2) s += c[i] * (double)F.V[(int64_t)i * m + rr];
+#pragma unroll
+        for (int q = 0; q < kFgSlots; ++q)
+            if (q < ns && 2 * q + half <= j) s += c[2 * q + half] * vv[q];
         s += __shfl_xor(s, 32, 64);
+        const T wt = (T)((double)w[rr] - s);
         if (half == 0 && r < m) {
-            const T wt = (T)((double)w[r] - s);
             w[r] = wt;
             if constexpr (PASS == 2) F.wd[r] = wt * dinv[r];
             nrm[0] += (double)wt * (double)wt;
         }
+        if constexpr (PASS == 1) {
+            const double wr = (r < m) ? (double)wt : 0.0;
+            double prod[kFgSlots];
+#pragma unroll
+            for (int q = 0; q < kFgSlots; ++q)
+                prod[q] = (q < ns && 2 * q + half <= j) ? vv[q] * wr : 0.0;
+            fg_slot_add<NW>(prod, ns, lds);
+        }
     }
     if constexpr (PASS == 1) {
-        __syncthreads();  // rows written by the other half are read below
-#pragma unroll 1
-        for (int i0 = 0; i0 <= j; i0 += 2 * kFgChunk) {
-            const int ib = i0 + half * kFgChunk;
-            double acc[kFgChunk];
-#pragma unroll
-            for (int q = 0; q < kFgChunk; ++q) acc[q] = 0.0;
-#pragma unroll 1
-            for (int64_t it = 0;; ++it) {
-                if ((bx + it * nb) * kThreads >= m) break;
-                const int64_t r = row(it);
-                if (r < m) {
-                    const double wr = (double)w[r];
-#pragma unroll
-                    for (int q = 0; q < kFgChunk; ++q)
-                        if (ib + q <= j) acc[q] += (double)F.V[(int64_t)(ib + q) * m + r] * wr;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < kFgChunk; ++q)
-#pragma unroll
-                for (int off = 16; off >= 1; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
-            if ((lane & 31) == 0) {
-#pragma unroll
-                for (int q = 0; q < kFgChunk; ++q) lds[(half * kFgChunk + q) * NW + wv] = acc[q];
-            }
-            __syncthreads();
-            if (threadIdx.x < 2 * kFgChunk && i0 + (int)threadIdx.x <= j) {
-                const int q = threadIdx.x;
-                double t = 0.0;
-#pragma unroll
-                for (int v = 0; v < NW; ++v) t += lds[q * NW + v];
-                F.s.part[(int64_t)(i0 + q) * kMaxBlocks + blockIdx.x] = t * F.s.vs[i0 + q];
-            }
-            __syncthreads();
-        }
+        fg_slot_partials<NW>(j, F.s.vs, F.s.part, lds);
     } else {
         rbf::block_sum<1>(nrm, lds);
         if (threadIdx.x == 0) F.s.part[blockIdx.x] = nrm[0];
