@@ -362,7 +362,8 @@ __global__ void __launch_bounds__(kThreads) k_aux_post(AuxOps<T> P, Lat L,
 // 2 kThreads threads on the same grid and rows per block as k_aux_post, so
 // the block sums of z keep their count.
 template <class T, bool MU>
-__global__ void __launch_bounds__(2 * kThreads) k_aux_post2(AuxOps<T> P, Lat L,
+__global__ void __launch_bounds__(2 * kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_aux_post2(AuxOps<T> P, Lat L,
                                                            const T *__restrict__ y,
                                                            const double *ys,
                                                            const T *__restrict__ t1,
@@ -371,23 +372,33 @@ __global__ void __launch_bounds__(2 * kThreads) k_aux_post2(AuxOps<T> P, Lat L,
     if (*L.flag != 0) return;
     __shared__ double lds[2 * kThreads / 64];
     const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
-    const int nb = gridDim.x;
+    const int nb = gridDim.x;  // <= kMaxBlocks = 2 blockDim.x: two partials per thread
+    // The partials of mu and the first row iteration's product (every block
+    // has one) are loaded before mu is reduced, so that the reduction
+    // overlaps the gathers.
+    const double pz0 = (MU && (int)threadIdx.x < nb) ? partZ[threadIdx.x] : 0.0;
+    const double pz1 =
+        (MU && (int)threadIdx.x + 2 * kThreads < nb) ? partZ[threadIdx.x + 2 * kThreads] : 0.0;
+    const int64_t bx = rbf::xcd_block(blockIdx.x, nb);
+    int64_t r = bx * kThreads + wv * 32 + (lane & 31);
+    int64_t rr = (r < P.m) ? r : P.m - 1;
+    T at = aux_row2<28>(P, rr, half, [&](int j) { return t1[j]; });
     double mu = 0.0;
     if constexpr (MU) {
-        double sz[1] = {0.0};
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) sz[0] += partZ[b];
+        double sz[1] = {pz0 + pz1};
         rbf::block_sum<1>(sz, lds);
         mu = (*L.mean / L.c - sz[0]) / (double)P.m;
     }
     const T sc = (T)*ys;
     double acc[1] = {0.0};
-    const int64_t bx = rbf::xcd_block(blockIdx.x, nb);
 #pragma unroll 1
     for (int64_t it = 0;; ++it) {
         if ((bx + it * nb) * kThreads >= P.m) break;
-        const int64_t r = (bx + it * nb) * kThreads + wv * 32 + (lane & 31);
-        const int64_t rr = (r < P.m) ? r : P.m - 1;
-        const T at = aux_row2<28>(P, rr, half, [&](int j) { return t1[j]; });
+        if (it > 0) {
+            r = (bx + it * nb) * kThreads + wv * 32 + (lane & 31);
+            rr = (r < P.m) ? r : P.m - 1;
+            at = aux_row2<28>(P, rr, half, [&](int j) { return t1[j]; });
+        }
         if (half == 0 && r < P.m) {
             const T zr = t1[r] + (T)mu + (MU ? (T)1 : (T)P.w2) * P.dinv[r] * (sc * y[r] - at);
             z[r] = zr;
@@ -588,22 +599,32 @@ __global__ void __launch_bounds__(kAvThreads) __attribute__((amdgpu_waves_per_eu
     constexpr int NW = kAvThreads / 64;
     __shared__ double lds[2 * kFgSlots * NW];
     const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
-    const int nb = gridDim.x;
-    double sz[1] = {0.0};
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) sz[0] += F.s.partO[b];
-    rbf::block_sum<1>(sz, lds);
-    const double bterm = vscale * sz[0];  // border: u1 c (1^T z)
+    const int nb = gridDim.x;  // <= kMaxBlocks = 2 blockDim.x: two partials per thread
     const T *z = F.Z + (int64_t)j * P.m;
     T *w = F.V + (int64_t)(j + 1) * P.m;
+    // The partials of 1^T z and the first row iteration's product (every
+    // block has one) are loaded before the border sum is reduced, so that
+    // the reduction overlaps the gathers.
+    const double po0 = ((int)threadIdx.x < nb) ? F.s.partO[threadIdx.x] : 0.0;
+    const double po1 =
+        ((int)threadIdx.x + kAvThreads < nb) ? F.s.partO[threadIdx.x + kAvThreads] : 0.0;
+    const int64_t bx = rbf::xcd_block(blockIdx.x, nb);
+    int64_t r = bx * kThreads + wv * 32 + (lane & 31);
+    int64_t rr = (r < P.m) ? r : P.m - 1;
+    T az = aux_row2<28>(P, rr, half, [&](int c) { return z[c]; });
+    double sz[1] = {po0 + po1};
+    rbf::block_sum<1>(sz, lds);
+    const double bterm = vscale * sz[0];  // border: u1 c (1^T z)
     const int ns = (j + 2) >> 1;
     fg_slot_zero<NW>(ns, lds);
-    const int64_t bx = rbf::xcd_block(blockIdx.x, nb);
 #pragma unroll 1
     for (int64_t it = 0;; ++it) {
         if ((bx + it * nb) * kThreads >= P.m) break;
-        const int64_t r = (bx + it * nb) * kThreads + wv * 32 + (lane & 31);
-        const int64_t rr = (r < P.m) ? r : P.m - 1;
-        const T az = aux_row2<28>(P, rr, half, [&](int c) { return z[c]; });
+        if (it > 0) {
+            r = (bx + it * nb) * kThreads + wv * 32 + (lane & 31);
+            rr = (r < P.m) ? r : P.m - 1;
+            az = aux_row2<28>(P, rr, half, [&](int c) { return z[c]; });
+        }
         const T wt = (T)((double)az + u1[rr] * bterm);
         // The basis is read after the product, so that the two sets of
         // loads in flight do not share the registers.  Slot c of half 1
