@@ -61,7 +61,9 @@ __device__ __forceinline__ void ell_row(const int *__restrict__ idx, const doubl
 
 // Half of row r's stencil for a two-lanes-per-row layout: slots
 // half * KT/2 .. (half + 1) * KT/2 - 1 (KT > 0, even); the caller adds the
-// two lanes' sums.
+// two lanes' sums.  Plain (temporal) loads of the operator: its user, the
+// viscous Jacobi sweep, reads it once per sweep, several times per solve,
+// and it stays in the memory-side cache between sweeps.
 template <int KT, class Gather>
 __device__ __forceinline__ void ell_half_row(const int *__restrict__ idx,
                                              const double *__restrict__ w, int64_t rows,
@@ -72,9 +74,9 @@ __device__ __forceinline__ void ell_half_row(const int *__restrict__ idx,
     int jj[H];
     double ww[H];
 #pragma unroll
-    for (int s = 0; s < H; ++s) jj[s] = ld_stream(idx + (int64_t)(half * H + s) * rows + r);
+    for (int s = 0; s < H; ++s) jj[s] = idx[(int64_t)(half * H + s) * rows + r];
 #pragma unroll
-    for (int s = 0; s < H; ++s) ww[s] = ld_stream(w + (int64_t)(half * H + s) * rows + r);
+    for (int s = 0; s < H; ++s) ww[s] = w[(int64_t)(half * H + s) * rows + r];
 #pragma unroll
     for (int s = 0; s < H; ++s) {
         double v[Gather::NV];
