@@ -122,10 +122,12 @@ __global__ void __launch_bounds__(kThreads) k_hm_sweep(HMix X, int i, int s, dou
             if constexpr (KT > 0) {
                 int jj[KT];
                 float ww[KT];
+                // Temporal loads: every sweep of the solve reads the operator
+                // again, and it stays in the memory-side cache between them.
 #pragma unroll
-                for (int q = 0; q < KT; ++q) jj[q] = rbf::ld_stream(X.idx + (int64_t)q * X.n + row);
+                for (int q = 0; q < KT; ++q) jj[q] = X.idx[(int64_t)q * X.n + row];
 #pragma unroll
-                for (int q = 0; q < KT; ++q) ww[q] = rbf::ld_stream(X.w32 + (int64_t)q * X.n + row);
+                for (int q = 0; q < KT; ++q) ww[q] = X.w32[(int64_t)q * X.n + row];
 #pragma unroll
                 for (int q = 0; q < KT; ++q) {
                     const float2 t = din[jj[q]];
