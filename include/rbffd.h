@@ -508,7 +508,7 @@ rbf_status rbf_solver_apply_precond(rbf_solver *s, const double *y, double *z);
  *   RBF_PROF_SMOOTH  the post-smoothing product of the auxiliary-lattice
  *                    preconditioner (k_aux_post2; k_aux_post for stencils
  *                    other than 28 nodes);
- *   RBF_PROF_GS      the first Gram-Schmidt update of FGMRES (k_fg_gs<1>).
+ *   RBF_PROF_GS      the Gram-Schmidt update of FGMRES (k_fg_gs<2>).
  * A sampled launch goes through hipExtLaunchKernelGGL with an event pair
  * that records the kernel's own start and end; the pairs are read at the
  * solver's next stream synchronisation (no extra synchronisation).

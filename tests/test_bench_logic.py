@@ -44,7 +44,7 @@ def test_kernel_bytes():
     b = bench.kernel_bytes(M, {}, 21.0)  # mean Arnoldi index 10: 11 basis vectors
     assert b["k_aux_post2"] == M * 368
     assert b["k_fg_av2"] == M * (352 + 8 * 11)
-    assert b["k_fg_gs<1>"] == M * (16 + 16 * 11)
+    assert b["k_fg_gs<2>"] == M * (32 + 8 * 11)
 
 
 def test_shedding_statistics():
