@@ -67,7 +67,7 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 # counters on a plain 256 MiB copy (2.0 and 1.0), mean over the working
 # launches of 3 steps from rest (mean Arnoldi index 11.9 for k_fg_av2 and
 # k_fg_gs<2>); None for a kernel changed since it was measured.
-TRAFFIC_BYTES = {"k_fg_av2": 87.09e6, "k_aux_post2": 68.82e6, "k_fg_gs<2>": None,
+TRAFFIC_BYTES = {"k_fg_av2": 87.08e6, "k_aux_post2": 68.83e6, "k_fg_gs<2>": 26.32e6,
                  "k_pc_gemm<0>": 22.75e6}
 
 
