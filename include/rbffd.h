@@ -504,7 +504,7 @@ rbf_status rbf_solver_apply_precond(rbf_solver *s, const double *y, double *z);
  *   RBF_PROF_SPMV    the Krylov product with the Poisson matrix (k_pc_av with
  *                    the lattice preconditioner, k_kry_a without one, k_fg_av2
  *                    in FGMRES (k_fg_av for stencils other than 28 nodes): the
- *                    product plus the first Gram-Schmidt dots);
+ *                    product plus the Gram-Schmidt dots);
  *   RBF_PROF_SMOOTH  the post-smoothing product of the auxiliary-lattice
  *                    preconditioner (k_aux_post2; k_aux_post for stencils
  *                    other than 28 nodes);

@@ -38,7 +38,8 @@
 // FP32-stored weights, vectors and transforms with FP64 dot products, and
 // the correction is added to the FP64 iterate).
 //
-// FGMRES(mr) with classical Gram-Schmidt applied twice; the Hessenberg
+// FGMRES(mr) with classical Gram-Schmidt (one pass per step, or two when
+// the solver enables re-orthogonalisation); the Hessenberg
 // column, the Givens rotations and the residual estimate are updated on the
 // device by one workgroup per step; the host reads a status block after each
 // batch of steps.  All reductions are fixed-order (block partials reduced by
@@ -86,7 +87,7 @@ struct FgScal {
     double *vs;      // [mr+1] inverse norms
     double *part;    // [kFgMax + 2][kMaxBlocks] partial sums
     double *h1, *h2; // [mr+1] Gram-Schmidt coefficients of the two passes
-    double *hn2;     // [1] ||w||^2 after the second pass
+    double *hn2;     // [1] ||w||^2 after the last Gram-Schmidt pass
     double *H;       // [(mr+1) * mr] Hessenberg matrix, column-major
     double *cs, *sn; // [mr] Givens rotations
     double *g;       // [mr+1] rotated right-hand side
@@ -648,9 +649,10 @@ __global__ void __launch_bounds__(kAvThreads) __attribute__((amdgpu_waves_per_eu
     fg_slot_partials<NW>(j, F.s.vs, F.s.part, lds);
 }
 
-// Gram-Schmidt update w -= sum_i h_i vs_i V_i (i <= j); PASS 1: then block
-// partial dots (V_i vs_i, w) for the second pass; PASS 2: then block
-// partial ||w||^2, and W w for the next preconditioner application.
+// Gram-Schmidt update w -= sum_i h_i vs_i V_i (i <= j).  PASS 1 (the first
+// of two passes): then block partial dots (V_i vs_i, w) for the second;
+// PASS 2 (the last pass, the only one by default): then block partial
+// ||w||^2, and W w for the next preconditioner application.
 // Blocks of 2 kThreads threads on the kThreads-rows grid: lanes l and l + 32
 // of a wave share row l, each reading the basis vectors of one parity
 // (slot c: i = 2c + h), which serve both the update and, in PASS 1, the
