@@ -63,14 +63,6 @@ __device__ __forceinline__ T ld_stream(const T *p) {
     return __builtin_nontemporal_load(p);
 }
 
-// Wave-level sum of a double (64 lanes) using cross-lane shuffles; the
-// order of additions is fixed, so results are deterministic.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // A double moved across lanes by one DPP control (both 32-bit halves with
 // the same pattern; every lane active).
 template <int CTRL>
@@ -100,6 +92,18 @@ __device__ __forceinline__ void half_wave_sums(double v, double &lo, double &hi)
     v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
     lo = readlane_double(v, 0) + readlane_double(v, 16);
     hi = readlane_double(v, 32) + readlane_double(v, 48);
+}
+
+// Wave-level sum of a double (64 lanes): the DPP sums of the four 16-lane
+// rows, added as (0 + 16) + (32 + 48); a fixed order of additions, so
+// results are deterministic; uniform result.  Every lane must be active.
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_move<0x128>(v);
+    v += dpp_move<0x124>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0xB1>(v);
+    return (readlane_double(v, 0) + readlane_double(v, 16)) +
+           (readlane_double(v, 32) + readlane_double(v, 48));
 }
 
 // Block sum of NV doubles per thread; every thread returns the totals.
