@@ -67,8 +67,8 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 # counters on a plain 256 MiB copy (2.0 and 1.0), mean over the working
 # launches of 3 steps from rest (mean Arnoldi index 11.9 for k_fg_av2 and
 # k_fg_gs<2>); None for a kernel changed since it was measured.
-TRAFFIC_BYTES = {"k_fg_av2": 87.08e6, "k_aux_post2": 68.83e6, "k_fg_gs<2>": 26.32e6,
-                 "k_pc_gemm<0>": 22.75e6}
+TRAFFIC_BYTES = {"k_fg_av2": 87.05e6, "k_aux_post2": 68.84e6, "k_fg_gs<2>": 26.30e6,
+                 "k_pc_gemm<0>": 22.76e6}
 
 
 def parse():
