@@ -1881,6 +1881,11 @@ struct rbf_solver {
     double prof_ms[RBF_PROF_N] = {};
     std::vector<hipEvent_t> prof_ev[RBF_PROF_N];
     int prof_pending[RBF_PROF_N] = {};
+    // Arnoldi step of each pending pair (-1: not an FGMRES step), so that
+    // launches made after convergence (they exit at the flag test) are not
+    // counted; prof_tag_now is the tag given to the pairs being recorded.
+    int prof_tag[RBF_PROF_N][kProfPairs] = {};
+    int prof_tag_now = -1;
     // lattice preconditioner of the pressure system
     bool pc_on = false;
     bool mixed = false;  // RBF_PRECISION_MIXED
@@ -1929,15 +1934,19 @@ bool prof_pair(rbf_solver *S, int q, hipEvent_t &e0, hipEvent_t &e1) {
     if (S->prof_pending[q] >= rbf_solver::kProfPairs || S->prof_ev[q].empty()) return false;
     e0 = S->prof_ev[q][2 * S->prof_pending[q]];
     e1 = S->prof_ev[q][2 * S->prof_pending[q] + 1];
+    S->prof_tag[q][S->prof_pending[q]] = S->prof_tag_now;
     ++S->prof_pending[q];
     return true;
 }
-// After a stream synchronisation: accumulate the recorded pairs.
-void prof_flush(rbf_solver *S) {
+// After a stream synchronisation: accumulate the recorded pairs; pairs of
+// FGMRES steps at or after steps_done (launched after convergence, so they
+// exited at the flag test) are dropped.
+void prof_flush(rbf_solver *S, int steps_done = 1 << 30) {
     for (int q = 0; q < RBF_PROF_N; ++q) {
         const int per = 1;
         for (int e = 0; e < S->prof_pending[q]; ++e) {
             float ms = 0.f;
+            if (S->prof_tag[q][e] >= steps_done) continue;
             if (hipEventElapsedTime(&ms, S->prof_ev[q][2 * e], S->prof_ev[q][2 * e + 1]) ==
                 hipSuccess) {
                 S->prof_ms[q] += ms;
@@ -2793,7 +2802,7 @@ rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, co
         RBF_HIP(hipMemcpyAsync(S->hflag, Fs.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         RBF_HIP(hipMemcpyAsync(S->hflag + 2, Fs.stat, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
         RBF_HIP(hipStreamSynchronize(st));
-        prof_flush(S);
+        prof_flush(S, S->hflag[1]);
         return RBF_OK;
     };
     rbf_status rc = RBF_OK;
@@ -2812,12 +2821,19 @@ rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, co
             break;
         }
         int j = 0;
-        int batch = (cycles == 0 && expect > 0) ? std::max(2, std::min(mr, expect - 2)) : 6;
+        // First batch of a cycle: the steps the last solve needed beyond
+        // those already taken, less one (later batches follow the
+        // residual's rate); 6 when nothing is known.
+        int batch = 6;
+        if (expect > 0)
+            batch = (cycles == 0) ? std::max(2, std::min(mr, expect - 2))
+                                  : std::max(2, std::min(6, expect - total - 1));
         for (;;) {
             const int stop = std::min(mr, j + batch);
             for (; j < stop; ++j) {
                 const int64_t o = (int64_t)j * m;
                 const bool sample = S->prof_every > 0 && (S->prof_launches++ % S->prof_every) == 0;
+                S->prof_tag_now = j;
                 aux_apply(S, P, F, F.V + o, F.wd, Fs.vs + j, F.Z + o, sample);
                 hipEvent_t e0 = nullptr, e1 = nullptr, g0 = nullptr, g1 = nullptr;
                 if (sample) {
@@ -2844,6 +2860,7 @@ rbf_status fgmres_run(rbf_solver *S, const AuxOps<T> &P, FgDev<T> &F, EllM A, co
                                           F, Fs.h1, P.dinv, m, j);
                 }
                 hipLaunchKernelGGL(k_fg_tail, one, red, 0, st, Fs, j, mr, nb);
+                S->prof_tag_now = -1;
             }
             RBF_CHECK_LAUNCH();
             if ((rc = status()) != RBF_OK) return rc;
